@@ -1,0 +1,73 @@
+"""Periodic box meshes of lx^3 GLL hexahedra.
+
+The paper measures on cubic meshes of N_E hexahedral elements (Sec. 4.4) and
+expands the solution on each element as a tensor product over the GLL points
+(Sec. 3, Eq. 3).  Readings taken where the paper is silent:
+  * the box is the unit cube, n elements per side, periodic in x, y and z;
+  * elements are numbered lexicographically, e = ex + n (ey + n ez), and the
+    nodes of one element as [k][j][i] with i fastest (the index order of
+    Listing 2);
+  * the undeformed position of node (i, j, k) of element (ex, ey, ez) is
+    X = (ex + (1 + xi_i) / 2) / n, likewise Y, Z;
+  * the deformed position is x = X + a sin(2 pi Y) sin(2 pi Z), with y and z
+    following cyclically, which keeps x(X + e_c) = x(X) + e_c, so periodic
+    copies of a node still coincide;
+  * the global id of a node is its position on the (nN)^3 periodic lattice,
+    g = ((ez N + k) mod nN) (nN)^2 + ((ey N + j) mod nN) nN + ((ex N + i) mod nN).
+Pins: multiplicity counts and unique-node counts (tests/test_oracle_gs.py),
+affine volumes and geometric factors (tests/test_oracle_geometry.py).
+"""
+import numpy as np
+
+from .gll import gll_nodes_weights
+
+
+def reference_coords(n, lx):
+    """Undeformed node positions X, Y, Z, each of shape (n^3, lx, lx, lx)."""
+    xi, _ = gll_nodes_weights(lx - 1)
+    E = n ** 3
+    X = np.empty((E, lx, lx, lx))
+    Y = np.empty_like(X)
+    Z = np.empty_like(X)
+    for e in range(E):
+        ex, ey, ez = e % n, (e // n) % n, e // (n * n)
+        px = (ex + 0.5 * (1.0 + xi)) / n
+        py = (ey + 0.5 * (1.0 + xi)) / n
+        pz = (ez + 0.5 * (1.0 + xi)) / n
+        X[e] = px[None, None, :]
+        Y[e] = py[None, :, None]
+        Z[e] = pz[:, None, None]
+    return X, Y, Z
+
+
+def deform(X, Y, Z, a):
+    """The cyclic sine deformation with amplitude a."""
+    tp = 2.0 * np.pi
+    x = X + a * np.sin(tp * Y) * np.sin(tp * Z)
+    y = Y + a * np.sin(tp * Z) * np.sin(tp * X)
+    z = Z + a * np.sin(tp * X) * np.sin(tp * Y)
+    return x, y, z
+
+
+def box_coords(n, lx, a=0.0):
+    return deform(*reference_coords(n, lx), a)
+
+
+def global_ids(n, lx):
+    """int64 global ids, shape (n^3, lx, lx, lx), values in [0, (n N)^3)."""
+    N = lx - 1
+    M = n * N
+    E = n ** 3
+    ids = np.empty((E, lx, lx, lx), dtype=np.int64)
+    r = np.arange(lx)
+    for e in range(E):
+        ex, ey, ez = e % n, (e // n) % n, e // (n * n)
+        gi = (ex * N + r) % M
+        gj = (ey * N + r) % M
+        gk = (ez * N + r) % M
+        ids[e] = gk[:, None, None] * M * M + gj[None, :, None] * M + gi[None, None, :]
+    return ids
+
+
+def n_unique(n, lx):
+    return (n * (lx - 1)) ** 3

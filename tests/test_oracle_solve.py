@@ -1,0 +1,74 @@
+"""Pins for oracle.solve: pseudo-inverse solutions, FCG = PCG for a fixed
+preconditioner, spectral convergence of a manufactured solution."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.assemble import assembled_matrix
+from oracle.gs import scatter
+from oracle.solve import BoxProblem, pcg, fcg1, iterative_refinement
+
+
+def test_pcg_matches_pseudoinverse():
+    n, lx = 2, 4
+    P = BoxProblem(n, lx, 0.1, synth.unique_uniform((n * (lx - 1)) ** 3, 0.5, 2.0, 1))
+    k, amp, ph = synth.fourier_modes(2, count=8, kmax=2)
+    b = P.fourier_rhs(k, amp, ph)
+    assert abs(b.sum()) < 1e-13 * np.abs(b).sum()
+    A = assembled_matrix(P.Dh, P.h1, P.G, P.ids, P.nu).toarray()
+    xref = np.linalg.pinv(A, rcond=1e-12) @ b
+    x, it, hist = pcg(P.apply, b, 1.0 / P.diagonal(), tol=1e-12)
+    assert hist[-1] <= 1e-12
+    assert np.max(np.abs(x - xref)) < 1e-9 * np.max(np.abs(xref))
+
+
+def test_fcg_reproduces_pcg_with_fixed_preconditioner():
+    P = BoxProblem(3, 4, 0.1)
+    k, amp, ph = synth.fourier_modes(5)
+    b = P.fourier_rhs(k, amp, ph)
+    Minv = 1.0 / P.diagonal()
+    x1, it1, h1 = pcg(P.apply, b, Minv, tol=1e-10)
+    x2, it2, h2 = fcg1(P.apply, b, lambda r: Minv * r, tol=1e-10)
+    assert abs(it1 - it2) <= 1
+    n = min(len(h1), len(h2), 30)
+    np.testing.assert_allclose(h1[:n], h2[:n], rtol=1e-6)
+    assert np.max(np.abs(x1 - x2)) < 1e-8 * np.max(np.abs(x1))
+
+
+def test_manufactured_solution_spectral_convergence():
+    """u = sin(2 pi x) sin(2 pi y) sin(2 pi z) solves -lap u = 12 pi^2 u on the
+    periodic unit box; the discrete error must fall spectrally in lx."""
+    errs = []
+    for lx in (4, 6, 8):
+        P = BoxProblem(2, lx, 0.0)
+        x, y, z = P.coords
+        u = np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y) * np.sin(2 * np.pi * z)
+        f = 12 * np.pi ** 2 * u
+        from oracle.gs import gather
+        b = gather(P.B * f, P.ids, P.nu)
+        b -= b.mean()
+        sol, it, hist = pcg(P.apply, b, 1.0 / P.diagonal(), tol=1e-13)
+        ex = np.zeros(P.nu); ex[P.ids.ravel()] = u.ravel()
+        errs.append(np.max(np.abs(sol - (ex - ex.mean()))))
+    # each step of 2 in lx gains more than two orders of magnitude
+    assert errs[0] > 100 * errs[1] and errs[1] > 100 * errs[2]
+    assert errs[2] < 1e-6
+
+
+def test_refinement_with_float32_inner_reaches_float64_tolerance():
+    P = BoxProblem(3, 4, 0.1)
+    k, amp, ph = synth.fourier_modes(6)
+    b = P.fourier_rhs(k, amp, ph)
+    Minv = 1.0 / P.diagonal()
+
+    def apply32(v):
+        return P.apply(v.astype(np.float32).astype(np.float64)).astype(np.float32).astype(np.float64)
+
+    def inner(rhat):
+        d, _, _ = pcg(apply32, rhat, Minv, tol=1e-5, maxit=500)
+        return d
+
+    x, outer, relres = iterative_refinement(P.apply, b, inner, tol=1e-10)
+    assert relres[-1] <= 1e-10 and outer >= 2
+    xref, _, _ = pcg(P.apply, b, Minv, tol=1e-13)
+    assert np.max(np.abs(x - xref)) < 1e-7 * np.max(np.abs(xref))
