@@ -1,0 +1,174 @@
+"""Benchmark: FP64 operator throughput on a 32^3 deformed periodic box at lx = 8.
+
+One step = one sem_ax application (the matrix-free operator of the paper's
+Listing 2) over all E = 32768 elements: three derivative passes, the h1 * G
+multiply and three transposed passes, streaming u, h1, g11..g23 and writing w.
+Inputs are resident in HBM before timing.  Prints one JSON line.
+
+Extra fields:
+  roofline      dominant kernel (the operator) against the MI355X HBM peak;
+                achieved = 72 B per local node (u, w, h1, six factors) per launch
+                divided by the launch's average duration from HIP events.
+  cpu_baseline  the plain-C oracle loop nest timed on this host's cores on a
+                bounded sample of the same workload shape.
+  gs            gather-scatter timing on the same mesh.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_NODE_F64 = 72
+
+
+def kernel_source_hash():
+    p = os.path.join(ROOT, "paper_2506_20994_amd", "csrc", "ax.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(n_local):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on a different kernel source."""
+    p = os.path.join(ROOT, "profiles", "ax_f64_lx8_e32768_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(lx, target_s=10.0):
+    import numpy as np
+    import synth
+    from oracle import cref
+    from oracle.gll import listing_matrices
+    nel = 4096
+    G, h1 = synth.random_spd_factors(nel, lx, 123)
+    u = synth.local_normal(nel, lx, 124)
+    M = listing_matrices(lx)
+    cref.ax_ref(u, *M, h1, *G)              # warm-up (and build if needed)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        cref.ax_ref(u, *M, h1, *G)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= target_s:
+            break
+    dofs = reps * nel * (lx - 1) ** 3
+    return {"value": dofs / el / 1e9, "unit": "GDOF/s", "cores": cref.num_threads(),
+            "kind": "oracle",
+            "sample": f"{nel} elements x lx={lx} (random SPD factors, h1, u), {reps} "
+                      f"applications of the plain-C loop nest in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--lx", type=int, default=8)
+    ap.add_argument("--amp", type=float, default=0.1)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this library runs on one GPU; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_2506_20994_amd as P
+    from paper_2506_20994_amd.box import BoxOperator
+
+    torch.cuda.set_device(0)
+    n, lx, amp = args.n, args.lx, args.amp
+    nu = (n * (lx - 1)) ** 3
+    ctx = P.sem_create()
+    op = BoxOperator(ctx, n, lx, amp, h1_unique=synth.unique_uniform(nu, 0.5, 2.0, 1),
+                     keep_coords=False)
+    u = op.scatter(synth.unique_normal(nu, 0))
+    w = torch.empty_like(u)
+    print(f"[bench] box {n}^3 lx={lx} amp={amp}: n_local={op.n_local} "
+          f"min detJ={op.min_detj:.3e}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        op.ax(w, u)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        op.ax(w, u)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ax_ms = ev0.elapsed_time(ev1) / args.steps
+    print(f"[bench] sem_ax: {ax_ms * 1e3:.1f} us per launch (events), wall {wall:.3f} s",
+          file=sys.stderr, flush=True)
+
+    # gather-scatter on the same mesh
+    for _ in range(5):
+        P.sem_gs(op.gs, w)
+    g0 = torch.cuda.Event(enable_timing=True)
+    g1 = torch.cuda.Event(enable_timing=True)
+    gsteps = max(10, args.steps // 4)
+    g0.record(stream)
+    for _ in range(gsteps):
+        P.sem_gs(op.gs, w)
+    g1.record(stream)
+    torch.cuda.synchronize()
+    gs_ms = g0.elapsed_time(g1) / gsteps
+
+    n_local = op.n_local
+    ms_per_step = wall * 1e3 / args.steps
+    gdofs = nel_dofs = op.nel * (lx - 1) ** 3
+    value = gdofs / (ms_per_step * 1e-3) / 1e9
+    alg_bytes = BYTES_PER_NODE_F64 * n_local
+    achieved = alg_bytes / (ax_ms * 1e-3) / 1e9
+    traffic = load_traffic(n_local)
+    _, n_shared = P.sem_gs_info(op.gs)
+    out = {
+        "metric": "Ax GDOF/s (unique dofs E*(lx-1)^3 per second), FP64, lx=8",
+        "value": round(value, 3),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"sem_ax on a {n}^3 periodic box (E={op.nel}) deformed with "
+                               f"amplitude {amp}, lx={lx}, h1~U[0.5,2], u~N(0,1)",
+                   "nel": op.nel, "lx": lx, "n_local": n_local, "unique_dofs": nel_dofs},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": f"ax_kernel<{lx}, double>",
+                     "avg_launch_us": round(ax_ms * 1e3, 2),
+                     "alg_bytes_per_launch": alg_bytes},
+        "gs": {"avg_launch_us": round(gs_ms * 1e3, 2), "shared_ids": n_shared,
+               "alg_bytes_per_launch": None},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(lx)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

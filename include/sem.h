@@ -1,0 +1,169 @@
+/* sem.h -- C ABI of the MI355X spectral-element operator library (libsem.so).
+ *
+ * The library evaluates the matrix-free Poisson/Helmholtz stiffness operator of
+ * a spectral-element solver on lx^3 Gauss-Lobatto-Legendre (GLL) hexahedra
+ * (arXiv 2506.20994, Sec. 3 and Sec. 4.2, Listing 2), the gather-scatter sum
+ * that assembles it (Sec. 2.1), and the set-up and solver steps around them.
+ *
+ * Conventions shared by every entry point
+ *  - Element-local fields are [nel][lx][lx][lx] with i fastest (the index order
+ *    of Listing 2), contiguous, no padding.  "n_local" = nel * lx^3.
+ *  - Pointers named "device" must point to device memory of the GPU that was
+ *    current when the context was created; the caller owns them and the library
+ *    never frees them.  Pointers named "host" are ordinary host memory.
+ *  - Calls that take a context run asynchronously on the context's stream
+ *    unless documented as synchronous.  No call allocates device memory except
+ *    sem_create and the *_setup / *_create calls.
+ *  - Every call returns a status: SEM_OK (0), a positive informational code, or
+ *    a negative error code.  On error nothing has been launched and
+ *    sem_last_error() returns a message.
+ *  - lx must be in [2, 12] (SEM_EUNSUPPORTED_LX otherwise).
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sem_ctx_s* sem_ctx_t;
+typedef struct sem_gs_s* sem_gs_t;
+
+typedef enum { SEM_F64 = 0, SEM_F32 = 1, SEM_BF16 = 2 } sem_dtype_t;
+
+enum {
+    SEM_OK = 0,
+    SEM_NOT_CONVERGED = 1,   /* solver stopped at maxit; results are valid but not converged */
+    SEM_FELL_BACK = 2,       /* learned preconditioner was abandoned for Jacobi */
+    SEM_EINVAL = -1,         /* bad argument (null pointer, size, alias, dtype) */
+    SEM_EUNSUPPORTED_LX = -2,
+    SEM_EHIP = -3,           /* a HIP runtime call failed */
+    SEM_EBREAKDOWN = -4,     /* solver breakdown: non-finite or non-positive curvature */
+    SEM_ENOMEM = -5,
+    SEM_EGEOMETRY = -6       /* folded mesh: det J <= 0 somewhere */
+};
+
+#define SEM_LX_MIN 2
+#define SEM_LX_MAX 12
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on the current HIP device.  `hip_stream` is a hipStream_t
+ * (NULL = the null stream) that the context borrows; it is not destroyed by
+ * sem_destroy.  Allocates a small device workspace (reduction partials). */
+int sem_create(sem_ctx_t* ctx, void* hip_stream);
+int sem_destroy(sem_ctx_t ctx);
+/* Switch the stream later calls are launched on (borrowed, as above). */
+int sem_set_stream(sem_ctx_t ctx, void* hip_stream);
+/* Message for the last error on this context (ctx = NULL: last error of a call
+ * that had no valid context).  Never NULL. */
+const char* sem_last_error(sem_ctx_t ctx);
+/* Block the host until all work queued on the context's stream is done. */
+int sem_sync(sem_ctx_t ctx);
+
+/* ----------------------------------------------------------------- set-up */
+
+/* GLL nodes xi[0..lx), weights w[0..lx) and the derivative matrix of the
+ * Lagrange basis (Sec. 3, Eq. 2-3), written in the layout of the operator's
+ * argument list (Listing 1/2):  dx[l*lx + i] = l_l'(xi_i) (the factor that
+ * multiplies u_l in the r-derivative at node i) and dxt[l*lx + i] = dx[i*lx + l].
+ * All outputs are host arrays; any of them may be NULL.  Synchronous, needs no
+ * context or GPU. */
+int sem_gll(int lx, double* xi, double* w, double* dx, double* dxt);
+
+/* Periodic box of n^3 elements on the unit cube with the cyclic sine
+ * deformation x = X + amp sin(2 pi Y) sin(2 pi Z) (y, z cyclically), where X is
+ * the position of the node on the undeformed uniform grid.  Elements are
+ * numbered e = ex + n (ey + n ez).  Writes node coordinates x, y, z (device
+ * float64, n_local each) and global node ids (device int64, n_local), the id
+ * being the node's position on the periodic (n (lx-1))^3 lattice.  Any output
+ * may be NULL. */
+int sem_box_mesh(sem_ctx_t ctx, int n, int lx, double amp,
+                 double* x, double* y, double* z, int64_t* ids);
+
+/* Geometric factors of the operator from node coordinates (isoparametric:
+ * the GLL derivative matrix applied to x, y, z gives the Jacobian).  With
+ * 1 = r, 2 = s, 3 = t and W = w_i w_j w_k |J|:
+ *   g_ab = W sum_c (dr_a/dx_c)(dr_b/dx_c),   bm = W (diagonal mass).
+ * All arrays device float64 of n_local.  bm may be NULL.  The call is
+ * synchronous: it returns SEM_EGEOMETRY when det J <= 0 at some node; if
+ * `min_detj` (host) is non-NULL it receives the minimum det J. */
+int sem_geometry(sem_ctx_t ctx, const double* x, const double* y, const double* z,
+                 int64_t nel, int lx,
+                 double* g11, double* g22, double* g33,
+                 double* g12, double* g13, double* g23, double* bm,
+                 double* min_detj);
+
+/* out_local[L] = in_unique[ids[L]] for L < n_local (the scatter Q; any dtype,
+ * in and out of the same dtype).  ids device int64 in [0, n_unique). */
+int sem_scatter(sem_ctx_t ctx, void* out_local, const void* in_unique,
+                const int64_t* ids, int64_t n_local, sem_dtype_t dtype);
+
+/* Element-local diagonal of the operator (before gather-scatter):
+ *   d = sum_l D_li^2 V11(l,j,k) + sum_l D_lj^2 V22(i,l,k) + sum_l D_lk^2 V33(i,j,l)
+ *     + 2 D_ii D_jj V12 + 2 D_ii D_kk V13 + 2 D_jj D_kk V23,   V_ab = h1 g_ab,
+ * with D_il = dx[l*lx + i].  h1 may be NULL (h1 = 1).  Device float64. */
+int sem_ax_diag(sem_ctx_t ctx, double* d, const double* dx, const double* h1,
+                const double* g11, const double* g22, const double* g33,
+                const double* g12, const double* g13, const double* g23,
+                int64_t nel, int lx);
+
+/* f[L] = scale[L] * sum_m amp[m] cos(2 pi (k[m].x_L) + phase[m]) for a sum of
+ * nmodes <= 64 Fourier modes (k host int64 [nmodes][3], amp and phase host
+ * float64).  scale may be NULL (1).  Device float64 in/out. */
+int sem_fourier(sem_ctx_t ctx, double* f, const double* x, const double* y,
+                const double* z, const double* scale, int64_t n_local,
+                const int64_t* k, const double* amp, const double* phase, int nmodes);
+
+/* Element-wise precision conversion dst = src, round-to-nearest-even; float64
+ * to bfloat16 rounds through float32.  Device arrays of n entries. */
+int sem_convert(sem_ctx_t ctx, void* dst, sem_dtype_t dst_dtype,
+                const void* src, sem_dtype_t src_dtype, int64_t n);
+
+/* ---------------------------------------------------------------- operator */
+
+/* w = A_e u on every element (Sec. 4.2, Listing 2; argument order of
+ * Listing 1, with nel and lx passed by value):
+ *   ur = sum_l dx[l,i] u[k,j,l],  us = sum_l dy[l,j] u[k,l,i],
+ *   ut = sum_l dz[l,k] u[l,j,i]
+ *   [vr vs vt] = h1 * [[g11 g12 g13] [g12 g22 g23] [g13 g23 g33]] [ur us ut]
+ *   w[k,j,i] = sum_l dxt[l,i] vr[k,j,l] + dyt[l,j] vs[k,l,i] + dzt[l,k] vt[l,j,i]
+ * field_dtype is the storage type of u, h1 and g.. (SEM_F64, SEM_F32 or
+ * SEM_BF16); the six lx*lx matrices are float64 for SEM_F64 and float32
+ * otherwise; arithmetic is float64 for SEM_F64 and float32 (accumulation
+ * included) otherwise.  out_dtype is SEM_F64 (only with field_dtype SEM_F64)
+ * or SEM_F32.  h1 may be NULL (h1 = 1).  w must not overlap any input.
+ * All pointers device.  Asynchronous. */
+int sem_ax(sem_ctx_t ctx, void* w, const void* u,
+           const void* dx, const void* dy, const void* dz,
+           const void* dxt, const void* dyt, const void* dzt,
+           const void* h1, const void* g11, const void* g22, const void* g33,
+           const void* g12, const void* g13, const void* g23,
+           int64_t nel, int lx, sem_dtype_t field_dtype, sem_dtype_t out_dtype);
+
+/* ---------------------------------------------------------- gather-scatter */
+
+/* Build the gather-scatter plan (Sec. 2.1) for a local numbering: ids (host
+ * int64, n_local entries, any non-negative values) names the global node of
+ * each local node.  Nodes whose id occurs once are left alone by sem_gs.  The
+ * plan lives on the context's device until sem_gs_destroy.  Synchronous.
+ * n_local must be < 2^31. */
+int sem_gs_setup(sem_ctx_t ctx, const int64_t* ids, int64_t n_local, sem_gs_t* gs);
+int sem_gs_destroy(sem_gs_t gs);
+/* Number of distinct ids, and of ids that occur more than once (host outs). */
+int sem_gs_info(sem_gs_t gs, int64_t* n_unique, int64_t* n_shared);
+/* In place u <- Q Q^T u: each local copy of a node receives the sum over all
+ * copies, added in a fixed order (deterministic).  dtype SEM_F64 or SEM_F32
+ * (float32 fields are summed in float32).  Device array of n_local. */
+int sem_gs(sem_gs_t gs, void* u, sem_dtype_t dtype);
+/* mult[L] = number of local copies of node L's id (device float64). */
+int sem_gs_mult(sem_gs_t gs, double* mult);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEM_H */

@@ -22,21 +22,26 @@ import numpy as np
 from .gll import gll_nodes_weights
 
 
-def reference_coords(n, lx):
-    """Undeformed node positions X, Y, Z, each of shape (n^3, lx, lx, lx)."""
+def _elements(n, elements):
+    return np.arange(n ** 3) if elements is None else np.asarray(elements, dtype=np.int64)
+
+
+def reference_coords(n, lx, elements=None):
+    """Undeformed node positions X, Y, Z, each of shape (E, lx, lx, lx), for
+    all n^3 elements or for the listed element numbers."""
     xi, _ = gll_nodes_weights(lx - 1)
-    E = n ** 3
-    X = np.empty((E, lx, lx, lx))
+    els = _elements(n, elements)
+    X = np.empty((len(els), lx, lx, lx))
     Y = np.empty_like(X)
     Z = np.empty_like(X)
-    for e in range(E):
+    for q, e in enumerate(els):
         ex, ey, ez = e % n, (e // n) % n, e // (n * n)
         px = (ex + 0.5 * (1.0 + xi)) / n
         py = (ey + 0.5 * (1.0 + xi)) / n
         pz = (ez + 0.5 * (1.0 + xi)) / n
-        X[e] = px[None, None, :]
-        Y[e] = py[None, :, None]
-        Z[e] = pz[:, None, None]
+        X[q] = px[None, None, :]
+        Y[q] = py[None, :, None]
+        Z[q] = pz[:, None, None]
     return X, Y, Z
 
 
@@ -49,23 +54,23 @@ def deform(X, Y, Z, a):
     return x, y, z
 
 
-def box_coords(n, lx, a=0.0):
-    return deform(*reference_coords(n, lx), a)
+def box_coords(n, lx, a=0.0, elements=None):
+    return deform(*reference_coords(n, lx, elements), a)
 
 
-def global_ids(n, lx):
-    """int64 global ids, shape (n^3, lx, lx, lx), values in [0, (n N)^3)."""
+def global_ids(n, lx, elements=None):
+    """int64 global ids, shape (E, lx, lx, lx), values in [0, (n N)^3)."""
     N = lx - 1
     M = n * N
-    E = n ** 3
-    ids = np.empty((E, lx, lx, lx), dtype=np.int64)
+    els = _elements(n, elements)
+    ids = np.empty((len(els), lx, lx, lx), dtype=np.int64)
     r = np.arange(lx)
-    for e in range(E):
+    for q, e in enumerate(els):
         ex, ey, ez = e % n, (e // n) % n, e // (n * n)
         gi = (ex * N + r) % M
         gj = (ey * N + r) % M
         gk = (ez * N + r) % M
-        ids[e] = gk[:, None, None] * M * M + gj[None, :, None] * M + gi[None, None, :]
+        ids[q] = gk[:, None, None] * M * M + gj[None, :, None] * M + gi[None, None, :]
     return ids
 
 

@@ -1,0 +1,251 @@
+"""ctypes binding of libsem.so.  Argument marshalling only."""
+import ctypes
+import os
+
+import torch
+
+__all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONVERGED",
+           "SEM_FELL_BACK", "SEM_EINVAL", "SEM_EUNSUPPORTED_LX", "SEM_EHIP", "SEM_EBREAKDOWN",
+           "SEM_ENOMEM", "SEM_EGEOMETRY", "lib", "lib_path", "sem_create", "sem_destroy",
+           "sem_sync", "sem_gll", "sem_box_mesh", "sem_geometry", "sem_scatter",
+           "sem_ax_diag", "sem_fourier", "sem_convert", "sem_ax", "sem_gs_setup",
+           "sem_gs_destroy", "sem_gs_info", "sem_gs", "sem_gs_mult", "Context", "GsPlan",
+           "dtype_code", "EXPORTS"]
+
+SEM_F64, SEM_F32, SEM_BF16 = 0, 1, 2
+SEM_OK, SEM_NOT_CONVERGED, SEM_FELL_BACK = 0, 1, 2
+SEM_EINVAL, SEM_EUNSUPPORTED_LX, SEM_EHIP = -1, -2, -3
+SEM_EBREAKDOWN, SEM_ENOMEM, SEM_EGEOMETRY = -4, -5, -6
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libsem.so")
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+_dbl = ctypes.c_double
+_pdbl = ctypes.POINTER(ctypes.c_double)
+_pi64 = ctypes.POINTER(ctypes.c_int64)
+
+# name -> (restype, argtypes); the exported C ABI
+EXPORTS = {
+    "sem_create": (_int, [ctypes.POINTER(_vp), _vp]),
+    "sem_destroy": (_int, [_vp]),
+    "sem_set_stream": (_int, [_vp, _vp]),
+    "sem_last_error": (ctypes.c_char_p, [_vp]),
+    "sem_sync": (_int, [_vp]),
+    "sem_gll": (_int, [_int, _pdbl, _pdbl, _pdbl, _pdbl]),
+    "sem_box_mesh": (_int, [_vp, _int, _int, _dbl, _vp, _vp, _vp, _vp]),
+    "sem_geometry": (_int, [_vp, _vp, _vp, _vp, _i64, _int] + [_vp] * 7 + [_pdbl]),
+    "sem_scatter": (_int, [_vp, _vp, _vp, _vp, _i64, _int]),
+    "sem_ax_diag": (_int, [_vp, _vp, _vp, _vp] + [_vp] * 6 + [_i64, _int]),
+    "sem_fourier": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i64, _pi64, _pdbl, _pdbl, _int]),
+    "sem_convert": (_int, [_vp, _vp, _int, _vp, _int, _i64]),
+    "sem_ax": (_int, [_vp, _vp, _vp] + [_vp] * 6 + [_vp] * 7 + [_i64, _int, _int, _int]),
+    "sem_gs_setup": (_int, [_vp, _pi64, _i64, ctypes.POINTER(_vp)]),
+    "sem_gs_destroy": (_int, [_vp]),
+    "sem_gs_info": (_int, [_vp, _pi64, _pi64]),
+    "sem_gs": (_int, [_vp, _vp, _int]),
+    "sem_gs_mult": (_int, [_vp, _vp]),
+}
+
+_LIB = None
+
+
+def lib():
+    """The loaded libsem.so; raises if it is not built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(lib_path):
+            raise ImportError(f"{lib_path} is not built; run python -m paper_2506_20994_amd.build")
+        L = ctypes.CDLL(lib_path)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+class SemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def _check(rc, ctx_handle=None):
+    if rc < 0:
+        msg = lib().sem_last_error(ctx_handle)
+        raise SemError(rc, msg.decode() if msg else "")
+    return rc
+
+
+_TORCH_CODES = {torch.float64: SEM_F64, torch.float32: SEM_F32, torch.bfloat16: SEM_BF16}
+
+
+def dtype_code(t):
+    return _TORCH_CODES[t.dtype]
+
+
+def _ptr(t):
+    """Device pointer of a contiguous GPU tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+class Context:
+    """Owns a sem_ctx_t; launches on torch's current stream at each call."""
+
+    def __init__(self):
+        h = _vp()
+        _check(lib().sem_create(ctypes.byref(h), _vp(torch.cuda.current_stream().cuda_stream)))
+        self.handle = h
+
+    def bind(self):
+        lib().sem_set_stream(self.handle, _vp(torch.cuda.current_stream().cuda_stream))
+        return self.handle
+
+    def close(self):
+        if self.handle:
+            lib().sem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GsPlan:
+    def __init__(self, ctx, handle):
+        self.ctx, self.handle = ctx, handle
+
+    def close(self):
+        if self.handle:
+            lib().sem_gs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sem_create():
+    return Context()
+
+
+def sem_destroy(ctx):
+    ctx.close()
+
+
+def sem_sync(ctx):
+    _check(lib().sem_sync(ctx.bind()), ctx.handle)
+
+
+def sem_gll(lx):
+    """(xi, w, dx, dxt) as float64 numpy arrays (host)."""
+    import numpy as np
+    xi, w = np.empty(lx), np.empty(lx)
+    dx, dxt = np.empty((lx, lx)), np.empty((lx, lx))
+    c = lambda a: a.ctypes.data_as(_pdbl)  # noqa: E731
+    _check(lib().sem_gll(lx, c(xi), c(w), c(dx), c(dxt)))
+    return xi, w, dx, dxt
+
+
+def sem_box_mesh(ctx, n, lx, amp, x=None, y=None, z=None, ids=None):
+    h = ctx.bind()
+    _check(lib().sem_box_mesh(h, n, lx, float(amp), _ptr(x), _ptr(y), _ptr(z), _ptr(ids)), h)
+
+
+def sem_geometry(ctx, x, y, z, nel, lx, g11, g22, g33, g12, g13, g23, bm=None):
+    """Returns min det J."""
+    h = ctx.bind()
+    dmin = _dbl(0.0)
+    _check(lib().sem_geometry(h, _ptr(x), _ptr(y), _ptr(z), nel, lx, _ptr(g11), _ptr(g22),
+                              _ptr(g33), _ptr(g12), _ptr(g13), _ptr(g23), _ptr(bm),
+                              ctypes.byref(dmin)), h)
+    return dmin.value
+
+
+def sem_scatter(ctx, out_local, in_unique, ids, n_local=None):
+    h = ctx.bind()
+    n = out_local.numel() if n_local is None else n_local
+    _check(lib().sem_scatter(h, _ptr(out_local), _ptr(in_unique), _ptr(ids), n,
+                             dtype_code(out_local)), h)
+
+
+def sem_ax_diag(ctx, d, dx, h1, g11, g22, g33, g12, g13, g23, nel, lx):
+    h = ctx.bind()
+    _check(lib().sem_ax_diag(h, _ptr(d), _ptr(dx), _ptr(h1), _ptr(g11), _ptr(g22), _ptr(g33),
+                             _ptr(g12), _ptr(g13), _ptr(g23), nel, lx), h)
+
+
+def sem_fourier(ctx, f, x, y, z, scale, k, amp, phase):
+    """k: int64 numpy (m, 3); amp, phase: float64 numpy (m,)."""
+    import numpy as np
+    h = ctx.bind()
+    k = np.ascontiguousarray(k, dtype=np.int64)
+    amp = np.ascontiguousarray(amp, dtype=np.float64)
+    phase = np.ascontiguousarray(phase, dtype=np.float64)
+    _check(lib().sem_fourier(h, _ptr(f), _ptr(x), _ptr(y), _ptr(z), _ptr(scale), f.numel(),
+                             k.ctypes.data_as(_pi64), amp.ctypes.data_as(_pdbl),
+                             phase.ctypes.data_as(_pdbl), len(amp)), h)
+
+
+def sem_convert(ctx, dst, src):
+    h = ctx.bind()
+    if dst.numel() != src.numel():
+        raise ValueError("size mismatch")
+    _check(lib().sem_convert(h, _ptr(dst), dtype_code(dst), _ptr(src), dtype_code(src),
+                             dst.numel()), h)
+
+
+def sem_ax(ctx, w, u, dx, dy, dz, dxt, dyt, dzt, h1, g11, g22, g33, g12, g13, g23, nel, lx,
+           field_dtype=None, out_dtype=None):
+    h = ctx.bind()
+    fd = dtype_code(u) if field_dtype is None else field_dtype
+    od = dtype_code(w) if out_dtype is None else out_dtype
+    _check(lib().sem_ax(h, _ptr(w), _ptr(u), _ptr(dx), _ptr(dy), _ptr(dz), _ptr(dxt), _ptr(dyt),
+                        _ptr(dzt), _ptr(h1), _ptr(g11), _ptr(g22), _ptr(g33), _ptr(g12),
+                        _ptr(g13), _ptr(g23), nel, lx, fd, od), h)
+
+
+def sem_gs_setup(ctx, ids_host):
+    """ids_host: int64 numpy array (host) of global ids."""
+    import numpy as np
+    ids_host = np.ascontiguousarray(ids_host, dtype=np.int64).ravel()
+    h = ctx.bind()
+    out = _vp()
+    _check(lib().sem_gs_setup(h, ids_host.ctypes.data_as(_pi64), ids_host.size,
+                              ctypes.byref(out)), h)
+    return GsPlan(ctx, out)
+
+
+def sem_gs_destroy(gs):
+    gs.close()
+
+
+def sem_gs_info(gs):
+    nu, ns = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().sem_gs_info(gs.handle, ctypes.byref(nu), ctypes.byref(ns)), gs.ctx.handle)
+    return nu.value, ns.value
+
+
+def sem_gs(gs, u):
+    gs.ctx.bind()
+    _check(lib().sem_gs(gs.handle, _ptr(u), dtype_code(u)), gs.ctx.handle)
+
+
+def sem_gs_mult(gs, mult):
+    gs.ctx.bind()
+    _check(lib().sem_gs_mult(gs.handle, _ptr(mult)), gs.ctx.handle)

@@ -1,0 +1,171 @@
+// Gather-scatter sum u <- Q Q^T u (paper Sec. 2.1).
+//
+// Plan: only ids that occur more than once need work.  Those "shared" ids are
+// listed in the order their first local copy appears (so neighbouring threads
+// touch neighbouring memory), each with the CSR list of its local copies in
+// increasing local index.  One thread per shared id sums its copies in that
+// fixed order and writes the sum back to every copy: deterministic, no atomics.
+#include <algorithm>
+#include <vector>
+
+#include "sem_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename T>
+__global__ void gs_kernel(T* __restrict__ u, const int32_t* __restrict__ off,
+                          const int32_t* __restrict__ idx, int64_t n_shared) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= n_shared) return;
+    const int32_t b = off[g], e = off[g + 1];
+    T s = 0;
+    for (int32_t q = b; q < e; ++q) s += u[idx[q]];
+    for (int32_t q = b; q < e; ++q) u[idx[q]] = s;
+}
+
+__global__ void mult_kernel(double* __restrict__ mult, const int32_t* __restrict__ off,
+                            const int32_t* __restrict__ idx, int64_t n_shared) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= n_shared) return;
+    const int32_t b = off[g], e = off[g + 1];
+    for (int32_t q = b; q < e; ++q) mult[idx[q]] = (double)(e - b);
+}
+
+__global__ void fill_kernel(double* __restrict__ p, double v, int64_t n) {
+    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
+         L += (int64_t)gridDim.x * blockDim.x)
+        p[L] = v;
+}
+
+}  // namespace
+
+extern "C" int sem_gs_setup(sem_ctx_t ctx, const int64_t* ids, int64_t n_local, sem_gs_t* out) {
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (!out) return sem::fail(ctx, SEM_EINVAL, "sem_gs_setup: null output pointer");
+    *out = nullptr;
+    if (n_local < 0 || n_local >= ((int64_t)1 << 31))
+        return sem::fail(ctx, SEM_EINVAL, "sem_gs_setup: n_local=%lld outside [0, 2^31)", (long long)n_local);
+    if (n_local > 0 && !ids) return sem::fail(ctx, SEM_EINVAL, "sem_gs_setup: null ids");
+    int64_t idmax = -1;
+    for (int64_t L = 0; L < n_local; ++L) {
+        if (ids[L] < 0) return sem::fail(ctx, SEM_EINVAL, "sem_gs_setup: negative id at %lld", (long long)L);
+        idmax = std::max(idmax, ids[L]);
+    }
+    // Dense relabelling when ids are sparse: map them onto 0..n_distinct-1 by
+    // their sorted order, so the counting arrays stay O(n_local).
+    std::vector<int64_t> relabel;
+    const int64_t* key = ids;
+    if (idmax > 4 * n_local + 1024) {
+        std::vector<int64_t> uniq(ids, ids + n_local);
+        std::sort(uniq.begin(), uniq.end());
+        uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+        relabel.resize((size_t)n_local);
+        for (int64_t L = 0; L < n_local; ++L)
+            relabel[(size_t)L] = std::lower_bound(uniq.begin(), uniq.end(), ids[L]) - uniq.begin();
+        idmax = (int64_t)uniq.size() - 1;
+        key = relabel.data();
+    }
+    // count copies per id
+    std::vector<int32_t> count((size_t)(idmax + 1), 0);
+    for (int64_t L = 0; L < n_local; ++L) ++count[(size_t)key[L]];
+    int64_t n_unique = 0;
+    for (int32_t c : count) n_unique += (c > 0);
+    // shared ids in order of first appearance; slot[id] = shared index or -1
+    std::vector<int32_t> slot((size_t)(idmax + 1), -1);
+    std::vector<int32_t> off(1, 0);
+    int64_t n_shared = 0;
+    for (int64_t L = 0; L < n_local; ++L) {
+        const int64_t g = key[L];
+        if (count[(size_t)g] > 1 && slot[(size_t)g] < 0) {
+            slot[(size_t)g] = (int32_t)n_shared++;
+            off.push_back(off.back() + count[(size_t)g]);
+        }
+    }
+    std::vector<int32_t> idx((size_t)off.back());
+    std::vector<int32_t> fillpos(off.begin(), off.end() - 1);
+    for (int64_t L = 0; L < n_local; ++L) {
+        const int32_t s = slot[(size_t)key[L]];
+        if (s >= 0) idx[(size_t)fillpos[(size_t)s]++] = (int32_t)L;
+    }
+    std::vector<int32_t>().swap(count);
+    std::vector<int32_t>().swap(slot);
+
+    auto* gs = new sem_gs_s();
+    gs->ctx = ctx;
+    gs->n_local = n_local;
+    gs->n_unique = n_unique;
+    gs->n_shared = n_shared;
+    gs->n_entries = (int64_t)idx.size();
+    hipError_t e = hipMalloc(&gs->off, sizeof(int32_t) * off.size());
+    if (e == hipSuccess && !idx.empty()) e = hipMalloc(&gs->idx, sizeof(int32_t) * idx.size());
+    if (e == hipSuccess && n_local > 0) e = hipMalloc(&gs->mult, sizeof(double) * n_local);
+    if (e == hipSuccess) e = hipMemcpy(gs->off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !idx.empty())
+        e = hipMemcpy(gs->idx, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_local > 0) {
+        fill_kernel<<<1024, kBlock, 0, ctx->stream>>>(gs->mult, 1.0, n_local);
+        e = hipGetLastError();
+        if (e == hipSuccess && n_shared > 0) {
+            mult_kernel<<<(unsigned)((n_shared + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(
+                gs->mult, gs->off, gs->idx, n_shared);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    }
+    if (e != hipSuccess) {
+        sem_gs_destroy(gs);
+        return sem::check_hip(ctx, e, "sem_gs_setup");
+    }
+    *out = gs;
+    return SEM_OK;
+}
+
+extern "C" int sem_gs_destroy(sem_gs_t gs) {
+    if (!gs) return SEM_OK;
+    if (gs->ctx) (void)hipSetDevice(gs->ctx->device);
+    if (gs->off) (void)hipFree(gs->off);
+    if (gs->idx) (void)hipFree(gs->idx);
+    if (gs->mult) (void)hipFree(gs->mult);
+    delete gs;
+    return SEM_OK;
+}
+
+extern "C" int sem_gs_info(sem_gs_t gs, int64_t* n_unique, int64_t* n_shared) {
+    if (!gs) return sem::fail(nullptr, SEM_EINVAL, "sem_gs_info: null plan");
+    if (n_unique) *n_unique = gs->n_unique;
+    if (n_shared) *n_shared = gs->n_shared;
+    return SEM_OK;
+}
+
+extern "C" int sem_gs(sem_gs_t gs, void* u, sem_dtype_t dtype) {
+    if (!gs) return sem::fail(nullptr, SEM_EINVAL, "sem_gs: null plan");
+    sem_ctx_t ctx = gs->ctx;
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (gs->n_shared == 0) return SEM_OK;
+    if (!u) return sem::fail(ctx, SEM_EINVAL, "sem_gs: null field");
+    const unsigned grid = (unsigned)((gs->n_shared + kBlock - 1) / kBlock);
+    if (dtype == SEM_F64)
+        gs_kernel<double><<<grid, kBlock, 0, ctx->stream>>>((double*)u, gs->off, gs->idx, gs->n_shared);
+    else if (dtype == SEM_F32)
+        gs_kernel<float><<<grid, kBlock, 0, ctx->stream>>>((float*)u, gs->off, gs->idx, gs->n_shared);
+    else
+        return sem::fail(ctx, SEM_EINVAL, "sem_gs: dtype %d not supported (F64 or F32)", (int)dtype);
+    SEM_LAUNCH_CHECK(ctx);
+    return SEM_OK;
+}
+
+extern "C" int sem_gs_mult(sem_gs_t gs, double* mult) {
+    if (!gs) return sem::fail(nullptr, SEM_EINVAL, "sem_gs_mult: null plan");
+    sem_ctx_t ctx = gs->ctx;
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (gs->n_local == 0) return SEM_OK;
+    if (!mult) return sem::fail(ctx, SEM_EINVAL, "sem_gs_mult: null output");
+    SEM_HIP(ctx, hipMemcpyAsync(mult, gs->mult, sizeof(double) * gs->n_local,
+                                hipMemcpyDeviceToDevice, ctx->stream));
+    return SEM_OK;
+}

@@ -9,3 +9,27 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU check")
+
+
+import pytest  # noqa: E402
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    """Name every GPU case on stderr, flushed, before it touches the GPU."""
+    if request.node.get_closest_marker("gpu") is not None:
+        sys.stderr.write(f"\n[gpu-case] {request.node.nodeid}\n")
+        sys.stderr.flush()
+    yield
+
+
+@pytest.fixture(scope="session")
+def sem_ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test selected but no GPU is visible")
+    import paper_2506_20994_amd as P
+    ctx = P.sem_create()
+    yield ctx
+    torch.cuda.synchronize()
+    ctx.close()

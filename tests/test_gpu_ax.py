@@ -1,0 +1,154 @@
+"""GPU parity of sem_ax against the oracle (element by element)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle.ax import ax_einsum
+from oracle.gll import listing_matrices
+from oracle.quant import to_bf16, to_f32
+from oracle.mesh import box_coords, global_ids
+from oracle.geometry import geometric_factors
+from tests.helpers import rel_inf, to_dev
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2506_20994_amd")
+
+TOL64 = 1e-12      # relative inf-norm, float64 operator
+TOL_LOW = 1e-5     # float32 / bfloat16 storage vs the input-quantised oracle
+
+
+def _gpu_D(lx, dtype=torch.float64):
+    _, _, dx, dxt = P.sem_gll(lx)
+    d = to_dev(dx, dtype)
+    t = to_dev(dxt, dtype)
+    return (d, d.clone(), d.clone(), t, t.clone(), t.clone())
+
+
+def _run(ctx, u, G, h1, lx, dtype=torch.float64, out=torch.float64):
+    nel = u.shape[0]
+    du = to_dev(u, dtype)
+    dG = [to_dev(g, dtype) for g in G]
+    dh = None if h1 is None else to_dev(h1, dtype)
+    w = torch.full(u.shape, float("nan"), dtype=out, device="cuda")
+    D = _gpu_D(lx, torch.float64 if dtype == torch.float64 else torch.float32)
+    P.sem_ax(ctx, w, du, *D, dh, *dG, nel, lx)
+    torch.cuda.synchronize()
+    return w.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("lx", list(range(2, 13)))
+@pytest.mark.parametrize("nel", [1, 7, 64])
+def test_ax_f64_random(sem_ctx, lx, nel):
+    G, h1 = synth.random_spd_factors(nel, lx, 1000 + lx)
+    u = synth.local_normal(nel, lx, 2000 + lx)
+    got = _run(sem_ctx, u, G, h1, lx)
+    ref = ax_einsum(u, *listing_matrices(lx), h1, *G)
+    assert rel_inf(got, ref) <= TOL64
+
+
+@pytest.mark.parametrize("lx", [3, 8, 12])
+def test_ax_f64_no_h1(sem_ctx, lx):
+    G, _ = synth.random_spd_factors(5, lx, 31)
+    u = synth.local_normal(5, lx, 32)
+    got = _run(sem_ctx, u, G, None, lx)
+    ref = ax_einsum(u, *listing_matrices(lx), None, *G)
+    assert rel_inf(got, ref) <= TOL64
+
+
+def test_ax_detects_swapped_matrices(sem_ctx):
+    """The GPU honours each of the six matrices: passing dxt where dx belongs
+    must change the result (Dhat is not symmetric)."""
+    lx, nel = 6, 4
+    G, h1 = synth.random_spd_factors(nel, lx, 41)
+    u = synth.local_normal(nel, lx, 42)
+    dx, dy, dz, dxt, dyt, dzt = _gpu_D(lx)
+    ref = ax_einsum(u, *listing_matrices(lx), h1, *G)
+    for swap in range(3):
+        D = [dx, dy, dz, dxt, dyt, dzt]
+        D[swap], D[swap + 3] = D[swap + 3], D[swap]
+        w = torch.empty(u.shape, dtype=torch.float64, device="cuda")
+        P.sem_ax(sem_ctx, w, to_dev(u), *D, to_dev(h1), *[to_dev(g) for g in G], nel, lx)
+        torch.cuda.synchronize()
+        assert rel_inf(w.cpu().numpy(), ref) > 1e-3
+
+
+@pytest.mark.parametrize("lx", [4, 8, 10])
+def test_ax_f32(sem_ctx, lx):
+    nel = 33
+    G, h1 = synth.random_spd_factors(nel, lx, 51)
+    u = synth.local_normal(nel, lx, 52)
+    got = _run(sem_ctx, u, G, h1, lx, torch.float32, torch.float32)
+    M = [to_f32(m) for m in listing_matrices(lx)]
+    ref = ax_einsum(to_f32(u), *M, to_f32(h1), *[to_f32(g) for g in G])
+    assert rel_inf(got, ref) <= TOL_LOW
+    assert rel_inf(got, ax_einsum(u, *listing_matrices(lx), h1, *G)) <= TOL_LOW
+
+
+@pytest.mark.parametrize("lx", [4, 8, 10])
+def test_ax_bf16(sem_ctx, lx):
+    nel = 33
+    G, h1 = synth.random_spd_factors(nel, lx, 61)
+    u = synth.local_normal(nel, lx, 62)
+    du = to_dev(to_bf16(u), torch.bfloat16)
+    dG = [to_dev(to_bf16(g), torch.bfloat16) for g in G]
+    dh = to_dev(to_bf16(h1), torch.bfloat16)
+    w = torch.empty(u.shape, dtype=torch.float32, device="cuda")
+    P.sem_ax(sem_ctx, w, du, *_gpu_D(lx, torch.float32), dh, *dG, nel, lx)
+    torch.cuda.synchronize()
+    M = [to_f32(m) for m in listing_matrices(lx)]
+    ref = ax_einsum(to_bf16(u), *M, to_bf16(h1), *[to_bf16(g) for g in G])
+    assert rel_inf(w.double().cpu().numpy(), ref) <= TOL_LOW
+
+
+def test_ax_full_size_sampled(sem_ctx):
+    """32^3 box (E = 32768), lx = 8, amplitude 0.1, h1 ~ U[0.5, 2] per unique
+    node, u ~ N(0, 1) per unique node: the benchmark's workload and launch.
+    Sampled elements are recomputed by the oracle from its own geometry."""
+    from paper_2506_20994_amd.box import BoxOperator
+    n, lx, amp = 32, 8, 0.1
+    nu = (n * (lx - 1)) ** 3
+    h1u = synth.unique_uniform(nu, 0.5, 2.0, 1)
+    uu = synth.unique_normal(nu, 0)
+    op = BoxOperator(sem_ctx, n, lx, amp, h1_unique=h1u, keep_coords=False)
+    u = op.scatter(uu)
+    w = torch.empty_like(u)
+    op.ax(w, u)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    els = np.unique(np.concatenate([[0, n ** 3 - 1], rng.integers(0, n ** 3, 48)]))
+    G, _, _ = geometric_factors(*box_coords(n, lx, amp, els), lx)
+    ids = global_ids(n, lx, els)
+    ref = ax_einsum(uu[ids], *listing_matrices(lx), h1u[ids], *G)
+    got = w[torch.as_tensor(els, device="cuda")].cpu().numpy()
+    assert rel_inf(got, ref) <= TOL64
+
+
+def test_ax_is_deterministic(sem_ctx):
+    lx, nel = 8, 300
+    G, h1 = synth.random_spd_factors(nel, lx, 71)
+    u = synth.local_normal(nel, lx, 72)
+    a = _run(sem_ctx, u, G, h1, lx)
+    b = _run(sem_ctx, u, G, h1, lx)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_ax_errors(sem_ctx):
+    lx, nel = 4, 2
+    u = torch.zeros((nel, lx, lx, lx), dtype=torch.float64, device="cuda")
+    G = [torch.zeros_like(u) for _ in range(6)]
+    D = _gpu_D(lx)
+    w = torch.empty_like(u)
+    with pytest.raises(P.SemError) as ei:
+        P.sem_ax(sem_ctx, w, u, *D, None, *G, nel, 13)
+    assert ei.value.code == P.SEM_EUNSUPPORTED_LX
+    with pytest.raises(P.SemError) as ei:
+        P.sem_ax(sem_ctx, u, u, *D, None, *G, nel, lx)        # w aliases u
+    assert ei.value.code == P.SEM_EINVAL
+    with pytest.raises(P.SemError) as ei:
+        P.sem_ax(sem_ctx, w, u, *D, None, *G, -1, lx)
+    assert ei.value.code == P.SEM_EINVAL
+    P.sem_ax(sem_ctx, w, u, *D, None, *G, 0, lx)              # empty: no-op
+    with pytest.raises(P.SemError):
+        P.sem_ax(sem_ctx, w.float(), u, *D, None, *G, nel, lx, out_dtype=P.SEM_BF16)
