@@ -31,6 +31,7 @@ extern "C" {
 
 typedef struct sem_ctx_s* sem_ctx_t;
 typedef struct sem_gs_s* sem_gs_t;
+typedef struct sem_cg_s* sem_cg_t;
 
 typedef enum { SEM_F64 = 0, SEM_F32 = 1, SEM_BF16 = 2 } sem_dtype_t;
 
@@ -161,6 +162,76 @@ int sem_gs_info(sem_gs_t gs, int64_t* n_unique, int64_t* n_shared);
 int sem_gs(sem_gs_t gs, void* u, sem_dtype_t dtype);
 /* mult[L] = number of local copies of node L's id (device float64). */
 int sem_gs_mult(sem_gs_t gs, double* mult);
+
+/* Owner weights for dot products of continuous fields: wgt[L] = 1 for the
+ * first local copy (lowest local index) of each id and 0 for the others, so
+ * sum_L wgt_L u_L v_L = u_G . v_G for u = Q u_G, v = Q v_G (device float64). */
+int sem_gs_owner(sem_gs_t gs, double* wgt);
+/* In place x <- x - mean_G(x) for a continuous field: the mean over unique
+ * nodes (owner-weighted sum / number of distinct ids) is subtracted from every
+ * local node, making sum_G x_G = 0 (the solvability condition of the periodic
+ * Poisson problem).  Device float64, n_local.  Asynchronous. */
+int sem_remove_mean(sem_gs_t gs, double* x);
+
+/* ------------------------------------------------------------------ solver */
+
+/* The assembled Poisson operator A_G = sum_e Q_e^T A_e Q_e in the local
+ * layout: y = gs(Ax(x)).  Float64 device arrays, the layout of sem_ax; h1 may
+ * be NULL (h1 = 1, the Poisson case). */
+typedef struct {
+    const double* dx; const double* dy; const double* dz;
+    const double* dxt; const double* dyt; const double* dzt;
+    const double* h1;
+    const double* g11; const double* g22; const double* g33;
+    const double* g12; const double* g13; const double* g23;
+    int64_t nel;
+    int lx;
+} sem_operator_t;
+
+typedef enum {
+    SEM_SOLVE_F64 = 0,      /* float64 Jacobi-PCG throughout */
+    SEM_SOLVE_F32_IR = 1,   /* float64 refinement around float32 inner PCG */
+    SEM_SOLVE_BF16_IR = 2   /* as F32_IR, inner operator with bfloat16 h1 and G */
+} sem_solve_precision_t;
+
+typedef struct {
+    double tol;          /* stop at ||b - A x||_2 <= tol ||b||_2 over unique dofs (e.g. 1e-10) */
+    int maxit;           /* limit on operator applications of the outer float64 loop
+                            (F64) or on inner iterations summed over all outer steps (IR) */
+    int precision;       /* sem_solve_precision_t */
+    double inner_tol;    /* IR: inner relative residual target (0: 1e-6 F32, 1e-2 BF16) */
+    int inner_maxit;     /* IR: iterations per inner solve (0: 500) */
+    int max_outer;       /* IR: outer refinement steps (0: 60) */
+    int check_every;     /* iterations between host convergence checks (0: 16) */
+} sem_solve_opts_t;
+
+typedef struct {
+    int iterations;      /* operator applications in the Krylov loops (all levels) */
+    int outer;           /* IR refinement steps (0 for F64) */
+    double relres;       /* final ||b - A x||_2 / ||b||_2, recomputed in float64 */
+    double relres_hist[64]; /* relres after each outer step (IR) */
+    int converged;       /* 1 if relres <= tol */
+    int breakdown;       /* 1 if a Krylov loop met a non-positive or non-finite curvature */
+} sem_solve_stats_t;
+
+/* Create a solver for A on the plan gs: allocates the work vectors, the
+ * assembled Jacobi diagonal (sem_ax_diag + sem_gs), and for the IR modes the
+ * reduced-precision copies of h1, G and D.  `opts` fixes the precision mode.
+ * Synchronous.  The operator arrays must stay valid while the solver lives. */
+int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
+                 const sem_solve_opts_t* opts, sem_cg_t* cg);
+int sem_cg_destroy(sem_cg_t cg);
+
+/* Solve A x = b (Jacobi-preconditioned CG; Hestenes-Stiefel; Saad Alg. 9.1),
+ * or float64 iterative refinement around reduced-precision inner PCG solves.
+ * b: device float64, local layout, continuous (b = Q b_G) with sum_G b_G = 0
+ * (the periodic operator's null space is the constants).  x: device float64
+ * output, local layout, continuous, with sum_G x_G = 0.  Starts from x = 0.
+ * Returns SEM_OK, SEM_NOT_CONVERGED (limit reached; x is the last iterate) or
+ * SEM_EBREAKDOWN.  Synchronous (reads convergence flags every check_every
+ * iterations). */
+int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_solve_opts_t* opts,
+                 sem_solve_stats_t* stats);
 
 #ifdef __cplusplus
 }

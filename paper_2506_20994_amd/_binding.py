@@ -10,7 +10,34 @@ __all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONV
            "sem_sync", "sem_gll", "sem_box_mesh", "sem_geometry", "sem_scatter",
            "sem_ax_diag", "sem_fourier", "sem_convert", "sem_ax", "sem_gs_setup",
            "sem_gs_destroy", "sem_gs_info", "sem_gs", "sem_gs_mult", "Context", "GsPlan",
-           "dtype_code", "EXPORTS"]
+           "dtype_code", "EXPORTS", "sem_gs_owner", "sem_remove_mean", "sem_cg_setup",
+           "sem_cg_destroy", "sem_cg_solve", "SemOperator", "SemSolveOpts", "SemSolveStats",
+           "CgSolver", "SEM_SOLVE_F64", "SEM_SOLVE_F32_IR", "SEM_SOLVE_BF16_IR"]
+
+SEM_SOLVE_F64, SEM_SOLVE_F32_IR, SEM_SOLVE_BF16_IR = 0, 1, 2
+
+
+class SemOperator(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("dx", "dy", "dz", "dxt", "dyt", "dzt", "h1", "g11", "g22", "g33", "g12", "g13",
+                 "g23")] + [("nel", ctypes.c_int64), ("lx", ctypes.c_int)]
+
+
+class SemSolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("precision", ctypes.c_int),
+                ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
+                ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+class SemSolveStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("outer", ctypes.c_int), ("relres", ctypes.c_double),
+                ("relres_hist", ctypes.c_double * 64), ("converged", ctypes.c_int),
+                ("breakdown", ctypes.c_int)]
+
+    def as_dict(self):
+        return {"iterations": self.iterations, "outer": self.outer, "relres": self.relres,
+                "relres_hist": list(self.relres_hist[:self.outer]),
+                "converged": bool(self.converged), "breakdown": bool(self.breakdown)}
 
 SEM_F64, SEM_F32, SEM_BF16 = 0, 1, 2
 SEM_OK, SEM_NOT_CONVERGED, SEM_FELL_BACK = 0, 1, 2
@@ -47,6 +74,11 @@ EXPORTS = {
     "sem_gs_info": (_int, [_vp, _pi64, _pi64]),
     "sem_gs": (_int, [_vp, _vp, _int]),
     "sem_gs_mult": (_int, [_vp, _vp]),
+    "sem_gs_owner": (_int, [_vp, _vp]),
+    "sem_remove_mean": (_int, [_vp, _vp]),
+    "sem_cg_setup": (_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    "sem_cg_destroy": (_int, [_vp]),
+    "sem_cg_solve": (_int, [_vp, _vp, _vp, _vp, _vp]),
 }
 
 _LIB = None
@@ -249,3 +281,59 @@ def sem_gs(gs, u):
 def sem_gs_mult(gs, mult):
     gs.ctx.bind()
     _check(lib().sem_gs_mult(gs.handle, _ptr(mult)), gs.ctx.handle)
+
+
+def sem_gs_owner(gs, wgt):
+    gs.ctx.bind()
+    _check(lib().sem_gs_owner(gs.handle, _ptr(wgt)), gs.ctx.handle)
+
+
+def sem_remove_mean(gs, x):
+    gs.ctx.bind()
+    _check(lib().sem_remove_mean(gs.handle, _ptr(x)), gs.ctx.handle)
+
+
+class CgSolver:
+    def __init__(self, ctx, handle, keep):
+        self.ctx, self.handle, self._keep = ctx, handle, keep
+
+    def close(self):
+        if self.handle:
+            lib().sem_cg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _opts(tol=1e-10, maxit=0, precision=SEM_SOLVE_F64, inner_tol=0.0, inner_maxit=0,
+          max_outer=0, check_every=0):
+    return SemSolveOpts(tol, maxit, precision, inner_tol, inner_maxit, max_outer, check_every)
+
+
+def sem_cg_setup(ctx, gs, D, h1, G, nel, lx, **opts):
+    """D = (dx, dy, dz, dxt, dyt, dzt), G = (g11, g22, g33, g12, g13, g23): float64
+    device tensors.  opts: see SemSolveOpts (precision fixed here)."""
+    A = SemOperator(*[_ptr(t) for t in D], _ptr(h1), *[_ptr(t) for t in G], nel, lx)
+    o = _opts(**opts)
+    h = ctx.bind()
+    out = _vp()
+    _check(lib().sem_cg_setup(h, gs.handle, ctypes.byref(A), ctypes.byref(o), ctypes.byref(out)), h)
+    return CgSolver(ctx, out, (D, h1, G, gs))
+
+
+def sem_cg_destroy(cg):
+    cg.close()
+
+
+def sem_cg_solve(cg, x, b, **opts):
+    """Returns (status, stats dict).  Raises on negative status."""
+    o = _opts(**opts)
+    st = SemSolveStats()
+    cg.ctx.bind()
+    rc = lib().sem_cg_solve(cg.handle, _ptr(x), _ptr(b), ctypes.byref(o), ctypes.byref(st))
+    _check(rc, cg.ctx.handle)
+    return rc, st.as_dict()

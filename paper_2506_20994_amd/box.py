@@ -67,3 +67,16 @@ class BoxOperator:
         """w = gs(Ax(u)): the assembled operator in the local layout."""
         self.ax(w, u)
         B.sem_gs(self.gs, w)
+
+    def fourier_rhs(self, k, amp, phase):
+        """Continuous right-hand side b = Q Q^T (B f) - mean for the Fourier sum f
+        at the node coordinates (needs keep_coords=True)."""
+        b = torch.empty_like(self.bm)
+        B.sem_fourier(self.ctx, b, self.x, self.y, self.z, self.bm, k, amp, phase)
+        B.sem_gs(self.gs, b)
+        B.sem_remove_mean(self.gs, b)
+        return b
+
+    def solver(self, precision=0, **opts):
+        return B.sem_cg_setup(self.ctx, self.gs, self.D, self.h1, self.G, self.nel, self.lx,
+                              precision=precision, **opts)

@@ -1,7 +1,8 @@
 // The element-local stiffness operator w = A_e u (paper Sec. 4.2, Listing 2).
 //
 // Work decomposition (gfx950, wave64): a workgroup holds EPB elements; each
-// element is owned by lx*lx threads, thread (i, j) owning the column
+// element is owned by lx*lx threads (one whole wave at lx = 8), thread (i, j)
+// owning the column
 // u[e][0..lx)[j][i].  The column lives in registers, so the t-derivative is a
 // register-only sum, and the t-flux of each slice is folded into the
 // transposed t-sum as soon as it is formed.  The r- and s-derivatives need the
@@ -18,42 +19,66 @@
 
 namespace {
 
+// Streamed arrays are touched once per application, so they are read and
+// written with the nontemporal hint: on gfx950 this keeps them from displacing
+// reusable lines and measurably raises the achieved HBM bandwidth.
 template <typename T> struct Load;
-template <> struct Load<double> { __device__ static double get(const double* p, int64_t o) { return p[o]; } };
-template <> struct Load<float> { __device__ static float get(const float* p, int64_t o) { return p[o]; } };
+template <> struct Load<double> {
+    __device__ static double get(const double* p, int64_t o) { return __builtin_nontemporal_load(p + o); }
+};
+template <> struct Load<float> {
+    __device__ static float get(const float* p, int64_t o) { return __builtin_nontemporal_load(p + o); }
+};
 template <> struct Load<uint16_t> {
-    __device__ static float get(const uint16_t* p, int64_t o) { return __uint_as_float((uint32_t)p[o] << 16); }
+    __device__ static float get(const uint16_t* p, int64_t o) {
+        return __uint_as_float((uint32_t)__builtin_nontemporal_load(p + o) << 16);
+    }
 };
 
-template <int LX> struct Shape;
-// elements per workgroup: keep the workgroup near a whole number of waves and
-// the three LDS element buffers of float64 within about 64 KiB.
-template <> struct Shape<2>  { static constexpr int EPB = 64; };
-template <> struct Shape<3>  { static constexpr int EPB = 28; };
-template <> struct Shape<4>  { static constexpr int EPB = 16; };
-template <> struct Shape<5>  { static constexpr int EPB = 10; };
-template <> struct Shape<6>  { static constexpr int EPB = 7; };
-template <> struct Shape<7>  { static constexpr int EPB = 5; };
-template <> struct Shape<8>  { static constexpr int EPB = 4; };
-template <> struct Shape<9>  { static constexpr int EPB = 3; };
-template <> struct Shape<10> { static constexpr int EPB = 2; };
-template <> struct Shape<11> { static constexpr int EPB = 2; };
-template <> struct Shape<12> { static constexpr int EPB = 1; };
+template <typename T>
+__device__ __forceinline__ void store_nt(T* p, int64_t o, T v) { __builtin_nontemporal_store(v, p + o); }
 
-template <int LX, int EPB, typename TS, typename TC, typename TW>
+// Elements whose lx*lx columns fit inside one 64-lane wave (lx = 2, 4, 8) are
+// "wave-private": no other wave touches their LDS, so the forward and
+// transposed phases need no workgroup barrier, and slice k of u can be
+// overwritten by the r-flux of slice k as soon as the wave has read it (LDS
+// operations of one wave complete in order).  Other lx use workgroup
+// barriers and a separate r-flux buffer.
+template <int LX> struct Shape {
+    static constexpr bool kWavePrivate = (64 % (LX * LX)) == 0;
+    // elements per workgroup: about four waves, LDS of float64 within ~64 KiB
+    static constexpr int EPB = LX == 2 ? 64 : LX == 3 ? 28 : LX == 4 ? 16 : LX == 5 ? 10
+                             : LX == 6 ? 7 : LX == 7 ? 5 : LX == 8 ? 4 : LX == 9 ? 3
+                             : LX <= 11 ? 2 : 1;
+};
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// FUSE: the solver form.  The kernel returns at once when *skip is non-zero
+// (a converged solve), and each workgroup writes sum_L u_L w_L over its
+// elements, accumulated in float64, to dot[blockIdx.x] (p^T A p before
+// gather-scatter).
+template <int LX, int EPB, typename TU, typename TS, typename TC, typename TW, bool FUSE>
 __global__ void __launch_bounds__(EPB * LX * LX)
-ax_kernel(TW* __restrict__ w, const TS* __restrict__ u,
+ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
           const TC* __restrict__ dx, const TC* __restrict__ dy, const TC* __restrict__ dz,
           const TC* __restrict__ dxt, const TC* __restrict__ dyt, const TC* __restrict__ dzt,
           const TS* __restrict__ h1, const TS* __restrict__ g11, const TS* __restrict__ g22,
           const TS* __restrict__ g33, const TS* __restrict__ g12, const TS* __restrict__ g13,
-          const TS* __restrict__ g23, int64_t nel) {
+          const TS* __restrict__ g23, int64_t nel, const int* __restrict__ skip,
+          double* __restrict__ dot) {
     constexpr int L2 = LX * LX;
     constexpr int L3 = L2 * LX;
-    __shared__ TC s_u[EPB * L3];   // the element's u
-    __shared__ TC s_r[EPB * L3];   // r-flux
-    __shared__ TC s_s[EPB * L3];   // s-flux
-    __shared__ TC s_d[6 * L2];     // dx, dy, dz, dxt, dyt, dzt
+    constexpr bool WP = Shape<LX>::kWavePrivate;
+    if (FUSE && *skip) return;
+    __shared__ TC s_u[EPB * L3];               // the element's u (wave-private: then the r-flux)
+    __shared__ TC s_s[EPB * L3];               // s-flux
+    __shared__ TC s_r0[WP ? 1 : EPB * L3];     // r-flux when elements span waves
+    __shared__ TC s_d[6 * L2];                 // dx, dy, dz, dxt, dyt, dzt
 
     const int tid = threadIdx.x;
     const int el = tid / L2;
@@ -64,13 +89,9 @@ ax_kernel(TW* __restrict__ w, const TS* __restrict__ u,
     const bool live = e < nel;
     const int64_t base = e * L3 + ij;
     TC* su = s_u + el * L3;
-    TC* sr = s_r + el * L3;
     TC* ss = s_s + el * L3;
-    const TC* sdx = s_d;
-    const TC* sdy = s_d + L2;
+    TC* sr = WP ? su : s_r0 + el * L3;
     const TC* sdz = s_d + 2 * L2;
-    const TC* sdxt = s_d + 3 * L2;
-    const TC* sdyt = s_d + 4 * L2;
     const TC* sdzt = s_d + 5 * L2;
 
     for (int q = tid; q < L2; q += EPB * L2) {
@@ -85,21 +106,20 @@ ax_kernel(TW* __restrict__ w, const TS* __restrict__ u,
     // the thread's column of u, kept in registers for the t-derivative
     TC uc[LX];
 #pragma unroll
-    for (int k = 0; k < LX; ++k) {
-        uc[k] = live ? (TC)Load<TS>::get(u, base + k * L2) : TC(0);
-        su[k * L2 + ij] = uc[k];
-    }
-    __syncthreads();
+    for (int k = 0; k < LX; ++k) uc[k] = live ? (TC)Load<TU>::get(u, base + k * L2) : TC(0);
+#pragma unroll
+    for (int k = 0; k < LX; ++k) su[k * L2 + ij] = uc[k];
+    __syncthreads();   // s_d is shared by every wave of the workgroup
 
     TC di[LX], dj[LX];
 #pragma unroll
     for (int l = 0; l < LX; ++l) {
-        di[l] = sdx[l * LX + i];
-        dj[l] = sdy[l * LX + j];
+        di[l] = s_d[l * LX + i];
+        dj[l] = s_d[L2 + l * LX + j];
     }
 
     // forward passes slice by slice; the t-flux of slice k is folded straight
-    // into the transposed t-pass: wt[m] += dzt[k, m] * vt_k
+    // into the transposed t-sum: wt[m] += dzt[k, m] * vt_k
     TC wt[LX];
 #pragma unroll
     for (int m = 0; m < LX; ++m) wt[m] = 0;
@@ -119,19 +139,23 @@ ax_kernel(TW* __restrict__ w, const TS* __restrict__ u,
             G12 = Load<TS>::get(g12, o); G13 = Load<TS>::get(g13, o); G23 = Load<TS>::get(g23, o);
             if (h1) H = Load<TS>::get(h1, o);
         }
-        sr[k * L2 + ij] = H * (G11 * r + G12 * s + G13 * t);
-        ss[k * L2 + ij] = H * (G12 * r + G22 * s + G23 * t);
+        const TC vr = H * (G11 * r + G12 * s + G13 * t);
+        const TC vs = H * (G12 * r + G22 * s + G23 * t);
         const TC vt = H * (G13 * r + G23 * s + G33 * t);
+        if (WP) wave_sync();   // every lane has read slice k before it is overwritten
+        sr[k * L2 + ij] = vr;
+        ss[k * L2 + ij] = vs;
 #pragma unroll
         for (int m = 0; m < LX; ++m) wt[m] += sdzt[k * LX + m] * vt;
     }
-    __syncthreads();
+    if (WP) wave_sync(); else __syncthreads();
 
 #pragma unroll
     for (int l = 0; l < LX; ++l) {
-        di[l] = sdxt[l * LX + i];
-        dj[l] = sdyt[l * LX + j];
+        di[l] = s_d[3 * L2 + l * LX + i];
+        dj[l] = s_d[4 * L2 + l * LX + j];
     }
+    double pw = 0.0;
 #pragma unroll
     for (int k = 0; k < LX; ++k) {
         TC acc = wt[k];
@@ -140,40 +164,62 @@ ax_kernel(TW* __restrict__ w, const TS* __restrict__ u,
             acc += di[l] * sr[k * L2 + j * LX + l];
             acc += dj[l] * ss[k * L2 + l * LX + i];
         }
-        if (live) w[base + k * L2] = (TW)acc;
+        if (live) store_nt(w, base + k * L2, (TW)acc);
+        if (FUSE) pw += (double)uc[k] * (double)(TW)acc;
+    }
+    if (FUSE) {
+        constexpr int NT = EPB * L2;
+        if constexpr (NT % 64 == 0) {          // whole waves: shuffle, then one value per wave
+            __shared__ double s_red[NT / 64];
+            pw = sem::wave_sum(pw);
+            if ((tid & 63) == 0) s_red[tid >> 6] = pw;
+            __syncthreads();
+            if (tid == 0) {
+                double t = 0.0;
+                for (int q = 0; q < NT / 64; ++q) t += s_red[q];
+                dot[blockIdx.x] = t;
+            }
+        } else {                               // partial last wave: LDS tree
+            __shared__ double s_red[NT];
+            s_red[tid] = pw;
+            __syncthreads();
+            constexpr int P2 = NT <= 128 ? 64 : NT <= 256 ? 128 : 256;
+            for (int st = P2; st > 0; st >>= 1) {
+                if (tid < st && tid + st < NT) s_red[tid] += s_red[tid + st];
+                __syncthreads();
+            }
+            if (tid == 0) dot[blockIdx.x] = s_red[0];
+        }
     }
 }
 
-template <int LX, typename TS, typename TC, typename TW>
+template <int LX, typename TU, typename TS, typename TC, typename TW>
 int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const void* h1,
-              const void* const* G, int64_t nel) {
+              const void* const* G, int64_t nel, const int* skip, double* dot) {
     constexpr int EPB = Shape<LX>::EPB;
     const int64_t blocks = (nel + EPB - 1) / EPB;
     if (blocks > 0x7fffffff) return sem::fail(ctx, SEM_EINVAL, "sem_ax: nel too large");
-    ax_kernel<LX, EPB, TS, TC, TW><<<(unsigned)blocks, EPB * LX * LX, 0, ctx->stream>>>(
-        (TW*)w, (const TS*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2],
-        (const TC*)D[3], (const TC*)D[4], (const TC*)D[5], (const TS*)h1,
-        (const TS*)G[0], (const TS*)G[1], (const TS*)G[2], (const TS*)G[3], (const TS*)G[4],
-        (const TS*)G[5], nel);
+#define SEM_AX_ARGS (TW*)w, (const TU*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2], \
+        (const TC*)D[3], (const TC*)D[4], (const TC*)D[5], (const TS*)h1, (const TS*)G[0],  \
+        (const TS*)G[1], (const TS*)G[2], (const TS*)G[3], (const TS*)G[4], (const TS*)G[5], \
+        nel, skip, dot
+    if (dot)
+        ax_kernel<LX, EPB, TU, TS, TC, TW, true><<<(unsigned)blocks, EPB * LX * LX, 0, ctx->stream>>>(SEM_AX_ARGS);
+    else
+        ax_kernel<LX, EPB, TU, TS, TC, TW, false><<<(unsigned)blocks, EPB * LX * LX, 0, ctx->stream>>>(SEM_AX_ARGS);
+#undef SEM_AX_ARGS
     SEM_LAUNCH_CHECK(ctx);
     return SEM_OK;
 }
 
-template <typename TS, typename TC, typename TW>
+template <typename TU, typename TS, typename TC, typename TW>
 int dispatch(sem_ctx_t ctx, int lx, void* w, const void* u, const void* const* D,
-             const void* h1, const void* const* G, int64_t nel) {
+             const void* h1, const void* const* G, int64_t nel, const int* skip, double* dot) {
     switch (lx) {
-        case 2: return launch_lx<2, TS, TC, TW>(ctx, w, u, D, h1, G, nel);
-        case 3: return launch_lx<3, TS, TC, TW>(ctx, w, u, D, h1, G, nel);
-        case 4: return launch_lx<4, TS, TC, TW>(ctx, w, u, D, h1, G, nel);
-        case 5: return launch_lx<5, TS, TC, TW>(ctx, w, u, D, h1, G, nel);
-        case 6: return launch_lx<6, TS, TC, TW>(ctx, w, u, D, h1, G, nel);
-        case 7: return launch_lx<7, TS, TC, TW>(ctx, w, u, D, h1, G, nel);
-        case 8: return launch_lx<8, TS, TC, TW>(ctx, w, u, D, h1, G, nel);
-        case 9: return launch_lx<9, TS, TC, TW>(ctx, w, u, D, h1, G, nel);
-        case 10: return launch_lx<10, TS, TC, TW>(ctx, w, u, D, h1, G, nel);
-        case 11: return launch_lx<11, TS, TC, TW>(ctx, w, u, D, h1, G, nel);
-        case 12: return launch_lx<12, TS, TC, TW>(ctx, w, u, D, h1, G, nel);
+#define SEM_AX_CASE(L) case L: return launch_lx<L, TU, TS, TC, TW>(ctx, w, u, D, h1, G, nel, skip, dot);
+        SEM_AX_CASE(2) SEM_AX_CASE(3) SEM_AX_CASE(4) SEM_AX_CASE(5) SEM_AX_CASE(6) SEM_AX_CASE(7)
+        SEM_AX_CASE(8) SEM_AX_CASE(9) SEM_AX_CASE(10) SEM_AX_CASE(11) SEM_AX_CASE(12)
+#undef SEM_AX_CASE
         default: return sem::fail(ctx, SEM_EUNSUPPORTED_LX, "sem_ax: lx=%d outside [2,12]", lx);
     }
 }
@@ -216,7 +262,38 @@ extern "C" int sem_ax(sem_ctx_t ctx, void* w, const void* u, const void* dx, con
     bool alias = overlaps(w, nw, u, nf) || overlaps(w, nw, h1, nf);
     for (int q = 0; q < 6; ++q) alias = alias || overlaps(w, nw, G[q], nf) || overlaps(w, nw, D[q], nd);
     if (alias) return sem::fail(ctx, SEM_EINVAL, "sem_ax: output overlaps an input");
-    if (f64) return dispatch<double, double, double>(ctx, lx, w, u, D, h1, G, nel);
-    if (field_dtype == SEM_F32) return dispatch<float, float, float>(ctx, lx, w, u, D, h1, G, nel);
-    return dispatch<uint16_t, float, float>(ctx, lx, w, u, D, h1, G, nel);
+    if (f64) return dispatch<double, double, double, double>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr);
+    if (field_dtype == SEM_F32) return dispatch<float, float, float, float>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr);
+    return dispatch<uint16_t, uint16_t, float, float>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr);
 }
+
+namespace sem {
+
+int ax_blocks(int lx, int64_t nel) {
+    int epb = 1;
+    switch (lx) {
+#define SEM_AX_EPB(L) case L: epb = Shape<L>::EPB; break;
+        SEM_AX_EPB(2) SEM_AX_EPB(3) SEM_AX_EPB(4) SEM_AX_EPB(5) SEM_AX_EPB(6) SEM_AX_EPB(7)
+        SEM_AX_EPB(8) SEM_AX_EPB(9) SEM_AX_EPB(10) SEM_AX_EPB(11) SEM_AX_EPB(12)
+#undef SEM_AX_EPB
+        default: break;
+    }
+    return (int)((nel + epb - 1) / epb);
+}
+
+int launch_ax(sem_ctx_t ctx, AxKind kind, const AxArgs& a, void* w, const void* u,
+              const int* skip, double* dot) {
+    const void* D[6] = {a.D[0], a.D[1], a.D[2], a.D[3], a.D[4], a.D[5]};
+    const void* G[6] = {a.G[0], a.G[1], a.G[2], a.G[3], a.G[4], a.G[5]};
+    switch (kind) {
+        case AxKind::F64:
+            return dispatch<double, double, double, double>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot);
+        case AxKind::F32:
+            return dispatch<float, float, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot);
+        case AxKind::F32_BF16:
+            return dispatch<float, uint16_t, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot);
+    }
+    return fail(ctx, SEM_EINVAL, "launch_ax: bad kind");
+}
+
+}  // namespace sem

@@ -33,6 +33,14 @@ __global__ void mult_kernel(double* __restrict__ mult, const int32_t* __restrict
     for (int32_t q = b; q < e; ++q) mult[idx[q]] = (double)(e - b);
 }
 
+__global__ void owner_kernel(double* __restrict__ owner, const int32_t* __restrict__ off,
+                             const int32_t* __restrict__ idx, int64_t n_shared) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= n_shared) return;
+    const int32_t b = off[g], e = off[g + 1];
+    for (int32_t q = b + 1; q < e; ++q) owner[idx[q]] = 0.0;   // idx is ascending: idx[b] owns
+}
+
 __global__ void fill_kernel(double* __restrict__ p, double v, int64_t n) {
     for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
          L += (int64_t)gridDim.x * blockDim.x)
@@ -102,15 +110,18 @@ extern "C" int sem_gs_setup(sem_ctx_t ctx, const int64_t* ids, int64_t n_local, 
     hipError_t e = hipMalloc(&gs->off, sizeof(int32_t) * off.size());
     if (e == hipSuccess && !idx.empty()) e = hipMalloc(&gs->idx, sizeof(int32_t) * idx.size());
     if (e == hipSuccess && n_local > 0) e = hipMalloc(&gs->mult, sizeof(double) * n_local);
+    if (e == hipSuccess && n_local > 0) e = hipMalloc(&gs->owner, sizeof(double) * n_local);
     if (e == hipSuccess) e = hipMemcpy(gs->off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !idx.empty())
         e = hipMemcpy(gs->idx, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && n_local > 0) {
         fill_kernel<<<1024, kBlock, 0, ctx->stream>>>(gs->mult, 1.0, n_local);
+        fill_kernel<<<1024, kBlock, 0, ctx->stream>>>(gs->owner, 1.0, n_local);
         e = hipGetLastError();
         if (e == hipSuccess && n_shared > 0) {
-            mult_kernel<<<(unsigned)((n_shared + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(
-                gs->mult, gs->off, gs->idx, n_shared);
+            const unsigned gr = (unsigned)((n_shared + kBlock - 1) / kBlock);
+            mult_kernel<<<gr, kBlock, 0, ctx->stream>>>(gs->mult, gs->off, gs->idx, n_shared);
+            owner_kernel<<<gr, kBlock, 0, ctx->stream>>>(gs->owner, gs->off, gs->idx, n_shared);
             e = hipGetLastError();
         }
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -129,6 +140,7 @@ extern "C" int sem_gs_destroy(sem_gs_t gs) {
     if (gs->off) (void)hipFree(gs->off);
     if (gs->idx) (void)hipFree(gs->idx);
     if (gs->mult) (void)hipFree(gs->mult);
+    if (gs->owner) (void)hipFree(gs->owner);
     delete gs;
     return SEM_OK;
 }
@@ -166,6 +178,18 @@ extern "C" int sem_gs_mult(sem_gs_t gs, double* mult) {
     if (gs->n_local == 0) return SEM_OK;
     if (!mult) return sem::fail(ctx, SEM_EINVAL, "sem_gs_mult: null output");
     SEM_HIP(ctx, hipMemcpyAsync(mult, gs->mult, sizeof(double) * gs->n_local,
+                                hipMemcpyDeviceToDevice, ctx->stream));
+    return SEM_OK;
+}
+
+extern "C" int sem_gs_owner(sem_gs_t gs, double* wgt) {
+    if (!gs) return sem::fail(nullptr, SEM_EINVAL, "sem_gs_owner: null plan");
+    sem_ctx_t ctx = gs->ctx;
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (gs->n_local == 0) return SEM_OK;
+    if (!wgt) return sem::fail(ctx, SEM_EINVAL, "sem_gs_owner: null output");
+    SEM_HIP(ctx, hipMemcpyAsync(wgt, gs->owner, sizeof(double) * gs->n_local,
                                 hipMemcpyDeviceToDevice, ctx->stream));
     return SEM_OK;
 }

@@ -24,6 +24,7 @@ struct sem_gs_s {
     int32_t* off = nullptr;     // device, n_shared + 1
     int32_t* idx = nullptr;     // device, n_entries local indices
     double* mult = nullptr;     // device, n_local multiplicities
+    double* owner = nullptr;    // device, n_local: 1 on the first copy of each id, else 0
 };
 
 namespace sem {
@@ -41,6 +42,35 @@ inline bool lx_ok(int lx) { return lx >= SEM_LX_MIN && lx <= SEM_LX_MAX; }
 
 // host-side GLL quantities (setup.hip)
 void gll_host(int lx, double* xi, double* w, double* dhat /* dhat[i*lx+l] = l_l'(xi_i) */);
+
+// operator arrays (device pointers); D in the compute precision, h1/G in the
+// storage precision of the chosen AxKind
+struct AxArgs {
+    const void* D[6];
+    const void* h1;
+    const void* G[6];
+    int64_t nel;
+    int lx;
+};
+enum class AxKind {
+    F64,        // u, h1, G, D, w float64
+    F32,        // u, h1, G, D, w float32
+    F32_BF16    // u, D, w float32; h1, G bfloat16; float32 arithmetic
+};
+// Launch the operator.  With dot != nullptr it also skips when *skip != 0 and
+// writes one float64 partial of sum u.w per workgroup (ax_blocks() of them).
+int launch_ax(sem_ctx_t ctx, AxKind kind, const AxArgs& a, void* w, const void* u,
+              const int* skip, double* dot);
+int ax_blocks(int lx, int64_t nel);
+
+#ifdef __HIPCC__
+// sum over the 64 lanes of a wave
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+#endif
 
 }  // namespace sem
 

@@ -1,0 +1,121 @@
+"""GPU solves (float64 Jacobi-PCG and float64 refinement around float32 /
+bfloat16 inner solves) against the oracle: right-hand-side parity, residuals
+recomputed by the oracle's operator, errors against an oracle solution."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle.solve import BoxProblem, pcg
+from oracle.gs import scatter
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2506_20994_amd")
+from paper_2506_20994_amd.box import BoxOperator  # noqa: E402
+
+
+def _setup(ctx, n, lx, amp, seed_rhs=2, with_h1=False):
+    nu = (n * (lx - 1)) ** 3
+    h1u = synth.unique_uniform(nu, 0.5, 2.0, 1) if with_h1 else None
+    op = BoxOperator(ctx, n, lx, amp, h1_unique=h1u)
+    k, a, ph = synth.fourier_modes(seed_rhs)
+    b = op.fourier_rhs(k, a, ph)
+    ref = BoxProblem(n, lx, amp, h1u)
+    bref = ref.fourier_rhs(k, a, ph)
+    return op, b, ref, bref
+
+
+def _unique(ref, xl):
+    """unique vector from a continuous local one (take the owner copy)"""
+    out = np.zeros(ref.nu)
+    out[ref.ids.ravel()] = xl.ravel()
+    return out
+
+
+@pytest.mark.parametrize("n,lx,amp,h1", [(3, 5, 0.1, True), (2, 8, 0.15, False), (4, 4, 0.0, False)])
+def test_pcg_f64(sem_ctx, n, lx, amp, h1):
+    op, b, ref, bref = _setup(sem_ctx, n, lx, amp, with_h1=h1)
+    np.testing.assert_allclose(_unique(ref, b.cpu().numpy()), bref, rtol=0,
+                               atol=1e-13 * np.abs(bref).max())
+    cg = op.solver(P.SEM_SOLVE_F64)
+    x = torch.empty_like(b)
+    rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10)
+    torch.cuda.synchronize()
+    assert rc == P.SEM_OK and st["converged"], st
+    xg = _unique(ref, x.cpu().numpy())
+    # the oracle re-checks the residual with its own operator and right-hand side
+    rel = np.linalg.norm(bref - ref.apply(xg)) / np.linalg.norm(bref)
+    assert rel <= 1.2e-10 and st["relres"] <= 1e-10
+    assert abs(xg.sum()) <= 1e-10 * np.abs(xg).sum()
+    xo, ito, _ = pcg(ref.apply, bref, 1.0 / ref.diagonal(), tol=1e-10)
+    assert abs(st["iterations"] - ito) <= 2, (st["iterations"], ito)
+    xs, _, _ = pcg(ref.apply, bref, 1.0 / ref.diagonal(), tol=1e-13)
+    assert np.max(np.abs(xg - xs)) <= 1e-6 * np.max(np.abs(xs))
+    cg.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_refinement(sem_ctx, prec):
+    n, lx, amp = 3, 8, 0.1
+    op, b, ref, bref = _setup(sem_ctx, n, lx, amp)
+    code = P.SEM_SOLVE_F32_IR if prec == "f32" else P.SEM_SOLVE_BF16_IR
+    cg = op.solver(code)
+    x = torch.empty_like(b)
+    rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10, precision=code)
+    torch.cuda.synchronize()
+    assert rc == P.SEM_OK and st["converged"], st
+    assert st["outer"] >= 2
+    xg = _unique(ref, x.cpu().numpy())
+    rel = np.linalg.norm(bref - ref.apply(xg)) / np.linalg.norm(bref)
+    assert rel <= 1.2e-10
+    xs, _, _ = pcg(ref.apply, bref, 1.0 / ref.diagonal(), tol=1e-13)
+    err = np.max(np.abs(xg - xs)) / np.max(np.abs(xs))
+    print(f"{prec} IR: outer={st['outer']} iters={st['iterations']} relres={st['relres']:.2e} "
+          f"err={err:.2e}")
+    assert err <= 1e-6
+    cg.close()
+
+
+def test_solve_is_deterministic(sem_ctx):
+    op, b, _, _ = _setup(sem_ctx, 2, 6, 0.1)
+    cg = op.solver(P.SEM_SOLVE_F64)
+    x1, x2 = torch.empty_like(b), torch.empty_like(b)
+    P.sem_cg_solve(cg, x1, b, tol=1e-10)
+    P.sem_cg_solve(cg, x2, b, tol=1e-10)
+    torch.cuda.synchronize()
+    assert torch.equal(x1, x2)
+    cg.close()
+
+
+def test_not_converged_and_errors(sem_ctx):
+    op, b, _, _ = _setup(sem_ctx, 2, 6, 0.1)
+    cg = op.solver(P.SEM_SOLVE_F64)
+    x = torch.empty_like(b)
+    rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10, maxit=3, check_every=1)
+    assert rc == P.SEM_NOT_CONVERGED and st["iterations"] == 3 and not st["converged"]
+    with pytest.raises(P.SemError):
+        P.sem_cg_solve(cg, x, b, tol=1e-10, precision=P.SEM_SOLVE_F32_IR)   # differs from set-up
+    with pytest.raises(P.SemError):
+        P.sem_cg_solve(cg, x, b, tol=0.0)
+    # zero right-hand side: x = 0 immediately
+    z = torch.zeros_like(b)
+    rc, st = P.sem_cg_solve(cg, x, z, tol=1e-10)
+    assert rc == P.SEM_OK and st["iterations"] == 0 and float(x.abs().max()) == 0.0
+    cg.close()
+
+
+def test_remove_mean_and_owner(sem_ctx):
+    n, lx = 2, 5
+    op = BoxOperator(sem_ctx, n, lx, 0.0, keep_coords=False)
+    nu = (n * (lx - 1)) ** 3
+    uu = synth.unique_normal(nu, 3) + 5.0
+    u = op.scatter(uu)
+    wgt = torch.empty_like(u)
+    P.sem_gs_owner(op.gs, wgt)
+    assert float(wgt.sum()) == nu
+    assert float((wgt * u).sum()) == pytest.approx(uu.sum(), rel=1e-13)
+    P.sem_remove_mean(op.gs, u)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(u.cpu().numpy(), scatter(uu - uu.mean(), op.ids.cpu().numpy()),
+                               atol=1e-13)
