@@ -12,6 +12,14 @@ Extra fields:
   cpu_baseline  the plain-C oracle loop nest timed on this host's cores on a
                 bounded sample of the same workload shape.
   gs            gather-scatter timing on the same mesh.
+  solve         Poisson solve to relative residual 1e-10 on the same 32^3 lx = 8
+                box (amplitude 0.1, h1 = 1, right-hand side of 32 random Fourier
+                modes with |k|_inf <= 8, mean removed): float64 Jacobi-PCG against
+                float64 refinement with float32 and with bfloat16-factor inner
+                solves; wall time of sem_cg_solve (set-up excluded).
+
+--mode copy times a plain 1 GiB device copy (used to calibrate the HBM byte
+counters of rocprofv3); it prints nothing on stdout.
 """
 import argparse
 import hashlib
@@ -68,6 +76,34 @@ def cpu_baseline(lx, target_s=10.0):
                       f"applications of the plain-C loop nest in {el:.1f} s"}
 
 
+def solve_comparison(ctx, P, n, lx, amp, tol=1e-10):
+    import torch
+    import synth
+    from paper_2506_20994_amd.box import BoxOperator
+    op = BoxOperator(ctx, n, lx, amp)
+    k, a, ph = synth.fourier_modes(2)
+    b = op.fourier_rhs(k, a, ph)
+    x = torch.empty_like(b)
+    res = {"workload": f"{n}^3 box lx={lx} amplitude {amp}, h1=1, 32 Fourier modes, tol {tol}"}
+    for name, code in (("fp64_pcg", P.SEM_SOLVE_F64), ("f32_ir", P.SEM_SOLVE_F32_IR),
+                       ("bf16_ir", P.SEM_SOLVE_BF16_IR)):
+        cg = op.solver(code)
+        P.sem_cg_solve(cg, x, b, tol=tol, precision=code)          # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = P.sem_cg_solve(cg, x, b, tol=tol, precision=code)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        res[name] = {"ms": round(ms, 2), "iterations": st["iterations"], "outer": st["outer"],
+                     "relres": st["relres"], "converged": st["converged"]}
+        print(f"[bench] solve {name}: {ms:.1f} ms, {st['iterations']} its, outer {st['outer']}, "
+              f"relres {st['relres']:.2e}", file=sys.stderr, flush=True)
+        cg.close()
+    base = res["fp64_pcg"]["ms"]
+    res["speedup_vs_fp64_pcg"] = {k2: round(base / res[k2]["ms"], 3) for k2 in ("f32_ir", "bf16_ir")}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +113,8 @@ def main():
     ap.add_argument("--lx", type=int, default=8)
     ap.add_argument("--amp", type=float, default=0.1)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this library runs on one GPU; --gpus {args.gpus} is not supported",
@@ -90,6 +128,14 @@ def main():
     from paper_2506_20994_amd.box import BoxOperator
 
     torch.cuda.set_device(0)
+    if args.mode == "copy":
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] copied {args.steps} x {a.numel() * 8} bytes", file=sys.stderr)
+        return
     n, lx, amp = args.n, args.lx, args.amp
     nu = (n * (lx - 1)) ** 3
     ctx = P.sem_create()
@@ -164,6 +210,10 @@ def main():
         "gs": {"avg_launch_us": round(gs_ms * 1e3, 2), "shared_ids": n_shared,
                "alg_bytes_per_launch": None},
     }
+    if not args.no_solve:
+        del op, u, w
+        torch.cuda.empty_cache()
+        out["solve"] = solve_comparison(ctx, P, n, lx, amp)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(lx)
     print(json.dumps(out), flush=True)
