@@ -84,3 +84,35 @@ def fourier_modes(seed, count=32, kmax=8):
 def amplitudes(seed, count, lo=0.0, hi=0.2):
     """``count`` deformation amplitudes ~ U[lo, hi)."""
     return rng(seed).uniform(lo, hi, int(count))
+
+
+# --- learned preconditioner: random draws the training method makes ----------
+MLP_SIZES = (518, 256, 256, 512)   # inputs (residual + 6 geometric features), hidden, hidden, outputs
+
+
+def mlp_init(seed, sizes=MLP_SIZES):
+    """He-normal initial weights and zero biases: for each layer a float64
+    (fan_out, fan_in) matrix ~ N(0, 2 / fan_in) and a zero vector."""
+    r = rng(seed)
+    params = []
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        params.append(r.standard_normal((fo, fi)) * np.sqrt(2.0 / fi))
+        params.append(np.zeros(fo))
+    return params
+
+
+def permutation(seed, n):
+    """A random permutation of range(n) (minibatch order)."""
+    return rng(seed).permutation(int(n))
+
+
+def choice(seed, n, k):
+    """k distinct indices from range(n)."""
+    return rng(seed).choice(int(n), size=int(k), replace=False)
+
+
+def snapshot_iterations(seed, count, kmax):
+    """``count`` iteration numbers spread log-uniformly over [1, kmax]."""
+    r = rng(seed)
+    ks = np.unique(np.round(np.exp(r.uniform(0.0, np.log(kmax), count))).astype(np.int64))
+    return np.clip(ks, 1, kmax)
