@@ -32,6 +32,7 @@ extern "C" {
 typedef struct sem_ctx_s* sem_ctx_t;
 typedef struct sem_gs_s* sem_gs_t;
 typedef struct sem_cg_s* sem_cg_t;
+typedef struct sem_lp_s* sem_lp_t;
 
 typedef enum { SEM_F64 = 0, SEM_F32 = 1, SEM_BF16 = 2 } sem_dtype_t;
 
@@ -54,7 +55,9 @@ enum {
 
 /* Create a context on the current HIP device.  `hip_stream` is a hipStream_t
  * (NULL = the null stream) that the context borrows; it is not destroyed by
- * sem_destroy.  Allocates a small device workspace (reduction partials). */
+ * sem_destroy.  Allocates a small device workspace (reduction partials).
+ * Plans, solvers and networks made from a context must be destroyed before
+ * the context. */
 int sem_create(sem_ctx_t* ctx, void* hip_stream);
 int sem_destroy(sem_ctx_t ctx);
 /* Switch the stream later calls are launched on (borrowed, as above). */
@@ -203,6 +206,9 @@ typedef struct {
     int inner_maxit;     /* IR: iterations per inner solve (0: 500) */
     int max_outer;       /* IR: outer refinement steps (0: 60) */
     int check_every;     /* iterations between host convergence checks (0: 16) */
+    sem_lp_t learned;    /* NULL: Jacobi-PCG.  Otherwise flexible CG (Notay's FCG(1))
+                            preconditioned by this network, bound to the same operator
+                            (sem_lp_bind), with the Jacobi fallback described below */
 } sem_solve_opts_t;
 
 typedef struct {
@@ -212,6 +218,8 @@ typedef struct {
     double relres_hist[64]; /* relres after each outer step (IR) */
     int converged;       /* 1 if relres <= tol */
     int breakdown;       /* 1 if a Krylov loop met a non-positive or non-finite curvature */
+    int jacobi_steps;    /* learned: iterations whose network output was replaced by Jacobi */
+    int fell_back;       /* learned: 1 if the solve switched to Jacobi for good */
 } sem_solve_stats_t;
 
 /* Create a solver for A on the plan gs: allocates the work vectors, the
@@ -224,6 +232,11 @@ int sem_cg_destroy(sem_cg_t cg);
 
 /* Solve A x = b (Jacobi-preconditioned CG; Hestenes-Stiefel; Saad Alg. 9.1),
  * or float64 iterative refinement around reduced-precision inner PCG solves.
+ * With opts->learned set, every Krylov loop is flexible CG with one stored
+ * direction (Notay 2000): z = P(r) is the network's output; an iteration whose
+ * z is non-finite or has r.z <= 0 uses the Jacobi z instead, and a solve whose
+ * relative residual has not halved over 256 iterations switches to Jacobi for
+ * good (stats->fell_back, return SEM_FELL_BACK when it then converges).
  * b: device float64, local layout, continuous (b = Q b_G) with sum_G b_G = 0
  * (the periodic operator's null space is the constants).  x: device float64
  * output, local layout, continuous, with sum_G x_G = 0.  Starts from x = 0.
@@ -232,6 +245,60 @@ int sem_cg_destroy(sem_cg_t cg);
  * iterations). */
 int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_solve_opts_t* opts,
                  sem_solve_stats_t* stats);
+
+/* --------------------------------------------- learned preconditioner */
+
+/* A per-element network for lx = 8 elements: inputs are the element's
+ * residual r_e / s_e (512 values, s_e = ||r_e||_2) and six geometric features
+ * mean(h1 g_ab) / kappa_e (kappa_e = mean(h1 (g11 + g22 + g33)) / 3); layers
+ * Linear(518, 256)-ReLU-Linear(256, 256)-ReLU-Linear(256, 512).  Applied as
+ *   z = Q Q^T (mult^-1 (s_e / kappa_e) NN(x_e)).
+ * Training minimises the mean squared error against t_e = err_e kappa_e / s_e
+ * with Adam.  Products run on bf16 MFMA with float32 accumulation; weights,
+ * moments, loss and bias gradients are float32.
+ * Parameter slots for sem_lp_set/get: 0 W1 (256 x 518, row-major, out x in),
+ * 1 b1 (256), 2 W2 (256 x 256), 3 b2, 4 W3 (512 x 256), 5 b3 (512); add 6 for
+ * Adam's first moments, 12 for the second moments, 18 for the gradients. */
+#define SEM_LP_IN 518
+#define SEM_LP_IN_PAD 528      /* row width of feature matrices (zero padded) */
+#define SEM_LP_HIDDEN 256
+#define SEM_LP_OUT 512
+
+/* Allocate a network with zero weights and workspace for up to max_rows rows
+ * (elements per inference, or batch rows per training step). */
+int sem_lp_create(sem_ctx_t ctx, int64_t max_rows, sem_lp_t* lp);
+int sem_lp_destroy(sem_lp_t lp);
+/* Copy `count` float32 values (host) into / out of slot `which`; count must
+ * equal the slot's size.  Synchronous. */
+int sem_lp_set(sem_lp_t lp, int which, const float* host, int64_t count);
+int sem_lp_get(sem_lp_t lp, int which, float* host, int64_t count);
+/* Adam's step counter (the number of updates taken). */
+int sem_lp_set_step(sem_lp_t lp, int64_t step);
+int sem_lp_get_step(sem_lp_t lp, int64_t* step);
+/* Bind to an operator (lx = 8, nel <= max_rows) and its plan: computes the
+ * per-element geometric features.  Needed by sem_lp_samples / sem_lp_apply. */
+int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs);
+/* Training rows for `count` elements elems[] (device int64) of the bound
+ * operator: X[row0 + q] = inputs (bf16, SEM_LP_IN_PAD wide) from the residual
+ * r, and, if T != NULL, T[row0 + q] = err_e kappa_e / s_e (float32, 512 wide)
+ * from the error err.  r, err: device float64 fields of the bound operator. */
+int sem_lp_samples(sem_lp_t lp, const double* r, const double* err, const int64_t* elems,
+                   int64_t count, uint16_t* X, float* T, int64_t row0);
+/* Y = NN(X) for `rows` rows (X device bf16 rows x SEM_LP_IN_PAD, Y device
+ * float32 rows x 512). */
+int sem_lp_forward(sem_lp_t lp, const uint16_t* X, int64_t rows, float* Y);
+/* Gradients of the batch MSE into the gradient slots; *loss (host) receives
+ * the loss.  X, T device, B rows (B % 8 == 0). */
+int sem_lp_gradients(sem_lp_t lp, const uint16_t* X, const float* T, int64_t B, float* loss);
+/* One Adam step from the gradient slots (increments the step counter). */
+int sem_lp_adam(sem_lp_t lp, double lr, double beta1, double beta2, double eps);
+/* Gather rows[0..B) of (X, T) (device), gradients, Adam (beta 0.9/0.999,
+ * eps 1e-8).  *loss is a device float32 that receives the batch loss.
+ * Asynchronous. */
+int sem_lp_train_step(sem_lp_t lp, const uint16_t* X, const float* T, const int64_t* rows,
+                      int64_t B, double lr, float* loss);
+/* z = P(r) on the bound operator; dtype SEM_F64 or SEM_F32 for both. */
+int sem_lp_apply(sem_lp_t lp, void* z, const void* r, sem_dtype_t dtype);
 
 #ifdef __cplusplus
 }

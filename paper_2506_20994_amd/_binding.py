@@ -1,6 +1,7 @@
 """ctypes binding of libsem.so.  Argument marshalling only."""
 import ctypes
 import os
+import weakref
 
 import torch
 
@@ -12,7 +13,15 @@ __all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONV
            "sem_gs_destroy", "sem_gs_info", "sem_gs", "sem_gs_mult", "Context", "GsPlan",
            "dtype_code", "EXPORTS", "sem_gs_owner", "sem_remove_mean", "sem_cg_setup",
            "sem_cg_destroy", "sem_cg_solve", "SemOperator", "SemSolveOpts", "SemSolveStats",
-           "CgSolver", "SEM_SOLVE_F64", "SEM_SOLVE_F32_IR", "SEM_SOLVE_BF16_IR"]
+           "CgSolver", "SEM_SOLVE_F64", "SEM_SOLVE_F32_IR", "SEM_SOLVE_BF16_IR",
+           "LearnedPrecond", "sem_lp_create", "sem_lp_destroy", "sem_lp_set", "sem_lp_get",
+           "sem_lp_set_step", "sem_lp_get_step", "sem_lp_bind", "sem_lp_samples", "sem_lp_forward",
+           "sem_lp_gradients", "sem_lp_adam", "sem_lp_train_step", "sem_lp_apply", "LP_SLOTS",
+           "SEM_LP_IN", "SEM_LP_IN_PAD", "SEM_LP_HIDDEN", "SEM_LP_OUT"]
+
+SEM_LP_IN, SEM_LP_IN_PAD, SEM_LP_HIDDEN, SEM_LP_OUT = 518, 528, 256, 512
+# slot -> shape of the float32 array it holds (parameters; +6 m, +12 v, +18 grads)
+LP_SLOTS = [(256, 518), (256,), (256, 256), (256,), (512, 256), (512,)]
 
 SEM_SOLVE_F64, SEM_SOLVE_F32_IR, SEM_SOLVE_BF16_IR = 0, 1, 2
 
@@ -26,18 +35,21 @@ class SemOperator(ctypes.Structure):
 class SemSolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
-                ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("learned", ctypes.c_void_p)]
 
 
 class SemSolveStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("outer", ctypes.c_int), ("relres", ctypes.c_double),
                 ("relres_hist", ctypes.c_double * 64), ("converged", ctypes.c_int),
-                ("breakdown", ctypes.c_int)]
+                ("breakdown", ctypes.c_int), ("jacobi_steps", ctypes.c_int),
+                ("fell_back", ctypes.c_int)]
 
     def as_dict(self):
         return {"iterations": self.iterations, "outer": self.outer, "relres": self.relres,
                 "relres_hist": list(self.relres_hist[:self.outer]),
-                "converged": bool(self.converged), "breakdown": bool(self.breakdown)}
+                "converged": bool(self.converged), "breakdown": bool(self.breakdown),
+                "jacobi_steps": self.jacobi_steps, "fell_back": bool(self.fell_back)}
 
 SEM_F64, SEM_F32, SEM_BF16 = 0, 1, 2
 SEM_OK, SEM_NOT_CONVERGED, SEM_FELL_BACK = 0, 1, 2
@@ -79,6 +91,19 @@ EXPORTS = {
     "sem_cg_setup": (_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
     "sem_cg_destroy": (_int, [_vp]),
     "sem_cg_solve": (_int, [_vp, _vp, _vp, _vp, _vp]),
+    "sem_lp_create": (_int, [_vp, _i64, ctypes.POINTER(_vp)]),
+    "sem_lp_destroy": (_int, [_vp]),
+    "sem_lp_set": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_float), _i64]),
+    "sem_lp_get": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_float), _i64]),
+    "sem_lp_set_step": (_int, [_vp, _i64]),
+    "sem_lp_get_step": (_int, [_vp, _pi64]),
+    "sem_lp_bind": (_int, [_vp, _vp, _vp]),
+    "sem_lp_samples": (_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64]),
+    "sem_lp_forward": (_int, [_vp, _vp, _i64, _vp]),
+    "sem_lp_gradients": (_int, [_vp, _vp, _vp, _i64, ctypes.POINTER(ctypes.c_float)]),
+    "sem_lp_adam": (_int, [_vp, _dbl, _dbl, _dbl, _dbl]),
+    "sem_lp_train_step": (_int, [_vp, _vp, _vp, _vp, _i64, _dbl, _vp]),
+    "sem_lp_apply": (_int, [_vp, _vp, _vp, _int]),
 }
 
 _LIB = None
@@ -133,19 +158,29 @@ def _ptr(t):
 
 
 class Context:
-    """Owns a sem_ctx_t; launches on torch's current stream at each call."""
+    """Owns a sem_ctx_t; launches on torch's current stream at each call.
+    Closing it first closes every plan, solver and network made from it."""
 
     def __init__(self):
         h = _vp()
         _check(lib().sem_create(ctypes.byref(h), _vp(torch.cuda.current_stream().cuda_stream)))
         self.handle = h
+        self._children = weakref.WeakSet()
 
     def bind(self):
+        if not self.handle:
+            raise SemError(SEM_EINVAL, "context is closed")
         lib().sem_set_stream(self.handle, _vp(torch.cuda.current_stream().cuda_stream))
         return self.handle
 
+    def adopt(self, child):
+        self._children.add(child)
+        return child
+
     def close(self):
         if self.handle:
+            for c in list(self._children):
+                c.close()
             lib().sem_destroy(self.handle)
             self.handle = None
 
@@ -159,6 +194,7 @@ class Context:
 class GsPlan:
     def __init__(self, ctx, handle):
         self.ctx, self.handle = ctx, handle
+        ctx.adopt(self)
 
     def close(self):
         if self.handle:
@@ -296,6 +332,7 @@ def sem_remove_mean(gs, x):
 class CgSolver:
     def __init__(self, ctx, handle, keep):
         self.ctx, self.handle, self._keep = ctx, handle, keep
+        ctx.adopt(self)
 
     def close(self):
         if self.handle:
@@ -310,8 +347,9 @@ class CgSolver:
 
 
 def _opts(tol=1e-10, maxit=0, precision=SEM_SOLVE_F64, inner_tol=0.0, inner_maxit=0,
-          max_outer=0, check_every=0):
-    return SemSolveOpts(tol, maxit, precision, inner_tol, inner_maxit, max_outer, check_every)
+          max_outer=0, check_every=0, learned=None):
+    return SemSolveOpts(tol, maxit, precision, inner_tol, inner_maxit, max_outer, check_every,
+                        learned.handle if learned is not None else None)
 
 
 def sem_cg_setup(ctx, gs, D, h1, G, nel, lx, **opts):
@@ -337,3 +375,100 @@ def sem_cg_solve(cg, x, b, **opts):
     rc = lib().sem_cg_solve(cg.handle, _ptr(x), _ptr(b), ctypes.byref(o), ctypes.byref(st))
     _check(rc, cg.ctx.handle)
     return rc, st.as_dict()
+
+
+class LearnedPrecond:
+    def __init__(self, ctx, handle, max_rows):
+        self.ctx, self.handle, self.max_rows = ctx, handle, max_rows
+        self._bound = None
+        ctx.adopt(self)
+
+    def close(self):
+        if self.handle:
+            lib().sem_lp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sem_lp_create(ctx, max_rows):
+    out = _vp()
+    h = ctx.bind()
+    _check(lib().sem_lp_create(h, int(max_rows), ctypes.byref(out)), h)
+    return LearnedPrecond(ctx, out, max_rows)
+
+
+def sem_lp_destroy(lp):
+    lp.close()
+
+
+def sem_lp_set(lp, which, values):
+    import numpy as np
+    a = np.ascontiguousarray(values, dtype=np.float32).ravel()
+    _check(lib().sem_lp_set(lp.handle, which, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                            a.size), lp.ctx.handle)
+
+
+def sem_lp_get(lp, which):
+    import numpy as np
+    shape = LP_SLOTS[which % 6]
+    a = np.empty(shape, dtype=np.float32)
+    _check(lib().sem_lp_get(lp.handle, which, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                            a.size), lp.ctx.handle)
+    return a
+
+
+def sem_lp_set_step(lp, step):
+    _check(lib().sem_lp_set_step(lp.handle, int(step)), lp.ctx.handle)
+
+
+def sem_lp_get_step(lp):
+    s = ctypes.c_int64(0)
+    _check(lib().sem_lp_get_step(lp.handle, ctypes.byref(s)), lp.ctx.handle)
+    return s.value
+
+
+def sem_lp_bind(lp, D, h1, G, nel, lx, gs):
+    A = SemOperator(*[_ptr(t) for t in D], _ptr(h1), *[_ptr(t) for t in G], nel, lx)
+    lp.ctx.bind()
+    _check(lib().sem_lp_bind(lp.handle, ctypes.byref(A), gs.handle), lp.ctx.handle)
+    lp._bound = (D, h1, G, gs)
+
+
+def sem_lp_samples(lp, r, err, elems, X, T, row0):
+    lp.ctx.bind()
+    _check(lib().sem_lp_samples(lp.handle, _ptr(r), _ptr(err), _ptr(elems), elems.numel(),
+                                _ptr(X), _ptr(T), int(row0)), lp.ctx.handle)
+
+
+def sem_lp_forward(lp, X, Y):
+    lp.ctx.bind()
+    _check(lib().sem_lp_forward(lp.handle, _ptr(X), X.shape[0], _ptr(Y)), lp.ctx.handle)
+
+
+def sem_lp_gradients(lp, X, T):
+    loss = ctypes.c_float(0.0)
+    lp.ctx.bind()
+    _check(lib().sem_lp_gradients(lp.handle, _ptr(X), _ptr(T), X.shape[0], ctypes.byref(loss)),
+           lp.ctx.handle)
+    return loss.value
+
+
+def sem_lp_adam(lp, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    lp.ctx.bind()
+    _check(lib().sem_lp_adam(lp.handle, lr, beta1, beta2, eps), lp.ctx.handle)
+
+
+def sem_lp_train_step(lp, X, T, rows, lr, loss_dev):
+    lp.ctx.bind()
+    _check(lib().sem_lp_train_step(lp.handle, _ptr(X), _ptr(T), _ptr(rows), rows.numel(), lr,
+                                   _ptr(loss_dev)), lp.ctx.handle)
+
+
+def sem_lp_apply(lp, z, r):
+    lp.ctx.bind()
+    _check(lib().sem_lp_apply(lp.handle, _ptr(z), _ptr(r), dtype_code(r)), lp.ctx.handle)

@@ -80,3 +80,7 @@ class BoxOperator:
     def solver(self, precision=0, **opts):
         return B.sem_cg_setup(self.ctx, self.gs, self.D, self.h1, self.G, self.nel, self.lx,
                               precision=precision, **opts)
+
+    def bind(self, lp):
+        """Bind a learned preconditioner to this operator."""
+        B.sem_lp_bind(lp, self.D, self.h1, self.G, self.nel, self.lx, self.gs)

@@ -26,8 +26,9 @@ constexpr int kGrid = 1024;           // vector kernels: fixed grid -> fixed par
 constexpr int kFinal = 1024;          // threads of the single-block finalisers
 
 struct Scal {
-    double rz, pAp, alpha, beta, rr, bb, tol2, mean;
+    double rz, pAp, alpha, beta, rr, bb, tol2, mean, pw_prev;
     int done, it, breakdown, maxit;
+    int usej, njac, fallback;   // flexible CG: Jacobi this iteration, count, for good
 };
 
 __device__ __forceinline__ bool owner_bit(const uint32_t* __restrict__ m, int64_t L) {
@@ -119,6 +120,8 @@ __global__ void pcg_init_final(Scal* __restrict__ S, const double* __restrict__ 
         S->it = 0;
         S->breakdown = 0;
         S->maxit = maxit;
+        S->njac = 0;
+        S->usej = 0;
         S->done = (bb == 0.0 || maxit <= 0) ? 1 : 0;
     }
 }
@@ -311,6 +314,106 @@ __global__ void to_bf16_kernel(uint16_t* __restrict__ out, const double* __restr
         out[L] = bf16_rne((float)in[L]);
 }
 
+
+// ---- flexible CG (Notay's FCG(1)) with a variable preconditioner ----------
+// partials over owners: r.z, non-finite count of z, z.w_prev, (Minv r).w_prev
+template <typename T>
+__global__ void fcg_dots_kernel(const T* __restrict__ r, const T* __restrict__ z,
+                                const T* __restrict__ wprev, const T* __restrict__ minv,
+                                const uint32_t* __restrict__ own, int64_t n,
+                                const Scal* __restrict__ S, double* __restrict__ part) {
+    if (S->done) return;
+    __shared__ double s_red[kBlock / 64];
+    const bool first = S->it == 0;
+    double rz = 0.0, bad = 0.0, zw = 0.0, jw = 0.0;
+    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
+         L += (int64_t)gridDim.x * blockDim.x) {
+        const double zv = (double)z[L];
+        if (!isfinite(zv)) bad += 1.0;
+        if (owner_bit(own, L)) {
+            const double rv = (double)r[L];
+            rz += rv * zv;
+            if (!first) {
+                const double wv = (double)wprev[L];
+                zw += zv * wv;
+                jw += (double)(minv[L] * r[L]) * wv;
+            }
+        }
+    }
+    rz = block_sum(rz, s_red);
+    bad = block_sum(bad, s_red);
+    zw = block_sum(zw, s_red);
+    jw = block_sum(jw, s_red);
+    if (threadIdx.x == 0) {
+        part[4 * blockIdx.x] = rz;
+        part[4 * blockIdx.x + 1] = bad;
+        part[4 * blockIdx.x + 2] = zw;
+        part[4 * blockIdx.x + 3] = jw;
+    }
+}
+
+__global__ void fcg_gamma_final(Scal* __restrict__ S, const double* __restrict__ part, int n) {
+    if (S->done) return;
+    __shared__ double s_red[kFinal / 64];
+    const double rz = final_sum(part, n, 4, s_red);
+    const double bad = final_sum(part + 1, n, 4, s_red);
+    const double zw = final_sum(part + 2, n, 4, s_red);
+    const double jw = final_sum(part + 3, n, 4, s_red);
+    if (threadIdx.x == 0) {
+        const int usej = (S->fallback || bad > 0.0 || !(rz > 0.0) || !isfinite(zw)) ? 1 : 0;
+        S->usej = usej;
+        S->njac += usej;
+        S->beta = S->it == 0 ? 0.0 : (usej ? jw : zw) / S->pw_prev;   // gamma of FCG(1)
+    }
+}
+
+// p = z_eff - gamma p (z_eff = Minv r when the network output is rejected);
+// partials over owners of p.r
+template <typename T>
+__global__ void fcg_p_kernel(T* __restrict__ p, const T* __restrict__ z, const T* __restrict__ r,
+                             const T* __restrict__ minv, const uint32_t* __restrict__ own, int64_t n,
+                             const Scal* __restrict__ S, double* __restrict__ part) {
+    if (S->done) return;
+    __shared__ double s_red[kBlock / 64];
+    const bool usej = S->usej != 0;
+    const bool first = S->it == 0;
+    const T gamma = (T)S->beta;
+    double pr = 0.0;
+    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
+         L += (int64_t)gridDim.x * blockDim.x) {
+        const T rv = r[L];
+        const T ze = usej ? minv[L] * rv : z[L];
+        const T pv = first ? ze : ze - gamma * p[L];
+        p[L] = pv;
+        if (owner_bit(own, L)) pr += (double)pv * (double)rv;
+    }
+    pr = block_sum(pr, s_red);
+    if (threadIdx.x == 0) part[blockIdx.x] = pr;
+}
+
+// alpha = p.r / p.A.p; keep p.A.p for the next gamma
+__global__ void fcg_alpha_final(Scal* __restrict__ S, const double* __restrict__ part_ax, int nax,
+                                const double* __restrict__ part_pr, int npr) {
+    if (S->done) return;
+    __shared__ double s_red[kFinal / 64];
+    const double pAp = final_sum(part_ax, nax, 1, s_red);
+    const double pr = final_sum(part_pr, npr, 1, s_red);
+    if (threadIdx.x == 0) {
+        S->pAp = pAp;
+        if (!(pAp > 0.0) || !isfinite(pAp) || !isfinite(pr)) {
+            S->breakdown = 1;
+            S->done = 1;
+        } else {
+            S->alpha = pr / pAp;
+            S->pw_prev = pAp;
+        }
+    }
+}
+
+__global__ void set_fallback(Scal* __restrict__ S) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) S->fallback = 1;
+}
+
 }  // namespace
 
 // One precision level of the solver: vectors of type T and the operator form
@@ -319,6 +422,7 @@ struct Level {
     sem::AxKind kind;
     sem::AxArgs A;
     void *x = nullptr, *r = nullptr, *p = nullptr, *w = nullptr, *minv = nullptr;
+    void* z = nullptr;   // flexible CG: the preconditioner's output
 };
 
 struct sem_cg_s {
@@ -330,7 +434,9 @@ struct sem_cg_s {
     sem::AxArgs A64{};
     uint32_t* own = nullptr;
     Scal* S = nullptr;
-    double* part = nullptr;        // max(2*kGrid, ax_blocks) doubles
+    double* part = nullptr;        // max(4*kGrid, ax_blocks) doubles
+    double* part2 = nullptr;       // kGrid doubles (flexible CG: p.r partials)
+    sem_lp_t lp = nullptr;
     double* sums = nullptr;        // 2 doubles
     Scal* S_host = nullptr;        // pinned
     double* sums_host = nullptr;   // pinned
@@ -389,6 +495,70 @@ int pcg_run(sem_cg_t cg, Level& lv, const T* rhs, double tol, int maxit, int che
     }
     *iters_out = done_it;
     *breakdown_out = cg->S_host->breakdown;
+    return SEM_OK;
+}
+
+// flexible CG on level lv with the bound network; same contract as pcg_run
+template <typename T>
+int fcg_run(sem_cg_t cg, Level& lv, const T* rhs, double tol, int maxit, int check_every,
+            int* iters_out, int* breakdown_out, int* njac_out, int* fell_back) {
+    sem_ctx_t ctx = cg->ctx;
+    hipStream_t st = ctx->stream;
+    const int64_t n = cg->n;
+    const unsigned g = vec_grid(n);
+    T* x = (T*)lv.x; T* r = (T*)lv.r; T* p = (T*)lv.p; T* w = (T*)lv.w; T* z = (T*)lv.z;
+    const T* minv = (const T*)lv.minv;
+    pcg_init_kernel<T><<<g, kBlock, 0, st>>>(x, r, p, rhs, minv, cg->own, n, cg->part);
+    pcg_init_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g, tol, maxit);
+    SEM_LAUNCH_CHECK(ctx);
+    const int nb = sem::ax_blocks(lv.A.lx, lv.A.nel);
+    const bool f64 = sizeof(T) == 8;
+    bool fallen = false;
+    // the fallback flag starts cleared for every solve
+    SEM_HIP(ctx, hipMemcpyAsync(cg->S_host, cg->S, sizeof(Scal), hipMemcpyDeviceToHost, st));
+    SEM_HIP(ctx, hipStreamSynchronize(st));
+    cg->S_host->fallback = 0;
+    SEM_HIP(ctx, hipMemcpyAsync(cg->S, cg->S_host, sizeof(Scal), hipMemcpyHostToDevice, st));
+    std::vector<std::pair<int, double>> hist;   // (iteration, rr) at each check
+    for (;;) {
+        for (int q = 0; q < check_every; ++q) {
+            int rc = SEM_OK;
+            if (!fallen) rc = sem::lp_apply(cg->lp, z, r, f64, &cg->S->done);
+            if (rc) return rc;
+            fcg_dots_kernel<T><<<g, kBlock, 0, st>>>(r, z, w, minv, cg->own, n, cg->S, cg->part);
+            fcg_gamma_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
+            fcg_p_kernel<T><<<g, kBlock, 0, st>>>(p, z, r, minv, cg->own, n, cg->S, cg->part2);
+            rc = sem::launch_ax(ctx, lv.kind, lv.A, w, p, &cg->S->done, cg->part);
+            if (rc) return rc;
+            rc = sem::gs_launch(cg->gs, w, f64 ? SEM_F64 : SEM_F32, &cg->S->done);
+            if (rc) return rc;
+            fcg_alpha_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, nb, cg->part2, (int)g);
+            pcg_update_kernel<T><<<g, kBlock, 0, st>>>(x, r, p, w, minv, cg->own, n, cg->S, cg->part);
+            pcg_beta_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
+        }
+        SEM_LAUNCH_CHECK(ctx);
+        SEM_HIP(ctx, hipMemcpyAsync(cg->S_host, cg->S, sizeof(Scal), hipMemcpyDeviceToHost, st));
+        SEM_HIP(ctx, hipStreamSynchronize(st));
+        if (cg->S_host->done) break;
+        // stagnation guard: relative residual not halved over 256 iterations
+        hist.emplace_back(cg->S_host->it, cg->S_host->rr);
+        if (!fallen) {
+            for (auto it = hist.rbegin(); it != hist.rend(); ++it) {
+                if (cg->S_host->it - it->first >= 256) {
+                    if (cg->S_host->rr > 0.25 * it->second) {   // rr is squared: halving = 1/4
+                        set_fallback<<<1, 1, 0, st>>>(cg->S);
+                        SEM_LAUNCH_CHECK(ctx);
+                        fallen = true;
+                    }
+                    break;
+                }
+            }
+        }
+    }
+    *iters_out = cg->S_host->it;
+    *breakdown_out = cg->S_host->breakdown;
+    *njac_out = cg->S_host->njac;
+    *fell_back = fallen ? 1 : 0;
     return SEM_OK;
 }
 
@@ -469,7 +639,7 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
     hipStream_t st = ctx->stream;
     const unsigned g = vec_grid(n);
     const int nb = sem::ax_blocks(A->lx, A->nel);
-    const size_t npart = (size_t)std::max(2 * kGrid, nb);
+    const size_t npart = (size_t)std::max(4 * kGrid, nb);
     const int64_t nw = (n + 31) / 32;
     const size_t v64 = sizeof(double) * n, v32 = sizeof(float) * n;
     auto bail = [&](int code) { sem_cg_destroy(cg); return code; };
@@ -478,6 +648,12 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
     CG_ALLOC(cg->S, sizeof(Scal));
     CG_ALLOC(cg->part, sizeof(double) * npart);
     CG_ALLOC(cg->sums, sizeof(double) * 2);
+    CG_ALLOC(cg->part2, sizeof(double) * kGrid);
+    if (opts->learned) {
+        if (sem::lp_rows(opts->learned) != A->nel || sem::lp_plan(opts->learned) != gs)
+            return bail(sem::fail(ctx, SEM_EINVAL, "sem_cg_setup: the network is not bound to this operator and plan"));
+        cg->lp = opts->learned;
+    }
     CG_ALLOC(cg->r64, v64);
     CG_ALLOC(cg->w64, v64);
     {
@@ -498,6 +674,7 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
     L64.A = cg->A64;
     if (opts->precision == SEM_SOLVE_F64) {
         CG_ALLOC(L64.x, v64); CG_ALLOC(L64.r, v64); CG_ALLOC(L64.p, v64); CG_ALLOC(L64.minv, v64);
+        if (cg->lp) CG_ALLOC(L64.z, v64);
         L64.w = cg->w64;
         recip_kernel<double><<<g, kBlock, 0, st>>>((double*)L64.minv, cg->r64, n);
     } else {
@@ -506,6 +683,7 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
         L.kind = bf ? sem::AxKind::F32_BF16 : sem::AxKind::F32;
         CG_ALLOC(L.x, v32); CG_ALLOC(L.r, v32); CG_ALLOC(L.p, v32); CG_ALLOC(L.w, v32); CG_ALLOC(L.minv, v32);
         CG_ALLOC(cg->rhs32, v32);
+        if (cg->lp) CG_ALLOC(L.z, v32);
         recip_kernel<float><<<g, kBlock, 0, st>>>((float*)L.minv, cg->r64, n);
         // derivative matrices in float32
         const int l2 = A->lx * A->lx;
@@ -558,6 +736,8 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
     if (opts->precision != cg->precision)
         return sem::fail(ctx, SEM_EINVAL, "sem_cg_solve: precision %d differs from set-up (%d)",
                          opts->precision, cg->precision);
+    if (opts->learned != cg->lp)
+        return sem::fail(ctx, SEM_EINVAL, "sem_cg_solve: preconditioner differs from set-up");
     if (!(opts->tol > 0.0)) return sem::fail(ctx, SEM_EINVAL, "sem_cg_solve: tol must be > 0");
     *stats = sem_solve_stats_t{};
     const int check = opts->check_every > 0 ? opts->check_every : 16;
@@ -574,9 +754,12 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
 
     if (cg->precision == SEM_SOLVE_F64) {
         Level& L = cg->lv64;
-        int its = 0, brk = 0;
-        rc = pcg_run<double>(cg, L, b, opts->tol, maxit, check, &its, &brk);
+        int its = 0, brk = 0, nj = 0, fb = 0;
+        if (cg->lp) rc = fcg_run<double>(cg, L, b, opts->tol, maxit, check, &its, &brk, &nj, &fb);
+        else rc = pcg_run<double>(cg, L, b, opts->tol, maxit, check, &its, &brk);
         if (rc) return rc;
+        stats->jacobi_steps = nj;
+        stats->fell_back = fb;
         SEM_HIP(ctx, hipMemcpyAsync(x, L.x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
         rc = remove_mean(cg, x);
         if (rc) return rc;
@@ -605,10 +788,16 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
             if (rel <= opts->tol || total >= maxit) break;
             ir_scale_kernel<<<vec_grid(n), kBlock, 0, st>>>(cg->rhs32, cg->r64, cg->sums,
                                                              cg->n_unique, n);
-            int its = 0, brk = 0;
-            rc = pcg_run<float>(cg, L, cg->rhs32, itol, std::min(imax, maxit - total),
-                                check, &its, &brk);
+            int its = 0, brk = 0, nj = 0, fb = 0;
+            if (cg->lp)
+                rc = fcg_run<float>(cg, L, cg->rhs32, itol, std::min(imax, maxit - total), check,
+                                    &its, &brk, &nj, &fb);
+            else
+                rc = pcg_run<float>(cg, L, cg->rhs32, itol, std::min(imax, maxit - total), check,
+                                    &its, &brk);
             if (rc) return rc;
+            stats->jacobi_steps += nj;
+            stats->fell_back |= fb;
             total += its;
             stats->outer = outer + 1;
             if (brk) stats->breakdown = 1;
@@ -633,7 +822,8 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
     stats->relres = rel;
     stats->converged = rel <= opts->tol;
     if (stats->breakdown && !stats->converged) return sem::fail(ctx, SEM_EBREAKDOWN, "sem_cg_solve: breakdown");
-    return stats->converged ? SEM_OK : SEM_NOT_CONVERGED;
+    if (!stats->converged) return SEM_NOT_CONVERGED;
+    return stats->fell_back ? SEM_FELL_BACK : SEM_OK;
 }
 
 extern "C" int sem_remove_mean(sem_gs_t gs, double* x) {

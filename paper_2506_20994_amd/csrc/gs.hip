@@ -16,7 +16,8 @@ constexpr int kBlock = 256;
 
 template <typename T>
 __global__ void gs_kernel(T* __restrict__ u, const int32_t* __restrict__ off,
-                          const int32_t* __restrict__ idx, int64_t n_shared) {
+                          const int32_t* __restrict__ idx, int64_t n_shared, const int* __restrict__ skip) {
+    if (skip && *skip) return;
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= n_shared) return;
     const int32_t b = off[g], e = off[g + 1];
@@ -152,22 +153,30 @@ extern "C" int sem_gs_info(sem_gs_t gs, int64_t* n_unique, int64_t* n_shared) {
     return SEM_OK;
 }
 
-extern "C" int sem_gs(sem_gs_t gs, void* u, sem_dtype_t dtype) {
-    if (!gs) return sem::fail(nullptr, SEM_EINVAL, "sem_gs: null plan");
+namespace sem {
+
+int gs_launch(sem_gs_t gs, void* u, sem_dtype_t dtype, const int* skip) {
     sem_ctx_t ctx = gs->ctx;
-    int rc = sem::enter(ctx);
-    if (rc) return rc;
     if (gs->n_shared == 0) return SEM_OK;
-    if (!u) return sem::fail(ctx, SEM_EINVAL, "sem_gs: null field");
+    if (!u) return fail(ctx, SEM_EINVAL, "sem_gs: null field");
     const unsigned grid = (unsigned)((gs->n_shared + kBlock - 1) / kBlock);
     if (dtype == SEM_F64)
-        gs_kernel<double><<<grid, kBlock, 0, ctx->stream>>>((double*)u, gs->off, gs->idx, gs->n_shared);
+        gs_kernel<double><<<grid, kBlock, 0, ctx->stream>>>((double*)u, gs->off, gs->idx, gs->n_shared, skip);
     else if (dtype == SEM_F32)
-        gs_kernel<float><<<grid, kBlock, 0, ctx->stream>>>((float*)u, gs->off, gs->idx, gs->n_shared);
+        gs_kernel<float><<<grid, kBlock, 0, ctx->stream>>>((float*)u, gs->off, gs->idx, gs->n_shared, skip);
     else
-        return sem::fail(ctx, SEM_EINVAL, "sem_gs: dtype %d not supported (F64 or F32)", (int)dtype);
+        return fail(ctx, SEM_EINVAL, "sem_gs: dtype %d not supported (F64 or F32)", (int)dtype);
     SEM_LAUNCH_CHECK(ctx);
     return SEM_OK;
+}
+
+}  // namespace sem
+
+extern "C" int sem_gs(sem_gs_t gs, void* u, sem_dtype_t dtype) {
+    if (!gs) return sem::fail(nullptr, SEM_EINVAL, "sem_gs: null plan");
+    int rc = sem::enter(gs->ctx);
+    if (rc) return rc;
+    return sem::gs_launch(gs, u, dtype, nullptr);
 }
 
 extern "C" int sem_gs_mult(sem_gs_t gs, double* mult) {

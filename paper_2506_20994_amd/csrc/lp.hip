@@ -1,0 +1,692 @@
+// Learned per-element preconditioner: a 518-256-256-512 MLP applied to each
+// lx = 8 element's normalised residual plus six geometric features, trained on
+// the GPU with Adam.  The dense contractions run on bf16 MFMA
+// (v_mfma_f32_16x16x32_bf16) with float32 accumulation; master weights, Adam
+// moments, the loss and the bias gradients are float32.
+//
+// GEMM form used throughout: C[M][N] = A[M][K] . B[N][K]^T with both operands
+// k-contiguous (row-major bf16); the other products of backpropagation are
+// brought to this form with explicit transposes.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "sem_internal.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16;
+
+constexpr int kIn = 518, kInPad = 528, kHid = 256, kOut = 512;
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ u16 bf16_rne(float f) {
+    uint32_t b = __float_as_uint(f);
+    if ((b & 0x7fffffffu) > 0x7f800000u) return (u16)((b >> 16) | 0x40u);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return (u16)(b >> 16);
+}
+__device__ __forceinline__ float bf16_f(u16 h) { return __uint_as_float((uint32_t)h << 16); }
+
+enum { EPI_BIAS = 1, EPI_RELU = 2, EPI_MASK = 4 };
+constexpr int BM = 128, BN = 128, BK = 32, LDK = BK + 8;
+
+// C = A . B^T (+bias[n]) (relu) (*(mask[m][n] > 0)); Cf float and/or Cb bf16.
+// Requires K % 8 == 0, lda % 8 == 0, ldb % 8 == 0 and 16-byte aligned bases.
+__global__ void __launch_bounds__(256)
+gemm_nt(int M, int N, int K, const u16* __restrict__ A, int lda, const u16* __restrict__ B, int ldb,
+        const float* __restrict__ bias, const u16* __restrict__ mask, int ldm,
+        float* __restrict__ Cf, u16* __restrict__ Cb, int ldc, int epi, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    __shared__ __attribute__((aligned(16))) u16 sA[BM * LDK];
+    __shared__ __attribute__((aligned(16))) u16 sB[BN * LDK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+        for (int c = tid; c < BM * BK / 8; c += 256) {
+            const int row = c >> 2, kc = (c & 3) * 8;
+            const int gm = m0 + row, gk = k0 + kc;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (gm < M && gk < K) v = *reinterpret_cast<const uint4*>(A + (int64_t)gm * lda + gk);
+            *reinterpret_cast<uint4*>(sA + row * LDK + kc) = v;
+        }
+#pragma unroll
+        for (int c = tid; c < BN * BK / 8; c += 256) {
+            const int row = c >> 2, kc = (c & 3) * 8;
+            const int gn = n0 + row, gk = k0 + kc;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (gn < N && gk < K) v = *reinterpret_cast<const uint4*>(B + (int64_t)gn * ldb + gk);
+            *reinterpret_cast<uint4*>(sB + row * LDK + kc) = v;
+        }
+        __syncthreads();
+        bf16x8 af[4], bfv[4];
+        const int ko = (lane >> 4) * 8;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            af[i] = *reinterpret_cast<const bf16x8*>(sA + (wm * 64 + i * 16 + (lane & 15)) * LDK + ko);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            bfv[j] = *reinterpret_cast<const bf16x8*>(sB + (wn * 64 + j * 16 + (lane & 15)) * LDK + ko);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfv[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // acc[i][j][q] = C[wm*64 + i*16 + 4*(lane/16) + q][wn*64 + j*16 + lane%16]
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+            if (n >= N) continue;
+            const float bv = (epi & EPI_BIAS) ? bias[n] : 0.f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + q;
+                if (m >= M) continue;
+                float v = acc[i][j][q] + bv;
+                if (epi & EPI_RELU) v = fmaxf(v, 0.f);
+                if ((epi & EPI_MASK) && !(bf16_f(mask[(int64_t)m * ldm + n]) > 0.f)) v = 0.f;
+                if (Cf) Cf[(int64_t)m * ldc + n] = v;
+                if (Cb) Cb[(int64_t)m * ldc + n] = bf16_rne(v);
+            }
+        }
+}
+
+// out[c][r] = in[r][c] (bf16), rows x cols, leading dims ldi / ldo
+__global__ void transpose_bf16(u16* __restrict__ out, int ldo, const u16* __restrict__ in, int ldi,
+                               int rows, int cols) {
+    __shared__ u16 t[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 32 x 8
+    for (int y = ty; y < 32; y += 8) {
+        const int r = r0 + y, c = c0 + tx;
+        t[y][tx] = (r < rows && c < cols) ? in[(int64_t)r * ldi + c] : (u16)0;
+    }
+    __syncthreads();
+    for (int y = ty; y < 32; y += 8) {
+        const int c = c0 + y, r = r0 + tx;
+        if (c < cols && r < rows) out[(int64_t)c * ldo + r] = t[tx][y];
+    }
+}
+
+// float32 master (rows x cols) -> bf16 copy with leading dim ldo (zero pad)
+// and, if outT != null, its bf16 transpose (cols x rows)
+__global__ void weights_to_bf16(u16* __restrict__ out, int ldo, u16* __restrict__ outT,
+                                const float* __restrict__ w, int rows, int cols) {
+    const int64_t n = (int64_t)rows * ldo;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(q / ldo), c = (int)(q % ldo);
+        const u16 v = c < cols ? bf16_rne(w[(int64_t)r * cols + c]) : (u16)0;
+        out[q] = v;
+        if (outT && c < cols) outT[(int64_t)c * rows + r] = v;
+    }
+}
+
+// batch gather: Xb[i] = X[rows[i]] (bf16, kInPad wide), Tb[i] = T[rows[i]] (float, kOut)
+__global__ void gather_rows(u16* __restrict__ Xb, float* __restrict__ Tb, const u16* __restrict__ X,
+                            const float* __restrict__ T, const int64_t* __restrict__ rows, int B) {
+    const int i = blockIdx.x;
+    if (i >= B) return;
+    const int64_t r = rows[i];
+    for (int c = threadIdx.x; c < kInPad; c += blockDim.x) Xb[(int64_t)i * kInPad + c] = X[r * kInPad + c];
+    for (int c = threadIdx.x; c < kOut; c += blockDim.x) Tb[(int64_t)i * kOut + c] = T[r * kOut + c];
+}
+
+// d3 = 2 (Y3 - T) / (B * kOut) as float and bf16; per-block partial of sum (Y3 - T)^2
+__global__ void mse_grad(float* __restrict__ d3f, u16* __restrict__ d3b, const float* __restrict__ Y3,
+                         const float* __restrict__ T, int64_t n, float scale, double* __restrict__ part) {
+    __shared__ double s[kBlock / 64];
+    double acc = 0.0;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const float d = Y3[q] - T[q];
+        acc += (double)d * d;
+        const float g = scale * d;
+        d3f[q] = g;
+        d3b[q] = bf16_rne(g);
+    }
+    acc = sem::wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < kBlock / 64; ++q) t += s[q];
+        part[blockIdx.x] = t;
+    }
+}
+
+__global__ void loss_final(float* __restrict__ loss, const double* __restrict__ part, int nb, double inv_n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < nb; ++q) t += part[q];
+        *loss = (float)(t * inv_n);
+    }
+}
+
+// out[c] = sum_r d[r][c] (float), fixed order
+__global__ void colsum(float* __restrict__ out, const float* __restrict__ d, int rows, int cols) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    float s = 0.f;
+    for (int r = 0; r < rows; ++r) s += d[(int64_t)r * cols + c];
+    out[c] = s;
+}
+
+// Adam on a (rows x cols) parameter whose gradient has leading dim ldg
+__global__ void adam_kernel(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ g, int rows, int cols, int ldg, float lr,
+                            float b1, float omb1, float b2, float omb2, float eps, float c1, float c2) {
+    const int64_t n = (int64_t)rows * cols;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = q / cols, c = q % cols;
+        const float gv = g[r * ldg + c];
+        const float mv = b1 * m[q] + omb1 * gv;
+        const float vv = b2 * v[q] + omb2 * gv * gv;
+        m[q] = mv;
+        v[q] = vv;
+        p[q] -= lr * (mv / c1) / (sqrtf(vv / c2) + eps);
+    }
+}
+
+// per-element geometric features (six means of h1 g_ab over kappa) and kappa
+__global__ void geo_kernel(float* __restrict__ geo, float* __restrict__ kappa,
+                           const double* __restrict__ h1, const double* __restrict__ g11,
+                           const double* __restrict__ g22, const double* __restrict__ g33,
+                           const double* __restrict__ g12, const double* __restrict__ g13,
+                           const double* __restrict__ g23, int64_t nel) {
+    const int64_t e = blockIdx.x;
+    if (e >= nel) return;
+    const double* G[6] = {g11, g22, g33, g12, g13, g23};
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int q = threadIdx.x; q < kOut; q += 64) {
+        const int64_t L = e * kOut + q;
+        const double h = h1 ? h1[L] : 1.0;
+        for (int a = 0; a < 6; ++a) s[a] += h * G[a][L];
+    }
+    for (int a = 0; a < 6; ++a) s[a] = sem::wave_sum(s[a]);
+    if (threadIdx.x == 0) {
+        const double kap = (s[0] + s[1] + s[2]) / (3.0 * kOut);
+        kappa[e] = (float)kap;
+        for (int a = 0; a < 6; ++a) geo[e * 6 + a] = (float)(s[a] / kOut / kap);
+    }
+}
+
+// X[row] = [bf16(r_e / s_e) (512), geo (6), 0 (10)]; scale[row] = s_e / kappa_e;
+// optionally T[row] = err_e * kappa_e / s_e.  One wave per element.
+template <typename T>
+__global__ void features_kernel(u16* __restrict__ X, float* __restrict__ scale, float* __restrict__ Tt,
+                                const T* __restrict__ r, const double* __restrict__ err,
+                                const float* __restrict__ geo, const float* __restrict__ kappa,
+                                const int64_t* __restrict__ elems, int64_t count, int64_t row0,
+                                const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int64_t q = blockIdx.x;
+    if (q >= count) return;
+    const int64_t e = elems ? elems[q] : q;
+    const int64_t row = row0 + q;
+    const int lane = threadIdx.x;
+    double v[8];
+    double ss = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        v[c] = (double)r[e * kOut + c * 64 + lane];
+        ss += v[c] * v[c];
+    }
+    ss = sem::wave_sum(ss);
+    const double s = sqrt(ss) + 1e-30;
+    const double kap = (double)kappa[e];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) X[row * kInPad + c * 64 + lane] = bf16_rne((float)(v[c] / s));
+    if (lane < kInPad - kOut)
+        X[row * kInPad + kOut + lane] = lane < 6 ? bf16_rne(geo[e * 6 + lane]) : (u16)0;
+    if (lane == 0 && scale) scale[row] = (float)(s / kap);
+    if (Tt) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            Tt[row * kOut + c * 64 + lane] = (float)(err[e * kOut + c * 64 + lane] * kap / s);
+    }
+}
+
+// z_L = scale[e] * Y3[e][node] / mult_L
+template <typename T>
+__global__ void lp_output_kernel(T* __restrict__ z, const float* __restrict__ Y3,
+                                 const float* __restrict__ scale, const double* __restrict__ mult,
+                                 int64_t n, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
+         L += (int64_t)gridDim.x * blockDim.x)
+        z[L] = (T)((double)scale[L / kOut] * (double)Y3[L] / mult[L]);
+}
+
+unsigned grid_of(int64_t n, int64_t cap = 4096) {
+    int64_t b = (n + kBlock - 1) / kBlock;
+    return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+}  // namespace
+
+struct sem_lp_s {
+    sem_ctx_t ctx = nullptr;
+    int64_t max_rows = 0;
+    // float32 masters, Adam moments, gradients (W1 gradient is 256 x 528)
+    float *W[3] = {}, *b[3] = {}, *mW[3] = {}, *mb[3] = {}, *vW[3] = {}, *vb[3] = {};
+    float *gW[3] = {}, *gb[3] = {};
+    int64_t step = 0;
+    // bf16 copies: W1 (256 x 528), W2 (256 x 256), W3 (512 x 256), W2^T, W3^T
+    u16 *W1b = nullptr, *W2b = nullptr, *W3b = nullptr, *W2t = nullptr, *W3t = nullptr;
+    bool dirty = true;
+    // activations / work for up to max_rows rows
+    u16 *X = nullptr, *Y1 = nullptr, *Y2 = nullptr, *d3b = nullptr, *d2b = nullptr, *d1b = nullptr;
+    float *Y3 = nullptr, *T = nullptr, *d3f = nullptr, *d2f = nullptr, *d1f = nullptr, *scale = nullptr;
+    u16 *tA = nullptr, *tB = nullptr;   // transposes (kInPad x max_rows each)
+    double* part = nullptr;
+    float* loss = nullptr;
+    // bound operator (inference)
+    int64_t nel = 0;
+    float *geo = nullptr, *kappa = nullptr;
+    sem_gs_t gs = nullptr;
+    const int* skip = nullptr;   // set by the solver: kernels return when *skip != 0
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+constexpr int kParamRows[3] = {kHid, kHid, kOut};
+constexpr int kParamCols[3] = {kIn, kHid, kHid};
+
+int lp_alloc(sem_lp_t lp, void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return sem::check_hip(lp->ctx, e, "sem_lp: hipMalloc");
+    lp->allocs.push_back(*p);
+    SEM_HIP(lp->ctx, hipMemsetAsync(*p, 0, bytes, lp->ctx->stream));
+    return SEM_OK;
+}
+
+int gemm(sem_lp_t lp, int M, int N, int K, const u16* A, int lda, const u16* B, int ldb,
+         const float* bias, const u16* mask, int ldm, float* Cf, u16* Cb, int ldc, int epi) {
+    if (M == 0 || N == 0) return SEM_OK;
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+    gemm_nt<<<grid, 256, 0, lp->ctx->stream>>>(M, N, K, A, lda, B, ldb, bias, mask, ldm, Cf, Cb, ldc, epi,
+                                               lp->skip);
+    SEM_LAUNCH_CHECK(lp->ctx);
+    return SEM_OK;
+}
+
+int transpose(sem_lp_t lp, u16* out, int ldo, const u16* in, int ldi, int rows, int cols) {
+    dim3 grid((cols + 31) / 32, (rows + 31) / 32);
+    transpose_bf16<<<grid, 256, 0, lp->ctx->stream>>>(out, ldo, in, ldi, rows, cols);
+    SEM_LAUNCH_CHECK(lp->ctx);
+    return SEM_OK;
+}
+
+int refresh_bf16(sem_lp_t lp) {
+    if (!lp->dirty) return SEM_OK;
+    hipStream_t st = lp->ctx->stream;
+    weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W1b, kInPad, nullptr, lp->W[0], kHid, kIn);
+    weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W2b, kHid, lp->W2t, lp->W[1], kHid, kHid);
+    weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W3b, kHid, lp->W3t, lp->W[2], kOut, kHid);
+    SEM_LAUNCH_CHECK(lp->ctx);
+    lp->dirty = false;
+    return SEM_OK;
+}
+
+// forward of rows [0, M) of lp->X into Y1, Y2 (bf16) and Y3 (float)
+int forward(sem_lp_t lp, const u16* X, int64_t M) {
+    int rc = refresh_bf16(lp);
+    if (rc) return rc;
+    if (M > 0x7fffffff) return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp: too many rows");
+    const int m = (int)M;
+    rc = gemm(lp, m, kHid, kInPad, X, kInPad, lp->W1b, kInPad, lp->b[0], nullptr, 0, nullptr, lp->Y1, kHid, EPI_BIAS | EPI_RELU);
+    if (!rc) rc = gemm(lp, m, kHid, kHid, lp->Y1, kHid, lp->W2b, kHid, lp->b[1], nullptr, 0, nullptr, lp->Y2, kHid, EPI_BIAS | EPI_RELU);
+    if (!rc) rc = gemm(lp, m, kOut, kHid, lp->Y2, kHid, lp->W3b, kHid, lp->b[2], nullptr, 0, lp->Y3, nullptr, kOut, EPI_BIAS);
+    return rc;
+}
+
+float** param_slot(sem_lp_t lp, int which, int64_t* count, int* ld) {
+    // 0..5 params, 6..11 first moments, 12..17 second moments, 18..23 gradients
+    const int kind = which / 6, idx = which % 6, layer = idx / 2;
+    const bool isW = (idx % 2) == 0;
+    *count = isW ? (int64_t)kParamRows[layer] * kParamCols[layer] : kParamRows[layer];
+    *ld = isW ? kParamCols[layer] : 1;
+    if (kind == 3 && isW && layer == 0) *ld = kInPad;
+    switch (kind) {
+        case 0: return isW ? &lp->W[layer] : &lp->b[layer];
+        case 1: return isW ? &lp->mW[layer] : &lp->mb[layer];
+        case 2: return isW ? &lp->vW[layer] : &lp->vb[layer];
+        case 3: return isW ? &lp->gW[layer] : &lp->gb[layer];
+    }
+    return nullptr;
+}
+
+}  // namespace
+
+extern "C" int sem_lp_create(sem_ctx_t ctx, int64_t max_rows, sem_lp_t* out) {
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (!out) return sem::fail(ctx, SEM_EINVAL, "sem_lp_create: null output");
+    *out = nullptr;
+    if (max_rows < 1 || max_rows > (1ll << 26))
+        return sem::fail(ctx, SEM_EINVAL, "sem_lp_create: max_rows=%lld outside [1, 2^26]", (long long)max_rows);
+    auto* lp = new sem_lp_s();
+    lp->ctx = ctx;
+    lp->max_rows = max_rows;
+    auto bail = [&](int code) { sem_lp_destroy(lp); return code; };
+#define LP_ALLOC(ptr, bytes) do { int rc_ = lp_alloc(lp, (void**)&(ptr), (bytes)); if (rc_) return bail(rc_); } while (0)
+    for (int l = 0; l < 3; ++l) {
+        const size_t nw = (size_t)kParamRows[l] * kParamCols[l], nb = kParamRows[l];
+        LP_ALLOC(lp->W[l], 4 * nw); LP_ALLOC(lp->mW[l], 4 * nw); LP_ALLOC(lp->vW[l], 4 * nw);
+        LP_ALLOC(lp->b[l], 4 * nb); LP_ALLOC(lp->mb[l], 4 * nb); LP_ALLOC(lp->vb[l], 4 * nb);
+        LP_ALLOC(lp->gW[l], 4 * (size_t)kParamRows[l] * (l == 0 ? kInPad : kParamCols[l]));
+        LP_ALLOC(lp->gb[l], 4 * nb);
+    }
+    LP_ALLOC(lp->W1b, 2 * (size_t)kHid * kInPad);
+    LP_ALLOC(lp->W2b, 2 * (size_t)kHid * kHid);
+    LP_ALLOC(lp->W3b, 2 * (size_t)kOut * kHid);
+    LP_ALLOC(lp->W2t, 2 * (size_t)kHid * kHid);
+    LP_ALLOC(lp->W3t, 2 * (size_t)kHid * kOut);
+    const size_t R = (size_t)max_rows;
+    LP_ALLOC(lp->X, 2 * R * kInPad);
+    LP_ALLOC(lp->Y1, 2 * R * kHid);
+    LP_ALLOC(lp->Y2, 2 * R * kHid);
+    LP_ALLOC(lp->Y3, 4 * R * kOut);
+    LP_ALLOC(lp->T, 4 * R * kOut);
+    LP_ALLOC(lp->scale, 4 * R);
+    LP_ALLOC(lp->part, 8 * 4096);
+    LP_ALLOC(lp->loss, 4);
+#undef LP_ALLOC
+    SEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *out = lp;
+    return SEM_OK;
+}
+
+extern "C" int sem_lp_destroy(sem_lp_t lp) {
+    if (!lp) return SEM_OK;
+    if (lp->ctx) {
+        (void)hipSetDevice(lp->ctx->device);
+        (void)hipStreamSynchronize(lp->ctx->stream);
+    }
+    for (void* p : lp->allocs) (void)hipFree(p);
+    delete lp;
+    return SEM_OK;
+}
+
+extern "C" int sem_lp_set(sem_lp_t lp, int which, const float* host, int64_t count) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_set: null network");
+    int rc = sem::enter(lp->ctx);
+    if (rc) return rc;
+    if (which < 0 || which >= 24 || !host) return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_set: bad slot %d", which);
+    int64_t n;
+    int ld;
+    float** slot = param_slot(lp, which, &n, &ld);
+    if (count != n) return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_set: slot %d holds %lld values, got %lld",
+                                     which, (long long)n, (long long)count);
+    SEM_HIP(lp->ctx, hipStreamSynchronize(lp->ctx->stream));
+    if (ld == kInPad) {   // W1 gradient: 256 x 518 values into a 256 x 528 array
+        for (int r = 0; r < kHid; ++r)
+            SEM_HIP(lp->ctx, hipMemcpy(*slot + (size_t)r * kInPad, host + (size_t)r * kIn, 4 * kIn, hipMemcpyHostToDevice));
+    } else {
+        SEM_HIP(lp->ctx, hipMemcpy(*slot, host, 4 * (size_t)n, hipMemcpyHostToDevice));
+    }
+    if (which < 6) lp->dirty = true;
+    return SEM_OK;
+}
+
+extern "C" int sem_lp_get(sem_lp_t lp, int which, float* host, int64_t count) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_get: null network");
+    int rc = sem::enter(lp->ctx);
+    if (rc) return rc;
+    if (which < 0 || which >= 24 || !host) return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_get: bad slot %d", which);
+    int64_t n;
+    int ld;
+    float** slot = param_slot(lp, which, &n, &ld);
+    if (count != n) return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_get: slot %d holds %lld values, got %lld",
+                                     which, (long long)n, (long long)count);
+    SEM_HIP(lp->ctx, hipStreamSynchronize(lp->ctx->stream));
+    if (ld == kInPad) {
+        for (int r = 0; r < kHid; ++r)
+            SEM_HIP(lp->ctx, hipMemcpy(host + (size_t)r * kIn, *slot + (size_t)r * kInPad, 4 * kIn, hipMemcpyDeviceToHost));
+    } else {
+        SEM_HIP(lp->ctx, hipMemcpy(host, *slot, 4 * (size_t)n, hipMemcpyDeviceToHost));
+    }
+    return SEM_OK;
+}
+
+extern "C" int sem_lp_set_step(sem_lp_t lp, int64_t step) {
+    if (!lp || step < 0) return sem::fail(lp ? lp->ctx : nullptr, SEM_EINVAL, "sem_lp_set_step: bad argument");
+    lp->step = step;
+    return SEM_OK;
+}
+
+extern "C" int sem_lp_get_step(sem_lp_t lp, int64_t* step) {
+    if (!lp || !step) return sem::fail(lp ? lp->ctx : nullptr, SEM_EINVAL, "sem_lp_get_step: bad argument");
+    *step = lp->step;
+    return SEM_OK;
+}
+
+extern "C" int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_bind: null network");
+    sem_ctx_t ctx = lp->ctx;
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (!A || !gs) return sem::fail(ctx, SEM_EINVAL, "sem_lp_bind: null operator or plan");
+    if (A->lx != 8) return sem::fail(ctx, SEM_EUNSUPPORTED_LX, "sem_lp_bind: the network is built for lx = 8, got %d", A->lx);
+    if (A->nel < 1 || A->nel > lp->max_rows)
+        return sem::fail(ctx, SEM_EINVAL, "sem_lp_bind: nel=%lld outside [1, max_rows=%lld]",
+                         (long long)A->nel, (long long)lp->max_rows);
+    if (gs->n_local != A->nel * kOut) return sem::fail(ctx, SEM_EINVAL, "sem_lp_bind: plan size mismatch");
+    if (!A->g11 || !A->g22 || !A->g33 || !A->g12 || !A->g13 || !A->g23)
+        return sem::fail(ctx, SEM_EINVAL, "sem_lp_bind: null geometric factor");
+    if (lp->nel < A->nel) {
+        void* p = nullptr;
+        rc = lp_alloc(lp, &p, 4 * 6 * (size_t)A->nel);
+        if (rc) return rc;
+        lp->geo = (float*)p;
+        rc = lp_alloc(lp, &p, 4 * (size_t)A->nel);
+        if (rc) return rc;
+        lp->kappa = (float*)p;
+    }
+    lp->nel = A->nel;
+    lp->gs = gs;
+    geo_kernel<<<(unsigned)A->nel, 64, 0, ctx->stream>>>(lp->geo, lp->kappa, A->h1, A->g11, A->g22, A->g33,
+                                                         A->g12, A->g13, A->g23, A->nel);
+    SEM_LAUNCH_CHECK(ctx);
+    return SEM_OK;
+}
+
+extern "C" int sem_lp_samples(sem_lp_t lp, const double* r, const double* err, const int64_t* elems,
+                              int64_t count, uint16_t* X, float* T, int64_t row0) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_samples: null network");
+    sem_ctx_t ctx = lp->ctx;
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (!lp->geo) return sem::fail(ctx, SEM_EINVAL, "sem_lp_samples: bind an operator first");
+    if (!r || !X || !elems || count < 0 || row0 < 0 || (T && !err))
+        return sem::fail(ctx, SEM_EINVAL, "sem_lp_samples: bad argument");
+    if (count == 0) return SEM_OK;
+    features_kernel<double><<<(unsigned)count, 64, 0, ctx->stream>>>(X, nullptr, T, r, err, lp->geo, lp->kappa,
+                                                                      elems, count, row0, nullptr);
+    SEM_LAUNCH_CHECK(ctx);
+    return SEM_OK;
+}
+
+extern "C" int sem_lp_forward(sem_lp_t lp, const uint16_t* X, int64_t rows, float* Y) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_forward: null network");
+    sem_ctx_t ctx = lp->ctx;
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (!X || !Y || rows < 0 || rows > lp->max_rows) return sem::fail(ctx, SEM_EINVAL, "sem_lp_forward: bad argument");
+    if (rows == 0) return SEM_OK;
+    rc = forward(lp, X, rows);
+    if (rc) return rc;
+    SEM_HIP(ctx, hipMemcpyAsync(Y, lp->Y3, 4 * (size_t)rows * kOut, hipMemcpyDeviceToDevice, ctx->stream));
+    return SEM_OK;
+}
+
+// gradients of the batch loss into the gradient slots (and the loss into *loss_dev)
+static int lp_backward(sem_lp_t lp, const uint16_t* Xb, const float* Tb, int B) {
+    sem_ctx_t ctx = lp->ctx;
+    hipStream_t st = ctx->stream;
+    int rc = forward(lp, Xb, B);
+    if (rc) return rc;
+    const int64_t n3 = (int64_t)B * kOut;
+    const unsigned g = grid_of(n3);
+    mse_grad<<<g, kBlock, 0, st>>>(lp->d3f, lp->d3b, lp->Y3, Tb, n3, 2.0f / (float)n3, lp->part);
+    loss_final<<<1, 64, 0, st>>>(lp->loss, lp->part, (int)g, 1.0 / (double)n3);
+    SEM_LAUNCH_CHECK(ctx);
+    // layer 3: gW3 = d3^T Y2, gb3 = colsum d3, d2 = (d3 W3) * (Y2 > 0)
+    rc = transpose(lp, lp->tA, B, lp->d3b, kOut, B, kOut);           // d3^T: 512 x B
+    if (!rc) rc = transpose(lp, lp->tB, B, lp->Y2, kHid, B, kHid);   // Y2^T: 256 x B
+    if (!rc) rc = gemm(lp, kOut, kHid, B, lp->tA, B, lp->tB, B, nullptr, nullptr, 0, lp->gW[2], nullptr, kHid, 0);
+    colsum<<<(kOut + 255) / 256, 256, 0, st>>>(lp->gb[2], lp->d3f, B, kOut);
+    if (!rc) rc = gemm(lp, B, kHid, kOut, lp->d3b, kOut, lp->W3t, kOut, nullptr, lp->Y2, kHid, lp->d2f, lp->d2b, kHid, EPI_MASK);
+    // layer 2
+    if (!rc) rc = transpose(lp, lp->tA, B, lp->d2b, kHid, B, kHid);
+    if (!rc) rc = transpose(lp, lp->tB, B, lp->Y1, kHid, B, kHid);
+    if (!rc) rc = gemm(lp, kHid, kHid, B, lp->tA, B, lp->tB, B, nullptr, nullptr, 0, lp->gW[1], nullptr, kHid, 0);
+    colsum<<<(kHid + 255) / 256, 256, 0, st>>>(lp->gb[1], lp->d2f, B, kHid);
+    if (!rc) rc = gemm(lp, B, kHid, kHid, lp->d2b, kHid, lp->W2t, kHid, nullptr, lp->Y1, kHid, lp->d1f, lp->d1b, kHid, EPI_MASK);
+    // layer 1
+    if (!rc) rc = transpose(lp, lp->tA, B, lp->d1b, kHid, B, kHid);
+    if (!rc) rc = transpose(lp, lp->tB, B, Xb, kInPad, B, kInPad);
+    if (!rc) rc = gemm(lp, kHid, kInPad, B, lp->tA, B, lp->tB, B, nullptr, nullptr, 0, lp->gW[0], nullptr, kInPad, 0);
+    colsum<<<(kHid + 255) / 256, 256, 0, st>>>(lp->gb[0], lp->d1f, B, kHid);
+    SEM_LAUNCH_CHECK(ctx);
+    return rc;
+}
+
+static int lp_train_buffers(sem_lp_t lp, int B) {
+    if (lp->d3f) return SEM_OK;
+    const size_t R = (size_t)lp->max_rows;
+    void* p = nullptr;
+    int rc;
+#define LP_ALLOC2(ptr, bytes) do { rc = lp_alloc(lp, &p, (bytes)); if (rc) return rc; ptr = (decltype(ptr))p; } while (0)
+    LP_ALLOC2(lp->d3f, 4 * R * kOut);
+    LP_ALLOC2(lp->d3b, 2 * R * kOut);
+    LP_ALLOC2(lp->d2f, 4 * R * kHid);
+    LP_ALLOC2(lp->d2b, 2 * R * kHid);
+    LP_ALLOC2(lp->d1f, 4 * R * kHid);
+    LP_ALLOC2(lp->d1b, 2 * R * kHid);
+    LP_ALLOC2(lp->tA, 2 * R * kInPad);
+    LP_ALLOC2(lp->tB, 2 * R * kInPad);
+#undef LP_ALLOC2
+    (void)B;
+    return SEM_OK;
+}
+
+extern "C" int sem_lp_gradients(sem_lp_t lp, const uint16_t* X, const float* T, int64_t B, float* loss) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_gradients: null network");
+    sem_ctx_t ctx = lp->ctx;
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (!X || !T || B < 1 || B > lp->max_rows || B % 8)
+        return sem::fail(ctx, SEM_EINVAL, "sem_lp_gradients: batch %lld must be in [1, max_rows], a multiple of 8",
+                         (long long)B);
+    rc = lp_train_buffers(lp, (int)B);
+    if (!rc) rc = lp_backward(lp, X, T, (int)B);
+    if (rc) return rc;
+    if (loss) {
+        SEM_HIP(ctx, hipMemcpyAsync(loss, lp->loss, 4, hipMemcpyDeviceToHost, ctx->stream));
+        SEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return SEM_OK;
+}
+
+extern "C" int sem_lp_adam(sem_lp_t lp, double lr, double beta1, double beta2, double eps) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_adam: null network");
+    sem_ctx_t ctx = lp->ctx;
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    lp->step += 1;
+    const double c1 = 1.0 - std::pow(beta1, (double)lp->step);
+    const double c2 = 1.0 - std::pow(beta2, (double)lp->step);
+    for (int l = 0; l < 3; ++l) {
+        const int rows = kParamRows[l], cols = kParamCols[l];
+        adam_kernel<<<grid_of((int64_t)rows * cols), kBlock, 0, ctx->stream>>>(
+            lp->W[l], lp->mW[l], lp->vW[l], lp->gW[l], rows, cols, l == 0 ? kInPad : cols, (float)lr,
+            (float)beta1, (float)(1.0 - beta1), (float)beta2, (float)(1.0 - beta2), (float)eps,
+            (float)c1, (float)c2);
+        adam_kernel<<<grid_of(rows), kBlock, 0, ctx->stream>>>(
+            lp->b[l], lp->mb[l], lp->vb[l], lp->gb[l], 1, rows, rows, (float)lr, (float)beta1,
+            (float)(1.0 - beta1), (float)beta2, (float)(1.0 - beta2), (float)eps, (float)c1, (float)c2);
+    }
+    SEM_LAUNCH_CHECK(ctx);
+    lp->dirty = true;
+    return SEM_OK;
+}
+
+extern "C" int sem_lp_train_step(sem_lp_t lp, const uint16_t* X, const float* T, const int64_t* rows,
+                                 int64_t B, double lr, float* loss) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_train_step: null network");
+    sem_ctx_t ctx = lp->ctx;
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (!X || !T || !rows || B < 8 || B > lp->max_rows || B % 8)
+        return sem::fail(ctx, SEM_EINVAL, "sem_lp_train_step: bad batch (%lld)", (long long)B);
+    rc = lp_train_buffers(lp, (int)B);
+    if (rc) return rc;
+    gather_rows<<<(unsigned)B, 256, 0, ctx->stream>>>(lp->X, lp->T, X, T, rows, (int)B);
+    SEM_LAUNCH_CHECK(ctx);
+    rc = lp_backward(lp, lp->X, lp->T, (int)B);
+    if (rc) return rc;
+    rc = sem_lp_adam(lp, lr, 0.9, 0.999, 1e-8);
+    if (rc) return rc;
+    if (loss) SEM_HIP(ctx, hipMemcpyAsync(loss, lp->loss, 4, hipMemcpyDeviceToDevice, ctx->stream));
+    return SEM_OK;
+}
+
+namespace sem {
+
+// z = Q Q^T (mult^-1 (s/kappa) NN(features(r))) for the bound operator
+template <typename T>
+int lp_apply_t(sem_lp_t lp, T* z, const T* r) {
+    sem_ctx_t ctx = lp->ctx;
+    hipStream_t st = ctx->stream;
+    const int64_t nel = lp->nel;
+    features_kernel<T><<<(unsigned)nel, 64, 0, st>>>(lp->X, lp->scale, nullptr, r, nullptr, lp->geo,
+                                                     lp->kappa, nullptr, nel, 0, lp->skip);
+    SEM_LAUNCH_CHECK(ctx);
+    int rc = forward(lp, lp->X, nel);
+    if (rc) return rc;
+    const int64_t n = nel * kOut;
+    lp_output_kernel<T><<<grid_of(n), kBlock, 0, st>>>(z, lp->Y3, lp->scale, lp->gs->mult, n, lp->skip);
+    SEM_LAUNCH_CHECK(ctx);
+    return gs_launch(lp->gs, z, sizeof(T) == 8 ? SEM_F64 : SEM_F32, lp->skip);
+}
+
+int lp_apply(sem_lp_t lp, void* z, const void* r, bool f64, const int* skip) {
+    if (!lp->geo || !lp->gs) return fail(lp->ctx, SEM_EINVAL, "learned preconditioner has no bound operator");
+    lp->skip = skip;
+    const int rc = f64 ? lp_apply_t<double>(lp, (double*)z, (const double*)r)
+                       : lp_apply_t<float>(lp, (float*)z, (const float*)r);
+    lp->skip = nullptr;
+    return rc;
+}
+
+int64_t lp_rows(sem_lp_t lp) { return lp->nel; }
+sem_gs_t lp_plan(sem_lp_t lp) { return lp->gs; }
+
+}  // namespace sem
+
+extern "C" int sem_lp_apply(sem_lp_t lp, void* z, const void* r, sem_dtype_t dtype) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_apply: null network");
+    int rc = sem::enter(lp->ctx);
+    if (rc) return rc;
+    if (!z || !r || (dtype != SEM_F64 && dtype != SEM_F32))
+        return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_apply: bad argument");
+    return sem::lp_apply(lp, z, r, dtype == SEM_F64, nullptr);
+}

@@ -62,6 +62,13 @@ enum class AxKind {
 int launch_ax(sem_ctx_t ctx, AxKind kind, const AxArgs& a, void* w, const void* u,
               const int* skip, double* dot);
 int ax_blocks(int lx, int64_t nel);
+// gather-scatter launch that returns at once when skip && *skip
+int gs_launch(sem_gs_t gs, void* u, sem_dtype_t dtype, const int* skip);
+// learned preconditioner z = P(r) on the bound operator (lp.hip); vectors
+// float64 (f64) or float32; kernels return at once when skip && *skip
+int lp_apply(sem_lp_t lp, void* z, const void* r, bool f64, const int* skip);
+int64_t lp_rows(sem_lp_t lp);
+sem_gs_t lp_plan(sem_lp_t lp);
 
 #ifdef __HIPCC__
 // sum over the 64 lanes of a wave

@@ -1,0 +1,246 @@
+"""GPU kernels of the learned preconditioner against the FP64 oracle
+(oracle/mlp.py): forward, gradients, Adam, features, apply; training
+determinism and checkpoint/resume; flexible CG with its Jacobi fallbacks."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import mlp
+from oracle.quant import to_bf16
+from oracle.mesh import global_ids
+from oracle.solve import BoxProblem, pcg
+from tests.helpers import to_dev
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2506_20994_amd")
+from paper_2506_20994_amd.box import BoxOperator  # noqa: E402
+
+GRAD_TOL = 2e-2    # normwise, bf16 operands with float32 accumulation
+
+
+def _nrm(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def _params(seed, bias_scale=0.1):
+    p = synth.mlp_init(seed)
+    r = synth.rng(seed + 1)
+    return [q if q.ndim == 2 else bias_scale * r.standard_normal(q.shape) for q in p]
+
+
+def _load(lp, params):
+    for s, q in enumerate(params):
+        P.sem_lp_set(lp, s, q.astype(np.float32))
+
+
+def _inputs(B, seed):
+    r = synth.rng(seed)
+    X = r.standard_normal((B, 518))
+    X[:, :512] /= np.linalg.norm(X[:, :512], axis=1, keepdims=True)
+    Xq = to_bf16(X)
+    Xpad = np.zeros((B, 528), dtype=np.float32)
+    Xpad[:, :518] = Xq
+    T = r.standard_normal((B, 512)) * 0.1
+    return Xq, torch.from_numpy(Xpad).to(torch.bfloat16).cuda(), T
+
+
+def _qparams(params):
+    return [to_bf16(q) if q.ndim == 2 else q.astype(np.float32).astype(np.float64) for q in params]
+
+
+def test_forward(sem_ctx):
+    B = 300
+    params = _params(10)
+    lp = P.sem_lp_create(sem_ctx, 512)
+    _load(lp, params)
+    Xq, Xd, _ = _inputs(B, 11)
+    Y = torch.empty((B, 512), dtype=torch.float32, device="cuda")
+    P.sem_lp_forward(lp, Xd, Y)
+    torch.cuda.synchronize()
+    ref = mlp.forward(_qparams(params), Xq)[2]
+    assert _nrm(Y.cpu().numpy(), ref) <= GRAD_TOL
+    lp.close()
+
+
+def test_gradients(sem_ctx):
+    B = 256
+    params = _params(20)
+    lp = P.sem_lp_create(sem_ctx, B)
+    _load(lp, params)
+    Xq, Xd, T = _inputs(B, 21)
+    loss = P.sem_lp_gradients(lp, Xd, to_dev(T.astype(np.float32)))
+    l_ref, g_ref = mlp.backward(_qparams(params), Xq, T)
+    assert abs(loss - l_ref) <= GRAD_TOL * l_ref
+    for s in range(6):
+        g = P.sem_lp_get(lp, 18 + s)
+        assert _nrm(g, g_ref[s]) <= GRAD_TOL, (s, _nrm(g, g_ref[s]))
+    lp.close()
+
+
+def test_adam_matches_oracle(sem_ctx):
+    lp = P.sem_lp_create(sem_ctx, 8)
+    params = _params(30)
+    _load(lp, params)
+    r = synth.rng(31)
+    grads = [r.standard_normal(q.shape) for q in params]
+    m = [np.zeros(q.shape) for q in params]
+    v = [np.zeros(q.shape) for q in params]
+    p_ref = [q.astype(np.float32).astype(np.float64) for q in params]
+    for t in range(1, 4):
+        for s, g in enumerate(grads):
+            P.sem_lp_set(lp, 18 + s, (g * t).astype(np.float32))
+        P.sem_lp_adam(lp, lr=1e-2)
+        p_ref, m, v = mlp.adam_step(p_ref, [g * t for g in grads], m, v, t, lr=1e-2)
+    assert P.sem_lp_get_step(lp) == 3
+    for s in range(6):
+        got = P.sem_lp_get(lp, s)
+        assert np.max(np.abs(got - p_ref[s])) <= 1e-5 * max(1.0, np.max(np.abs(p_ref[s]))), s
+        assert _nrm(P.sem_lp_get(lp, 6 + s), m[s]) <= 1e-6
+        assert _nrm(P.sem_lp_get(lp, 12 + s), v[s]) <= 1e-6
+    lp.close()
+
+
+def _box_with_lp(ctx, n, amp, seed=40, max_rows=None):
+    op = BoxOperator(ctx, n, 8, amp)
+    lp = P.sem_lp_create(ctx, max_rows or op.nel)
+    op.bind(lp)
+    return op, lp
+
+
+def test_features_and_targets(sem_ctx):
+    n, amp = 2, 0.1
+    op, lp = _box_with_lp(sem_ctx, n, amp)
+    ref = BoxProblem(n, 8, amp)
+    rG = synth.unique_normal(ref.nu, 41)
+    eG = synth.unique_normal(ref.nu, 42)
+    r = op.scatter(rG)
+    e = op.scatter(eG)
+    els = torch.tensor([3, 0, 7, 5], dtype=torch.int64, device="cuda")
+    X = torch.zeros((6, 528), dtype=torch.bfloat16, device="cuda")
+    T = torch.zeros((6, 512), dtype=torch.float32, device="cuda")
+    P.sem_lp_samples(lp, r, e, els, X, T, 2)
+    torch.cuda.synchronize()
+    ids = ref.ids
+    sel = els.cpu().numpy()
+    Xr, s, kap = mlp.features(rG[ids][sel], tuple(g[sel] for g in ref.G), None)
+    Tr = mlp.targets(eG[ids][sel], s, kap)
+    Xg = X.float().cpu().numpy()
+    assert np.all(Xg[:2] == 0) and np.all(Xg[2:, 518:] == 0)
+    # bf16 of the same float64 quantity: equal up to one bf16 ulp
+    assert np.max(np.abs(Xg[2:, :518] - to_bf16(Xr)) / np.maximum(np.abs(to_bf16(Xr)), 1e-30)) <= 2 ** -7
+    np.testing.assert_allclose(T[2:].cpu().numpy(), Tr, rtol=1e-5, atol=1e-7 * np.abs(Tr).max())
+    lp.close()
+
+
+def test_apply_matches_oracle(sem_ctx):
+    n, amp = 2, 0.1
+    op, lp = _box_with_lp(sem_ctx, n, amp)
+    params = _params(50)
+    _load(lp, params)
+    ref = BoxProblem(n, 8, amp)
+    rG = synth.unique_normal(ref.nu, 51)
+    for dt in (torch.float64, torch.float32):
+        r = op.scatter(rG).to(dt)
+        z = torch.empty_like(r)
+        P.sem_lp_apply(lp, z, r)
+        torch.cuda.synchronize()
+        zref = mlp.apply(_qparams(params), rG[ref.ids], ref.G, None, ref.ids, ref.nu)
+        assert _nrm(z.double().cpu().numpy(), zref) <= GRAD_TOL
+        zu = np.zeros(ref.nu)
+        zu[ref.ids.ravel()] = z.double().cpu().numpy().ravel()
+        np.testing.assert_array_equal(z.double().cpu().numpy(), zu[ref.ids])   # continuous
+    lp.close()
+
+
+def _train(lp, X, T, steps, seed, B=64):
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    out = []
+    for k in range(steps):
+        rows = torch.from_numpy(synth.choice(seed + k, X.shape[0], B)).cuda()
+        P.sem_lp_train_step(lp, X, T, rows, 1e-3, loss)
+        out.append(float(loss))
+    return out
+
+
+def test_training_reduces_loss_and_resumes_bitwise(sem_ctx):
+    N = 512
+    r = synth.rng(60)
+    Xf = np.zeros((N, 528), dtype=np.float32)
+    Xf[:, :518] = to_bf16(r.standard_normal((N, 518)) * 0.2)
+    A = r.standard_normal((518, 512)) * 0.05
+    T = (Xf[:, :518] @ A).astype(np.float32)
+    X = torch.from_numpy(Xf).to(torch.bfloat16).cuda()
+    Td = to_dev(T)
+    params = _params(61)
+    lp = P.sem_lp_create(sem_ctx, 64)
+    _load(lp, params)
+    losses = _train(lp, X, Td, 40, 1000)
+    assert np.mean(losses[-5:]) < 0.5 * np.mean(losses[:5])
+    # resume: 20 steps, save, reload into a new network, 20 more == 40 straight
+    lp2 = P.sem_lp_create(sem_ctx, 64)
+    _load(lp2, params)
+    _train(lp2, X, Td, 20, 1000)
+    saved = [P.sem_lp_get(lp2, s) for s in range(18)]
+    step = P.sem_lp_get_step(lp2)
+    lp3 = P.sem_lp_create(sem_ctx, 64)
+    for s in range(18):
+        P.sem_lp_set(lp3, s, saved[s])
+    P.sem_lp_set_step(lp3, step)
+    _train(lp3, X, Td, 20, 1020)
+    for s in range(6):
+        np.testing.assert_array_equal(P.sem_lp_get(lp3, s), P.sem_lp_get(lp, s))
+    for h in (lp, lp2, lp3):
+        h.close()
+
+
+@pytest.mark.parametrize("kind", ["nan", "zero"])
+def test_fcg_falls_back_to_jacobi(sem_ctx, kind):
+    """A network that outputs NaN (or zero) is replaced by Jacobi on every
+    iteration: FCG then reproduces Jacobi-PCG and still converges."""
+    n, amp = 2, 0.1
+    op, lp = _box_with_lp(sem_ctx, n, amp)
+    params = _params(70)
+    if kind == "nan":
+        params[5] = params[5] + np.nan
+    else:
+        params = [0 * q for q in params]
+    _load(lp, params)
+    k, a, ph = synth.fourier_modes(2)
+    b = op.fourier_rhs(k, a, ph)
+    x = torch.empty_like(b)
+    cg = op.solver(P.SEM_SOLVE_F64, learned=lp)
+    rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10, learned=lp)
+    assert st["converged"] and st["relres"] <= 1e-10
+    assert st["jacobi_steps"] == st["iterations"]
+    cg0 = op.solver(P.SEM_SOLVE_F64)
+    x0 = torch.empty_like(b)
+    _, st0 = P.sem_cg_solve(cg0, x0, b, tol=1e-10)
+    assert abs(st["iterations"] - st0["iterations"]) <= 1
+    torch.cuda.synchronize()
+    assert float((x - x0).abs().max()) <= 1e-8 * float(x0.abs().max())
+    for h in (cg, cg0, lp):
+        h.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fcg_untrained_network_converges(sem_ctx, prec):
+    n, amp = 3, 0.1
+    op, lp = _box_with_lp(sem_ctx, n, amp)
+    _load(lp, _params(80))
+    k, a, ph = synth.fourier_modes(3)
+    b = op.fourier_rhs(k, a, ph)
+    ref = BoxProblem(n, 8, amp)
+    bref = ref.fourier_rhs(k, a, ph)
+    x = torch.empty_like(b)
+    cg = op.solver(prec, learned=lp)
+    rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10, precision=prec, learned=lp, maxit=20000)
+    torch.cuda.synchronize()
+    assert st["converged"], st
+    xg = np.zeros(ref.nu)
+    xg[ref.ids.ravel()] = x.cpu().numpy().ravel()
+    assert np.linalg.norm(bref - ref.apply(xg)) / np.linalg.norm(bref) <= 1.2e-10
+    print(f"untrained FCG prec={prec}: {st}")
+    for h in (cg, lp):
+        h.close()
