@@ -9,13 +9,21 @@ the library adds around the paper's Poisson solve.  Readings taken:
   * target: t_e = e_e kappa_e / s_e (dimensionless), e_e the element's error;
   * network: Linear-ReLU-Linear-ReLU-Linear, 518 -> 256 -> 256 -> 512,
     weights (fan_out, fan_in);
-  * loss: mean squared error over all outputs of the batch;
+  * loss: mean squared error over all outputs of the batch, or, with a metric
+    K, the batch mean of (y - t)^T K (y - t).  The preconditioner is judged
+    in the energy norm (the norm CG minimises), so the metric used is
+    K = A_ref + mu B_ref: the stiffness of the undeformed reference element
+    (geometric factors w_i w_j w_k on the diagonal, scaled so that its kappa
+    is 1) plus mu times its mass matrix scaled to unit mean diagonal, which
+    pins the element-wise constant the stiffness alone leaves free;
   * optimiser: Adam (Kingma and Ba 2015) with bias correction;
   * apply: z_e = (s_e / kappa_e) t_hat_e, then the partition-of-unity average
     z = Q Q^T (z_local / mult) to make z continuous.
 Pins (tests/test_oracle_mlp.py): backpropagation against central finite
-differences; Adam against its closed form for a constant gradient; the
-features' scale invariance; apply returns a continuous field.
+differences (both losses); Adam against its closed form for a constant
+gradient; the features' scale invariance; apply returns a continuous field;
+the reference metric is symmetric positive definite and its stiffness part
+gives the exact energy of polynomials of degree <= N on the reference cube.
 """
 import numpy as np
 
@@ -50,15 +58,39 @@ def forward(params, X):
     return y1, y2, y3
 
 
-def loss(params, X, T):
-    return float(np.mean((forward(params, X)[2] - T) ** 2))
+def reference_metric(lx=8, mu=1.0):
+    """K = A_ref + mu B_ref (see module docstring), (lx^3, lx^3)."""
+    from .gll import gll_nodes_weights, deriv_matrix
+    from .ax import element_matrix
+    xi, w = gll_nodes_weights(lx - 1)
+    Dh = deriv_matrix(xi)
+    wq = (w[:, None, None] * w[None, :, None] * w[None, None, :])[None]
+    zero = np.zeros_like(wq)
+    A = element_matrix(Dh, None, (wq, wq, wq, zero[0:1], zero[0:1], zero[0:1]))
+    kappa = np.mean(wq)            # mean of (g11 + g22 + g33) / 3
+    Bm = np.diag(wq.ravel() / np.mean(wq))
+    return A / kappa + mu * Bm
 
 
-def backward(params, X, T):
-    """(loss, grads) of the mean squared error, grads in params' order."""
+def loss(params, X, T, K=None):
+    d = forward(params, X)[2] - T
+    if K is None:
+        return float(np.mean(d ** 2))
+    return float(np.mean(np.einsum("bi,ij,bj->b", d, K, d)))
+
+
+def backward(params, X, T, K=None):
+    """(loss, grads) of the loss above, grads in params' order."""
     W1, b1, W2, b2, W3, b3 = params
     y1, y2, y3 = forward(params, X)
-    d3 = 2.0 * (y3 - T) / y3.size
+    if K is None:
+        d3 = 2.0 * (y3 - T) / y3.size
+        lval = float(np.mean((y3 - T) ** 2))
+    else:
+        d = y3 - T
+        Kd = d @ K
+        d3 = 2.0 * Kd / d.shape[0]
+        lval = float(np.mean(np.sum(d * Kd, axis=1)))
     gW3 = d3.T @ y2
     gb3 = d3.sum(axis=0)
     d2 = (d3 @ W3) * (y2 > 0)
@@ -67,7 +99,7 @@ def backward(params, X, T):
     d1 = (d2 @ W2) * (y1 > 0)
     gW1 = d1.T @ X
     gb1 = d1.sum(axis=0)
-    return float(np.mean((y3 - T) ** 2)), [gW1, gb1, gW2, gb2, gW3, gb3]
+    return lval, [gW1, gb1, gW2, gb2, gW3, gb3]
 
 
 def adam_step(params, grads, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

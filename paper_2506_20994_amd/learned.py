@@ -1,0 +1,106 @@
+"""Training pipeline of the learned preconditioner: snapshot generation from
+float64 Jacobi-PCG solves, minibatch training, held-out evaluation.
+
+Orchestration only: every array is produced by libsem.so kernels (mesh,
+geometry, solves, operator, features, MLP, Adam); random draws come from
+``synth``.  Recipe (readings of the training set-up):
+  * training boxes: n^3 periodic, lx = 8, deformation amplitude ~ U[0, 0.2],
+    draws whose minimum det J falls below 5% of the undeformed value rejected
+    (the map folds near 1 / (2 pi));
+  * right-hand side: 32 random Fourier modes per box;
+  * x* from float64 Jacobi-PCG to 1e-12; snapshots x_k at iterations k spread
+    log-uniformly over the solve, r_k = b - A x_k, e_k = x* - x_k;
+  * per snapshot, `elems_per_snapshot` random elements become training rows.
+"""
+import time
+
+import numpy as np
+import torch
+
+import synth
+from . import _binding as B
+from .box import BoxOperator
+
+
+def _residual(op, x, b, out):
+    """out = b - gs(Ax(x))"""
+    op.apply(out, x)
+    torch.sub(b, out, out=out)
+    return out
+
+
+def generate(ctx, lp, n=16, boxes=16, snapshots=16, elems_per_snapshot=64, seed=100,
+             amp_range=(0.0, 0.2), min_rel_detj=0.05, verbose=False):
+    """Returns (X bf16 [rows, 528], T float32 [rows, 512], info)."""
+    lx = 8
+    nel = n ** 3
+    rows = boxes * snapshots * elems_per_snapshot
+    X = torch.zeros((rows, B.SEM_LP_IN_PAD), dtype=torch.bfloat16, device="cuda")
+    T = torch.zeros((rows, B.SEM_LP_OUT), dtype=torch.float32, device="cuda")
+    row, box, draw, rejected = 0, 0, 0, 0
+    t0 = time.perf_counter()
+    amps = []
+    while box < boxes:
+        a = float(synth.amplitudes(seed + draw, 1, *amp_range)[0])
+        draw += 1
+        try:
+            op = BoxOperator(ctx, n, lx, a)
+        except B.SemError:
+            rejected += 1
+            continue
+        if op.min_detj * 8 * n ** 3 <= min_rel_detj:
+            rejected += 1
+            continue
+        amps.append(a)
+        k, am, ph = synth.fourier_modes(seed + 10_000 + box)
+        b = op.fourier_rhs(k, am, ph)
+        cg = op.solver(B.SEM_SOLVE_F64)
+        xs = torch.empty_like(b)
+        _, st = B.sem_cg_solve(cg, xs, b, tol=1e-12, maxit=100000)
+        kmax = max(1, st["iterations"] - 1)
+        its = synth.snapshot_iterations(seed + 20_000 + box, snapshots, kmax)
+        its = np.resize(its, snapshots)       # duplicates if the draw collapsed
+        op.bind(lp)
+        xk = torch.empty_like(b)
+        rk = torch.empty_like(b)
+        for q, kq in enumerate(its):
+            B.sem_cg_solve(cg, xk, b, tol=1e-12, maxit=int(kq), check_every=int(min(kq, 16)))
+            _residual(op, xk, b, rk)
+            err = xs - xk
+            els = torch.from_numpy(synth.choice(seed + 30_000 + box * 1000 + q, nel,
+                                                elems_per_snapshot)).cuda()
+            B.sem_lp_samples(lp, rk, err, els, X, T, row)
+            row += elems_per_snapshot
+        cg.close()
+        op.gs.close()
+        if verbose:
+            print(f"[learned] box {box}: amp {a:.3f}, x* in {st['iterations']} its, "
+                  f"snapshots {list(its[:4])}...", flush=True)
+        box += 1
+    torch.cuda.synchronize()
+    info = {"rows": rows, "boxes": boxes, "rejected_draws": rejected, "amplitudes": amps,
+            "seconds": time.perf_counter() - t0}
+    return X, T, info
+
+
+def train(lp, X, T, epochs=4, batch=1024, lr=1e-3, seed=500, verbose=False):
+    """Minibatch Adam over (X, T); returns per-epoch mean losses."""
+    rows = X.shape[0]
+    nb = rows // batch
+    loss = torch.zeros(nb, dtype=torch.float32, device="cuda")
+    hist = []
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        perm = torch.from_numpy(synth.permutation(seed + ep, rows)).cuda()
+        for q in range(nb):
+            B.sem_lp_train_step(lp, X, T, perm[q * batch:(q + 1) * batch], lr, loss[q:q + 1])
+        hist.append(float(loss.mean()))
+        if verbose:
+            print(f"[learned] epoch {ep}: loss {hist[-1]:.4e} ({time.perf_counter() - t0:.1f} s)",
+                  flush=True)
+    return hist
+
+
+def init_network(lp, seed=7):
+    for s, p in enumerate(synth.mlp_init(seed)):
+        B.sem_lp_set(lp, s, p.astype(np.float32))

@@ -12,24 +12,53 @@ def _small_net(seed, sizes=(10, 7, 6, 5)):
     return synth.mlp_init(seed, sizes)
 
 
-def test_backprop_matches_finite_differences():
+@pytest.mark.parametrize("metric", [False, True])
+def test_backprop_matches_finite_differences(metric):
     r = np.random.default_rng(0)
     params = _small_net(1)
     params = [p + 0.05 * r.standard_normal(p.shape) for p in params]   # non-zero biases too
     X = r.standard_normal((9, 10))
     T = r.standard_normal((9, 5))
-    _, grads = mlp.backward(params, X, T)
+    K = None
+    if metric:
+        L = r.standard_normal((5, 5))
+        K = L @ L.T + 0.1 * np.eye(5)
+    lval, grads = mlp.backward(params, X, T, K)
+    assert lval == pytest.approx(mlp.loss(params, X, T, K), rel=1e-13)
     h = 1e-6
     for pi, p in enumerate(params):
         fd = np.zeros_like(p)
         for idx in np.ndindex(p.shape):
             pp = [q.copy() for q in params]
             pp[pi][idx] += h
-            lp = mlp.loss(pp, X, T)
+            lp = mlp.loss(pp, X, T, K)
             pp[pi][idx] -= 2 * h
-            lm = mlp.loss(pp, X, T)
+            lm = mlp.loss(pp, X, T, K)
             fd[idx] = (lp - lm) / (2 * h)
         assert np.max(np.abs(fd - grads[pi])) <= 1e-6 * max(1.0, np.max(np.abs(fd))), pi
+
+
+def test_reference_metric():
+    """Stiffness part: exact energy of a degree-N polynomial on the reference
+    cube [-1, 1]^3 (geometric factors w w w, kappa = mean(w w w)); with the
+    mass term the metric is positive definite."""
+    lx = 5
+    from oracle.gll import gll_nodes_weights
+    xi, w = gll_nodes_weights(lx - 1)
+    K0 = mlp.reference_metric(lx, mu=0.0)
+    K1 = mlp.reference_metric(lx, mu=1.0)
+    np.testing.assert_allclose(K1, K1.T, atol=1e-13)
+    ev = np.linalg.eigvalsh(K1)
+    assert ev[0] > 1e-3
+    assert abs(np.linalg.eigvalsh(K0)[0]) < 1e-10        # constants: zero stiffness
+    Z, Y, Xc = np.meshgrid(xi, xi, xi, indexing="ij")
+    u = (Xc ** 2 * Y + 0.5 * Z ** 3 - Xc * Y * Z).ravel()   # total degree 3 <= N = 4
+    kappa = np.mean(w[:, None, None] * w[None, :, None] * w[None, None, :])
+    gq, gw = np.polynomial.legendre.leggauss(6)
+    Qz, Qy, Qx = np.meshgrid(gq, gq, gq, indexing="ij")
+    Wq = gw[:, None, None] * gw[None, :, None] * gw[None, None, :]
+    grad2 = (2 * Qx * Qy - Qy * Qz) ** 2 + (Qx ** 2 - Qx * Qz) ** 2 + (1.5 * Qz ** 2 - Qx * Qy) ** 2
+    assert u @ K0 @ u == pytest.approx(np.sum(Wq * grad2) / kappa, rel=1e-12)
 
 
 def test_adam_constant_gradient_closed_form():
