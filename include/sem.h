@@ -275,6 +275,19 @@ int sem_lp_get(sem_lp_t lp, int which, float* host, int64_t count);
 /* Adam's step counter (the number of updates taken). */
 int sem_lp_set_step(sem_lp_t lp, int64_t step);
 int sem_lp_get_step(sem_lp_t lp, int64_t* step);
+/* Training loss.  mu < 0: mean squared error (the default).  mu >= 0: the
+ * batch mean of (y - t)^T K (y - t) with K = A_ref + mu B_ref, where A_ref is
+ * the stiffness matrix of the undeformed reference element [-1, 1]^3 divided
+ * by its kappa (mean of w_i w_j w_k) and B_ref = diag(w_i w_j w_k) / kappa:
+ * the energy norm CG minimises, plus a mass term that fixes the element-wise
+ * constant.  K is held in bfloat16. */
+int sem_lp_set_metric(sem_lp_t lp, double mu);
+/* Jacobi base (on != 0): the preconditioner becomes z = Minv r + P_net(r),
+ * Minv the inverse assembled diagonal of the bound operator, and training
+ * targets become (err - Minv r) kappa / s, so the network learns the
+ * correction to Jacobi (a network that outputs zero is exactly Jacobi).
+ * Takes effect at the next sem_lp_bind. */
+int sem_lp_set_jacobi_base(sem_lp_t lp, int on);
 /* Bind to an operator (lx = 8, nel <= max_rows) and its plan: computes the
  * per-element geometric features.  Needed by sem_lp_samples / sem_lp_apply. */
 int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs);

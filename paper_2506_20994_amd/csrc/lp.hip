@@ -169,6 +169,40 @@ __global__ void mse_grad(float* __restrict__ d3f, u16* __restrict__ d3b, const f
     }
 }
 
+// d = Y3 - T as float and bf16 (the metric loss's residual)
+__global__ void diff_kernel(float* __restrict__ df, u16* __restrict__ db, const float* __restrict__ Y3,
+                            const float* __restrict__ T, int64_t n) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const float d = Y3[q] - T[q];
+        df[q] = d;
+        db[q] = bf16_rne(d);
+    }
+}
+
+// loss partials sum d.Kd; gradient d3 = scale * Kd (float and bf16)
+__global__ void metric_grad(float* __restrict__ d3f, u16* __restrict__ d3b, const float* __restrict__ df,
+                            const float* __restrict__ Kd, int64_t n, float scale, double* __restrict__ part) {
+    __shared__ double s[kBlock / 64];
+    double acc = 0.0;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const float k = Kd[q];
+        acc += (double)df[q] * k;
+        const float g = scale * k;
+        d3f[q] = g;
+        d3b[q] = bf16_rne(g);
+    }
+    acc = sem::wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < kBlock / 64; ++q) t += s[q];
+        part[blockIdx.x] = t;
+    }
+}
+
 __global__ void loss_final(float* __restrict__ loss, const double* __restrict__ part, int nb, double inv_n) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         double t = 0.0;
@@ -231,6 +265,7 @@ __global__ void geo_kernel(float* __restrict__ geo, float* __restrict__ kappa,
 template <typename T>
 __global__ void features_kernel(u16* __restrict__ X, float* __restrict__ scale, float* __restrict__ Tt,
                                 const T* __restrict__ r, const double* __restrict__ err,
+                                const double* __restrict__ minv,
                                 const float* __restrict__ geo, const float* __restrict__ kappa,
                                 const int64_t* __restrict__ elems, int64_t count, int64_t row0,
                                 const int* __restrict__ skip) {
@@ -257,20 +292,33 @@ __global__ void features_kernel(u16* __restrict__ X, float* __restrict__ scale, 
     if (lane == 0 && scale) scale[row] = (float)(s / kap);
     if (Tt) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-            Tt[row * kOut + c * 64 + lane] = (float)(err[e * kOut + c * 64 + lane] * kap / s);
+        for (int c = 0; c < 8; ++c) {
+            const int64_t L = e * kOut + c * 64 + lane;
+            const double ev = minv ? err[L] - minv[L] * v[c] : err[L];   // Jacobi base removed
+            Tt[row * kOut + c * 64 + lane] = (float)(ev * kap / s);
+        }
     }
 }
 
-// z_L = scale[e] * Y3[e][node] / mult_L
+// z_L = (scale[e] * Y3[e][node] (+ minv_L r_L)) / mult_L
 template <typename T>
 __global__ void lp_output_kernel(T* __restrict__ z, const float* __restrict__ Y3,
                                  const float* __restrict__ scale, const double* __restrict__ mult,
+                                 const double* __restrict__ minv, const T* __restrict__ r,
                                  int64_t n, const int* __restrict__ skip) {
     if (skip && *skip) return;
     for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
+         L += (int64_t)gridDim.x * blockDim.x) {
+        double v = (double)scale[L / kOut] * (double)Y3[L];
+        if (minv) v += minv[L] * (double)r[L];
+        z[L] = (T)(v / mult[L]);
+    }
+}
+
+__global__ void inv_kernel(double* __restrict__ x, int64_t n) {
+    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
          L += (int64_t)gridDim.x * blockDim.x)
-        z[L] = (T)((double)scale[L / kOut] * (double)Y3[L] / mult[L]);
+        x[L] = 1.0 / x[L];
 }
 
 unsigned grid_of(int64_t n, int64_t cap = 4096) {
@@ -297,10 +345,19 @@ struct sem_lp_s {
     double* part = nullptr;
     float* loss = nullptr;
     // bound operator (inference)
-    int64_t nel = 0;
+    int64_t nel = 0, geo_cap = 0;
     float *geo = nullptr, *kappa = nullptr;
+    bool bound = false;
     sem_gs_t gs = nullptr;
     const int* skip = nullptr;   // set by the solver: kernels return when *skip != 0
+    // energy-norm loss: metric K (512 x 512, bf16) and work arrays
+    u16* K = nullptr;
+    float *dF = nullptr, *Kd = nullptr;
+    u16* dB = nullptr;
+    // Jacobi base: z = Minv r + network correction (Minv of the bound operator)
+    bool jacobi_base = false;
+    double* minv = nullptr;
+    int64_t minv_n = 0;
     std::vector<void*> allocs;
 };
 
@@ -478,6 +535,74 @@ extern "C" int sem_lp_get_step(sem_lp_t lp, int64_t* step) {
     return SEM_OK;
 }
 
+extern "C" int sem_lp_set_metric(sem_lp_t lp, double mu) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_set_metric: null network");
+    sem_ctx_t ctx = lp->ctx;
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (mu < 0) {            // back to the plain mean squared error
+        lp->K = nullptr;
+        return SEM_OK;
+    }
+    constexpr int lx = 8;
+    double xi[lx], w[lx], D[lx * lx];   // D[m*lx + i] = l_i'(xi_m)
+    sem::gll_host(lx, xi, w, D);
+    double Kh[lx][lx];                  // 1-D stiffness sum_m w_m l_i'(xi_m) l_i''(xi_m)
+    for (int i = 0; i < lx; ++i)
+        for (int ip = 0; ip < lx; ++ip) {
+            double s = 0.0;
+            for (int m = 0; m < lx; ++m) s += w[m] * D[m * lx + i] * D[m * lx + ip];
+            Kh[i][ip] = s;
+        }
+    double wsum = 0.0;
+    for (int i = 0; i < lx; ++i) wsum += w[i];
+    const double kappa = std::pow(wsum / lx, 3);     // mean of w_i w_j w_k
+    std::vector<u16> Kb((size_t)kOut * kOut);
+    for (int p = 0; p < kOut; ++p) {
+        const int i = p % lx, j = (p / lx) % lx, k = p / (lx * lx);
+        for (int q = 0; q < kOut; ++q) {
+            const int ip = q % lx, jp = (q / lx) % lx, kp = q / (lx * lx);
+            double v = 0.0;
+            if (j == jp && k == kp) v += Kh[i][ip] * w[j] * w[k];
+            if (i == ip && k == kp) v += w[i] * Kh[j][jp] * w[k];
+            if (i == ip && j == jp) v += w[i] * w[j] * Kh[k][kp];
+            v /= kappa;
+            if (p == q) v += mu * w[i] * w[j] * w[k] / kappa;
+            const float f = (float)v;
+            uint32_t b;
+            std::memcpy(&b, &f, 4);
+            b += 0x7fffu + ((b >> 16) & 1u);
+            Kb[(size_t)p * kOut + q] = (u16)(b >> 16);
+        }
+    }
+    if (!lp->K) {
+        const size_t R = (size_t)lp->max_rows;
+        void* p = nullptr;
+        rc = lp_alloc(lp, &p, 2 * (size_t)kOut * kOut);
+        if (rc) return rc;
+        lp->K = (u16*)p;
+        rc = lp_alloc(lp, &p, 4 * R * kOut);
+        if (rc) return rc;
+        lp->dF = (float*)p;
+        rc = lp_alloc(lp, &p, 4 * R * kOut);
+        if (rc) return rc;
+        lp->Kd = (float*)p;
+        rc = lp_alloc(lp, &p, 2 * R * kOut);
+        if (rc) return rc;
+        lp->dB = (u16*)p;
+    }
+    SEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    SEM_HIP(ctx, hipMemcpy(lp->K, Kb.data(), 2 * Kb.size(), hipMemcpyHostToDevice));
+    return SEM_OK;
+}
+
+extern "C" int sem_lp_set_jacobi_base(sem_lp_t lp, int on) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_set_jacobi_base: null network");
+    lp->jacobi_base = on != 0;
+    lp->bound = false;    // a new bind is required
+    return SEM_OK;
+}
+
 extern "C" int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs) {
     if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_bind: null network");
     sem_ctx_t ctx = lp->ctx;
@@ -491,7 +616,8 @@ extern "C" int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs) {
     if (gs->n_local != A->nel * kOut) return sem::fail(ctx, SEM_EINVAL, "sem_lp_bind: plan size mismatch");
     if (!A->g11 || !A->g22 || !A->g33 || !A->g12 || !A->g13 || !A->g23)
         return sem::fail(ctx, SEM_EINVAL, "sem_lp_bind: null geometric factor");
-    if (lp->nel < A->nel) {
+    if (lp->geo_cap < A->nel) {
+        lp->geo_cap = A->nel;
         void* p = nullptr;
         rc = lp_alloc(lp, &p, 4 * 6 * (size_t)A->nel);
         if (rc) return rc;
@@ -502,9 +628,27 @@ extern "C" int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs) {
     }
     lp->nel = A->nel;
     lp->gs = gs;
+    lp->bound = true;
     geo_kernel<<<(unsigned)A->nel, 64, 0, ctx->stream>>>(lp->geo, lp->kappa, A->h1, A->g11, A->g22, A->g33,
                                                          A->g12, A->g13, A->g23, A->nel);
     SEM_LAUNCH_CHECK(ctx);
+    if (lp->jacobi_base) {
+        const int64_t n = A->nel * kOut;
+        if (lp->minv_n < n) {
+            void* p = nullptr;
+            rc = lp_alloc(lp, &p, 8 * (size_t)n);
+            if (rc) return rc;
+            lp->minv = (double*)p;
+            lp->minv_n = n;
+        }
+        rc = sem_ax_diag(ctx, lp->minv, A->dx, A->h1, A->g11, A->g22, A->g33, A->g12, A->g13, A->g23,
+                         A->nel, A->lx);
+        if (rc) return rc;
+        rc = sem_gs(gs, lp->minv, SEM_F64);
+        if (rc) return rc;
+        inv_kernel<<<grid_of(n), kBlock, 0, ctx->stream>>>(lp->minv, n);
+        SEM_LAUNCH_CHECK(ctx);
+    }
     return SEM_OK;
 }
 
@@ -514,11 +658,13 @@ extern "C" int sem_lp_samples(sem_lp_t lp, const double* r, const double* err, c
     sem_ctx_t ctx = lp->ctx;
     int rc = sem::enter(ctx);
     if (rc) return rc;
-    if (!lp->geo) return sem::fail(ctx, SEM_EINVAL, "sem_lp_samples: bind an operator first");
+    if (!lp->bound) return sem::fail(ctx, SEM_EINVAL, "sem_lp_samples: bind an operator first");
     if (!r || !X || !elems || count < 0 || row0 < 0 || (T && !err))
         return sem::fail(ctx, SEM_EINVAL, "sem_lp_samples: bad argument");
     if (count == 0) return SEM_OK;
-    features_kernel<double><<<(unsigned)count, 64, 0, ctx->stream>>>(X, nullptr, T, r, err, lp->geo, lp->kappa,
+    features_kernel<double><<<(unsigned)count, 64, 0, ctx->stream>>>(X, nullptr, T, r, err,
+                                                                      lp->jacobi_base ? lp->minv : nullptr,
+                                                                      lp->geo, lp->kappa,
                                                                       elems, count, row0, nullptr);
     SEM_LAUNCH_CHECK(ctx);
     return SEM_OK;
@@ -545,8 +691,17 @@ static int lp_backward(sem_lp_t lp, const uint16_t* Xb, const float* Tb, int B) 
     if (rc) return rc;
     const int64_t n3 = (int64_t)B * kOut;
     const unsigned g = grid_of(n3);
-    mse_grad<<<g, kBlock, 0, st>>>(lp->d3f, lp->d3b, lp->Y3, Tb, n3, 2.0f / (float)n3, lp->part);
-    loss_final<<<1, 64, 0, st>>>(lp->loss, lp->part, (int)g, 1.0 / (double)n3);
+    if (lp->K) {
+        // loss = mean_b d_b^T K d_b, gradient 2 K d / B
+        diff_kernel<<<g, kBlock, 0, st>>>(lp->dF, lp->dB, lp->Y3, Tb, n3);
+        rc = gemm(lp, B, kOut, kOut, lp->dB, kOut, lp->K, kOut, nullptr, nullptr, 0, lp->Kd, nullptr, kOut, 0);
+        if (rc) return rc;
+        metric_grad<<<g, kBlock, 0, st>>>(lp->d3f, lp->d3b, lp->dF, lp->Kd, n3, 2.0f / (float)B, lp->part);
+        loss_final<<<1, 64, 0, st>>>(lp->loss, lp->part, (int)g, 1.0 / (double)B);
+    } else {
+        mse_grad<<<g, kBlock, 0, st>>>(lp->d3f, lp->d3b, lp->Y3, Tb, n3, 2.0f / (float)n3, lp->part);
+        loss_final<<<1, 64, 0, st>>>(lp->loss, lp->part, (int)g, 1.0 / (double)n3);
+    }
     SEM_LAUNCH_CHECK(ctx);
     // layer 3: gW3 = d3^T Y2, gb3 = colsum d3, d2 = (d3 W3) * (Y2 > 0)
     rc = transpose(lp, lp->tA, B, lp->d3b, kOut, B, kOut);           // d3^T: 512 x B
@@ -657,19 +812,20 @@ int lp_apply_t(sem_lp_t lp, T* z, const T* r) {
     sem_ctx_t ctx = lp->ctx;
     hipStream_t st = ctx->stream;
     const int64_t nel = lp->nel;
-    features_kernel<T><<<(unsigned)nel, 64, 0, st>>>(lp->X, lp->scale, nullptr, r, nullptr, lp->geo,
-                                                     lp->kappa, nullptr, nel, 0, lp->skip);
+    features_kernel<T><<<(unsigned)nel, 64, 0, st>>>(lp->X, lp->scale, nullptr, r, nullptr, nullptr,
+                                                     lp->geo, lp->kappa, nullptr, nel, 0, lp->skip);
     SEM_LAUNCH_CHECK(ctx);
     int rc = forward(lp, lp->X, nel);
     if (rc) return rc;
     const int64_t n = nel * kOut;
-    lp_output_kernel<T><<<grid_of(n), kBlock, 0, st>>>(z, lp->Y3, lp->scale, lp->gs->mult, n, lp->skip);
+    lp_output_kernel<T><<<grid_of(n), kBlock, 0, st>>>(z, lp->Y3, lp->scale, lp->gs->mult,
+                                                       lp->jacobi_base ? lp->minv : nullptr, r, n, lp->skip);
     SEM_LAUNCH_CHECK(ctx);
     return gs_launch(lp->gs, z, sizeof(T) == 8 ? SEM_F64 : SEM_F32, lp->skip);
 }
 
 int lp_apply(sem_lp_t lp, void* z, const void* r, bool f64, const int* skip) {
-    if (!lp->geo || !lp->gs) return fail(lp->ctx, SEM_EINVAL, "learned preconditioner has no bound operator");
+    if (!lp->bound || !lp->gs) return fail(lp->ctx, SEM_EINVAL, "learned preconditioner has no bound operator");
     lp->skip = skip;
     const int rc = f64 ? lp_apply_t<double>(lp, (double*)z, (const double*)r)
                        : lp_apply_t<float>(lp, (float*)z, (const float*)r);

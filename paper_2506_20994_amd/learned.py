@@ -7,9 +7,11 @@ geometry, solves, operator, features, MLP, Adam); random draws come from
   * training boxes: n^3 periodic, lx = 8, deformation amplitude ~ U[0, 0.2],
     draws whose minimum det J falls below 5% of the undeformed value rejected
     (the map folds near 1 / (2 pi));
-  * right-hand side: 32 random Fourier modes per box;
+  * right-hand side: 32 random Fourier modes per box ("fourier"), or white
+    noise b_G ~ N(0, 1) per unique node, mean removed ("noise");
   * x* from float64 Jacobi-PCG to 1e-12; snapshots x_k at iterations k spread
-    log-uniformly over the solve, r_k = b - A x_k, e_k = x* - x_k;
+    log-uniformly over the solve (k = 0, i.e. r = b and e = x*, included when
+    `include_zero`), r_k = b - A x_k, e_k = x* - x_k;
   * per snapshot, `elems_per_snapshot` random elements become training rows.
 """
 import time
@@ -30,7 +32,8 @@ def _residual(op, x, b, out):
 
 
 def generate(ctx, lp, n=16, boxes=16, snapshots=16, elems_per_snapshot=64, seed=100,
-             amp_range=(0.0, 0.2), min_rel_detj=0.05, verbose=False):
+             amp_range=(0.0, 0.2), min_rel_detj=0.05, rhs="fourier", include_zero=False,
+             verbose=False):
     """Returns (X bf16 [rows, 528], T float32 [rows, 512], info)."""
     lx = 8
     nel = n ** 3
@@ -52,19 +55,28 @@ def generate(ctx, lp, n=16, boxes=16, snapshots=16, elems_per_snapshot=64, seed=
             rejected += 1
             continue
         amps.append(a)
-        k, am, ph = synth.fourier_modes(seed + 10_000 + box)
-        b = op.fourier_rhs(k, am, ph)
+        if rhs == "noise":
+            b = op.scatter(synth.unique_normal(op.n_unique, seed + 10_000 + box))
+            B.sem_remove_mean(op.gs, b)
+        else:
+            k, am, ph = synth.fourier_modes(seed + 10_000 + box)
+            b = op.fourier_rhs(k, am, ph)
         cg = op.solver(B.SEM_SOLVE_F64)
         xs = torch.empty_like(b)
         _, st = B.sem_cg_solve(cg, xs, b, tol=1e-12, maxit=100000)
         kmax = max(1, st["iterations"] - 1)
         its = synth.snapshot_iterations(seed + 20_000 + box, snapshots, kmax)
+        if include_zero:
+            its = np.concatenate([[0], its])
         its = np.resize(its, snapshots)       # duplicates if the draw collapsed
         op.bind(lp)
         xk = torch.empty_like(b)
         rk = torch.empty_like(b)
         for q, kq in enumerate(its):
-            B.sem_cg_solve(cg, xk, b, tol=1e-12, maxit=int(kq), check_every=int(min(kq, 16)))
+            if kq == 0:
+                xk.zero_()
+            else:
+                B.sem_cg_solve(cg, xk, b, tol=1e-12, maxit=int(kq), check_every=int(min(kq, 16)))
             _residual(op, xk, b, rk)
             err = xs - xk
             els = torch.from_numpy(synth.choice(seed + 30_000 + box * 1000 + q, nel,
@@ -101,6 +113,17 @@ def train(lp, X, T, epochs=4, batch=1024, lr=1e-3, seed=500, verbose=False):
     return hist
 
 
-def init_network(lp, seed=7):
+def init_network(lp, seed=7, mu=None, jacobi_base=None, out_scale=1.0):
+    """He-initialised weights (the last layer scaled by out_scale); mu >= 0
+    selects the energy-norm loss; jacobi_base selects z = Minv r + network."""
+    if mu is not None:
+        B.sem_lp_set_metric(lp, mu)
+    if jacobi_base is not None:
+        B.sem_lp_set_jacobi_base(lp, jacobi_base)
+    params = synth.mlp_init(seed)
+    params[4] = params[4] * out_scale
+    for s, p in enumerate(params):
+        B.sem_lp_set(lp, s, p.astype(np.float32))
+    return
     for s, p in enumerate(synth.mlp_init(seed)):
         B.sem_lp_set(lp, s, p.astype(np.float32))

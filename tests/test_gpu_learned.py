@@ -79,6 +79,25 @@ def test_gradients(sem_ctx):
     lp.close()
 
 
+def test_gradients_energy_metric(sem_ctx):
+    B = 128
+    params = _params(22)
+    lp = P.sem_lp_create(sem_ctx, B)
+    _load(lp, params)
+    P.sem_lp_set_metric(lp, 1.0)
+    Xq, Xd, T = _inputs(B, 23)
+    loss = P.sem_lp_gradients(lp, Xd, to_dev(T.astype(np.float32)))
+    K = mlp.reference_metric(8, 1.0)
+    l_ref, g_ref = mlp.backward(_qparams(params), Xq, T, K)
+    assert abs(loss - l_ref) <= GRAD_TOL * l_ref
+    for s in range(6):
+        assert _nrm(P.sem_lp_get(lp, 18 + s), g_ref[s]) <= GRAD_TOL, s
+    P.sem_lp_set_metric(lp, -1.0)        # back to the mean squared error
+    loss2 = P.sem_lp_gradients(lp, Xd, to_dev(T.astype(np.float32)))
+    assert abs(loss2 - mlp.loss(_qparams(params), Xq, T)) <= GRAD_TOL * loss2
+    lp.close()
+
+
 def test_adam_matches_oracle(sem_ctx):
     lp = P.sem_lp_create(sem_ctx, 8)
     params = _params(30)
