@@ -85,13 +85,15 @@ def solve_comparison(ctx, P, n, lx, amp, tol=1e-10):
     b = op.fourier_rhs(k, a, ph)
     x = torch.empty_like(b)
     res = {"workload": f"{n}^3 box lx={lx} amplitude {amp}, h1=1, 32 Fourier modes, tol {tol}"}
-    for name, code in (("fp64_pcg", P.SEM_SOLVE_F64), ("f32_ir", P.SEM_SOLVE_F32_IR),
-                       ("bf16_ir", P.SEM_SOLVE_BF16_IR)):
+    variants = (("fp64_pcg", P.SEM_SOLVE_F64, 0), ("f32_ir", P.SEM_SOLVE_F32_IR, 0),
+                ("bf16_ir", P.SEM_SOLVE_BF16_IR, 0), ("f32_rr", P.SEM_SOLVE_F32_IR, 1),
+                ("bf16_rr", P.SEM_SOLVE_BF16_IR, 1))
+    for name, code, mode in variants:
         cg = op.solver(code)
-        P.sem_cg_solve(cg, x, b, tol=tol, precision=code)          # warm-up
+        P.sem_cg_solve(cg, x, b, tol=tol, precision=code, ir_mode=mode)          # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rc, st = P.sem_cg_solve(cg, x, b, tol=tol, precision=code)
+        rc, st = P.sem_cg_solve(cg, x, b, tol=tol, precision=code, ir_mode=mode)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
         res[name] = {"ms": round(ms, 2), "iterations": st["iterations"], "outer": st["outer"],
@@ -100,7 +102,8 @@ def solve_comparison(ctx, P, n, lx, amp, tol=1e-10):
               f"relres {st['relres']:.2e}", file=sys.stderr, flush=True)
         cg.close()
     base = res["fp64_pcg"]["ms"]
-    res["speedup_vs_fp64_pcg"] = {k2: round(base / res[k2]["ms"], 3) for k2 in ("f32_ir", "bf16_ir")}
+    res["speedup_vs_fp64_pcg"] = {k2: round(base / res[k2]["ms"], 3)
+                                  for k2, _, _ in variants[1:]}
     return res
 
 

@@ -209,6 +209,14 @@ typedef struct {
     sem_lp_t learned;    /* NULL: Jacobi-PCG.  Otherwise flexible CG (Notay's FCG(1))
                             preconditioned by this network, bound to the same operator
                             (sem_lp_bind), with the Jacobi fallback described below */
+    int ir_mode;         /* IR modes: 0 restarted refinement (each outer step runs a fresh
+                            inner PCG on r / ||r||), 1 residual replacement ("reliable
+                            updates"): one reduced-precision Krylov iteration whose
+                            residual is replaced by the float64 b - A x, and whose
+                            accumulated update is added to the float64 x, each time its
+                            residual has fallen by the factor `delta`; the search
+                            direction is kept */
+    double delta;        /* ir_mode 1: replacement trigger (0: 0.1) */
 } sem_solve_opts_t;
 
 typedef struct {

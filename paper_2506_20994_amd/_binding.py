@@ -36,7 +36,7 @@ class SemSolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("learned", ctypes.c_void_p)]
+                ("learned", ctypes.c_void_p), ("ir_mode", ctypes.c_int), ("delta", ctypes.c_double)]
 
 
 class SemSolveStats(ctypes.Structure):
@@ -349,9 +349,9 @@ class CgSolver:
 
 
 def _opts(tol=1e-10, maxit=0, precision=SEM_SOLVE_F64, inner_tol=0.0, inner_maxit=0,
-          max_outer=0, check_every=0, learned=None):
+          max_outer=0, check_every=0, learned=None, ir_mode=0, delta=0.0):
     return SemSolveOpts(tol, maxit, precision, inner_tol, inner_maxit, max_outer, check_every,
-                        learned.handle if learned is not None else None)
+                        learned.handle if learned is not None else None, ir_mode, delta)
 
 
 def sem_cg_setup(ctx, gs, D, h1, G, nel, lx, **opts):

@@ -62,7 +62,10 @@ __device__ __forceinline__ void wave_sync() {
 // (a converged solve), and each workgroup writes sum_L u_L w_L over its
 // elements, accumulated in float64, to dot[blockIdx.x] (p^T A p before
 // gather-scatter).
-template <int LX, int EPB, typename TU, typename TS, typename TC, typename TW, bool FUSE>
+// GATHER: u is a unique-node vector, read as u[lid[L]] (lid streamed, u
+// through the caches, since neighbouring elements share nodes), and the
+// output of node L goes to w[pos[L]], the plan's CSR order.
+template <int LX, int EPB, typename TU, typename TS, typename TC, typename TW, bool FUSE, bool GATHER>
 __global__ void __launch_bounds__(EPB * LX * LX)
 ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
           const TC* __restrict__ dx, const TC* __restrict__ dy, const TC* __restrict__ dz,
@@ -70,7 +73,8 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
           const TS* __restrict__ h1, const TS* __restrict__ g11, const TS* __restrict__ g22,
           const TS* __restrict__ g33, const TS* __restrict__ g12, const TS* __restrict__ g13,
           const TS* __restrict__ g23, int64_t nel, const int* __restrict__ skip,
-          double* __restrict__ dot) {
+          double* __restrict__ dot, const int32_t* __restrict__ lid,
+          const int32_t* __restrict__ pos) {
     constexpr int L2 = LX * LX;
     constexpr int L3 = L2 * LX;
     constexpr bool WP = Shape<LX>::kWavePrivate;
@@ -106,7 +110,12 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
     // the thread's column of u, kept in registers for the t-derivative
     TC uc[LX];
 #pragma unroll
-    for (int k = 0; k < LX; ++k) uc[k] = live ? (TC)Load<TU>::get(u, base + k * L2) : TC(0);
+    for (int k = 0; k < LX; ++k) {
+        if constexpr (GATHER)
+            uc[k] = live ? (TC)u[__builtin_nontemporal_load(lid + base + k * L2)] : TC(0);
+        else
+            uc[k] = live ? (TC)Load<TU>::get(u, base + k * L2) : TC(0);
+    }
 #pragma unroll
     for (int k = 0; k < LX; ++k) su[k * L2 + ij] = uc[k];
     __syncthreads();   // s_d is shared by every wave of the workgroup
@@ -164,7 +173,10 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
             acc += di[l] * sr[k * L2 + j * LX + l];
             acc += dj[l] * ss[k * L2 + l * LX + i];
         }
-        if (live) store_nt(w, base + k * L2, (TW)acc);
+        if (live) {
+            if constexpr (GATHER) w[__builtin_nontemporal_load(pos + base + k * L2)] = (TW)acc;
+            else store_nt(w, base + k * L2, (TW)acc);
+        }
         if (FUSE) pw += (double)uc[k] * (double)(TW)acc;
     }
     if (FUSE) {
@@ -195,18 +207,24 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
 
 template <int LX, typename TU, typename TS, typename TC, typename TW>
 int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const void* h1,
-              const void* const* G, int64_t nel, const int* skip, double* dot) {
+              const void* const* G, int64_t nel, const int* skip, double* dot, const int32_t* lid,
+              const int32_t* pos) {
     constexpr int EPB = Shape<LX>::EPB;
     const int64_t blocks = (nel + EPB - 1) / EPB;
     if (blocks > 0x7fffffff) return sem::fail(ctx, SEM_EINVAL, "sem_ax: nel too large");
 #define SEM_AX_ARGS (TW*)w, (const TU*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2], \
         (const TC*)D[3], (const TC*)D[4], (const TC*)D[5], (const TS*)h1, (const TS*)G[0],  \
         (const TS*)G[1], (const TS*)G[2], (const TS*)G[3], (const TS*)G[4], (const TS*)G[5], \
-        nel, skip, dot
-    if (dot)
-        ax_kernel<LX, EPB, TU, TS, TC, TW, true><<<(unsigned)blocks, EPB * LX * LX, 0, ctx->stream>>>(SEM_AX_ARGS);
+        nel, skip, dot, lid, pos
+    const dim3 grid((unsigned)blocks), block(EPB * LX * LX);
+    if (dot && lid)
+        ax_kernel<LX, EPB, TU, TS, TC, TW, true, true><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
+    else if (dot)
+        ax_kernel<LX, EPB, TU, TS, TC, TW, true, false><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
+    else if (lid)
+        ax_kernel<LX, EPB, TU, TS, TC, TW, false, true><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
     else
-        ax_kernel<LX, EPB, TU, TS, TC, TW, false><<<(unsigned)blocks, EPB * LX * LX, 0, ctx->stream>>>(SEM_AX_ARGS);
+        ax_kernel<LX, EPB, TU, TS, TC, TW, false, false><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
 #undef SEM_AX_ARGS
     SEM_LAUNCH_CHECK(ctx);
     return SEM_OK;
@@ -214,9 +232,10 @@ int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const
 
 template <typename TU, typename TS, typename TC, typename TW>
 int dispatch(sem_ctx_t ctx, int lx, void* w, const void* u, const void* const* D,
-             const void* h1, const void* const* G, int64_t nel, const int* skip, double* dot) {
+             const void* h1, const void* const* G, int64_t nel, const int* skip, double* dot,
+             const int32_t* lid = nullptr, const int32_t* pos = nullptr) {
     switch (lx) {
-#define SEM_AX_CASE(L) case L: return launch_lx<L, TU, TS, TC, TW>(ctx, w, u, D, h1, G, nel, skip, dot);
+#define SEM_AX_CASE(L) case L: return launch_lx<L, TU, TS, TC, TW>(ctx, w, u, D, h1, G, nel, skip, dot, lid, pos);
         SEM_AX_CASE(2) SEM_AX_CASE(3) SEM_AX_CASE(4) SEM_AX_CASE(5) SEM_AX_CASE(6) SEM_AX_CASE(7)
         SEM_AX_CASE(8) SEM_AX_CASE(9) SEM_AX_CASE(10) SEM_AX_CASE(11) SEM_AX_CASE(12)
 #undef SEM_AX_CASE
@@ -282,16 +301,17 @@ int ax_blocks(int lx, int64_t nel) {
 }
 
 int launch_ax(sem_ctx_t ctx, AxKind kind, const AxArgs& a, void* w, const void* u,
-              const int* skip, double* dot) {
+              const int* skip, double* dot, const int32_t* lid, const int32_t* pos) {
+    if ((lid == nullptr) != (pos == nullptr)) return fail(ctx, SEM_EINVAL, "launch_ax: lid and pos go together");
     const void* D[6] = {a.D[0], a.D[1], a.D[2], a.D[3], a.D[4], a.D[5]};
     const void* G[6] = {a.G[0], a.G[1], a.G[2], a.G[3], a.G[4], a.G[5]};
     switch (kind) {
         case AxKind::F64:
-            return dispatch<double, double, double, double>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot);
+            return dispatch<double, double, double, double>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos);
         case AxKind::F32:
-            return dispatch<float, float, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot);
+            return dispatch<float, float, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos);
         case AxKind::F32_BF16:
-            return dispatch<float, uint16_t, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot);
+            return dispatch<float, uint16_t, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos);
     }
     return fail(ctx, SEM_EINVAL, "launch_ax: bad kind");
 }

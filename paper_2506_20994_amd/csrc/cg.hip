@@ -7,13 +7,18 @@
 //    float32 or the bfloat16-factor form of the element operator; dot products
 //    are always accumulated in float64.
 //
-// Everything stays on the device: scalars (alpha, beta, r.z, ...) live in a
-// small device struct, a `done` flag turns every later kernel of a converged
-// solve into an early return, and the host reads the flag once every
-// `check_every` iterations.  Dots of continuous fields count one owner copy of
-// each global node (a bit mask), so they equal the dots of the unique vectors.
-// Reductions are two-stage with a fixed number of partials and a fixed
-// summation order: results are bitwise reproducible.
+// Krylov vectors live on the unique (assembled) nodes, numbered densely by
+// the gather-scatter plan: the operator reads p[lid[L]] for every local node L
+// and writes its element-local output w_L; the update kernel assembles
+// w_u = sum of the local copies of u (the plan's CSR) on the fly, so no
+// separate gather-scatter pass and no duplicated vector traffic remain.
+// p^T A p is the element-local sum of p_L w_L taken in the operator's
+// epilogue.  Everything stays on the device: scalars (alpha, beta, r.z, ...)
+// live in a small device struct, a `done` flag turns every later kernel of a
+// converged solve into an early return, and the host reads the flag once
+// every `check_every` iterations.  Reductions are two-stage with a fixed
+// number of partials and a fixed summation order: results are bitwise
+// reproducible.
 #include <cmath>
 #include <vector>
 
@@ -22,20 +27,18 @@
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kGrid = 1024;           // vector kernels: fixed grid -> fixed partial count
+constexpr int kGrid = 8192;           // vector kernels: fixed grid -> fixed partial count
 constexpr int kFinal = 1024;          // threads of the single-block finalisers
 
 struct Scal {
     double rz, pAp, alpha, beta, rr, bb, tol2, mean, pw_prev;
     int done, it, breakdown, maxit;
     int usej, njac, fallback;   // flexible CG: Jacobi this iteration, count, for good
+    double delta2, rmax2;       // residual replacement: pause when rr < delta2 * rmax2
+    int pause;
 };
 
-__device__ __forceinline__ bool owner_bit(const uint32_t* __restrict__ m, int64_t L) {
-    return (m[L >> 5] >> (L & 31)) & 1u;
-}
-
-// sum of a per-thread double over a 256-thread block, written by thread 0
+// sum of a per-thread double over a 256-thread block, valid in thread 0
 __device__ __forceinline__ double block_sum(double v, double* s_red) {
     v = sem::wave_sum(v);
     if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
@@ -60,45 +63,62 @@ __device__ double final_sum(const double* __restrict__ part, int n, int stride, 
     return t;
 }
 
-__global__ void owner_bits_kernel(uint32_t* __restrict__ bits, const double* __restrict__ owner,
-                                  int64_t n) {
-    const int64_t wd = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t nw = (n + 31) >> 5;
-    if (wd >= nw) return;
-    uint32_t b = 0;
-    for (int q = 0; q < 32; ++q) {
-        const int64_t L = (wd << 5) + q;
-        if (L < n && owner[L] != 0.0) b |= 1u << q;
-    }
-    bits[wd] = b;
-}
+#define GRID_LOOP(i, n) \
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
+// assembled value of unique node u: sum of its local copies, which the
+// operator stored contiguously at wc[uoff[u] .. uoff[u+1]) (CSR order)
 template <typename T>
-__global__ void recip_kernel(T* __restrict__ out, const double* __restrict__ d, int64_t n) {
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x)
-        out[L] = (T)(1.0 / d[L]);
+__device__ __forceinline__ T assemble(const T* __restrict__ wc, const int32_t* __restrict__ uoff,
+                                      int64_t u) {
+    const int32_t b = uoff[u], e = uoff[u + 1];
+    T s = wc[b];
+    for (int32_t q = b + 1; q < e; ++q) s += wc[q];
+    return s;
 }
 
-// r = rhs, x = 0, p = Minv r; partials (r.Minv.r, r.r) over owners
+// out_u = (T) in_L at the first local copy of u (a continuous local field)
+template <typename T>
+__global__ void to_unique_kernel(T* __restrict__ out, const double* __restrict__ in,
+                                 const int32_t* __restrict__ uoff, const int32_t* __restrict__ uidx,
+                                 int64_t nu) {
+    GRID_LOOP(u, nu) out[u] = (T)in[uidx[uoff[u]]];
+}
+
+// out_L = in_u[lid[L]]
+__global__ void to_local_kernel(double* __restrict__ out, const double* __restrict__ in,
+                                const int32_t* __restrict__ lid, int64_t n) {
+    GRID_LOOP(L, n) out[L] = in[lid[L]];
+}
+
+// out_u = 1 / (sum of the copies of the element diagonal d_L)
+template <typename T>
+__global__ void assembled_recip_kernel(T* __restrict__ out, const double* __restrict__ d,
+                                       const int32_t* __restrict__ uoff,
+                                       const int32_t* __restrict__ uidx, int64_t nu) {
+    GRID_LOOP(u, nu) {
+        const int32_t b = uoff[u], e = uoff[u + 1];
+        double s = 0.0;
+        for (int32_t q = b; q < e; ++q) s += d[uidx[q]];
+        out[u] = (T)(1.0 / s);
+    }
+}
+
+// r = rhs, x = 0, p = Minv r; partials (r.Minv.r, r.r)
 template <typename T>
 __global__ void pcg_init_kernel(T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
-                                const T* __restrict__ rhs, const T* __restrict__ minv,
-                                const uint32_t* __restrict__ own, int64_t n,
+                                const T* __restrict__ rhs, const T* __restrict__ minv, int64_t n,
                                 double* __restrict__ part) {
     __shared__ double s_red[kBlock / 64];
     double a = 0.0, b = 0.0;
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x) {
-        const T rv = rhs[L];
-        const T z = minv[L] * rv;
-        x[L] = T(0);
-        r[L] = rv;
-        p[L] = z;
-        if (owner_bit(own, L)) {
-            a += (double)rv * (double)z;
-            b += (double)rv * (double)rv;
-        }
+    GRID_LOOP(u, n) {
+        const T rv = rhs[u];
+        const T z = minv[u] * rv;
+        x[u] = T(0);
+        r[u] = rv;
+        p[u] = z;
+        a += (double)rv * (double)z;
+        b += (double)rv * (double)rv;
     }
     a = block_sum(a, s_red);
     b = block_sum(b, s_red);
@@ -122,6 +142,10 @@ __global__ void pcg_init_final(Scal* __restrict__ S, const double* __restrict__ 
         S->maxit = maxit;
         S->njac = 0;
         S->usej = 0;
+        S->fallback = 0;
+        S->delta2 = 0.0;
+        S->rmax2 = bb;
+        S->pause = 0;
         S->done = (bb == 0.0 || maxit <= 0) ? 1 : 0;
     }
 }
@@ -141,25 +165,23 @@ __global__ void pcg_alpha_final(Scal* __restrict__ S, const double* __restrict__
     }
 }
 
-// x += alpha p, r -= alpha w; partials (r.Minv.r, r.r) over owners
+// w_u = assembled w_L; x += alpha p, r -= alpha w; partials (r.Minv.r, r.r)
 template <typename T>
 __global__ void pcg_update_kernel(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-                                  const T* __restrict__ w, const T* __restrict__ minv,
-                                  const uint32_t* __restrict__ own, int64_t n,
-                                  const Scal* __restrict__ S, double* __restrict__ part) {
+                                  const T* __restrict__ wl, const T* __restrict__ minv,
+                                  const int32_t* __restrict__ uoff, const int32_t* __restrict__ uidx,
+                                  int64_t n, const Scal* __restrict__ S, double* __restrict__ part) {
     if (S->done) return;
     __shared__ double s_red[kBlock / 64];
     const T alpha = (T)S->alpha;
     double a = 0.0, b = 0.0;
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x) {
-        x[L] += alpha * p[L];
-        const T rv = r[L] - alpha * w[L];
-        r[L] = rv;
-        if (owner_bit(own, L)) {
-            a += (double)rv * (double)(minv[L] * rv);
-            b += (double)rv * (double)rv;
-        }
+    GRID_LOOP(u, n) {
+        const T wv = assemble(wl, uoff, u);
+        x[u] += alpha * p[u];
+        const T rv = r[u] - alpha * wv;
+        r[u] = rv;
+        a += (double)rv * (double)(minv[u] * rv);
+        b += (double)rv * (double)rv;
     }
     a = block_sum(a, s_red);
     b = block_sum(b, s_red);
@@ -182,6 +204,9 @@ __global__ void pcg_beta_final(Scal* __restrict__ S, const double* __restrict__ 
         if (!isfinite(rr) || !isfinite(rz)) {
             S->breakdown = 1;
             S->done = 1;
+        } else if (S->delta2 > 0.0 && (rr <= S->tol2 || rr < S->delta2 * S->rmax2)) {
+            S->pause = 1;            // residual replacement due (or convergence to verify)
+            S->done = 1;
         } else if (rr <= S->tol2 || S->it >= S->maxit) {
             S->done = 1;
         }
@@ -194,24 +219,18 @@ __global__ void pcg_p_kernel(T* __restrict__ p, const T* __restrict__ r, const T
                              int64_t n, const Scal* __restrict__ S) {
     if (S->done) return;
     const T beta = (T)S->beta;
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x)
-        p[L] = minv[L] * r[L] + beta * p[L];
+    GRID_LOOP(u, n) p[u] = minv[u] * r[u] + beta * p[u];
 }
 
-// partials of (sum_own a, sum_own a*a) for a float64 or float32 vector
+// partials of (sum a, sum a*a)
 template <typename T>
-__global__ void owner_sums_kernel(const T* __restrict__ a, const uint32_t* __restrict__ own,
-                                  int64_t n, double* __restrict__ part) {
+__global__ void sums_kernel(const T* __restrict__ a, int64_t n, double* __restrict__ part) {
     __shared__ double s_red[kBlock / 64];
     double s = 0.0, q = 0.0;
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x) {
-        if (owner_bit(own, L)) {
-            const double v = (double)a[L];
-            s += v;
-            q += v * v;
-        }
+    GRID_LOOP(u, n) {
+        const double v = (double)a[u];
+        s += v;
+        q += v * v;
     }
     s = block_sum(s, s_red);
     q = block_sum(q, s_red);
@@ -231,53 +250,44 @@ __global__ void sums_final(double* __restrict__ out, const double* __restrict__ 
     }
 }
 
-// x -= c, with c = sums[0] / n_unique (the mean over unique nodes)
-__global__ void sub_mean_kernel(double* __restrict__ x, const double* __restrict__ sums,
-                                double n_unique, int64_t n) {
-    const double c = sums[0] / n_unique;
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x)
-        x[L] -= c;
+// x -= sums[0] / count
+__global__ void sub_mean_kernel(double* __restrict__ x, const double* __restrict__ sums, double count,
+                                int64_t n) {
+    const double c = sums[0] / count;
+    GRID_LOOP(u, n) x[u] -= c;
 }
 
-// r = b - w (float64)
+// r_u = b_u - assembled w_L
 __global__ void residual_kernel(double* __restrict__ r, const double* __restrict__ b,
-                                const double* __restrict__ w, int64_t n) {
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x)
-        r[L] = b[L] - w[L];
+                                const double* __restrict__ wl, const int32_t* __restrict__ uoff,
+                                const int32_t* __restrict__ uidx, int64_t nu) {
+    GRID_LOOP(u, nu) r[u] = b[u] - assemble(wl, uoff, u);
 }
 
-// IR: rhat = (float)((r - mean) / norm) with mean = s0/nu, norm = sqrt(q - nu mean^2)
+// IR: rhat = (float)((r - mean) / norm), mean = s0 / nu, norm^2 = q - nu mean^2
 __global__ void ir_scale_kernel(float* __restrict__ rhat, const double* __restrict__ r,
-                                const double* __restrict__ sums, double n_unique, int64_t n) {
-    const double c = sums[0] / n_unique;
-    const double nrm2 = sums[1] - n_unique * c * c;
+                                const double* __restrict__ sums, double nu, int64_t n) {
+    const double c = sums[0] / nu;
+    const double nrm2 = sums[1] - nu * c * c;
     const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x)
-        rhat[L] = (float)((r[L] - c) * inv);
+    GRID_LOOP(u, n) rhat[u] = (float)((r[u] - c) * inv);
 }
 
 // IR: x += norm * d (float64 update)
 __global__ void ir_update_kernel(double* __restrict__ x, const float* __restrict__ d,
-                                 const double* __restrict__ sums, double n_unique, int64_t n) {
-    const double c = sums[0] / n_unique;
-    const double nrm2 = sums[1] - n_unique * c * c;
+                                 const double* __restrict__ sums, double nu, int64_t n) {
+    const double c = sums[0] / nu;
+    const double nrm2 = sums[1] - nu * c * c;
     const double nrm = nrm2 > 0.0 ? sqrt(nrm2) : 0.0;
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x)
-        x[L] += nrm * (double)d[L];
+    GRID_LOOP(u, n) x[u] += nrm * (double)d[u];
 }
 
-// partials of sum_L owner_L x_L (float64 owner weights)
+// partials of sum_L owner_L x_L (float64 owner weights), for sem_remove_mean
 __global__ void wsum_kernel(const double* __restrict__ x, const double* __restrict__ owner,
                             int64_t n, double* __restrict__ part) {
     __shared__ double s_red[kBlock / 64];
     double s = 0.0;
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x)
-        s += owner[L] * x[L];
+    GRID_LOOP(L, n) s += owner[L] * x[L];
     s = block_sum(s, s_red);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
@@ -289,16 +299,12 @@ __global__ void wsum_final(double* __restrict__ out, const double* __restrict__ 
 }
 
 __global__ void zero_kernel(double* __restrict__ x, int64_t n) {
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x)
-        x[L] = 0.0;
+    GRID_LOOP(u, n) x[u] = 0.0;
 }
 
 template <typename T>
 __global__ void to_type_kernel(T* __restrict__ out, const double* __restrict__ in, int64_t n) {
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x)
-        out[L] = (T)in[L];
+    GRID_LOOP(L, n) out[L] = (T)in[L];
 }
 
 __device__ inline uint16_t bf16_rne(float f) {
@@ -309,35 +315,28 @@ __device__ inline uint16_t bf16_rne(float f) {
 }
 
 __global__ void to_bf16_kernel(uint16_t* __restrict__ out, const double* __restrict__ in, int64_t n) {
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x)
-        out[L] = bf16_rne((float)in[L]);
+    GRID_LOOP(L, n) out[L] = bf16_rne((float)in[L]);
 }
 
-
 // ---- flexible CG (Notay's FCG(1)) with a variable preconditioner ----------
-// partials over owners: r.z, non-finite count of z, z.w_prev, (Minv r).w_prev
+// partials: r.z, non-finite count of z, z.w_prev, (Minv r).w_prev
 template <typename T>
 __global__ void fcg_dots_kernel(const T* __restrict__ r, const T* __restrict__ z,
-                                const T* __restrict__ wprev, const T* __restrict__ minv,
-                                const uint32_t* __restrict__ own, int64_t n,
+                                const T* __restrict__ wprev, const T* __restrict__ minv, int64_t n,
                                 const Scal* __restrict__ S, double* __restrict__ part) {
     if (S->done) return;
     __shared__ double s_red[kBlock / 64];
     const bool first = S->it == 0;
     double rz = 0.0, bad = 0.0, zw = 0.0, jw = 0.0;
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x) {
-        const double zv = (double)z[L];
+    GRID_LOOP(u, n) {
+        const double zv = (double)z[u];
+        const double rv = (double)r[u];
         if (!isfinite(zv)) bad += 1.0;
-        if (owner_bit(own, L)) {
-            const double rv = (double)r[L];
-            rz += rv * zv;
-            if (!first) {
-                const double wv = (double)wprev[L];
-                zw += zv * wv;
-                jw += (double)(minv[L] * r[L]) * wv;
-            }
+        rz += rv * zv;
+        if (!first) {
+            const double wv = (double)wprev[u];
+            zw += zv * wv;
+            jw += (double)(minv[u] * r[u]) * wv;
         }
     }
     rz = block_sum(rz, s_red);
@@ -367,25 +366,23 @@ __global__ void fcg_gamma_final(Scal* __restrict__ S, const double* __restrict__
     }
 }
 
-// p = z_eff - gamma p (z_eff = Minv r when the network output is rejected);
-// partials over owners of p.r
+// p = z_eff - gamma p (z_eff = Minv r when the network output is rejected); partials p.r
 template <typename T>
 __global__ void fcg_p_kernel(T* __restrict__ p, const T* __restrict__ z, const T* __restrict__ r,
-                             const T* __restrict__ minv, const uint32_t* __restrict__ own, int64_t n,
-                             const Scal* __restrict__ S, double* __restrict__ part) {
+                             const T* __restrict__ minv, int64_t n, const Scal* __restrict__ S,
+                             double* __restrict__ part) {
     if (S->done) return;
     __shared__ double s_red[kBlock / 64];
     const bool usej = S->usej != 0;
     const bool first = S->it == 0;
     const T gamma = (T)S->beta;
     double pr = 0.0;
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x) {
-        const T rv = r[L];
-        const T ze = usej ? minv[L] * rv : z[L];
-        const T pv = first ? ze : ze - gamma * p[L];
-        p[L] = pv;
-        if (owner_bit(own, L)) pr += (double)pv * (double)rv;
+    GRID_LOOP(u, n) {
+        const T rv = r[u];
+        const T ze = usej ? minv[u] * rv : z[u];
+        const T pv = first ? ze : ze - gamma * p[u];
+        p[u] = pv;
+        pr += (double)pv * (double)rv;
     }
     pr = block_sum(pr, s_red);
     if (threadIdx.x == 0) part[blockIdx.x] = pr;
@@ -410,39 +407,115 @@ __global__ void fcg_alpha_final(Scal* __restrict__ S, const double* __restrict__
     }
 }
 
+// FCG keeps the assembled w of the previous iteration: w_u = assembled w_L,
+// then x += alpha p, r -= alpha w_u; partials (r.Minv.r, r.r)
+template <typename T>
+__global__ void fcg_update_kernel(T* __restrict__ x, T* __restrict__ r, T* __restrict__ wu,
+                                  const T* __restrict__ p, const T* __restrict__ wl,
+                                  const T* __restrict__ minv, const int32_t* __restrict__ uoff,
+                                  const int32_t* __restrict__ uidx, int64_t n,
+                                  const Scal* __restrict__ S, double* __restrict__ part) {
+    if (S->done) return;
+    __shared__ double s_red[kBlock / 64];
+    const T alpha = (T)S->alpha;
+    double a = 0.0, b = 0.0;
+    GRID_LOOP(u, n) {
+        const T wv = assemble(wl, uoff, u);
+        wu[u] = wv;
+        x[u] += alpha * p[u];
+        const T rv = r[u] - alpha * wv;
+        r[u] = rv;
+        a += (double)rv * (double)(minv[u] * rv);
+        b += (double)rv * (double)rv;
+    }
+    a = block_sum(a, s_red);
+    b = block_sum(b, s_red);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+// residual replacement: x64 += xl, xl = 0 (float64 accumulation of the
+// low-precision update)
+__global__ void rr_accumulate_kernel(double* __restrict__ x64, float* __restrict__ xl, int64_t n) {
+    GRID_LOOP(u, n) {
+        x64[u] += (double)xl[u];
+        xl[u] = 0.f;
+    }
+}
+
+// r = (float) r64; partials (r.Minv.r, r.r) in float64 from the float values
+__global__ void rr_replace_kernel(float* __restrict__ r, const double* __restrict__ r64,
+                                  const float* __restrict__ minv, int64_t n, double* __restrict__ part) {
+    __shared__ double s_red[kBlock / 64];
+    double a = 0.0, b = 0.0;
+    GRID_LOOP(u, n) {
+        const float rv = (float)r64[u];
+        r[u] = rv;
+        a += (double)rv * (double)(minv[u] * rv);
+        b += (double)rv * (double)rv;
+    }
+    a = block_sum(a, s_red);
+    b = block_sum(b, s_red);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+// resume after a replacement: rz from the new residual, rmax = its norm
+__global__ void rr_resume_final(Scal* __restrict__ S, const double* __restrict__ part, int n) {
+    __shared__ double s_red[kFinal / 64];
+    const double rz = final_sum(part, n, 2, s_red);
+    const double rr = final_sum(part + 1, n, 2, s_red);
+    if (threadIdx.x == 0) {
+        S->rz = rz;
+        S->rr = rr;
+        S->rmax2 = rr;
+        S->pause = 0;
+        S->done = (S->it >= S->maxit) ? 1 : 0;
+    }
+}
+
+__global__ void set_delta(Scal* __restrict__ S, double delta2) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) S->delta2 = delta2;
+}
+
 __global__ void set_fallback(Scal* __restrict__ S) {
     if (threadIdx.x == 0 && blockIdx.x == 0) S->fallback = 1;
 }
 
 }  // namespace
 
-// One precision level of the solver: vectors of type T and the operator form
-// that acts on them.
+// One precision level of the solver: unique-node vectors of type T (x, r, p,
+// Minv, and for flexible CG z and the assembled w), the element-local operator
+// output wl (n_local), and the operator form that acts on them.
 struct Level {
     sem::AxKind kind;
     sem::AxArgs A;
-    void *x = nullptr, *r = nullptr, *p = nullptr, *w = nullptr, *minv = nullptr;
-    void* z = nullptr;   // flexible CG: the preconditioner's output
+    void *x = nullptr, *r = nullptr, *p = nullptr, *wl = nullptr, *minv = nullptr;
+    void *z = nullptr, *wu = nullptr;
 };
 
 struct sem_cg_s {
     sem_ctx_t ctx = nullptr;
     sem_gs_t gs = nullptr;
     int precision = SEM_SOLVE_F64;
-    int64_t n = 0;
-    double n_unique = 0;
+    int64_t n = 0;                 // local nodes
+    int64_t nu = 0;                // unique nodes
     sem::AxArgs A64{};
-    uint32_t* own = nullptr;
     Scal* S = nullptr;
     double* part = nullptr;        // max(4*kGrid, ax_blocks) doubles
     double* part2 = nullptr;       // kGrid doubles (flexible CG: p.r partials)
-    sem_lp_t lp = nullptr;
     double* sums = nullptr;        // 2 doubles
     Scal* S_host = nullptr;        // pinned
     double* sums_host = nullptr;   // pinned
     Level lv64{}, lv32{};
-    double *r64 = nullptr, *w64 = nullptr;
-    float* rhs32 = nullptr;        // IR: normalised inner right-hand side
+    double *b64 = nullptr, *x64 = nullptr, *r64 = nullptr;   // unique float64
+    double* wl64 = nullptr;                                    // local float64
+    float* rhs32 = nullptr;        // IR: normalised inner right-hand side (unique)
+    sem_lp_t lp = nullptr;
     std::vector<void*> allocs;
 };
 
@@ -460,40 +533,110 @@ unsigned vec_grid(int64_t n) {
     return (unsigned)(b < kGrid ? (b < 1 ? 1 : b) : kGrid);
 }
 
-// PCG on level lv from x = 0 with right-hand side rhs (type T, continuous);
-// leaves the iterate in lv.x.  Returns SEM_OK and fills S_host on exit.
+// PCG on level lv from x = 0 with right-hand side rhs (unique, type T);
+// leaves the iterate in lv.x.
 template <typename T>
 int pcg_run(sem_cg_t cg, Level& lv, const T* rhs, double tol, int maxit, int check_every,
             int* iters_out, int* breakdown_out) {
     sem_ctx_t ctx = cg->ctx;
     hipStream_t st = ctx->stream;
-    const int64_t n = cg->n;
+    const int64_t n = cg->nu;
     const unsigned g = vec_grid(n);
-    T* x = (T*)lv.x; T* r = (T*)lv.r; T* p = (T*)lv.p; T* w = (T*)lv.w;
+    T* x = (T*)lv.x; T* r = (T*)lv.r; T* p = (T*)lv.p; T* wl = (T*)lv.wl;
     const T* minv = (const T*)lv.minv;
-    pcg_init_kernel<T><<<g, kBlock, 0, st>>>(x, r, p, rhs, minv, cg->own, n, cg->part);
+    const int32_t *lid = cg->gs->lid, *uoff = cg->gs->uoff, *uidx = cg->gs->uidx;
+    pcg_init_kernel<T><<<g, kBlock, 0, st>>>(x, r, p, rhs, minv, n, cg->part);
     pcg_init_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g, tol, maxit);
     SEM_LAUNCH_CHECK(ctx);
     const int nb = sem::ax_blocks(lv.A.lx, lv.A.nel);
-    int done_it = 0;
     for (;;) {
         for (int q = 0; q < check_every; ++q) {
-            int rc = sem::launch_ax(ctx, lv.kind, lv.A, w, p, &cg->S->done, cg->part);
-            if (rc) return rc;
-            rc = sem_gs(cg->gs, w, sizeof(T) == 8 ? SEM_F64 : SEM_F32);
+            int rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid, cg->gs->upos);
             if (rc) return rc;
             pcg_alpha_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, nb);
-            pcg_update_kernel<T><<<g, kBlock, 0, st>>>(x, r, p, w, minv, cg->own, n, cg->S, cg->part);
+            pcg_update_kernel<T><<<g, kBlock, 0, st>>>(x, r, p, wl, minv, uoff, uidx, n, cg->S, cg->part);
             pcg_beta_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
             pcg_p_kernel<T><<<g, kBlock, 0, st>>>(p, r, minv, n, cg->S);
         }
         SEM_LAUNCH_CHECK(ctx);
         SEM_HIP(ctx, hipMemcpyAsync(cg->S_host, cg->S, sizeof(Scal), hipMemcpyDeviceToHost, st));
         SEM_HIP(ctx, hipStreamSynchronize(st));
-        done_it = cg->S_host->it;
         if (cg->S_host->done) break;
     }
-    *iters_out = done_it;
+    *iters_out = cg->S_host->it;
+    *breakdown_out = cg->S_host->breakdown;
+    return SEM_OK;
+}
+
+int residual64(sem_cg_t cg, const double* xu);
+template <typename T> int vec_sums(sem_cg_t cg, const T* a);
+int read_sums(sem_cg_t cg, double* s, double* q);
+
+// Mixed-precision CG with residual replacement (reliable updates; Strzodka
+// and Goeddeke 2006, Clark et al. 2010): float32 vectors and the reduced
+// operator drive the Krylov iteration; whenever the float32 residual has
+// fallen by `delta` since the last replacement, the accumulated update is
+// added to the float64 x, the residual is replaced by the float64 b - A x, and
+// the iteration continues with the same search direction.  Converged when
+// the replaced float64 residual meets tol.
+int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int check_every,
+           double bnorm, int* iters_out, int* replacements, int* breakdown_out, double* hist, int nhist) {
+    sem_ctx_t ctx = cg->ctx;
+    hipStream_t st = ctx->stream;
+    const int64_t n = cg->nu;
+    const unsigned g = vec_grid(n);
+    float* x = (float*)lv.x; float* r = (float*)lv.r; float* p = (float*)lv.p; float* wl = (float*)lv.wl;
+    const float* minv = (const float*)lv.minv;
+    const int32_t *lid = cg->gs->lid, *uoff = cg->gs->uoff, *uidx = cg->gs->uidx;
+    // x64 = 0, r64 = b; inner start: x = 0, r = (float) b, p = Minv r
+    zero_kernel<<<g, kBlock, 0, st>>>(cg->x64, n);
+    rr_replace_kernel<<<g, kBlock, 0, st>>>(cg->rhs32, cg->b64, minv, n, cg->part);
+    pcg_init_kernel<float><<<g, kBlock, 0, st>>>(x, r, p, cg->rhs32, minv, n, cg->part);
+    pcg_init_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g, tol, maxit);
+    set_delta<<<1, 1, 0, st>>>(cg->S, delta * delta);
+    SEM_LAUNCH_CHECK(ctx);
+    const int nb = sem::ax_blocks(lv.A.lx, lv.A.nel);
+    int nrep = 0;
+    for (;;) {
+        for (int q = 0; q < check_every; ++q) {
+            int rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid, cg->gs->upos);
+            if (rc) return rc;
+            pcg_alpha_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, nb);
+            pcg_update_kernel<float><<<g, kBlock, 0, st>>>(x, r, p, wl, minv, uoff, uidx, n, cg->S, cg->part);
+            pcg_beta_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
+            pcg_p_kernel<float><<<g, kBlock, 0, st>>>(p, r, minv, n, cg->S);
+        }
+        SEM_LAUNCH_CHECK(ctx);
+        SEM_HIP(ctx, hipMemcpyAsync(cg->S_host, cg->S, sizeof(Scal), hipMemcpyDeviceToHost, st));
+        SEM_HIP(ctx, hipStreamSynchronize(st));
+        const Scal& H = *cg->S_host;
+        if (!H.done) continue;
+        if (H.breakdown) break;
+        // replacement: fold the update into x64, recompute the float64 residual
+        rr_accumulate_kernel<<<g, kBlock, 0, st>>>(cg->x64, x, n);
+        SEM_LAUNCH_CHECK(ctx);
+        int rc = residual64(cg, cg->x64);
+        if (rc) return rc;
+        rc = vec_sums(cg, cg->r64);
+        if (rc) return rc;
+        double s0, q0;
+        rc = read_sums(cg, &s0, &q0);
+        if (rc) return rc;
+        const double rel = bnorm > 0 ? std::sqrt(q0) / bnorm : 0.0;
+        if (nrep < nhist) hist[nrep] = rel;
+        ++nrep;
+        if (rel <= tol || H.it >= maxit) break;
+        // the float64 residual carries the (tiny) mean that rounding left; drop it
+        sub_mean_kernel<<<g, kBlock, 0, st>>>(cg->r64, cg->sums, (double)n, n);
+        rr_replace_kernel<<<g, kBlock, 0, st>>>(r, cg->r64, minv, n, cg->part);
+        rr_resume_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
+        // the paused iteration skipped its direction update: p = Minv r + beta p
+        // with the replaced residual and the beta of that iteration
+        pcg_p_kernel<float><<<g, kBlock, 0, st>>>(p, r, minv, n, cg->S);
+        SEM_LAUNCH_CHECK(ctx);
+    }
+    *iters_out = cg->S_host->it;
+    *replacements = nrep;
     *breakdown_out = cg->S_host->breakdown;
     return SEM_OK;
 }
@@ -504,36 +647,31 @@ int fcg_run(sem_cg_t cg, Level& lv, const T* rhs, double tol, int maxit, int che
             int* iters_out, int* breakdown_out, int* njac_out, int* fell_back) {
     sem_ctx_t ctx = cg->ctx;
     hipStream_t st = ctx->stream;
-    const int64_t n = cg->n;
+    const int64_t n = cg->nu;
     const unsigned g = vec_grid(n);
-    T* x = (T*)lv.x; T* r = (T*)lv.r; T* p = (T*)lv.p; T* w = (T*)lv.w; T* z = (T*)lv.z;
+    T* x = (T*)lv.x; T* r = (T*)lv.r; T* p = (T*)lv.p; T* wl = (T*)lv.wl; T* z = (T*)lv.z;
+    T* wu = (T*)lv.wu;
     const T* minv = (const T*)lv.minv;
-    pcg_init_kernel<T><<<g, kBlock, 0, st>>>(x, r, p, rhs, minv, cg->own, n, cg->part);
+    const int32_t *lid = cg->gs->lid, *uoff = cg->gs->uoff, *uidx = cg->gs->uidx;
+    pcg_init_kernel<T><<<g, kBlock, 0, st>>>(x, r, p, rhs, minv, n, cg->part);
     pcg_init_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g, tol, maxit);
     SEM_LAUNCH_CHECK(ctx);
     const int nb = sem::ax_blocks(lv.A.lx, lv.A.nel);
     const bool f64 = sizeof(T) == 8;
     bool fallen = false;
-    // the fallback flag starts cleared for every solve
-    SEM_HIP(ctx, hipMemcpyAsync(cg->S_host, cg->S, sizeof(Scal), hipMemcpyDeviceToHost, st));
-    SEM_HIP(ctx, hipStreamSynchronize(st));
-    cg->S_host->fallback = 0;
-    SEM_HIP(ctx, hipMemcpyAsync(cg->S, cg->S_host, sizeof(Scal), hipMemcpyHostToDevice, st));
-    std::vector<std::pair<int, double>> hist;   // (iteration, rr) at each check
+    std::vector<std::pair<int, double>> hist;   // (iteration, r.r) at each check
     for (;;) {
         for (int q = 0; q < check_every; ++q) {
             int rc = SEM_OK;
-            if (!fallen) rc = sem::lp_apply(cg->lp, z, r, f64, &cg->S->done);
+            if (!fallen) rc = sem::lp_apply(cg->lp, z, r, f64, &cg->S->done, true);
             if (rc) return rc;
-            fcg_dots_kernel<T><<<g, kBlock, 0, st>>>(r, z, w, minv, cg->own, n, cg->S, cg->part);
+            fcg_dots_kernel<T><<<g, kBlock, 0, st>>>(r, z, wu, minv, n, cg->S, cg->part);
             fcg_gamma_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
-            fcg_p_kernel<T><<<g, kBlock, 0, st>>>(p, z, r, minv, cg->own, n, cg->S, cg->part2);
-            rc = sem::launch_ax(ctx, lv.kind, lv.A, w, p, &cg->S->done, cg->part);
-            if (rc) return rc;
-            rc = sem::gs_launch(cg->gs, w, f64 ? SEM_F64 : SEM_F32, &cg->S->done);
+            fcg_p_kernel<T><<<g, kBlock, 0, st>>>(p, z, r, minv, n, cg->S, cg->part2);
+            rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid, cg->gs->upos);
             if (rc) return rc;
             fcg_alpha_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, nb, cg->part2, (int)g);
-            pcg_update_kernel<T><<<g, kBlock, 0, st>>>(x, r, p, w, minv, cg->own, n, cg->S, cg->part);
+            fcg_update_kernel<T><<<g, kBlock, 0, st>>>(x, r, wu, p, wl, minv, uoff, uidx, n, cg->S, cg->part);
             pcg_beta_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
         }
         SEM_LAUNCH_CHECK(ctx);
@@ -562,11 +700,11 @@ int fcg_run(sem_cg_t cg, Level& lv, const T* rhs, double tol, int maxit, int che
     return SEM_OK;
 }
 
-// sums over owners of (a, a*a) into cg->sums (device) -- asynchronous
+// sums of (a, a*a) over the unique vector a into cg->sums (device)
 template <typename T>
-int owner_sums(sem_cg_t cg, const T* a) {
-    const unsigned g = vec_grid(cg->n);
-    owner_sums_kernel<T><<<g, kBlock, 0, cg->ctx->stream>>>(a, cg->own, cg->n, cg->part);
+int vec_sums(sem_cg_t cg, const T* a) {
+    const unsigned g = vec_grid(cg->nu);
+    sums_kernel<T><<<g, kBlock, 0, cg->ctx->stream>>>(a, cg->nu, cg->part);
     sums_final<<<1, kFinal, 0, cg->ctx->stream>>>(cg->sums, cg->part, (int)g);
     SEM_LAUNCH_CHECK(cg->ctx);
     return SEM_OK;
@@ -581,26 +719,21 @@ int read_sums(sem_cg_t cg, double* s, double* q) {
     return SEM_OK;
 }
 
-// relres of x against b in float64: w = A x, r = b - w
-int true_relres(sem_cg_t cg, const double* x, const double* b, double bnorm, double* relres) {
-    int rc = sem::launch_ax(cg->ctx, sem::AxKind::F64, cg->A64, cg->w64, x, nullptr, nullptr);
+// r64 = b64 - A x (unique, float64)
+int residual64(sem_cg_t cg, const double* xu) {
+    int rc = sem::launch_ax(cg->ctx, sem::AxKind::F64, cg->A64, cg->wl64, xu, nullptr, nullptr, cg->gs->lid,
+                            cg->gs->upos);
     if (rc) return rc;
-    rc = sem_gs(cg->gs, cg->w64, SEM_F64);
-    if (rc) return rc;
-    residual_kernel<<<vec_grid(cg->n), kBlock, 0, cg->ctx->stream>>>(cg->r64, b, cg->w64, cg->n);
-    rc = owner_sums(cg, cg->r64);
-    if (rc) return rc;
-    double s, q;
-    rc = read_sums(cg, &s, &q);
-    if (rc) return rc;
-    *relres = bnorm > 0 ? std::sqrt(q) / bnorm : 0.0;
+    residual_kernel<<<vec_grid(cg->nu), kBlock, 0, cg->ctx->stream>>>(cg->r64, cg->b64, cg->wl64,
+                                                                      cg->gs->uoff, cg->gs->uidx, cg->nu);
+    SEM_LAUNCH_CHECK(cg->ctx);
     return SEM_OK;
 }
 
-int remove_mean(sem_cg_t cg, double* x) {
-    int rc = owner_sums(cg, x);
+int remove_mean_u(sem_cg_t cg, double* xu) {
+    int rc = vec_sums(cg, xu);
     if (rc) return rc;
-    sub_mean_kernel<<<vec_grid(cg->n), kBlock, 0, cg->ctx->stream>>>(x, cg->sums, cg->n_unique, cg->n);
+    sub_mean_kernel<<<vec_grid(cg->nu), kBlock, 0, cg->ctx->stream>>>(xu, cg->sums, (double)cg->nu, cg->nu);
     SEM_LAUNCH_CHECK(cg->ctx);
     return SEM_OK;
 }
@@ -631,61 +764,60 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
     cg->gs = gs;
     cg->precision = opts->precision;
     cg->n = n;
-    cg->n_unique = (double)gs->n_unique;
+    cg->nu = gs->n_unique;
     for (int q = 0; q < 6; ++q) { cg->A64.D[q] = Dp[q]; cg->A64.G[q] = Gp[q]; }
     cg->A64.h1 = A->h1;
     cg->A64.nel = A->nel;
     cg->A64.lx = A->lx;
     hipStream_t st = ctx->stream;
-    const unsigned g = vec_grid(n);
+    const int64_t nu = cg->nu;
+    const unsigned gl = vec_grid(n), gu = vec_grid(nu);
     const int nb = sem::ax_blocks(A->lx, A->nel);
     const size_t npart = (size_t)std::max(4 * kGrid, nb);
-    const int64_t nw = (n + 31) / 32;
-    const size_t v64 = sizeof(double) * n, v32 = sizeof(float) * n;
+    const size_t u64 = sizeof(double) * nu, u32 = sizeof(float) * nu;
     auto bail = [&](int code) { sem_cg_destroy(cg); return code; };
 #define CG_ALLOC(ptr, bytes) do { int rc_ = cg_alloc(cg, (void**)&(ptr), (bytes)); if (rc_) return bail(rc_); } while (0)
-    CG_ALLOC(cg->own, sizeof(uint32_t) * nw);
     CG_ALLOC(cg->S, sizeof(Scal));
     CG_ALLOC(cg->part, sizeof(double) * npart);
-    CG_ALLOC(cg->sums, sizeof(double) * 2);
     CG_ALLOC(cg->part2, sizeof(double) * kGrid);
-    if (opts->learned) {
-        if (sem::lp_rows(opts->learned) != A->nel || sem::lp_plan(opts->learned) != gs)
-            return bail(sem::fail(ctx, SEM_EINVAL, "sem_cg_setup: the network is not bound to this operator and plan"));
-        cg->lp = opts->learned;
-    }
-    CG_ALLOC(cg->r64, v64);
-    CG_ALLOC(cg->w64, v64);
+    CG_ALLOC(cg->sums, sizeof(double) * 2);
+    CG_ALLOC(cg->b64, u64);
+    CG_ALLOC(cg->x64, u64);
+    CG_ALLOC(cg->r64, u64);
+    CG_ALLOC(cg->wl64, sizeof(double) * n);
     {
         hipError_t e = hipHostMalloc(&cg->S_host, sizeof(Scal), hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc(&cg->sums_host, 2 * sizeof(double), hipHostMallocDefault);
         if (e != hipSuccess) return bail(sem::check_hip(ctx, e, "sem_cg_setup: hipHostMalloc"));
     }
-    owner_bits_kernel<<<(unsigned)((nw + kBlock - 1) / kBlock), kBlock, 0, st>>>(cg->own, gs->owner, n);
-    // assembled Jacobi diagonal (float64) in r64
-    rc = sem_ax_diag(ctx, cg->r64, A->dx, A->h1, A->g11, A->g22, A->g33, A->g12, A->g13, A->g23,
+    if (opts->learned) {
+        if (sem::lp_rows(opts->learned) != A->nel || sem::lp_plan(opts->learned) != gs)
+            return bail(sem::fail(ctx, SEM_EINVAL, "sem_cg_setup: the network is not bound to this operator and plan"));
+        cg->lp = opts->learned;
+    }
+    // element diagonal (local, float64) in wl64; assembled and inverted per level below
+    rc = sem_ax_diag(ctx, cg->wl64, A->dx, A->h1, A->g11, A->g22, A->g33, A->g12, A->g13, A->g23,
                      A->nel, A->lx);
-    if (rc) return bail(rc);
-    rc = sem_gs(gs, cg->r64, SEM_F64);
     if (rc) return bail(rc);
 
     Level& L64 = cg->lv64;
     L64.kind = sem::AxKind::F64;
     L64.A = cg->A64;
     if (opts->precision == SEM_SOLVE_F64) {
-        CG_ALLOC(L64.x, v64); CG_ALLOC(L64.r, v64); CG_ALLOC(L64.p, v64); CG_ALLOC(L64.minv, v64);
-        if (cg->lp) CG_ALLOC(L64.z, v64);
-        L64.w = cg->w64;
-        recip_kernel<double><<<g, kBlock, 0, st>>>((double*)L64.minv, cg->r64, n);
+        CG_ALLOC(L64.r, u64); CG_ALLOC(L64.p, u64); CG_ALLOC(L64.minv, u64);
+        L64.x = cg->x64;
+        L64.wl = cg->wl64;
+        if (cg->lp) { CG_ALLOC(L64.z, u64); CG_ALLOC(L64.wu, u64); }
+        assembled_recip_kernel<double><<<gu, kBlock, 0, st>>>((double*)L64.minv, cg->wl64, gs->uoff, gs->uidx, nu);
     } else {
         Level& L = cg->lv32;
         const bool bf = opts->precision == SEM_SOLVE_BF16_IR;
         L.kind = bf ? sem::AxKind::F32_BF16 : sem::AxKind::F32;
-        CG_ALLOC(L.x, v32); CG_ALLOC(L.r, v32); CG_ALLOC(L.p, v32); CG_ALLOC(L.w, v32); CG_ALLOC(L.minv, v32);
-        CG_ALLOC(cg->rhs32, v32);
-        if (cg->lp) CG_ALLOC(L.z, v32);
-        recip_kernel<float><<<g, kBlock, 0, st>>>((float*)L.minv, cg->r64, n);
-        // derivative matrices in float32
+        CG_ALLOC(L.x, u32); CG_ALLOC(L.r, u32); CG_ALLOC(L.p, u32); CG_ALLOC(L.minv, u32);
+        CG_ALLOC(L.wl, sizeof(float) * n);
+        CG_ALLOC(cg->rhs32, u32);
+        if (cg->lp) { CG_ALLOC(L.z, u32); CG_ALLOC(L.wu, u32); }
+        assembled_recip_kernel<float><<<gu, kBlock, 0, st>>>((float*)L.minv, cg->wl64, gs->uoff, gs->uidx, nu);
         const int l2 = A->lx * A->lx;
         for (int q = 0; q < 6; ++q) {
             void* d = nullptr;
@@ -693,14 +825,15 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
             to_type_kernel<float><<<1, kBlock, 0, st>>>((float*)d, Dp[q], l2);
             L.A.D[q] = d;
         }
-        const size_t vs = bf ? sizeof(uint16_t) * n : v32;
+        const size_t vs = bf ? sizeof(uint16_t) * n : sizeof(float) * n;
         const double* src[7] = {Gp[0], Gp[1], Gp[2], Gp[3], Gp[4], Gp[5], A->h1};
+        L.A.h1 = nullptr;
         for (int q = 0; q < 7; ++q) {
-            if (!src[q]) { L.A.h1 = nullptr; continue; }
+            if (!src[q]) continue;
             void* d = nullptr;
             CG_ALLOC(d, vs);
-            if (bf) to_bf16_kernel<<<g, kBlock, 0, st>>>((uint16_t*)d, src[q], n);
-            else to_type_kernel<float><<<g, kBlock, 0, st>>>((float*)d, src[q], n);
+            if (bf) to_bf16_kernel<<<gl, kBlock, 0, st>>>((uint16_t*)d, src[q], n);
+            else to_type_kernel<float><<<gl, kBlock, 0, st>>>((float*)d, src[q], n);
             if (q < 6) L.A.G[q] = d; else L.A.h1 = d;
         }
         L.A.nel = A->nel;
@@ -738,14 +871,22 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
                          opts->precision, cg->precision);
     if (opts->learned != cg->lp)
         return sem::fail(ctx, SEM_EINVAL, "sem_cg_solve: preconditioner differs from set-up");
+    if (opts->ir_mode != 0 && opts->ir_mode != 1)
+        return sem::fail(ctx, SEM_EINVAL, "sem_cg_solve: bad ir_mode %d", opts->ir_mode);
+    if (opts->ir_mode == 1 && cg->lp)
+        return sem::fail(ctx, SEM_EINVAL, "sem_cg_solve: residual replacement is not combined with the learned preconditioner");
     if (!(opts->tol > 0.0)) return sem::fail(ctx, SEM_EINVAL, "sem_cg_solve: tol must be > 0");
     *stats = sem_solve_stats_t{};
     const int check = opts->check_every > 0 ? opts->check_every : 16;
     const int maxit = opts->maxit > 0 ? opts->maxit : 100000;
     hipStream_t st = ctx->stream;
-    const int64_t n = cg->n;
+    const int64_t nu = cg->nu;
+    const unsigned gu = vec_grid(nu);
+    const int32_t *uoff = cg->gs->uoff, *uidx = cg->gs->uidx;
 
-    rc = owner_sums(cg, b);
+    to_unique_kernel<double><<<gu, kBlock, 0, st>>>(cg->b64, b, uoff, uidx, nu);
+    SEM_LAUNCH_CHECK(ctx);
+    rc = vec_sums(cg, cg->b64);
     if (rc) return rc;
     double bs, bq;
     rc = read_sums(cg, &bs, &bq);
@@ -755,39 +896,46 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
     if (cg->precision == SEM_SOLVE_F64) {
         Level& L = cg->lv64;
         int its = 0, brk = 0, nj = 0, fb = 0;
-        if (cg->lp) rc = fcg_run<double>(cg, L, b, opts->tol, maxit, check, &its, &brk, &nj, &fb);
-        else rc = pcg_run<double>(cg, L, b, opts->tol, maxit, check, &its, &brk);
+        if (cg->lp) rc = fcg_run<double>(cg, L, cg->b64, opts->tol, maxit, check, &its, &brk, &nj, &fb);
+        else rc = pcg_run<double>(cg, L, cg->b64, opts->tol, maxit, check, &its, &brk);
         if (rc) return rc;
         stats->jacobi_steps = nj;
         stats->fell_back = fb;
-        SEM_HIP(ctx, hipMemcpyAsync(x, L.x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-        rc = remove_mean(cg, x);
-        if (rc) return rc;
         stats->iterations = its;
         stats->breakdown = brk;
     } else {
         Level& L = cg->lv32;
         const bool bf = cg->precision == SEM_SOLVE_BF16_IR;
+        if (opts->ir_mode == 1 && !cg->lp) {
+            int its = 0, nrep = 0, brk = 0;
+            rc = rr_run(cg, L, opts->tol, opts->delta > 0 ? opts->delta : 0.1, maxit, check, bnorm, &its,
+                        &nrep, &brk, stats->relres_hist, 64);
+            if (rc) return rc;
+            stats->iterations = its + nrep;
+            stats->outer = nrep;
+            stats->breakdown = brk;
+            goto finish;
+        }
+        {
         const double itol = opts->inner_tol > 0 ? opts->inner_tol : (bf ? 1e-2 : 1e-6);
         const int imax = opts->inner_maxit > 0 ? opts->inner_maxit : 500;
         const int omax = std::min(opts->max_outer > 0 ? opts->max_outer : 60, 64);
-        zero_kernel<<<vec_grid(n), kBlock, 0, st>>>(x, n);
-        SEM_HIP(ctx, hipMemcpyAsync(cg->r64, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        zero_kernel<<<gu, kBlock, 0, st>>>(cg->x64, nu);
+        SEM_HIP(ctx, hipMemcpyAsync(cg->r64, cg->b64, sizeof(double) * nu, hipMemcpyDeviceToDevice, st));
         int total = 0;
         for (int outer = 0; outer < omax; ++outer) {
             // r64 holds b - A x; project out its mean and normalise into the inner rhs
-            rc = owner_sums(cg, cg->r64);
+            rc = vec_sums(cg, cg->r64);
             if (rc) return rc;
             double s, q;
             rc = read_sums(cg, &s, &q);
             if (rc) return rc;
-            const double c = s / cg->n_unique;
-            const double rn = std::sqrt(std::max(q - cg->n_unique * c * c, 0.0));
+            const double c = s / (double)nu;
+            const double rn = std::sqrt(std::max(q - (double)nu * c * c, 0.0));
             const double rel = bnorm > 0 ? rn / bnorm : 0.0;
             if (outer > 0) stats->relres_hist[outer - 1] = rel;
             if (rel <= opts->tol || total >= maxit) break;
-            ir_scale_kernel<<<vec_grid(n), kBlock, 0, st>>>(cg->rhs32, cg->r64, cg->sums,
-                                                             cg->n_unique, n);
+            ir_scale_kernel<<<gu, kBlock, 0, st>>>(cg->rhs32, cg->r64, cg->sums, (double)nu, nu);
             int its = 0, brk = 0, nj = 0, fb = 0;
             if (cg->lp)
                 rc = fcg_run<float>(cg, L, cg->rhs32, itol, std::min(imax, maxit - total), check,
@@ -801,26 +949,32 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
             total += its;
             stats->outer = outer + 1;
             if (brk) stats->breakdown = 1;
-            ir_update_kernel<<<vec_grid(n), kBlock, 0, st>>>(x, (const float*)L.x, cg->sums,
-                                                              cg->n_unique, n);
-            rc = remove_mean(cg, x);
+            ir_update_kernel<<<gu, kBlock, 0, st>>>(cg->x64, (const float*)L.x, cg->sums, (double)nu, nu);
+            rc = remove_mean_u(cg, cg->x64);
             if (rc) return rc;
-            // float64 residual r64 = b - A x
-            rc = sem::launch_ax(ctx, sem::AxKind::F64, cg->A64, cg->w64, x, nullptr, nullptr);
+            rc = residual64(cg, cg->x64);
             if (rc) return rc;
-            rc = sem_gs(cg->gs, cg->w64, SEM_F64);
-            if (rc) return rc;
-            residual_kernel<<<vec_grid(n), kBlock, 0, st>>>(cg->r64, b, cg->w64, n);
-            SEM_LAUNCH_CHECK(ctx);
             total += 1;
         }
         stats->iterations = total;
+        }
     }
-    double rel = 0.0;
-    rc = true_relres(cg, x, b, bnorm, &rel);
+finish:
+    // x: mean-free, back to the local layout; final float64 residual
+    rc = remove_mean_u(cg, cg->x64);
     if (rc) return rc;
-    stats->relres = rel;
-    stats->converged = rel <= opts->tol;
+    rc = residual64(cg, cg->x64);
+    if (rc) return rc;
+    rc = vec_sums(cg, cg->r64);
+    if (rc) return rc;
+    double rs, rq;
+    rc = read_sums(cg, &rs, &rq);
+    if (rc) return rc;
+    to_local_kernel<<<vec_grid(cg->n), kBlock, 0, st>>>(x, cg->x64, cg->gs->lid, cg->n);
+    SEM_LAUNCH_CHECK(ctx);
+    SEM_HIP(ctx, hipStreamSynchronize(st));
+    stats->relres = bnorm > 0 ? std::sqrt(rq) / bnorm : 0.0;
+    stats->converged = stats->relres <= opts->tol;
     if (stats->breakdown && !stats->converged) return sem::fail(ctx, SEM_EBREAKDOWN, "sem_cg_solve: breakdown");
     if (!stats->converged) return SEM_NOT_CONVERGED;
     return stats->fell_back ? SEM_FELL_BACK : SEM_OK;

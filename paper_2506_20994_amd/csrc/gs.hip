@@ -99,6 +99,31 @@ extern "C" int sem_gs_setup(sem_ctx_t ctx, const int64_t* ids, int64_t n_local, 
         const int32_t s = slot[(size_t)key[L]];
         if (s >= 0) idx[(size_t)fillpos[(size_t)s]++] = (int32_t)L;
     }
+    std::vector<int32_t>().swap(fillpos);
+    // dense unique numbering in order of first appearance and the CSR of the
+    // local copies of every unique node (reuses `slot` as id -> unique index)
+    std::fill(slot.begin(), slot.end(), -1);
+    std::vector<int32_t> lid((size_t)n_local);
+    std::vector<int32_t> uoff(1, 0);
+    uoff.reserve((size_t)n_unique + 1);
+    int32_t nu = 0;
+    for (int64_t L = 0; L < n_local; ++L) {
+        const int64_t g = key[L];
+        if (slot[(size_t)g] < 0) {
+            slot[(size_t)g] = nu++;
+            uoff.push_back(uoff.back() + count[(size_t)g]);
+        }
+        lid[(size_t)L] = slot[(size_t)g];
+    }
+    std::vector<int32_t> uidx((size_t)n_local), upos((size_t)n_local);
+    {
+        std::vector<int32_t> pos(uoff.begin(), uoff.end() - 1);
+        for (int64_t L = 0; L < n_local; ++L) {
+            const int32_t q = pos[(size_t)lid[(size_t)L]]++;
+            uidx[(size_t)q] = (int32_t)L;
+            upos[(size_t)L] = q;
+        }
+    }
     std::vector<int32_t>().swap(count);
     std::vector<int32_t>().swap(slot);
 
@@ -112,6 +137,17 @@ extern "C" int sem_gs_setup(sem_ctx_t ctx, const int64_t* ids, int64_t n_local, 
     if (e == hipSuccess && !idx.empty()) e = hipMalloc(&gs->idx, sizeof(int32_t) * idx.size());
     if (e == hipSuccess && n_local > 0) e = hipMalloc(&gs->mult, sizeof(double) * n_local);
     if (e == hipSuccess && n_local > 0) e = hipMalloc(&gs->owner, sizeof(double) * n_local);
+    if (e == hipSuccess && n_local > 0) e = hipMalloc(&gs->lid, sizeof(int32_t) * n_local);
+    if (e == hipSuccess && n_local > 0) e = hipMalloc(&gs->uidx, sizeof(int32_t) * n_local);
+    if (e == hipSuccess && n_local > 0) e = hipMalloc(&gs->upos, sizeof(int32_t) * n_local);
+    if (e == hipSuccess && n_local > 0)
+        e = hipMemcpy(gs->upos, upos.data(), sizeof(int32_t) * n_local, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&gs->uoff, sizeof(int32_t) * uoff.size());
+    if (e == hipSuccess && n_local > 0)
+        e = hipMemcpy(gs->lid, lid.data(), sizeof(int32_t) * n_local, hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_local > 0)
+        e = hipMemcpy(gs->uidx, uidx.data(), sizeof(int32_t) * n_local, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(gs->uoff, uoff.data(), sizeof(int32_t) * uoff.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(gs->off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !idx.empty())
         e = hipMemcpy(gs->idx, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice);
@@ -142,6 +178,10 @@ extern "C" int sem_gs_destroy(sem_gs_t gs) {
     if (gs->idx) (void)hipFree(gs->idx);
     if (gs->mult) (void)hipFree(gs->mult);
     if (gs->owner) (void)hipFree(gs->owner);
+    if (gs->lid) (void)hipFree(gs->lid);
+    if (gs->uoff) (void)hipFree(gs->uoff);
+    if (gs->uidx) (void)hipFree(gs->uidx);
+    if (gs->upos) (void)hipFree(gs->upos);
     delete gs;
     return SEM_OK;
 }

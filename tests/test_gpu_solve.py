@@ -55,14 +55,16 @@ def test_pcg_f64(sem_ctx, n, lx, amp, h1):
     cg.close()
 
 
+@pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_refinement(sem_ctx, prec):
+def test_refinement(sem_ctx, prec, mode):
+    """mode 0: restarted refinement; mode 1: residual replacement."""
     n, lx, amp = 3, 8, 0.1
     op, b, ref, bref = _setup(sem_ctx, n, lx, amp)
     code = P.SEM_SOLVE_F32_IR if prec == "f32" else P.SEM_SOLVE_BF16_IR
     cg = op.solver(code)
     x = torch.empty_like(b)
-    rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10, precision=code)
+    rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10, precision=code, ir_mode=mode)
     torch.cuda.synchronize()
     assert rc == P.SEM_OK and st["converged"], st
     assert st["outer"] >= 2
@@ -71,8 +73,8 @@ def test_refinement(sem_ctx, prec):
     assert rel <= 1.2e-10
     xs, _, _ = pcg(ref.apply, bref, 1.0 / ref.diagonal(), tol=1e-13)
     err = np.max(np.abs(xg - xs)) / np.max(np.abs(xs))
-    print(f"{prec} IR: outer={st['outer']} iters={st['iterations']} relres={st['relres']:.2e} "
-          f"err={err:.2e}")
+    print(f"{prec} IR mode {mode}: outer={st['outer']} iters={st['iterations']} "
+          f"relres={st['relres']:.2e} err={err:.2e}")
     assert err <= 1e-6
     cg.close()
 
