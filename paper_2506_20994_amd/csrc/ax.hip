@@ -38,12 +38,40 @@ template <> struct Load<uint16_t> {
 template <typename T>
 __device__ __forceinline__ void store_nt(T* p, int64_t o, T v) { __builtin_nontemporal_store(v, p + o); }
 
-// Elements whose lx*lx columns fit inside one 64-lane wave (lx = 2, 4, 8) are
-// "wave-private": no other wave touches their LDS, so the forward and
-// transposed phases need no workgroup barrier, and slice k of u can be
-// overwritten by the r-flux of slice k as soon as the wave has read it (LDS
-// operations of one wave complete in order).  Other lx use workgroup
-// barriers and a separate r-flux buffer.
+// Solver copies of the six factors, slice-blocked in pairs: for the slice
+// (e, k) the pairs (g11, g22), (g33, g12), (g13, g23) of all lx*lx columns are
+// stored as three consecutive runs of lx*lx two-element vectors, so each wave
+// load is one contiguous block (1 KiB in float64 at lx = 8).
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+template <typename TS> struct Packed;
+template <> struct Packed<double> {
+    __device__ static void get(const double* gp, int64_t slice, int ij, int l2, double* g) {
+        const dvec2* q = reinterpret_cast<const dvec2*>(gp) + slice * 3 + ij;
+        const dvec2 a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + l2),
+                    c = __builtin_nontemporal_load(q + 2 * l2);
+        g[0] = a.x; g[1] = a.y; g[2] = b.x; g[3] = b.y; g[4] = c.x; g[5] = c.y;
+    }
+};
+template <> struct Packed<float> {
+    __device__ static void get(const float* gp, int64_t slice, int ij, int l2, float* g) {
+        const fvec2* q = reinterpret_cast<const fvec2*>(gp) + slice * 3 + ij;
+        const fvec2 a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + l2),
+                    c = __builtin_nontemporal_load(q + 2 * l2);
+        g[0] = a.x; g[1] = a.y; g[2] = b.x; g[3] = b.y; g[4] = c.x; g[5] = c.y;
+    }
+};
+template <> struct Packed<uint16_t> {
+    __device__ static void get(const uint16_t* gp, int64_t slice, int ij, int l2, float* g) {
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(gp) + slice * 3 + ij;
+        const uint32_t a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + l2),
+                       c = __builtin_nontemporal_load(q + 2 * l2);
+        g[0] = __uint_as_float(a << 16); g[1] = __uint_as_float(a & 0xffff0000u);
+        g[2] = __uint_as_float(b << 16); g[3] = __uint_as_float(b & 0xffff0000u);
+        g[4] = __uint_as_float(c << 16); g[5] = __uint_as_float(c & 0xffff0000u);
+    }
+};
+
 template <int LX> struct Shape {
     static constexpr bool kWavePrivate = (64 % (LX * LX)) == 0;
     // elements per workgroup: about four waves, LDS of float64 within ~64 KiB
@@ -74,7 +102,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
           const TS* __restrict__ g33, const TS* __restrict__ g12, const TS* __restrict__ g13,
           const TS* __restrict__ g23, int64_t nel, const int* __restrict__ skip,
           double* __restrict__ dot, const int32_t* __restrict__ lid,
-          const int32_t* __restrict__ pos) {
+          const int32_t* __restrict__ pos, const TS* __restrict__ gp) {
     constexpr int L2 = LX * LX;
     constexpr int L3 = L2 * LX;
     constexpr bool WP = Shape<LX>::kWavePrivate;
@@ -144,8 +172,14 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
         const int64_t o = base + k * L2;
         TC G11 = 0, G22 = 0, G33 = 0, G12 = 0, G13 = 0, G23 = 0, H = 1;
         if (live) {
-            G11 = Load<TS>::get(g11, o); G22 = Load<TS>::get(g22, o); G33 = Load<TS>::get(g33, o);
-            G12 = Load<TS>::get(g12, o); G13 = Load<TS>::get(g13, o); G23 = Load<TS>::get(g23, o);
+            if constexpr (GATHER) {            // the solver form reads the packed factors
+                TC g[6];
+                Packed<TS>::get(gp, o - ij, ij, L2, g);   // o - ij = e lx^3 + k lx^2
+                G11 = g[0]; G22 = g[1]; G33 = g[2]; G12 = g[3]; G13 = g[4]; G23 = g[5];
+            } else {
+                G11 = Load<TS>::get(g11, o); G22 = Load<TS>::get(g22, o); G33 = Load<TS>::get(g33, o);
+                G12 = Load<TS>::get(g12, o); G13 = Load<TS>::get(g13, o); G23 = Load<TS>::get(g23, o);
+            }
             if (h1) H = Load<TS>::get(h1, o);
         }
         const TC vr = H * (G11 * r + G12 * s + G13 * t);
@@ -208,23 +242,24 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
 template <int LX, typename TU, typename TS, typename TC, typename TW>
 int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const void* h1,
               const void* const* G, int64_t nel, const int* skip, double* dot, const int32_t* lid,
-              const int32_t* pos) {
+              const int32_t* pos, const void* gp) {
     constexpr int EPB = Shape<LX>::EPB;
     const int64_t blocks = (nel + EPB - 1) / EPB;
     if (blocks > 0x7fffffff) return sem::fail(ctx, SEM_EINVAL, "sem_ax: nel too large");
 #define SEM_AX_ARGS (TW*)w, (const TU*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2], \
         (const TC*)D[3], (const TC*)D[4], (const TC*)D[5], (const TS*)h1, (const TS*)G[0],  \
         (const TS*)G[1], (const TS*)G[2], (const TS*)G[3], (const TS*)G[4], (const TS*)G[5], \
-        nel, skip, dot, lid, pos
+        nel, skip, dot, lid, pos, (const TS*)gp
     const dim3 grid((unsigned)blocks), block(EPB * LX * LX);
+    if (lid && !gp) return sem::fail(ctx, SEM_EINVAL, "launch_ax: the solver form needs packed factors");
     if (dot && lid)
         ax_kernel<LX, EPB, TU, TS, TC, TW, true, true><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
-    else if (dot)
-        ax_kernel<LX, EPB, TU, TS, TC, TW, true, false><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
     else if (lid)
         ax_kernel<LX, EPB, TU, TS, TC, TW, false, true><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
-    else
+    else if (!dot)
         ax_kernel<LX, EPB, TU, TS, TC, TW, false, false><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
+    else
+        return sem::fail(ctx, SEM_EINVAL, "launch_ax: the fused dot needs the solver form");
 #undef SEM_AX_ARGS
     SEM_LAUNCH_CHECK(ctx);
     return SEM_OK;
@@ -233,9 +268,9 @@ int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const
 template <typename TU, typename TS, typename TC, typename TW>
 int dispatch(sem_ctx_t ctx, int lx, void* w, const void* u, const void* const* D,
              const void* h1, const void* const* G, int64_t nel, const int* skip, double* dot,
-             const int32_t* lid = nullptr, const int32_t* pos = nullptr) {
+             const int32_t* lid = nullptr, const int32_t* pos = nullptr, const void* gp = nullptr) {
     switch (lx) {
-#define SEM_AX_CASE(L) case L: return launch_lx<L, TU, TS, TC, TW>(ctx, w, u, D, h1, G, nel, skip, dot, lid, pos);
+#define SEM_AX_CASE(L) case L: return launch_lx<L, TU, TS, TC, TW>(ctx, w, u, D, h1, G, nel, skip, dot, lid, pos, gp);
         SEM_AX_CASE(2) SEM_AX_CASE(3) SEM_AX_CASE(4) SEM_AX_CASE(5) SEM_AX_CASE(6) SEM_AX_CASE(7)
         SEM_AX_CASE(8) SEM_AX_CASE(9) SEM_AX_CASE(10) SEM_AX_CASE(11) SEM_AX_CASE(12)
 #undef SEM_AX_CASE
@@ -307,11 +342,11 @@ int launch_ax(sem_ctx_t ctx, AxKind kind, const AxArgs& a, void* w, const void* 
     const void* G[6] = {a.G[0], a.G[1], a.G[2], a.G[3], a.G[4], a.G[5]};
     switch (kind) {
         case AxKind::F64:
-            return dispatch<double, double, double, double>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos);
+            return dispatch<double, double, double, double>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos, a.Gp);
         case AxKind::F32:
-            return dispatch<float, float, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos);
+            return dispatch<float, float, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos, a.Gp);
         case AxKind::F32_BF16:
-            return dispatch<float, uint16_t, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos);
+            return dispatch<float, uint16_t, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos, a.Gp);
     }
     return fail(ctx, SEM_EINVAL, "launch_ax: bad kind");
 }

@@ -318,6 +318,28 @@ __global__ void to_bf16_kernel(uint16_t* __restrict__ out, const double* __restr
     GRID_LOOP(L, n) out[L] = bf16_rne((float)in[L]);
 }
 
+// slice-blocked pair packing of the six factors (the layout of AxArgs::Gp):
+// local node L = s + ij with s = e lx^3 + k lx^2; pair a at 2-vector 3 s + a lx^2 + ij
+struct Six { const double* g[6]; int l2; };
+template <typename T>
+__device__ __forceinline__ T cvt(double v);
+template <> __device__ __forceinline__ double cvt<double>(double v) { return v; }
+template <> __device__ __forceinline__ float cvt<float>(double v) { return (float)v; }
+template <> __device__ __forceinline__ uint16_t cvt<uint16_t>(double v) { return bf16_rne((float)v); }
+
+template <typename T>
+__global__ void pack_kernel(T* __restrict__ out, Six G, int64_t n) {
+    GRID_LOOP(L, n) {
+        const int64_t ij = L % G.l2, s = L - ij;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int64_t v = 3 * s + (int64_t)a * G.l2 + ij;
+            out[2 * v] = cvt<T>(G.g[2 * a][L]);
+            out[2 * v + 1] = cvt<T>(G.g[2 * a + 1][L]);
+        }
+    }
+}
+
 // ---- flexible CG (Notay's FCG(1)) with a variable preconditioner ----------
 // partials: r.z, non-finite count of z, z.w_prev, (Minv r).w_prev
 template <typename T>
@@ -785,6 +807,15 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
     CG_ALLOC(cg->x64, u64);
     CG_ALLOC(cg->r64, u64);
     CG_ALLOC(cg->wl64, sizeof(double) * n);
+    Six six;
+    for (int q = 0; q < 6; ++q) six.g[q] = Gp[q];
+    six.l2 = A->lx * A->lx;
+    {
+        void* gp = nullptr;
+        CG_ALLOC(gp, sizeof(double) * 6 * n);
+        pack_kernel<double><<<gl, kBlock, 0, st>>>((double*)gp, six, n);
+        cg->A64.Gp = gp;
+    }
     {
         hipError_t e = hipHostMalloc(&cg->S_host, sizeof(Scal), hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc(&cg->sums_host, 2 * sizeof(double), hipHostMallocDefault);
@@ -825,16 +856,22 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
             to_type_kernel<float><<<1, kBlock, 0, st>>>((float*)d, Dp[q], l2);
             L.A.D[q] = d;
         }
-        const size_t vs = bf ? sizeof(uint16_t) * n : sizeof(float) * n;
-        const double* src[7] = {Gp[0], Gp[1], Gp[2], Gp[3], Gp[4], Gp[5], A->h1};
+        const size_t vs = bf ? sizeof(uint16_t) : sizeof(float);
         L.A.h1 = nullptr;
-        for (int q = 0; q < 7; ++q) {
-            if (!src[q]) continue;
+        for (int q = 0; q < 6; ++q) L.A.G[q] = nullptr;     // the solver form reads the packed copy
+        {
             void* d = nullptr;
-            CG_ALLOC(d, vs);
-            if (bf) to_bf16_kernel<<<gl, kBlock, 0, st>>>((uint16_t*)d, src[q], n);
-            else to_type_kernel<float><<<gl, kBlock, 0, st>>>((float*)d, src[q], n);
-            if (q < 6) L.A.G[q] = d; else L.A.h1 = d;
+            CG_ALLOC(d, vs * 6 * n);
+            if (bf) pack_kernel<uint16_t><<<gl, kBlock, 0, st>>>((uint16_t*)d, six, n);
+            else pack_kernel<float><<<gl, kBlock, 0, st>>>((float*)d, six, n);
+            L.A.Gp = d;
+        }
+        if (A->h1) {
+            void* d = nullptr;
+            CG_ALLOC(d, vs * n);
+            if (bf) to_bf16_kernel<<<gl, kBlock, 0, st>>>((uint16_t*)d, A->h1, n);
+            else to_type_kernel<float><<<gl, kBlock, 0, st>>>((float*)d, A->h1, n);
+            L.A.h1 = d;
         }
         L.A.nel = A->nel;
         L.A.lx = A->lx;

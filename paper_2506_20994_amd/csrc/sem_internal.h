@@ -56,6 +56,11 @@ struct AxArgs {
     const void* G[6];
     int64_t nel;
     int lx;
+    // the solver form (lid != 0) reads the six factors from one slice-blocked
+    // array: for slice s = e lx^3 + k lx^2 (a multiple of lx^2) and column ij,
+    // pair a of (g11,g22), (g33,g12), (g13,g23) sits at 2-vector index
+    // 3 s + a lx^2 + ij, in the storage type
+    const void* Gp = nullptr;
 };
 enum class AxKind {
     F64,        // u, h1, G, D, w float64
