@@ -16,7 +16,11 @@ Extra fields:
                 box (amplitude 0.1, h1 = 1, right-hand side of 32 random Fourier
                 modes with |k|_inf <= 8, mean removed): float64 Jacobi-PCG against
                 float64 refinement with float32 and with bfloat16-factor inner
-                solves; wall time of sem_cg_solve (set-up excluded).
+                solves, restarted (_ir) and by residual replacement (_rr); wall
+                time of sem_cg_solve (set-up excluded).
+  learned       the per-element network trained on the GPU from float64
+                Jacobi-PCG snapshot pairs on 16^3 boxes, then used in flexible CG
+                on the same 32^3 solve.
 
 --mode copy times a plain 1 GiB device copy (used to calibrate the HBM byte
 counters of rocprofv3); it prints nothing on stdout.
@@ -107,6 +111,55 @@ def solve_comparison(ctx, P, n, lx, amp, tol=1e-10):
     return res
 
 
+def learned_comparison(ctx, P, n, lx, amp, tol=1e-10):
+    """Train the per-element network on snapshot pairs from float64 Jacobi-PCG
+    solves on 16^3 boxes (random amplitudes, white-noise right-hand sides),
+    then solve the held-out box with flexible CG + network (float64, and
+    float32 refinement) against Jacobi-PCG."""
+    import torch
+    import synth
+    from paper_2506_20994_amd.box import BoxOperator
+    from paper_2506_20994_amd import learned as LR
+    lp = P.sem_lp_create(ctx, n ** 3)
+    LR.init_network(lp, 7, mu=-1.0, jacobi_base=True, out_scale=0.1)
+    t0 = time.perf_counter()
+    X, T, info = LR.generate(ctx, lp, n=16, boxes=16, snapshots=16, elems_per_snapshot=256,
+                             rhs="noise", include_zero=True)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hist = LR.train(lp, X, T, epochs=10, batch=1024, lr=1e-3)
+    t_train = time.perf_counter() - t0
+    del X, T
+    op = BoxOperator(ctx, n, lx, amp)
+    k, a, ph = synth.fourier_modes(2)
+    b = op.fourier_rhs(k, a, ph)
+    x = torch.empty_like(b)
+    op.bind(lp)
+    res = {"training": {"rows": info["rows"], "boxes": info["boxes"],
+                        "rejected_amplitude_draws": info["rejected_draws"],
+                        "datagen_s": round(t_gen, 2), "train_s": round(t_train, 2),
+                        "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}}
+    for name, code, use in (("jacobi_pcg_f64", P.SEM_SOLVE_F64, False),
+                            ("learned_fcg_f64", P.SEM_SOLVE_F64, True),
+                            ("learned_fcg_f32_ir", P.SEM_SOLVE_F32_IR, True)):
+        kw = dict(tol=tol, precision=code, learned=lp if use else None, maxit=50000,
+                  inner_maxit=5000)
+        cg = op.solver(code, learned=lp if use else None)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = P.sem_cg_solve(cg, x, b, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        res[name] = {"ms": round(ms, 2), "iterations": st["iterations"],
+                     "jacobi_steps": st["jacobi_steps"], "fell_back": st["fell_back"],
+                     "relres": st["relres"], "converged": st["converged"]}
+        print(f"[bench] learned {name}: {ms:.1f} ms, {st['iterations']} its, "
+              f"{st['jacobi_steps']} Jacobi, fell back {st['fell_back']}", file=sys.stderr, flush=True)
+        cg.close()
+    lp.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +170,7 @@ def main():
     ap.add_argument("--amp", type=float, default=0.1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--mode", default="bench", choices=["bench", "copy"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -217,6 +271,8 @@ def main():
         del op, u, w
         torch.cuda.empty_cache()
         out["solve"] = solve_comparison(ctx, P, n, lx, amp)
+        if not args.no_learned and lx == 8:
+            out["learned"] = learned_comparison(ctx, P, n, lx, amp)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(lx)
     print(json.dumps(out), flush=True)
