@@ -8,7 +8,10 @@ the library adds around the paper's Poisson solve.  Readings taken:
     scale), in the order g11, g22, g33, g12, g13, g23;
   * target: t_e = e_e kappa_e / s_e (dimensionless), e_e the element's error;
   * network: Linear-ReLU-Linear-ReLU-Linear, 518 -> 256 -> 256 -> 512,
-    weights (fan_out, fan_in);
+    weights (fan_out, fan_in); or its linear form (identity activations, no
+    biases, geometric inputs zeroed), which makes the preconditioner a fixed
+    linear map of r -- the element-local linear predictor of the error from
+    the residual, whose white-noise optimum is the element block of A^+;
   * loss: mean squared error over all outputs of the batch, or, with a metric
     K, the batch mean of (y - t)^T K (y - t).  The preconditioner is judged
     in the energy norm (the norm CG minimises), so the metric used is
@@ -48,8 +51,13 @@ def targets(err_e, s, kappa):
     return err_e.reshape(E, -1) * (kappa / s)[:, None]
 
 
-def forward(params, X):
+def forward(params, X, linear=False):
+    """Linear=True: identity activations and no biases (y3 = W3 W2 W1 x)."""
     W1, b1, W2, b2, W3, b3 = params
+    if linear:
+        y1 = X @ W1.T
+        y2 = y1 @ W2.T
+        return y1, y2, y2 @ W3.T
     a1 = X @ W1.T + b1
     y1 = np.maximum(a1, 0.0)
     a2 = y1 @ W2.T + b2
@@ -72,17 +80,18 @@ def reference_metric(lx=8, mu=1.0):
     return A / kappa + mu * Bm
 
 
-def loss(params, X, T, K=None):
-    d = forward(params, X)[2] - T
+def loss(params, X, T, K=None, linear=False):
+    d = forward(params, X, linear)[2] - T
     if K is None:
         return float(np.mean(d ** 2))
     return float(np.mean(np.einsum("bi,ij,bj->b", d, K, d)))
 
 
-def backward(params, X, T, K=None):
-    """(loss, grads) of the loss above, grads in params' order."""
+def backward(params, X, T, K=None, linear=False):
+    """(loss, grads) of the loss above, grads in params' order (bias gradients
+    are zero in the linear form, whose biases are not used)."""
     W1, b1, W2, b2, W3, b3 = params
-    y1, y2, y3 = forward(params, X)
+    y1, y2, y3 = forward(params, X, linear)
     if K is None:
         d3 = 2.0 * (y3 - T) / y3.size
         lval = float(np.mean((y3 - T) ** 2))
@@ -93,12 +102,14 @@ def backward(params, X, T, K=None):
         lval = float(np.mean(np.sum(d * Kd, axis=1)))
     gW3 = d3.T @ y2
     gb3 = d3.sum(axis=0)
-    d2 = (d3 @ W3) * (y2 > 0)
+    d2 = d3 @ W3 if linear else (d3 @ W3) * (y2 > 0)
     gW2 = d2.T @ y1
     gb2 = d2.sum(axis=0)
-    d1 = (d2 @ W2) * (y1 > 0)
+    d1 = d2 @ W2 if linear else (d2 @ W2) * (y1 > 0)
     gW1 = d1.T @ X
     gb1 = d1.sum(axis=0)
+    if linear:
+        gb1, gb2, gb3 = 0 * gb1, 0 * gb2, 0 * gb3
     return lval, [gW1, gb1, gW2, gb2, gW3, gb3]
 
 
@@ -116,12 +127,14 @@ def adam_step(params, grads, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8)
     return out_p, out_m, out_v
 
 
-def apply(params, r_local, G, h1, ids, n_unique):
+def apply(params, r_local, G, h1, ids, n_unique, linear=False):
     """Preconditioner z = Q Q^T (mult^-1 (s/kappa) NN(features(r))) on the
-    local layout."""
+    local layout (linear: geometric inputs zeroed, so z is linear in r)."""
     from .gs import gs, multiplicity
     X, s, kappa = features(r_local, G, h1)
-    t = forward(params, X)[2]
+    if linear:
+        X[:, 512:] = 0.0
+    t = forward(params, X, linear)[2]
     z = (t * (s / kappa)[:, None]).reshape(r_local.shape)
     mult = multiplicity(ids, n_unique)
     return gs(z / mult, ids, n_unique)

@@ -239,6 +239,83 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
     }
 }
 
+// One thread per node ("3D" mapping): every load and store of the streamed
+// arrays is contiguous across the workgroup, which matters when lx^2 does not
+// fill whole waves (lx = 3, 5, 6, 7).  u and the three fluxes go through LDS;
+// each thread keeps the derivative-matrix rows it needs (its i, j, k) in
+// registers.  Used for the public operator only.
+template <int LX> struct Shape3D {
+    static constexpr int EPB = LX == 3 ? 16 : LX == 5 ? 4 : LX == 6 ? 2 : 1;
+};
+
+template <int LX, int EPB, typename TS, typename TC, typename TW>
+__global__ void __launch_bounds__(EPB * LX * LX * LX)
+ax3d_kernel(TW* __restrict__ w, const TS* __restrict__ u,
+            const TC* __restrict__ dx, const TC* __restrict__ dy, const TC* __restrict__ dz,
+            const TC* __restrict__ dxt, const TC* __restrict__ dyt, const TC* __restrict__ dzt,
+            const TS* __restrict__ h1, const TS* __restrict__ g11, const TS* __restrict__ g22,
+            const TS* __restrict__ g33, const TS* __restrict__ g12, const TS* __restrict__ g13,
+            const TS* __restrict__ g23, int64_t nel) {
+    constexpr int L2 = LX * LX;
+    constexpr int L3 = L2 * LX;
+    __shared__ TC s_u[EPB * L3];
+    __shared__ TC s_r[EPB * L3];
+    __shared__ TC s_s[EPB * L3];
+    __shared__ TC s_t[EPB * L3];
+    const int tid = threadIdx.x;
+    const int el = tid / L3;
+    const int p = tid - el * L3;
+    const int i = p % LX, j = (p / LX) % LX, k = p / L2;
+    const int64_t e = (int64_t)blockIdx.x * EPB + el;
+    const bool live = e < nel;
+    const int64_t g = e * L3 + p;               // contiguous across the workgroup
+    TC* su = s_u + el * L3;
+    TC* sr = s_r + el * L3;
+    TC* ss = s_s + el * L3;
+    TC* st = s_t + el * L3;
+    TC uv = 0, G11 = 0, G22 = 0, G33 = 0, G12 = 0, G13 = 0, G23 = 0, H = 1;
+    if (live) {
+        uv = Load<TS>::get(u, g);
+        G11 = Load<TS>::get(g11, g); G22 = Load<TS>::get(g22, g); G33 = Load<TS>::get(g33, g);
+        G12 = Load<TS>::get(g12, g); G13 = Load<TS>::get(g13, g); G23 = Load<TS>::get(g23, g);
+        if (h1) H = Load<TS>::get(h1, g);
+    }
+    su[p] = uv;
+    TC di[LX], dj[LX], dk[LX];
+#pragma unroll
+    for (int l = 0; l < LX; ++l) {
+        di[l] = dx[l * LX + i];
+        dj[l] = dy[l * LX + j];
+        dk[l] = dz[l * LX + k];
+    }
+    __syncthreads();
+    TC r = 0, s = 0, t = 0;
+#pragma unroll
+    for (int l = 0; l < LX; ++l) {
+        r += di[l] * su[k * L2 + j * LX + l];
+        s += dj[l] * su[k * L2 + l * LX + i];
+        t += dk[l] * su[l * L2 + j * LX + i];
+    }
+    sr[p] = H * (G11 * r + G12 * s + G13 * t);
+    ss[p] = H * (G12 * r + G22 * s + G23 * t);
+    st[p] = H * (G13 * r + G23 * s + G33 * t);
+#pragma unroll
+    for (int l = 0; l < LX; ++l) {
+        di[l] = dxt[l * LX + i];
+        dj[l] = dyt[l * LX + j];
+        dk[l] = dzt[l * LX + k];
+    }
+    __syncthreads();
+    TC acc = 0;
+#pragma unroll
+    for (int l = 0; l < LX; ++l) {
+        acc += di[l] * sr[k * L2 + j * LX + l];
+        acc += dj[l] * ss[k * L2 + l * LX + i];
+        acc += dk[l] * st[l * L2 + j * LX + i];
+    }
+    if (live) store_nt(w, g, (TW)acc);
+}
+
 template <int LX, typename TU, typename TS, typename TC, typename TW>
 int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const void* h1,
               const void* const* G, int64_t nel, const int* skip, double* dot, const int32_t* lid,
@@ -252,6 +329,18 @@ int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const
         nel, skip, dot, lid, pos, (const TS*)gp
     const dim3 grid((unsigned)blocks), block(EPB * LX * LX);
     if (lid && !gp) return sem::fail(ctx, SEM_EINVAL, "launch_ax: the solver form needs packed factors");
+    if constexpr (LX == 3 || LX == 5 || LX == 6 || LX == 7) {
+        if (!lid && !dot) {
+            constexpr int E3 = Shape3D<LX>::EPB;
+            const int64_t b3 = (nel + E3 - 1) / E3;
+            ax3d_kernel<LX, E3, TS, TC, TW><<<(unsigned)b3, E3 * LX * LX * LX, 0, ctx->stream>>>(
+                (TW*)w, (const TS*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2], (const TC*)D[3],
+                (const TC*)D[4], (const TC*)D[5], (const TS*)h1, (const TS*)G[0], (const TS*)G[1],
+                (const TS*)G[2], (const TS*)G[3], (const TS*)G[4], (const TS*)G[5], nel);
+            SEM_LAUNCH_CHECK(ctx);
+            return SEM_OK;
+        }
+    }
     if (dot && lid)
         ax_kernel<LX, EPB, TU, TS, TC, TW, true, true><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
     else if (lid)

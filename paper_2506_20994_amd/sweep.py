@@ -1,0 +1,83 @@
+"""The paper's measurement grid on this GPU: float64 operator throughput for the
+nine cubic meshes N_E = 128 ... 32768 elements and 3 <= lx <= 8 (Sec. 4.4 and
+Sec. 5), reported as Gflop/s with 12 lx + 18 flop per local node (the paper
+states no flop formula; this counts 6 lx multiply-adds per node for the three
+derivative passes, 6 lx for the transposed passes and 18 for the geometric
+multiply), plus GB/s at 72 B per local node and unique GDOF/s.
+
+The operator is element-local, so its throughput depends only on the element
+count and lx: every point uses N_E elements of random symmetric positive
+definite factors, h1 ~ U[0.5, 2] and u ~ N(0, 1).
+
+Usage: python -m paper_2506_20994_amd.sweep [--reps R] [--out FILE]
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+import synth
+from . import _binding as B
+
+SIZES = [128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768]
+LXS = [3, 4, 5, 6, 7, 8]
+
+
+def _fields(ctx, nel, lx, seed=0):
+    """Random operator inputs of nel elements (the operator is element-local, so
+    the throughput does not depend on how the elements are connected)."""
+    G, h1 = synth.random_spd_factors(nel, lx, seed)
+    u = synth.local_normal(nel, lx, seed + 1)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    _, _, dx, dxt = B.sem_gll(lx)
+    D = [dev(dx)] * 3 + [dev(dxt)] * 3
+    return dev(u), [dev(g) for g in G], dev(h1), D
+
+
+def run(reps=50):
+    ctx = B.sem_create()
+    rows = []
+    for lx in LXS:
+        for nel in SIZES:
+            u, G, h1, D = _fields(ctx, nel, lx)
+            w = torch.empty_like(u)
+            for _ in range(5):
+                B.sem_ax(ctx, w, u, *D, h1, *G, nel, lx)
+            st = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(st)
+            for _ in range(reps):
+                B.sem_ax(ctx, w, u, *D, h1, *G, nel, lx)
+            e1.record(st)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / reps * 1e-3
+            nl = nel * lx ** 3
+            rows.append({"lx": lx, "nel": nel, "us": round(t * 1e6, 2),
+                         "gflops": round((12 * lx + 18) * nl / t / 1e9, 1),
+                         "gbs": round(72 * nl / t / 1e9, 1),
+                         "gdofs": round(nel * (lx - 1) ** 3 / t / 1e9, 3)})
+            print(json.dumps(rows[-1]), flush=True)
+    ctx.close()
+    return rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--reps", type=int, default=50)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    rows = run(a.reps)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(rows, f, indent=1)
+    print(f"[sweep] {len(rows)} points in {time.perf_counter() - t0:.1f} s", file=sys.stderr)
+
+
+if __name__ == "__main__":
+    main()

@@ -12,8 +12,8 @@ def _small_net(seed, sizes=(10, 7, 6, 5)):
     return synth.mlp_init(seed, sizes)
 
 
-@pytest.mark.parametrize("metric", [False, True])
-def test_backprop_matches_finite_differences(metric):
+@pytest.mark.parametrize("metric,linear", [(False, False), (True, False), (False, True)])
+def test_backprop_matches_finite_differences(metric, linear):
     r = np.random.default_rng(0)
     params = _small_net(1)
     params = [p + 0.05 * r.standard_normal(p.shape) for p in params]   # non-zero biases too
@@ -23,17 +23,17 @@ def test_backprop_matches_finite_differences(metric):
     if metric:
         L = r.standard_normal((5, 5))
         K = L @ L.T + 0.1 * np.eye(5)
-    lval, grads = mlp.backward(params, X, T, K)
-    assert lval == pytest.approx(mlp.loss(params, X, T, K), rel=1e-13)
+    lval, grads = mlp.backward(params, X, T, K, linear)
+    assert lval == pytest.approx(mlp.loss(params, X, T, K, linear), rel=1e-13)
     h = 1e-6
     for pi, p in enumerate(params):
         fd = np.zeros_like(p)
         for idx in np.ndindex(p.shape):
             pp = [q.copy() for q in params]
             pp[pi][idx] += h
-            lp = mlp.loss(pp, X, T, K)
+            lp = mlp.loss(pp, X, T, K, linear)
             pp[pi][idx] -= 2 * h
-            lm = mlp.loss(pp, X, T, K)
+            lm = mlp.loss(pp, X, T, K, linear)
             fd[idx] = (lp - lm) / (2 * h)
         assert np.max(np.abs(fd - grads[pi])) <= 1e-6 * max(1.0, np.max(np.abs(fd))), pi
 
@@ -97,3 +97,11 @@ def test_apply_is_continuous():
     zg = np.zeros(P.nu)
     zg[P.ids.ravel()] = z.ravel()
     np.testing.assert_allclose(z, zg[P.ids], rtol=1e-14)
+
+
+def test_linear_form_is_linear():
+    params = _small_net(3)
+    r = np.random.default_rng(1)
+    x1, x2 = r.standard_normal((4, 10)), r.standard_normal((4, 10))
+    f = lambda x: mlp.forward(params, x, linear=True)[2]  # noqa: E731
+    np.testing.assert_allclose(f(2.0 * x1 - 3.0 * x2), 2.0 * f(x1) - 3.0 * f(x2), atol=1e-12)
