@@ -290,6 +290,13 @@ int sem_lp_get_step(sem_lp_t lp, int64_t* step);
  * the energy norm CG minimises, plus a mass term that fixes the element-wise
  * constant.  K is held in bfloat16. */
 int sem_lp_set_metric(sem_lp_t lp, double mu);
+/* Linear form (on != 0): identity activations, biases unused (their
+ * gradients are zero), geometric inputs zeroed.  The network output is then
+ * W3 W2 W1 x and the preconditioner a fixed linear map of r (flexible CG keeps
+ * its conjugacy); trained on white-noise residual/error pairs it approximates
+ * the element block of the inverse operator.  Applies to training and
+ * inference from the next call on. */
+int sem_lp_set_linear(sem_lp_t lp, int on);
 /* Jacobi base (on != 0): the preconditioner becomes z = Minv r + P_net(r),
  * Minv the inverse assembled diagonal of the bound operator, and training
  * targets become (err - Minv r) kappa / s, so the network learns the

@@ -16,7 +16,7 @@ __all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONV
            "CgSolver", "SEM_SOLVE_F64", "SEM_SOLVE_F32_IR", "SEM_SOLVE_BF16_IR",
            "LearnedPrecond", "sem_lp_create", "sem_lp_destroy", "sem_lp_set", "sem_lp_get",
            "sem_lp_set_step", "sem_lp_get_step", "sem_lp_bind", "sem_lp_samples", "sem_lp_forward",
-           "sem_lp_gradients", "sem_lp_adam", "sem_lp_set_metric", "sem_lp_set_jacobi_base", "sem_lp_train_step", "sem_lp_apply", "LP_SLOTS",
+           "sem_lp_gradients", "sem_lp_adam", "sem_lp_set_metric", "sem_lp_set_jacobi_base", "sem_lp_set_linear", "sem_lp_train_step", "sem_lp_apply", "LP_SLOTS",
            "SEM_LP_IN", "SEM_LP_IN_PAD", "SEM_LP_HIDDEN", "SEM_LP_OUT"]
 
 SEM_LP_IN, SEM_LP_IN_PAD, SEM_LP_HIDDEN, SEM_LP_OUT = 518, 528, 256, 512
@@ -106,6 +106,7 @@ EXPORTS = {
     "sem_lp_apply": (_int, [_vp, _vp, _vp, _int]),
     "sem_lp_set_metric": (_int, [_vp, _dbl]),
     "sem_lp_set_jacobi_base": (_int, [_vp, _int]),
+    "sem_lp_set_linear": (_int, [_vp, _int]),
 }
 
 _LIB = None
@@ -482,3 +483,7 @@ def sem_lp_set_metric(lp, mu):
 
 def sem_lp_set_jacobi_base(lp, on):
     _check(lib().sem_lp_set_jacobi_base(lp.handle, int(bool(on))), lp.ctx.handle)
+
+
+def sem_lp_set_linear(lp, on):
+    _check(lib().sem_lp_set_linear(lp.handle, int(bool(on))), lp.ctx.handle)

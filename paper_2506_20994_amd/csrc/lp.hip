@@ -289,7 +289,7 @@ __global__ void features_kernel(u16* __restrict__ X, float* __restrict__ scale, 
 #pragma unroll
     for (int c = 0; c < 8; ++c) X[row * kInPad + c * 64 + lane] = bf16_rne((float)(v[c] / s));
     if (lane < kInPad - kOut)
-        X[row * kInPad + kOut + lane] = lane < 6 ? bf16_rne(geo[e * 6 + lane]) : (u16)0;
+        X[row * kInPad + kOut + lane] = (lane < 6 && geo) ? bf16_rne(geo[e * 6 + lane]) : (u16)0;
     if (lane == 0 && scale) scale[row] = (float)(s / kap);
     if (Tt) {
 #pragma unroll
@@ -339,6 +339,10 @@ __global__ void lp_output_unique_kernel(T* __restrict__ z, const float* __restri
     }
 }
 
+__global__ void zero_f32(float* __restrict__ x, int n) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) x[q] = 0.f;
+}
+
 __global__ void inv_kernel(double* __restrict__ x, int64_t n) {
     for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
          L += (int64_t)gridDim.x * blockDim.x)
@@ -378,6 +382,8 @@ struct sem_lp_s {
     u16* K = nullptr;
     float *dF = nullptr, *Kd = nullptr;
     u16* dB = nullptr;
+    // linear form: identity activations, no biases, geometric inputs zeroed
+    bool linear = false;
     // Jacobi base: z = Minv r + network correction (Minv of the bound operator)
     bool jacobi_base = false;
     double* minv = nullptr;
@@ -432,9 +438,10 @@ int forward(sem_lp_t lp, const u16* X, int64_t M) {
     if (rc) return rc;
     if (M > 0x7fffffff) return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp: too many rows");
     const int m = (int)M;
-    rc = gemm(lp, m, kHid, kInPad, X, kInPad, lp->W1b, kInPad, lp->b[0], nullptr, 0, nullptr, lp->Y1, kHid, EPI_BIAS | EPI_RELU);
-    if (!rc) rc = gemm(lp, m, kHid, kHid, lp->Y1, kHid, lp->W2b, kHid, lp->b[1], nullptr, 0, nullptr, lp->Y2, kHid, EPI_BIAS | EPI_RELU);
-    if (!rc) rc = gemm(lp, m, kOut, kHid, lp->Y2, kHid, lp->W3b, kHid, lp->b[2], nullptr, 0, lp->Y3, nullptr, kOut, EPI_BIAS);
+    const int hid = lp->linear ? 0 : EPI_BIAS | EPI_RELU, out = lp->linear ? 0 : EPI_BIAS;
+    rc = gemm(lp, m, kHid, kInPad, X, kInPad, lp->W1b, kInPad, lp->b[0], nullptr, 0, nullptr, lp->Y1, kHid, hid);
+    if (!rc) rc = gemm(lp, m, kHid, kHid, lp->Y1, kHid, lp->W2b, kHid, lp->b[1], nullptr, 0, nullptr, lp->Y2, kHid, hid);
+    if (!rc) rc = gemm(lp, m, kOut, kHid, lp->Y2, kHid, lp->W3b, kHid, lp->b[2], nullptr, 0, lp->Y3, nullptr, kOut, out);
     return rc;
 }
 
@@ -620,6 +627,12 @@ extern "C" int sem_lp_set_metric(sem_lp_t lp, double mu) {
     return SEM_OK;
 }
 
+extern "C" int sem_lp_set_linear(sem_lp_t lp, int on) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_set_linear: null network");
+    lp->linear = on != 0;
+    return SEM_OK;
+}
+
 extern "C" int sem_lp_set_jacobi_base(sem_lp_t lp, int on) {
     if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_set_jacobi_base: null network");
     lp->jacobi_base = on != 0;
@@ -688,7 +701,7 @@ extern "C" int sem_lp_samples(sem_lp_t lp, const double* r, const double* err, c
     if (count == 0) return SEM_OK;
     features_kernel<double><<<(unsigned)count, 64, 0, ctx->stream>>>(X, nullptr, T, r, err,
                                                                       lp->jacobi_base ? lp->minv : nullptr,
-                                                                      lp->geo, lp->kappa,
+                                                                      lp->linear ? nullptr : lp->geo, lp->kappa,
                                                                       elems, count, row0, nullptr, nullptr);
     SEM_LAUNCH_CHECK(ctx);
     return SEM_OK;
@@ -731,19 +744,25 @@ static int lp_backward(sem_lp_t lp, const uint16_t* Xb, const float* Tb, int B) 
     rc = transpose(lp, lp->tA, B, lp->d3b, kOut, B, kOut);           // d3^T: 512 x B
     if (!rc) rc = transpose(lp, lp->tB, B, lp->Y2, kHid, B, kHid);   // Y2^T: 256 x B
     if (!rc) rc = gemm(lp, kOut, kHid, B, lp->tA, B, lp->tB, B, nullptr, nullptr, 0, lp->gW[2], nullptr, kHid, 0);
+    const int mask = lp->linear ? 0 : EPI_MASK;
     colsum<<<(kOut + 255) / 256, 256, 0, st>>>(lp->gb[2], lp->d3f, B, kOut);
-    if (!rc) rc = gemm(lp, B, kHid, kOut, lp->d3b, kOut, lp->W3t, kOut, nullptr, lp->Y2, kHid, lp->d2f, lp->d2b, kHid, EPI_MASK);
+    if (!rc) rc = gemm(lp, B, kHid, kOut, lp->d3b, kOut, lp->W3t, kOut, nullptr, lp->Y2, kHid, lp->d2f, lp->d2b, kHid, mask);
     // layer 2
     if (!rc) rc = transpose(lp, lp->tA, B, lp->d2b, kHid, B, kHid);
     if (!rc) rc = transpose(lp, lp->tB, B, lp->Y1, kHid, B, kHid);
     if (!rc) rc = gemm(lp, kHid, kHid, B, lp->tA, B, lp->tB, B, nullptr, nullptr, 0, lp->gW[1], nullptr, kHid, 0);
     colsum<<<(kHid + 255) / 256, 256, 0, st>>>(lp->gb[1], lp->d2f, B, kHid);
-    if (!rc) rc = gemm(lp, B, kHid, kHid, lp->d2b, kHid, lp->W2t, kHid, nullptr, lp->Y1, kHid, lp->d1f, lp->d1b, kHid, EPI_MASK);
+    if (!rc) rc = gemm(lp, B, kHid, kHid, lp->d2b, kHid, lp->W2t, kHid, nullptr, lp->Y1, kHid, lp->d1f, lp->d1b, kHid, mask);
     // layer 1
     if (!rc) rc = transpose(lp, lp->tA, B, lp->d1b, kHid, B, kHid);
     if (!rc) rc = transpose(lp, lp->tB, B, Xb, kInPad, B, kInPad);
     if (!rc) rc = gemm(lp, kHid, kInPad, B, lp->tA, B, lp->tB, B, nullptr, nullptr, 0, lp->gW[0], nullptr, kInPad, 0);
     colsum<<<(kHid + 255) / 256, 256, 0, st>>>(lp->gb[0], lp->d1f, B, kHid);
+    if (lp->linear) {   // the biases are not used: their gradients are zero
+        zero_f32<<<1, 256, 0, st>>>(lp->gb[0], kHid);
+        zero_f32<<<1, 256, 0, st>>>(lp->gb[1], kHid);
+        zero_f32<<<2, 256, 0, st>>>(lp->gb[2], kOut);
+    }
     SEM_LAUNCH_CHECK(ctx);
     return rc;
 }
@@ -837,7 +856,8 @@ int lp_apply_t(sem_lp_t lp, T* z, const T* r, bool unique) {
     hipStream_t st = ctx->stream;
     const int64_t nel = lp->nel;
     features_kernel<T><<<(unsigned)nel, 64, 0, st>>>(lp->X, lp->scale, nullptr, r, nullptr, nullptr,
-                                                     lp->geo, lp->kappa, nullptr, nel, 0, lp->skip,
+                                                     lp->linear ? nullptr : lp->geo, lp->kappa, nullptr,
+                                                     nel, 0, lp->skip,
                                                      unique ? lp->gs->lid : nullptr);
     SEM_LAUNCH_CHECK(ctx);
     int rc = forward(lp, lp->X, nel);

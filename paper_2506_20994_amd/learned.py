@@ -113,13 +113,16 @@ def train(lp, X, T, epochs=4, batch=1024, lr=1e-3, seed=500, verbose=False):
     return hist
 
 
-def init_network(lp, seed=7, mu=None, jacobi_base=None, out_scale=1.0):
+def init_network(lp, seed=7, mu=None, jacobi_base=None, out_scale=1.0, linear=None):
     """He-initialised weights (the last layer scaled by out_scale); mu >= 0
-    selects the energy-norm loss; jacobi_base selects z = Minv r + network."""
+    selects the energy-norm loss; jacobi_base selects z = Minv r + network;
+    linear selects the linear form (identity activations, no biases)."""
     if mu is not None:
         B.sem_lp_set_metric(lp, mu)
     if jacobi_base is not None:
         B.sem_lp_set_jacobi_base(lp, jacobi_base)
+    if linear is not None:
+        B.sem_lp_set_linear(lp, linear)
     params = synth.mlp_init(seed)
     params[4] = params[4] * out_scale
     for s, p in enumerate(params):

@@ -98,6 +98,23 @@ def test_gradients_energy_metric(sem_ctx):
     lp.close()
 
 
+def test_gradients_linear_form(sem_ctx):
+    B = 128
+    params = _params(24)
+    lp = P.sem_lp_create(sem_ctx, B)
+    _load(lp, params)
+    P.sem_lp_set_linear(lp, 1)
+    Xq, Xd, T = _inputs(B, 25)
+    loss = P.sem_lp_gradients(lp, Xd, to_dev(T.astype(np.float32)))
+    l_ref, g_ref = mlp.backward(_qparams(params), Xq, T, linear=True)
+    assert abs(loss - l_ref) <= GRAD_TOL * l_ref
+    for s in (0, 2, 4):
+        assert _nrm(P.sem_lp_get(lp, 18 + s), g_ref[s]) <= GRAD_TOL, s
+    for s in (1, 3, 5):
+        assert np.all(P.sem_lp_get(lp, 18 + s) == 0)
+    lp.close()
+
+
 def test_adam_matches_oracle(sem_ctx):
     lp = P.sem_lp_create(sem_ctx, 8)
     params = _params(30)
