@@ -74,6 +74,9 @@ template <> struct Packed<uint16_t> {
 
 template <int LX> struct Shape {
     static constexpr bool kWavePrivate = (64 % (LX * LX)) == 0;
+    // occupancy floor (waves per SIMD) handed to the register allocator (a
+    // floor of 3 at lx = 10 gave three waves per SIMD but a slower kernel)
+    static constexpr int kWavesPerEU = 1;
     // elements per workgroup: about four waves, LDS of float64 within ~64 KiB
     static constexpr int EPB = LX == 2 ? 64 : LX == 3 ? 28 : LX == 4 ? 16 : LX == 5 ? 10
                              : LX == 6 ? 7 : LX == 7 ? 5 : LX == 8 ? 4 : LX == 9 ? 3
@@ -94,7 +97,7 @@ __device__ __forceinline__ void wave_sync() {
 // through the caches, since neighbouring elements share nodes), and the
 // output of node L goes to w[pos[L]], the plan's CSR order.
 template <int LX, int EPB, typename TU, typename TS, typename TC, typename TW, bool FUSE, bool GATHER>
-__global__ void __launch_bounds__(EPB * LX * LX)
+__global__ void __launch_bounds__(EPB * LX * LX) __attribute__((amdgpu_waves_per_eu(Shape<LX>::kWavesPerEU, 8)))
 ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
           const TC* __restrict__ dx, const TC* __restrict__ dy, const TC* __restrict__ dz,
           const TC* __restrict__ dxt, const TC* __restrict__ dyt, const TC* __restrict__ dzt,
@@ -240,12 +243,13 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
 }
 
 // One thread per node ("3D" mapping): every load and store of the streamed
-// arrays is contiguous across the workgroup, which matters when lx^2 does not
-// fill whole waves (lx = 3, 5, 6, 7).  u and the three fluxes go through LDS;
-// each thread keeps the derivative-matrix rows it needs (its i, j, k) in
-// registers.  Used for the public operator only.
+// arrays is contiguous across the workgroup.  u and the three fluxes go
+// through LDS; each thread keeps the derivative-matrix rows it needs (its i,
+// j, k) in registers.  Used for the public operator at lx = 3, where nine
+// columns per element leave the column mapping's loads badly fragmented (it
+// measured slower than the column kernel at lx = 5, 6, 7).
 template <int LX> struct Shape3D {
-    static constexpr int EPB = LX == 3 ? 16 : LX == 5 ? 4 : LX == 6 ? 2 : 1;
+    static constexpr int EPB = 16;
 };
 
 template <int LX, int EPB, typename TS, typename TC, typename TW>
@@ -329,7 +333,7 @@ int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const
         nel, skip, dot, lid, pos, (const TS*)gp
     const dim3 grid((unsigned)blocks), block(EPB * LX * LX);
     if (lid && !gp) return sem::fail(ctx, SEM_EINVAL, "launch_ax: the solver form needs packed factors");
-    if constexpr (LX == 3 || LX == 5 || LX == 6 || LX == 7) {
+    if constexpr (LX == 3) {
         if (!lid && !dot) {
             constexpr int E3 = Shape3D<LX>::EPB;
             const int64_t b3 = (nel + E3 - 1) / E3;

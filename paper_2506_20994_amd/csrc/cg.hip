@@ -602,7 +602,8 @@ int read_sums(sem_cg_t cg, double* s, double* q);
 // the iteration continues with the same search direction.  Converged when
 // the replaced float64 residual meets tol.
 int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int check_every,
-           double bnorm, int* iters_out, int* replacements, int* breakdown_out, double* hist, int nhist) {
+           double bnorm, int* iters_out, int* replacements, int* breakdown_out, double* hist, int nhist,
+           int* njac_out) {
     sem_ctx_t ctx = cg->ctx;
     hipStream_t st = ctx->stream;
     const int64_t n = cg->nu;
@@ -619,8 +620,24 @@ int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int chec
     SEM_LAUNCH_CHECK(ctx);
     const int nb = sem::ax_blocks(lv.A.lx, lv.A.nel);
     int nrep = 0;
+    float* z = (float*)lv.z;
+    float* wu = (float*)lv.wu;
     for (;;) {
         for (int q = 0; q < check_every; ++q) {
+            if (cg->lp) {   // flexible CG step with the network (Jacobi where it is rejected)
+                int rc = sem::lp_apply(cg->lp, z, r, false, &cg->S->done, true);
+                if (rc) return rc;
+                fcg_dots_kernel<float><<<g, kBlock, 0, st>>>(r, z, wu, minv, n, cg->S, cg->part);
+                fcg_gamma_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
+                fcg_p_kernel<float><<<g, kBlock, 0, st>>>(p, z, r, minv, n, cg->S, cg->part2);
+                rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid, cg->gs->upos);
+                if (rc) return rc;
+                fcg_alpha_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, nb, cg->part2, (int)g);
+                fcg_update_kernel<float><<<g, kBlock, 0, st>>>(x, r, wu, p, wl, minv, uoff, uidx, n, cg->S,
+                                                               cg->part);
+                pcg_beta_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
+                continue;
+            }
             int rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid, cg->gs->upos);
             if (rc) return rc;
             pcg_alpha_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, nb);
@@ -652,14 +669,16 @@ int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int chec
         sub_mean_kernel<<<g, kBlock, 0, st>>>(cg->r64, cg->sums, (double)n, n);
         rr_replace_kernel<<<g, kBlock, 0, st>>>(r, cg->r64, minv, n, cg->part);
         rr_resume_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
-        // the paused iteration skipped its direction update: p = Minv r + beta p
-        // with the replaced residual and the beta of that iteration
-        pcg_p_kernel<float><<<g, kBlock, 0, st>>>(p, r, minv, n, cg->S);
+        // PCG: the paused iteration skipped its direction update, redone with
+        // the replaced residual and that iteration's beta (flexible CG forms
+        // its direction at the start of the next iteration instead)
+        if (!cg->lp) pcg_p_kernel<float><<<g, kBlock, 0, st>>>(p, r, minv, n, cg->S);
         SEM_LAUNCH_CHECK(ctx);
     }
     *iters_out = cg->S_host->it;
     *replacements = nrep;
     *breakdown_out = cg->S_host->breakdown;
+    *njac_out = cg->S_host->njac;
     return SEM_OK;
 }
 
@@ -910,8 +929,7 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
         return sem::fail(ctx, SEM_EINVAL, "sem_cg_solve: preconditioner differs from set-up");
     if (opts->ir_mode != 0 && opts->ir_mode != 1)
         return sem::fail(ctx, SEM_EINVAL, "sem_cg_solve: bad ir_mode %d", opts->ir_mode);
-    if (opts->ir_mode == 1 && cg->lp)
-        return sem::fail(ctx, SEM_EINVAL, "sem_cg_solve: residual replacement is not combined with the learned preconditioner");
+
     if (!(opts->tol > 0.0)) return sem::fail(ctx, SEM_EINVAL, "sem_cg_solve: tol must be > 0");
     *stats = sem_solve_stats_t{};
     const int check = opts->check_every > 0 ? opts->check_every : 16;
@@ -943,11 +961,12 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
     } else {
         Level& L = cg->lv32;
         const bool bf = cg->precision == SEM_SOLVE_BF16_IR;
-        if (opts->ir_mode == 1 && !cg->lp) {
-            int its = 0, nrep = 0, brk = 0;
+        if (opts->ir_mode == 1) {
+            int its = 0, nrep = 0, brk = 0, nj = 0;
             rc = rr_run(cg, L, opts->tol, opts->delta > 0 ? opts->delta : 0.1, maxit, check, bnorm, &its,
-                        &nrep, &brk, stats->relres_hist, 64);
+                        &nrep, &brk, stats->relres_hist, 64, &nj);
             if (rc) return rc;
+            stats->jacobi_steps = nj;
             stats->iterations = its + nrep;
             stats->outer = nrep;
             stats->breakdown = brk;

@@ -31,10 +31,13 @@ __device__ __forceinline__ u16 bf16_rne(float f) {
 __device__ __forceinline__ float bf16_f(u16 h) { return __uint_as_float((uint32_t)h << 16); }
 
 enum { EPI_BIAS = 1, EPI_RELU = 2, EPI_MASK = 4 };
-constexpr int BM = 128, BN = 128, BK = 32, LDK = BK + 8;
+constexpr int BM = 128, BN = 128, BK = 64, LDK = BK + 8;
 
 // C = A . B^T (+bias[n]) (relu) (*(mask[m][n] > 0)); Cf float and/or Cb bf16.
 // Requires K % 8 == 0, lda % 8 == 0, ldb % 8 == 0 and 16-byte aligned bases.
+// 128 x 128 tile per 256-thread workgroup, each wave 64 x 64 as 4 x 4
+// 16x16x32 MFMA blocks; the next 64-wide k-slab is fetched into registers
+// while the current one is multiplied out of LDS.
 __global__ void __launch_bounds__(256)
 gemm_nt(int M, int N, int K, const u16* __restrict__ A, int lda, const u16* __restrict__ B, int ldb,
         const float* __restrict__ bias, const u16* __restrict__ mask, int ldm,
@@ -51,37 +54,49 @@ gemm_nt(int M, int N, int K, const u16* __restrict__ A, int lda, const u16* __re
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // each thread moves 4 chunks of 8 bf16 of A and of B per slab
+    constexpr int CH = BM * BK / 8 / 256;
+    uint4 ra[CH], rb[CH];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int c = tid + q * 256;
+            const int row = c >> 3, kc = (c & 7) * 8;
+            const int gk = k0 + kc;
+            const int gm = m0 + row, gn = n0 + row;
+            ra[q] = (gm < M && gk < K) ? *reinterpret_cast<const uint4*>(A + (int64_t)gm * lda + gk)
+                                       : uint4{0u, 0u, 0u, 0u};
+            rb[q] = (gn < N && gk < K) ? *reinterpret_cast<const uint4*>(B + (int64_t)gn * ldb + gk)
+                                       : uint4{0u, 0u, 0u, 0u};
+        }
+    };
+    fetch(0);
     for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
-        for (int c = tid; c < BM * BK / 8; c += 256) {
-            const int row = c >> 2, kc = (c & 3) * 8;
-            const int gm = m0 + row, gk = k0 + kc;
-            uint4 v = {0u, 0u, 0u, 0u};
-            if (gm < M && gk < K) v = *reinterpret_cast<const uint4*>(A + (int64_t)gm * lda + gk);
-            *reinterpret_cast<uint4*>(sA + row * LDK + kc) = v;
-        }
-#pragma unroll
-        for (int c = tid; c < BN * BK / 8; c += 256) {
-            const int row = c >> 2, kc = (c & 3) * 8;
-            const int gn = n0 + row, gk = k0 + kc;
-            uint4 v = {0u, 0u, 0u, 0u};
-            if (gn < N && gk < K) v = *reinterpret_cast<const uint4*>(B + (int64_t)gn * ldb + gk);
-            *reinterpret_cast<uint4*>(sB + row * LDK + kc) = v;
+        for (int q = 0; q < CH; ++q) {
+            const int c = tid + q * 256;
+            const int row = c >> 3, kc = (c & 7) * 8;
+            *reinterpret_cast<uint4*>(sA + row * LDK + kc) = ra[q];
+            *reinterpret_cast<uint4*>(sB + row * LDK + kc) = rb[q];
         }
         __syncthreads();
-        bf16x8 af[4], bfv[4];
-        const int ko = (lane >> 4) * 8;
+        if (k0 + BK < K) fetch(k0 + BK);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            af[i] = *reinterpret_cast<const bf16x8*>(sA + (wm * 64 + i * 16 + (lane & 15)) * LDK + ko);
+        for (int kk = 0; kk < BK; kk += 32) {
+            bf16x8 af[4], bfv[4];
+            const int ko = kk + (lane >> 4) * 8;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            bfv[j] = *reinterpret_cast<const bf16x8*>(sB + (wn * 64 + j * 16 + (lane & 15)) * LDK + ko);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 4; ++i)
+                af[i] = *reinterpret_cast<const bf16x8*>(sA + (wm * 64 + i * 16 + (lane & 15)) * LDK + ko);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfv[j], acc[i][j], 0, 0, 0);
+                bfv[j] = *reinterpret_cast<const bf16x8*>(sB + (wn * 64 + j * 16 + (lane & 15)) * LDK + ko);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfv[j], acc[i][j], 0, 0, 0);
+        }
         __syncthreads();
     }
     // acc[i][j][q] = C[wm*64 + i*16 + 4*(lane/16) + q][wn*64 + j*16 + lane%16]
@@ -103,6 +118,22 @@ gemm_nt(int M, int N, int K, const u16* __restrict__ A, int lda, const u16* __re
                 if (Cb) Cb[(int64_t)m * ldc + n] = bf16_rne(v);
             }
         }
+}
+
+// C[r][c] = sum_k A[r][k] B[k][c] in float32 (small products of the weights)
+__global__ void matmul_f32(float* __restrict__ C, const float* __restrict__ A, const float* __restrict__ B,
+                           int rows, int inner, int cols, int lda, int ldb, int ldc) {
+    const int r = blockIdx.y, c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows || c >= cols) return;
+    float s = 0.f;
+    for (int k = 0; k < inner; ++k) s += A[(int64_t)r * lda + k] * B[(int64_t)k * ldb + c];
+    C[(int64_t)r * ldc + c] = s;
+}
+
+__global__ void f32_to_bf16(u16* __restrict__ out, const float* __restrict__ in, int64_t n) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        out[q] = bf16_rne(in[q]);
 }
 
 // out[c][r] = in[r][c] (bf16), rows x cols, leading dims ldi / ldo
@@ -382,8 +413,11 @@ struct sem_lp_s {
     u16* K = nullptr;
     float *dF = nullptr, *Kd = nullptr;
     u16* dB = nullptr;
-    // linear form: identity activations, no biases, geometric inputs zeroed
+    // linear form: identity activations, no biases, geometric inputs zeroed;
+    // inference then uses the folded matrix (W3 W2 W1)[:, :512] (bf16)
     bool linear = false;
+    float *T32 = nullptr, *Wf32 = nullptr;
+    u16* Wfb = nullptr;
     // Jacobi base: z = Minv r + network correction (Minv of the bound operator)
     bool jacobi_base = false;
     double* minv = nullptr;
@@ -427,6 +461,13 @@ int refresh_bf16(sem_lp_t lp) {
     weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W1b, kInPad, nullptr, lp->W[0], kHid, kIn);
     weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W2b, kHid, lp->W2t, lp->W[1], kHid, kHid);
     weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W3b, kHid, lp->W3t, lp->W[2], kOut, kHid);
+    if (lp->linear && lp->Wfb) {   // folded (W3 W2 W1)[:, :512] for inference
+        matmul_f32<<<dim3((kHid + 255) / 256, kOut), 256, 0, st>>>(lp->T32, lp->W[2], lp->W[1], kOut, kHid,
+                                                                   kHid, kHid, kHid, kHid);
+        matmul_f32<<<dim3((kOut + 255) / 256, kOut), 256, 0, st>>>(lp->Wf32, lp->T32, lp->W[0], kOut, kHid,
+                                                                   kOut, kHid, kIn, kOut);
+        f32_to_bf16<<<256, kBlock, 0, st>>>(lp->Wfb, lp->Wf32, (int64_t)kOut * kOut);
+    }
     SEM_LAUNCH_CHECK(lp->ctx);
     lp->dirty = false;
     return SEM_OK;
@@ -629,7 +670,22 @@ extern "C" int sem_lp_set_metric(sem_lp_t lp, double mu) {
 
 extern "C" int sem_lp_set_linear(sem_lp_t lp, int on) {
     if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_set_linear: null network");
+    int rc = sem::enter(lp->ctx);
+    if (rc) return rc;
     lp->linear = on != 0;
+    if (lp->linear && !lp->Wfb) {
+        void* p = nullptr;
+        rc = lp_alloc(lp, &p, 4 * (size_t)kOut * kHid);
+        if (rc) return rc;
+        lp->T32 = (float*)p;
+        rc = lp_alloc(lp, &p, 4 * (size_t)kOut * kOut);
+        if (rc) return rc;
+        lp->Wf32 = (float*)p;
+        rc = lp_alloc(lp, &p, 2 * (size_t)kOut * kOut);
+        if (rc) return rc;
+        lp->Wfb = (u16*)p;
+    }
+    lp->dirty = true;
     return SEM_OK;
 }
 
@@ -860,7 +916,14 @@ int lp_apply_t(sem_lp_t lp, T* z, const T* r, bool unique) {
                                                      nel, 0, lp->skip,
                                                      unique ? lp->gs->lid : nullptr);
     SEM_LAUNCH_CHECK(ctx);
-    int rc = forward(lp, lp->X, nel);
+    int rc;
+    if (lp->linear) {   // one product with the folded matrix
+        rc = refresh_bf16(lp);
+        if (!rc) rc = gemm(lp, (int)nel, kOut, kOut, lp->X, kInPad, lp->Wfb, kOut, nullptr, nullptr, 0,
+                           lp->Y3, nullptr, kOut, 0);
+    } else {
+        rc = forward(lp, lp->X, nel);
+    }
     if (rc) return rc;
     if (unique) {
         const int64_t nu = lp->gs->n_unique;

@@ -37,11 +37,11 @@ def _fields(ctx, nel, lx, seed=0):
     return dev(u), [dev(g) for g in G], dev(h1), D
 
 
-def run(reps=50):
+def run(reps=50, lxs=LXS, sizes=SIZES):
     ctx = B.sem_create()
     rows = []
-    for lx in LXS:
-        for nel in SIZES:
+    for lx in lxs:
+        for nel in sizes:
             u, G, h1, D = _fields(ctx, nel, lx)
             w = torch.empty_like(u)
             for _ in range(5):
@@ -69,10 +69,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=50)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--lx", default=None, help="comma-separated lx values (default 3..8)")
+    ap.add_argument("--sizes", default=None, help="comma-separated element counts")
     a = ap.parse_args()
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    rows = run(a.reps)
+    lxs = [int(v) for v in a.lx.split(",")] if a.lx else LXS
+    sizes = [int(v) for v in a.sizes.split(",")] if a.sizes else SIZES
+    rows = run(a.reps, lxs, sizes)
     if a.out:
         with open(a.out, "w") as f:
             json.dump(rows, f, indent=1)
