@@ -292,8 +292,13 @@ int sem_lp_get_step(sem_lp_t lp, int64_t* step);
 int sem_lp_set_metric(sem_lp_t lp, double mu);
 /* Linear form (on != 0): identity activations, biases unused (their
  * gradients are zero), geometric inputs zeroed.  The network output is then
- * W3 W2 W1 x and the preconditioner a fixed linear map of r (flexible CG keeps
- * its conjugacy); trained on white-noise residual/error pairs it approximates
+ * W x with W = W3 W2 W1 (the first 512 input columns), and inference applies
+ * the symmetric additive preconditioner
+ *     z = sum_e Q_e S_e W_s S_e Q_e^T r / kappa_e  (+ Minv r with the Jacobi base),
+ * W_s = (W + W^T) / 2 held in bfloat16, S_e = diag(mult^-1/2) on the element's
+ * nodes, kappa_e the element's stiffness scale: a fixed symmetric map of r, so
+ * CG's conjugacy holds.  Trained with the energy-norm loss
+ * (sem_lp_set_metric) on white-noise residual/error pairs it approximates
  * the element block of the inverse operator.  Applies to training and
  * inference from the next call on. */
 int sem_lp_set_linear(sem_lp_t lp, int on);
@@ -325,8 +330,16 @@ int sem_lp_adam(sem_lp_t lp, double lr, double beta1, double beta2, double eps);
  * Asynchronous. */
 int sem_lp_train_step(sem_lp_t lp, const uint16_t* X, const float* T, const int64_t* rows,
                       int64_t B, double lr, float* loss);
-/* z = P(r) on the bound operator; dtype SEM_F64 or SEM_F32 for both. */
+/* z = P(r) on the bound operator; dtype SEM_F64 or SEM_F32 for both.
+ * z and r are continuous fields in the local layout (nel * 512 values). */
 int sem_lp_apply(sem_lp_t lp, void* z, const void* r, sem_dtype_t dtype);
+/* The same on unique-node vectors of the bound plan (sem_gs_info's n_unique
+ * values, the layout sem_cg_solve iterates in): unique nodes are numbered in
+ * the order in which their global ids first appear in the local layout.  The linear form runs one
+ * fused kernel (gather of S r, bf16 MFMA product, CSR-ordered output) and an
+ * assembly pass.  Asynchronous; the network's workspace is shared with the
+ * other calls on lp, so calls on one lp must not overlap. */
+int sem_lp_apply_unique(sem_lp_t lp, void* z, const void* r, sem_dtype_t dtype);
 
 #ifdef __cplusplus
 }

@@ -21,12 +21,18 @@ the library adds around the paper's Poisson solve.  Readings taken:
     pins the element-wise constant the stiffness alone leaves free;
   * optimiser: Adam (Kingma and Ba 2015) with bias correction;
   * apply: z_e = (s_e / kappa_e) t_hat_e, then the partition-of-unity average
-    z = Q Q^T (z_local / mult) to make z continuous.
+    z = Q Q^T (z_local / mult) to make z continuous; the linear form instead
+    applies the symmetric part of its folded matrix with square-root
+    multiplicity weights on both sides (``apply_linear``), a symmetric
+    additive (one-level Schwarz-type) preconditioner.
 Pins (tests/test_oracle_mlp.py): backpropagation against central finite
 differences (both losses); Adam against its closed form for a constant
 gradient; the features' scale invariance; apply returns a continuous field;
 the reference metric is symmetric positive definite and its stiffness part
-gives the exact energy of polynomials of degree <= N on the reference cube.
+gives the exact energy of polynomials of degree <= N on the reference cube;
+the linear apply with an identity block returns r / kappa (partition of
+unity), is exactly symmetric for any weights, and is positive definite when
+the folded matrix's symmetric part is.
 """
 import numpy as np
 
@@ -128,13 +134,41 @@ def adam_step(params, grads, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8)
 
 
 def apply(params, r_local, G, h1, ids, n_unique, linear=False):
-    """Preconditioner z = Q Q^T (mult^-1 (s/kappa) NN(features(r))) on the
-    local layout (linear: geometric inputs zeroed, so z is linear in r)."""
+    """Preconditioner on the local layout.  Nonlinear form:
+    z = Q Q^T (mult^-1 (s/kappa) NN(features(r))).  Linear form: see
+    ``apply_linear``."""
     from .gs import gs, multiplicity
-    X, s, kappa = features(r_local, G, h1)
     if linear:
-        X[:, 512:] = 0.0
+        return apply_linear(params, r_local, G, h1, ids, n_unique)
+    X, s, kappa = features(r_local, G, h1)
     t = forward(params, X, linear)[2]
     z = (t * (s / kappa)[:, None]).reshape(r_local.shape)
     mult = multiplicity(ids, n_unique)
     return gs(z / mult, ids, n_unique)
+
+
+def folded_matrix(params, nloc):
+    """The linear form's map of the element residual: (W3 W2 W1)[:, :nloc]."""
+    W1, _, W2, _, W3, _ = params
+    return W3 @ (W2 @ W1[:, :nloc])
+
+
+def apply_linear(params, r_local, G, h1, ids, n_unique):
+    """Linear form as a symmetric additive preconditioner:
+    z = sum_e Q_e S_e W_s S_e Q_e^T r / kappa_e, with W_s the symmetric part
+    of the folded matrix and S_e = diag(mult^-1/2) on the element's nodes.
+    Since sum over the copies of a node of S^2 = 1, an identity W_s gives
+    z = r / kappa on a box of constant kappa; W_s symmetric (positive
+    definite) makes the preconditioner symmetric (positive definite), so CG's
+    conjugacy holds.  The network is trained on unweighted element pairs
+    (r_e, e_e); the white-noise optimum of that regression is the element
+    block of A^+, applied here with the square-root weights."""
+    from .gs import gs, multiplicity
+    E = r_local.shape[0]
+    nloc = r_local[0].size
+    W = folded_matrix(params, nloc)
+    Ws = 0.5 * (W + W.T)
+    _, _, kappa = features(r_local, G, h1)
+    S = 1.0 / np.sqrt(multiplicity(ids, n_unique).reshape(E, nloc))
+    z = ((S * r_local.reshape(E, nloc)) @ Ws.T) * S / kappa[:, None]
+    return gs(z.reshape(r_local.shape), ids, n_unique)

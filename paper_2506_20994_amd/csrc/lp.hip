@@ -137,6 +137,14 @@ __global__ void f32_to_bf16(u16* __restrict__ out, const float* __restrict__ in,
 }
 
 // out[c][r] = in[r][c] (bf16), rows x cols, leading dims ldi / ldo
+// out = bf16((in + in^T) / 2) for an n x n row-major matrix
+__global__ void sym_to_bf16(u16* __restrict__ out, const float* __restrict__ in, int n) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n * n; q += gridDim.x * blockDim.x) {
+        const int i = q / n, j = q % n;
+        out[q] = bf16_rne(0.5f * (in[q] + in[j * n + i]));
+    }
+}
+
 __global__ void transpose_bf16(u16* __restrict__ out, int ldo, const u16* __restrict__ in, int ldi,
                                int rows, int cols) {
     __shared__ u16 t[32][33];
@@ -292,14 +300,17 @@ __global__ void geo_kernel(float* __restrict__ geo, float* __restrict__ kappa,
 }
 
 // X[row] = [bf16(r_e / s_e) (512), geo (6), 0 (10)]; scale[row] = s_e / kappa_e;
-// optionally T[row] = err_e * kappa_e / s_e.  One wave per element.
+// optionally T[row] = err_e * kappa_e / s_e.  With uoff (unique layout) or mult
+// (local layout) the residual is first weighted by S = mult^-1/2 (the linear
+// form's symmetric apply).  One wave per element.
 template <typename T>
 __global__ void features_kernel(u16* __restrict__ X, float* __restrict__ scale, float* __restrict__ Tt,
                                 const T* __restrict__ r, const double* __restrict__ err,
                                 const double* __restrict__ minv,
                                 const float* __restrict__ geo, const float* __restrict__ kappa,
                                 const int64_t* __restrict__ elems, int64_t count, int64_t row0,
-                                const int* __restrict__ skip, const int32_t* __restrict__ lid) {
+                                const int* __restrict__ skip, const int32_t* __restrict__ lid,
+                                const int32_t* __restrict__ uoff, const double* __restrict__ mult) {
     if (skip && *skip) return;
     const int64_t q = blockIdx.x;
     if (q >= count) return;
@@ -311,7 +322,10 @@ __global__ void features_kernel(u16* __restrict__ X, float* __restrict__ scale, 
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const int64_t L = e * kOut + c * 64 + lane;
-        v[c] = (double)r[lid ? (int64_t)lid[L] : L];
+        const int64_t u = lid ? (int64_t)lid[L] : L;
+        v[c] = (double)r[u];
+        if (uoff) v[c] *= rsqrt((double)(uoff[u + 1] - uoff[u]));     // S = mult^-1/2
+        else if (mult) v[c] *= rsqrt(mult[L]);
         ss += v[c] * v[c];
     }
     ss = sem::wave_sum(ss);
@@ -332,29 +346,36 @@ __global__ void features_kernel(u16* __restrict__ X, float* __restrict__ scale, 
     }
 }
 
-// z_L = (scale[e] * Y3[e][node] (+ minv_L r_L)) / mult_L
+// z_L = (scale[e] * Y3[e][node] (+ minv_L r_L)) / mult_L, or with sym
+// z_L = scale[e] * Y3[e][node] / sqrt(mult_L) (+ minv_L r_L / mult_L)
 template <typename T>
 __global__ void lp_output_kernel(T* __restrict__ z, const float* __restrict__ Y3,
                                  const float* __restrict__ scale, const double* __restrict__ mult,
                                  const double* __restrict__ minv, const T* __restrict__ r,
-                                 int64_t n, const int* __restrict__ skip) {
+                                 int64_t n, const int* __restrict__ skip, bool sym) {
     if (skip && *skip) return;
     for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
          L += (int64_t)gridDim.x * blockDim.x) {
         double v = (double)scale[L / kOut] * (double)Y3[L];
+        if (sym) {     // S y + Minv r / mult; the gather-scatter sums the copies
+            v *= rsqrt(mult[L]);
+            if (minv) v += minv[L] * (double)r[L] / mult[L];
+            z[L] = (T)v;
+            continue;
+        }
         if (minv) v += minv[L] * (double)r[L];
         z[L] = (T)(v / mult[L]);
     }
 }
 
-// unique layout: z_u = mean over the copies L of u of scale[e(L)] Y3[L]
-// (+ Minv_u r_u with the Jacobi base)
+// unique layout: z_u = mean over the copies L of u of scale[e(L)] Y3[L], or with
+// sym their sum weighted by mult_u^-1/2 (+ Minv_u r_u with the Jacobi base)
 template <typename T>
 __global__ void lp_output_unique_kernel(T* __restrict__ z, const float* __restrict__ Y3,
                                         const float* __restrict__ scale, const double* __restrict__ minv,
                                         const T* __restrict__ r, const int32_t* __restrict__ uoff,
                                         const int32_t* __restrict__ uidx, int64_t nu,
-                                        const int* __restrict__ skip) {
+                                        const int* __restrict__ skip, bool sym) {
     if (skip && *skip) return;
     for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < nu;
          u += (int64_t)gridDim.x * blockDim.x) {
@@ -364,10 +385,207 @@ __global__ void lp_output_unique_kernel(T* __restrict__ z, const float* __restri
             const int32_t L = uidx[q];
             s += (double)scale[L / kOut] * (double)Y3[L];
         }
-        s /= (double)(e - b);
+        s *= sym ? rsqrt((double)(e - b)) : 1.0 / (double)(e - b);
         if (minv) s += minv[uidx[b]] * (double)r[u];
         z[u] = (T)s;
     }
+}
+
+// ---- linear form on unique-layout vectors ----------------------------------
+// zl[upos[L]] = (1/kappa_e) sum_k Ws[n][k] S_k r_k for every local node
+// L = (e, n) of an element, with S = mult^-1/2 per unique node (sq) and Ws the
+// symmetric folded matrix, so that summing zl over the copies of a node and
+// weighting by S gives the symmetric additive preconditioner.  Three passes:
+// a gather of S r into element-major bf16 rows (many waves, so the dependent
+// index -> value loads overlap), the product, and the assembly.  The product
+// takes 64 elements per 256-thread block, 16 per wave as the rows of 16x16x32
+// bf16 MFMA blocks: a wave keeps its 16 x 512 residual block in registers and
+// its 16 x 512 outputs in 32 accumulator tiles while Ws streams through LDS in
+// 32-wide k-slabs, the next slab fetched into registers during the current
+// one's products.  The outputs land in CSR order, where the assembly reads
+// each node's copies contiguously.
+constexpr int kLinBK = 32, kLinSlabs = kOut / kLinBK;
+
+__device__ __forceinline__ bf16x8 pack_bf16x8(const float* v) {
+    uint4 w;
+    w.x = (uint32_t)bf16_rne(v[0]) | ((uint32_t)bf16_rne(v[1]) << 16);
+    w.y = (uint32_t)bf16_rne(v[2]) | ((uint32_t)bf16_rne(v[3]) << 16);
+    w.z = (uint32_t)bf16_rne(v[4]) | ((uint32_t)bf16_rne(v[5]) << 16);
+    w.w = (uint32_t)bf16_rne(v[6]) | ((uint32_t)bf16_rne(v[7]) << 16);
+    return __builtin_bit_cast(bf16x8, w);
+}
+
+// X[e][n] = bf16(S r) at the unique node of local node (e, n); 8 nodes per thread
+template <typename T>
+__global__ void lin_gather_kernel(u16* __restrict__ X, const T* __restrict__ r, const float* __restrict__ sq,
+                                  const int32_t* __restrict__ lid, int64_t n8, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n8;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t L = t * 8;
+        const int4 i0 = *reinterpret_cast<const int4*>(lid + L);
+        const int4 i1 = *reinterpret_cast<const int4*>(lid + L + 4);
+        float v[8];
+        v[0] = (float)r[i0.x] * sq[i0.x];
+        v[1] = (float)r[i0.y] * sq[i0.y];
+        v[2] = (float)r[i0.z] * sq[i0.z];
+        v[3] = (float)r[i0.w] * sq[i0.w];
+        v[4] = (float)r[i1.x] * sq[i1.x];
+        v[5] = (float)r[i1.y] * sq[i1.y];
+        v[6] = (float)r[i1.z] * sq[i1.z];
+        v[7] = (float)r[i1.w] * sq[i1.w];
+        *reinterpret_cast<bf16x8*>(X + (L / kOut) * kInPad + (L % kOut)) = pack_bf16x8(v);
+    }
+}
+
+// zl[upos[L]] = (1/kappa_e) (Ws X_e)_n for every local node L = (e, n).
+// Weight-stationary: block b owns half of Ws's rows (256 output nodes), each of
+// its 8 waves 32 of them, held for the whole kernel as the B fragments of
+// 16x16x32 bf16 MFMA blocks (128 registers).  The block walks over 16-element
+// chunks of X (chunks g, g + groups, ...), staged through a double-buffered LDS
+// tile with a kWsDepth-deep register prefetch; the outputs' CSR positions and
+// scales are fetched one chunk ahead.  The two halves of a group run 8 block
+// indices apart, on the same XCD, so a chunk of X is read from HBM once.
+constexpr int kWsChunk = 16, kWsLd = kOut + 8, kWsDepth = 3, kWsGroupsMax = 128;
+
+__device__ __forceinline__ void ws_load_chunk(uint4& lo, uint4& hi, const u16* __restrict__ X, int64_t c,
+                                              int64_t nchunks, int64_t nel, int se, int sk) {
+    const int64_t e = c * kWsChunk + se;
+    if (c < nchunks && e < nel) {
+        const u16* p = X + e * kInPad + sk;
+        lo = *reinterpret_cast<const uint4*>(p);
+        hi = *reinterpret_cast<const uint4*>(p + 8);
+    } else {
+        lo = uint4{0u, 0u, 0u, 0u};
+        hi = lo;
+    }
+}
+
+__device__ __forceinline__ void ws_load_pos(int32_t (&pos)[2][4], float (&kinv)[4], const int32_t* __restrict__ upos,
+                                            const float* __restrict__ kappa, int64_t c, int64_t nel, int grp,
+                                            int col) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        int64_t e = c * kWsChunk + 4 * grp + j;
+        e = e < nel ? e : nel - 1;        // rows past the end read valid data and are not stored
+        kinv[j] = 1.f / kappa[e];
+        pos[0][j] = upos[e * kOut + col];
+        pos[1][j] = upos[e * kOut + col + 16];
+    }
+}
+
+// One chunk: positions of the chunk after it, products out of LDS buffer
+// `buf`, stores; then the chunk `groups` ahead (held in lo/hi since two steps
+// ago) goes to the other buffer and lo/hi start fetching the chunk three steps
+// ahead.  Two register sets alternate between consecutive steps.
+__device__ __forceinline__ void ws_step(float* __restrict__ zl, const u16* __restrict__ X,
+                                        const int32_t* __restrict__ upos, const float* __restrict__ kappa,
+                                        u16 (*sx)[kWsChunk * kWsLd], const bf16x8 (&w)[kLinSlabs][2],
+                                        int64_t c, int buf, int64_t groups, int64_t nchunks, int64_t nel,
+                                        uint4& lo, uint4& hi, const int32_t (&pos)[2][4], const float (&kinv)[4],
+                                        int32_t (&pnext)[2][4], float (&knext)[4], int row, int grp, int col,
+                                        int se, int sk) {
+    ws_load_pos(pnext, knext, upos, kappa, c + groups, nel, grp, col);
+    f32x4 acc0 = f32x4{0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+    const u16* xs = sx[buf] + row * kWsLd + 8 * grp;
+#pragma unroll
+    for (int kb = 0; kb < kLinSlabs; ++kb) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(xs + kb * kLinBK);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w[kb][0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w[kb][1], acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (c * kWsChunk + 4 * grp + j < nel) {
+            zl[pos[0][j]] = acc0[j] * kinv[j];
+            zl[pos[1][j]] = acc1[j] * kinv[j];
+        }
+    }
+    *reinterpret_cast<uint4*>(sx[buf ^ 1] + se * kWsLd + sk) = lo;
+    *reinterpret_cast<uint4*>(sx[buf ^ 1] + se * kWsLd + sk + 8) = hi;
+    ws_load_chunk(lo, hi, X, c + 3 * groups, nchunks, nel, se, sk);
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+lin_gemm_kernel(float* __restrict__ zl, const u16* __restrict__ X, const int32_t* __restrict__ upos,
+                const float* __restrict__ kappa, const u16* __restrict__ Ws, int64_t nel, int groups,
+                const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    __shared__ __attribute__((aligned(16))) u16 sx[2][kWsChunk * kWsLd];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row = lane & 15, grp = lane >> 4;
+    const int b = blockIdx.x;
+    const int half = (b >> 3) & 1;
+    const int64_t g = (b & 7) + 8 * (b >> 4);
+    const int64_t nchunks = (nel + kWsChunk - 1) / kWsChunk;
+    if (g >= nchunks) return;                 // uniform over the block, before any barrier
+    const int col = half * 256 + wave * 32 + row;   // this lane's output node (and col + 16)
+
+    bf16x8 w[kLinSlabs][2];
+#pragma unroll
+    for (int kb = 0; kb < kLinSlabs; ++kb)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+            w[kb][t] = *reinterpret_cast<const bf16x8*>(Ws + (int64_t)(col - row + 16 * t + row) * kOut +
+                                                        kb * kLinBK + 8 * grp);
+
+    const int se = tid >> 5, sk = (tid & 31) * 16;   // staging: element se, columns sk .. sk + 15
+    uint4 lo0, hi0, lo1, hi1;
+    {
+        uint4 lo, hi;
+        ws_load_chunk(lo, hi, X, g, nchunks, nel, se, sk);
+        ws_load_chunk(lo0, hi0, X, g + groups, nchunks, nel, se, sk);
+        ws_load_chunk(lo1, hi1, X, g + 2 * groups, nchunks, nel, se, sk);
+        *reinterpret_cast<uint4*>(sx[0] + se * kWsLd + sk) = lo;
+        *reinterpret_cast<uint4*>(sx[0] + se * kWsLd + sk + 8) = hi;
+    }
+    int32_t pos0[2][4], pos1[2][4];
+    float kinv0[4], kinv1[4];
+    ws_load_pos(pos0, kinv0, upos, kappa, g, nel, grp, col);
+    __syncthreads();
+
+    for (int64_t c = g; c < nchunks; c += 2 * groups) {
+        ws_step(zl, X, upos, kappa, sx, w, c, 0, groups, nchunks, nel, lo0, hi0, pos0, kinv0, pos1, kinv1,
+                row, grp, col, se, sk);
+        if (c + groups >= nchunks) break;     // uniform over the block
+        ws_step(zl, X, upos, kappa, sx, w, c + groups, 1, groups, nchunks, nel, lo1, hi1, pos1, kinv1, pos0,
+                kinv0, row, grp, col, se, sk);
+    }
+}
+
+// z_u = S_u sum over the CSR segment of u of zl (+ Minv_u r_u with the Jacobi
+// base, Minv on unique nodes)
+template <typename T>
+__global__ void lin_assemble_kernel(T* __restrict__ z, const float* __restrict__ zl,
+                                    const double* __restrict__ minvu, const T* __restrict__ r,
+                                    const int32_t* __restrict__ uoff, int64_t nu,
+                                    const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < nu;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = uoff[u], e = uoff[u + 1];
+        float s = 0.f;
+        for (int32_t q = b; q < e; ++q) s += zl[q];
+        double v = (double)s * rsqrt((double)(e - b));
+        if (minvu) v += minvu[u] * (double)r[u];
+        z[u] = (T)v;
+    }
+}
+
+// unique-layout copy of a continuous local field: out[u] = in[uidx[uoff[u]]]
+__global__ void first_copy_kernel(double* __restrict__ out, const double* __restrict__ in,
+                                  const int32_t* __restrict__ uoff, const int32_t* __restrict__ uidx,
+                                  int64_t nu) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < nu;
+         u += (int64_t)gridDim.x * blockDim.x)
+        out[u] = in[uidx[uoff[u]]];
+}
+
+__global__ void sq_kernel(float* __restrict__ sq, const int32_t* __restrict__ uoff, int64_t nu) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < nu;
+         u += (int64_t)gridDim.x * blockDim.x)
+        sq[u] = (float)(1.0 / sqrt((double)(uoff[u + 1] - uoff[u])));
 }
 
 __global__ void zero_f32(float* __restrict__ x, int n) {
@@ -422,6 +640,10 @@ struct sem_lp_s {
     bool jacobi_base = false;
     double* minv = nullptr;
     int64_t minv_n = 0;
+    float* sq = nullptr;      // mult^-1/2 per unique node of the bound plan
+    int64_t sq_n = 0;
+    double* minvu = nullptr;  // Minv on the unique nodes of the bound plan (Jacobi base)
+    int64_t minvu_n = 0;
     std::vector<void*> allocs;
 };
 
@@ -461,12 +683,12 @@ int refresh_bf16(sem_lp_t lp) {
     weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W1b, kInPad, nullptr, lp->W[0], kHid, kIn);
     weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W2b, kHid, lp->W2t, lp->W[1], kHid, kHid);
     weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W3b, kHid, lp->W3t, lp->W[2], kOut, kHid);
-    if (lp->linear && lp->Wfb) {   // folded (W3 W2 W1)[:, :512] for inference
+    if (lp->linear && lp->Wfb) {   // symmetric part of the folded (W3 W2 W1)[:, :512] for inference
         matmul_f32<<<dim3((kHid + 255) / 256, kOut), 256, 0, st>>>(lp->T32, lp->W[2], lp->W[1], kOut, kHid,
                                                                    kHid, kHid, kHid, kHid);
         matmul_f32<<<dim3((kOut + 255) / 256, kOut), 256, 0, st>>>(lp->Wf32, lp->T32, lp->W[0], kOut, kHid,
                                                                    kOut, kHid, kIn, kOut);
-        f32_to_bf16<<<256, kBlock, 0, st>>>(lp->Wfb, lp->Wf32, (int64_t)kOut * kOut);
+        sym_to_bf16<<<256, kBlock, 0, st>>>(lp->Wfb, lp->Wf32, kOut);
     }
     SEM_LAUNCH_CHECK(lp->ctx);
     lp->dirty = false;
@@ -725,6 +947,15 @@ extern "C" int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs) {
     geo_kernel<<<(unsigned)A->nel, 64, 0, ctx->stream>>>(lp->geo, lp->kappa, A->h1, A->g11, A->g22, A->g33,
                                                          A->g12, A->g13, A->g23, A->nel);
     SEM_LAUNCH_CHECK(ctx);
+    if (lp->sq_n < gs->n_unique) {
+        void* p = nullptr;
+        rc = lp_alloc(lp, &p, 4 * (size_t)gs->n_unique);
+        if (rc) return rc;
+        lp->sq = (float*)p;
+        lp->sq_n = gs->n_unique;
+    }
+    sq_kernel<<<grid_of(gs->n_unique), kBlock, 0, ctx->stream>>>(lp->sq, gs->uoff, gs->n_unique);
+    SEM_LAUNCH_CHECK(ctx);
     if (lp->jacobi_base) {
         const int64_t n = A->nel * kOut;
         if (lp->minv_n < n) {
@@ -740,6 +971,16 @@ extern "C" int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs) {
         rc = sem_gs(gs, lp->minv, SEM_F64);
         if (rc) return rc;
         inv_kernel<<<grid_of(n), kBlock, 0, ctx->stream>>>(lp->minv, n);
+        SEM_LAUNCH_CHECK(ctx);
+        if (lp->minvu_n < gs->n_unique) {
+            void* p = nullptr;
+            rc = lp_alloc(lp, &p, 8 * (size_t)gs->n_unique);
+            if (rc) return rc;
+            lp->minvu = (double*)p;
+            lp->minvu_n = gs->n_unique;
+        }
+        first_copy_kernel<<<grid_of(gs->n_unique), kBlock, 0, ctx->stream>>>(lp->minvu, lp->minv, gs->uoff,
+                                                                             gs->uidx, gs->n_unique);
         SEM_LAUNCH_CHECK(ctx);
     }
     return SEM_OK;
@@ -758,7 +999,8 @@ extern "C" int sem_lp_samples(sem_lp_t lp, const double* r, const double* err, c
     features_kernel<double><<<(unsigned)count, 64, 0, ctx->stream>>>(X, nullptr, T, r, err,
                                                                       lp->jacobi_base ? lp->minv : nullptr,
                                                                       lp->linear ? nullptr : lp->geo, lp->kappa,
-                                                                      elems, count, row0, nullptr, nullptr);
+                                                                      elems, count, row0, nullptr, nullptr,
+                                                                      nullptr, nullptr);
     SEM_LAUNCH_CHECK(ctx);
     return SEM_OK;
 }
@@ -911,10 +1153,30 @@ int lp_apply_t(sem_lp_t lp, T* z, const T* r, bool unique) {
     sem_ctx_t ctx = lp->ctx;
     hipStream_t st = ctx->stream;
     const int64_t nel = lp->nel;
+    if (unique && lp->linear) {   // fused product and CSR-ordered output, then assembly
+        int rc = refresh_bf16(lp);
+        if (rc) return rc;
+        lin_gather_kernel<T><<<grid_of(nel * kOut / 8, 8192), kBlock, 0, st>>>(lp->X, r, lp->sq, lp->gs->lid,
+                                                                           nel * kOut / 8, lp->skip);
+        SEM_LAUNCH_CHECK(ctx);
+        const int64_t nchunks = (nel + kWsChunk - 1) / kWsChunk;
+        const int groups = (int)std::min<int64_t>(kWsGroupsMax, (nchunks + 7) / 8 * 8);
+        lin_gemm_kernel<<<(unsigned)(2 * groups), 512, 0, st>>>(lp->Y3, lp->X, lp->gs->upos, lp->kappa, lp->Wfb,
+                                                                nel, groups, lp->skip);
+        SEM_LAUNCH_CHECK(ctx);
+        const int64_t nu = lp->gs->n_unique;
+        lin_assemble_kernel<T><<<grid_of(nu, 8192), kBlock, 0, st>>>(z, lp->Y3,
+                                                                     lp->jacobi_base ? lp->minvu : nullptr, r,
+                                                                     lp->gs->uoff, nu, lp->skip);
+        SEM_LAUNCH_CHECK(ctx);
+        return SEM_OK;
+    }
     features_kernel<T><<<(unsigned)nel, 64, 0, st>>>(lp->X, lp->scale, nullptr, r, nullptr, nullptr,
                                                      lp->linear ? nullptr : lp->geo, lp->kappa, nullptr,
                                                      nel, 0, lp->skip,
-                                                     unique ? lp->gs->lid : nullptr);
+                                                     unique ? lp->gs->lid : nullptr,
+                                                     lp->linear && unique ? lp->gs->uoff : nullptr,
+                                                     lp->linear && !unique ? lp->gs->mult : nullptr);
     SEM_LAUNCH_CHECK(ctx);
     int rc;
     if (lp->linear) {   // one product with the folded matrix
@@ -929,13 +1191,14 @@ int lp_apply_t(sem_lp_t lp, T* z, const T* r, bool unique) {
         const int64_t nu = lp->gs->n_unique;
         lp_output_unique_kernel<T><<<grid_of(nu), kBlock, 0, st>>>(
             z, lp->Y3, lp->scale, lp->jacobi_base ? lp->minv : nullptr, r, lp->gs->uoff, lp->gs->uidx,
-            nu, lp->skip);
+            nu, lp->skip, lp->linear);
         SEM_LAUNCH_CHECK(ctx);
         return SEM_OK;
     }
     const int64_t n = nel * kOut;
     lp_output_kernel<T><<<grid_of(n), kBlock, 0, st>>>(z, lp->Y3, lp->scale, lp->gs->mult,
-                                                       lp->jacobi_base ? lp->minv : nullptr, r, n, lp->skip);
+                                                       lp->jacobi_base ? lp->minv : nullptr, r, n, lp->skip,
+                                                       lp->linear);
     SEM_LAUNCH_CHECK(ctx);
     return gs_launch(lp->gs, z, sizeof(T) == 8 ? SEM_F64 : SEM_F32, lp->skip);
 }
@@ -961,4 +1224,13 @@ extern "C" int sem_lp_apply(sem_lp_t lp, void* z, const void* r, sem_dtype_t dty
     if (!z || !r || (dtype != SEM_F64 && dtype != SEM_F32))
         return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_apply: bad argument");
     return sem::lp_apply(lp, z, r, dtype == SEM_F64, nullptr, false);
+}
+
+extern "C" int sem_lp_apply_unique(sem_lp_t lp, void* z, const void* r, sem_dtype_t dtype) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_apply_unique: null network");
+    int rc = sem::enter(lp->ctx);
+    if (rc) return rc;
+    if (!z || !r || z == r || (dtype != SEM_F64 && dtype != SEM_F32))
+        return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_apply_unique: bad argument");
+    return sem::lp_apply(lp, z, r, dtype == SEM_F64, nullptr, true);
 }

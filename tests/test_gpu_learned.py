@@ -190,6 +190,66 @@ def test_apply_matches_oracle(sem_ctx):
     lp.close()
 
 
+def test_apply_linear_form_matches_oracle(sem_ctx):
+    """Linear form: the symmetric part of the folded matrix applied with
+    mult^-1/2 weights on both sides, local layout, float64 and float32."""
+    n, amp = 2, 0.1
+    op, lp = _box_with_lp(sem_ctx, n, amp)
+    params = _params(52)
+    P.sem_lp_set_linear(lp, 1)
+    _load(lp, params)
+    ref = BoxProblem(n, 8, amp)
+    rG = synth.unique_normal(ref.nu, 53)
+    f32 = [q.astype(np.float32).astype(np.float64) for q in params]
+    zref = mlp.apply_linear(f32, rG[ref.ids], ref.G, None, ref.ids, ref.nu)
+    for dt in (torch.float64, torch.float32):
+        r = op.scatter(rG).to(dt)
+        z = torch.empty_like(r)
+        P.sem_lp_apply(lp, z, r)
+        torch.cuda.synchronize()
+        assert _nrm(z.double().cpu().numpy(), zref) <= GRAD_TOL
+    lp.close()
+
+
+@pytest.mark.parametrize("n,jb", [(3, False), (5, True)])
+def test_apply_unique_linear_form_matches_oracle(sem_ctx, n, jb):
+    """Fused linear-form apply on unique-node vectors (27 and 125 elements: a
+    partial and a ragged 64-element block), float64 and float32, with and
+    without the Jacobi base, against the oracle's symmetric apply."""
+    amp = 0.1
+    op = BoxOperator(sem_ctx, n, 8, amp)
+    lp = P.sem_lp_create(sem_ctx, op.nel)
+    P.sem_lp_set_linear(lp, 1)
+    P.sem_lp_set_jacobi_base(lp, int(jb))
+    op.bind(lp)
+    params = _params(54)
+    _load(lp, params)
+    ref = BoxProblem(n, 8, amp)
+    rG = synth.unique_normal(ref.nu, 55)
+    f32 = [q.astype(np.float32).astype(np.float64) for q in params]
+    zl = mlp.apply_linear(f32, rG[ref.ids], ref.G, None, ref.ids, ref.nu)
+    zref = np.zeros(ref.nu)
+    zref[ref.ids.ravel()] = zl.ravel()
+    if jb:
+        zref += rG / ref.diagonal()
+    # the plan numbers unique nodes in order of first appearance in the local layout
+    _, first = np.unique(ref.ids.ravel(), return_index=True)
+    plan_of = np.empty(ref.nu, dtype=np.int64)
+    plan_of[np.argsort(first)] = np.arange(ref.nu)
+    rp = np.empty(ref.nu)
+    rp[plan_of] = rG
+    for dt in (torch.float64, torch.float32):
+        r = torch.from_numpy(rp).to(dt).cuda()
+        z = torch.full_like(r, float("nan"))
+        P.sem_lp_apply_unique(lp, z, r)
+        torch.cuda.synchronize()
+        zg = z.double().cpu().numpy()[plan_of]
+        assert np.all(np.isfinite(zg))
+        assert _nrm(zg, zref) <= GRAD_TOL
+    lp.close()
+    op.gs.close()
+
+
 def _train(lp, X, T, steps, seed, B=64):
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     out = []
@@ -260,10 +320,11 @@ def test_fcg_falls_back_to_jacobi(sem_ctx, kind):
         h.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_fcg_untrained_network_converges(sem_ctx, prec):
+@pytest.mark.parametrize("prec,linear", [(0, False), (1, False), (0, True), (1, True)])
+def test_fcg_untrained_network_converges(sem_ctx, prec, linear):
     n, amp = 3, 0.1
     op, lp = _box_with_lp(sem_ctx, n, amp)
+    P.sem_lp_set_linear(lp, int(linear))
     _load(lp, _params(80))
     k, a, ph = synth.fourier_modes(3)
     b = op.fourier_rhs(k, a, ph)

@@ -105,3 +105,62 @@ def test_linear_form_is_linear():
     x1, x2 = r.standard_normal((4, 10)), r.standard_normal((4, 10))
     f = lambda x: mlp.forward(params, x, linear=True)[2]  # noqa: E731
     np.testing.assert_allclose(f(2.0 * x1 - 3.0 * x2), 2.0 * f(x1) - 3.0 * f(x2), atol=1e-12)
+
+
+def _identity_params(nloc, ngeo=6):
+    W1 = np.zeros((nloc, nloc + ngeo))
+    W1[:, :nloc] = np.eye(nloc)
+    W1[:, nloc:] = 1.0      # geometric inputs do not enter the linear form
+    return [W1, np.ones(nloc), np.eye(nloc), np.ones(nloc), np.eye(nloc), np.ones(nloc)]
+
+
+@pytest.mark.parametrize("amp", [0.0, 0.15])
+def test_linear_apply_identity_block_is_partition_of_unity(amp):
+    """An identity folded matrix gives z_u = r_u * mean_{e containing u} 1/kappa_e
+    (sum over copies of S^2 = 1): r / kappa on the undeformed box."""
+    lx = 4
+    P = BoxProblem(2, lx, amp)
+    rG = synth.unique_normal(P.nu, 11)
+    z = mlp.apply_linear(_identity_params(lx ** 3), scatter(rG, P.ids), P.G, None, P.ids, P.nu)
+    _, _, kappa = mlp.features(scatter(rG, P.ids), P.G)
+    inv_k = np.zeros(P.nu)
+    cnt = np.zeros(P.nu)
+    for e in range(P.ids.shape[0]):
+        np.add.at(inv_k, P.ids[e].ravel(), 1.0 / kappa[e])
+        np.add.at(cnt, P.ids[e].ravel(), 1.0)
+    expect = rG * inv_k / cnt
+    np.testing.assert_allclose(z, expect[P.ids], rtol=1e-13, atol=0)
+    if amp == 0.0:
+        assert np.ptp(kappa) <= 1e-14 * kappa[0]
+        np.testing.assert_allclose(z, scatter(rG / kappa[0], P.ids), rtol=1e-13)
+
+
+def _dense_precond(params, P):
+    cols = []
+    for j in range(P.nu):
+        ej = np.zeros(P.nu)
+        ej[j] = 1.0
+        z = mlp.apply_linear(params, scatter(ej, P.ids), P.G, None, P.ids, P.nu)
+        zu = np.zeros(P.nu)
+        zu[P.ids.ravel()] = z.ravel()
+        cols.append(zu)
+    return np.array(cols).T
+
+
+def test_linear_apply_symmetric_and_positive_definite():
+    """The linear apply is an exactly symmetric operator for any weights, and
+    positive definite when the folded matrix is (W = C^T C)."""
+    lx = 3
+    nloc = lx ** 3
+    P = BoxProblem(2, lx, 0.1)
+    r = np.random.default_rng(3)
+    params = [r.standard_normal(p.shape) for p in synth.mlp_init(5, (nloc + 6, 9, 9, nloc))]
+    M = _dense_precond(params, P)
+    assert np.linalg.norm(M - M.T) <= 1e-13 * np.linalg.norm(M)
+    W = mlp.folded_matrix(params, nloc)
+    assert np.linalg.norm(W - W.T) >= 0.1 * np.linalg.norm(W)     # the weights are not symmetric
+    C = r.standard_normal((nloc, nloc))
+    W1 = np.concatenate([C, r.standard_normal((nloc, 6))], axis=1)
+    spd = [W1, np.zeros(nloc), np.eye(nloc), np.zeros(nloc), C.T.copy(), np.zeros(nloc)]
+    ev = np.linalg.eigvalsh(_dense_precond(spd, P))
+    assert ev[0] > 1e-8 * ev[-1]
