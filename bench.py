@@ -18,9 +18,11 @@ Extra fields:
                 float64 refinement with float32 and with bfloat16-factor inner
                 solves, restarted (_ir) and by residual replacement (_rr); wall
                 time of sem_cg_solve (set-up excluded).
-  learned       the per-element network trained on the GPU from float64
-                Jacobi-PCG snapshot pairs on 16^3 boxes, then used in flexible CG
-                on the same 32^3 solve.
+  learned       the per-element network (linear form, energy-norm loss) trained
+                on the GPU from float64 Jacobi-PCG residual/error pairs on 16^3
+                boxes, then used as a symmetric additive preconditioner inside
+                flexible CG on the same 32^3 solve, in float64 and inside float64
+                residual replacement around float32 / bfloat16-factor iterations.
 
 --mode copy times a plain 1 GiB device copy (used to calibrate the HBM byte
 counters of rocprofv3); it prints nothing on stdout.
@@ -111,25 +113,28 @@ def solve_comparison(ctx, P, n, lx, amp, tol=1e-10):
     return res
 
 
-def learned_comparison(ctx, P, n, lx, amp, tol=1e-10):
-    """Train the per-element network on snapshot pairs from float64 Jacobi-PCG
-    solves on 16^3 boxes (random amplitudes, white-noise right-hand sides),
-    then solve the held-out box with flexible CG + network (float64, and
-    float32 refinement) against Jacobi-PCG."""
+def learned_comparison(ctx, P, n, lx, amp, solve=None, tol=1e-10):
+    """Train the per-element network (linear form, energy-norm loss, Jacobi
+    base) on the GPU from float64 Jacobi-PCG pairs on 16^3 boxes (random
+    amplitudes U[0, 0.2], white-noise right-hand sides: residual b, error x*),
+    then solve the held-out box with flexible CG + network: float64, and float64
+    refinement by residual replacement around float32 / bfloat16-factor inner
+    iterations, against float64 Jacobi-PCG."""
     import torch
     import synth
     from paper_2506_20994_amd.box import BoxOperator
     from paper_2506_20994_amd import learned as LR
     lp = P.sem_lp_create(ctx, n ** 3)
-    LR.init_network(lp, 7, mu=-1.0, jacobi_base=True, out_scale=0.1)
+    LR.init_network(lp, 7, mu=1.0, jacobi_base=True, out_scale=0.0, linear=True)
     t0 = time.perf_counter()
-    X, T, info = LR.generate(ctx, lp, n=16, boxes=16, snapshots=16, elems_per_snapshot=256,
+    X, T, info = LR.generate(ctx, lp, n=16, boxes=64, snapshots=1, elems_per_snapshot=4096,
                              rhs="noise", include_zero=True)
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    hist = LR.train(lp, X, T, epochs=10, batch=1024, lr=1e-3)
+    hist = LR.train(lp, X, T, epochs=60, batch=1024, lr=3e-4)
     t_train = time.perf_counter() - t0
     del X, T
+    torch.cuda.empty_cache()
     op = BoxOperator(ctx, n, lx, amp)
     k, a, ph = synth.fourier_modes(2)
     b = op.fourier_rhs(k, a, ph)
@@ -139,12 +144,14 @@ def learned_comparison(ctx, P, n, lx, amp, tol=1e-10):
                         "rejected_amplitude_draws": info["rejected_draws"],
                         "datagen_s": round(t_gen, 2), "train_s": round(t_train, 2),
                         "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}}
-    for name, code, use in (("jacobi_pcg_f64", P.SEM_SOLVE_F64, False),
-                            ("learned_fcg_f64", P.SEM_SOLVE_F64, True),
-                            ("learned_fcg_f32_ir", P.SEM_SOLVE_F32_IR, True)):
-        kw = dict(tol=tol, precision=code, learned=lp if use else None, maxit=50000,
-                  inner_maxit=5000)
+    variants = (("jacobi_pcg_f64", P.SEM_SOLVE_F64, 0, False),
+                ("learned_fcg_f64", P.SEM_SOLVE_F64, 0, True),
+                ("learned_f32_rr", P.SEM_SOLVE_F32_IR, 1, True),
+                ("learned_bf16_rr", P.SEM_SOLVE_BF16_IR, 1, True))
+    for name, code, mode, use in variants:
+        kw = dict(tol=tol, precision=code, ir_mode=mode, learned=lp if use else None, maxit=50000)
         cg = op.solver(code, learned=lp if use else None)
+        P.sem_cg_solve(cg, x, b, **kw)                    # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rc, st = P.sem_cg_solve(cg, x, b, **kw)
@@ -156,7 +163,14 @@ def learned_comparison(ctx, P, n, lx, amp, tol=1e-10):
         print(f"[bench] learned {name}: {ms:.1f} ms, {st['iterations']} its, "
               f"{st['jacobi_steps']} Jacobi, fell back {st['fell_back']}", file=sys.stderr, flush=True)
         cg.close()
+    base = res["jacobi_pcg_f64"]["ms"]
+    res["speedup_vs_fp64_pcg"] = {v[0]: round(base / res[v[0]]["ms"], 3) for v in variants[1:]}
+    if solve:    # the same precision without the network: what the network adds
+        res["speedup_vs_same_precision_without_network"] = {
+            "f32_rr": round(solve["f32_rr"]["ms"] / res["learned_f32_rr"]["ms"], 3),
+            "bf16_rr": round(solve["bf16_rr"]["ms"] / res["learned_bf16_rr"]["ms"], 3)}
     lp.close()
+    op.gs.close()
     return res
 
 
@@ -272,7 +286,7 @@ def main():
         torch.cuda.empty_cache()
         out["solve"] = solve_comparison(ctx, P, n, lx, amp)
         if not args.no_learned and lx == 8:
-            out["learned"] = learned_comparison(ctx, P, n, lx, amp)
+            out["learned"] = learned_comparison(ctx, P, n, lx, amp, solve=out["solve"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(lx)
     print(json.dumps(out), flush=True)

@@ -3,7 +3,7 @@ float64 Jacobi-PCG solves, minibatch training, held-out evaluation.
 
 Orchestration only: every array is produced by libsem.so kernels (mesh,
 geometry, solves, operator, features, MLP, Adam); random draws come from
-``synth``.  Recipe (readings of the training set-up):
+``synth``.  Recipe:
   * training boxes: n^3 periodic, lx = 8, deformation amplitude ~ U[0, 0.2],
     draws whose minimum det J falls below 5% of the undeformed value rejected
     (the map folds near 1 / (2 pi));
@@ -13,6 +13,11 @@ geometry, solves, operator, features, MLP, Adam); random draws come from
     log-uniformly over the solve (k = 0, i.e. r = b and e = x*, included when
     `include_zero`), r_k = b - A x_k, e_k = x* - x_k;
   * per snapshot, `elems_per_snapshot` random elements become training rows.
+The preconditioner that beats Jacobi is the linear form trained with the
+energy-norm loss (mu = 1) on white-noise pairs at k = 0 (r = b, e = x*): the
+regression target is then the element block of the inverse operator.
+Smooth (Fourier) right-hand sides or too few rows leave the symmetric part of
+the learned block indefinite, and flexible CG falls back to Jacobi.
 """
 import time
 
@@ -116,7 +121,9 @@ def train(lp, X, T, epochs=4, batch=1024, lr=1e-3, seed=500, verbose=False):
 def init_network(lp, seed=7, mu=None, jacobi_base=None, out_scale=1.0, linear=None):
     """He-initialised weights (the last layer scaled by out_scale); mu >= 0
     selects the energy-norm loss; jacobi_base selects z = Minv r + network;
-    linear selects the linear form (identity activations, no biases)."""
+    linear selects the linear form (identity activations, no biases).  For the
+    linear form, out_scale = 0 starts the folded matrix at zero, so that no
+    random (indefinite) component of the initial product survives training."""
     if mu is not None:
         B.sem_lp_set_metric(lp, mu)
     if jacobi_base is not None:
@@ -126,7 +133,4 @@ def init_network(lp, seed=7, mu=None, jacobi_base=None, out_scale=1.0, linear=No
     params = synth.mlp_init(seed)
     params[4] = params[4] * out_scale
     for s, p in enumerate(params):
-        B.sem_lp_set(lp, s, p.astype(np.float32))
-    return
-    for s, p in enumerate(synth.mlp_init(seed)):
         B.sem_lp_set(lp, s, p.astype(np.float32))
