@@ -242,20 +242,44 @@ __global__ void metric_grad(float* __restrict__ d3f, u16* __restrict__ d3b, cons
     }
 }
 
+// one 256-thread block: strided partial sums, then a fixed-order tree
 __global__ void loss_final(float* __restrict__ loss, const double* __restrict__ part, int nb, double inv_n) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double t = 0.0;
-        for (int q = 0; q < nb; ++q) t += part[q];
-        *loss = (float)(t * inv_n);
+    __shared__ double s_red[256];
+    double t = 0.0;
+    for (int q = threadIdx.x; q < nb; q += 256) t += part[q];
+    s_red[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s_red[threadIdx.x] += s_red[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *loss = (float)(s_red[0] * inv_n);
 }
 
 // out[c] = sum_r d[r][c] (float), fixed order
-__global__ void colsum(float* __restrict__ out, const float* __restrict__ d, int rows, int cols) {
+// column sums of a (rows x cols) row-major matrix in two deterministic passes:
+// part[chunk][c] = sum over the 64 rows of the chunk (256 threads: 4 row groups
+// x 64 columns, combined in a fixed order), then out[c] = sum over the chunks
+constexpr int kColRows = 64;
+__global__ void colsum_part(float* __restrict__ part, const float* __restrict__ d, int rows, int cols) {
+    __shared__ float s_red[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63), rg = threadIdx.x >> 6;
+    const int r0 = blockIdx.y * kColRows;
+    float s = 0.f;
+    if (c < cols)
+        for (int r = r0 + rg; r < r0 + kColRows && r < rows; r += 4) s += d[(int64_t)r * cols + c];
+    s_red[rg][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (rg == 0 && c < cols)
+        part[(int64_t)blockIdx.y * cols + c] = (s_red[0][threadIdx.x] + s_red[1][threadIdx.x]) +
+                                              (s_red[2][threadIdx.x] + s_red[3][threadIdx.x]);
+}
+
+__global__ void colsum_final(float* __restrict__ out, const float* __restrict__ part, int chunks, int cols) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cols) return;
     float s = 0.f;
-    for (int r = 0; r < rows; ++r) s += d[(int64_t)r * cols + c];
+    for (int q = 0; q < chunks; ++q) s += part[(int64_t)q * cols + c];
     out[c] = s;
 }
 
@@ -614,7 +638,9 @@ struct sem_lp_s {
     int64_t step = 0;
     // bf16 copies: W1 (256 x 528), W2 (256 x 256), W3 (512 x 256), W2^T, W3^T
     u16 *W1b = nullptr, *W2b = nullptr, *W3b = nullptr, *W2t = nullptr, *W3t = nullptr;
-    bool dirty = true;
+    bool dirty = true;        // bf16 copies of the weights out of date
+    bool fold_dirty = true;   // folded matrix of the linear form out of date
+    float* colpart = nullptr; // column-sum partials (bias gradients)
     // activations / work for up to max_rows rows
     u16 *X = nullptr, *Y1 = nullptr, *Y2 = nullptr, *d3b = nullptr, *d2b = nullptr, *d1b = nullptr;
     float *Y3 = nullptr, *T = nullptr, *d3f = nullptr, *d2f = nullptr, *d1f = nullptr, *scale = nullptr;
@@ -683,15 +709,24 @@ int refresh_bf16(sem_lp_t lp) {
     weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W1b, kInPad, nullptr, lp->W[0], kHid, kIn);
     weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W2b, kHid, lp->W2t, lp->W[1], kHid, kHid);
     weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W3b, kHid, lp->W3t, lp->W[2], kOut, kHid);
-    if (lp->linear && lp->Wfb) {   // symmetric part of the folded (W3 W2 W1)[:, :512] for inference
-        matmul_f32<<<dim3((kHid + 255) / 256, kOut), 256, 0, st>>>(lp->T32, lp->W[2], lp->W[1], kOut, kHid,
-                                                                   kHid, kHid, kHid, kHid);
-        matmul_f32<<<dim3((kOut + 255) / 256, kOut), 256, 0, st>>>(lp->Wf32, lp->T32, lp->W[0], kOut, kHid,
-                                                                   kOut, kHid, kIn, kOut);
-        sym_to_bf16<<<256, kBlock, 0, st>>>(lp->Wfb, lp->Wf32, kOut);
-    }
     SEM_LAUNCH_CHECK(lp->ctx);
     lp->dirty = false;
+    return SEM_OK;
+}
+
+// symmetric part of the folded (W3 W2 W1)[:, :512] of the linear form, in bf16;
+// needed by inference only, so training steps do not recompute it
+int refresh_fold(sem_lp_t lp) {
+    int rc = refresh_bf16(lp);
+    if (rc || !lp->fold_dirty || !lp->linear || !lp->Wfb) return rc;
+    hipStream_t st = lp->ctx->stream;
+    matmul_f32<<<dim3((kHid + 255) / 256, kOut), 256, 0, st>>>(lp->T32, lp->W[2], lp->W[1], kOut, kHid,
+                                                               kHid, kHid, kHid, kHid);
+    matmul_f32<<<dim3((kOut + 255) / 256, kOut), 256, 0, st>>>(lp->Wf32, lp->T32, lp->W[0], kOut, kHid,
+                                                               kOut, kHid, kIn, kOut);
+    sym_to_bf16<<<256, kBlock, 0, st>>>(lp->Wfb, lp->Wf32, kOut);
+    SEM_LAUNCH_CHECK(lp->ctx);
+    lp->fold_dirty = false;
     return SEM_OK;
 }
 
@@ -793,7 +828,7 @@ extern "C" int sem_lp_set(sem_lp_t lp, int which, const float* host, int64_t cou
     } else {
         SEM_HIP(lp->ctx, hipMemcpy(*slot, host, 4 * (size_t)n, hipMemcpyHostToDevice));
     }
-    if (which < 6) lp->dirty = true;
+    if (which < 6) lp->dirty = lp->fold_dirty = true;
     return SEM_OK;
 }
 
@@ -907,7 +942,7 @@ extern "C" int sem_lp_set_linear(sem_lp_t lp, int on) {
         if (rc) return rc;
         lp->Wfb = (u16*)p;
     }
-    lp->dirty = true;
+    lp->dirty = lp->fold_dirty = true;
     return SEM_OK;
 }
 
@@ -1018,6 +1053,13 @@ extern "C" int sem_lp_forward(sem_lp_t lp, const uint16_t* X, int64_t rows, floa
     return SEM_OK;
 }
 
+static void colsum(sem_lp_t lp, float* out, const float* d, int rows, int cols) {
+    hipStream_t st = lp->ctx->stream;
+    const int chunks = (rows + kColRows - 1) / kColRows;
+    colsum_part<<<dim3((cols + 63) / 64, chunks), 256, 0, st>>>(lp->colpart, d, rows, cols);
+    colsum_final<<<(cols + 255) / 256, 256, 0, st>>>(out, lp->colpart, chunks, cols);
+}
+
 // gradients of the batch loss into the gradient slots (and the loss into *loss_dev)
 static int lp_backward(sem_lp_t lp, const uint16_t* Xb, const float* Tb, int B) {
     sem_ctx_t ctx = lp->ctx;
@@ -1032,10 +1074,10 @@ static int lp_backward(sem_lp_t lp, const uint16_t* Xb, const float* Tb, int B) 
         rc = gemm(lp, B, kOut, kOut, lp->dB, kOut, lp->K, kOut, nullptr, nullptr, 0, lp->Kd, nullptr, kOut, 0);
         if (rc) return rc;
         metric_grad<<<g, kBlock, 0, st>>>(lp->d3f, lp->d3b, lp->dF, lp->Kd, n3, 2.0f / (float)B, lp->part);
-        loss_final<<<1, 64, 0, st>>>(lp->loss, lp->part, (int)g, 1.0 / (double)B);
+        loss_final<<<1, 256, 0, st>>>(lp->loss, lp->part, (int)g, 1.0 / (double)B);
     } else {
         mse_grad<<<g, kBlock, 0, st>>>(lp->d3f, lp->d3b, lp->Y3, Tb, n3, 2.0f / (float)n3, lp->part);
-        loss_final<<<1, 64, 0, st>>>(lp->loss, lp->part, (int)g, 1.0 / (double)n3);
+        loss_final<<<1, 256, 0, st>>>(lp->loss, lp->part, (int)g, 1.0 / (double)n3);
     }
     SEM_LAUNCH_CHECK(ctx);
     // layer 3: gW3 = d3^T Y2, gb3 = colsum d3, d2 = (d3 W3) * (Y2 > 0)
@@ -1043,19 +1085,19 @@ static int lp_backward(sem_lp_t lp, const uint16_t* Xb, const float* Tb, int B) 
     if (!rc) rc = transpose(lp, lp->tB, B, lp->Y2, kHid, B, kHid);   // Y2^T: 256 x B
     if (!rc) rc = gemm(lp, kOut, kHid, B, lp->tA, B, lp->tB, B, nullptr, nullptr, 0, lp->gW[2], nullptr, kHid, 0);
     const int mask = lp->linear ? 0 : EPI_MASK;
-    colsum<<<(kOut + 255) / 256, 256, 0, st>>>(lp->gb[2], lp->d3f, B, kOut);
+    if (!lp->linear) colsum(lp, lp->gb[2], lp->d3f, B, kOut);
     if (!rc) rc = gemm(lp, B, kHid, kOut, lp->d3b, kOut, lp->W3t, kOut, nullptr, lp->Y2, kHid, lp->d2f, lp->d2b, kHid, mask);
     // layer 2
     if (!rc) rc = transpose(lp, lp->tA, B, lp->d2b, kHid, B, kHid);
     if (!rc) rc = transpose(lp, lp->tB, B, lp->Y1, kHid, B, kHid);
     if (!rc) rc = gemm(lp, kHid, kHid, B, lp->tA, B, lp->tB, B, nullptr, nullptr, 0, lp->gW[1], nullptr, kHid, 0);
-    colsum<<<(kHid + 255) / 256, 256, 0, st>>>(lp->gb[1], lp->d2f, B, kHid);
+    if (!lp->linear) colsum(lp, lp->gb[1], lp->d2f, B, kHid);
     if (!rc) rc = gemm(lp, B, kHid, kHid, lp->d2b, kHid, lp->W2t, kHid, nullptr, lp->Y1, kHid, lp->d1f, lp->d1b, kHid, mask);
     // layer 1
     if (!rc) rc = transpose(lp, lp->tA, B, lp->d1b, kHid, B, kHid);
     if (!rc) rc = transpose(lp, lp->tB, B, Xb, kInPad, B, kInPad);
     if (!rc) rc = gemm(lp, kHid, kInPad, B, lp->tA, B, lp->tB, B, nullptr, nullptr, 0, lp->gW[0], nullptr, kInPad, 0);
-    colsum<<<(kHid + 255) / 256, 256, 0, st>>>(lp->gb[0], lp->d1f, B, kHid);
+    if (!lp->linear) colsum(lp, lp->gb[0], lp->d1f, B, kHid);
     if (lp->linear) {   // the biases are not used: their gradients are zero
         zero_f32<<<1, 256, 0, st>>>(lp->gb[0], kHid);
         zero_f32<<<1, 256, 0, st>>>(lp->gb[1], kHid);
@@ -1079,6 +1121,7 @@ static int lp_train_buffers(sem_lp_t lp, int B) {
     LP_ALLOC2(lp->d1b, 2 * R * kHid);
     LP_ALLOC2(lp->tA, 2 * R * kInPad);
     LP_ALLOC2(lp->tB, 2 * R * kInPad);
+    LP_ALLOC2(lp->colpart, 4 * ((R + kColRows - 1) / kColRows) * kOut);
 #undef LP_ALLOC2
     (void)B;
     return SEM_OK;
@@ -1121,7 +1164,7 @@ extern "C" int sem_lp_adam(sem_lp_t lp, double lr, double beta1, double beta2, d
             (float)(1.0 - beta1), (float)beta2, (float)(1.0 - beta2), (float)eps, (float)c1, (float)c2);
     }
     SEM_LAUNCH_CHECK(ctx);
-    lp->dirty = true;
+    lp->dirty = lp->fold_dirty = true;
     return SEM_OK;
 }
 
@@ -1154,7 +1197,7 @@ int lp_apply_t(sem_lp_t lp, T* z, const T* r, bool unique) {
     hipStream_t st = ctx->stream;
     const int64_t nel = lp->nel;
     if (unique && lp->linear) {   // fused product and CSR-ordered output, then assembly
-        int rc = refresh_bf16(lp);
+        int rc = refresh_fold(lp);
         if (rc) return rc;
         lin_gather_kernel<T><<<grid_of(nel * kOut / 8, 8192), kBlock, 0, st>>>(lp->X, r, lp->sq, lp->gs->lid,
                                                                            nel * kOut / 8, lp->skip);
@@ -1180,7 +1223,7 @@ int lp_apply_t(sem_lp_t lp, T* z, const T* r, bool unique) {
     SEM_LAUNCH_CHECK(ctx);
     int rc;
     if (lp->linear) {   // one product with the folded matrix
-        rc = refresh_bf16(lp);
+        rc = refresh_fold(lp);
         if (!rc) rc = gemm(lp, (int)nel, kOut, kOut, lp->X, kInPad, lp->Wfb, kOut, nullptr, nullptr, 0,
                            lp->Y3, nullptr, kOut, 0);
     } else {
