@@ -373,6 +373,47 @@ __global__ void fcg_dots_kernel(const T* __restrict__ r, const T* __restrict__ z
     }
 }
 
+// the same partials, with z assembled here from the network's CSR-ordered
+// element contributions: z_u = mult_u^-1/2 sum_segment zl (+ Minv_u r_u), written out
+template <typename T>
+__global__ void fcg_dots_asm_kernel(T* __restrict__ z, const float* __restrict__ zl,
+                                    const int32_t* __restrict__ uoff, const T* __restrict__ r,
+                                    const T* __restrict__ wprev, const T* __restrict__ minv, bool jbase,
+                                    int64_t n, const Scal* __restrict__ S, double* __restrict__ part) {
+    if (S->done) return;
+    __shared__ double s_red[kBlock / 64];
+    const bool first = S->it == 0;
+    double rz = 0.0, bad = 0.0, zw = 0.0, jw = 0.0;
+    GRID_LOOP(u, n) {
+        const int32_t b = uoff[u], e = uoff[u + 1];
+        float s = 0.f;
+        for (int32_t q = b; q < e; ++q) s += zl[q];
+        const T rt = r[u], mv = minv[u];
+        double zd = (double)s * rsqrt((double)(e - b));
+        if (jbase) zd += (double)mv * (double)rt;
+        const T zt = (T)zd;
+        z[u] = zt;
+        const double zv = (double)zt, rv = (double)rt;
+        if (!isfinite(zv)) bad += 1.0;
+        rz += rv * zv;
+        if (!first) {
+            const double wv = (double)wprev[u];
+            zw += zv * wv;
+            jw += (double)(mv * rt) * wv;
+        }
+    }
+    rz = block_sum(rz, s_red);
+    bad = block_sum(bad, s_red);
+    zw = block_sum(zw, s_red);
+    jw = block_sum(jw, s_red);
+    if (threadIdx.x == 0) {
+        part[4 * blockIdx.x] = rz;
+        part[4 * blockIdx.x + 1] = bad;
+        part[4 * blockIdx.x + 2] = zw;
+        part[4 * blockIdx.x + 3] = jw;
+    }
+}
+
 __global__ void fcg_gamma_final(Scal* __restrict__ S, const double* __restrict__ part, int n) {
     if (S->done) return;
     __shared__ double s_red[kFinal / 64];
@@ -625,9 +666,17 @@ int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int chec
     for (;;) {
         for (int q = 0; q < check_every; ++q) {
             if (cg->lp) {   // flexible CG step with the network (Jacobi where it is rejected)
-                int rc = sem::lp_apply(cg->lp, z, r, false, &cg->S->done, true);
-                if (rc) return rc;
-                fcg_dots_kernel<float><<<g, kBlock, 0, st>>>(r, z, wu, minv, n, cg->S, cg->part);
+                const float* zl = nullptr;
+                bool jb = false;
+                int rc = sem::lp_apply_partial(cg->lp, r, false, &cg->S->done, &zl, &jb);
+                if (rc == SEM_OK) {
+                    fcg_dots_asm_kernel<float><<<g, kBlock, 0, st>>>(z, zl, uoff, r, wu, minv, jb, n, cg->S,
+                                                                     cg->part);
+                } else {
+                    rc = sem::lp_apply(cg->lp, z, r, false, &cg->S->done, true);
+                    if (rc) return rc;
+                    fcg_dots_kernel<float><<<g, kBlock, 0, st>>>(r, z, wu, minv, n, cg->S, cg->part);
+                }
                 fcg_gamma_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
                 fcg_p_kernel<float><<<g, kBlock, 0, st>>>(p, z, r, minv, n, cg->S, cg->part2);
                 rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid, cg->gs->upos);
@@ -704,9 +753,16 @@ int fcg_run(sem_cg_t cg, Level& lv, const T* rhs, double tol, int maxit, int che
     for (;;) {
         for (int q = 0; q < check_every; ++q) {
             int rc = SEM_OK;
-            if (!fallen) rc = sem::lp_apply(cg->lp, z, r, f64, &cg->S->done, true);
-            if (rc) return rc;
-            fcg_dots_kernel<T><<<g, kBlock, 0, st>>>(r, z, wu, minv, n, cg->S, cg->part);
+            const float* zl = nullptr;
+            bool jb = false;
+            if (!fallen) rc = sem::lp_apply_partial(cg->lp, r, f64, &cg->S->done, &zl, &jb);
+            if (!fallen && rc == SEM_OK) {
+                fcg_dots_asm_kernel<T><<<g, kBlock, 0, st>>>(z, zl, uoff, r, wu, minv, jb, n, cg->S, cg->part);
+            } else {
+                if (!fallen) rc = sem::lp_apply(cg->lp, z, r, f64, &cg->S->done, true);
+                if (rc) return rc;
+                fcg_dots_kernel<T><<<g, kBlock, 0, st>>>(r, z, wu, minv, n, cg->S, cg->part);
+            }
             fcg_gamma_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
             fcg_p_kernel<T><<<g, kBlock, 0, st>>>(p, z, r, minv, n, cg->S, cg->part2);
             rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid, cg->gs->upos);

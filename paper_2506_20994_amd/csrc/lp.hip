@@ -300,8 +300,8 @@ __global__ void adam_kernel(float* __restrict__ p, float* __restrict__ m, float*
     }
 }
 
-// per-element geometric features (six means of h1 g_ab over kappa) and kappa
-__global__ void geo_kernel(float* __restrict__ geo, float* __restrict__ kappa,
+// per-element geometric features (six means of h1 g_ab over kappa), kappa and 1/kappa
+__global__ void geo_kernel(float* __restrict__ geo, float* __restrict__ kappa, float* __restrict__ kappa_inv,
                            const double* __restrict__ h1, const double* __restrict__ g11,
                            const double* __restrict__ g22, const double* __restrict__ g33,
                            const double* __restrict__ g12, const double* __restrict__ g13,
@@ -319,6 +319,7 @@ __global__ void geo_kernel(float* __restrict__ geo, float* __restrict__ kappa,
     if (threadIdx.x == 0) {
         const double kap = (s[0] + s[1] + s[2]) / (3.0 * kOut);
         kappa[e] = (float)kap;
+        kappa_inv[e] = (float)(1.0 / kap);
         for (int a = 0; a < 6; ++a) geo[e * 6 + a] = (float)(s[a] / kOut / kap);
     }
 }
@@ -486,13 +487,13 @@ __device__ __forceinline__ void ws_load_chunk(uint4& lo, uint4& hi, const u16* _
 }
 
 __device__ __forceinline__ void ws_load_pos(int32_t (&pos)[2][4], float (&kinv)[4], const int32_t* __restrict__ upos,
-                                            const float* __restrict__ kappa, int64_t c, int64_t nel, int grp,
+                                            const float* __restrict__ kappa_inv, int64_t c, int64_t nel, int grp,
                                             int col) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         int64_t e = c * kWsChunk + 4 * grp + j;
         e = e < nel ? e : nel - 1;        // rows past the end read valid data and are not stored
-        kinv[j] = 1.f / kappa[e];
+        kinv[j] = kappa_inv[e];
         pos[0][j] = upos[e * kOut + col];
         pos[1][j] = upos[e * kOut + col + 16];
     }
@@ -503,21 +504,28 @@ __device__ __forceinline__ void ws_load_pos(int32_t (&pos)[2][4], float (&kinv)[
 // ago) goes to the other buffer and lo/hi start fetching the chunk three steps
 // ahead.  Two register sets alternate between consecutive steps.
 __device__ __forceinline__ void ws_step(float* __restrict__ zl, const u16* __restrict__ X,
-                                        const int32_t* __restrict__ upos, const float* __restrict__ kappa,
+                                        const int32_t* __restrict__ upos, const float* __restrict__ kappa_inv,
                                         u16 (*sx)[kWsChunk * kWsLd], const bf16x8 (&w)[kLinSlabs][2],
                                         int64_t c, int buf, int64_t groups, int64_t nchunks, int64_t nel,
                                         uint4& lo, uint4& hi, const int32_t (&pos)[2][4], const float (&kinv)[4],
                                         int32_t (&pnext)[2][4], float (&knext)[4], int row, int grp, int col,
                                         int se, int sk) {
-    ws_load_pos(pnext, knext, upos, kappa, c + groups, nel, grp, col);
-    f32x4 acc0 = f32x4{0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+    ws_load_pos(pnext, knext, upos, kappa_inv, c + groups, nel, grp, col);
+    // four accumulators (two k halves x two column tiles) keep four independent
+    // MFMA chains in flight
+    f32x4 acc0 = f32x4{0.f, 0.f, 0.f, 0.f}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
     const u16* xs = sx[buf] + row * kWsLd + 8 * grp;
 #pragma unroll
-    for (int kb = 0; kb < kLinSlabs; ++kb) {
+    for (int kb = 0; kb < kLinSlabs / 2; ++kb) {
         const bf16x8 a = *reinterpret_cast<const bf16x8*>(xs + kb * kLinBK);
+        const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(xs + (kb + kLinSlabs / 2) * kLinBK);
         acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w[kb][0], acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w[kb][1], acc1, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, w[kb + kLinSlabs / 2][0], acc2, 0, 0, 0);
+        acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, w[kb + kLinSlabs / 2][1], acc3, 0, 0, 0);
     }
+    acc0 += acc2;
+    acc1 += acc3;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         if (c * kWsChunk + 4 * grp + j < nel) {
@@ -533,7 +541,7 @@ __device__ __forceinline__ void ws_step(float* __restrict__ zl, const u16* __res
 
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 lin_gemm_kernel(float* __restrict__ zl, const u16* __restrict__ X, const int32_t* __restrict__ upos,
-                const float* __restrict__ kappa, const u16* __restrict__ Ws, int64_t nel, int groups,
+                const float* __restrict__ kappa_inv, const u16* __restrict__ Ws, int64_t nel, int groups,
                 const int* __restrict__ skip) {
     if (skip && *skip) return;
     __shared__ __attribute__((aligned(16))) u16 sx[2][kWsChunk * kWsLd];
@@ -566,14 +574,14 @@ lin_gemm_kernel(float* __restrict__ zl, const u16* __restrict__ X, const int32_t
     }
     int32_t pos0[2][4], pos1[2][4];
     float kinv0[4], kinv1[4];
-    ws_load_pos(pos0, kinv0, upos, kappa, g, nel, grp, col);
+    ws_load_pos(pos0, kinv0, upos, kappa_inv, g, nel, grp, col);
     __syncthreads();
 
     for (int64_t c = g; c < nchunks; c += 2 * groups) {
-        ws_step(zl, X, upos, kappa, sx, w, c, 0, groups, nchunks, nel, lo0, hi0, pos0, kinv0, pos1, kinv1,
+        ws_step(zl, X, upos, kappa_inv, sx, w, c, 0, groups, nchunks, nel, lo0, hi0, pos0, kinv0, pos1, kinv1,
                 row, grp, col, se, sk);
         if (c + groups >= nchunks) break;     // uniform over the block
-        ws_step(zl, X, upos, kappa, sx, w, c + groups, 1, groups, nchunks, nel, lo1, hi1, pos1, kinv1, pos0,
+        ws_step(zl, X, upos, kappa_inv, sx, w, c + groups, 1, groups, nchunks, nel, lo1, hi1, pos1, kinv1, pos0,
                 kinv0, row, grp, col, se, sk);
     }
 }
@@ -649,7 +657,7 @@ struct sem_lp_s {
     float* loss = nullptr;
     // bound operator (inference)
     int64_t nel = 0, geo_cap = 0;
-    float *geo = nullptr, *kappa = nullptr;
+    float *geo = nullptr, *kappa = nullptr, *kappa_inv = nullptr;
     bool bound = false;
     sem_gs_t gs = nullptr;
     const int* skip = nullptr;   // set by the solver: kernels return when *skip != 0
@@ -975,11 +983,14 @@ extern "C" int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs) {
         rc = lp_alloc(lp, &p, 4 * (size_t)A->nel);
         if (rc) return rc;
         lp->kappa = (float*)p;
+        rc = lp_alloc(lp, &p, 4 * (size_t)A->nel);
+        if (rc) return rc;
+        lp->kappa_inv = (float*)p;
     }
     lp->nel = A->nel;
     lp->gs = gs;
     lp->bound = true;
-    geo_kernel<<<(unsigned)A->nel, 64, 0, ctx->stream>>>(lp->geo, lp->kappa, A->h1, A->g11, A->g22, A->g33,
+    geo_kernel<<<(unsigned)A->nel, 64, 0, ctx->stream>>>(lp->geo, lp->kappa, lp->kappa_inv, A->h1, A->g11, A->g22, A->g33,
                                                          A->g12, A->g13, A->g23, A->nel);
     SEM_LAUNCH_CHECK(ctx);
     if (lp->sq_n < gs->n_unique) {
@@ -1191,22 +1202,33 @@ extern "C" int sem_lp_train_step(sem_lp_t lp, const uint16_t* X, const float* T,
 namespace sem {
 
 // z = Q Q^T (mult^-1 (s/kappa) NN(features(r))) for the bound operator
+// linear form, unique layout: gather of S r and the product into lp->Y3 (CSR order)
+template <typename T>
+int lin_product(sem_lp_t lp, const T* r) {
+    int rc = refresh_fold(lp);
+    if (rc) return rc;
+    sem_ctx_t ctx = lp->ctx;
+    hipStream_t st = ctx->stream;
+    const int64_t nel = lp->nel;
+    lin_gather_kernel<T><<<grid_of(nel * kOut / 8, 8192), kBlock, 0, st>>>(lp->X, r, lp->sq, lp->gs->lid,
+                                                                       nel * kOut / 8, lp->skip);
+    SEM_LAUNCH_CHECK(ctx);
+    const int64_t nchunks = (nel + kWsChunk - 1) / kWsChunk;
+    const int groups = (int)std::min<int64_t>(kWsGroupsMax, (nchunks + 7) / 8 * 8);
+    lin_gemm_kernel<<<(unsigned)(2 * groups), 512, 0, st>>>(lp->Y3, lp->X, lp->gs->upos, lp->kappa_inv, lp->Wfb,
+                                                            nel, groups, lp->skip);
+    SEM_LAUNCH_CHECK(ctx);
+    return SEM_OK;
+}
+
 template <typename T>
 int lp_apply_t(sem_lp_t lp, T* z, const T* r, bool unique) {
     sem_ctx_t ctx = lp->ctx;
     hipStream_t st = ctx->stream;
     const int64_t nel = lp->nel;
-    if (unique && lp->linear) {   // fused product and CSR-ordered output, then assembly
-        int rc = refresh_fold(lp);
+    if (unique && lp->linear) {   // product with CSR-ordered output, then assembly
+        int rc = lin_product(lp, r);
         if (rc) return rc;
-        lin_gather_kernel<T><<<grid_of(nel * kOut / 8, 8192), kBlock, 0, st>>>(lp->X, r, lp->sq, lp->gs->lid,
-                                                                           nel * kOut / 8, lp->skip);
-        SEM_LAUNCH_CHECK(ctx);
-        const int64_t nchunks = (nel + kWsChunk - 1) / kWsChunk;
-        const int groups = (int)std::min<int64_t>(kWsGroupsMax, (nchunks + 7) / 8 * 8);
-        lin_gemm_kernel<<<(unsigned)(2 * groups), 512, 0, st>>>(lp->Y3, lp->X, lp->gs->upos, lp->kappa, lp->Wfb,
-                                                                nel, groups, lp->skip);
-        SEM_LAUNCH_CHECK(ctx);
         const int64_t nu = lp->gs->n_unique;
         lin_assemble_kernel<T><<<grid_of(nu, 8192), kBlock, 0, st>>>(z, lp->Y3,
                                                                      lp->jacobi_base ? lp->minvu : nullptr, r,
@@ -1244,6 +1266,17 @@ int lp_apply_t(sem_lp_t lp, T* z, const T* r, bool unique) {
                                                        lp->linear);
     SEM_LAUNCH_CHECK(ctx);
     return gs_launch(lp->gs, z, sizeof(T) == 8 ? SEM_F64 : SEM_F32, lp->skip);
+}
+
+int lp_apply_partial(sem_lp_t lp, const void* r, bool f64, const int* skip, const float** zl, bool* jacobi_base) {
+    if (!lp->bound || !lp->gs) return fail(lp->ctx, SEM_EINVAL, "learned preconditioner has no bound operator");
+    if (!lp->linear) return SEM_EUNSUPPORTED_LX;
+    lp->skip = skip;
+    const int rc = f64 ? lin_product<double>(lp, (const double*)r) : lin_product<float>(lp, (const float*)r);
+    lp->skip = nullptr;
+    *zl = lp->Y3;
+    *jacobi_base = lp->jacobi_base;
+    return rc;
 }
 
 int lp_apply(sem_lp_t lp, void* z, const void* r, bool f64, const int* skip, bool unique) {

@@ -82,6 +82,12 @@ int gs_launch(sem_gs_t gs, void* u, sem_dtype_t dtype, const int* skip);
 // float64 (f64) or float32; kernels return at once when skip && *skip
 // unique: r and z are unique-node vectors of the bound plan, else local fields
 int lp_apply(sem_lp_t lp, void* z, const void* r, bool f64, const int* skip, bool unique);
+// Linear form on unique-node vectors without the final assembly: leaves the
+// CSR-ordered element contributions (already weighted by 1/kappa_e, not yet by
+// S = mult^-1/2) in *zl and reports whether the Jacobi base is on; the caller
+// assembles z_u = S_u sum_segment zl (+ Minv_u r_u).  Returns SEM_EUNSUPPORTED_LX
+// without launching anything when the network is not in its linear form.
+int lp_apply_partial(sem_lp_t lp, const void* r, bool f64, const int* skip, const float** zl, bool* jacobi_base);
 int64_t lp_rows(sem_lp_t lp);
 sem_gs_t lp_plan(sem_lp_t lp);
 
