@@ -72,16 +72,45 @@ template <> struct Packed<uint16_t> {
     }
 };
 
+#ifndef SEM_AX_PREFETCH
+#define SEM_AX_PREFETCH(LX) ((LX) != 2 && (LX) != 8)
+#endif
+
 template <int LX> struct Shape {
     static constexpr bool kWavePrivate = (64 % (LX * LX)) == 0;
     // occupancy floor (waves per SIMD) handed to the register allocator (a
     // floor of 3 at lx = 10 gave three waves per SIMD but a slower kernel)
     static constexpr int kWavesPerEU = 1;
+    // fetch the next slice's h1 and G while the current slice is computed
+    static constexpr bool kPrefetch = SEM_AX_PREFETCH(LX);
     // elements per workgroup: about four waves, LDS of float64 within ~64 KiB
     static constexpr int EPB = LX == 2 ? 64 : LX == 3 ? 28 : LX == 4 ? 16 : LX == 5 ? 10
                              : LX == 6 ? 7 : LX == 7 ? 5 : LX == 8 ? 4 : LX == 9 ? 3
                              : LX <= 11 ? 2 : 1;
 };
+
+// h1 and the six factors at offset o (node ij of a slice) of a live element;
+// h = 1 and zero factors for a dead one
+template <typename TS, typename TC, bool GATHER>
+__device__ __forceinline__ void load_factors(TC (&g)[6], TC& h, bool live, int64_t o, int ij, int l2,
+                                             const TS* __restrict__ h1, const TS* __restrict__ g11,
+                                             const TS* __restrict__ g22, const TS* __restrict__ g33,
+                                             const TS* __restrict__ g12, const TS* __restrict__ g13,
+                                             const TS* __restrict__ g23, const TS* __restrict__ gp) {
+    h = 1;
+    if (!live) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) g[a] = 0;
+        return;
+    }
+    if constexpr (GATHER) {                    // the solver form reads the packed factors
+        Packed<TS>::get(gp, o - ij, ij, l2, g);   // o - ij = e lx^3 + k lx^2
+    } else {
+        g[0] = Load<TS>::get(g11, o); g[1] = Load<TS>::get(g22, o); g[2] = Load<TS>::get(g33, o);
+        g[3] = Load<TS>::get(g12, o); g[4] = Load<TS>::get(g13, o); g[5] = Load<TS>::get(g23, o);
+    }
+    if (h1) h = Load<TS>::get(h1, o);
+}
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -163,8 +192,22 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
     TC wt[LX];
 #pragma unroll
     for (int m = 0; m < LX; ++m) wt[m] = 0;
+    constexpr bool PF = Shape<LX>::kPrefetch;
+    TC ng[6], nh;                              // the next slice's factors (prefetch)
+    if constexpr (PF) load_factors<TS, TC, GATHER>(ng, nh, live, base, ij, L2, h1, g11, g22, g33, g12, g13, g23, gp);
 #pragma unroll 1
     for (int k = 0; k < LX; ++k) {
+        const int64_t o = base + k * L2;
+        TC g[6], H;
+        if constexpr (PF) {
+#pragma unroll
+            for (int a = 0; a < 6; ++a) g[a] = ng[a];
+            H = nh;
+            if (k + 1 < LX)
+                load_factors<TS, TC, GATHER>(ng, nh, live, o + L2, ij, L2, h1, g11, g22, g33, g12, g13, g23, gp);
+        } else {
+            load_factors<TS, TC, GATHER>(g, H, live, o, ij, L2, h1, g11, g22, g33, g12, g13, g23, gp);
+        }
         TC r = 0, s = 0, t = 0;
 #pragma unroll
         for (int l = 0; l < LX; ++l) {
@@ -172,19 +215,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
             s += dj[l] * su[k * L2 + l * LX + i];
             t += sdz[l * LX + k] * uc[l];
         }
-        const int64_t o = base + k * L2;
-        TC G11 = 0, G22 = 0, G33 = 0, G12 = 0, G13 = 0, G23 = 0, H = 1;
-        if (live) {
-            if constexpr (GATHER) {            // the solver form reads the packed factors
-                TC g[6];
-                Packed<TS>::get(gp, o - ij, ij, L2, g);   // o - ij = e lx^3 + k lx^2
-                G11 = g[0]; G22 = g[1]; G33 = g[2]; G12 = g[3]; G13 = g[4]; G23 = g[5];
-            } else {
-                G11 = Load<TS>::get(g11, o); G22 = Load<TS>::get(g22, o); G33 = Load<TS>::get(g33, o);
-                G12 = Load<TS>::get(g12, o); G13 = Load<TS>::get(g13, o); G23 = Load<TS>::get(g23, o);
-            }
-            if (h1) H = Load<TS>::get(h1, o);
-        }
+        const TC G11 = g[0], G22 = g[1], G33 = g[2], G12 = g[3], G13 = g[4], G23 = g[5];
         const TC vr = H * (G11 * r + G12 * s + G13 * t);
         const TC vs = H * (G12 * r + G22 * s + G23 * t);
         const TC vt = H * (G13 * r + G23 * s + G33 * t);
