@@ -15,3 +15,37 @@ def to_dev(a, dtype=None):
     if dtype is not None:
         t = t.to(dtype)
     return t.cuda()
+
+
+def linear_apply_at_nodes(params, n, lx, amp, ids, r_glob, gids, jacobi=False):
+    """The oracle's linear-form apply (oracle.mlp.apply_linear, plus Minv r with
+    the Jacobi base) evaluated only at the global ids `gids` of the n^3 box,
+    each from the elements that contain it: for large meshes, where the
+    whole-mesh oracle is too slow.  ids: the box's global ids (E, lx, lx, lx)."""
+    from oracle import mlp
+    from oracle.mesh import box_coords
+    from oracle.geometry import geometric_factors
+    from oracle.gll import gll_nodes_weights, deriv_matrix
+    from oracle.assemble import element_diagonal
+    flat = ids.reshape(len(ids), -1)
+    counts = np.bincount(flat.ravel())
+    W = mlp.folded_matrix(params, lx ** 3)
+    Ws = 0.5 * (W + W.T)
+    xi, _ = gll_nodes_weights(lx - 1)
+    Dh = deriv_matrix(xi)
+    out = np.empty(len(gids))
+    for q, g in enumerate(gids):
+        els = np.nonzero((flat == g).any(axis=1))[0]
+        x, y, z = box_coords(n, lx, amp, elements=els)
+        G, _, _ = geometric_factors(x, y, z, lx)
+        _, _, kappa = mlp.features(r_glob[ids[els]], G)
+        diag = element_diagonal(Dh, None, G).reshape(len(els), -1)
+        acc, dg = 0.0, 0.0
+        for a, e in enumerate(els):
+            S = 1.0 / np.sqrt(counts[flat[e]])
+            yv = Ws @ (S * r_glob[flat[e]])
+            at = flat[e] == g
+            acc += np.sum(S[at] * yv[at]) / kappa[a]
+            dg += np.sum(diag[a][at])
+        out[q] = acc + (r_glob[g] / dg if jacobi else 0.0)
+    return out

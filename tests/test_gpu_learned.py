@@ -413,3 +413,42 @@ def test_trained_linear_network_beats_jacobi(sem_ctx):
     for h in (cg0, lp):
         h.close()
     op.gs.close()
+
+
+def test_apply_unique_linear_full_size_sampled(sem_ctx):
+    """The linear-form apply at the benchmark size (32^3 box, lx = 8, 16.8M local
+    nodes, the launch configuration of the solves), float64 and float32, with
+    the Jacobi base: z at 48 sampled unique nodes against the oracle evaluated
+    node by node from the (at most 8) elements containing each node
+    (tests/helpers.linear_apply_at_nodes, itself checked against the oracle's
+    whole-mesh apply on the CPU)."""
+    from oracle.mesh import global_ids
+    from tests.helpers import linear_apply_at_nodes
+    n, lx, amp = 32, 8, 0.1
+    op = BoxOperator(sem_ctx, n, lx, amp, keep_coords=False)
+    lp = P.sem_lp_create(sem_ctx, op.nel)
+    P.sem_lp_set_linear(lp, 1)
+    P.sem_lp_set_jacobi_base(lp, 1)
+    op.bind(lp)
+    params = _params(56)
+    _load(lp, params)
+    ids = global_ids(n, lx)
+    _, first = np.unique(ids.ravel(), return_index=True)
+    gid_of_plan = np.argsort(first)             # plan index -> global id
+    nu = len(first)
+    r_plan = synth.unique_normal(nu, 57)
+    r_glob = np.empty(nu)
+    r_glob[gid_of_plan] = r_plan
+    f32 = [q.astype(np.float32).astype(np.float64) for q in params]
+    samples = synth.choice(58, nu, 48)
+    zref = linear_apply_at_nodes(f32, n, lx, amp, ids, r_glob, gid_of_plan[samples], jacobi=True)
+    for dt in (torch.float64, torch.float32):
+        r = torch.from_numpy(r_plan).to(dt).cuda()
+        z = torch.empty_like(r)
+        P.sem_lp_apply_unique(lp, z, r)
+        torch.cuda.synchronize()
+        zs = z.double().cpu().numpy()[samples]
+        assert np.all(np.isfinite(zs))
+        assert _nrm(zs, zref) <= GRAD_TOL, (dt, _nrm(zs, zref))
+    lp.close()
+    op.gs.close()

@@ -164,3 +164,21 @@ def test_linear_apply_symmetric_and_positive_definite():
     spd = [W1, np.zeros(nloc), np.eye(nloc), np.zeros(nloc), C.T.copy(), np.zeros(nloc)]
     ev = np.linalg.eigvalsh(_dense_precond(spd, P))
     assert ev[0] > 1e-8 * ev[-1]
+
+
+def test_linear_apply_at_nodes_matches_whole_mesh():
+    """The node-by-node evaluation used by the full-size GPU test equals the
+    oracle's whole-mesh linear apply (plus the Jacobi term) at every node."""
+    from tests.helpers import linear_apply_at_nodes
+    from oracle.assemble import element_diagonal
+    n, lx, amp = 2, 4, 0.12
+    P = BoxProblem(n, lx, amp)
+    r = np.random.default_rng(9)
+    params = [r.standard_normal(p.shape) for p in synth.mlp_init(5, (lx ** 3 + 6, 20, 20, lx ** 3))]
+    rG = synth.unique_normal(P.nu, 10)
+    z = mlp.apply_linear(params, scatter(rG, P.ids), P.G, None, P.ids, P.nu)
+    zu = np.zeros(P.nu)
+    zu[P.ids.ravel()] = z.ravel()
+    zu += rG / P.diagonal()
+    got = linear_apply_at_nodes(params, n, lx, amp, P.ids, rG, np.arange(P.nu), jacobi=True)
+    np.testing.assert_allclose(got, zu, rtol=1e-12, atol=1e-12 * np.abs(zu).max())
