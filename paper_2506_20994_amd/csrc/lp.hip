@@ -468,22 +468,28 @@ __global__ void lin_gather_kernel(u16* __restrict__ X, const T* __restrict__ r, 
 // its 8 waves 32 of them, held for the whole kernel as the B fragments of
 // 16x16x32 bf16 MFMA blocks (128 registers).  The block walks over 16-element
 // chunks of X (chunks g, g + groups, ...), staged through a double-buffered LDS
-// tile with a kWsDepth-deep register prefetch; the outputs' CSR positions and
-// scales are fetched one chunk ahead.  The two halves of a group run 8 block
+// tile with a two-chunk register prefetch.  The two halves of a group run 8 block
 // indices apart, on the same XCD, so a chunk of X is read from HBM once.
-constexpr int kWsChunk = 16, kWsLd = kOut + 8, kWsDepth = 3, kWsGroupsMax = 128;
+constexpr int kWsChunk = 16, kWsLd = kOut + 8, kWsGroupsMax = 128;
 
-__device__ __forceinline__ void ws_load_chunk(uint4& lo, uint4& hi, const u16* __restrict__ X, int64_t c,
-                                              int64_t nchunks, int64_t nel, int se, int sk) {
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
+
+// 16 bf16 of chunk c (element se of the chunk, columns sk .. sk + 15), zero past
+// the end; the load always reads a valid row (clamped) and the select zeroes it
+__device__ __forceinline__ u32x8 ws_load_chunk(const u16* __restrict__ X, int64_t c, int64_t nchunks, int64_t nel,
+                                               int se, int sk) {
     const int64_t e = c * kWsChunk + se;
-    if (c < nchunks && e < nel) {
-        const u16* p = X + e * kInPad + sk;
-        lo = *reinterpret_cast<const uint4*>(p);
-        hi = *reinterpret_cast<const uint4*>(p + 8);
-    } else {
-        lo = uint4{0u, 0u, 0u, 0u};
-        hi = lo;
-    }
+    const bool ok = c < nchunks && e < nel;
+    const u16* p = X + (ok ? e : 0) * kInPad + sk;
+    const u32x4 a = *reinterpret_cast<const u32x4*>(p), b = *reinterpret_cast<const u32x4*>(p + 8);
+    const u32x8 v = u32x8{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    return ok ? v : u32x8{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+}
+
+__device__ __forceinline__ void ws_stage(u16* __restrict__ dst, u32x8 v) {
+    *reinterpret_cast<u32x4*>(dst) = u32x4{v[0], v[1], v[2], v[3]};
+    *reinterpret_cast<u32x4*>(dst + 8) = u32x4{v[4], v[5], v[6], v[7]};
 }
 
 __device__ __forceinline__ void ws_load_pos(int32_t (&pos)[2][4], float (&kinv)[4], const int32_t* __restrict__ upos,
@@ -499,33 +505,29 @@ __device__ __forceinline__ void ws_load_pos(int32_t (&pos)[2][4], float (&kinv)[
     }
 }
 
-// One chunk: positions of the chunk after it, products out of LDS buffer
-// `buf`, stores; then the chunk `groups` ahead (held in lo/hi since two steps
-// ago) goes to the other buffer and lo/hi start fetching the chunk three steps
-// ahead.  Two register sets alternate between consecutive steps.
+// One chunk c.  Loads are issued in the order they are needed, because the
+// vector-memory counter is waited on in order: first the next chunk's CSR
+// positions and scales, then (after this chunk's products out of LDS buffer
+// `buf` and its stores, which use positions fetched one step ago) the chunk
+// `groups` ahead goes from its registers (fetched two steps ago) to the other
+// buffer, and those registers start fetching the chunk three steps ahead.
+// Two register sets alternate between consecutive steps.
 __device__ __forceinline__ void ws_step(float* __restrict__ zl, const u16* __restrict__ X,
                                         const int32_t* __restrict__ upos, const float* __restrict__ kappa_inv,
                                         u16 (*sx)[kWsChunk * kWsLd], const bf16x8 (&w)[kLinSlabs][2],
                                         int64_t c, int buf, int64_t groups, int64_t nchunks, int64_t nel,
-                                        uint4& lo, uint4& hi, const int32_t (&pos)[2][4], const float (&kinv)[4],
+                                        u32x8& nx, const int32_t (&pos)[2][4], const float (&kinv)[4],
                                         int32_t (&pnext)[2][4], float (&knext)[4], int row, int grp, int col,
                                         int se, int sk) {
     ws_load_pos(pnext, knext, upos, kappa_inv, c + groups, nel, grp, col);
-    // four accumulators (two k halves x two column tiles) keep four independent
-    // MFMA chains in flight
-    f32x4 acc0 = f32x4{0.f, 0.f, 0.f, 0.f}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
+    f32x4 acc0 = f32x4{0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
     const u16* xs = sx[buf] + row * kWsLd + 8 * grp;
 #pragma unroll
-    for (int kb = 0; kb < kLinSlabs / 2; ++kb) {
+    for (int kb = 0; kb < kLinSlabs; ++kb) {
         const bf16x8 a = *reinterpret_cast<const bf16x8*>(xs + kb * kLinBK);
-        const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(xs + (kb + kLinSlabs / 2) * kLinBK);
         acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w[kb][0], acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w[kb][1], acc1, 0, 0, 0);
-        acc2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, w[kb + kLinSlabs / 2][0], acc2, 0, 0, 0);
-        acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, w[kb + kLinSlabs / 2][1], acc3, 0, 0, 0);
     }
-    acc0 += acc2;
-    acc1 += acc3;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         if (c * kWsChunk + 4 * grp + j < nel) {
@@ -533,9 +535,8 @@ __device__ __forceinline__ void ws_step(float* __restrict__ zl, const u16* __res
             zl[pos[1][j]] = acc1[j] * kinv[j];
         }
     }
-    *reinterpret_cast<uint4*>(sx[buf ^ 1] + se * kWsLd + sk) = lo;
-    *reinterpret_cast<uint4*>(sx[buf ^ 1] + se * kWsLd + sk + 8) = hi;
-    ws_load_chunk(lo, hi, X, c + 3 * groups, nchunks, nel, se, sk);
+    ws_stage(sx[buf ^ 1] + se * kWsLd + sk, nx);
+    nx = ws_load_chunk(X, c + 3 * groups, nchunks, nel, se, sk);
     __syncthreads();
 }
 
@@ -559,29 +560,27 @@ lin_gemm_kernel(float* __restrict__ zl, const u16* __restrict__ X, const int32_t
     for (int kb = 0; kb < kLinSlabs; ++kb)
 #pragma unroll
         for (int t = 0; t < 2; ++t)
-            w[kb][t] = *reinterpret_cast<const bf16x8*>(Ws + (int64_t)(col - row + 16 * t + row) * kOut +
-                                                        kb * kLinBK + 8 * grp);
+            w[kb][t] = *reinterpret_cast<const bf16x8*>(Ws + (int64_t)(col + 16 * t) * kOut + kb * kLinBK +
+                                                        8 * grp);
 
     const int se = tid >> 5, sk = (tid & 31) * 16;   // staging: element se, columns sk .. sk + 15
-    uint4 lo0, hi0, lo1, hi1;
-    {
-        uint4 lo, hi;
-        ws_load_chunk(lo, hi, X, g, nchunks, nel, se, sk);
-        ws_load_chunk(lo0, hi0, X, g + groups, nchunks, nel, se, sk);
-        ws_load_chunk(lo1, hi1, X, g + 2 * groups, nchunks, nel, se, sk);
-        *reinterpret_cast<uint4*>(sx[0] + se * kWsLd + sk) = lo;
-        *reinterpret_cast<uint4*>(sx[0] + se * kWsLd + sk + 8) = hi;
-    }
     int32_t pos0[2][4], pos1[2][4];
     float kinv0[4], kinv1[4];
+    ws_stage(sx[0] + se * kWsLd + sk, ws_load_chunk(X, g, nchunks, nel, se, sk));
     ws_load_pos(pos0, kinv0, upos, kappa_inv, g, nel, grp, col);
+    // everything loaded so far (the W fragments above all) has arrived: the loop
+    // below then carries no pending-load state for W, and its only waits are for
+    // loads issued one (positions) or two (chunks) steps earlier
+    __builtin_amdgcn_s_waitcnt(0);
+    u32x8 nx0 = ws_load_chunk(X, g + groups, nchunks, nel, se, sk);
+    u32x8 nx1 = ws_load_chunk(X, g + 2 * groups, nchunks, nel, se, sk);
     __syncthreads();
 
     for (int64_t c = g; c < nchunks; c += 2 * groups) {
-        ws_step(zl, X, upos, kappa_inv, sx, w, c, 0, groups, nchunks, nel, lo0, hi0, pos0, kinv0, pos1, kinv1,
-                row, grp, col, se, sk);
+        ws_step(zl, X, upos, kappa_inv, sx, w, c, 0, groups, nchunks, nel, nx0, pos0, kinv0, pos1, kinv1, row,
+                grp, col, se, sk);
         if (c + groups >= nchunks) break;     // uniform over the block
-        ws_step(zl, X, upos, kappa_inv, sx, w, c + groups, 1, groups, nchunks, nel, lo1, hi1, pos1, kinv1, pos0,
+        ws_step(zl, X, upos, kappa_inv, sx, w, c + groups, 1, groups, nchunks, nel, nx1, pos1, kinv1, pos0,
                 kinv0, row, grp, col, se, sk);
     }
 }
