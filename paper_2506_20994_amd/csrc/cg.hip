@@ -642,9 +642,19 @@ int read_sums(sem_cg_t cg, double* s, double* q);
 // added to the float64 x, the residual is replaced by the float64 b - A x, and
 // the iteration continues with the same search direction.  Converged when
 // the replaced float64 residual meets tol.
+// stagnation guard of the network: records (iteration, r.r) and reports
+// whether r.r has failed to fall by 4x (the relative residual to halve) over
+// the last 256 iterations
+bool stagnated(std::vector<std::pair<int, double>>& hist, int it, double rr) {
+    hist.emplace_back(it, rr);
+    for (auto q = hist.rbegin(); q != hist.rend(); ++q)
+        if (it - q->first >= 256) return rr > 0.25 * q->second;
+    return false;
+}
+
 int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int check_every,
            double bnorm, int* iters_out, int* replacements, int* breakdown_out, double* hist, int nhist,
-           int* njac_out) {
+           int* njac_out, int* fell_back) {
     sem_ctx_t ctx = cg->ctx;
     hipStream_t st = ctx->stream;
     const int64_t n = cg->nu;
@@ -663,17 +673,20 @@ int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int chec
     int nrep = 0;
     float* z = (float*)lv.z;
     float* wu = (float*)lv.wu;
+    bool fallen = false;
+    std::vector<std::pair<int, double>> rr_hist;
     for (;;) {
         for (int q = 0; q < check_every; ++q) {
             if (cg->lp) {   // flexible CG step with the network (Jacobi where it is rejected)
                 const float* zl = nullptr;
                 bool jb = false;
-                int rc = sem::lp_apply_partial(cg->lp, r, false, &cg->S->done, &zl, &jb);
-                if (rc == SEM_OK) {
+                int rc = SEM_OK;
+                if (!fallen) rc = sem::lp_apply_partial(cg->lp, r, false, &cg->S->done, &zl, &jb);
+                if (!fallen && rc == SEM_OK) {
                     fcg_dots_asm_kernel<float><<<g, kBlock, 0, st>>>(z, zl, uoff, r, wu, minv, jb, n, cg->S,
                                                                      cg->part);
                 } else {
-                    rc = sem::lp_apply(cg->lp, z, r, false, &cg->S->done, true);
+                    if (!fallen) rc = sem::lp_apply(cg->lp, z, r, false, &cg->S->done, true);
                     if (rc) return rc;
                     fcg_dots_kernel<float><<<g, kBlock, 0, st>>>(r, z, wu, minv, n, cg->S, cg->part);
                 }
@@ -698,7 +711,14 @@ int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int chec
         SEM_HIP(ctx, hipMemcpyAsync(cg->S_host, cg->S, sizeof(Scal), hipMemcpyDeviceToHost, st));
         SEM_HIP(ctx, hipStreamSynchronize(st));
         const Scal& H = *cg->S_host;
-        if (!H.done) continue;
+        if (!H.done) {
+            if (cg->lp && !fallen && stagnated(rr_hist, H.it, H.rr)) {
+                set_fallback<<<1, 1, 0, st>>>(cg->S);      // Jacobi for good
+                SEM_LAUNCH_CHECK(ctx);
+                fallen = true;
+            }
+            continue;
+        }
         if (H.breakdown) break;
         // replacement: fold the update into x64, recompute the float64 residual
         rr_accumulate_kernel<<<g, kBlock, 0, st>>>(cg->x64, x, n);
@@ -728,6 +748,7 @@ int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int chec
     *replacements = nrep;
     *breakdown_out = cg->S_host->breakdown;
     *njac_out = cg->S_host->njac;
+    *fell_back = fallen ? 1 : 0;
     return SEM_OK;
 }
 
@@ -775,19 +796,10 @@ int fcg_run(sem_cg_t cg, Level& lv, const T* rhs, double tol, int maxit, int che
         SEM_HIP(ctx, hipMemcpyAsync(cg->S_host, cg->S, sizeof(Scal), hipMemcpyDeviceToHost, st));
         SEM_HIP(ctx, hipStreamSynchronize(st));
         if (cg->S_host->done) break;
-        // stagnation guard: relative residual not halved over 256 iterations
-        hist.emplace_back(cg->S_host->it, cg->S_host->rr);
-        if (!fallen) {
-            for (auto it = hist.rbegin(); it != hist.rend(); ++it) {
-                if (cg->S_host->it - it->first >= 256) {
-                    if (cg->S_host->rr > 0.25 * it->second) {   // rr is squared: halving = 1/4
-                        set_fallback<<<1, 1, 0, st>>>(cg->S);
-                        SEM_LAUNCH_CHECK(ctx);
-                        fallen = true;
-                    }
-                    break;
-                }
-            }
+        if (!fallen && stagnated(hist, cg->S_host->it, cg->S_host->rr)) {
+            set_fallback<<<1, 1, 0, st>>>(cg->S);
+            SEM_LAUNCH_CHECK(ctx);
+            fallen = true;
         }
     }
     *iters_out = cg->S_host->it;
@@ -1018,11 +1030,12 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
         Level& L = cg->lv32;
         const bool bf = cg->precision == SEM_SOLVE_BF16_IR;
         if (opts->ir_mode == 1) {
-            int its = 0, nrep = 0, brk = 0, nj = 0;
+            int its = 0, nrep = 0, brk = 0, nj = 0, fb = 0;
             rc = rr_run(cg, L, opts->tol, opts->delta > 0 ? opts->delta : 0.1, maxit, check, bnorm, &its,
-                        &nrep, &brk, stats->relres_hist, 64, &nj);
+                        &nrep, &brk, stats->relres_hist, 64, &nj, &fb);
             if (rc) return rc;
             stats->jacobi_steps = nj;
+            stats->fell_back = fb;
             stats->iterations = its + nrep;
             stats->outer = nrep;
             stats->breakdown = brk;

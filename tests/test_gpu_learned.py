@@ -320,6 +320,31 @@ def test_fcg_falls_back_to_jacobi(sem_ctx, kind):
         h.close()
 
 
+@pytest.mark.parametrize("prec,mode", [(0, 0), (1, 1)])
+def test_stagnating_network_switches_to_jacobi(sem_ctx, prec, mode):
+    """A network that is accepted on every iteration (r.z > 0) but stalls the
+    solve -- the linear form with the all-ones block, a positive semidefinite
+    preconditioner of rank <= nel -- trips the stagnation guard: the solve
+    switches to Jacobi for good (float64 flexible CG, and float32 residual
+    replacement) and converges."""
+    n, amp = 3, 0.1
+    op, lp = _box_with_lp(sem_ctx, n, amp)
+    P.sem_lp_set_linear(lp, 1)
+    W1 = np.zeros((256, 518)); W1[0, :512] = 1.0
+    W2 = np.zeros((256, 256)); W2[0, 0] = 1.0
+    W3 = np.zeros((512, 256)); W3[:, 0] = 1.0
+    _load(lp, [W1, np.zeros(256), W2, np.zeros(256), W3, np.zeros(512)])
+    k, a, ph = synth.fourier_modes(6)
+    b = op.fourier_rhs(k, a, ph)
+    x = torch.empty_like(b)
+    cg = op.solver(prec, learned=lp)
+    rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10, precision=prec, ir_mode=mode, learned=lp, maxit=20000)
+    assert st["fell_back"] == 1 and rc == P.SEM_FELL_BACK, st
+    assert st["converged"] and st["relres"] <= 1e-10
+    for h in (cg, lp):
+        h.close()
+
+
 @pytest.mark.parametrize("prec,linear", [(0, False), (1, False), (0, True), (1, True)])
 def test_fcg_untrained_network_converges(sem_ctx, prec, linear):
     n, amp = 3, 0.1
