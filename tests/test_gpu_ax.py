@@ -102,12 +102,15 @@ def test_ax_bf16(sem_ctx, lx):
     assert rel_inf(w.double().cpu().numpy(), ref) <= TOL_LOW
 
 
-def test_ax_full_size_sampled(sem_ctx):
-    """32^3 box (E = 32768), lx = 8, amplitude 0.1, h1 ~ U[0.5, 2] per unique
-    node, u ~ N(0, 1) per unique node: the benchmark's workload and launch.
-    Sampled elements are recomputed by the oracle from its own geometry."""
+@pytest.mark.parametrize("lx", [6, 8, 10, 12])
+def test_ax_full_size_sampled(sem_ctx, lx):
+    """32^3 box (E = 32768), amplitude 0.1, h1 ~ U[0.5, 2] per unique node,
+    u ~ N(0, 1) per unique node: the benchmark's workload and launch at lx = 8,
+    and the lx = 6, 10, 12 points of the throughput sweep (up to 56.6M local
+    nodes).  Sampled elements are recomputed by the oracle from its own
+    geometry."""
     from paper_2506_20994_amd.box import BoxOperator
-    n, lx, amp = 32, 8, 0.1
+    n, amp = 32, 0.1
     nu = (n * (lx - 1)) ** 3
     h1u = synth.unique_uniform(nu, 0.5, 2.0, 1)
     uu = synth.unique_normal(nu, 0)

@@ -72,3 +72,16 @@ def test_refinement_with_float32_inner_reaches_float64_tolerance():
     assert relres[-1] <= 1e-10 and outer >= 2
     xref, _, _ = pcg(P.apply, b, Minv, tol=1e-13)
     assert np.max(np.abs(x - xref)) < 1e-7 * np.max(np.abs(xref))
+
+
+def test_operator_at_nodes_matches_whole_mesh():
+    """The node-by-node operator used by the full-size GPU solve test equals the
+    oracle's assembled operator at every node."""
+    from tests.helpers import operator_at_nodes
+    from oracle.mesh import global_ids
+    n, lx, amp = 2, 4, 0.12
+    P = BoxProblem(n, lx, amp)
+    xG = synth.unique_normal(P.nu, 3)
+    got = operator_at_nodes(n, lx, amp, global_ids(n, lx), xG, np.arange(P.nu))
+    ref = P.apply(xG)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
