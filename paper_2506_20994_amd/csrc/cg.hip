@@ -67,13 +67,23 @@ __device__ double final_sum(const double* __restrict__ part, int n, int stride, 
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
 // assembled value of unique node u: sum of its local copies, which the
-// operator stored contiguously at wc[uoff[u] .. uoff[u+1]) (CSR order)
+// operator stored contiguously at wc[uoff[u] .. uoff[u+1]) (CSR order).  The
+// first eight copies (every node of a conforming hexahedral mesh) are loaded
+// by independent predicated loads, issued together, and summed in CSR order;
+// a longer segment continues in a loop.  The count of copies goes to *m.
 template <typename T>
 __device__ __forceinline__ T assemble(const T* __restrict__ wc, const int32_t* __restrict__ uoff,
-                                      int64_t u) {
+                                      int64_t u, int32_t* m = nullptr) {
     const int32_t b = uoff[u], e = uoff[u + 1];
-    T s = wc[b];
-    for (int32_t q = b + 1; q < e; ++q) s += wc[q];
+    T v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = b + q < e ? wc[b + q] : T(0);
+    T s = v[0];
+#pragma unroll
+    for (int q = 1; q < 8; ++q)
+        if (b + q < e) s += v[q];
+    for (int32_t q = b + 8; q < e; ++q) s += wc[q];
+    if (m) *m = e - b;
     return s;
 }
 
@@ -385,11 +395,10 @@ __global__ void fcg_dots_asm_kernel(T* __restrict__ z, const float* __restrict__
     const bool first = S->it == 0;
     double rz = 0.0, bad = 0.0, zw = 0.0, jw = 0.0;
     GRID_LOOP(u, n) {
-        const int32_t b = uoff[u], e = uoff[u + 1];
-        float s = 0.f;
-        for (int32_t q = b; q < e; ++q) s += zl[q];
+        int32_t m;
+        const float s = assemble(zl, uoff, u, &m);
         const T rt = r[u], mv = minv[u];
-        double zd = (double)s * rsqrt((double)(e - b));
+        double zd = (double)s * rsqrt((double)m);
         if (jbase) zd += (double)mv * (double)rt;
         const T zt = (T)zd;
         z[u] = zt;
