@@ -27,7 +27,12 @@
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kGrid = 8192;           // vector kernels: fixed grid -> fixed partial count
+// vector kernels run on a fixed grid (fixed partial count, deterministic
+// reductions): 8192 blocks for float64 vectors, 2048 for float32 ones, whose
+// lighter per-node traffic is better served by more nodes per thread and
+// shorter single-block finalisers (measured at 32^3, lx = 8)
+constexpr int kGrid = 8192;
+constexpr int kGrid32 = 2048;
 constexpr int kFinal = 1024;          // threads of the single-block finalisers
 
 struct Scal {
@@ -600,10 +605,13 @@ int cg_alloc(sem_cg_t cg, void** p, size_t bytes) {
     return SEM_OK;
 }
 
-unsigned vec_grid(int64_t n) {
+unsigned vec_grid(int64_t n, int cap = kGrid) {
     int64_t b = (n + kBlock - 1) / kBlock;
-    return (unsigned)(b < kGrid ? (b < 1 ? 1 : b) : kGrid);
+    return (unsigned)(b < cap ? (b < 1 ? 1 : b) : cap);
 }
+
+template <typename T>
+unsigned vec_grid_t(int64_t n) { return vec_grid(n, sizeof(T) == 8 ? kGrid : kGrid32); }
 
 // PCG on level lv from x = 0 with right-hand side rhs (unique, type T);
 // leaves the iterate in lv.x.
@@ -613,7 +621,7 @@ int pcg_run(sem_cg_t cg, Level& lv, const T* rhs, double tol, int maxit, int che
     sem_ctx_t ctx = cg->ctx;
     hipStream_t st = ctx->stream;
     const int64_t n = cg->nu;
-    const unsigned g = vec_grid(n);
+    const unsigned g = vec_grid_t<T>(n);
     T* x = (T*)lv.x; T* r = (T*)lv.r; T* p = (T*)lv.p; T* wl = (T*)lv.wl;
     const T* minv = (const T*)lv.minv;
     const int32_t *lid = cg->gs->lid, *uoff = cg->gs->uoff, *uidx = cg->gs->uidx;
@@ -667,7 +675,7 @@ int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int chec
     sem_ctx_t ctx = cg->ctx;
     hipStream_t st = ctx->stream;
     const int64_t n = cg->nu;
-    const unsigned g = vec_grid(n);
+    const unsigned g = vec_grid_t<float>(n);
     float* x = (float*)lv.x; float* r = (float*)lv.r; float* p = (float*)lv.p; float* wl = (float*)lv.wl;
     const float* minv = (const float*)lv.minv;
     const int32_t *lid = cg->gs->lid, *uoff = cg->gs->uoff, *uidx = cg->gs->uidx;
@@ -768,7 +776,7 @@ int fcg_run(sem_cg_t cg, Level& lv, const T* rhs, double tol, int maxit, int che
     sem_ctx_t ctx = cg->ctx;
     hipStream_t st = ctx->stream;
     const int64_t n = cg->nu;
-    const unsigned g = vec_grid(n);
+    const unsigned g = vec_grid_t<T>(n);
     T* x = (T*)lv.x; T* r = (T*)lv.r; T* p = (T*)lv.p; T* wl = (T*)lv.wl; T* z = (T*)lv.z;
     T* wu = (T*)lv.wu;
     const T* minv = (const T*)lv.minv;
