@@ -418,7 +418,7 @@ __global__ void lp_output_unique_kernel(T* __restrict__ z, const float* __restri
 
 // ---- linear form on unique-layout vectors ----------------------------------
 // zl[upos[L]] = (1/kappa_e) sum_k Ws[n][k] S_k r_k for every local node
-// L = (e, n) of an element, with S = mult^-1/2 per unique node (sq) and Ws the
+// L = (e, n) of an element, with S = mult^-1/2 (sl, per local node) and Ws the
 // symmetric folded matrix, so that summing zl over the copies of a node and
 // weighting by S gives the symmetric additive preconditioner.  Three passes:
 // a gather of S r into element-major bf16 rows (many waves, so the dependent
@@ -440,9 +440,11 @@ __device__ __forceinline__ bf16x8 pack_bf16x8(const float* v) {
     return __builtin_bit_cast(bf16x8, w);
 }
 
-// X[e][n] = bf16(S r) at the unique node of local node (e, n); 8 nodes per thread
+// X[e][n] = bf16(S r) at the unique node of local node (e, n); 8 nodes per
+// thread.  S comes per local node (sl, a coalesced stream), so r is the only
+// gathered array.
 template <typename T>
-__global__ void lin_gather_kernel(u16* __restrict__ X, const T* __restrict__ r, const float* __restrict__ sq,
+__global__ void lin_gather_kernel(u16* __restrict__ X, const T* __restrict__ r, const float* __restrict__ sl,
                                   const int32_t* __restrict__ lid, int64_t n8, const int* __restrict__ skip) {
     if (skip && *skip) return;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n8;
@@ -450,16 +452,28 @@ __global__ void lin_gather_kernel(u16* __restrict__ X, const T* __restrict__ r, 
         const int64_t L = t * 8;
         const int4 i0 = *reinterpret_cast<const int4*>(lid + L);
         const int4 i1 = *reinterpret_cast<const int4*>(lid + L + 4);
+        const float4 s0 = *reinterpret_cast<const float4*>(sl + L);
+        const float4 s1 = *reinterpret_cast<const float4*>(sl + L + 4);
         float v[8];
-        v[0] = (float)r[i0.x] * sq[i0.x];
-        v[1] = (float)r[i0.y] * sq[i0.y];
-        v[2] = (float)r[i0.z] * sq[i0.z];
-        v[3] = (float)r[i0.w] * sq[i0.w];
-        v[4] = (float)r[i1.x] * sq[i1.x];
-        v[5] = (float)r[i1.y] * sq[i1.y];
-        v[6] = (float)r[i1.z] * sq[i1.z];
-        v[7] = (float)r[i1.w] * sq[i1.w];
+        v[0] = (float)r[i0.x] * s0.x;
+        v[1] = (float)r[i0.y] * s0.y;
+        v[2] = (float)r[i0.z] * s0.z;
+        v[3] = (float)r[i0.w] * s0.w;
+        v[4] = (float)r[i1.x] * s1.x;
+        v[5] = (float)r[i1.y] * s1.y;
+        v[6] = (float)r[i1.z] * s1.z;
+        v[7] = (float)r[i1.w] * s1.w;
         *reinterpret_cast<bf16x8*>(X + (L / kOut) * kInPad + (L % kOut)) = pack_bf16x8(v);
+    }
+}
+
+// sl[L] = mult^-1/2 of local node L
+__global__ void sl_kernel(float* __restrict__ sl, const int32_t* __restrict__ lid, const int32_t* __restrict__ uoff,
+                          int64_t n) {
+    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
+         L += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = lid[L];
+        sl[L] = (float)(1.0 / sqrt((double)(uoff[u + 1] - uoff[u])));
     }
 }
 
@@ -613,12 +627,6 @@ __global__ void first_copy_kernel(double* __restrict__ out, const double* __rest
         out[u] = in[uidx[uoff[u]]];
 }
 
-__global__ void sq_kernel(float* __restrict__ sq, const int32_t* __restrict__ uoff, int64_t nu) {
-    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < nu;
-         u += (int64_t)gridDim.x * blockDim.x)
-        sq[u] = (float)(1.0 / sqrt((double)(uoff[u + 1] - uoff[u])));
-}
-
 __global__ void zero_f32(float* __restrict__ x, int n) {
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) x[q] = 0.f;
 }
@@ -673,8 +681,8 @@ struct sem_lp_s {
     bool jacobi_base = false;
     double* minv = nullptr;
     int64_t minv_n = 0;
-    float* sq = nullptr;      // mult^-1/2 per unique node of the bound plan
-    int64_t sq_n = 0;
+    float* sl = nullptr;      // mult^-1/2 per local node of the bound plan
+    int64_t sl_n = 0;
     double* minvu = nullptr;  // Minv on the unique nodes of the bound plan (Jacobi base)
     int64_t minvu_n = 0;
     std::vector<void*> allocs;
@@ -992,14 +1000,14 @@ extern "C" int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs) {
     geo_kernel<<<(unsigned)A->nel, 64, 0, ctx->stream>>>(lp->geo, lp->kappa, lp->kappa_inv, A->h1, A->g11, A->g22, A->g33,
                                                          A->g12, A->g13, A->g23, A->nel);
     SEM_LAUNCH_CHECK(ctx);
-    if (lp->sq_n < gs->n_unique) {
+    if (lp->sl_n < gs->n_local) {
         void* p = nullptr;
-        rc = lp_alloc(lp, &p, 4 * (size_t)gs->n_unique);
+        rc = lp_alloc(lp, &p, 4 * (size_t)gs->n_local);
         if (rc) return rc;
-        lp->sq = (float*)p;
-        lp->sq_n = gs->n_unique;
+        lp->sl = (float*)p;
+        lp->sl_n = gs->n_local;
     }
-    sq_kernel<<<grid_of(gs->n_unique), kBlock, 0, ctx->stream>>>(lp->sq, gs->uoff, gs->n_unique);
+    sl_kernel<<<grid_of(gs->n_local), kBlock, 0, ctx->stream>>>(lp->sl, gs->lid, gs->uoff, gs->n_local);
     SEM_LAUNCH_CHECK(ctx);
     if (lp->jacobi_base) {
         const int64_t n = A->nel * kOut;
@@ -1209,7 +1217,7 @@ int lin_product(sem_lp_t lp, const T* r) {
     sem_ctx_t ctx = lp->ctx;
     hipStream_t st = ctx->stream;
     const int64_t nel = lp->nel;
-    lin_gather_kernel<T><<<grid_of(nel * kOut / 8, 8192), kBlock, 0, st>>>(lp->X, r, lp->sq, lp->gs->lid,
+    lin_gather_kernel<T><<<grid_of(nel * kOut / 8, 8192), kBlock, 0, st>>>(lp->X, r, lp->sl, lp->gs->lid,
                                                                        nel * kOut / 8, lp->skip);
     SEM_LAUNCH_CHECK(ctx);
     const int64_t nchunks = (nel + kWsChunk - 1) / kWsChunk;
