@@ -127,7 +127,7 @@ def learned_comparison(ctx, P, n, lx, amp, solve=None, tol=1e-10):
     lp = P.sem_lp_create(ctx, n ** 3)
     LR.init_network(lp, 7, mu=1.0, jacobi_base=True, out_scale=0.0, linear=True)
     t0 = time.perf_counter()
-    X, T, info = LR.generate(ctx, lp, n=16, boxes=64, snapshots=1, elems_per_snapshot=4096,
+    X, T, info = LR.generate(ctx, lp, n=16, boxes=128, snapshots=1, elems_per_snapshot=4096,
                              rhs="noise", include_zero=True)
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
