@@ -283,6 +283,17 @@ int sem_lp_get(sem_lp_t lp, int which, float* host, int64_t count);
 /* Adam's step counter (the number of updates taken). */
 int sem_lp_set_step(sem_lp_t lp, int64_t step);
 int sem_lp_get_step(sem_lp_t lp, int64_t* step);
+/* Checkpoint of the network: its form (linear, Jacobi base), training metric,
+ * Adam step, parameters and Adam moments, to a binary file ("SEMLP001",
+ * version 1, little-endian: int32 version, linear, jacobi_base; double mu;
+ * int64 step; then for each of slots 0..17 an int64 count and that many
+ * float32 values).  sem_lp_load reads and checks the whole file before it
+ * changes anything (SEM_EINVAL for a missing, truncated or foreign file);
+ * loading then equals sem_lp_set_linear / _set_jacobi_base / _set_metric /
+ * sem_lp_set of slots 0..17 / sem_lp_set_step, so training resumes bitwise
+ * and the Jacobi base takes effect at the next sem_lp_bind.  Synchronous. */
+int sem_lp_save(sem_lp_t lp, const char* path);
+int sem_lp_load(sem_lp_t lp, const char* path);
 /* Training loss.  mu < 0: mean squared error (the default).  mu >= 0: the
  * batch mean of (y - t)^T K (y - t) with K = A_ref + mu B_ref, where A_ref is
  * the stiffness matrix of the undeformed reference element [-1, 1]^3 divided

@@ -16,7 +16,7 @@ __all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONV
            "CgSolver", "SEM_SOLVE_F64", "SEM_SOLVE_F32_IR", "SEM_SOLVE_BF16_IR",
            "LearnedPrecond", "sem_lp_create", "sem_lp_destroy", "sem_lp_set", "sem_lp_get",
            "sem_lp_set_step", "sem_lp_get_step", "sem_lp_bind", "sem_lp_samples", "sem_lp_forward",
-           "sem_lp_gradients", "sem_lp_adam", "sem_lp_set_metric", "sem_lp_set_jacobi_base", "sem_lp_set_linear", "sem_lp_train_step", "sem_lp_apply", "sem_lp_apply_unique", "LP_SLOTS",
+           "sem_lp_gradients", "sem_lp_adam", "sem_lp_set_metric", "sem_lp_set_jacobi_base", "sem_lp_set_linear", "sem_lp_train_step", "sem_lp_apply", "sem_lp_apply_unique", "sem_lp_save", "sem_lp_load", "LP_SLOTS",
            "SEM_LP_IN", "SEM_LP_IN_PAD", "SEM_LP_HIDDEN", "SEM_LP_OUT"]
 
 SEM_LP_IN, SEM_LP_IN_PAD, SEM_LP_HIDDEN, SEM_LP_OUT = 518, 528, 256, 512
@@ -105,6 +105,8 @@ EXPORTS = {
     "sem_lp_train_step": (_int, [_vp, _vp, _vp, _vp, _i64, _dbl, _vp]),
     "sem_lp_apply": (_int, [_vp, _vp, _vp, _int]),
     "sem_lp_apply_unique": (_int, [_vp, _vp, _vp, _int]),
+    "sem_lp_save": (_int, [_vp, ctypes.c_char_p]),
+    "sem_lp_load": (_int, [_vp, ctypes.c_char_p]),
     "sem_lp_set_metric": (_int, [_vp, _dbl]),
     "sem_lp_set_jacobi_base": (_int, [_vp, _int]),
     "sem_lp_set_linear": (_int, [_vp, _int]),
@@ -476,6 +478,16 @@ def sem_lp_train_step(lp, X, T, rows, lr, loss_dev):
 def sem_lp_apply(lp, z, r):
     lp.ctx.bind()
     _check(lib().sem_lp_apply(lp.handle, _ptr(z), _ptr(r), dtype_code(r)), lp.ctx.handle)
+
+
+def sem_lp_save(lp, path):
+    lp.ctx.bind()
+    _check(lib().sem_lp_save(lp.handle, os.fsencode(path)), lp.ctx.handle)
+
+
+def sem_lp_load(lp, path):
+    lp.ctx.bind()
+    _check(lib().sem_lp_load(lp.handle, os.fsencode(path)), lp.ctx.handle)
 
 
 def sem_lp_apply_unique(lp, z, r):

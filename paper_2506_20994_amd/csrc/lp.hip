@@ -653,6 +653,7 @@ struct sem_lp_s {
     int64_t step = 0;
     // bf16 copies: W1 (256 x 528), W2 (256 x 256), W3 (512 x 256), W2^T, W3^T
     u16 *W1b = nullptr, *W2b = nullptr, *W3b = nullptr, *W2t = nullptr, *W3t = nullptr;
+    double mu = -1.0;         // training metric (< 0: mean squared error)
     bool dirty = true;        // bf16 copies of the weights out of date
     bool fold_dirty = true;   // folded matrix of the linear form out of date
     float* colpart = nullptr; // column-sum partials (bias gradients)
@@ -884,6 +885,7 @@ extern "C" int sem_lp_set_metric(sem_lp_t lp, double mu) {
     sem_ctx_t ctx = lp->ctx;
     int rc = sem::enter(ctx);
     if (rc) return rc;
+    lp->mu = mu < 0 ? -1.0 : mu;
     if (mu < 0) {            // back to the plain mean squared error
         lp->K = nullptr;
         return SEM_OK;
@@ -1316,4 +1318,75 @@ extern "C" int sem_lp_apply_unique(sem_lp_t lp, void* z, const void* r, sem_dtyp
     if (!z || !r || z == r || (dtype != SEM_F64 && dtype != SEM_F32))
         return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_apply_unique: bad argument");
     return sem::lp_apply(lp, z, r, dtype == SEM_F64, nullptr, true);
+}
+
+// ---- checkpoint file -------------------------------------------------------
+// "SEMLP001", int32 version 1, int32 linear, int32 jacobi_base, double mu,
+// int64 Adam step, then for each of the 18 slots 0..17 (parameters, first and
+// second moments, in sem_lp_set order) int64 count + count float32 values.
+namespace {
+constexpr char kMagic[8] = {'S', 'E', 'M', 'L', 'P', '0', '0', '1'};
+}
+
+extern "C" int sem_lp_save(sem_lp_t lp, const char* path) {
+    if (!lp || !path) return sem::fail(lp ? lp->ctx : nullptr, SEM_EINVAL, "sem_lp_save: null argument");
+    int rc = sem::enter(lp->ctx);
+    if (rc) return rc;
+    std::vector<std::vector<float>> slots(18);
+    for (int w = 0; w < 18; ++w) {
+        int64_t n;
+        int ld;
+        param_slot(lp, w, &n, &ld);
+        slots[w].resize((size_t)n);
+        rc = sem_lp_get(lp, w, slots[w].data(), n);
+        if (rc) return rc;
+    }
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_save: cannot open %s", path);
+    const int32_t hdr[3] = {1, lp->linear ? 1 : 0, lp->jacobi_base ? 1 : 0};
+    const int64_t step = lp->step;
+    bool ok = std::fwrite(kMagic, 1, 8, f) == 8 && std::fwrite(hdr, 4, 3, f) == 3 &&
+              std::fwrite(&lp->mu, 8, 1, f) == 1 && std::fwrite(&step, 8, 1, f) == 1;
+    for (int w = 0; ok && w < 18; ++w) {
+        const int64_t n = (int64_t)slots[w].size();
+        ok = std::fwrite(&n, 8, 1, f) == 1 && std::fwrite(slots[w].data(), 4, (size_t)n, f) == (size_t)n;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_save: write to %s failed", path);
+    return SEM_OK;
+}
+
+extern "C" int sem_lp_load(sem_lp_t lp, const char* path) {
+    if (!lp || !path) return sem::fail(lp ? lp->ctx : nullptr, SEM_EINVAL, "sem_lp_load: null argument");
+    int rc = sem::enter(lp->ctx);
+    if (rc) return rc;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_load: cannot open %s", path);
+    char magic[8];
+    int32_t hdr[3];
+    double mu;
+    int64_t step;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMagic, 8) == 0 &&
+              std::fread(hdr, 4, 3, f) == 3 && hdr[0] == 1 && std::fread(&mu, 8, 1, f) == 1 &&
+              std::fread(&step, 8, 1, f) == 1 && step >= 0;
+    std::vector<std::vector<float>> slots(18);
+    for (int w = 0; ok && w < 18; ++w) {
+        int64_t n, want;
+        int ld;
+        param_slot(lp, w, &want, &ld);
+        ok = std::fread(&n, 8, 1, f) == 1 && n == want;
+        if (ok) {
+            slots[w].resize((size_t)n);
+            ok = std::fread(slots[w].data(), 4, (size_t)n, f) == (size_t)n;
+        }
+    }
+    std::fclose(f);
+    if (!ok) return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_load: %s is not a network checkpoint of this shape", path);
+    // nothing is changed before the whole file has been read and checked
+    rc = sem_lp_set_linear(lp, hdr[1]);
+    if (!rc) rc = sem_lp_set_jacobi_base(lp, hdr[2]);
+    if (!rc) rc = sem_lp_set_metric(lp, mu);
+    for (int w = 0; !rc && w < 18; ++w) rc = sem_lp_set(lp, w, slots[w].data(), (int64_t)slots[w].size());
+    if (!rc) rc = sem_lp_set_step(lp, step);
+    return rc;
 }
