@@ -25,7 +25,9 @@ Extra fields:
                 residual replacement around float32 / bfloat16-factor iterations.
 
 --mode copy times a plain 1 GiB device copy (used to calibrate the HBM byte
-counters of rocprofv3); it prints nothing on stdout.
+counters of rocprofv3); it prints nothing on stdout.  --mode scale runs the
+full stack on a 64^3 box (lx 8 and 10; several minutes) and prints one JSON
+line of its own.
 """
 import argparse
 import hashlib
@@ -174,6 +176,73 @@ def learned_comparison(ctx, P, n, lx, amp, solve=None, tol=1e-10):
     return res
 
 
+def scale_run(ctx, P, n=64, amp=0.15, tol=1e-10):
+    """The full stack at scale (--mode scale): a 64^3 box (E = 262144) with
+    amplitude 0.15 at lx = 8 (134M local nodes) and lx = 10 (262M): operator
+    throughput, float64 Jacobi-PCG against float32 residual replacement, and at
+    lx = 8 the network (trained as in learned_comparison on 16^3 boxes) with
+    float32 / bfloat16 residual replacement.  Several minutes of GPU time."""
+    import torch
+    import synth
+    from paper_2506_20994_amd.box import BoxOperator
+    from paper_2506_20994_amd import learned as LR
+    lp = P.sem_lp_create(ctx, n ** 3)
+    LR.init_network(lp, 7, mu=1.0, jacobi_base=True, out_scale=0.0, linear=True)
+    t0 = time.perf_counter()
+    X, T, _ = LR.generate(ctx, lp, n=16, boxes=128, snapshots=1, elems_per_snapshot=4096,
+                          rhs="noise", include_zero=True)
+    LR.train(lp, X, T, epochs=60, batch=1024, lr=3e-4)
+    del X, T
+    torch.cuda.empty_cache()
+    res = {"workload": f"{n}^3 box amplitude {amp}, h1=1, 32 Fourier modes, tol {tol}",
+           "training_s": round(time.perf_counter() - t0, 1)}
+    for lx in (8, 10):
+        op = BoxOperator(ctx, n, lx, amp)
+        r = {"n_local": op.n_local}
+        u = op.scatter(synth.unique_normal(op.n_unique, 0))
+        w = torch.empty_like(u)
+        for _ in range(3):
+            op.ax(w, u)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            op.ax(w, u)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / 10 * 1e3
+        r["ax_us"] = round(us, 1)
+        r["ax_gbs"] = round(BYTES_PER_NODE_F64 * op.n_local / us / 1e3, 1)
+        r["ax_gdofs"] = round(op.nel * (lx - 1) ** 3 / us / 1e3, 2)
+        del u, w
+        k, a, ph = synth.fourier_modes(2)
+        b = op.fourier_rhs(k, a, ph)
+        x = torch.empty_like(b)
+        variants = [("fp64_pcg", P.SEM_SOLVE_F64, 0, None), ("f32_rr", P.SEM_SOLVE_F32_IR, 1, None)]
+        if lx == 8:
+            op.bind(lp)
+            variants += [("learned_f32_rr", P.SEM_SOLVE_F32_IR, 1, lp),
+                         ("learned_bf16_rr", P.SEM_SOLVE_BF16_IR, 1, lp)]
+        for name, code, mode, L in variants:
+            cg = op.solver(code, learned=L)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st = P.sem_cg_solve(cg, x, b, tol=tol, precision=code, ir_mode=mode, learned=L, maxit=200000)
+            torch.cuda.synchronize()
+            r[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 1), "iterations": st["iterations"],
+                       "relres": st["relres"], "converged": st["converged"],
+                       "jacobi_steps": st["jacobi_steps"], "fell_back": st["fell_back"]}
+            print(f"[bench] scale lx={lx} {name}: {r[name]['ms']:.0f} ms, {st['iterations']} its",
+                  file=sys.stderr, flush=True)
+            cg.close()
+        r["speedup_vs_fp64_pcg"] = {v[0]: round(r["fp64_pcg"]["ms"] / r[v[0]]["ms"], 3) for v in variants[1:]}
+        res[f"lx{lx}"] = r
+        op.gs.close()
+        del op, b, x
+        torch.cuda.empty_cache()
+    lp.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,7 +254,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--mode", default="bench", choices=["bench", "copy"])
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "scale"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this library runs on one GPU; --gpus {args.gpus} is not supported",
@@ -206,6 +275,12 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(f"[bench] copied {args.steps} x {a.numel() * 8} bytes", file=sys.stderr)
+        return
+    if args.mode == "scale":
+        ctx = P.sem_create()
+        print(json.dumps({"mode": "scale", "n_gpus": 1, "dtype": "f64",
+                          "scale": scale_run(ctx, P)}), flush=True)
+        ctx.close()
         return
     n, lx, amp = args.n, args.lx, args.amp
     nu = (n * (lx - 1)) ** 3

@@ -313,6 +313,10 @@ __global__ void wsum_final(double* __restrict__ out, const double* __restrict__ 
     if (threadIdx.x == 0) out[0] = s;
 }
 
+__global__ void add_kernel(double* __restrict__ x, const double* __restrict__ d, int64_t n) {
+    GRID_LOOP(u, n) x[u] += d[u];
+}
+
 __global__ void zero_kernel(double* __restrict__ x, int64_t n) {
     GRID_LOOP(u, n) x[u] = 0.0;
 }
@@ -590,6 +594,7 @@ struct sem_cg_s {
     double* sums_host = nullptr;   // pinned
     Level lv64{}, lv32{};
     double *b64 = nullptr, *x64 = nullptr, *r64 = nullptr;   // unique float64
+    double* d64 = nullptr;         // float64 solves: correction after a true-residual check
     double* wl64 = nullptr;                                    // local float64
     float* rhs32 = nullptr;        // IR: normalised inner right-hand side (unique)
     sem_lp_t lp = nullptr;
@@ -652,13 +657,6 @@ int residual64(sem_cg_t cg, const double* xu);
 template <typename T> int vec_sums(sem_cg_t cg, const T* a);
 int read_sums(sem_cg_t cg, double* s, double* q);
 
-// Mixed-precision CG with residual replacement (reliable updates; Strzodka
-// and Goeddeke 2006, Clark et al. 2010): float32 vectors and the reduced
-// operator drive the Krylov iteration; whenever the float32 residual has
-// fallen by `delta` since the last replacement, the accumulated update is
-// added to the float64 x, the residual is replaced by the float64 b - A x, and
-// the iteration continues with the same search direction.  Converged when
-// the replaced float64 residual meets tol.
 // stagnation guard of the network: records (iteration, r.r) and reports
 // whether r.r has failed to fall by 4x (the relative residual to halve) over
 // the last 256 iterations
@@ -669,6 +667,13 @@ bool stagnated(std::vector<std::pair<int, double>>& hist, int it, double rr) {
     return false;
 }
 
+// Mixed-precision CG with residual replacement (reliable updates; Strzodka
+// and Goeddeke 2006, Clark et al. 2010): float32 vectors and the reduced
+// operator drive the Krylov iteration; whenever the float32 residual has
+// fallen by `delta` since the last replacement, the accumulated update is
+// added to the float64 x, the residual is replaced by the float64 b - A x, and
+// the iteration continues with the same search direction.  Converged when
+// the replaced float64 residual meets tol.
 int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int check_every,
            double bnorm, int* iters_out, int* replacements, int* breakdown_out, double* hist, int nhist,
            int* njac_out, int* fell_back) {
@@ -943,6 +948,7 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
         L64.x = cg->x64;
         L64.wl = cg->wl64;
         if (cg->lp) { CG_ALLOC(L64.z, u64); CG_ALLOC(L64.wu, u64); }
+        CG_ALLOC(cg->d64, u64);
         assembled_recip_kernel<double><<<gu, kBlock, 0, st>>>((double*)L64.minv, cg->wl64, gs->uoff, gs->uidx, nu);
     } else {
         Level& L = cg->lv32;
@@ -1039,6 +1045,34 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
         if (cg->lp) rc = fcg_run<double>(cg, L, cg->b64, opts->tol, maxit, check, &its, &brk, &nj, &fb);
         else rc = pcg_run<double>(cg, L, cg->b64, opts->tol, maxit, check, &its, &brk);
         if (rc) return rc;
+        // The Krylov loop stops on its recursively updated residual, which can
+        // drift below the true one.  Check b - A x in float64; while it misses
+        // tol, solve A d = r to the relative tolerance that closes the gap and
+        // add d to x (at most four times, within the same iteration budget).
+        for (int pass = 0; pass < 4 && !brk && its < maxit; ++pass) {
+            rc = residual64(cg, cg->x64);
+            if (!rc) rc = vec_sums(cg, cg->r64);
+            double rs, rq;
+            if (!rc) rc = read_sums(cg, &rs, &rq);
+            if (rc) return rc;
+            const double rnorm = std::sqrt(rq);
+            if (!(rnorm > opts->tol * bnorm)) break;
+            sub_mean_kernel<<<gu, kBlock, 0, st>>>(cg->r64, cg->sums, (double)nu, nu);
+            SEM_LAUNCH_CHECK(ctx);
+            const double tol_d = opts->tol * bnorm / rnorm;
+            int its_d = 0, brk_d = 0, nj_d = 0, fb_d = 0;
+            L.x = cg->d64;                       // the correction goes to d64, x64 is kept
+            if (cg->lp) rc = fcg_run<double>(cg, L, cg->r64, tol_d, maxit - its, check, &its_d, &brk_d, &nj_d, &fb_d);
+            else rc = pcg_run<double>(cg, L, cg->r64, tol_d, maxit - its, check, &its_d, &brk_d);
+            L.x = cg->x64;
+            if (rc) return rc;
+            add_kernel<<<gu, kBlock, 0, st>>>(cg->x64, cg->d64, nu);
+            SEM_LAUNCH_CHECK(ctx);
+            its += its_d;
+            brk |= brk_d;
+            nj += nj_d;
+            fb |= fb_d;
+        }
         stats->jacobi_steps = nj;
         stats->fell_back = fb;
         stats->iterations = its;
