@@ -12,6 +12,8 @@ Extra fields:
   cpu_baseline  the plain-C oracle loop nest timed on this host's cores on a
                 bounded sample of the same workload shape.
   gs            gather-scatter timing on the same mesh.
+  helmholtz     sem_ax_helmholtz (h2b = the mass, one more stream: 80 B per node)
+                on the same mesh.
   solve         Poisson solve to relative residual 1e-10 on the same 32^3 lx = 8
                 box (amplitude 0.1, h1 = 1, right-hand side of 32 random Fourier
                 modes with |k|_inf <= 8, mean removed): float64 Jacobi-PCG against
@@ -324,6 +326,18 @@ def main():
     torch.cuda.synchronize()
     gs_ms = g0.elapsed_time(g1) / gsteps
 
+    # Helmholtz form (h2 = 1: h2b = bm) on the same mesh: one more stream
+    h0 = torch.cuda.Event(enable_timing=True)
+    h1e = torch.cuda.Event(enable_timing=True)
+    for _ in range(5):
+        P.sem_ax_helmholtz(ctx, w, u, *op.D, op.h1, *op.G, op.bm, op.nel, lx)
+    h0.record(stream)
+    for _ in range(gsteps):
+        P.sem_ax_helmholtz(ctx, w, u, *op.D, op.h1, *op.G, op.bm, op.nel, lx)
+    h1e.record(stream)
+    torch.cuda.synchronize()
+    helm_ms = h0.elapsed_time(h1e) / gsteps
+
     n_local = op.n_local
     ms_per_step = wall * 1e3 / args.steps
     gdofs = nel_dofs = op.nel * (lx - 1) ** 3
@@ -355,6 +369,9 @@ def main():
                      "alg_bytes_per_launch": alg_bytes},
         "gs": {"avg_launch_us": round(gs_ms * 1e3, 2), "shared_ids": n_shared,
                "alg_bytes_per_launch": None},
+        "helmholtz": {"avg_launch_us": round(helm_ms * 1e3, 2),
+                      "alg_bytes_per_launch": (BYTES_PER_NODE_F64 + 8) * n_local,
+                      "achieved_gbs": round((BYTES_PER_NODE_F64 + 8) * n_local / (helm_ms * 1e-3) / 1e9, 1)},
     }
     if not args.no_solve:
         del op, u, w

@@ -148,6 +148,21 @@ int sem_ax(sem_ctx_t ctx, void* w, const void* u,
            const void* g12, const void* g13, const void* g23,
            int64_t nel, int lx, sem_dtype_t field_dtype, sem_dtype_t out_dtype);
 
+/* Helmholtz form of the operator: w = A_e u + h2b .* u on every element, the
+ * stiffness of sem_ax plus the diagonal mass term h2 B u of the velocity
+ * (Helmholtz) solves.  The paper's routine bears that name (ax_helm, Listing
+ * 1) while its arithmetic (Listing 2) carries only the h1 stiffness; this is
+ * the adjacent step.  h2b = h2 * bm per local node (bm: the diagonal mass of
+ * sem_geometry; h2: the Helmholtz coefficient), stored in field_dtype like u;
+ * it must not be NULL.  Every other argument, type and rule as in sem_ax; the
+ * extra stream makes it 80 B per local node in float64. */
+int sem_ax_helmholtz(sem_ctx_t ctx, void* w, const void* u,
+                     const void* dx, const void* dy, const void* dz,
+                     const void* dxt, const void* dyt, const void* dzt,
+                     const void* h1, const void* g11, const void* g22, const void* g33,
+                     const void* g12, const void* g13, const void* g23, const void* h2b,
+                     int64_t nel, int lx, sem_dtype_t field_dtype, sem_dtype_t out_dtype);
+
 /* ---------------------------------------------------------- gather-scatter */
 
 /* Build the gather-scatter plan (Sec. 2.1) for a local numbering: ids (host

@@ -22,6 +22,12 @@ u^T A u >= 0; exact energy for polynomials of total degree <= N on affine
 elements; lx = 2 reduces to h times the 7-point Laplacian; Kronecker closed
 form on uniform boxes; swapping dx and dxt is detected
 (tests/test_oracle_ax.py, tests/test_oracle_assemble.py).
+
+ax_helmholtz adds the diagonal mass term of the Helmholtz form (the routine of
+Listing 1 is named ax_helm; Listing 2 carries only the h1 stiffness):
+w = A_e u + h2b u with h2b = h2 w_i w_j w_k |J| per node.  Pins: on affine
+elements u^T w = int |grad u|^2 + h2 int u^2 exactly for total degree <= N - 1,
+not beyond; the assembled A + h2 B is positive definite where A is singular.
 """
 import numpy as np
 
@@ -116,3 +122,9 @@ def ax_dense(u, Dh, h1, G):
         Ae = element_matrix(Dh, None if h1 is None else h1[e], tuple(g[e] for g in G))
         w[e] = (Ae @ u[e].ravel()).reshape(lx, lx, lx)
     return w
+
+
+def ax_helmholtz(u, dx, dy, dz, dxt, dyt, dzt, h1, g11, g22, g33, g12, g13, g23, h2b):
+    """Helmholtz form: the stiffness of ax_einsum plus the diagonal mass term
+    h2b * u, with h2b = h2 B per local node (B = w_i w_j w_k |J|)."""
+    return ax_einsum(u, dx, dy, dz, dxt, dyt, dzt, h1, g11, g22, g33, g12, g13, g23) + h2b * u

@@ -9,7 +9,7 @@ __all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONV
            "SEM_FELL_BACK", "SEM_EINVAL", "SEM_EUNSUPPORTED_LX", "SEM_EHIP", "SEM_EBREAKDOWN",
            "SEM_ENOMEM", "SEM_EGEOMETRY", "lib", "lib_path", "sem_create", "sem_destroy",
            "sem_sync", "sem_gll", "sem_box_mesh", "sem_geometry", "sem_scatter",
-           "sem_ax_diag", "sem_fourier", "sem_convert", "sem_ax", "sem_gs_setup",
+           "sem_ax_diag", "sem_fourier", "sem_convert", "sem_ax", "sem_ax_helmholtz", "sem_gs_setup",
            "sem_gs_destroy", "sem_gs_info", "sem_gs", "sem_gs_mult", "Context", "GsPlan",
            "dtype_code", "EXPORTS", "sem_gs_owner", "sem_remove_mean", "sem_cg_setup",
            "sem_cg_destroy", "sem_cg_solve", "SemOperator", "SemSolveOpts", "SemSolveStats",
@@ -81,6 +81,7 @@ EXPORTS = {
     "sem_fourier": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i64, _pi64, _pdbl, _pdbl, _int]),
     "sem_convert": (_int, [_vp, _vp, _int, _vp, _int, _i64]),
     "sem_ax": (_int, [_vp, _vp, _vp] + [_vp] * 6 + [_vp] * 7 + [_i64, _int, _int, _int]),
+    "sem_ax_helmholtz": (_int, [_vp, _vp, _vp] + [_vp] * 6 + [_vp] * 7 + [_vp, _i64, _int, _int, _int]),
     "sem_gs_setup": (_int, [_vp, _pi64, _i64, ctypes.POINTER(_vp)]),
     "sem_gs_destroy": (_int, [_vp]),
     "sem_gs_info": (_int, [_vp, _pi64, _pi64]),
@@ -292,6 +293,16 @@ def sem_ax(ctx, w, u, dx, dy, dz, dxt, dyt, dzt, h1, g11, g22, g33, g12, g13, g2
     _check(lib().sem_ax(h, _ptr(w), _ptr(u), _ptr(dx), _ptr(dy), _ptr(dz), _ptr(dxt), _ptr(dyt),
                         _ptr(dzt), _ptr(h1), _ptr(g11), _ptr(g22), _ptr(g33), _ptr(g12),
                         _ptr(g13), _ptr(g23), nel, lx, fd, od), h)
+
+
+def sem_ax_helmholtz(ctx, w, u, dx, dy, dz, dxt, dyt, dzt, h1, g11, g22, g33, g12, g13, g23, h2b, nel,
+                     lx, field_dtype=None, out_dtype=None):
+    h = ctx.bind()
+    fd = dtype_code(u) if field_dtype is None else field_dtype
+    od = dtype_code(w) if out_dtype is None else out_dtype
+    _check(lib().sem_ax_helmholtz(h, _ptr(w), _ptr(u), _ptr(dx), _ptr(dy), _ptr(dz), _ptr(dxt), _ptr(dyt),
+                                  _ptr(dzt), _ptr(h1), _ptr(g11), _ptr(g22), _ptr(g33), _ptr(g12),
+                                  _ptr(g13), _ptr(g23), _ptr(h2b), nel, lx, fd, od), h)
 
 
 def sem_gs_setup(ctx, ids_host):

@@ -134,7 +134,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
           const TS* __restrict__ g33, const TS* __restrict__ g12, const TS* __restrict__ g13,
           const TS* __restrict__ g23, int64_t nel, const int* __restrict__ skip,
           double* __restrict__ dot, const int32_t* __restrict__ lid,
-          const int32_t* __restrict__ pos, const TS* __restrict__ gp) {
+          const int32_t* __restrict__ pos, const TS* __restrict__ gp, const TS* __restrict__ hb) {
     constexpr int L2 = LX * LX;
     constexpr int L3 = L2 * LX;
     constexpr bool WP = Shape<LX>::kWavePrivate;
@@ -242,8 +242,12 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
             acc += dj[l] * ss[k * L2 + l * LX + i];
         }
         if (live) {
-            if constexpr (GATHER) w[__builtin_nontemporal_load(pos + base + k * L2)] = (TW)acc;
-            else store_nt(w, base + k * L2, (TW)acc);
+            if constexpr (GATHER) {
+                w[__builtin_nontemporal_load(pos + base + k * L2)] = (TW)acc;
+            } else {
+                if (hb) acc += Load<TS>::get(hb, base + k * L2) * uc[k];   // Helmholtz: + h2 B u
+                store_nt(w, base + k * L2, (TW)acc);
+            }
         }
         if (FUSE) pw += (double)uc[k] * (double)(TW)acc;
     }
@@ -290,7 +294,7 @@ ax3d_kernel(TW* __restrict__ w, const TS* __restrict__ u,
             const TC* __restrict__ dxt, const TC* __restrict__ dyt, const TC* __restrict__ dzt,
             const TS* __restrict__ h1, const TS* __restrict__ g11, const TS* __restrict__ g22,
             const TS* __restrict__ g33, const TS* __restrict__ g12, const TS* __restrict__ g13,
-            const TS* __restrict__ g23, int64_t nel) {
+            const TS* __restrict__ g23, int64_t nel, const TS* __restrict__ hb) {
     constexpr int L2 = LX * LX;
     constexpr int L3 = L2 * LX;
     __shared__ TC s_u[EPB * L3];
@@ -348,22 +352,24 @@ ax3d_kernel(TW* __restrict__ w, const TS* __restrict__ u,
         acc += dj[l] * ss[k * L2 + l * LX + i];
         acc += dk[l] * st[l * L2 + j * LX + i];
     }
+    if (live && hb) acc += Load<TS>::get(hb, g) * uv;   // Helmholtz: + h2 B u
     if (live) store_nt(w, g, (TW)acc);
 }
 
 template <int LX, typename TU, typename TS, typename TC, typename TW>
 int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const void* h1,
               const void* const* G, int64_t nel, const int* skip, double* dot, const int32_t* lid,
-              const int32_t* pos, const void* gp) {
+              const int32_t* pos, const void* gp, const void* hb) {
     constexpr int EPB = Shape<LX>::EPB;
     const int64_t blocks = (nel + EPB - 1) / EPB;
     if (blocks > 0x7fffffff) return sem::fail(ctx, SEM_EINVAL, "sem_ax: nel too large");
 #define SEM_AX_ARGS (TW*)w, (const TU*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2], \
         (const TC*)D[3], (const TC*)D[4], (const TC*)D[5], (const TS*)h1, (const TS*)G[0],  \
         (const TS*)G[1], (const TS*)G[2], (const TS*)G[3], (const TS*)G[4], (const TS*)G[5], \
-        nel, skip, dot, lid, pos, (const TS*)gp
+        nel, skip, dot, lid, pos, (const TS*)gp, (const TS*)hb
     const dim3 grid((unsigned)blocks), block(EPB * LX * LX);
     if (lid && !gp) return sem::fail(ctx, SEM_EINVAL, "launch_ax: the solver form needs packed factors");
+    if (lid && hb) return sem::fail(ctx, SEM_EINVAL, "launch_ax: the solver form has no Helmholtz term");
     if constexpr (LX == 3) {
         if (!lid && !dot) {
             constexpr int E3 = Shape3D<LX>::EPB;
@@ -371,7 +377,7 @@ int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const
             ax3d_kernel<LX, E3, TS, TC, TW><<<(unsigned)b3, E3 * LX * LX * LX, 0, ctx->stream>>>(
                 (TW*)w, (const TS*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2], (const TC*)D[3],
                 (const TC*)D[4], (const TC*)D[5], (const TS*)h1, (const TS*)G[0], (const TS*)G[1],
-                (const TS*)G[2], (const TS*)G[3], (const TS*)G[4], (const TS*)G[5], nel);
+                (const TS*)G[2], (const TS*)G[3], (const TS*)G[4], (const TS*)G[5], nel, (const TS*)hb);
             SEM_LAUNCH_CHECK(ctx);
             return SEM_OK;
         }
@@ -392,9 +398,10 @@ int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const
 template <typename TU, typename TS, typename TC, typename TW>
 int dispatch(sem_ctx_t ctx, int lx, void* w, const void* u, const void* const* D,
              const void* h1, const void* const* G, int64_t nel, const int* skip, double* dot,
-             const int32_t* lid = nullptr, const int32_t* pos = nullptr, const void* gp = nullptr) {
+             const int32_t* lid = nullptr, const int32_t* pos = nullptr, const void* gp = nullptr,
+             const void* hb = nullptr) {
     switch (lx) {
-#define SEM_AX_CASE(L) case L: return launch_lx<L, TU, TS, TC, TW>(ctx, w, u, D, h1, G, nel, skip, dot, lid, pos, gp);
+#define SEM_AX_CASE(L) case L: return launch_lx<L, TU, TS, TC, TW>(ctx, w, u, D, h1, G, nel, skip, dot, lid, pos, gp, hb);
         SEM_AX_CASE(2) SEM_AX_CASE(3) SEM_AX_CASE(4) SEM_AX_CASE(5) SEM_AX_CASE(6) SEM_AX_CASE(7)
         SEM_AX_CASE(8) SEM_AX_CASE(9) SEM_AX_CASE(10) SEM_AX_CASE(11) SEM_AX_CASE(12)
 #undef SEM_AX_CASE
@@ -413,11 +420,12 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 
 }  // namespace
 
-extern "C" int sem_ax(sem_ctx_t ctx, void* w, const void* u, const void* dx, const void* dy,
-                      const void* dz, const void* dxt, const void* dyt, const void* dzt,
-                      const void* h1, const void* g11, const void* g22, const void* g33,
-                      const void* g12, const void* g13, const void* g23, int64_t nel, int lx,
-                      sem_dtype_t field_dtype, sem_dtype_t out_dtype) {
+namespace {
+
+int ax_public(sem_ctx_t ctx, void* w, const void* u, const void* dx, const void* dy, const void* dz,
+              const void* dxt, const void* dyt, const void* dzt, const void* h1, const void* g11,
+              const void* g22, const void* g33, const void* g12, const void* g13, const void* g23,
+              const void* hb, int64_t nel, int lx, sem_dtype_t field_dtype, sem_dtype_t out_dtype) {
     int rc = sem::enter(ctx);
     if (rc) return rc;
     if (!sem::lx_ok(lx)) return sem::fail(ctx, SEM_EUNSUPPORTED_LX, "sem_ax: lx=%d outside [2,12]", lx);
@@ -437,12 +445,38 @@ extern "C" int sem_ax(sem_ctx_t ctx, void* w, const void* u, const void* dx, con
     const int64_t n = nel * lx * lx * lx;
     const size_t nw = (size_t)n * dsize(out_dtype), nf = (size_t)n * dsize(field_dtype);
     const size_t nd = (size_t)lx * lx * (f64 ? 8 : 4);
-    bool alias = overlaps(w, nw, u, nf) || overlaps(w, nw, h1, nf);
+    bool alias = overlaps(w, nw, u, nf) || overlaps(w, nw, h1, nf) || overlaps(w, nw, hb, nf);
     for (int q = 0; q < 6; ++q) alias = alias || overlaps(w, nw, G[q], nf) || overlaps(w, nw, D[q], nd);
     if (alias) return sem::fail(ctx, SEM_EINVAL, "sem_ax: output overlaps an input");
-    if (f64) return dispatch<double, double, double, double>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr);
-    if (field_dtype == SEM_F32) return dispatch<float, float, float, float>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr);
-    return dispatch<uint16_t, uint16_t, float, float>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr);
+    if (f64)
+        return dispatch<double, double, double, double>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr, nullptr,
+                                                        nullptr, nullptr, hb);
+    if (field_dtype == SEM_F32)
+        return dispatch<float, float, float, float>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr, nullptr,
+                                                    nullptr, nullptr, hb);
+    return dispatch<uint16_t, uint16_t, float, float>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr, nullptr,
+                                                      nullptr, nullptr, hb);
+}
+
+}  // namespace
+
+extern "C" int sem_ax(sem_ctx_t ctx, void* w, const void* u, const void* dx, const void* dy,
+                      const void* dz, const void* dxt, const void* dyt, const void* dzt,
+                      const void* h1, const void* g11, const void* g22, const void* g33,
+                      const void* g12, const void* g13, const void* g23, int64_t nel, int lx,
+                      sem_dtype_t field_dtype, sem_dtype_t out_dtype) {
+    return ax_public(ctx, w, u, dx, dy, dz, dxt, dyt, dzt, h1, g11, g22, g33, g12, g13, g23, nullptr, nel, lx,
+                     field_dtype, out_dtype);
+}
+
+extern "C" int sem_ax_helmholtz(sem_ctx_t ctx, void* w, const void* u, const void* dx, const void* dy,
+                                const void* dz, const void* dxt, const void* dyt, const void* dzt,
+                                const void* h1, const void* g11, const void* g22, const void* g33,
+                                const void* g12, const void* g13, const void* g23, const void* h2b,
+                                int64_t nel, int lx, sem_dtype_t field_dtype, sem_dtype_t out_dtype) {
+    if (!h2b && nel > 0) return sem::fail(ctx, SEM_EINVAL, "sem_ax_helmholtz: null h2b");
+    return ax_public(ctx, w, u, dx, dy, dz, dxt, dyt, dzt, h1, g11, g22, g33, g12, g13, g23, h2b, nel, lx,
+                     field_dtype, out_dtype);
 }
 
 namespace sem {

@@ -155,3 +155,66 @@ def test_ax_errors(sem_ctx):
     P.sem_ax(sem_ctx, w, u, *D, None, *G, 0, lx)              # empty: no-op
     with pytest.raises(P.SemError):
         P.sem_ax(sem_ctx, w.float(), u, *D, None, *G, nel, lx, out_dtype=P.SEM_BF16)
+
+
+def _run_helm(ctx, u, G, h1, hb, lx, dtype=torch.float64, out=torch.float64):
+    nel = u.shape[0]
+    du = to_dev(u, dtype)
+    dG = [to_dev(g, dtype) for g in G]
+    dh = None if h1 is None else to_dev(h1, dtype)
+    dhb = to_dev(hb, dtype)
+    w = torch.full(u.shape, float("nan"), dtype=out, device="cuda")
+    D = _gpu_D(lx, torch.float64 if dtype == torch.float64 else torch.float32)
+    P.sem_ax_helmholtz(ctx, w, du, *D, dh, *dG, dhb, nel, lx)
+    torch.cuda.synchronize()
+    return w.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("lx", [2, 3, 5, 8, 10, 12])
+def test_ax_helmholtz(sem_ctx, lx):
+    """w = A_e u + h2b u (the lx = 3 one-thread-per-node kernel included), in
+    float64 against the oracle to 1e-12, in float32 and bfloat16 storage
+    against the input-quantised oracle to 1e-5; the Helmholtz term changes the
+    result (it is not dropped)."""
+    from oracle.ax import ax_helmholtz
+    nel = 7
+    G, h1 = synth.random_spd_factors(nel, lx, 3000 + lx)
+    u = synth.local_normal(nel, lx, 3100 + lx)
+    hb = synth.local_normal(nel, lx, 3200 + lx) ** 2 + 0.1
+    M = listing_matrices(lx)
+    got = _run_helm(sem_ctx, u, G, h1, hb, lx)
+    ref = ax_helmholtz(u, *M, h1, *G, hb)
+    assert rel_inf(got, ref) <= TOL64
+    assert rel_inf(ax_einsum(u, *M, h1, *G), ref) > 1e3 * TOL64    # the term is not dropped
+    for dt, q in ((torch.float32, to_f32), (torch.bfloat16, to_bf16)):
+        got = _run_helm(sem_ctx, u, G, h1, hb, lx, dt, torch.float32)
+        ref = ax_helmholtz(q(u), *[to_f32(m) for m in M], q(h1), *[q(g) for g in G], q(hb))
+        assert rel_inf(got, ref) <= TOL_LOW
+
+
+def test_ax_helmholtz_full_size_sampled(sem_ctx):
+    """32^3 box, lx = 8, amplitude 0.1, h1 and h2 ~ U[0.5, 2] per unique node,
+    h2b = h2 * bm (the mass from the library's geometry): sampled elements
+    against the oracle's own geometry and mass."""
+    from oracle.ax import ax_helmholtz
+    from paper_2506_20994_amd.box import BoxOperator
+    n, lx, amp = 32, 8, 0.1
+    nu = (n * (lx - 1)) ** 3
+    h1u = synth.unique_uniform(nu, 0.5, 2.0, 1)
+    h2u = synth.unique_uniform(nu, 0.5, 2.0, 3)
+    uu = synth.unique_normal(nu, 0)
+    op = BoxOperator(sem_ctx, n, lx, amp, h1_unique=h1u, keep_coords=False)
+    u = op.scatter(uu)
+    h2b = op.scatter(h2u) * op.bm
+    w = torch.empty_like(u)
+    P.sem_ax_helmholtz(sem_ctx, w, u, *op.D, op.h1, *op.G, h2b, op.nel, lx)
+    torch.cuda.synchronize()
+    els = np.unique(np.concatenate([[0, n ** 3 - 1], np.random.default_rng(8).integers(0, n ** 3, 32)]))
+    G, Bm, _ = geometric_factors(*box_coords(n, lx, amp, els), lx)
+    ids = global_ids(n, lx, els)
+    ref = ax_helmholtz(uu[ids], *listing_matrices(lx), h1u[ids], *G, h2u[ids] * Bm)
+    got = w[torch.as_tensor(els, device="cuda")].cpu().numpy()
+    assert rel_inf(got, ref) <= TOL64
+    with pytest.raises(P.SemError):
+        P.sem_ax_helmholtz(sem_ctx, w, u, *op.D, op.h1, *op.G, None, op.nel, lx)
+    op.gs.close()

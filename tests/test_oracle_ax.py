@@ -123,3 +123,74 @@ def test_energy_not_exact_beyond_total_degree():
     exact = np.sum(Wq * 16 * ((X ** 3 * Y ** 4 * Z ** 4) ** 2 + (X ** 4 * Y ** 3 * Z ** 4) ** 2
                               + (X ** 4 * Y ** 4 * Z ** 3) ** 2))
     assert abs(np.sum(u * w) - exact) > 1e-3 * exact
+
+
+def _affine_elements(lx, r):
+    xi, _ = gll_nodes_weights(lx - 1)
+    R = np.stack(np.meshgrid(xi, xi, xi, indexing="ij")[::-1], -1)
+    for _ in range(3):
+        A = 0.4 * (np.eye(3) + 0.25 * r.standard_normal((3, 3)))
+        c = 0.3 * r.standard_normal(3)
+        yield A, c, R @ A.T + c
+
+
+@pytest.mark.parametrize("lx", [3, 5, 8])
+def test_helmholtz_exact_on_affine_elements(lx):
+    """u^T (A + h2 B) u = int |grad u|^2 + h2 int u^2 for u of total degree
+    <= N - 1 on sheared affine elements (the GLL rule integrates u^2 exactly up
+    to degree 2N - 1 per coordinate), by an independent Gauss-Legendre rule."""
+    from oracle.ax import ax_helmholtz
+    N, h2 = lx - 1, 0.7
+    f, grad = _poly(N - 1, 10 + lx)
+    r = np.random.default_rng(6)
+    gq, gw = np.polynomial.legendre.leggauss(N + 2)
+    Rq = np.stack(np.meshgrid(gq, gq, gq, indexing="ij")[::-1], -1)
+    Wq = gw[:, None, None] * gw[None, :, None] * gw[None, None, :]
+    got, exact = 0.0, 0.0
+    for A, c, X in _affine_elements(lx, r):
+        x, y, z = (X[None, ..., d] for d in range(3))
+        G, Bm, _ = geometric_factors(x, y, z, lx)
+        u = f(x, y, z)
+        got += np.sum(u * ax_helmholtz(u, *listing_matrices(lx), None, *G, h2 * Bm))
+        Xq = Rq @ A.T + c
+        gx, gy, gz = grad(Xq[..., 0], Xq[..., 1], Xq[..., 2])
+        uq = f(Xq[..., 0], Xq[..., 1], Xq[..., 2])
+        exact += abs(np.linalg.det(A)) * np.sum(Wq * (gx ** 2 + gy ** 2 + gz ** 2 + h2 * uq ** 2))
+    assert abs(got - exact) <= 1e-12 * abs(exact)
+
+
+def test_helmholtz_mass_not_exact_beyond_degree():
+    """With the stiffness switched off (G = 0), u = x^N makes u^2 of degree 2N,
+    past the GLL rule: the mass identity must fail, so the test above has teeth."""
+    from oracle.ax import ax_helmholtz
+    lx = 5
+    N = lx - 1
+    xi, _ = gll_nodes_weights(N)
+    R = np.stack(np.meshgrid(xi, xi, xi, indexing="ij")[::-1], -1)
+    x, y, z = (R[None, ..., d] for d in range(3))
+    G, Bm, _ = geometric_factors(x, y, z, lx)
+    u = x ** N
+    w = ax_helmholtz(u, *listing_matrices(lx), None, *[0 * g for g in G], Bm)
+    exact = 8.0 / (2 * N + 1)          # int over [-1, 1]^3 of x^(2N)
+    assert abs(np.sum(u * w) - exact) > 1e-3 * exact
+
+
+def test_helmholtz_assembled_is_positive_definite():
+    """A alone is singular on the periodic box (constants); A + h2 B is not."""
+    from oracle.ax import ax_helmholtz
+    from oracle.solve import BoxProblem
+    from oracle.gs import gather, scatter
+    P = BoxProblem(2, 3, 0.1)
+    cols = []
+    for j in range(P.nu):
+        e = np.zeros(P.nu)
+        e[j] = 1.0
+        w = ax_helmholtz(scatter(e, P.ids), P.dx, P.dx, P.dx, P.dxt, P.dxt, P.dxt, None, *P.G, 0.5 * P.B)
+        cols.append(gather(w, P.ids, P.nu))
+    M = np.array(cols).T
+    assert np.linalg.norm(M - M.T) <= 1e-13 * np.linalg.norm(M)
+    ev = np.linalg.eigvalsh(0.5 * (M + M.T))
+    assert ev[0] > 1e-6 * ev[-1]
+    A = np.array([gather(ax_helmholtz(scatter(np.eye(P.nu)[j], P.ids), P.dx, P.dx, P.dx, P.dxt, P.dxt,
+                                      P.dxt, None, *P.G, 0 * P.B), P.ids, P.nu) for j in range(P.nu)]).T
+    assert abs(np.linalg.eigvalsh(0.5 * (A + A.T))[0]) < 1e-10 * ev[-1]
