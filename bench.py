@@ -167,6 +167,29 @@ def learned_comparison(ctx, P, n, lx, amp, solve=None, tol=1e-10):
         print(f"[bench] learned {name}: {ms:.1f} ms, {st['iterations']} its, "
               f"{st['jacobi_steps']} Jacobi, fell back {st['fell_back']}", file=sys.stderr, flush=True)
         cg.close()
+    # the classical comparison: the kappa-normalised inverse of the operator on
+    # one undeformed element as the block, applied by the same kernels
+    t0 = time.perf_counter()
+    blk = P.sem_lp_create(ctx, n ** 3)
+    P.sem_lp_set_block(blk, LR.reference_block(ctx, lx))
+    op.bind(blk)
+    res["classical_block_setup_s"] = round(time.perf_counter() - t0, 2)
+    kw = dict(tol=tol, precision=P.SEM_SOLVE_F32_IR, ir_mode=1, learned=blk, maxit=50000)
+    cg = op.solver(P.SEM_SOLVE_F32_IR, learned=blk)
+    P.sem_cg_solve(cg, x, b, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st = P.sem_cg_solve(cg, x, b, **kw)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    res["classical_block_f32_rr"] = {"ms": round(ms, 2), "iterations": st["iterations"],
+                                     "jacobi_steps": st["jacobi_steps"], "fell_back": st["fell_back"],
+                                     "relres": st["relres"], "converged": st["converged"]}
+    print(f"[bench] learned classical_block_f32_rr: {ms:.1f} ms, {st['iterations']} its", file=sys.stderr,
+          flush=True)
+    cg.close()
+    blk.close()
+    variants = variants + (("classical_block_f32_rr", None, None, None),)
     base = res["jacobi_pcg_f64"]["ms"]
     res["speedup_vs_fp64_pcg"] = {v[0]: round(base / res[v[0]]["ms"], 3) for v in variants[1:]}
     if solve:    # the same precision without the network: what the network adds

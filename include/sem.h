@@ -328,6 +328,15 @@ int sem_lp_set_metric(sem_lp_t lp, double mu);
  * the element block of the inverse operator.  Applies to training and
  * inference from the next call on. */
 int sem_lp_set_linear(sem_lp_t lp, int on);
+/* Set the linear form's 512 x 512 element block directly (host float32,
+ * row-major, count = 512 * 512) instead of folding it from the weights: the
+ * preconditioner becomes z = sum_e Q_e S_e W_s S_e Q_e^T r / kappa_e (+ Minv r
+ * with the Jacobi base), W_s the symmetric part of W, applied by the same
+ * kernels.  For classical (non-learned) element blocks used as a comparison.
+ * Switches the network to its linear form; the block holds until the weights
+ * change (sem_lp_set, a training step or sem_lp_load), which folds them
+ * again. */
+int sem_lp_set_block(sem_lp_t lp, const float* W, int64_t count);
 /* Jacobi base (on != 0): the preconditioner becomes z = Minv r + P_net(r),
  * Minv the inverse assembled diagonal of the bound operator, and training
  * targets become (err - Minv r) kappa / s, so the network learns the

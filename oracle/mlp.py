@@ -163,10 +163,15 @@ def apply_linear(params, r_local, G, h1, ids, n_unique):
     conjugacy holds.  The network is trained on unweighted element pairs
     (r_e, e_e); the white-noise optimum of that regression is the element
     block of A^+, applied here with the square-root weights."""
+    return apply_block(folded_matrix(params, r_local[0].size), r_local, G, h1, ids, n_unique)
+
+
+def apply_block(W, r_local, G, h1, ids, n_unique):
+    """The symmetric additive apply of a given element block W (nloc x nloc):
+    z = sum_e Q_e S_e W_s S_e Q_e^T r / kappa_e, W_s = (W + W^T) / 2."""
     from .gs import gs, multiplicity
     E = r_local.shape[0]
     nloc = r_local[0].size
-    W = folded_matrix(params, nloc)
     Ws = 0.5 * (W + W.T)
     _, _, kappa = features(r_local, G, h1)
     S = 1.0 / np.sqrt(multiplicity(ids, n_unique).reshape(E, nloc))

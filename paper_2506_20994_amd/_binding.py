@@ -16,7 +16,7 @@ __all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONV
            "CgSolver", "SEM_SOLVE_F64", "SEM_SOLVE_F32_IR", "SEM_SOLVE_BF16_IR",
            "LearnedPrecond", "sem_lp_create", "sem_lp_destroy", "sem_lp_set", "sem_lp_get",
            "sem_lp_set_step", "sem_lp_get_step", "sem_lp_bind", "sem_lp_samples", "sem_lp_forward",
-           "sem_lp_gradients", "sem_lp_adam", "sem_lp_set_metric", "sem_lp_set_jacobi_base", "sem_lp_set_linear", "sem_lp_train_step", "sem_lp_apply", "sem_lp_apply_unique", "sem_lp_save", "sem_lp_load", "LP_SLOTS",
+           "sem_lp_gradients", "sem_lp_adam", "sem_lp_set_metric", "sem_lp_set_jacobi_base", "sem_lp_set_linear", "sem_lp_train_step", "sem_lp_apply", "sem_lp_apply_unique", "sem_lp_save", "sem_lp_load", "sem_lp_set_block", "LP_SLOTS",
            "SEM_LP_IN", "SEM_LP_IN_PAD", "SEM_LP_HIDDEN", "SEM_LP_OUT"]
 
 SEM_LP_IN, SEM_LP_IN_PAD, SEM_LP_HIDDEN, SEM_LP_OUT = 518, 528, 256, 512
@@ -107,6 +107,7 @@ EXPORTS = {
     "sem_lp_apply": (_int, [_vp, _vp, _vp, _int]),
     "sem_lp_apply_unique": (_int, [_vp, _vp, _vp, _int]),
     "sem_lp_save": (_int, [_vp, ctypes.c_char_p]),
+    "sem_lp_set_block": (_int, [_vp, _vp, _i64]),
     "sem_lp_load": (_int, [_vp, ctypes.c_char_p]),
     "sem_lp_set_metric": (_int, [_vp, _dbl]),
     "sem_lp_set_jacobi_base": (_int, [_vp, _int]),
@@ -489,6 +490,13 @@ def sem_lp_train_step(lp, X, T, rows, lr, loss_dev):
 def sem_lp_apply(lp, z, r):
     lp.ctx.bind()
     _check(lib().sem_lp_apply(lp.handle, _ptr(z), _ptr(r), dtype_code(r)), lp.ctx.handle)
+
+
+def sem_lp_set_block(lp, W):
+    import numpy as np
+    a = np.ascontiguousarray(W, dtype=np.float32).ravel()
+    lp.ctx.bind()
+    _check(lib().sem_lp_set_block(lp.handle, a.ctypes.data, a.size), lp.ctx.handle)
 
 
 def sem_lp_save(lp, path):

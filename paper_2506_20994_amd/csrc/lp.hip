@@ -1390,3 +1390,21 @@ extern "C" int sem_lp_load(sem_lp_t lp, const char* path) {
     if (!rc) rc = sem_lp_set_step(lp, step);
     return rc;
 }
+
+extern "C" int sem_lp_set_block(sem_lp_t lp, const float* W, int64_t count) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_set_block: null network");
+    int rc = sem::enter(lp->ctx);
+    if (rc) return rc;
+    if (!W || count != (int64_t)kOut * kOut)
+        return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_set_block: need %d x %d values", kOut, kOut);
+    rc = sem_lp_set_linear(lp, 1);
+    if (rc) return rc;
+    rc = refresh_bf16(lp);
+    if (rc) return rc;
+    SEM_HIP(lp->ctx, hipStreamSynchronize(lp->ctx->stream));
+    SEM_HIP(lp->ctx, hipMemcpy(lp->Wf32, W, 4 * (size_t)count, hipMemcpyHostToDevice));
+    sym_to_bf16<<<256, kBlock, 0, lp->ctx->stream>>>(lp->Wfb, lp->Wf32, kOut);
+    SEM_LAUNCH_CHECK(lp->ctx);
+    lp->fold_dirty = false;      // until the weights change again
+    return SEM_OK;
+}

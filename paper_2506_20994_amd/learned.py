@@ -134,3 +134,31 @@ def init_network(lp, seed=7, mu=None, jacobi_base=None, out_scale=1.0, linear=No
     params[4] = params[4] * out_scale
     for s, p in enumerate(params):
         B.sem_lp_set(lp, s, p.astype(np.float32))
+
+
+def reference_block(ctx, lx=8):
+    """The classical counterpart of the learned block: kappa times the inverse
+    of the assembled operator restricted to the nodes of one element (the local
+    solve of one-level additive Schwarz with minimal overlap), on an undeformed
+    periodic 3^3 box, where every element sees the same matrix.  The columns
+    come from the library's operator and gather-scatter applied to unit
+    vectors; the 512 x 512 inverse is taken on the host.  Returns float64."""
+    n, e = 3, 13                                   # the centre element
+    op = BoxOperator(ctx, n, lx, 0.0, keep_coords=False)
+    nloc = lx ** 3
+    ids = op.ids[e].reshape(-1).cpu().numpy()
+    A = np.empty((nloc, nloc))
+    u = torch.zeros((op.nel, lx, lx, lx), dtype=torch.float64, device=op.ids.device)
+    w = torch.empty_like(u)
+    uu = np.zeros(op.n_unique)
+    for j in range(nloc):
+        uu[ids[j]] = 1.0
+        u = op.scatter(uu)
+        uu[ids[j]] = 0.0
+        op.apply(w, u)
+        A[:, j] = w[e].reshape(-1).cpu().numpy()
+    g = [t[e].reshape(-1).cpu().numpy() for t in op.G[:3]]
+    kappa = float(np.mean(g[0] + g[1] + g[2]) / 3.0)
+    op.gs.close()
+    A = 0.5 * (A + A.T)
+    return kappa * np.linalg.inv(A)
