@@ -22,15 +22,17 @@ from .ax import element_matrix
 
 
 def assembled_matrix(Dh, h1, G, ids, n_unique):
-    """Sparse CSR A_G (n_unique x n_unique)."""
+    """Sparse CSR A_G (n_unique x n_unique); rows and columns of Dirichlet
+    nodes (negative ids) are left out."""
     nel = ids.shape[0]
     rows, cols, vals = [], [], []
     for e in range(nel):
         Ae = element_matrix(Dh, None if h1 is None else h1[e], tuple(g[e] for g in G))
         q = ids[e].ravel()
-        rows.append(np.repeat(q, len(q)))
-        cols.append(np.tile(q, len(q)))
-        vals.append(Ae.ravel())
+        f = np.flatnonzero(q >= 0)
+        rows.append(np.repeat(q[f], len(f)))
+        cols.append(np.tile(q[f], len(f)))
+        vals.append(Ae[np.ix_(f, f)].ravel())
     A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(n_unique, n_unique))
     return A.tocsr()

@@ -4,7 +4,10 @@ Paper Sec. 2.1 names gather-scatter as one of the two main ingredients of the
 solver.  With Q the scatter from unique (global) nodes to element-local nodes
 (u_L = u_G[id_L]), gather-scatter is u <- Q Q^T u: every local copy of a node
 receives the sum of all copies (summation in any order; the assembled value is
-unique up to rounding).  Reading: periodic boxes, so no node is masked.
+unique up to rounding).  A node with a negative id is a Dirichlet node: it is
+no unknown, so Q^T skips it and Q gives it the value 0 (the masked
+gather-scatter of a homogeneous Dirichlet problem); its multiplicity is taken
+as 1.
 
 Pins: gs(1) = multiplicity, exactly; the multiplicity census of a periodic
 element ((N-1)^3 ones, 6(N-1)^2 twos, 12(N-1) fours, 8 eights); the weighted
@@ -15,13 +18,17 @@ import numpy as np
 
 
 def gather(u_local, ids, n_unique):
-    """Q^T u: sum of the local copies per global id."""
-    return np.bincount(ids.ravel(), weights=u_local.ravel(), minlength=n_unique)
+    """Q^T u: sum of the local copies per global id (Dirichlet nodes skipped)."""
+    free = ids.ravel() >= 0
+    return np.bincount(ids.ravel()[free], weights=u_local.ravel()[free], minlength=n_unique)
 
 
 def scatter(u_unique, ids):
-    """Q u: copy each unique value to all its local nodes."""
-    return u_unique[ids]
+    """Q u: copy each unique value to all its local nodes (0 on Dirichlet nodes)."""
+    out = np.zeros(ids.shape, dtype=np.asarray(u_unique).dtype)
+    free = ids >= 0
+    out[free] = u_unique[ids[free]]
+    return out
 
 
 def gs(u_local, ids, n_unique):
@@ -30,8 +37,11 @@ def gs(u_local, ids, n_unique):
 
 def multiplicity(ids, n_unique):
     """Number of local copies of each local node's global id."""
-    counts = np.bincount(ids.ravel(), minlength=n_unique)
-    return counts[ids].astype(np.float64)
+    free = ids >= 0
+    counts = np.bincount(ids[free], minlength=n_unique)
+    mult = np.ones(ids.shape)
+    mult[free] = counts[ids[free]]
+    return mult
 
 
 def weighted_dot(u_local, v_local, mult):

@@ -13,7 +13,12 @@ expands the solution on each element as a tensor product over the GLL points
     following cyclically, which keeps x(X + e_c) = x(X) + e_c, so periodic
     copies of a node still coincide;
   * the global id of a node is its position on the (nN)^3 periodic lattice,
-    g = ((ez N + k) mod nN) (nN)^2 + ((ey N + j) mod nN) nN + ((ex N + i) mod nN).
+    g = ((ez N + k) mod nN) (nN)^2 + ((ey N + j) mod nN) nN + ((ex N + i) mod nN);
+  * the Dirichlet box is the same mesh without the periodic identification and
+    with every node on the six faces of the undeformed cube held at zero
+    (homogeneous Dirichlet); those nodes get id -1 and are no unknowns, and the
+    interior nodes are numbered on the (nN - 1)^3 lattice of interior points,
+    g = (K - 1) (nN - 1)^2 + (J - 1) (nN - 1) + (I - 1) with I = ex N + i etc.
 Pins: multiplicity counts and unique-node counts (tests/test_oracle_gs.py),
 affine volumes and geometric factors (tests/test_oracle_geometry.py).
 """
@@ -76,3 +81,26 @@ def global_ids(n, lx, elements=None):
 
 def n_unique(n, lx):
     return (n * (lx - 1)) ** 3
+
+
+def global_ids_dirichlet(n, lx, elements=None):
+    """int64 ids of the Dirichlet box, shape (E, lx, lx, lx): -1 on the box
+    boundary, values in [0, (n N - 1)^3) inside."""
+    N = lx - 1
+    M = n * N
+    els = _elements(n, elements)
+    ids = np.empty((len(els), lx, lx, lx), dtype=np.int64)
+    r = np.arange(lx)
+    for q, e in enumerate(els):
+        ex, ey, ez = e % n, (e // n) % n, e // (n * n)
+        I, J, K = ex * N + r, ey * N + r, ez * N + r
+        inside = ((K > 0) & (K < M))[:, None, None] & ((J > 0) & (J < M))[None, :, None] \
+            & ((I > 0) & (I < M))[None, None, :]
+        g = (K - 1)[:, None, None] * (M - 1) ** 2 + (J - 1)[None, :, None] * (M - 1) \
+            + (I - 1)[None, None, :]
+        ids[q] = np.where(inside, g, -1)
+    return ids
+
+
+def n_unique_dirichlet(n, lx):
+    return max(n * (lx - 1) - 1, 0) ** 3

@@ -15,7 +15,9 @@ names no solver.  The readings used here:
     float64 outer residual r = b - A x, an inner solve of A d = r / ||r|| with a
     reduced-precision operator, x += ||r|| d in float64, until the float64
     relative residual is <= tol;
-  * flexible CG with one stored direction (Notay 2000, FCG(1)).
+  * flexible CG with one stored direction (Notay 2000, FCG(1));
+  * the Dirichlet box (oracle.mesh.global_ids_dirichlet) has no null space:
+    there the right-hand side is not projected and no mean is removed.
 Pins: on tiny meshes PCG agrees with the pseudo-inverse solution; FCG with the
 Jacobi preconditioner reproduces PCG's iterates; spectral convergence of a
 manufactured solution (tests/test_oracle_solve.py).
@@ -23,7 +25,7 @@ manufactured solution (tests/test_oracle_solve.py).
 import numpy as np
 
 from .gll import gll_nodes_weights, deriv_matrix
-from .mesh import box_coords, global_ids, n_unique
+from .mesh import box_coords, global_ids, n_unique, global_ids_dirichlet, n_unique_dirichlet
 from .geometry import geometric_factors
 from .ax import ax_einsum
 from .gs import gather, scatter, multiplicity
@@ -31,18 +33,21 @@ from .assemble import element_diagonal
 
 
 class BoxProblem:
-    """Periodic n^3 box, lx points per direction, deformation amplitude a."""
+    """n^3 box, lx points per direction, deformation amplitude a; periodic,
+    or with homogeneous Dirichlet conditions on the whole boundary."""
 
-    def __init__(self, n, lx, a=0.0, h1_unique=None):
+    def __init__(self, n, lx, a=0.0, h1_unique=None, dirichlet=False):
         self.n, self.lx, self.a = n, lx, a
+        self.dirichlet = dirichlet
+        self.project = not dirichlet       # the periodic operator is singular
         xi, self.wgll = gll_nodes_weights(lx - 1)
         self.Dh = deriv_matrix(xi)
         self.dx = np.ascontiguousarray(self.Dh.T)
         self.dxt = np.ascontiguousarray(self.Dh)
         self.coords = box_coords(n, lx, a)
         self.G, self.B, self.detJ = geometric_factors(*self.coords, lx)
-        self.ids = global_ids(n, lx)
-        self.nu = n_unique(n, lx)
+        self.ids = global_ids_dirichlet(n, lx) if dirichlet else global_ids(n, lx)
+        self.nu = n_unique_dirichlet(n, lx) if dirichlet else n_unique(n, lx)
         self.mult = multiplicity(self.ids, self.nu)
         self.h1 = None if h1_unique is None else scatter(h1_unique, self.ids)
 
@@ -59,18 +64,19 @@ class BoxProblem:
 
     def fourier_rhs(self, k, amp, phase):
         """b_G for f = sum_m amp_m cos(2 pi k_m . x + phase_m), projected to
-        1^T b_G = 0."""
+        1^T b_G = 0 on the periodic box."""
         x, y, z = self.coords
         f = np.zeros_like(x)
         for m in range(len(amp)):
             f += amp[m] * np.cos(2.0 * np.pi * (k[m, 0] * x + k[m, 1] * y + k[m, 2] * z)
                                  + phase[m])
         b = gather(self.B * f, self.ids, self.nu)
-        return b - b.mean()
+        return b - b.mean() if self.project else b
 
 
-def pcg(apply_A, b, Minv, tol=1e-10, maxit=10000, x0=None):
-    """Preconditioned CG; returns (x, iterations, relres history)."""
+def pcg(apply_A, b, Minv, tol=1e-10, maxit=10000, x0=None, project=True):
+    """Preconditioned CG; returns (x, iterations, relres history).  With
+    `project` (singular periodic operator) the mean of x is removed at the end."""
     x = np.zeros_like(b) if x0 is None else x0.copy()
     r = b - apply_A(x) if x0 is not None else b.copy()
     bnorm = np.linalg.norm(b)
@@ -94,10 +100,10 @@ def pcg(apply_A, b, Minv, tol=1e-10, maxit=10000, x0=None):
         rz_new = r @ z
         p = z + (rz_new / rz) * p
         rz = rz_new
-    return x - x.mean(), it, hist
+    return (x - x.mean() if project else x), it, hist
 
 
-def fcg1(apply_A, b, precond, tol=1e-10, maxit=10000):
+def fcg1(apply_A, b, precond, tol=1e-10, maxit=10000, project=True):
     """Flexible CG with one stored direction (Notay 2000).  ``precond(r)``
     returns z; it may change from one iteration to the next."""
     x = np.zeros_like(b)
@@ -123,10 +129,10 @@ def fcg1(apply_A, b, precond, tol=1e-10, maxit=10000):
         if hist[-1] <= tol:
             break
         p_prev, w_prev, pw_prev = p, w, pw
-    return x - x.mean(), it, hist
+    return (x - x.mean() if project else x), it, hist
 
 
-def iterative_refinement(apply_A64, b, inner_solve, tol=1e-10, max_outer=50):
+def iterative_refinement(apply_A64, b, inner_solve, tol=1e-10, max_outer=50, project=True):
     """Float64 refinement around ``inner_solve(rhat) -> d`` (an approximate
     solution of A d = rhat with ||rhat|| = 1).  Returns (x, outer, relres)."""
     x = np.zeros_like(b)
@@ -137,9 +143,11 @@ def iterative_refinement(apply_A64, b, inner_solve, tol=1e-10, max_outer=50):
         rn = np.linalg.norm(r)
         d = inner_solve(r / rn)
         x += rn * d
-        x -= x.mean()
+        if project:
+            x -= x.mean()
         r = b - apply_A64(x)
-        r -= r.mean()
+        if project:
+            r -= r.mean()
         relres.append(np.linalg.norm(r) / bnorm)
         if relres[-1] <= tol:
             return x, outer, relres
