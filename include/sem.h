@@ -88,6 +88,17 @@ int sem_gll(int lx, double* xi, double* w, double* dx, double* dxt);
 int sem_box_mesh(sem_ctx_t ctx, int n, int lx, double amp,
                  double* x, double* y, double* z, int64_t* ids);
 
+/* The same box and deformation without the periodic identification, with
+ * homogeneous Dirichlet conditions on the whole boundary (u = 0 on the six
+ * faces of the undeformed cube; a case the paper's Poisson setting (Sec. 3)
+ * leaves to the solver around the operator).  Boundary nodes get id -1 (no
+ * unknown); interior nodes get their position on the (M - 1)^3 lattice of
+ * interior points, M = n (lx - 1):
+ * id = ((K - 1) (M - 1) + (J - 1)) (M - 1) + (I - 1), I = ex (lx - 1) + i etc.
+ * Outputs and rules as in sem_box_mesh. */
+int sem_box_mesh_dirichlet(sem_ctx_t ctx, int n, int lx, double amp,
+                           double* x, double* y, double* z, int64_t* ids);
+
 /* Geometric factors of the operator from node coordinates (isoparametric:
  * the GLL derivative matrix applied to x, y, z gives the Jacobian).  With
  * 1 = r, 2 = s, 3 = t and W = w_i w_j w_k |J|:
@@ -102,7 +113,8 @@ int sem_geometry(sem_ctx_t ctx, const double* x, const double* y, const double* 
                  double* min_detj);
 
 /* out_local[L] = in_unique[ids[L]] for L < n_local (the scatter Q; any dtype,
- * in and out of the same dtype).  ids device int64 in [0, n_unique). */
+ * in and out of the same dtype).  ids device int64 in [0, n_unique), or
+ * negative for a Dirichlet node, which receives 0. */
 int sem_scatter(sem_ctx_t ctx, void* out_local, const void* in_unique,
                 const int64_t* ids, int64_t n_local, sem_dtype_t dtype);
 
@@ -166,29 +178,38 @@ int sem_ax_helmholtz(sem_ctx_t ctx, void* w, const void* u,
 /* ---------------------------------------------------------- gather-scatter */
 
 /* Build the gather-scatter plan (Sec. 2.1) for a local numbering: ids (host
- * int64, n_local entries, any non-negative values) names the global node of
- * each local node.  Nodes whose id occurs once are left alone by sem_gs.  The
- * plan lives on the context's device until sem_gs_destroy.  Synchronous.
- * n_local must be < 2^31. */
+ * int64, n_local entries) names the global node of each local node.  A
+ * negative id marks a Dirichlet node (homogeneous Dirichlet condition): it is
+ * no unknown, sem_gs sets it to 0, its multiplicity is 1 and its owner weight
+ * 0, and the solver keeps it at 0.  Nodes whose (non-negative) id occurs once
+ * are left alone by sem_gs.  The plan lives on the context's device until
+ * sem_gs_destroy.  Synchronous.  n_local must be < 2^31. */
 int sem_gs_setup(sem_ctx_t ctx, const int64_t* ids, int64_t n_local, sem_gs_t* gs);
 int sem_gs_destroy(sem_gs_t gs);
-/* Number of distinct ids, and of ids that occur more than once (host outs). */
+/* Number of distinct non-negative ids, and of ids that occur more than once
+ * (host outs). */
 int sem_gs_info(sem_gs_t gs, int64_t* n_unique, int64_t* n_shared);
+/* Number of local nodes with a negative id (Dirichlet nodes; host out). */
+int sem_gs_dirichlet_count(sem_gs_t gs, int64_t* n_dirichlet);
 /* In place u <- Q Q^T u: each local copy of a node receives the sum over all
- * copies, added in a fixed order (deterministic).  dtype SEM_F64 or SEM_F32
- * (float32 fields are summed in float32).  Device array of n_local. */
+ * copies, added in a fixed order (deterministic); Dirichlet nodes receive 0.
+ * dtype SEM_F64 or SEM_F32 (float32 fields are summed in float32).  Device
+ * array of n_local. */
 int sem_gs(sem_gs_t gs, void* u, sem_dtype_t dtype);
-/* mult[L] = number of local copies of node L's id (device float64). */
+/* mult[L] = number of local copies of node L's id, 1 on Dirichlet nodes
+ * (device float64). */
 int sem_gs_mult(sem_gs_t gs, double* mult);
 
 /* Owner weights for dot products of continuous fields: wgt[L] = 1 for the
- * first local copy (lowest local index) of each id and 0 for the others, so
- * sum_L wgt_L u_L v_L = u_G . v_G for u = Q u_G, v = Q v_G (device float64). */
+ * first local copy (lowest local index) of each id and 0 for the others and
+ * for Dirichlet nodes, so sum_L wgt_L u_L v_L = u_G . v_G for u = Q u_G,
+ * v = Q v_G (device float64). */
 int sem_gs_owner(sem_gs_t gs, double* wgt);
 /* In place x <- x - mean_G(x) for a continuous field: the mean over unique
  * nodes (owner-weighted sum / number of distinct ids) is subtracted from every
  * local node, making sum_G x_G = 0 (the solvability condition of the periodic
- * Poisson problem).  Device float64, n_local.  Asynchronous. */
+ * Poisson problem).  Device float64, n_local.  Asynchronous.  A plan with
+ * Dirichlet nodes has no such null space: SEM_EINVAL. */
 int sem_remove_mean(sem_gs_t gs, double* x);
 
 /* ------------------------------------------------------------------ solver */
@@ -263,6 +284,11 @@ int sem_cg_destroy(sem_cg_t cg);
  * b: device float64, local layout, continuous (b = Q b_G) with sum_G b_G = 0
  * (the periodic operator's null space is the constants).  x: device float64
  * output, local layout, continuous, with sum_G x_G = 0.  Starts from x = 0.
+ * On a plan with Dirichlet nodes the operator is the assembled one restricted
+ * to the free nodes (their rows and columns only), which has no null space:
+ * b needs no projection (its Dirichlet entries are ignored), no mean is
+ * removed, and x is 0 on the Dirichlet nodes.  A plan without free nodes is
+ * refused by sem_cg_setup (SEM_EINVAL).
  * Returns SEM_OK, SEM_NOT_CONVERGED (limit reached; x is the last iterate) or
  * SEM_EBREAKDOWN.  Synchronous (reads convergence flags every check_every
  * iterations). */

@@ -8,9 +8,9 @@ import torch
 __all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONVERGED",
            "SEM_FELL_BACK", "SEM_EINVAL", "SEM_EUNSUPPORTED_LX", "SEM_EHIP", "SEM_EBREAKDOWN",
            "SEM_ENOMEM", "SEM_EGEOMETRY", "lib", "lib_path", "sem_create", "sem_destroy",
-           "sem_sync", "sem_gll", "sem_box_mesh", "sem_geometry", "sem_scatter",
+           "sem_sync", "sem_gll", "sem_box_mesh", "sem_box_mesh_dirichlet", "sem_geometry", "sem_scatter",
            "sem_ax_diag", "sem_fourier", "sem_convert", "sem_ax", "sem_ax_helmholtz", "sem_gs_setup",
-           "sem_gs_destroy", "sem_gs_info", "sem_gs", "sem_gs_mult", "Context", "GsPlan",
+           "sem_gs_destroy", "sem_gs_info", "sem_gs_dirichlet_count", "sem_gs", "sem_gs_mult", "Context", "GsPlan",
            "dtype_code", "EXPORTS", "sem_gs_owner", "sem_remove_mean", "sem_cg_setup",
            "sem_cg_destroy", "sem_cg_solve", "SemOperator", "SemSolveOpts", "SemSolveStats",
            "CgSolver", "SEM_SOLVE_F64", "SEM_SOLVE_F32_IR", "SEM_SOLVE_BF16_IR",
@@ -75,6 +75,7 @@ EXPORTS = {
     "sem_sync": (_int, [_vp]),
     "sem_gll": (_int, [_int, _pdbl, _pdbl, _pdbl, _pdbl]),
     "sem_box_mesh": (_int, [_vp, _int, _int, _dbl, _vp, _vp, _vp, _vp]),
+    "sem_box_mesh_dirichlet": (_int, [_vp, _int, _int, _dbl, _vp, _vp, _vp, _vp]),
     "sem_geometry": (_int, [_vp, _vp, _vp, _vp, _i64, _int] + [_vp] * 7 + [_pdbl]),
     "sem_scatter": (_int, [_vp, _vp, _vp, _vp, _i64, _int]),
     "sem_ax_diag": (_int, [_vp, _vp, _vp, _vp] + [_vp] * 6 + [_i64, _int]),
@@ -85,6 +86,7 @@ EXPORTS = {
     "sem_gs_setup": (_int, [_vp, _pi64, _i64, ctypes.POINTER(_vp)]),
     "sem_gs_destroy": (_int, [_vp]),
     "sem_gs_info": (_int, [_vp, _pi64, _pi64]),
+    "sem_gs_dirichlet_count": (_int, [_vp, _pi64]),
     "sem_gs": (_int, [_vp, _vp, _int]),
     "sem_gs_mult": (_int, [_vp, _vp]),
     "sem_gs_owner": (_int, [_vp, _vp]),
@@ -243,6 +245,11 @@ def sem_box_mesh(ctx, n, lx, amp, x=None, y=None, z=None, ids=None):
     _check(lib().sem_box_mesh(h, n, lx, float(amp), _ptr(x), _ptr(y), _ptr(z), _ptr(ids)), h)
 
 
+def sem_box_mesh_dirichlet(ctx, n, lx, amp, x=None, y=None, z=None, ids=None):
+    h = ctx.bind()
+    _check(lib().sem_box_mesh_dirichlet(h, n, lx, float(amp), _ptr(x), _ptr(y), _ptr(z), _ptr(ids)), h)
+
+
 def sem_geometry(ctx, x, y, z, nel, lx, g11, g22, g33, g12, g13, g23, bm=None):
     """Returns min det J."""
     h = ctx.bind()
@@ -325,6 +332,12 @@ def sem_gs_info(gs):
     nu, ns = ctypes.c_int64(0), ctypes.c_int64(0)
     _check(lib().sem_gs_info(gs.handle, ctypes.byref(nu), ctypes.byref(ns)), gs.ctx.handle)
     return nu.value, ns.value
+
+
+def sem_gs_dirichlet_count(gs):
+    nd = ctypes.c_int64(0)
+    _check(lib().sem_gs_dirichlet_count(gs.handle, ctypes.byref(nd)), gs.ctx.handle)
+    return nd.value
 
 
 def sem_gs(gs, u):

@@ -1,5 +1,6 @@
-"""Device-resident periodic box problems assembled from the library's set-up
-calls (mesh, geometry, gather-scatter plan, multiplicity).  Orchestration and
+"""Device-resident box problems (periodic, or with homogeneous Dirichlet
+conditions on the whole boundary) assembled from the library's set-up calls
+(mesh, geometry, gather-scatter plan, multiplicity).  Orchestration and
 allocation only; every array is computed by libsem.so kernels."""
 import numpy as np
 import torch
@@ -8,7 +9,9 @@ from . import _binding as B
 
 
 class BoxOperator:
-    """n^3 periodic box, lx GLL points per direction, sine deformation ``amp``.
+    """n^3 box, lx GLL points per direction, sine deformation ``amp``;
+    periodic, or with ``dirichlet`` u = 0 on the whole boundary (boundary
+    nodes carry id -1 and are no unknowns).
 
     Attributes (all torch tensors on the current GPU, float64 unless noted):
       x, y, z          node coordinates, (nel, lx, lx, lx)
@@ -20,17 +23,19 @@ class BoxOperator:
       h1               None (h1 = 1) or the scattered coefficient
     """
 
-    def __init__(self, ctx, n, lx, amp=0.0, h1_unique=None, keep_coords=True):
+    def __init__(self, ctx, n, lx, amp=0.0, h1_unique=None, keep_coords=True, dirichlet=False):
         self.ctx, self.n, self.lx, self.amp = ctx, n, lx, amp
+        self.dirichlet = dirichlet
         self.nel = n ** 3
         self.n_local = self.nel * lx ** 3
-        self.n_unique = (n * (lx - 1)) ** 3
+        self.n_unique = max(n * (lx - 1) - 1, 0) ** 3 if dirichlet else (n * (lx - 1)) ** 3
         dev = torch.device("cuda", torch.cuda.current_device())
         shp = (self.nel, lx, lx, lx)
         f64 = dict(dtype=torch.float64, device=dev)
         self.x, self.y, self.z = (torch.empty(shp, **f64) for _ in range(3))
         self.ids = torch.empty(shp, dtype=torch.int64, device=dev)
-        B.sem_box_mesh(ctx, n, lx, amp, self.x, self.y, self.z, self.ids)
+        mesh = B.sem_box_mesh_dirichlet if dirichlet else B.sem_box_mesh
+        mesh(ctx, n, lx, amp, self.x, self.y, self.z, self.ids)
         self.G = tuple(torch.empty(shp, **f64) for _ in range(6))
         self.bm = torch.empty(shp, **f64)
         self.min_detj = B.sem_geometry(ctx, self.x, self.y, self.z, self.nel, lx, *self.G, self.bm)
@@ -69,12 +74,14 @@ class BoxOperator:
         B.sem_gs(self.gs, w)
 
     def fourier_rhs(self, k, amp, phase):
-        """Continuous right-hand side b = Q Q^T (B f) - mean for the Fourier sum f
-        at the node coordinates (needs keep_coords=True)."""
+        """Continuous right-hand side b = Q Q^T (B f) for the Fourier sum f at
+        the node coordinates, minus its mean on the periodic box (needs
+        keep_coords=True)."""
         b = torch.empty_like(self.bm)
         B.sem_fourier(self.ctx, b, self.x, self.y, self.z, self.bm, k, amp, phase)
         B.sem_gs(self.gs, b)
-        B.sem_remove_mean(self.gs, b)
+        if not self.dirichlet:
+            B.sem_remove_mean(self.gs, b)
         return b
 
     def solver(self, precision=0, **opts):

@@ -123,8 +123,9 @@ __device__ __forceinline__ void wave_sync() {
 // elements, accumulated in float64, to dot[blockIdx.x] (p^T A p before
 // gather-scatter).
 // GATHER: u is a unique-node vector, read as u[lid[L]] (lid streamed, u
-// through the caches, since neighbouring elements share nodes), and the
-// output of node L goes to w[pos[L]], the plan's CSR order.
+// through the caches, since neighbouring elements share nodes; lid < 0 marks
+// a Dirichlet node, read as 0), and the output of node L goes to w[pos[L]],
+// the plan's CSR order.
 template <int LX, int EPB, typename TU, typename TS, typename TC, typename TW, bool FUSE, bool GATHER>
 __global__ void __launch_bounds__(EPB * LX * LX) __attribute__((amdgpu_waves_per_eu(Shape<LX>::kWavesPerEU, 8)))
 ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
@@ -171,8 +172,10 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
     TC uc[LX];
 #pragma unroll
     for (int k = 0; k < LX; ++k) {
-        if constexpr (GATHER)
-            uc[k] = live ? (TC)u[__builtin_nontemporal_load(lid + base + k * L2)] : TC(0);
+        if constexpr (GATHER) {
+            const int32_t q = live ? __builtin_nontemporal_load(lid + base + k * L2) : -1;
+            uc[k] = q >= 0 ? (TC)u[q] : TC(0);
+        }
         else
             uc[k] = live ? (TC)Load<TU>::get(u, base + k * L2) : TC(0);
     }

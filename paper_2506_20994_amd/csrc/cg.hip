@@ -100,10 +100,13 @@ __global__ void to_unique_kernel(T* __restrict__ out, const double* __restrict__
     GRID_LOOP(u, nu) out[u] = (T)in[uidx[uoff[u]]];
 }
 
-// out_L = in_u[lid[L]]
+// out_L = in_u[lid[L]] (0 on Dirichlet nodes, lid = -1)
 __global__ void to_local_kernel(double* __restrict__ out, const double* __restrict__ in,
                                 const int32_t* __restrict__ lid, int64_t n) {
-    GRID_LOOP(L, n) out[L] = in[lid[L]];
+    GRID_LOOP(L, n) {
+        const int32_t u = lid[L];
+        out[L] = u >= 0 ? in[u] : 0.0;
+    }
 }
 
 // out_u = 1 / (sum of the copies of the element diagonal d_L)
@@ -279,20 +282,22 @@ __global__ void residual_kernel(double* __restrict__ r, const double* __restrict
     GRID_LOOP(u, nu) r[u] = b[u] - assemble(wl, uoff, u);
 }
 
-// IR: rhat = (float)((r - mean) / norm), mean = s0 / nu, norm^2 = q - nu mean^2
+// IR: rhat = (float)((r - mean) / norm), mean = s0 * inv_nu (inv_nu = 1 / nu on
+// the singular periodic operator, 0 where no mean is projected),
+// norm^2 = q - mean s0
 __global__ void ir_scale_kernel(float* __restrict__ rhat, const double* __restrict__ r,
-                                const double* __restrict__ sums, double nu, int64_t n) {
-    const double c = sums[0] / nu;
-    const double nrm2 = sums[1] - nu * c * c;
+                                const double* __restrict__ sums, double inv_nu, int64_t n) {
+    const double c = sums[0] * inv_nu;
+    const double nrm2 = sums[1] - c * sums[0];
     const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
     GRID_LOOP(u, n) rhat[u] = (float)((r[u] - c) * inv);
 }
 
 // IR: x += norm * d (float64 update)
 __global__ void ir_update_kernel(double* __restrict__ x, const float* __restrict__ d,
-                                 const double* __restrict__ sums, double nu, int64_t n) {
-    const double c = sums[0] / nu;
-    const double nrm2 = sums[1] - nu * c * c;
+                                 const double* __restrict__ sums, double inv_nu, int64_t n) {
+    const double c = sums[0] * inv_nu;
+    const double nrm2 = sums[1] - c * sums[0];
     const double nrm = nrm2 > 0.0 ? sqrt(nrm2) : 0.0;
     GRID_LOOP(u, n) x[u] += nrm * (double)d[u];
 }
@@ -603,6 +608,10 @@ struct sem_cg_s {
 
 namespace {
 
+// The periodic operator is singular (null space: the constants), so its
+// solves project out the mean; with Dirichlet nodes the operator is not.
+inline bool projects(sem_cg_t cg) { return cg->gs->n_masked == 0; }
+
 int cg_alloc(sem_cg_t cg, void** p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) return sem::check_hip(cg->ctx, e, "sem_cg_setup: hipMalloc");
@@ -757,7 +766,7 @@ int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int chec
         ++nrep;
         if (rel <= tol || H.it >= maxit) break;
         // the float64 residual carries the (tiny) mean that rounding left; drop it
-        sub_mean_kernel<<<g, kBlock, 0, st>>>(cg->r64, cg->sums, (double)n, n);
+        if (projects(cg)) sub_mean_kernel<<<g, kBlock, 0, st>>>(cg->r64, cg->sums, (double)n, n);
         rr_replace_kernel<<<g, kBlock, 0, st>>>(r, cg->r64, minv, n, cg->part);
         rr_resume_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
         // PCG: the paused iteration skipped its direction update, redone with
@@ -862,6 +871,7 @@ int residual64(sem_cg_t cg, const double* xu) {
 }
 
 int remove_mean_u(sem_cg_t cg, double* xu) {
+    if (!projects(cg)) return SEM_OK;
     int rc = vec_sums(cg, xu);
     if (rc) return rc;
     sub_mean_kernel<<<vec_grid(cg->nu), kBlock, 0, cg->ctx->stream>>>(xu, cg->sums, (double)cg->nu, cg->nu);
@@ -889,6 +899,7 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
         if (!Dp[q] || !Gp[q]) return sem::fail(ctx, SEM_EINVAL, "sem_cg_setup: null operator array");
     if (opts->precision < SEM_SOLVE_F64 || opts->precision > SEM_SOLVE_BF16_IR)
         return sem::fail(ctx, SEM_EINVAL, "sem_cg_setup: bad precision %d", opts->precision);
+    if (gs->n_unique == 0) return sem::fail(ctx, SEM_EINVAL, "sem_cg_setup: the plan has no unknowns");
 
     auto* cg = new sem_cg_s();
     cg->ctx = ctx;
@@ -1057,8 +1068,10 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
             if (rc) return rc;
             const double rnorm = std::sqrt(rq);
             if (!(rnorm > opts->tol * bnorm)) break;
-            sub_mean_kernel<<<gu, kBlock, 0, st>>>(cg->r64, cg->sums, (double)nu, nu);
-            SEM_LAUNCH_CHECK(ctx);
+            if (projects(cg)) {
+                sub_mean_kernel<<<gu, kBlock, 0, st>>>(cg->r64, cg->sums, (double)nu, nu);
+                SEM_LAUNCH_CHECK(ctx);
+            }
             const double tol_d = opts->tol * bnorm / rnorm;
             int its_d = 0, brk_d = 0, nj_d = 0, fb_d = 0;
             L.x = cg->d64;                       // the correction goes to d64, x64 is kept
@@ -1093,6 +1106,7 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
             goto finish;
         }
         {
+        const double inv_nu = projects(cg) && nu > 0 ? 1.0 / (double)nu : 0.0;
         const double itol = opts->inner_tol > 0 ? opts->inner_tol : (bf ? 1e-2 : 1e-6);
         const int imax = opts->inner_maxit > 0 ? opts->inner_maxit : 500;
         const int omax = std::min(opts->max_outer > 0 ? opts->max_outer : 60, 64);
@@ -1106,12 +1120,12 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
             double s, q;
             rc = read_sums(cg, &s, &q);
             if (rc) return rc;
-            const double c = s / (double)nu;
-            const double rn = std::sqrt(std::max(q - (double)nu * c * c, 0.0));
+            const double c = s * inv_nu;
+            const double rn = std::sqrt(std::max(q - c * s, 0.0));
             const double rel = bnorm > 0 ? rn / bnorm : 0.0;
             if (outer > 0) stats->relres_hist[outer - 1] = rel;
             if (rel <= opts->tol || total >= maxit) break;
-            ir_scale_kernel<<<gu, kBlock, 0, st>>>(cg->rhs32, cg->r64, cg->sums, (double)nu, nu);
+            ir_scale_kernel<<<gu, kBlock, 0, st>>>(cg->rhs32, cg->r64, cg->sums, inv_nu, nu);
             int its = 0, brk = 0, nj = 0, fb = 0;
             if (cg->lp)
                 rc = fcg_run<float>(cg, L, cg->rhs32, itol, std::min(imax, maxit - total), check,
@@ -1125,7 +1139,7 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
             total += its;
             stats->outer = outer + 1;
             if (brk) stats->breakdown = 1;
-            ir_update_kernel<<<gu, kBlock, 0, st>>>(cg->x64, (const float*)L.x, cg->sums, (double)nu, nu);
+            ir_update_kernel<<<gu, kBlock, 0, st>>>(cg->x64, (const float*)L.x, cg->sums, inv_nu, nu);
             rc = remove_mean_u(cg, cg->x64);
             if (rc) return rc;
             rc = residual64(cg, cg->x64);
@@ -1136,7 +1150,7 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
         }
     }
 finish:
-    // x: mean-free, back to the local layout; final float64 residual
+    // x: mean-free (periodic), back to the local layout; final float64 residual
     rc = remove_mean_u(cg, cg->x64);
     if (rc) return rc;
     rc = residual64(cg, cg->x64);
@@ -1161,6 +1175,8 @@ extern "C" int sem_remove_mean(sem_gs_t gs, double* x) {
     sem_ctx_t ctx = gs->ctx;
     int rc = sem::enter(ctx);
     if (rc) return rc;
+    if (gs->n_masked > 0)
+        return sem::fail(ctx, SEM_EINVAL, "sem_remove_mean: the plan has Dirichlet nodes (no null space)");
     if (gs->n_local == 0) return SEM_OK;
     if (!x) return sem::fail(ctx, SEM_EINVAL, "sem_remove_mean: null field");
     const int64_t n = gs->n_local;

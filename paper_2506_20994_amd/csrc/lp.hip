@@ -348,9 +348,10 @@ __global__ void features_kernel(u16* __restrict__ X, float* __restrict__ scale, 
     for (int c = 0; c < 8; ++c) {
         const int64_t L = e * kOut + c * 64 + lane;
         const int64_t u = lid ? (int64_t)lid[L] : L;
-        v[c] = (double)r[u];
-        if (uoff) v[c] *= rsqrt((double)(uoff[u + 1] - uoff[u]));     // S = mult^-1/2
-        else if (mult) v[c] *= rsqrt(mult[L]);
+        if (u < 0) v[c] = 0.0;                                         // Dirichlet node
+        else if (uoff) v[c] = (double)r[u] * rsqrt((double)(uoff[u + 1] - uoff[u]));  // S = mult^-1/2
+        else if (mult) v[c] = (double)r[u] * rsqrt(mult[L]);
+        else v[c] = (double)r[u];
         ss += v[c] * v[c];
     }
     ss = sem::wave_sum(ss);
@@ -440,6 +441,12 @@ __device__ __forceinline__ bf16x8 pack_bf16x8(const float* v) {
     return __builtin_bit_cast(bf16x8, w);
 }
 
+// r[u], or 0 for a Dirichlet node (u < 0)
+template <typename T>
+__device__ __forceinline__ float ld_free(const T* __restrict__ r, int32_t u) {
+    return u >= 0 ? (float)r[u] : 0.0f;
+}
+
 // X[e][n] = bf16(S r) at the unique node of local node (e, n); 8 nodes per
 // thread.  S comes per local node (sl, a coalesced stream), so r is the only
 // gathered array.
@@ -455,25 +462,25 @@ __global__ void lin_gather_kernel(u16* __restrict__ X, const T* __restrict__ r, 
         const float4 s0 = *reinterpret_cast<const float4*>(sl + L);
         const float4 s1 = *reinterpret_cast<const float4*>(sl + L + 4);
         float v[8];
-        v[0] = (float)r[i0.x] * s0.x;
-        v[1] = (float)r[i0.y] * s0.y;
-        v[2] = (float)r[i0.z] * s0.z;
-        v[3] = (float)r[i0.w] * s0.w;
-        v[4] = (float)r[i1.x] * s1.x;
-        v[5] = (float)r[i1.y] * s1.y;
-        v[6] = (float)r[i1.z] * s1.z;
-        v[7] = (float)r[i1.w] * s1.w;
+        v[0] = ld_free(r, i0.x) * s0.x;
+        v[1] = ld_free(r, i0.y) * s0.y;
+        v[2] = ld_free(r, i0.z) * s0.z;
+        v[3] = ld_free(r, i0.w) * s0.w;
+        v[4] = ld_free(r, i1.x) * s1.x;
+        v[5] = ld_free(r, i1.y) * s1.y;
+        v[6] = ld_free(r, i1.z) * s1.z;
+        v[7] = ld_free(r, i1.w) * s1.w;
         *reinterpret_cast<bf16x8*>(X + (L / kOut) * kInPad + (L % kOut)) = pack_bf16x8(v);
     }
 }
 
-// sl[L] = mult^-1/2 of local node L
+// sl[L] = mult^-1/2 of local node L (0 on Dirichlet nodes)
 __global__ void sl_kernel(float* __restrict__ sl, const int32_t* __restrict__ lid, const int32_t* __restrict__ uoff,
                           int64_t n) {
     for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
          L += (int64_t)gridDim.x * blockDim.x) {
         const int32_t u = lid[L];
-        sl[L] = (float)(1.0 / sqrt((double)(uoff[u + 1] - uoff[u])));
+        sl[L] = u >= 0 ? (float)(1.0 / sqrt((double)(uoff[u + 1] - uoff[u]))) : 0.0f;
     }
 }
 
@@ -631,10 +638,11 @@ __global__ void zero_f32(float* __restrict__ x, int n) {
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) x[q] = 0.f;
 }
 
+// x = 1 / x, with 0 kept at 0 (Dirichlet nodes, zeroed by the gather-scatter)
 __global__ void inv_kernel(double* __restrict__ x, int64_t n) {
     for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
          L += (int64_t)gridDim.x * blockDim.x)
-        x[L] = 1.0 / x[L];
+        x[L] = x[L] != 0.0 ? 1.0 / x[L] : 0.0;
 }
 
 unsigned grid_of(int64_t n, int64_t cap = 4096) {

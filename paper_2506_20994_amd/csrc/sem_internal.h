@@ -21,14 +21,16 @@ struct sem_ctx_s {
 struct sem_gs_s {
     sem_ctx_t ctx = nullptr;
     int64_t n_local = 0, n_unique = 0, n_shared = 0, n_entries = 0;
+    int64_t n_masked = 0;       // Dirichlet nodes (negative ids): no unique index, zeroed by gs
     int32_t* off = nullptr;     // device, n_shared + 1
     int32_t* idx = nullptr;     // device, n_entries local indices
     double* mult = nullptr;     // device, n_local multiplicities
     double* owner = nullptr;    // device, n_local: 1 on the first copy of each id, else 0
     // dense unique numbering (ids renumbered in order of first appearance)
-    int32_t* lid = nullptr;     // device, n_local: unique index of each local node
+    int32_t* lid = nullptr;     // device, n_local: unique index of each local node (-1: Dirichlet)
     int32_t* uoff = nullptr;    // device, n_unique + 1: CSR of the local copies of every unique node
-    int32_t* uidx = nullptr;    // device, n_local: local indices, ascending within a row
+    int32_t* uidx = nullptr;    // device, n_local: local indices, ascending within a row; the
+                                //   n_masked Dirichlet nodes last
     int32_t* upos = nullptr;    // device, n_local: position of each local node in uidx
 };
 

@@ -106,9 +106,11 @@ inline unsigned grid_for(int64_t n, int64_t cap = 1 << 20) {
     return (unsigned)b;
 }
 
+// ids: periodic lattice position, or (dirichlet) -1 on the box boundary and
+// the position on the (M - 1)^3 lattice of interior points
 __global__ void box_mesh_kernel(int n, int lx, double amp, GllArgs g, int64_t n_local,
                                 double* __restrict__ x, double* __restrict__ y,
-                                double* __restrict__ z, int64_t* __restrict__ ids) {
+                                double* __restrict__ z, int64_t* __restrict__ ids, bool dirichlet) {
     const int N = lx - 1;
     const int64_t M = (int64_t)n * N;
     const int64_t l3 = (int64_t)lx * lx * lx;
@@ -128,7 +130,11 @@ __global__ void box_mesh_kernel(int n, int lx, double amp, GllArgs g, int64_t n_
             if (y) y[L] = Y + amp * sz * sx;
             if (z) z[L] = Z + amp * sx * sy;
         }
-        if (ids) {
+        if (ids && dirichlet) {
+            const int64_t I = ex * N + i, J = ey * N + j, K = ez * N + k;
+            const bool inside = I > 0 && I < M && J > 0 && J < M && K > 0 && K < M;
+            ids[L] = inside ? ((K - 1) * (M - 1) + (J - 1)) * (M - 1) + (I - 1) : -1;
+        } else if (ids) {
             const int64_t gi = (ex * N + i) % M, gj = (ey * N + j) % M, gk = (ez * N + k) % M;
             ids[L] = (gk * M + gj) * M + gi;
         }
@@ -212,8 +218,10 @@ template <typename T>
 __global__ void scatter_kernel(T* __restrict__ out, const T* __restrict__ in,
                                const int64_t* __restrict__ ids, int64_t n) {
     for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
-         L += (int64_t)gridDim.x * blockDim.x)
-        out[L] = in[ids[L]];
+         L += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = ids[L];
+        out[L] = g >= 0 ? in[g] : T(0);          // negative id: Dirichlet node, 0
+    }
 }
 
 __global__ void ax_diag_kernel(double* __restrict__ d, const double* __restrict__ dx,
@@ -297,17 +305,32 @@ __global__ void convert_kernel(TD* __restrict__ dst, const TS* __restrict__ src,
 
 }  // namespace
 
-extern "C" int sem_box_mesh(sem_ctx_t ctx, int n, int lx, double amp, double* x, double* y,
-                            double* z, int64_t* ids) {
+namespace {
+
+int box_mesh(sem_ctx_t ctx, const char* name, int n, int lx, double amp, double* x, double* y, double* z,
+             int64_t* ids, bool dirichlet) {
     int rc = sem::enter(ctx);
     if (rc) return rc;
-    if (!sem::lx_ok(lx)) return sem::fail(ctx, SEM_EUNSUPPORTED_LX, "sem_box_mesh: lx=%d", lx);
-    if (n < 1) return sem::fail(ctx, SEM_EINVAL, "sem_box_mesh: n=%d < 1", n);
+    if (!sem::lx_ok(lx)) return sem::fail(ctx, SEM_EUNSUPPORTED_LX, "%s: lx=%d", name, lx);
+    if (n < 1) return sem::fail(ctx, SEM_EINVAL, "%s: n=%d < 1", name, n);
     const int64_t n_local = (int64_t)n * n * n * lx * lx * lx;
     GllArgs g = make_gll(lx);
-    box_mesh_kernel<<<grid_for(n_local), kBlock, 0, ctx->stream>>>(n, lx, amp, g, n_local, x, y, z, ids);
+    box_mesh_kernel<<<grid_for(n_local), kBlock, 0, ctx->stream>>>(n, lx, amp, g, n_local, x, y, z, ids,
+                                                                   dirichlet);
     SEM_LAUNCH_CHECK(ctx);
     return SEM_OK;
+}
+
+}  // namespace
+
+extern "C" int sem_box_mesh(sem_ctx_t ctx, int n, int lx, double amp, double* x, double* y,
+                            double* z, int64_t* ids) {
+    return box_mesh(ctx, "sem_box_mesh", n, lx, amp, x, y, z, ids, false);
+}
+
+extern "C" int sem_box_mesh_dirichlet(sem_ctx_t ctx, int n, int lx, double amp, double* x, double* y,
+                                      double* z, int64_t* ids) {
+    return box_mesh(ctx, "sem_box_mesh_dirichlet", n, lx, amp, x, y, z, ids, true);
 }
 
 extern "C" int sem_geometry(sem_ctx_t ctx, const double* x, const double* y, const double* z,
