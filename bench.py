@@ -25,6 +25,12 @@ Extra fields:
                 boxes, then used as a symmetric additive preconditioner inside
                 flexible CG on the same 32^3 solve, in float64 and inside float64
                 residual replacement around float32 / bfloat16-factor iterations.
+  dirichlet     the same solves on the 32^3 box with homogeneous Dirichlet
+                conditions on the whole boundary (boundary nodes no unknowns):
+                float64 Jacobi-PCG, float32 / bfloat16 residual replacement,
+                and flexible CG with the learned block (trained on periodic
+                boxes) and with the classical block inside float32 residual
+                replacement.
 
 --mode copy times a plain 1 GiB device copy (used to calibrate the HBM byte
 counters of rocprofv3); it prints nothing on stdout.  --mode scale runs the
@@ -117,7 +123,61 @@ def solve_comparison(ctx, P, n, lx, amp, tol=1e-10):
     return res
 
 
-def learned_comparison(ctx, P, n, lx, amp, solve=None, tol=1e-10):
+def _timed_solve(P, op, x, b, code, mode, lp, tol):
+    """One warm-up and one timed sem_cg_solve; returns (ms, stats)."""
+    import torch
+    kw = dict(tol=tol, precision=code, ir_mode=mode, learned=lp, maxit=50000)
+    cg = op.solver(code, learned=lp)
+    P.sem_cg_solve(cg, x, b, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st = P.sem_cg_solve(cg, x, b, **kw)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    cg.close()
+    return ms, st
+
+
+def dirichlet_comparison(ctx, P, n, lx, amp, lp=None, tol=1e-10):
+    """Solves on the n^3 box with u = 0 on the whole boundary (same deformation
+    and right-hand side as the periodic solves, no mean projection)."""
+    import torch
+    import synth
+    from paper_2506_20994_amd.box import BoxOperator
+    from paper_2506_20994_amd import learned as LR
+    op = BoxOperator(ctx, n, lx, amp, dirichlet=True)
+    k, a, ph = synth.fourier_modes(2)
+    b = op.fourier_rhs(k, a, ph)
+    x = torch.empty_like(b)
+    res = {"workload": f"{n}^3 box lx={lx} amplitude {amp}, u=0 on the boundary, h1=1, "
+                       f"32 Fourier modes, tol {tol}", "unique_dofs": op.n_unique}
+    blk = None
+    if lx == 8:
+        blk = P.sem_lp_create(ctx, n ** 3)
+        P.sem_lp_set_block(blk, LR.reference_block(ctx, lx))
+    variants = [("fp64_pcg", P.SEM_SOLVE_F64, 0, None), ("f32_rr", P.SEM_SOLVE_F32_IR, 1, None),
+                ("bf16_rr", P.SEM_SOLVE_BF16_IR, 1, None)]
+    if lp is not None:
+        variants.append(("learned_f32_rr", P.SEM_SOLVE_F32_IR, 1, lp))
+    if blk is not None:
+        variants.append(("classical_block_f32_rr", P.SEM_SOLVE_F32_IR, 1, blk))
+    for name, code, mode, net in variants:
+        if net is not None:
+            op.bind(net)
+        ms, st = _timed_solve(P, op, x, b, code, mode, net, tol)
+        res[name] = {"ms": round(ms, 2), "iterations": st["iterations"], "relres": st["relres"],
+                     "jacobi_steps": st["jacobi_steps"], "converged": st["converged"]}
+        print(f"[bench] dirichlet {name}: {ms:.1f} ms, {st['iterations']} its, relres {st['relres']:.2e}",
+              file=sys.stderr, flush=True)
+    base = res["fp64_pcg"]["ms"]
+    res["speedup_vs_fp64_pcg"] = {v[0]: round(base / res[v[0]]["ms"], 3) for v in variants[1:]}
+    if blk is not None:
+        blk.close()
+    op.gs.close()
+    return res
+
+
+def learned_comparison(ctx, P, n, lx, amp, solve=None, tol=1e-10, keep=False):
     """Train the per-element network (linear form, energy-norm loss, Jacobi
     base) on the GPU from float64 Jacobi-PCG pairs on 16^3 boxes (random
     amplitudes U[0, 0.2], white-noise right-hand sides: residual b, error x*),
@@ -196,8 +256,10 @@ def learned_comparison(ctx, P, n, lx, amp, solve=None, tol=1e-10):
         res["speedup_vs_same_precision_without_network"] = {
             "f32_rr": round(solve["f32_rr"]["ms"] / res["learned_f32_rr"]["ms"], 3),
             "bf16_rr": round(solve["bf16_rr"]["ms"] / res["learned_bf16_rr"]["ms"], 3)}
-    lp.close()
     op.gs.close()
+    if keep:
+        return res, lp
+    lp.close()
     return res
 
 
@@ -405,8 +467,12 @@ def main():
         del op, u, w
         torch.cuda.empty_cache()
         out["solve"] = solve_comparison(ctx, P, n, lx, amp)
+        lp = None
         if not args.no_learned and lx == 8:
-            out["learned"] = learned_comparison(ctx, P, n, lx, amp, solve=out["solve"])
+            out["learned"], lp = learned_comparison(ctx, P, n, lx, amp, solve=out["solve"], keep=True)
+        out["dirichlet"] = dirichlet_comparison(ctx, P, n, lx, amp, lp)
+        if lp is not None:
+            lp.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(lx)
     print(json.dumps(out), flush=True)

@@ -54,18 +54,20 @@ def linear_apply_at_nodes(params, n, lx, amp, ids, r_glob, gids, jacobi=False):
 def operator_at_nodes(n, lx, amp, ids, x_glob, gids, h1_glob=None):
     """(A x)_g of the n^3 box's assembled operator at the global ids `gids`, each
     from the elements that contain it (oracle geometry and einsum operator):
-    for large meshes, where the whole-mesh oracle is too slow."""
+    for large meshes, where the whole-mesh oracle is too slow.  Negative ids
+    (Dirichlet nodes) read 0."""
     from oracle.mesh import box_coords
     from oracle.geometry import geometric_factors
     from oracle.gll import listing_matrices
     from oracle.ax import ax_einsum
+    from oracle.gs import scatter
     flat = ids.reshape(len(ids), -1)
     M = listing_matrices(lx)
     out = np.empty(len(gids))
     for q, g in enumerate(gids):
         els = np.nonzero((flat == g).any(axis=1))[0]
         G, _, _ = geometric_factors(*box_coords(n, lx, amp, els), lx)
-        h1 = None if h1_glob is None else h1_glob[ids[els]]
-        w = ax_einsum(x_glob[ids[els]], *M, h1, *G).reshape(len(els), -1)
+        h1 = None if h1_glob is None else scatter(h1_glob, ids[els])
+        w = ax_einsum(scatter(x_glob, ids[els]), *M, h1, *G).reshape(len(els), -1)
         out[q] = np.sum(w[flat[els] == g])
     return out

@@ -123,17 +123,19 @@ def test_remove_mean_and_owner(sem_ctx):
                                atol=1e-13)
 
 
-@pytest.mark.parametrize("prec,mode", [("f64", 0), ("f32", 1), ("bf16", 1)])
-def test_solve_full_size_sampled(sem_ctx, prec, mode):
-    """The benchmark's solve (32^3 box, lx = 8, amplitude 0.1, 32 Fourier modes,
-    relres 1e-10) in float64 PCG and float32 / bfloat16 residual replacement:
-    the oracle recomputes b - A x at 48 sampled unique nodes from the elements
-    containing each (its own geometry and operator), and every component must
-    satisfy |r_g| <= ||r||_2 <= 1.2e-10 ||b||_2."""
-    from oracle.mesh import global_ids
+@pytest.mark.parametrize("prec,mode,dirichlet", [("f64", 0, False), ("f32", 1, False), ("bf16", 1, False),
+                                                  ("f64", 0, True), ("f32", 1, True)])
+def test_solve_full_size_sampled(sem_ctx, prec, mode, dirichlet):
+    """The benchmark's solves (32^3 box, lx = 8, amplitude 0.1, 32 Fourier modes,
+    relres 1e-10; periodic, and with Dirichlet conditions on the boundary) in
+    float64 PCG and float32 / bfloat16 residual replacement: the oracle
+    recomputes b - A x at 48 sampled unique nodes from the elements containing
+    each (its own geometry and operator), and every component must satisfy
+    |r_g| <= ||r||_2 <= 1.2e-10 ||b||_2."""
+    from oracle.mesh import global_ids, global_ids_dirichlet
     from tests.helpers import operator_at_nodes
     n, lx, amp = 32, 8, 0.1
-    op = BoxOperator(sem_ctx, n, lx, amp)
+    op = BoxOperator(sem_ctx, n, lx, amp, dirichlet=dirichlet)
     k, a, ph = synth.fourier_modes(2)
     b = op.fourier_rhs(k, a, ph)
     code = {"f64": P.SEM_SOLVE_F64, "f32": P.SEM_SOLVE_F32_IR, "bf16": P.SEM_SOLVE_BF16_IR}[prec]
@@ -142,15 +144,19 @@ def test_solve_full_size_sampled(sem_ctx, prec, mode):
     rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10, precision=code, ir_mode=mode)
     torch.cuda.synchronize()
     assert rc == P.SEM_OK and st["converged"] and st["relres"] <= 1e-10, st
-    ids = global_ids(n, lx)
-    nu = (n * (lx - 1)) ** 3
+    ids = global_ids_dirichlet(n, lx) if dirichlet else global_ids(n, lx)
+    nu = op.n_unique
+    free = ids >= 0
+    bl, xl = b.cpu().numpy(), x.cpu().numpy()
+    assert np.all(bl[~free] == 0.0) and np.all(xl[~free] == 0.0)
     bg = np.zeros(nu)
     xg = np.zeros(nu)
-    bg[ids.ravel()] = b.cpu().numpy().ravel()
-    xg[ids.ravel()] = x.cpu().numpy().ravel()
+    bg[ids[free]] = bl[free]
+    xg[ids[free]] = xl[free]
     gids = synth.choice(60, nu, 48)
     r = bg[gids] - operator_at_nodes(n, lx, amp, ids, xg, gids)
     assert np.max(np.abs(r)) <= 1.2e-10 * np.linalg.norm(bg), (np.max(np.abs(r)), np.linalg.norm(bg))
-    assert abs(xg.sum()) <= 1e-10 * np.abs(xg).sum()
+    if not dirichlet:
+        assert abs(xg.sum()) <= 1e-10 * np.abs(xg).sum()
     cg.close()
     op.gs.close()
