@@ -17,7 +17,10 @@ names no solver.  The readings used here:
     relative residual is <= tol;
   * flexible CG with one stored direction (Notay 2000, FCG(1));
   * the Dirichlet box (oracle.mesh.global_ids_dirichlet) has no null space:
-    there the right-hand side is not projected and no mean is removed.
+    there the right-hand side is not projected and no mean is removed;
+  * the Helmholtz problem (velocity-type solves): the operator A + h2 B with a
+    constant h2 > 0 and the diagonal mass B (oracle.ax.ax_helmholtz); it is
+    positive definite on either box, so nothing is projected either.
 Pins: on tiny meshes PCG agrees with the pseudo-inverse solution; FCG with the
 Jacobi preconditioner reproduces PCG's iterates; spectral convergence of a
 manufactured solution (tests/test_oracle_solve.py).
@@ -27,19 +30,21 @@ import numpy as np
 from .gll import gll_nodes_weights, deriv_matrix
 from .mesh import box_coords, global_ids, n_unique, global_ids_dirichlet, n_unique_dirichlet
 from .geometry import geometric_factors
-from .ax import ax_einsum
+from .ax import ax_einsum, ax_helmholtz
 from .gs import gather, scatter, multiplicity
 from .assemble import element_diagonal
 
 
 class BoxProblem:
     """n^3 box, lx points per direction, deformation amplitude a; periodic,
-    or with homogeneous Dirichlet conditions on the whole boundary."""
+    or with homogeneous Dirichlet conditions on the whole boundary; Poisson,
+    or Helmholtz with the constant h2 (operator A + h2 B)."""
 
-    def __init__(self, n, lx, a=0.0, h1_unique=None, dirichlet=False):
+    def __init__(self, n, lx, a=0.0, h1_unique=None, dirichlet=False, h2=None):
         self.n, self.lx, self.a = n, lx, a
         self.dirichlet = dirichlet
-        self.project = not dirichlet       # the periodic operator is singular
+        # only the periodic Poisson operator is singular (null space: constants)
+        self.project = not dirichlet and h2 is None
         xi, self.wgll = gll_nodes_weights(lx - 1)
         self.Dh = deriv_matrix(xi)
         self.dx = np.ascontiguousarray(self.Dh.T)
@@ -50,9 +55,12 @@ class BoxProblem:
         self.nu = n_unique_dirichlet(n, lx) if dirichlet else n_unique(n, lx)
         self.mult = multiplicity(self.ids, self.nu)
         self.h1 = None if h1_unique is None else scatter(h1_unique, self.ids)
+        self.h2b = None if h2 is None else h2 * self.B
 
     def ax_local(self, u_local):
         d, t = self.dx, self.dxt
+        if self.h2b is not None:
+            return ax_helmholtz(u_local, d, d, d, t, t, t, self.h1, *self.G, self.h2b)
         return ax_einsum(u_local, d, d, d, t, t, t, self.h1, *self.G)
 
     def apply(self, x_unique):
@@ -60,11 +68,14 @@ class BoxProblem:
         return gather(self.ax_local(scatter(x_unique, self.ids)), self.ids, self.nu)
 
     def diagonal(self):
-        return gather(element_diagonal(self.Dh, self.h1, self.G), self.ids, self.nu)
+        d = element_diagonal(self.Dh, self.h1, self.G)
+        if self.h2b is not None:
+            d = d + self.h2b
+        return gather(d, self.ids, self.nu)
 
     def fourier_rhs(self, k, amp, phase):
         """b_G for f = sum_m amp_m cos(2 pi k_m . x + phase_m), projected to
-        1^T b_G = 0 on the periodic box."""
+        1^T b_G = 0 for the periodic Poisson operator."""
         x, y, z = self.coords
         f = np.zeros_like(x)
         for m in range(len(amp)):

@@ -87,3 +87,47 @@ def test_operator_at_nodes_matches_whole_mesh(dirichlet):
     got = operator_at_nodes(n, lx, amp, ids, xG, np.arange(P.nu))
     ref = P.apply(xG)
     np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_helmholtz_manufactured_solution():
+    """(-lap + h2) u = f on the periodic unit box with u = sin(2 pi x)
+    sin(2 pi y) sin(2 pi z), f = (12 pi^2 + h2) u: the Helmholtz operator is
+    non-singular, so nothing is projected, and the discrete error falls
+    spectrally in lx."""
+    from oracle.gs import gather
+    h2 = 50.0
+    errs = []
+    for lx in (4, 6, 8):
+        P = BoxProblem(2, lx, 0.0, h2=h2)
+        assert not P.project
+        x, y, z = P.coords
+        u = np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y) * np.sin(2 * np.pi * z)
+        b = gather(P.B * (12 * np.pi ** 2 + h2) * u, P.ids, P.nu)
+        sol, it, hist = pcg(P.apply, b, 1.0 / P.diagonal(), tol=1e-13, project=False)
+        ex = np.zeros(P.nu)
+        ex[P.ids.ravel()] = u.ravel()
+        errs.append(np.max(np.abs(sol - ex)))
+    assert errs[0] > 100 * errs[1] and errs[1] > 100 * errs[2]
+    assert errs[2] < 1e-6
+
+
+@pytest.mark.parametrize("dirichlet", [False, True])
+def test_helmholtz_operator_bounds(dirichlet):
+    """A + h2 B with the diagonal mass: the matrix-free apply equals the
+    assembled stiffness plus the assembled (diagonal) mass, and since A is
+    positive semi-definite every eigenvalue is at least h2 min_G (Q^T B)_G."""
+    from oracle.gs import gather
+    h2 = 3.0
+    n, lx = (3, 4) if dirichlet else (2, 4)
+    P = BoxProblem(n, lx, 0.1, dirichlet=dirichlet, h2=h2)
+    A = assembled_matrix(P.Dh, None, P.G, P.ids, P.nu).toarray()
+    m = gather(P.B, P.ids, P.nu)
+    H = A + np.diag(h2 * m)
+    x = synth.unique_normal(P.nu, 4)
+    np.testing.assert_allclose(P.apply(x), H @ x, rtol=1e-12, atol=1e-12 * np.abs(H @ x).max())
+    np.testing.assert_allclose(P.diagonal(), np.diag(H), rtol=1e-12)
+    ev = np.linalg.eigvalsh(0.5 * (H + H.T))
+    assert ev[0] >= h2 * m.min() * (1 - 1e-10)
+    b = P.fourier_rhs(*synth.fourier_modes(2, count=8, kmax=2))
+    xs, _, _ = pcg(P.apply, b, 1.0 / P.diagonal(), tol=1e-12, project=False)
+    np.testing.assert_allclose(xs, np.linalg.solve(H, b), rtol=0, atol=1e-9 * np.abs(xs).max())
