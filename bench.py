@@ -31,6 +31,10 @@ Extra fields:
                 and flexible CG with the learned block (trained on periodic
                 boxes) and with the classical block inside float32 residual
                 replacement.
+  helmholtz_solve  the Helmholtz operator A + h2 B (h2 = 1e3, a velocity-type
+                solve; constant plus Fourier source, no projection) on the
+                periodic 32^3 box: float64 Jacobi-PCG against float32 residual
+                replacement, and flexible CG with the classical block.
 
 --mode copy times a plain 1 GiB device copy (used to calibrate the HBM byte
 counters of rocprofv3); it prints nothing on stdout.  --mode scale runs the
@@ -168,6 +172,52 @@ def dirichlet_comparison(ctx, P, n, lx, amp, lp=None, tol=1e-10):
         res[name] = {"ms": round(ms, 2), "iterations": st["iterations"], "relres": st["relres"],
                      "jacobi_steps": st["jacobi_steps"], "converged": st["converged"]}
         print(f"[bench] dirichlet {name}: {ms:.1f} ms, {st['iterations']} its, relres {st['relres']:.2e}",
+              file=sys.stderr, flush=True)
+    base = res["fp64_pcg"]["ms"]
+    res["speedup_vs_fp64_pcg"] = {v[0]: round(base / res[v[0]]["ms"], 3) for v in variants[1:]}
+    if blk is not None:
+        blk.close()
+    op.gs.close()
+    return res
+
+
+def helmholtz_solve_comparison(ctx, P, n, lx, amp, h2=1e3, tol=1e-10):
+    """A + h2 B on the periodic box (f = 1 + the Fourier sum; nothing projected)."""
+    import torch
+    import synth
+    from paper_2506_20994_amd.box import BoxOperator
+    from paper_2506_20994_amd import learned as LR
+    op = BoxOperator(ctx, n, lx, amp)
+    k, a, ph = synth.fourier_modes(2)
+    b = op.fourier_rhs(k, a, ph, project=False)
+    mass = op.bm.clone()
+    P.sem_gs(op.gs, mass)
+    b += mass
+    x = torch.empty_like(b)
+    h2b = h2 * op.bm
+    res = {"workload": f"{n}^3 periodic box lx={lx} amplitude {amp}, A + h2 B with h2={h2:g}, "
+                       f"f = 1 + 32 Fourier modes, tol {tol}"}
+    blk = None
+    if lx == 8:
+        blk = P.sem_lp_create(ctx, n ** 3)
+        P.sem_lp_set_block(blk, LR.reference_block(ctx, lx))
+        op.bind(blk)
+    variants = [("fp64_pcg", P.SEM_SOLVE_F64, 0, None), ("f32_rr", P.SEM_SOLVE_F32_IR, 1, None)]
+    if blk is not None:
+        variants.append(("classical_block_f32_rr", P.SEM_SOLVE_F32_IR, 1, blk))
+    for name, code, mode, net in variants:
+        kw = dict(tol=tol, precision=code, ir_mode=mode, learned=net, maxit=50000)
+        cg = op.solver(code, h2b=h2b, learned=net)
+        P.sem_cg_solve(cg, x, b, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = P.sem_cg_solve(cg, x, b, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        cg.close()
+        res[name] = {"ms": round(ms, 2), "iterations": st["iterations"], "relres": st["relres"],
+                     "converged": st["converged"]}
+        print(f"[bench] helmholtz_solve {name}: {ms:.1f} ms, {st['iterations']} its, relres {st['relres']:.2e}",
               file=sys.stderr, flush=True)
     base = res["fp64_pcg"]["ms"]
     res["speedup_vs_fp64_pcg"] = {v[0]: round(base / res[v[0]]["ms"], 3) for v in variants[1:]}
@@ -473,6 +523,7 @@ def main():
         out["dirichlet"] = dirichlet_comparison(ctx, P, n, lx, amp, lp)
         if lp is not None:
             lp.close()
+        out["helmholtz_solve"] = helmholtz_solve_comparison(ctx, P, n, lx, amp)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(lx)
     print(json.dumps(out), flush=True)

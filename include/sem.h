@@ -216,7 +216,10 @@ int sem_remove_mean(sem_gs_t gs, double* x);
 
 /* The assembled Poisson operator A_G = sum_e Q_e^T A_e Q_e in the local
  * layout: y = gs(Ax(x)).  Float64 device arrays, the layout of sem_ax; h1 may
- * be NULL (h1 = 1, the Poisson case). */
+ * be NULL (h1 = 1, the Poisson case).  With h2b non-NULL the operator is the
+ * Helmholtz form of sem_ax_helmholtz, A_e + diag(h2b) on every element
+ * (h2b = h2 * bm per local node, h2 > 0: the velocity-type solves), whose
+ * assembled matrix is positive definite. */
 typedef struct {
     const double* dx; const double* dy; const double* dz;
     const double* dxt; const double* dyt; const double* dzt;
@@ -225,6 +228,7 @@ typedef struct {
     const double* g12; const double* g13; const double* g23;
     int64_t nel;
     int lx;
+    const double* h2b;
 } sem_operator_t;
 
 typedef enum {
@@ -287,7 +291,9 @@ int sem_cg_destroy(sem_cg_t cg);
  * On a plan with Dirichlet nodes the operator is the assembled one restricted
  * to the free nodes (their rows and columns only), which has no null space:
  * b needs no projection (its Dirichlet entries are ignored), no mean is
- * removed, and x is 0 on the Dirichlet nodes.  A plan without free nodes is
+ * removed, and x is 0 on the Dirichlet nodes.  The same holds without
+ * projection for the Helmholtz operator (A->h2b set at sem_cg_setup); the
+ * Jacobi diagonal then includes h2b.  A plan without free nodes is
  * refused by sem_cg_setup (SEM_EINVAL).
  * Returns SEM_OK, SEM_NOT_CONVERGED (limit reached; x is the last iterate) or
  * SEM_EBREAKDOWN.  Synchronous (reads convergence flags every check_every
@@ -370,7 +376,9 @@ int sem_lp_set_block(sem_lp_t lp, const float* W, int64_t count);
  * Takes effect at the next sem_lp_bind. */
 int sem_lp_set_jacobi_base(sem_lp_t lp, int on);
 /* Bind to an operator (lx = 8, nel <= max_rows) and its plan: computes the
- * per-element geometric features.  Needed by sem_lp_samples / sem_lp_apply. */
+ * per-element geometric features.  Needed by sem_lp_samples / sem_lp_apply.
+ * Only the stiffness is read (A->h2b is ignored): with a Helmholtz solve the
+ * Jacobi base uses the stiffness diagonal. */
 int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs);
 /* Training rows for `count` elements elems[] (device int64) of the bound
  * operator: X[row0 + q] = inputs (bf16, SEM_LP_IN_PAD wide) from the residual

@@ -29,7 +29,7 @@ SEM_SOLVE_F64, SEM_SOLVE_F32_IR, SEM_SOLVE_BF16_IR = 0, 1, 2
 class SemOperator(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
                 ("dx", "dy", "dz", "dxt", "dyt", "dzt", "h1", "g11", "g22", "g33", "g12", "g13",
-                 "g23")] + [("nel", ctypes.c_int64), ("lx", ctypes.c_int)]
+                 "g23")] + [("nel", ctypes.c_int64), ("lx", ctypes.c_int), ("h2b", ctypes.c_void_p)]
 
 
 class SemSolveOpts(ctypes.Structure):
@@ -383,15 +383,16 @@ def _opts(tol=1e-10, maxit=0, precision=SEM_SOLVE_F64, inner_tol=0.0, inner_maxi
                         learned.handle if learned is not None else None, ir_mode, delta)
 
 
-def sem_cg_setup(ctx, gs, D, h1, G, nel, lx, **opts):
+def sem_cg_setup(ctx, gs, D, h1, G, nel, lx, h2b=None, **opts):
     """D = (dx, dy, dz, dxt, dyt, dzt), G = (g11, g22, g33, g12, g13, g23): float64
-    device tensors.  opts: see SemSolveOpts (precision fixed here)."""
-    A = SemOperator(*[_ptr(t) for t in D], _ptr(h1), *[_ptr(t) for t in G], nel, lx)
+    device tensors; h2b (optional) the Helmholtz mass term h2 * bm.  opts: see
+    SemSolveOpts (precision fixed here)."""
+    A = SemOperator(*[_ptr(t) for t in D], _ptr(h1), *[_ptr(t) for t in G], nel, lx, _ptr(h2b))
     o = _opts(**opts)
     h = ctx.bind()
     out = _vp()
     _check(lib().sem_cg_setup(h, gs.handle, ctypes.byref(A), ctypes.byref(o), ctypes.byref(out)), h)
-    return CgSolver(ctx, out, (D, h1, G, gs))
+    return CgSolver(ctx, out, (D, h1, G, gs, h2b))
 
 
 def sem_cg_destroy(cg):

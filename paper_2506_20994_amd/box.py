@@ -73,20 +73,23 @@ class BoxOperator:
         self.ax(w, u)
         B.sem_gs(self.gs, w)
 
-    def fourier_rhs(self, k, amp, phase):
+    def fourier_rhs(self, k, amp, phase, project=None):
         """Continuous right-hand side b = Q Q^T (B f) for the Fourier sum f at
-        the node coordinates, minus its mean on the periodic box (needs
-        keep_coords=True)."""
+        the node coordinates, minus its mean when ``project`` (default: on the
+        periodic box, for the singular Poisson operator; pass False for a
+        Helmholtz solve).  Needs keep_coords=True."""
         b = torch.empty_like(self.bm)
         B.sem_fourier(self.ctx, b, self.x, self.y, self.z, self.bm, k, amp, phase)
         B.sem_gs(self.gs, b)
-        if not self.dirichlet:
+        if (not self.dirichlet) if project is None else project:
             B.sem_remove_mean(self.gs, b)
         return b
 
-    def solver(self, precision=0, **opts):
+    def solver(self, precision=0, h2b=None, **opts):
+        """A solver for this operator; with ``h2b`` (h2 * bm, local layout) the
+        Helmholtz operator A + h2 B."""
         return B.sem_cg_setup(self.ctx, self.gs, self.D, self.h1, self.G, self.nel, self.lx,
-                              precision=precision, **opts)
+                              h2b=h2b, precision=precision, **opts)
 
     def bind(self, lp):
         """Bind a learned preconditioner to this operator."""

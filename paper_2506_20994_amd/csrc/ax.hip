@@ -245,12 +245,11 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
             acc += dj[l] * ss[k * L2 + l * LX + i];
         }
         if (live) {
-            if constexpr (GATHER) {
+            if (hb) acc += Load<TS>::get(hb, base + k * L2) * uc[k];       // Helmholtz: + h2 B u
+            if constexpr (GATHER)
                 w[__builtin_nontemporal_load(pos + base + k * L2)] = (TW)acc;
-            } else {
-                if (hb) acc += Load<TS>::get(hb, base + k * L2) * uc[k];   // Helmholtz: + h2 B u
+            else
                 store_nt(w, base + k * L2, (TW)acc);
-            }
         }
         if (FUSE) pw += (double)uc[k] * (double)(TW)acc;
     }
@@ -372,7 +371,6 @@ int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const
         nel, skip, dot, lid, pos, (const TS*)gp, (const TS*)hb
     const dim3 grid((unsigned)blocks), block(EPB * LX * LX);
     if (lid && !gp) return sem::fail(ctx, SEM_EINVAL, "launch_ax: the solver form needs packed factors");
-    if (lid && hb) return sem::fail(ctx, SEM_EINVAL, "launch_ax: the solver form has no Helmholtz term");
     if constexpr (LX == 3) {
         if (!lid && !dot) {
             constexpr int E3 = Shape3D<LX>::EPB;
@@ -503,11 +501,14 @@ int launch_ax(sem_ctx_t ctx, AxKind kind, const AxArgs& a, void* w, const void* 
     const void* G[6] = {a.G[0], a.G[1], a.G[2], a.G[3], a.G[4], a.G[5]};
     switch (kind) {
         case AxKind::F64:
-            return dispatch<double, double, double, double>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos, a.Gp);
+            return dispatch<double, double, double, double>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos,
+                                                            a.Gp, a.hb);
         case AxKind::F32:
-            return dispatch<float, float, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos, a.Gp);
+            return dispatch<float, float, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos,
+                                                        a.Gp, a.hb);
         case AxKind::F32_BF16:
-            return dispatch<float, uint16_t, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos, a.Gp);
+            return dispatch<float, uint16_t, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos,
+                                                           a.Gp, a.hb);
     }
     return fail(ctx, SEM_EINVAL, "launch_ax: bad kind");
 }

@@ -608,9 +608,10 @@ struct sem_cg_s {
 
 namespace {
 
-// The periodic operator is singular (null space: the constants), so its
-// solves project out the mean; with Dirichlet nodes the operator is not.
-inline bool projects(sem_cg_t cg) { return cg->gs->n_masked == 0; }
+// The periodic Poisson operator is singular (null space: the constants), so
+// its solves project out the mean; with Dirichlet nodes or a Helmholtz mass
+// term the operator is positive definite.
+inline bool projects(sem_cg_t cg) { return cg->gs->n_masked == 0 && !cg->A64.hb; }
 
 int cg_alloc(sem_cg_t cg, void** p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes);
@@ -909,6 +910,7 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
     cg->nu = gs->n_unique;
     for (int q = 0; q < 6; ++q) { cg->A64.D[q] = Dp[q]; cg->A64.G[q] = Gp[q]; }
     cg->A64.h1 = A->h1;
+    cg->A64.hb = A->h2b;
     cg->A64.nel = A->nel;
     cg->A64.lx = A->lx;
     hipStream_t st = ctx->stream;
@@ -950,6 +952,7 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
     rc = sem_ax_diag(ctx, cg->wl64, A->dx, A->h1, A->g11, A->g22, A->g33, A->g12, A->g13, A->g23,
                      A->nel, A->lx);
     if (rc) return bail(rc);
+    if (A->h2b) add_kernel<<<gl, kBlock, 0, st>>>(cg->wl64, A->h2b, n);   // + the diagonal mass term
 
     Level& L64 = cg->lv64;
     L64.kind = sem::AxKind::F64;
@@ -993,6 +996,13 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
             if (bf) to_bf16_kernel<<<gl, kBlock, 0, st>>>((uint16_t*)d, A->h1, n);
             else to_type_kernel<float><<<gl, kBlock, 0, st>>>((float*)d, A->h1, n);
             L.A.h1 = d;
+        }
+        if (A->h2b) {          // the mass term in the storage type of h1 and G
+            void* d = nullptr;
+            CG_ALLOC(d, vs * n);
+            if (bf) to_bf16_kernel<<<gl, kBlock, 0, st>>>((uint16_t*)d, A->h2b, n);
+            else to_type_kernel<float><<<gl, kBlock, 0, st>>>((float*)d, A->h2b, n);
+            L.A.hb = d;
         }
         L.A.nel = A->nel;
         L.A.lx = A->lx;

@@ -63,6 +63,8 @@ struct AxArgs {
     // pair a of (g11,g22), (g33,g12), (g13,g23) sits at 2-vector index
     // 3 s + a lx^2 + ij, in the storage type
     const void* Gp = nullptr;
+    // Helmholtz: h2 B per local node in the storage type (+ h2 B u), or null
+    const void* hb = nullptr;
 };
 enum class AxKind {
     F64,        // u, h1, G, D, w float64

@@ -51,11 +51,11 @@ def linear_apply_at_nodes(params, n, lx, amp, ids, r_glob, gids, jacobi=False):
     return out
 
 
-def operator_at_nodes(n, lx, amp, ids, x_glob, gids, h1_glob=None):
+def operator_at_nodes(n, lx, amp, ids, x_glob, gids, h1_glob=None, h2=None):
     """(A x)_g of the n^3 box's assembled operator at the global ids `gids`, each
     from the elements that contain it (oracle geometry and einsum operator):
     for large meshes, where the whole-mesh oracle is too slow.  Negative ids
-    (Dirichlet nodes) read 0."""
+    (Dirichlet nodes) read 0.  With h2, the Helmholtz operator A + h2 B."""
     from oracle.mesh import box_coords
     from oracle.geometry import geometric_factors
     from oracle.gll import listing_matrices
@@ -66,8 +66,12 @@ def operator_at_nodes(n, lx, amp, ids, x_glob, gids, h1_glob=None):
     out = np.empty(len(gids))
     for q, g in enumerate(gids):
         els = np.nonzero((flat == g).any(axis=1))[0]
-        G, _, _ = geometric_factors(*box_coords(n, lx, amp, els), lx)
+        G, Bm, _ = geometric_factors(*box_coords(n, lx, amp, els), lx)
         h1 = None if h1_glob is None else scatter(h1_glob, ids[els])
-        w = ax_einsum(scatter(x_glob, ids[els]), *M, h1, *G).reshape(len(els), -1)
+        xe = scatter(x_glob, ids[els])
+        w = ax_einsum(xe, *M, h1, *G)
+        if h2 is not None:
+            w = w + h2 * Bm * xe
+        w = w.reshape(len(els), -1)
         out[q] = np.sum(w[flat[els] == g])
     return out

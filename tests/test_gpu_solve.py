@@ -123,23 +123,24 @@ def test_remove_mean_and_owner(sem_ctx):
                                atol=1e-13)
 
 
-@pytest.mark.parametrize("prec,mode,dirichlet", [("f64", 0, False), ("f32", 1, False), ("bf16", 1, False),
-                                                  ("f64", 0, True), ("f32", 1, True)])
-def test_solve_full_size_sampled(sem_ctx, prec, mode, dirichlet):
+@pytest.mark.parametrize("prec,mode,dirichlet,h2", [("f64", 0, False, None), ("f32", 1, False, None),
+                                                     ("bf16", 1, False, None), ("f64", 0, True, None),
+                                                     ("f32", 1, True, None), ("f32", 1, False, 1e3)])
+def test_solve_full_size_sampled(sem_ctx, prec, mode, dirichlet, h2):
     """The benchmark's solves (32^3 box, lx = 8, amplitude 0.1, 32 Fourier modes,
-    relres 1e-10; periodic, and with Dirichlet conditions on the boundary) in
-    float64 PCG and float32 / bfloat16 residual replacement: the oracle
-    recomputes b - A x at 48 sampled unique nodes from the elements containing
-    each (its own geometry and operator), and every component must satisfy
-    |r_g| <= ||r||_2 <= 1.2e-10 ||b||_2."""
+    relres 1e-10; periodic, with Dirichlet conditions on the boundary, and the
+    Helmholtz operator with h2 = 1e3) in float64 PCG and float32 / bfloat16
+    residual replacement: the oracle recomputes b - A x at 48 sampled unique
+    nodes from the elements containing each (its own geometry and operator),
+    and every component must satisfy |r_g| <= ||r||_2 <= 1.2e-10 ||b||_2."""
     from oracle.mesh import global_ids, global_ids_dirichlet
     from tests.helpers import operator_at_nodes
     n, lx, amp = 32, 8, 0.1
     op = BoxOperator(sem_ctx, n, lx, amp, dirichlet=dirichlet)
     k, a, ph = synth.fourier_modes(2)
-    b = op.fourier_rhs(k, a, ph)
+    b = op.fourier_rhs(k, a, ph, project=(not dirichlet and h2 is None))
     code = {"f64": P.SEM_SOLVE_F64, "f32": P.SEM_SOLVE_F32_IR, "bf16": P.SEM_SOLVE_BF16_IR}[prec]
-    cg = op.solver(code)
+    cg = op.solver(code, h2b=None if h2 is None else h2 * op.bm)
     x = torch.empty_like(b)
     rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10, precision=code, ir_mode=mode)
     torch.cuda.synchronize()
@@ -154,9 +155,84 @@ def test_solve_full_size_sampled(sem_ctx, prec, mode, dirichlet):
     bg[ids[free]] = bl[free]
     xg[ids[free]] = xl[free]
     gids = synth.choice(60, nu, 48)
-    r = bg[gids] - operator_at_nodes(n, lx, amp, ids, xg, gids)
+    r = bg[gids] - operator_at_nodes(n, lx, amp, ids, xg, gids, h2=h2)
     assert np.max(np.abs(r)) <= 1.2e-10 * np.linalg.norm(bg), (np.max(np.abs(r)), np.linalg.norm(bg))
-    if not dirichlet:
+    if not dirichlet and h2 is None:
         assert abs(xg.sum()) <= 1e-10 * np.abs(xg).sum()
     cg.close()
     op.gs.close()
+
+
+@pytest.mark.parametrize("dirichlet", [False, True])
+@pytest.mark.parametrize("prec,mode", [("f64", 0), ("f32", 0), ("f32", 1), ("bf16", 1)])
+def test_helmholtz_solve(sem_ctx, prec, mode, dirichlet):
+    """The Helmholtz operator A + h2 B (h2 = 20, velocity-type solve) on the
+    periodic and the Dirichlet box, against the oracle's: no projection, the
+    residual recomputed by the oracle, the solution error, float64 iteration
+    counts within 2 of the oracle's PCG, and on the periodic box the exact
+    balance h2 (Q^T B) . x = sum b (the stiffness annihilates constants)."""
+    n, lx, amp, h2 = 3, 8, 0.1, 20.0
+    op = BoxOperator(sem_ctx, n, lx, amp, dirichlet=dirichlet)
+    ref = BoxProblem(n, lx, amp, dirichlet=dirichlet, h2=h2)
+    k, a, ph = synth.fourier_modes(3)
+    # plus the constant source f = 1, so that the solution has a clear mean
+    b = op.fourier_rhs(k, a, ph, project=False)
+    mass = op.bm.clone()
+    P.sem_gs(op.gs, mass)
+    b += mass
+    from oracle.gs import gather
+    m = gather(ref.B, ref.ids, ref.nu)
+    bref = ref.fourier_rhs(k, a, ph) + m
+    free = ref.ids >= 0
+    bg = np.zeros(ref.nu)
+    bg[ref.ids[free]] = b.cpu().numpy()[free]
+    np.testing.assert_allclose(bg, bref, rtol=0, atol=1e-13 * np.abs(bref).max())
+    code = {"f64": P.SEM_SOLVE_F64, "f32": P.SEM_SOLVE_F32_IR, "bf16": P.SEM_SOLVE_BF16_IR}[prec]
+    cg = op.solver(code, h2b=h2 * op.bm)
+    x = torch.empty_like(b)
+    rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10, precision=code, ir_mode=mode)
+    torch.cuda.synchronize()
+    assert rc == P.SEM_OK and st["converged"], st
+    xl = x.cpu().numpy()
+    xg = np.zeros(ref.nu)
+    xg[ref.ids[free]] = xl[free]
+    assert np.linalg.norm(bref - ref.apply(xg)) / np.linalg.norm(bref) <= 1.2e-10
+    xs, ito, _ = pcg(ref.apply, bref, 1.0 / ref.diagonal(), tol=1e-13, project=False)
+    assert np.max(np.abs(xg - xs)) <= 1e-6 * np.max(np.abs(xs))
+    if prec == "f64":
+        _, ito, _ = pcg(ref.apply, bref, 1.0 / ref.diagonal(), tol=1e-10, project=False)
+        assert abs(st["iterations"] - ito) <= 2, (st["iterations"], ito)
+    if not dirichlet:
+        assert h2 * (m @ xg) == pytest.approx(bref.sum(), rel=1e-7)
+        assert m @ xg > 0.5 / h2           # the constant source's share: nothing projected
+    cg.close()
+    op.gs.close()
+
+
+def test_helmholtz_flexible_cg_with_block(sem_ctx):
+    """Flexible CG with the classical element block on the Helmholtz operator
+    (float32 residual replacement): converges to the oracle's solution."""
+    from paper_2506_20994_amd import learned as LR
+    n, lx, amp, h2 = 4, 8, 0.1, 20.0
+    op = BoxOperator(sem_ctx, n, lx, amp)
+    ref = BoxProblem(n, lx, amp, h2=h2)
+    k, a, ph = synth.fourier_modes(3)
+    b = op.fourier_rhs(k, a, ph, project=False)
+    bref = ref.fourier_rhs(k, a, ph)
+    lp = P.sem_lp_create(sem_ctx, op.nel)
+    op.bind(lp)
+    P.sem_lp_set_block(lp, LR.reference_block(sem_ctx))
+    cg = op.solver(P.SEM_SOLVE_F32_IR, h2b=h2 * op.bm, learned=lp)
+    x = torch.empty_like(b)
+    rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10, precision=P.SEM_SOLVE_F32_IR, ir_mode=1, learned=lp)
+    torch.cuda.synchronize()
+    assert rc == P.SEM_OK and st["converged"] and st["jacobi_steps"] == 0, st
+    xg = np.zeros(ref.nu)
+    xg[ref.ids.ravel()] = x.cpu().numpy().ravel()
+    assert np.linalg.norm(bref - ref.apply(xg)) / np.linalg.norm(bref) <= 1.2e-10
+    xs, _, _ = pcg(ref.apply, bref, 1.0 / ref.diagonal(), tol=1e-13, project=False)
+    assert np.max(np.abs(xg - xs)) <= 1e-6 * np.max(np.abs(xs))
+    cg.close()
+    lp.close()
+    op.gs.close()
+

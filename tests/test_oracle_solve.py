@@ -74,17 +74,18 @@ def test_refinement_with_float32_inner_reaches_float64_tolerance():
     assert np.max(np.abs(x - xref)) < 1e-7 * np.max(np.abs(xref))
 
 
-@pytest.mark.parametrize("dirichlet", [False, True])
-def test_operator_at_nodes_matches_whole_mesh(dirichlet):
+@pytest.mark.parametrize("dirichlet,h2", [(False, None), (True, None), (False, 7.0)])
+def test_operator_at_nodes_matches_whole_mesh(dirichlet, h2):
     """The node-by-node operator used by the full-size GPU solve test equals the
-    oracle's assembled operator at every node (periodic and Dirichlet box)."""
+    oracle's assembled operator at every node (periodic and Dirichlet box,
+    Poisson and Helmholtz)."""
     from tests.helpers import operator_at_nodes
     from oracle.mesh import global_ids, global_ids_dirichlet
     n, lx, amp = (3, 4, 0.12) if dirichlet else (2, 4, 0.12)
-    P = BoxProblem(n, lx, amp, dirichlet=dirichlet)
+    P = BoxProblem(n, lx, amp, dirichlet=dirichlet, h2=h2)
     xG = synth.unique_normal(P.nu, 3)
     ids = global_ids_dirichlet(n, lx) if dirichlet else global_ids(n, lx)
-    got = operator_at_nodes(n, lx, amp, ids, xG, np.arange(P.nu))
+    got = operator_at_nodes(n, lx, amp, ids, xG, np.arange(P.nu), h2=h2)
     ref = P.apply(xG)
     np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
