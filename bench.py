@@ -37,7 +37,10 @@ Extra fields:
                 replacement, and flexible CG with the classical block.
 
 --mode copy times a plain 1 GiB device copy (used to calibrate the HBM byte
-counters of rocprofv3); it prints nothing on stdout.  --mode scale runs the
+counters of rocprofv3); it prints nothing on stdout.  --mode trials prints one
+JSON line with five trials of the operator (200 launches each, HIP events) and
+five of a 1 GiB device copy, for the median / min and the fraction of the
+measured copy bandwidth.  --mode scale runs the
 full stack on a 64^3 box (lx 8 and 10; several minutes) and prints one JSON
 line of its own.
 """
@@ -313,6 +316,51 @@ def learned_comparison(ctx, P, n, lx, amp, solve=None, tol=1e-10, keep=False):
     return res
 
 
+def trials_run(P, n, lx, amp, trials=5, reps=200):
+    """Five trials of the operator on the bench box and of a 1 GiB device copy
+    (torch copy_, read + write counted), HIP events on the current stream."""
+    import statistics
+    import torch
+    import synth
+    from paper_2506_20994_amd.box import BoxOperator
+    ctx = P.sem_create()
+    nu = (n * (lx - 1)) ** 3
+    op = BoxOperator(ctx, n, lx, amp, h1_unique=synth.unique_uniform(nu, 0.5, 2.0, 1), keep_coords=False)
+    u = op.scatter(synth.unique_normal(nu, 0))
+    w = torch.empty_like(u)
+    st = torch.cuda.current_stream()
+
+    def timed(fn, count, warm):
+        for _ in range(warm):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(count):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / count * 1e3          # us
+
+    ax_us = [timed(lambda: op.ax(w, u), reps, 20) for _ in range(trials)]
+    del op, u, w
+    torch.cuda.empty_cache()
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    copy_us = [timed(lambda: b.copy_(a), 50, 5) for _ in range(trials)]
+    ctx.close()
+    alg = BYTES_PER_NODE_F64 * n ** 3 * lx ** 3
+    ax_gbs = [alg / t / 1e3 for t in ax_us]
+    copy_gbs = [2 * a.numel() * 8 / t / 1e3 for t in copy_us]
+    med = statistics.median(ax_gbs)
+    return {"mode": "trials", "workload": f"sem_ax on the {n}^3 box lx={lx} amplitude {amp}",
+            "ax_us": [round(t, 2) for t in ax_us], "ax_us_median": round(statistics.median(ax_us), 2),
+            "ax_us_min": round(min(ax_us), 2), "ax_gbs_median": round(med, 1),
+            "frac_of_hbm_peak": round(med / HBM_PEAK_GBS, 4),
+            "copy_gbs": [round(v, 1) for v in copy_gbs], "copy_gbs_median": round(statistics.median(copy_gbs), 1),
+            "frac_of_measured_copy": round(med / statistics.median(copy_gbs), 4)}
+
+
 def scale_run(ctx, P, n=64, amp=0.15, tol=1e-10):
     """The full stack at scale (--mode scale): a 64^3 box (E = 262144) with
     amplitude 0.15 at lx = 8 (134M local nodes) and lx = 10 (262M): operator
@@ -393,7 +441,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-helmholtz", action="store_true",
                     help="skip the Helmholtz timing (it launches the same kernel as sem_ax)")
-    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "scale"])
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "scale", "trials"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this library runs on one GPU; --gpus {args.gpus} is not supported",
@@ -414,6 +462,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(f"[bench] copied {args.steps} x {a.numel() * 8} bytes", file=sys.stderr)
+        return
+    if args.mode == "trials":
+        print(json.dumps(trials_run(P, args.n, args.lx, args.amp)), flush=True)
         return
     if args.mode == "scale":
         ctx = P.sem_create()

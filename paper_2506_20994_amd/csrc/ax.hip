@@ -124,8 +124,9 @@ __device__ __forceinline__ void wave_sync() {
 // gather-scatter).
 // GATHER: u is a unique-node vector, read as u[lid[L]] (lid streamed, u
 // through the caches, since neighbouring elements share nodes; lid < 0 marks
-// a Dirichlet node, read as 0), and the output of node L goes to w[pos[L]],
-// the plan's CSR order.
+// a Dirichlet node, read as 0).  The output stays in the local layout
+// (coalesced nontemporal stores); the solver sums the copies of each unique
+// node through the plan's CSR lists.
 template <int LX, int EPB, typename TU, typename TS, typename TC, typename TW, bool FUSE, bool GATHER>
 __global__ void __launch_bounds__(EPB * LX * LX) __attribute__((amdgpu_waves_per_eu(Shape<LX>::kWavesPerEU, 8)))
 ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
@@ -135,7 +136,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
           const TS* __restrict__ g33, const TS* __restrict__ g12, const TS* __restrict__ g13,
           const TS* __restrict__ g23, int64_t nel, const int* __restrict__ skip,
           double* __restrict__ dot, const int32_t* __restrict__ lid,
-          const int32_t* __restrict__ pos, const TS* __restrict__ gp, const TS* __restrict__ hb) {
+          const TS* __restrict__ gp, const TS* __restrict__ hb) {
     constexpr int L2 = LX * LX;
     constexpr int L3 = L2 * LX;
     constexpr bool WP = Shape<LX>::kWavePrivate;
@@ -246,10 +247,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
         }
         if (live) {
             if (hb) acc += Load<TS>::get(hb, base + k * L2) * uc[k];       // Helmholtz: + h2 B u
-            if constexpr (GATHER)
-                w[__builtin_nontemporal_load(pos + base + k * L2)] = (TW)acc;
-            else
-                store_nt(w, base + k * L2, (TW)acc);
+            store_nt(w, base + k * L2, (TW)acc);
         }
         if (FUSE) pw += (double)uc[k] * (double)(TW)acc;
     }
@@ -361,14 +359,14 @@ ax3d_kernel(TW* __restrict__ w, const TS* __restrict__ u,
 template <int LX, typename TU, typename TS, typename TC, typename TW>
 int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const void* h1,
               const void* const* G, int64_t nel, const int* skip, double* dot, const int32_t* lid,
-              const int32_t* pos, const void* gp, const void* hb) {
+              const void* gp, const void* hb) {
     constexpr int EPB = Shape<LX>::EPB;
     const int64_t blocks = (nel + EPB - 1) / EPB;
     if (blocks > 0x7fffffff) return sem::fail(ctx, SEM_EINVAL, "sem_ax: nel too large");
 #define SEM_AX_ARGS (TW*)w, (const TU*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2], \
         (const TC*)D[3], (const TC*)D[4], (const TC*)D[5], (const TS*)h1, (const TS*)G[0],  \
         (const TS*)G[1], (const TS*)G[2], (const TS*)G[3], (const TS*)G[4], (const TS*)G[5], \
-        nel, skip, dot, lid, pos, (const TS*)gp, (const TS*)hb
+        nel, skip, dot, lid, (const TS*)gp, (const TS*)hb
     const dim3 grid((unsigned)blocks), block(EPB * LX * LX);
     if (lid && !gp) return sem::fail(ctx, SEM_EINVAL, "launch_ax: the solver form needs packed factors");
     if constexpr (LX == 3) {
@@ -399,10 +397,10 @@ int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const
 template <typename TU, typename TS, typename TC, typename TW>
 int dispatch(sem_ctx_t ctx, int lx, void* w, const void* u, const void* const* D,
              const void* h1, const void* const* G, int64_t nel, const int* skip, double* dot,
-             const int32_t* lid = nullptr, const int32_t* pos = nullptr, const void* gp = nullptr,
+             const int32_t* lid = nullptr, const void* gp = nullptr,
              const void* hb = nullptr) {
     switch (lx) {
-#define SEM_AX_CASE(L) case L: return launch_lx<L, TU, TS, TC, TW>(ctx, w, u, D, h1, G, nel, skip, dot, lid, pos, gp, hb);
+#define SEM_AX_CASE(L) case L: return launch_lx<L, TU, TS, TC, TW>(ctx, w, u, D, h1, G, nel, skip, dot, lid, gp, hb);
         SEM_AX_CASE(2) SEM_AX_CASE(3) SEM_AX_CASE(4) SEM_AX_CASE(5) SEM_AX_CASE(6) SEM_AX_CASE(7)
         SEM_AX_CASE(8) SEM_AX_CASE(9) SEM_AX_CASE(10) SEM_AX_CASE(11) SEM_AX_CASE(12)
 #undef SEM_AX_CASE
@@ -451,12 +449,12 @@ int ax_public(sem_ctx_t ctx, void* w, const void* u, const void* dx, const void*
     if (alias) return sem::fail(ctx, SEM_EINVAL, "sem_ax: output overlaps an input");
     if (f64)
         return dispatch<double, double, double, double>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr, nullptr,
-                                                        nullptr, nullptr, hb);
+                                                        nullptr, hb);
     if (field_dtype == SEM_F32)
         return dispatch<float, float, float, float>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr, nullptr,
-                                                    nullptr, nullptr, hb);
+                                                    nullptr, hb);
     return dispatch<uint16_t, uint16_t, float, float>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr, nullptr,
-                                                      nullptr, nullptr, hb);
+                                                      nullptr, hb);
 }
 
 }  // namespace
@@ -495,19 +493,18 @@ int ax_blocks(int lx, int64_t nel) {
 }
 
 int launch_ax(sem_ctx_t ctx, AxKind kind, const AxArgs& a, void* w, const void* u,
-              const int* skip, double* dot, const int32_t* lid, const int32_t* pos) {
-    if ((lid == nullptr) != (pos == nullptr)) return fail(ctx, SEM_EINVAL, "launch_ax: lid and pos go together");
+              const int* skip, double* dot, const int32_t* lid) {
     const void* D[6] = {a.D[0], a.D[1], a.D[2], a.D[3], a.D[4], a.D[5]};
     const void* G[6] = {a.G[0], a.G[1], a.G[2], a.G[3], a.G[4], a.G[5]};
     switch (kind) {
         case AxKind::F64:
-            return dispatch<double, double, double, double>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos,
+            return dispatch<double, double, double, double>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid,
                                                             a.Gp, a.hb);
         case AxKind::F32:
-            return dispatch<float, float, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos,
+            return dispatch<float, float, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid,
                                                         a.Gp, a.hb);
         case AxKind::F32_BF16:
-            return dispatch<float, uint16_t, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid, pos,
+            return dispatch<float, uint16_t, float, float>(ctx, a.lx, w, u, D, a.h1, G, a.nel, skip, dot, lid,
                                                            a.Gp, a.hb);
     }
     return fail(ctx, SEM_EINVAL, "launch_ax: bad kind");

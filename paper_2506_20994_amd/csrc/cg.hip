@@ -9,9 +9,10 @@
 //
 // Krylov vectors live on the unique (assembled) nodes, numbered densely by
 // the gather-scatter plan: the operator reads p[lid[L]] for every local node L
-// and writes its element-local output w_L; the update kernel assembles
-// w_u = sum of the local copies of u (the plan's CSR) on the fly, so no
-// separate gather-scatter pass and no duplicated vector traffic remain.
+// and writes its element-local output w_L in the local layout (coalesced);
+// the update kernel assembles w_u = sum of the local copies of u, read
+// through the plan's CSR lists, on the fly, so no separate gather-scatter
+// pass and no duplicated vector traffic remain.
 // p^T A p is the element-local sum of p_L w_L taken in the operator's
 // epilogue.  Everything stays on the device: scalars (alpha, beta, r.z, ...)
 // live in a small device struct, a `done` flag turns every later kernel of a
@@ -71,8 +72,8 @@ __device__ double final_sum(const double* __restrict__ part, int n, int stride, 
 #define GRID_LOOP(i, n) \
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
-// assembled value of unique node u: sum of its local copies, which the
-// operator stored contiguously at wc[uoff[u] .. uoff[u+1]) (CSR order).  The
+// assembled value of unique node u: sum of its local copies, stored
+// contiguously at wc[uoff[u] .. uoff[u+1]) (CSR order: the network's output).  The
 // first eight copies (every node of a conforming hexahedral mesh) are loaded
 // by independent predicated loads, issued together, and summed in CSR order;
 // a longer segment continues in a loop.  The count of copies goes to *m.
@@ -89,6 +90,27 @@ __device__ __forceinline__ T assemble(const T* __restrict__ wc, const int32_t* _
         if (b + q < e) s += v[q];
     for (int32_t q = b + 8; q < e; ++q) s += wc[q];
     if (m) *m = e - b;
+    return s;
+}
+
+// sum of the local copies of unique node u of a field in the local layout:
+// wl[uidx[q]] for q in [uoff[u], uoff[u+1]), the first eight by independent
+// predicated loads, summed in CSR order (the order of assemble above)
+template <typename T>
+__device__ __forceinline__ T assemble_local(const T* __restrict__ wl, const int32_t* __restrict__ uoff,
+                                            const int32_t* __restrict__ uidx, int64_t u) {
+    const int32_t b = uoff[u], e = uoff[u + 1];
+    int32_t L[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) L[q] = b + q < e ? uidx[b + q] : -1;
+    T v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = L[q] >= 0 ? wl[L[q]] : T(0);
+    T s = v[0];
+#pragma unroll
+    for (int q = 1; q < 8; ++q)
+        if (b + q < e) s += v[q];
+    for (int32_t q = b + 8; q < e; ++q) s += wl[uidx[q]];
     return s;
 }
 
@@ -194,7 +216,7 @@ __global__ void pcg_update_kernel(T* __restrict__ x, T* __restrict__ r, const T*
     const T alpha = (T)S->alpha;
     double a = 0.0, b = 0.0;
     GRID_LOOP(u, n) {
-        const T wv = assemble(wl, uoff, u);
+        const T wv = assemble_local(wl, uoff, uidx, u);
         x[u] += alpha * p[u];
         const T rv = r[u] - alpha * wv;
         r[u] = rv;
@@ -279,7 +301,7 @@ __global__ void sub_mean_kernel(double* __restrict__ x, const double* __restrict
 __global__ void residual_kernel(double* __restrict__ r, const double* __restrict__ b,
                                 const double* __restrict__ wl, const int32_t* __restrict__ uoff,
                                 const int32_t* __restrict__ uidx, int64_t nu) {
-    GRID_LOOP(u, nu) r[u] = b[u] - assemble(wl, uoff, u);
+    GRID_LOOP(u, nu) r[u] = b[u] - assemble_local(wl, uoff, uidx, u);
 }
 
 // IR: rhat = (float)((r - mean) / norm), mean = s0 * inv_nu (inv_nu = 1 / nu on
@@ -506,7 +528,7 @@ __global__ void fcg_update_kernel(T* __restrict__ x, T* __restrict__ r, T* __res
     const T alpha = (T)S->alpha;
     double a = 0.0, b = 0.0;
     GRID_LOOP(u, n) {
-        const T wv = assemble(wl, uoff, u);
+        const T wv = assemble_local(wl, uoff, uidx, u);
         wu[u] = wv;
         x[u] += alpha * p[u];
         const T rv = r[u] - alpha * wv;
@@ -646,7 +668,7 @@ int pcg_run(sem_cg_t cg, Level& lv, const T* rhs, double tol, int maxit, int che
     const int nb = sem::ax_blocks(lv.A.lx, lv.A.nel);
     for (;;) {
         for (int q = 0; q < check_every; ++q) {
-            int rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid, cg->gs->upos);
+            int rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid);
             if (rc) return rc;
             pcg_alpha_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, nb);
             pcg_update_kernel<T><<<g, kBlock, 0, st>>>(x, r, p, wl, minv, uoff, uidx, n, cg->S, cg->part);
@@ -724,7 +746,7 @@ int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int chec
                 }
                 fcg_gamma_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
                 fcg_p_kernel<float><<<g, kBlock, 0, st>>>(p, z, r, minv, n, cg->S, cg->part2);
-                rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid, cg->gs->upos);
+                rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid);
                 if (rc) return rc;
                 fcg_alpha_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, nb, cg->part2, (int)g);
                 fcg_update_kernel<float><<<g, kBlock, 0, st>>>(x, r, wu, p, wl, minv, uoff, uidx, n, cg->S,
@@ -732,7 +754,7 @@ int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int chec
                 pcg_beta_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
                 continue;
             }
-            int rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid, cg->gs->upos);
+            int rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid);
             if (rc) return rc;
             pcg_alpha_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, nb);
             pcg_update_kernel<float><<<g, kBlock, 0, st>>>(x, r, p, wl, minv, uoff, uidx, n, cg->S, cg->part);
@@ -818,7 +840,7 @@ int fcg_run(sem_cg_t cg, Level& lv, const T* rhs, double tol, int maxit, int che
             }
             fcg_gamma_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
             fcg_p_kernel<T><<<g, kBlock, 0, st>>>(p, z, r, minv, n, cg->S, cg->part2);
-            rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid, cg->gs->upos);
+            rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid);
             if (rc) return rc;
             fcg_alpha_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, nb, cg->part2, (int)g);
             fcg_update_kernel<T><<<g, kBlock, 0, st>>>(x, r, wu, p, wl, minv, uoff, uidx, n, cg->S, cg->part);
@@ -862,8 +884,7 @@ int read_sums(sem_cg_t cg, double* s, double* q) {
 
 // r64 = b64 - A x (unique, float64)
 int residual64(sem_cg_t cg, const double* xu) {
-    int rc = sem::launch_ax(cg->ctx, sem::AxKind::F64, cg->A64, cg->wl64, xu, nullptr, nullptr, cg->gs->lid,
-                            cg->gs->upos);
+    int rc = sem::launch_ax(cg->ctx, sem::AxKind::F64, cg->A64, cg->wl64, xu, nullptr, nullptr, cg->gs->lid);
     if (rc) return rc;
     residual_kernel<<<vec_grid(cg->nu), kBlock, 0, cg->ctx->stream>>>(cg->r64, cg->b64, cg->wl64,
                                                                       cg->gs->uoff, cg->gs->uidx, cg->nu);

@@ -73,12 +73,10 @@ enum class AxKind {
 };
 // Launch the operator.  With dot != nullptr it also skips when *skip != 0 and
 // writes one float64 partial of sum u.w per workgroup (ax_blocks() of them).
-// With lid != nullptr, u is a unique-node vector read as u[lid[L]] and the
-// output of local node L is stored at w[pos[L]] (the CSR order of the plan, so
-// the copies of every unique node are contiguous).
+// With lid != nullptr, u is a unique-node vector read as u[lid[L]] (0 where
+// lid < 0); the output stays in the local layout.
 int launch_ax(sem_ctx_t ctx, AxKind kind, const AxArgs& a, void* w, const void* u,
-              const int* skip, double* dot, const int32_t* lid = nullptr,
-              const int32_t* pos = nullptr);
+              const int* skip, double* dot, const int32_t* lid = nullptr);
 int ax_blocks(int lx, int64_t nel);
 // gather-scatter launch that returns at once when skip && *skip
 int gs_launch(sem_gs_t gs, void* u, sem_dtype_t dtype, const int* skip);
