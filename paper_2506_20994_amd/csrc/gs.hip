@@ -27,7 +27,7 @@ __global__ void gs_kernel(T* __restrict__ u, const int32_t* __restrict__ off,
                           const int32_t* __restrict__ idx, int64_t n_shared, const int* __restrict__ skip,
                           const int32_t* __restrict__ midx, int64_t n_masked) {
     if (skip && *skip) return;
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t g = sem::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (g >= n_shared) {
         if (g < n_shared + n_masked) u[midx[g - n_shared]] = T(0);
         return;
@@ -241,7 +241,7 @@ int gs_launch(sem_gs_t gs, void* u, sem_dtype_t dtype, const int* skip) {
     const int64_t nt = gs->n_shared + gs->n_masked;
     if (nt == 0) return SEM_OK;
     if (!u) return fail(ctx, SEM_EINVAL, "sem_gs: null field");
-    const unsigned grid = (unsigned)((nt + kBlock - 1) / kBlock);
+    const unsigned grid = (unsigned)((nt + 8 * kBlock - 1) / (8 * kBlock) * 8);   // a multiple of 8
     const int32_t* midx = gs->uidx + (gs->n_local - gs->n_masked);
     if (dtype == SEM_F64)
         gs_kernel<double><<<grid, kBlock, 0, ctx->stream>>>((double*)u, gs->off, gs->idx, gs->n_shared, skip,

@@ -94,6 +94,14 @@ int64_t lp_rows(sem_lp_t lp);
 sem_gs_t lp_plan(sem_lp_t lp);
 
 #ifdef __HIPCC__
+// Workgroup order for L2 locality: the hardware hands consecutive workgroups
+// to the eight XCDs (each with its own L2) in turn.  With a grid of G
+// workgroups, G a multiple of 8, logical block (b mod 8) G/8 + b/8 gives each
+// XCD one contiguous eighth of the work; other grids keep their order.
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t G) {
+    return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3);
+}
+
 // sum over the 64 lanes of a wave
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
