@@ -38,8 +38,10 @@ def _residual(op, x, b, out):
 
 def generate(ctx, lp, n=16, boxes=16, snapshots=16, elems_per_snapshot=64, seed=100,
              amp_range=(0.0, 0.2), min_rel_detj=0.05, rhs="fourier", include_zero=False,
-             verbose=False):
-    """Returns (X bf16 [rows, 528], T float32 [rows, 512], info)."""
+             verbose=False, dirichlet=False):
+    """Returns (X bf16 [rows, 528], T float32 [rows, 512], info).  With
+    ``dirichlet`` the pairs come from boxes with u = 0 on the boundary (no mean
+    projection of the right-hand side)."""
     lx = 8
     nel = n ** 3
     rows = boxes * snapshots * elems_per_snapshot
@@ -52,7 +54,7 @@ def generate(ctx, lp, n=16, boxes=16, snapshots=16, elems_per_snapshot=64, seed=
         a = float(synth.amplitudes(seed + draw, 1, *amp_range)[0])
         draw += 1
         try:
-            op = BoxOperator(ctx, n, lx, a)
+            op = BoxOperator(ctx, n, lx, a, dirichlet=dirichlet)
         except B.SemError:
             rejected += 1
             continue
@@ -62,7 +64,8 @@ def generate(ctx, lp, n=16, boxes=16, snapshots=16, elems_per_snapshot=64, seed=
         amps.append(a)
         if rhs == "noise":
             b = op.scatter(synth.unique_normal(op.n_unique, seed + 10_000 + box))
-            B.sem_remove_mean(op.gs, b)
+            if not dirichlet:
+                B.sem_remove_mean(op.gs, b)
         else:
             k, am, ph = synth.fourier_modes(seed + 10_000 + box)
             b = op.fourier_rhs(k, am, ph)

@@ -438,23 +438,26 @@ def test_pipeline_small(sem_ctx):
         h.close()
 
 
-def test_trained_linear_network_beats_jacobi(sem_ctx):
+@pytest.mark.parametrize("dirichlet", [False, True])
+def test_trained_linear_network_beats_jacobi(sem_ctx, dirichlet):
     """What the trained network gains: the linear form trained on the GPU with
     the energy-norm loss on float64 Jacobi-PCG pairs (white-noise right-hand
     sides) from 256 8^3 boxes (131k element rows: with a few tens of thousands
     the learned block stays indefinite) cuts the flexible-CG iteration count on a held-out
     12^3 box well below Jacobi-PCG's, with no Jacobi fallback, in float64 and
-    inside float32 residual replacement."""
+    inside float32 residual replacement; on periodic boxes, and trained and
+    tested on boxes with u = 0 on the boundary."""
     from paper_2506_20994_amd import learned as LR
     n = 12
     lp = P.sem_lp_create(sem_ctx, n ** 3)
     LR.init_network(lp, 7, mu=1.0, jacobi_base=True, out_scale=0.0, linear=True)
     X, T, info = LR.generate(sem_ctx, lp, n=8, boxes=256, snapshots=1, elems_per_snapshot=512,
-                             seed=400, rhs="noise", include_zero=True)
+                             seed=400, rhs="noise", include_zero=True, dirichlet=dirichlet)
+    assert torch.isfinite(T).all()
     hist = LR.train(lp, X, T, epochs=60, batch=1024, lr=3e-4)
     assert hist[-1] < hist[0]
     del X, T
-    op = BoxOperator(sem_ctx, n, 8, 0.1)
+    op = BoxOperator(sem_ctx, n, 8, 0.1, dirichlet=dirichlet)
     op.bind(lp)
     k, a, ph = synth.fourier_modes(5)
     b = op.fourier_rhs(k, a, ph)
@@ -469,7 +472,7 @@ def test_trained_linear_network_beats_jacobi(sem_ctx):
         assert st["jacobi_steps"] == 0 and not st["fell_back"]
         out[name] = st["iterations"]
         cg.close()
-    print(f"Jacobi-PCG {st0['iterations']} its; learned FCG {out}")
+    print(f"dirichlet={dirichlet}: Jacobi-PCG {st0['iterations']} its; learned FCG {out}")
     assert out["f64"] <= 0.6 * st0["iterations"]
     assert out["f32_rr"] <= 0.6 * st0["iterations"]
     for h in (cg0, lp):
