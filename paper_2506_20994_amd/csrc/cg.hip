@@ -71,6 +71,12 @@ __device__ double final_sum(const double* __restrict__ part, int n, int stride, 
 
 #define GRID_LOOP(i, n) \
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+// The same grid-stride loop with the workgroups in XCD order (sem::xcd_order):
+// in every sweep each XCD takes one contiguous eighth, so the copies that
+// neighbouring unique nodes gather from the same element lines meet in one L2.
+#define GRID_LOOP_XCD(i, n)                                                                       \
+    for (int64_t i = sem::xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < (n); \
+         i += (int64_t)gridDim.x * blockDim.x)
 
 // assembled value of unique node u: sum of its local copies, stored
 // contiguously at wc[uoff[u] .. uoff[u+1]) (CSR order: the network's output).  The
@@ -215,7 +221,7 @@ __global__ void pcg_update_kernel(T* __restrict__ x, T* __restrict__ r, const T*
     __shared__ double s_red[kBlock / 64];
     const T alpha = (T)S->alpha;
     double a = 0.0, b = 0.0;
-    GRID_LOOP(u, n) {
+    GRID_LOOP_XCD(u, n) {
         const T wv = assemble_local(wl, uoff, uidx, u);
         x[u] += alpha * p[u];
         const T rv = r[u] - alpha * wv;
@@ -301,7 +307,7 @@ __global__ void sub_mean_kernel(double* __restrict__ x, const double* __restrict
 __global__ void residual_kernel(double* __restrict__ r, const double* __restrict__ b,
                                 const double* __restrict__ wl, const int32_t* __restrict__ uoff,
                                 const int32_t* __restrict__ uidx, int64_t nu) {
-    GRID_LOOP(u, nu) r[u] = b[u] - assemble_local(wl, uoff, uidx, u);
+    GRID_LOOP_XCD(u, nu) r[u] = b[u] - assemble_local(wl, uoff, uidx, u);
 }
 
 // IR: rhat = (float)((r - mean) / norm), mean = s0 * inv_nu (inv_nu = 1 / nu on
@@ -527,7 +533,7 @@ __global__ void fcg_update_kernel(T* __restrict__ x, T* __restrict__ r, T* __res
     __shared__ double s_red[kBlock / 64];
     const T alpha = (T)S->alpha;
     double a = 0.0, b = 0.0;
-    GRID_LOOP(u, n) {
+    GRID_LOOP_XCD(u, n) {
         const T wv = assemble_local(wl, uoff, uidx, u);
         wu[u] = wv;
         x[u] += alpha * p[u];
