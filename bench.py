@@ -11,7 +11,8 @@ Extra fields:
                 divided by the launch's average duration from HIP events.
   cpu_baseline  the plain-C oracle loop nest timed on this host's cores on a
                 bounded sample of the same workload shape.
-  gs            gather-scatter timing on the same mesh.
+  gs            gather-scatter timing on the same mesh, with its algorithmic bytes
+                (20 B per shared local entry + 4 B per shared id) and rate.
   helmholtz     sem_ax_helmholtz (h2b = the mass, one more stream: 80 B per node)
                 on the same mesh.
   solve         Poisson solve to relative residual 1e-10 on the same 32^3 lx = 8
@@ -536,6 +537,10 @@ def main():
     achieved = alg_bytes / (ax_ms * 1e-3) / 1e9
     traffic = load_traffic(n_local)
     _, n_shared = P.sem_gs_info(op.gs)
+    # gather-scatter: per shared local entry its index (4 B), one read and one
+    # write (8 B each); per shared id its CSR offset (4 B)
+    n_entries = int((op.mult > 1).sum())
+    gs_bytes = 20 * n_entries + 4 * n_shared
     out = {
         "metric": "Ax GDOF/s (unique dofs E*(lx-1)^3 per second), FP64, lx=8",
         "value": round(value, 3),
@@ -557,8 +562,9 @@ def main():
                      "traffic": traffic, "kernel": f"ax_kernel<{lx}, double>",
                      "avg_launch_us": round(ax_ms * 1e3, 2),
                      "alg_bytes_per_launch": alg_bytes},
-        "gs": {"avg_launch_us": round(gs_ms * 1e3, 2), "shared_ids": n_shared,
-               "alg_bytes_per_launch": None},
+        "gs": {"avg_launch_us": round(gs_ms * 1e3, 2), "shared_ids": n_shared, "shared_entries": n_entries,
+               "alg_bytes_per_launch": gs_bytes,
+               "achieved_gbs": round(gs_bytes / (gs_ms * 1e-3) / 1e9, 1)},
         "helmholtz": None if helm_ms is None else {
             "avg_launch_us": round(helm_ms * 1e3, 2),
             "alg_bytes_per_launch": (BYTES_PER_NODE_F64 + 8) * n_local,
