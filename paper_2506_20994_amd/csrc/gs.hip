@@ -241,14 +241,15 @@ int gs_launch(sem_gs_t gs, void* u, sem_dtype_t dtype, const int* skip) {
     const int64_t nt = gs->n_shared + gs->n_masked;
     if (nt == 0) return SEM_OK;
     if (!u) return fail(ctx, SEM_EINVAL, "sem_gs: null field");
-    const unsigned grid = (unsigned)((nt + 8 * kBlock - 1) / (8 * kBlock) * 8);   // a multiple of 8
+    constexpr int kGsBlock = 512;           // measured: 256 and 1024 threads are slower
+    const unsigned grid = (unsigned)((nt + 8 * kGsBlock - 1) / (8 * kGsBlock) * 8);   // a multiple of 8
     const int32_t* midx = gs->uidx + (gs->n_local - gs->n_masked);
     if (dtype == SEM_F64)
-        gs_kernel<double><<<grid, kBlock, 0, ctx->stream>>>((double*)u, gs->off, gs->idx, gs->n_shared, skip,
-                                                            midx, gs->n_masked);
+        gs_kernel<double><<<grid, kGsBlock, 0, ctx->stream>>>((double*)u, gs->off, gs->idx, gs->n_shared, skip,
+                                                              midx, gs->n_masked);
     else if (dtype == SEM_F32)
-        gs_kernel<float><<<grid, kBlock, 0, ctx->stream>>>((float*)u, gs->off, gs->idx, gs->n_shared, skip,
-                                                           midx, gs->n_masked);
+        gs_kernel<float><<<grid, kGsBlock, 0, ctx->stream>>>((float*)u, gs->off, gs->idx, gs->n_shared, skip,
+                                                             midx, gs->n_masked);
     else
         return fail(ctx, SEM_EINVAL, "sem_gs: dtype %d not supported (F64 or F32)", (int)dtype);
     SEM_LAUNCH_CHECK(ctx);
