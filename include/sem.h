@@ -404,9 +404,10 @@ int sem_lp_train_step(sem_lp_t lp, const uint16_t* X, const float* T, const int6
 int sem_lp_apply(sem_lp_t lp, void* z, const void* r, sem_dtype_t dtype);
 /* The same on unique-node vectors of the bound plan (sem_gs_info's n_unique
  * values, the layout sem_cg_solve iterates in): unique nodes are numbered in
- * the order in which their global ids first appear in the local layout.  The linear form runs one
- * fused kernel (gather of S r, bf16 MFMA product, CSR-ordered output) and an
- * assembly pass.  Asynchronous; the network's workspace is shared with the
+ * the order in which their global ids first appear in the local layout
+ * (Dirichlet nodes excluded).  The linear form runs a gather kernel (S r to
+ * bfloat16), the weight-stationary bf16 MFMA product (CSR-ordered output) and
+ * an assembly pass.  Asynchronous; the network's workspace is shared with the
  * other calls on lp, so calls on one lp must not overlap. */
 int sem_lp_apply_unique(sem_lp_t lp, void* z, const void* r, sem_dtype_t dtype);
 
