@@ -146,3 +146,30 @@ def test_config0_against_assembled_matrix(sem_ctx):
     AG = assembled_matrix(Dh, None, G, ids, nu)
     ref = (AG @ uu)[ids]
     assert rel_inf(w.cpu().numpy(), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("amp", [0.0, 0.1])
+def test_config0_dirichlet_against_assembled_matrix(sem_ctx, amp):
+    """The 4^3 box with u = 0 on the boundary (lx = 8, h1 = 1): one operator
+    application plus the masked gather-scatter equals Q (A_G u_G) with the
+    oracle's masked assembled matrix (the natural-boundary matrix with the
+    boundary rows and columns deleted), and 0 on the Dirichlet nodes."""
+    from oracle.mesh import global_ids_dirichlet, n_unique_dirichlet
+    from oracle.gs import scatter
+    n, lx = 4, 8
+    nu = n_unique_dirichlet(n, lx)
+    op = BoxOperator(sem_ctx, n, lx, amp, keep_coords=False, dirichlet=True)
+    uu = synth.unique_normal(nu, 0)
+    u = op.scatter(uu)
+    w = torch.full_like(u, float("nan"))
+    op.apply(w, u)
+    torch.cuda.synchronize()
+    G, _, _ = geometric_factors(*box_coords(n, lx, amp), lx)
+    ids = global_ids_dirichlet(n, lx)
+    Dh = deriv_matrix(gll_nodes_weights(lx - 1)[0])
+    AG = assembled_matrix(Dh, None, G, ids, nu)
+    ref = scatter(AG @ uu, ids)
+    wl = w.cpu().numpy()
+    assert np.all(wl[ids < 0] == 0.0)
+    assert rel_inf(wl, ref) <= 1e-12
+    op.gs.close()
