@@ -77,27 +77,94 @@ def load_traffic(n_local):
 
 
 def cpu_baseline(lx, target_s=10.0):
+    """The plain-C oracle (oracle/sem_ref.c) on this host: the operator on all
+    threads (the headline, GDOF/s) and on one thread, float64 Jacobi-PCG to
+    relres 1e-10 on the 16^3 box, and 20 PCG iterations on the 32^3 box."""
     import numpy as np
     import synth
     from oracle import cref
-    from oracle.gll import listing_matrices
+    from oracle.gll import gll_nodes_weights, deriv_matrix
     nel = 4096
     G, h1 = synth.random_spd_factors(nel, lx, 123)
     u = synth.local_normal(nel, lx, 124)
-    M = listing_matrices(lx)
-    cref.ax_ref(u, *M, h1, *G)              # warm-up (and build if needed)
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        cref.ax_ref(u, *M, h1, *G)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= target_s:
-            break
-    dofs = reps * nel * (lx - 1) ** 3
-    return {"value": dofs / el / 1e9, "unit": "GDOF/s", "cores": cref.num_threads(),
-            "kind": "oracle",
-            "sample": f"{nel} elements x lx={lx} (random SPD factors, h1, u), {reps} "
-                      f"applications of the plain-C loop nest in {el:.1f} s"}
+    Dh = deriv_matrix(gll_nodes_weights(lx - 1)[0])
+    threads = cref.num_threads()
+
+    def rate(seconds):
+        cref.ax(u, Dh, h1, G)                # warm-up
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            cref.ax(u, Dh, h1, G)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                return reps, el
+
+    reps, el = rate(target_s)
+    out = {"value": reps * nel * (lx - 1) ** 3 / el / 1e9, "unit": "GDOF/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{nel} elements x lx={lx} (random SPD factors, h1, u), {reps} "
+                     f"applications of the plain-C operator in {el:.1f} s on {threads} threads; "
+                     "solve legs: float64 Jacobi-PCG of the C oracle"}
+    cref.set_threads(1)
+    reps1, el1 = rate(2.0)
+    cref.set_threads(threads)
+    out["ax_1_thread_gdofs"] = round(reps1 * nel * (lx - 1) ** 3 / el1 / 1e9, 4)
+    k, a, ph = synth.fourier_modes(2)
+    box = cref.BigBox(16, lx, 0.1)
+    b = box.fourier_rhs(k, a, ph)
+    t0 = time.perf_counter()
+    _, its, rel = box.pcg(b, tol=1e-10)
+    el = time.perf_counter() - t0
+    out["pcg_16cubed"] = {"s": round(el, 2), "iterations": its, "relres": rel, "threads": threads,
+                          "workload": "16^3 box lx=8 amplitude 0.1, 32 Fourier modes, tol 1e-10"}
+    del box
+    box = cref.BigBox(32, lx, 0.1)
+    b = box.fourier_rhs(k, a, ph)
+    t0 = time.perf_counter()
+    _, its, _ = box.pcg(b, tol=1e-30, maxit=20)
+    el = time.perf_counter() - t0
+    out["pcg_32cubed_20_iterations"] = {"s": round(el, 2), "ms_per_iteration": round(el / its * 1e3, 1),
+                                        "threads": threads}
+    print(f"[bench] cpu baseline: {out['value']:.3f} GDOF/s on {threads} threads, "
+          f"{out['ax_1_thread_gdofs']:.3f} on 1; PCG 16^3 {out['pcg_16cubed']['s']} s; "
+          f"32^3 {out['pcg_32cubed_20_iterations']['ms_per_iteration']} ms/iteration",
+          file=sys.stderr, flush=True)
+    return out
+
+
+class Golden:
+    """The oracle's reference solution of a 32^3 solve, sampled at 1024 unique
+    nodes (tests/golden/solve_*.json, written by the oracle alone), and the
+    local position of each sampled node on the library's box."""
+
+    def __init__(self, name, ids_device, n, lx):
+        import numpy as np
+        p = os.path.join(ROOT, "tests", "golden", f"solve_{name}_n{n}_lx{lx}.json")
+        self.ok = os.path.exists(p)
+        if not self.ok:
+            return
+        d = json.load(open(p))
+        self.gids = np.array(d["sample_ids"])
+        self.xs = np.array(d["x_sample"])
+        ids = ids_device.reshape(-1).cpu().numpy()
+        order = np.argsort(ids, kind="stable")
+        first = np.searchsorted(ids[order], self.gids)
+        self.pos = order[first]
+        assert np.all(ids[self.pos] == self.gids)
+
+    def error(self, x):
+        """sqrt(sum (x - x*)^2 / sum x*^2) over the sampled nodes"""
+        import numpy as np
+        if not self.ok:
+            return None
+        xv = x.reshape(-1)[torch_index(self.pos, x.device)].cpu().numpy()
+        return float(np.sqrt(np.sum((xv - self.xs) ** 2) / np.sum(self.xs ** 2)))
+
+
+def torch_index(a, device):
+    import torch
+    return torch.from_numpy(a).to(device)
 
 
 def solve_comparison(ctx, P, n, lx, amp, tol=1e-10):
@@ -108,7 +175,10 @@ def solve_comparison(ctx, P, n, lx, amp, tol=1e-10):
     k, a, ph = synth.fourier_modes(2)
     b = op.fourier_rhs(k, a, ph)
     x = torch.empty_like(b)
-    res = {"workload": f"{n}^3 box lx={lx} amplitude {amp}, h1=1, 32 Fourier modes, tol {tol}"}
+    gold = Golden("periodic", op.ids, n, lx)
+    res = {"workload": f"{n}^3 box lx={lx} amplitude {amp}, h1=1, 32 Fourier modes, tol {tol}",
+           "err_vs_oracle": "sqrt(sum (x - x*)^2 / sum x*^2) over 1024 sampled unique nodes, x* the "
+                            "oracle's float64 PCG solution (tests/golden)"}
     variants = (("fp64_pcg", P.SEM_SOLVE_F64, 0), ("f32_ir", P.SEM_SOLVE_F32_IR, 0),
                 ("bf16_ir", P.SEM_SOLVE_BF16_IR, 0), ("f32_rr", P.SEM_SOLVE_F32_IR, 1),
                 ("bf16_rr", P.SEM_SOLVE_BF16_IR, 1))
@@ -121,9 +191,9 @@ def solve_comparison(ctx, P, n, lx, amp, tol=1e-10):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
         res[name] = {"ms": round(ms, 2), "iterations": st["iterations"], "outer": st["outer"],
-                     "relres": st["relres"], "converged": st["converged"]}
+                     "relres": st["relres"], "converged": st["converged"], "err_vs_oracle": gold.error(x)}
         print(f"[bench] solve {name}: {ms:.1f} ms, {st['iterations']} its, outer {st['outer']}, "
-              f"relres {st['relres']:.2e}", file=sys.stderr, flush=True)
+              f"relres {st['relres']:.2e}, err {res[name]['err_vs_oracle']}", file=sys.stderr, flush=True)
         cg.close()
     base = res["fp64_pcg"]["ms"]
     res["speedup_vs_fp64_pcg"] = {k2: round(base / res[k2]["ms"], 3)
@@ -159,6 +229,7 @@ def dirichlet_comparison(ctx, P, n, lx, amp, lp=None, tol=1e-10):
     x = torch.empty_like(b)
     res = {"workload": f"{n}^3 box lx={lx} amplitude {amp}, u=0 on the boundary, h1=1, "
                        f"32 Fourier modes, tol {tol}", "unique_dofs": op.n_unique}
+    gold = Golden("dirichlet", op.ids, n, lx)
     blk = None
     if lx == 8:
         blk = P.sem_lp_create(ctx, n ** 3)
@@ -174,7 +245,8 @@ def dirichlet_comparison(ctx, P, n, lx, amp, lp=None, tol=1e-10):
             op.bind(net)
         ms, st = _timed_solve(P, op, x, b, code, mode, net, tol)
         res[name] = {"ms": round(ms, 2), "iterations": st["iterations"], "relres": st["relres"],
-                     "jacobi_steps": st["jacobi_steps"], "converged": st["converged"]}
+                     "jacobi_steps": st["jacobi_steps"], "converged": st["converged"],
+                     "err_vs_oracle": gold.error(x)}
         print(f"[bench] dirichlet {name}: {ms:.1f} ms, {st['iterations']} its, relres {st['relres']:.2e}",
               file=sys.stderr, flush=True)
     base = res["fp64_pcg"]["ms"]
@@ -201,6 +273,7 @@ def helmholtz_solve_comparison(ctx, P, n, lx, amp, h2=1e3, tol=1e-10):
     h2b = h2 * op.bm
     res = {"workload": f"{n}^3 periodic box lx={lx} amplitude {amp}, A + h2 B with h2={h2:g}, "
                        f"f = 1 + 32 Fourier modes, tol {tol}"}
+    gold = Golden("helmholtz", op.ids, n, lx)
     blk = None
     if lx == 8:
         blk = P.sem_lp_create(ctx, n ** 3)
@@ -220,7 +293,7 @@ def helmholtz_solve_comparison(ctx, P, n, lx, amp, h2=1e3, tol=1e-10):
         ms = (time.perf_counter() - t0) * 1e3
         cg.close()
         res[name] = {"ms": round(ms, 2), "iterations": st["iterations"], "relres": st["relres"],
-                     "converged": st["converged"]}
+                     "converged": st["converged"], "err_vs_oracle": gold.error(x)}
         print(f"[bench] helmholtz_solve {name}: {ms:.1f} ms, {st['iterations']} its, relres {st['relres']:.2e}",
               file=sys.stderr, flush=True)
     base = res["fp64_pcg"]["ms"]
@@ -258,6 +331,7 @@ def learned_comparison(ctx, P, n, lx, amp, solve=None, tol=1e-10, keep=False):
     b = op.fourier_rhs(k, a, ph)
     x = torch.empty_like(b)
     op.bind(lp)
+    gold = Golden("periodic", op.ids, n, lx)
     res = {"training": {"rows": info["rows"], "boxes": info["boxes"],
                         "rejected_amplitude_draws": info["rejected_draws"],
                         "datagen_s": round(t_gen, 2), "train_s": round(t_train, 2),
@@ -277,7 +351,7 @@ def learned_comparison(ctx, P, n, lx, amp, solve=None, tol=1e-10, keep=False):
         ms = (time.perf_counter() - t0) * 1e3
         res[name] = {"ms": round(ms, 2), "iterations": st["iterations"],
                      "jacobi_steps": st["jacobi_steps"], "fell_back": st["fell_back"],
-                     "relres": st["relres"], "converged": st["converged"]}
+                     "relres": st["relres"], "converged": st["converged"], "err_vs_oracle": gold.error(x)}
         print(f"[bench] learned {name}: {ms:.1f} ms, {st['iterations']} its, "
               f"{st['jacobi_steps']} Jacobi, fell back {st['fell_back']}", file=sys.stderr, flush=True)
         cg.close()
@@ -298,7 +372,8 @@ def learned_comparison(ctx, P, n, lx, amp, solve=None, tol=1e-10, keep=False):
     ms = (time.perf_counter() - t0) * 1e3
     res["classical_block_f32_rr"] = {"ms": round(ms, 2), "iterations": st["iterations"],
                                      "jacobi_steps": st["jacobi_steps"], "fell_back": st["fell_back"],
-                                     "relres": st["relres"], "converged": st["converged"]}
+                                     "relres": st["relres"], "converged": st["converged"],
+                                     "err_vs_oracle": gold.error(x)}
     print(f"[bench] learned classical_block_f32_rr: {ms:.1f} ms, {st['iterations']} its", file=sys.stderr,
           flush=True)
     cg.close()

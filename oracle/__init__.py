@@ -14,13 +14,13 @@ Modules
   gll       GLL nodes, weights, Lagrange basis and derivative matrix (Sec. 3, Eq. 2)
   mesh      periodic box mesh: node positions, deformation, global numbering (Sec. 3, Eq. 3)
   geometry  isoparametric Jacobian, geometric factors G_ab, mass weights (Sec. 3, Eq. 1)
-  ax        the element operator: Listing 2 loops, einsum form, dense Kronecker form
+  ax        the element operator: node-by-node quadrature form, einsum form, dense Kronecker form
   gs        gather-scatter via bincount, multiplicity (Sec. 2.1)
   assemble  dense assembled matrix, Jacobi diagonal
   solve     textbook Jacobi-PCG, mixed-precision refinement, flexible CG
   quant     round-to-nearest-even float32 / bfloat16 emulation
   mlp       per-element MLP forward/backward and Adam
-  cref      ctypes loader for ax_ref.c, the literal loop nest in plain C (timing)
+  cref      ctypes loader for sem_ref.c: the path in plain C (CPU baseline, 32^3 reference solutions)
 
 Parity status of each function is stated in its docstring; anything without
 an independent pin says "parity unpinned".

@@ -27,7 +27,14 @@ the library adds around the paper's Poisson solve.  Readings taken:
     additive (one-level Schwarz-type) preconditioner.
 Pins (tests/test_oracle_mlp.py): backpropagation against central finite
 differences (both losses); Adam against its closed form for a constant
-gradient; the features' scale invariance; apply returns a continuous field;
+gradient; the features' scale invariance; features and kappa against the
+closed form of axis-aligned rectangular and sheared affine elements (kappa =
+(8 / lx^3)(bc/a + ac/b + ab/c) / 6 for an a x b x c brick, 4 h / lx^3 on the
+uniform box, features (1, 1, 1, 0, 0, 0) there); targets against that
+closed-form kappa; the nonlinear apply of a constant-output network: a
+constant residual c on the uniform box gives |c| sqrt(lx^3) lx^3 n / 4 at
+every node, and a general residual gives the copy-by-copy average of
+(s_e / kappa_e) NN_p over the element copies of each node;
 the reference metric is symmetric positive definite and its stiffness part
 gives the exact energy of polynomials of degree <= N on the reference cube;
 the linear apply with an identity block returns r / kappa (partition of
@@ -176,4 +183,101 @@ def apply_block(W, r_local, G, h1, ids, n_unique):
     _, _, kappa = features(r_local, G, h1)
     S = 1.0 / np.sqrt(multiplicity(ids, n_unique).reshape(E, nloc))
     z = ((S * r_local.reshape(E, nloc)) @ Ws.T) * S / kappa[:, None]
+    return gs(z.reshape(r_local.shape), ids, n_unique)
+
+
+# ---------------------------------------------------------------------------
+# bfloat16-storage emulation: the same network with its operands rounded as
+# the product kernels store them (weights, inputs, hidden activations and the
+# back-propagated errors in bfloat16; biases, outputs and gradients in
+# float32), every product summed exactly in float64.  The kernels accumulate
+# in float32, so they differ from these only by accumulation rounding and by
+# the bfloat16 roundings that such rounding can tip (a value within a few
+# float32 ulps of a bfloat16 rounding boundary).  Pins: equal to the exact
+# functions above when every operand and intermediate is a bfloat16 number;
+# within bfloat16 rounding of them otherwise (tests/test_oracle_mlp.py).
+
+def forward_bf16(params, Xq, linear=False):
+    """Forward pass of bfloat16 inputs Xq (already rounded) with bfloat16
+    weights and bfloat16 hidden activations; returns (y1, y2, y3)."""
+    from .quant import to_bf16, to_f32
+    W1, b1, W2, b2, W3, b3 = params
+    Wq = [to_bf16(W) for W in (W1, W2, W3)]
+    if linear:
+        y1 = to_bf16(Xq @ Wq[0].T)
+        y2 = to_bf16(y1 @ Wq[1].T)
+        return y1, y2, to_f32(y2 @ Wq[2].T)
+    y1 = to_bf16(np.maximum(Xq @ Wq[0].T + to_f32(b1), 0.0))
+    y2 = to_bf16(np.maximum(y1 @ Wq[1].T + to_f32(b2), 0.0))
+    return y1, y2, to_f32(y2 @ Wq[2].T + to_f32(b3))
+
+
+def backward_bf16(params, Xq, T, K=None, linear=False):
+    """(loss, grads) with the roundings of the training kernels: the loss
+    gradient d3 in float32 and bfloat16 (with the metric, d = y3 - T and K
+    rounded to bfloat16 before K d), back-propagated errors rounded to
+    bfloat16 after the ReLU mask, weight gradients from bfloat16 factors,
+    bias gradients from the float32 errors."""
+    from .quant import to_bf16, to_f32
+    W1, b1, W2, b2, W3, b3 = params
+    Wq = [to_bf16(W) for W in (W1, W2, W3)]
+    y1, y2, y3 = forward_bf16(params, Xq, linear)
+    B = y3.shape[0]
+    if K is None:
+        d = to_f32(y3 - T)
+        lval = float(np.mean(d * d))
+        d3f = to_f32(d * (2.0 / y3.size))
+    else:
+        d = to_f32(y3 - T)
+        Kd = to_f32(to_bf16(d) @ to_bf16(K).T)
+        lval = float(np.mean(np.sum(d * Kd, axis=1)))
+        d3f = to_f32(Kd * (2.0 / B))
+    d3b = to_bf16(d3f)
+    gW3 = to_f32(d3b.T @ y2)
+    d2f = to_f32(d3b @ Wq[2]) * (1.0 if linear else (y2 > 0))
+    d2b = to_bf16(d2f)
+    gW2 = to_f32(d2b.T @ y1)
+    d1f = to_f32(d2b @ Wq[1]) * (1.0 if linear else (y1 > 0))
+    d1b = to_bf16(d1f)
+    gW1 = to_f32(d1b.T @ Xq)
+    if linear:
+        gb = [np.zeros(W1.shape[0]), np.zeros(W2.shape[0]), np.zeros(W3.shape[0])]
+    else:
+        gb = [d1f.sum(axis=0), d2f.sum(axis=0), d3f.sum(axis=0)]
+    return lval, [gW1, gb[0], gW2, gb[1], gW3, gb[2]]
+
+
+def apply_bf16(params, r_local, G, h1, ids, n_unique):
+    """The nonlinear apply with bfloat16 inputs (features rounded float64 ->
+    float32 -> bfloat16), the bfloat16 network above and the float32 scale
+    s_e / kappa_e (kappa_e held in float32)."""
+    from .gs import gs, multiplicity
+    from .quant import to_bf16, to_f32
+    X, s, kappa = features(r_local, G, h1)
+    t = forward_bf16(params, to_bf16(X))[2]
+    scale = to_f32(s / to_f32(kappa))
+    z = (t * scale[:, None]).reshape(r_local.shape)
+    return gs(z / multiplicity(ids, n_unique), ids, n_unique)
+
+
+def apply_block_bf16(W, r_local, G, h1, ids, n_unique, normalise=True):
+    """The symmetric additive apply of a float32 element block W as the
+    linear-form kernels evaluate it: W_s = bf16((W + W^T) / 2), the weighted
+    element residual S r_e rounded to bfloat16 -- divided by its 2-norm s_e
+    first (``normalise``, the local-layout path, output scaled back by s_e)
+    or not (the unique-layout path) -- the product summed exactly, the output
+    weighted by S / kappa_e and assembled."""
+    from .gs import gs, multiplicity
+    from .quant import to_bf16
+    E = r_local.shape[0]
+    nloc = r_local[0].size
+    Wq = to_bf16(0.5 * (W + W.T))
+    _, _, kappa = features(r_local, G, h1)
+    S = 1.0 / np.sqrt(multiplicity(ids, n_unique).reshape(E, nloc))
+    v = S * r_local.reshape(E, nloc)
+    if normalise:
+        s = np.sqrt(np.sum(v * v, axis=1)) + EPS
+        z = (to_bf16(v / s[:, None]) @ Wq.T) * (s / kappa)[:, None] * S
+    else:
+        z = (to_bf16(v) @ Wq.T) * S / kappa[:, None]
     return gs(z.reshape(r_local.shape), ids, n_unique)

@@ -17,11 +17,15 @@ def to_dev(a, dtype=None):
     return t.cuda()
 
 
-def linear_apply_at_nodes(params, n, lx, amp, ids, r_glob, gids, jacobi=False):
+def linear_apply_at_nodes(params, n, lx, amp, ids, r_glob, gids, jacobi=False, bf16=False):
     """The oracle's linear-form apply (oracle.mlp.apply_linear, plus Minv r with
     the Jacobi base) evaluated only at the global ids `gids` of the n^3 box,
     each from the elements that contain it: for large meshes, where the
-    whole-mesh oracle is too slow.  ids: the box's global ids (E, lx, lx, lx)."""
+    whole-mesh oracle is too slow.  ids: the box's global ids (E, lx, lx, lx).
+    With bf16, the unique-layout kernels' storage is emulated as in
+    oracle.mlp.apply_block_bf16(normalise=False): the symmetric block and
+    each element's S r rounded to bfloat16."""
+    from oracle.quant import to_bf16
     from oracle import mlp
     from oracle.mesh import box_coords
     from oracle.geometry import geometric_factors
@@ -31,6 +35,8 @@ def linear_apply_at_nodes(params, n, lx, amp, ids, r_glob, gids, jacobi=False):
     counts = np.bincount(flat.ravel())
     W = mlp.folded_matrix(params, lx ** 3)
     Ws = 0.5 * (W + W.T)
+    if bf16:
+        Ws = to_bf16(Ws)
     xi, _ = gll_nodes_weights(lx - 1)
     Dh = deriv_matrix(xi)
     out = np.empty(len(gids))
@@ -43,7 +49,8 @@ def linear_apply_at_nodes(params, n, lx, amp, ids, r_glob, gids, jacobi=False):
         acc, dg = 0.0, 0.0
         for a, e in enumerate(els):
             S = 1.0 / np.sqrt(counts[flat[e]])
-            yv = Ws @ (S * r_glob[flat[e]])
+            xv = S * r_glob[flat[e]]
+            yv = Ws @ (to_bf16(xv) if bf16 else xv)
             at = flat[e] == g
             acc += np.sum(S[at] * yv[at]) / kappa[a]
             dg += np.sum(diag[a][at])

@@ -6,7 +6,7 @@ import pytest
 
 import synth
 from oracle.gll import gll_nodes_weights, deriv_matrix, listing_matrices
-from oracle.ax import ax_loops, ax_einsum, ax_dense, element_matrix
+from oracle.ax import ax_quadrature, ax_einsum, ax_dense, element_matrix
 from oracle.geometry import geometric_factors
 
 
@@ -22,7 +22,7 @@ def test_three_forms_agree(lx):
     M = listing_matrices(lx)
     xi, _ = gll_nodes_weights(lx - 1)
     Dh = deriv_matrix(xi)
-    w1 = ax_loops(u, *M, h1, *G)
+    w1 = ax_quadrature(u, Dh, h1, *G)
     w2 = ax_einsum(u, *M, h1, *G)
     w3 = ax_dense(u, Dh, h1, G)
     s = np.max(np.abs(w3))

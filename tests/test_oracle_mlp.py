@@ -182,3 +182,259 @@ def test_linear_apply_at_nodes_matches_whole_mesh():
     zu += rG / P.diagonal()
     got = linear_apply_at_nodes(params, n, lx, amp, P.ids, rG, np.arange(P.nu), jacobi=True)
     np.testing.assert_allclose(got, zu, rtol=1e-12, atol=1e-12 * np.abs(zu).max())
+
+
+# ----------------------------------------------------------------------------
+# Closed-form pins of features, targets and the nonlinear apply.  On an
+# axis-aligned rectangular element [0, a] x [0, b] x [0, c] the Jacobian is
+# diag(a, b, c) / 2, so g11 = w_i w_j w_k bc / (2a), g22 = w w w ac / (2b),
+# g33 = w w w ab / (2c) and the off-diagonal factors vanish; the mean of
+# w_i w_j w_k over the lx^3 nodes is (sum w)^3 / lx^3 = 8 / lx^3.  Hence
+#   kappa = (8 / lx^3) (bc/a + ac/b + ab/c) / 6,
+#   geometric features = (bc/a, ac/b, ab/c, 0, 0, 0) * (8 / lx^3) / kappa.
+# On the uniform periodic box with side h = 1/n: kappa = 4 h / lx^3 and the
+# features are (1, 1, 1, 0, 0, 0).
+
+def _rect_element(lx, a, b, c):
+    from oracle.gll import gll_nodes_weights
+    xi, _ = gll_nodes_weights(lx - 1)
+    Z, Y, X = np.meshgrid(c * (1 + xi) / 2, b * (1 + xi) / 2, a * (1 + xi) / 2, indexing="ij")
+    return X[None], Y[None], Z[None]
+
+
+@pytest.mark.parametrize("lx,dims", [(4, (1.0, 1.0, 1.0)), (5, (0.3, 0.7, 1.9)), (8, (2.0, 0.5, 0.25))])
+def test_features_closed_form_on_rectangular_element(lx, dims):
+    """kappa (with its 1/3) and the order g11, g22, g33, g12, g13, g23 of the
+    geometric features against the rectangle's closed form.  A kappa without
+    the 1/3, a permuted feature order or a dropped weight fails."""
+    from oracle.geometry import geometric_factors
+    a, b, c = dims
+    G, _, _ = geometric_factors(*_rect_element(lx, a, b, c), lx)
+    r = synth.local_normal(1, lx, 4)
+    X, s, kappa = mlp.features(r, G)
+    diag = np.array([b * c / a, a * c / b, a * b / c])
+    kappa_cf = (8.0 / lx ** 3) * diag.sum() / 6.0
+    assert kappa[0] == pytest.approx(kappa_cf, rel=1e-13)
+    geo_cf = np.concatenate([diag * (8.0 / lx ** 3) / 2.0 / kappa_cf, np.zeros(3)])
+    np.testing.assert_allclose(X[0, lx ** 3:], geo_cf, rtol=1e-13, atol=1e-14)
+    assert s[0] == pytest.approx(np.sqrt(np.sum(r ** 2)), rel=1e-14)
+    np.testing.assert_allclose(X[0, :lx ** 3], r.ravel() / np.sqrt(np.sum(r ** 2)), rtol=1e-13)
+
+
+def test_features_sheared_element_off_diagonal_order():
+    """An affine element x = A xi (xi in [-1, 1]^3): g_ab = w w w |det A|
+    (A^-1 A^-T)_ab, so the off-diagonal features come in the order (r,s),
+    (r,t), (s,t).  A is chosen with three distinct off-diagonal entries."""
+    from oracle.geometry import geometric_factors
+    from oracle.gll import gll_nodes_weights
+    lx = 4
+    A = np.array([[1.0, 0.2, -0.1], [0.05, 0.8, 0.3], [0.0, -0.15, 1.2]])
+    xi, _ = gll_nodes_weights(lx - 1)
+    T, S, R = np.meshgrid(xi, xi, xi, indexing="ij")
+    P = np.einsum("ca,a...->c...", A, np.stack([R, S, T]))
+    G, _, _ = geometric_factors(P[0][None], P[1][None], P[2][None], lx)
+    _, _, kappa = mlp.features(synth.local_normal(1, lx, 1), G)
+    Ai = np.linalg.inv(A)
+    M = Ai @ Ai.T * abs(np.linalg.det(A)) * (8.0 / lx ** 3)
+    assert kappa[0] == pytest.approx(np.trace(M) / 3.0, rel=1e-12)
+    X, _, _ = mlp.features(synth.local_normal(1, lx, 1), G)
+    want = np.array([M[0, 0], M[1, 1], M[2, 2], M[0, 1], M[0, 2], M[1, 2]]) / kappa[0]
+    np.testing.assert_allclose(X[0, lx ** 3:], want, rtol=1e-11, atol=1e-13)
+
+
+@pytest.mark.parametrize("n,lx", [(2, 4), (3, 3)])
+def test_features_uniform_box_closed_form(n, lx):
+    P = BoxProblem(n, lx, 0.0)
+    r = synth.local_normal(n ** 3, lx, 2)
+    X, _, kappa = mlp.features(r, P.G)
+    np.testing.assert_allclose(kappa, 4.0 / n / lx ** 3, rtol=1e-13)
+    np.testing.assert_allclose(X[:, lx ** 3:], np.tile([1, 1, 1, 0, 0, 0], (n ** 3, 1)),
+                               rtol=1e-13, atol=1e-14)
+
+
+def test_targets_closed_form():
+    """t_e = err_e kappa_e / s_e with the closed-form kappa of the uniform box
+    (4 h / lx^3) and s_e the 2-norm of the element's residual."""
+    n, lx = 2, 4
+    P = BoxProblem(n, lx, 0.0)
+    r = synth.local_normal(n ** 3, lx, 5)
+    err = synth.local_normal(n ** 3, lx, 6)
+    _, s, kappa = mlp.features(r, P.G)
+    T = mlp.targets(err, s, kappa)
+    norms = np.sqrt(np.sum(r.reshape(n ** 3, -1) ** 2, axis=1))
+    np.testing.assert_allclose(T, err.reshape(n ** 3, -1) * (4.0 / n / lx ** 3) / norms[:, None],
+                               rtol=1e-13)
+
+
+def _constant_output_params(lx, out):
+    """Network with zero weights and last-layer bias `out`: NN(x) = out."""
+    p = synth.mlp_init(3, (lx ** 3 + 6, 16, 16, lx ** 3))
+    return [np.zeros_like(p[0]), np.zeros_like(p[1]), np.zeros_like(p[2]),
+            np.zeros_like(p[3]), np.zeros_like(p[4]), np.asarray(out, dtype=np.float64)]
+
+
+@pytest.mark.parametrize("n,lx,c", [(2, 4, 1.0), (3, 3, -2.5)])
+def test_nonlinear_apply_constant_residual_closed_form(n, lx, c):
+    """NN = 1 at every output and r = c on the uniform box: every element has
+    s = |c| sqrt(lx^3) and kappa = 4 h / lx^3, so z_e = s / kappa and the
+    partition-of-unity average returns z = |c| sqrt(lx^3) lx^3 n / 4 at every
+    node.  A dropped mult^-1 multiplies shared nodes by their multiplicity; a
+    dropped s or 1/kappa changes the constant."""
+    P = BoxProblem(n, lx, 0.0)
+    r = np.full((n ** 3, lx, lx, lx), c)
+    z = mlp.apply(_constant_output_params(lx, np.ones(lx ** 3)), r, P.G, None, P.ids, P.nu)
+    np.testing.assert_allclose(z, abs(c) * np.sqrt(lx ** 3) * lx ** 3 * n / 4.0, rtol=1e-12)
+
+
+def test_nonlinear_apply_averages_element_outputs():
+    """NN = v (a fixed output vector) on a deformed box: every local node of a
+    global node u receives (1 / mult_u) sum over the copies (e, p) of u of
+    (s_e / kappa_e) v_p, computed here copy by copy."""
+    n, lx = 2, 3
+    P = BoxProblem(n, lx, 0.1)
+    v = np.linspace(0.5, 1.5, lx ** 3)
+    rG = synth.unique_normal(P.nu, 8)
+    r = scatter(rG, P.ids)
+    z = mlp.apply(_constant_output_params(lx, v), r, P.G, None, P.ids, P.nu)
+    E = n ** 3
+    acc = np.zeros(P.nu)
+    cnt = np.zeros(P.nu)
+    for e in range(E):
+        s_e = np.sqrt(np.sum(r[e] ** 2))
+        g = [gg[e] for gg in P.G]
+        kap = np.mean(g[0] + g[1] + g[2]) / 3.0
+        for p, gid in enumerate(P.ids[e].ravel()):
+            acc[gid] += s_e / kap * v[p]
+            cnt[gid] += 1
+    np.testing.assert_allclose(z, (acc / cnt)[P.ids], rtol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# bfloat16-storage emulation (forward_bf16, backward_bf16, apply_bf16,
+# apply_block_bf16).  Exactness pin: with operands drawn from a few dyadic
+# values and banded weights (at most two nonzeros per row and per column),
+# every intermediate has few significant bits, so rounding to bfloat16 or
+# float32 changes nothing and the emulation must equal the exact functions.
+
+def _banded(rows, cols, r, scale=0.125):
+    W = np.zeros((rows, cols))
+    for i in range(rows):
+        for j in (i % cols, (i + 1) % cols):
+            W[i, j] = scale * r.choice([-1.0, 1.0])
+    return W
+
+
+def _dyadic_net(r, sizes=(10, 7, 6, 4)):
+    p = []
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        p.append(_banded(b, a, r))
+        p.append(r.choice([-0.125, 0.0, 0.125, 0.25], size=b))
+    return p
+
+
+@pytest.mark.parametrize("linear", [False, True])
+@pytest.mark.parametrize("metric", [False, True])
+def test_bf16_forms_exact_on_bf16_numbers(linear, metric):
+    r = np.random.default_rng(5)
+    params = _dyadic_net(r)
+    B = 4          # the loss scales 2 / (B * 4) and 2 / B are powers of two
+    X = r.choice([-0.75, -0.5, -0.25, 0.25, 0.5, 0.75], size=(B, 10))
+    y3 = mlp.forward(params, X, linear)[2]
+    np.testing.assert_array_equal(mlp.forward_bf16(params, X, linear)[2], y3)
+    T = y3 - r.choice([-0.125, -0.0625, 0.0625, 0.125], size=y3.shape)
+    K = None
+    if metric:
+        K = _banded(4, 4, r)
+        K = 0.5 * (K + K.T)
+    l_ref, g_ref = mlp.backward(params, X, T, K, linear)
+    l_q, g_q = mlp.backward_bf16(params, X, T, K, linear)
+    assert l_q == pytest.approx(l_ref, rel=1e-14)
+    for a, b in zip(g_q, g_ref):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("linear", [False, True])
+def test_bf16_forms_within_rounding_of_exact_forms(linear):
+    """On random He-initialised data the emulation differs from the exact
+    network by bfloat16 rounding: more than zero, a few 2^-8 at most."""
+    params = _small_net(3, (40, 32, 32, 24))
+    params = [p + (0.05 * np.random.default_rng(7).standard_normal(p.shape) if p.ndim == 1 else 0)
+              for p in params]
+    r = np.random.default_rng(8)
+    X = to_bf16_(r.standard_normal((16, 40)))
+    T = r.standard_normal((16, 24))
+    y = mlp.forward(params, X, linear)[2]
+    yq = mlp.forward_bf16(params, X, linear)[2]
+    d = np.linalg.norm(yq - y) / np.linalg.norm(y)
+    assert 0 < d < 3 * 2 ** -8
+    _, g = mlp.backward(params, X, T, None, linear)
+    _, gq = mlp.backward_bf16(params, X, T, None, linear)
+    for s in (0, 2, 4):
+        d = np.linalg.norm(gq[s] - g[s]) / np.linalg.norm(g[s])
+        assert 0 < d < 4 * 2 ** -8, (s, d)
+
+
+def to_bf16_(a):
+    from oracle.quant import to_bf16
+    return to_bf16(a)
+
+
+def test_apply_bf16_within_rounding_of_apply():
+    n, lx = 2, 3
+    P = BoxProblem(n, lx, 0.1)
+    params = synth.mlp_init(4, (lx ** 3 + 6, 16, 16, lx ** 3))
+    r = scatter(synth.unique_normal(P.nu, 5), P.ids)
+    z = mlp.apply(params, r, P.G, None, P.ids, P.nu)
+    zq = mlp.apply_bf16(params, r, P.G, None, P.ids, P.nu)
+    d = np.linalg.norm(zq - z) / np.linalg.norm(z)
+    assert 0 < d < 3 * 2 ** -8
+    zg = np.zeros(P.nu)
+    zg[P.ids.ravel()] = zq.ravel()
+    np.testing.assert_array_equal(zq, zg[P.ids])          # continuous
+
+
+@pytest.mark.parametrize("normalise", [False, True])
+def test_apply_block_bf16_identity_closed_form(normalise):
+    """Identity block (a bfloat16 number) on the uniform box (one kappa): every
+    node gets sqrt(mult) q_u / kappa where q = S r.  With r = sqrt(mult) q for
+    bfloat16 numbers q the unnormalised path rounds nothing; the normalised
+    path rounds q / s_e, within 2^-9 relative."""
+    from oracle.gs import multiplicity
+    n, lx = 2, 4
+    P = BoxProblem(n, lx, 0.0)
+    q = to_bf16_(synth.unique_normal(P.nu, 6))
+    mult = multiplicity(P.ids, P.nu)
+    r = scatter(q, P.ids) * np.sqrt(mult)          # not continuous: only the apply's arithmetic is pinned
+    _, _, kappa = mlp.features(r, P.G)
+    z = mlp.apply_block_bf16(np.eye(lx ** 3), r, P.G, None, P.ids, P.nu, normalise=normalise)
+    want = np.sqrt(mult) * scatter(q, P.ids) / kappa[0]
+    if normalise:
+        np.testing.assert_allclose(z, want, rtol=2 ** -8, atol=0)
+    else:
+        np.testing.assert_allclose(z, want, rtol=1e-14, atol=0)
+    # and against the exact block apply on a continuous residual
+    rc = scatter(synth.unique_normal(P.nu, 7), P.ids)
+    W = synth.rng(8).standard_normal((lx ** 3, lx ** 3))
+    z0 = mlp.apply_block(W, rc, P.G, None, P.ids, P.nu)
+    zq = mlp.apply_block_bf16(W, rc, P.G, None, P.ids, P.nu, normalise=normalise)
+    d = np.linalg.norm(zq - z0) / np.linalg.norm(z0)
+    assert 0 < d < 3 * 2 ** -8
+
+
+def test_bf16_forward_rounds_hidden_activations():
+    """One path 1 -> 1 -> 1 -> 1 of bfloat16 numbers whose products need 10
+    significant bits: (1 + 2^-3)(1 + 2^-6) = 1 + 2^-3 + 2^-6 + 2^-9 rounds to
+    1 + 2^-3 + 2^-6 in bfloat16 (8 significant bits); the second layer's
+    product (1 + 2^-3 + 2^-6)(1 + 2^-4) is rounded again.  A dropped rounding
+    of either hidden layer changes the output."""
+    from oracle.quant import to_bf16
+    one = np.ones(1)
+    X = np.array([[1 + 2 ** -3]])
+    params = [np.array([[1 + 2 ** -6]]), 0 * one, np.array([[1 + 2 ** -4]]), 0 * one, np.array([[1.0]]), 0 * one]
+    y1 = to_bf16(np.array([(1 + 2 ** -3) * (1 + 2 ** -6)]))
+    assert y1[0] == 1 + 2 ** -3 + 2 ** -6
+    y2 = to_bf16(y1 * (1 + 2 ** -4))
+    assert y2[0] != y1[0] * (1 + 2 ** -4)
+    for linear in (False, True):
+        assert mlp.forward_bf16(params, X, linear)[2][0, 0] == y2[0]
+        assert mlp.forward(params, X, linear)[2][0, 0] != y2[0]
