@@ -260,21 +260,33 @@ def apply_bf16(params, r_local, G, h1, ids, n_unique):
     return gs(z / multiplicity(ids, n_unique), ids, n_unique)
 
 
-def apply_block_bf16(W, r_local, G, h1, ids, n_unique, normalise=True):
+def apply_block_bf16(W, r_local, G, h1, ids, n_unique, normalise=True, f32_decisions=False):
     """The symmetric additive apply of a float32 element block W as the
     linear-form kernels evaluate it: W_s = bf16((W + W^T) / 2), the weighted
     element residual S r_e rounded to bfloat16 -- divided by its 2-norm s_e
     first (``normalise``, the local-layout path, output scaled back by s_e)
     or not (the unique-layout path) -- the product summed exactly, the output
-    weighted by S / kappa_e and assembled."""
+    weighted by S / kappa_e and assembled.
+    f32_decisions: the two roundings to bfloat16 are taken from the float32
+    values the kernels round (both sides decide in the same precision): W_s
+    from the float32 sum of the float32 block and its transpose, halved
+    (exact), and S r from the float32 product of float32 S and float32 r (a
+    product of two float32 numbers is exact in float64, so one rounding to
+    float32 reproduces the float32 multiply).  Unnormalised path only."""
     from .gs import gs, multiplicity
-    from .quant import to_bf16
+    from .quant import to_bf16, to_f32
     E = r_local.shape[0]
     nloc = r_local[0].size
-    Wq = to_bf16(0.5 * (W + W.T))
-    _, _, kappa = features(r_local, G, h1)
     S = 1.0 / np.sqrt(multiplicity(ids, n_unique).reshape(E, nloc))
-    v = S * r_local.reshape(E, nloc)
+    if f32_decisions:
+        assert not normalise
+        W32 = to_f32(W)
+        Wq = to_bf16(0.5 * to_f32(W32 + W32.T))
+        v = to_f32(to_f32(S) * to_f32(r_local.reshape(E, nloc)))
+    else:
+        Wq = to_bf16(0.5 * (W + W.T))
+        v = S * r_local.reshape(E, nloc)
+    _, _, kappa = features(r_local, G, h1)
     if normalise:
         s = np.sqrt(np.sum(v * v, axis=1)) + EPS
         z = (to_bf16(v / s[:, None]) @ Wq.T) * (s / kappa)[:, None] * S

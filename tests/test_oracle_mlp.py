@@ -438,3 +438,32 @@ def test_bf16_forward_rounds_hidden_activations():
     for linear in (False, True):
         assert mlp.forward_bf16(params, X, linear)[2][0, 0] == y2[0]
         assert mlp.forward(params, X, linear)[2][0, 0] != y2[0]
+
+
+def test_apply_block_bf16_float32_decisions():
+    """f32_decisions takes the bfloat16 roundings from float32 values.  Where
+    those values are float32 numbers already (a symmetric block of bfloat16
+    numbers; a residual of bfloat16 numbers on the nodes of multiplicity 1,
+    where S = 1, and 0 elsewhere) it equals the float64-decision form bit for
+    bit; on a general residual it stays within bfloat16 rounding of the exact
+    block apply.  A dropped S, a missing symmetrisation or a transposed block
+    fails one of the two."""
+    from oracle.gs import multiplicity
+    n, lx = 2, 4
+    P = BoxProblem(n, lx, 0.1)
+    nloc = lx ** 3
+    A = to_bf16_(synth.rng(9).standard_normal((nloc, nloc)))
+    Wsym = A + A.T                                  # bfloat16 numbers: halving and rounding are exact
+    mult = multiplicity(P.ids, P.nu)
+    r = to_bf16_(scatter(synth.unique_normal(P.nu, 10), P.ids)) * (mult == 1)
+    z64 = mlp.apply_block_bf16(Wsym, r, P.G, None, P.ids, P.nu, normalise=False)
+    z32 = mlp.apply_block_bf16(Wsym, r, P.G, None, P.ids, P.nu, normalise=False, f32_decisions=True)
+    np.testing.assert_array_equal(z32, z64)
+    W = synth.rng(11).standard_normal((nloc, nloc))
+    rc = scatter(synth.unique_normal(P.nu, 12), P.ids)
+    z0 = mlp.apply_block(W, rc, P.G, None, P.ids, P.nu)
+    zq = mlp.apply_block_bf16(W, rc, P.G, None, P.ids, P.nu, normalise=False, f32_decisions=True)
+    d = np.linalg.norm(zq - z0) / np.linalg.norm(z0)
+    assert 0 < d < 3 * 2 ** -8
+    zt = mlp.apply_block(W.T @ np.diag(np.arange(1.0, nloc + 1)), rc, P.G, None, P.ids, P.nu)
+    assert np.linalg.norm(zq - zt) / np.linalg.norm(zt) > 0.1
