@@ -195,17 +195,44 @@ def solve_comparison(ctx, P, n, lx, amp, tol=1e-10):
         print(f"[bench] solve {name}: {ms:.1f} ms, {st['iterations']} its, outer {st['outer']}, "
               f"relres {st['relres']:.2e}, err {res[name]['err_vs_oracle']}", file=sys.stderr, flush=True)
         cg.close()
+    # the multigrid V-cycle (classical coarse-space preconditioner) in flexible CG
+    t0 = time.perf_counter()
+    mg = op.multigrid()
+    torch.cuda.synchronize()
+    res["mg_setup_s"] = round(time.perf_counter() - t0, 3)
+    res["mg_levels"] = [list(P.sem_mg_level_info(mg, q)) for q in range(P.sem_mg_levels(mg))]
+    mg_variants = (("mg_fcg_f64", P.SEM_SOLVE_F64, 0), ("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1))
+    for name, code, mode in mg_variants:
+        ms, st = _timed_solve(P, op, x, b, code, mode, None, tol, mg=mg)
+        res[name] = {"ms": round(ms, 2), "iterations": st["iterations"], "outer": st["outer"],
+                     "relres": st["relres"], "converged": st["converged"], "err_vs_oracle": gold.error(x)}
+        print(f"[bench] solve {name}: {ms:.1f} ms, {st['iterations']} its, relres {st['relres']:.2e}, "
+              f"err {res[name]['err_vs_oracle']}", file=sys.stderr, flush=True)
+    mg.close()
     base = res["fp64_pcg"]["ms"]
     res["speedup_vs_fp64_pcg"] = {k2: round(base / res[k2]["ms"], 3)
-                                  for k2, _, _ in variants[1:]}
+                                  for k2, _, _ in variants[1:] + mg_variants}
+    # the same solve on the 16^3 box: how the iteration counts grow with the mesh
+    op16 = BoxOperator(ctx, n // 2, lx, amp)
+    b16 = op16.fourier_rhs(k, a, ph)
+    x16 = torch.empty_like(b16)
+    mg16 = op16.multigrid()
+    growth = {}
+    for name, code, mode, m in (("fp64_pcg", P.SEM_SOLVE_F64, 0, None), ("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1, mg16)):
+        _, st = _timed_solve(P, op16, x16, b16, code, mode, None, tol, mg=m)
+        growth[name] = {"iterations_half_n": st["iterations"], "iterations": res[name]["iterations"],
+                        "ratio": round(res[name]["iterations"] / st["iterations"], 3)}
+    res["iteration_growth_from_half_n"] = growth
+    mg16.close()
+    op16.gs.close()
     return res
 
 
-def _timed_solve(P, op, x, b, code, mode, lp, tol):
+def _timed_solve(P, op, x, b, code, mode, lp, tol, mg=None, h2b=None):
     """One warm-up and one timed sem_cg_solve; returns (ms, stats)."""
     import torch
-    kw = dict(tol=tol, precision=code, ir_mode=mode, learned=lp, maxit=50000)
-    cg = op.solver(code, learned=lp)
+    kw = dict(tol=tol, precision=code, ir_mode=mode, learned=lp, maxit=50000, mg=mg)
+    cg = op.solver(code, learned=lp, mg=mg, h2b=h2b)
     P.sem_cg_solve(cg, x, b, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -240,10 +267,15 @@ def dirichlet_comparison(ctx, P, n, lx, amp, lp=None, tol=1e-10):
         variants.append(("learned_f32_rr", P.SEM_SOLVE_F32_IR, 1, lp))
     if blk is not None:
         variants.append(("classical_block_f32_rr", P.SEM_SOLVE_F32_IR, 1, blk))
+    mg = op.multigrid()
+    variants.append(("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1, mg))
     for name, code, mode, net in variants:
-        if net is not None:
-            op.bind(net)
-        ms, st = _timed_solve(P, op, x, b, code, mode, net, tol)
+        if net is mg:
+            ms, st = _timed_solve(P, op, x, b, code, mode, None, tol, mg=mg)
+        else:
+            if net is not None:
+                op.bind(net)
+            ms, st = _timed_solve(P, op, x, b, code, mode, net, tol)
         res[name] = {"ms": round(ms, 2), "iterations": st["iterations"], "relres": st["relres"],
                      "jacobi_steps": st["jacobi_steps"], "converged": st["converged"],
                      "err_vs_oracle": gold.error(x)}
@@ -253,6 +285,7 @@ def dirichlet_comparison(ctx, P, n, lx, amp, lp=None, tol=1e-10):
     res["speedup_vs_fp64_pcg"] = {v[0]: round(base / res[v[0]]["ms"], 3) for v in variants[1:]}
     if blk is not None:
         blk.close()
+    mg.close()
     op.gs.close()
     return res
 
@@ -282,16 +315,13 @@ def helmholtz_solve_comparison(ctx, P, n, lx, amp, h2=1e3, tol=1e-10):
     variants = [("fp64_pcg", P.SEM_SOLVE_F64, 0, None), ("f32_rr", P.SEM_SOLVE_F32_IR, 1, None)]
     if blk is not None:
         variants.append(("classical_block_f32_rr", P.SEM_SOLVE_F32_IR, 1, blk))
+    mg = op.multigrid(h2=h2)
+    variants.append(("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1, mg))
     for name, code, mode, net in variants:
-        kw = dict(tol=tol, precision=code, ir_mode=mode, learned=net, maxit=50000)
-        cg = op.solver(code, h2b=h2b, learned=net)
-        P.sem_cg_solve(cg, x, b, **kw)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rc, st = P.sem_cg_solve(cg, x, b, **kw)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3
-        cg.close()
+        if net is mg:
+            ms, st = _timed_solve(P, op, x, b, code, mode, None, tol, mg=mg, h2b=h2b)
+        else:
+            ms, st = _timed_solve(P, op, x, b, code, mode, net, tol, h2b=h2b)
         res[name] = {"ms": round(ms, 2), "iterations": st["iterations"], "relres": st["relres"],
                      "converged": st["converged"], "err_vs_oracle": gold.error(x)}
         print(f"[bench] helmholtz_solve {name}: {ms:.1f} ms, {st['iterations']} its, relres {st['relres']:.2e}",
@@ -300,6 +330,7 @@ def helmholtz_solve_comparison(ctx, P, n, lx, amp, h2=1e3, tol=1e-10):
     res["speedup_vs_fp64_pcg"] = {v[0]: round(base / res[v[0]]["ms"], 3) for v in variants[1:]}
     if blk is not None:
         blk.close()
+    mg.close()
     op.gs.close()
     return res
 

@@ -33,6 +33,7 @@ typedef struct sem_ctx_s* sem_ctx_t;
 typedef struct sem_gs_s* sem_gs_t;
 typedef struct sem_cg_s* sem_cg_t;
 typedef struct sem_lp_s* sem_lp_t;
+typedef struct sem_mg_s* sem_mg_t;
 
 typedef enum { SEM_F64 = 0, SEM_F32 = 1, SEM_BF16 = 2 } sem_dtype_t;
 
@@ -257,6 +258,9 @@ typedef struct {
                             residual has fallen by the factor `delta`; the search
                             direction is kept */
     double delta;        /* ir_mode 1: replacement trigger (0: 0.1) */
+    sem_mg_t mg;         /* NULL: none.  Otherwise flexible CG preconditioned by this
+                            multigrid V-cycle (sem_mg_create on the same operator and
+                            plan); not together with `learned` */
 } sem_solve_opts_t;
 
 typedef struct {
@@ -300,6 +304,58 @@ int sem_cg_destroy(sem_cg_t cg);
  * iterations). */
 int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_solve_opts_t* opts,
                  sem_solve_stats_t* stats);
+
+/* ------------------------------------------------ multigrid preconditioner */
+
+/* A multigrid V-cycle for the operators of the box meshes (sem_box_mesh and
+ * sem_box_mesh_dirichlet): the preconditioner whose iteration count does not
+ * grow with the mesh, for the Poisson (and Helmholtz) solve the operator
+ * serves (Sec. 3).  Levels: the caller's operator (n^3 elements, lx), then
+ * lx -> max(2, lx / 2) on the same elements down to lx = 2 (p-coarsening),
+ * then the lx = 2 box n^3 -> (n/2)^3 while n is even and n/2 >= n_coarse
+ * (h-coarsening).  Each level below the first is re-discretised by the
+ * library's set-up calls on the same deformed box (h1 = 1; h2 times that
+ * level's mass for Helmholtz operators).  Transfer: the coarse level's field
+ * evaluated at the fine level's nodes (the coarse Lagrange basis on the same
+ * element; the parent's trilinear basis); restriction by its transpose.
+ * Smoothing: `degree` steps of the Chebyshev semi-iteration in D^-1 A (D the
+ * assembled diagonal) on [lo lmax, hi lmax], lmax of every level estimated by
+ * `lanczos_steps` Lanczos steps at creation.  The coarsest level is solved
+ * with a dense inverse (at most 2048 unknowns; of A + c 1 1^T on the singular
+ * periodic box, c = mean diagonal / unknowns).  V(b): pre-smoothing from 0,
+ * coarse correction of the residual, post-smoothing: a fixed symmetric positive
+ * definite map.  Vectors and operators of the V-cycle are float32. */
+typedef struct {
+    int n;               /* elements per side of the box the operator lives on */
+    double amp;          /* the box's deformation amplitude (sem_box_mesh) */
+    int dirichlet;       /* 1: the Dirichlet box (its plan has Dirichlet nodes), 0: periodic */
+    double h2;           /* Helmholtz coefficient (> 0 exactly when A->h2b is set; 0: Poisson) */
+    int degree;          /* Chebyshev steps per smoothing (0: 2) */
+    double lo, hi;       /* smoothing interval in units of lmax (0: 0.3 and 1.1) */
+    int n_coarse;        /* h-coarsening keeps n >= n_coarse (0: 2) */
+    int lanczos_steps;   /* Lanczos steps per level for lmax (0: 20) */
+} sem_mg_opts_t;
+
+/* Build the hierarchy for the operator A (h1 must be NULL) on the plan gs of
+ * the n^3 box: allocates every level's factors, plans and work vectors, and
+ * estimates each lmax.  Synchronous.  SEM_EINVAL if the sizes do not match
+ * n^3 elements, the plan's Dirichlet nodes do not match opts->dirichlet, or
+ * the coarsest level would exceed 2048 unknowns (choose n_coarse).  The
+ * operator arrays must stay valid while the hierarchy lives. */
+int sem_mg_create(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A, const sem_mg_opts_t* opts,
+                  sem_mg_t* mg);
+int sem_mg_destroy(sem_mg_t mg);
+/* Number of levels (host out). */
+int sem_mg_levels(sem_mg_t mg, int* count);
+/* Level `level` (0 = the caller's): elements per side, lx, unknowns, and the
+ * estimated lmax of D^-1 A (0 on the coarsest level).  Any out may be NULL. */
+int sem_mg_level_info(sem_mg_t mg, int level, int* n, int* lx, int64_t* n_unique, double* lmax);
+/* Replace the lmax of a smoothed level (every level but the coarsest). */
+int sem_mg_set_lmax(sem_mg_t mg, int level, double lmax);
+/* z = V(r) on unique-node vectors of the finest plan (the layout of
+ * sem_lp_apply_unique); dtype SEM_F64 or SEM_F32 for both; z must not alias r.
+ * Asynchronous; the hierarchy's work vectors are shared by all calls on mg. */
+int sem_mg_apply(sem_mg_t mg, void* z, const void* r, sem_dtype_t dtype);
 
 /* --------------------------------------------- learned preconditioner */
 
@@ -376,7 +432,8 @@ int sem_lp_set_block(sem_lp_t lp, const float* W, int64_t count);
  * Takes effect at the next sem_lp_bind. */
 int sem_lp_set_jacobi_base(sem_lp_t lp, int on);
 /* Bind to an operator (lx = 8, nel <= max_rows) and its plan: computes the
- * per-element geometric features.  Needed by sem_lp_samples / sem_lp_apply.
+ * per-element geometric features and keeps the operator's arrays for
+ * sem_lp_snapshot (they must stay valid while bound).  Needed by sem_lp_samples / sem_lp_apply.
  * Only the stiffness is read (A->h2b is ignored): with a Helmholtz solve the
  * Jacobi base uses the stiffness diagonal. */
 int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs);
@@ -386,6 +443,27 @@ int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs);
  * from the error err.  r, err: device float64 fields of the bound operator. */
 int sem_lp_samples(sem_lp_t lp, const double* r, const double* err, const int64_t* elems,
                    int64_t count, uint16_t* X, float* T, int64_t row0);
+/* One snapshot of a solve A x_k = b with reference solution xstar on the
+ * bound operator: forms the residual r = b - Q Q^T A x_k and the error
+ * err = xstar - x_k (float64, into the caller's work arrays r_out and err_out,
+ * n_local each, which must not alias the inputs), then writes the training
+ * rows of sem_lp_samples for the `count` elements elems[].  x, xstar, b:
+ * device float64 continuous fields of the bound operator.  The bound
+ * operator's arrays must still be valid.  Asynchronous. */
+int sem_lp_snapshot(sem_lp_t lp, const double* x, const double* xstar, const double* b,
+                    double* r_out, double* err_out, const int64_t* elems, int64_t count,
+                    uint16_t* X, float* T, int64_t row0);
+/* The classical element block the learned one is compared with: kappa times
+ * the inverse of the assembled operator restricted to the lx^3 nodes of one
+ * element (the local solve of one-level additive Schwarz with minimal
+ * overlap), on the undeformed periodic 3^3 box, where every element has the
+ * same matrix; kappa = mean(g11 + g22 + g33) / 3 of that element.  The
+ * columns come from the library's operator and gather-scatter applied to unit
+ * vectors; the (lx^3)^2 matrix is symmetrised and inverted by Cholesky on the
+ * host.  W: host float64, (lx^3)^2, row-major.  Allocates and frees
+ * temporary device memory; synchronous.  Pass it (rounded to float32) to
+ * sem_lp_set_block for lx = 8. */
+int sem_lp_reference_block(sem_ctx_t ctx, int lx, double* W);
 /* Y = NN(X) for `rows` rows (X device bf16 rows x SEM_LP_IN_PAD, Y device
  * float32 rows x 512). */
 int sem_lp_forward(sem_lp_t lp, const uint16_t* X, int64_t rows, float* Y);

@@ -17,7 +17,9 @@ __all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONV
            "LearnedPrecond", "sem_lp_create", "sem_lp_destroy", "sem_lp_set", "sem_lp_get",
            "sem_lp_set_step", "sem_lp_get_step", "sem_lp_bind", "sem_lp_samples", "sem_lp_forward",
            "sem_lp_gradients", "sem_lp_adam", "sem_lp_set_metric", "sem_lp_set_jacobi_base", "sem_lp_set_linear", "sem_lp_train_step", "sem_lp_apply", "sem_lp_apply_unique", "sem_lp_save", "sem_lp_load", "sem_lp_set_block", "LP_SLOTS",
-           "SEM_LP_IN", "SEM_LP_IN_PAD", "SEM_LP_HIDDEN", "SEM_LP_OUT"]
+           "SEM_LP_IN", "SEM_LP_IN_PAD", "SEM_LP_HIDDEN", "SEM_LP_OUT", "SemMgOpts", "Multigrid",
+           "sem_mg_create", "sem_mg_destroy", "sem_mg_levels", "sem_mg_level_info", "sem_mg_set_lmax",
+           "sem_mg_apply", "sem_lp_snapshot", "sem_lp_reference_block"]
 
 SEM_LP_IN, SEM_LP_IN_PAD, SEM_LP_HIDDEN, SEM_LP_OUT = 518, 528, 256, 512
 # slot -> shape of the float32 array it holds (parameters; +6 m, +12 v, +18 grads)
@@ -36,7 +38,14 @@ class SemSolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("learned", ctypes.c_void_p), ("ir_mode", ctypes.c_int), ("delta", ctypes.c_double)]
+                ("learned", ctypes.c_void_p), ("ir_mode", ctypes.c_int), ("delta", ctypes.c_double),
+                ("mg", ctypes.c_void_p)]
+
+
+class SemMgOpts(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("amp", ctypes.c_double), ("dirichlet", ctypes.c_int),
+                ("h2", ctypes.c_double), ("degree", ctypes.c_int), ("lo", ctypes.c_double),
+                ("hi", ctypes.c_double), ("n_coarse", ctypes.c_int), ("lanczos_steps", ctypes.c_int)]
 
 
 class SemSolveStats(ctypes.Structure):
@@ -114,6 +123,14 @@ EXPORTS = {
     "sem_lp_set_metric": (_int, [_vp, _dbl]),
     "sem_lp_set_jacobi_base": (_int, [_vp, _int]),
     "sem_lp_set_linear": (_int, [_vp, _int]),
+    "sem_lp_snapshot": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64]),
+    "sem_lp_reference_block": (_int, [_vp, _int, _pdbl]),
+    "sem_mg_create": (_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    "sem_mg_destroy": (_int, [_vp]),
+    "sem_mg_levels": (_int, [_vp, ctypes.POINTER(_int)]),
+    "sem_mg_level_info": (_int, [_vp, _int, ctypes.POINTER(_int), ctypes.POINTER(_int), _pi64, _pdbl]),
+    "sem_mg_set_lmax": (_int, [_vp, _int, _dbl]),
+    "sem_mg_apply": (_int, [_vp, _vp, _vp, _int]),
 }
 
 _LIB = None
@@ -378,9 +395,10 @@ class CgSolver:
 
 
 def _opts(tol=1e-10, maxit=0, precision=SEM_SOLVE_F64, inner_tol=0.0, inner_maxit=0,
-          max_outer=0, check_every=0, learned=None, ir_mode=0, delta=0.0):
+          max_outer=0, check_every=0, learned=None, ir_mode=0, delta=0.0, mg=None):
     return SemSolveOpts(tol, maxit, precision, inner_tol, inner_maxit, max_outer, check_every,
-                        learned.handle if learned is not None else None, ir_mode, delta)
+                        learned.handle if learned is not None else None, ir_mode, delta,
+                        mg.handle if mg is not None else None)
 
 
 def sem_cg_setup(ctx, gs, D, h1, G, nel, lx, h2b=None, **opts):
@@ -538,3 +556,75 @@ def sem_lp_set_jacobi_base(lp, on):
 
 def sem_lp_set_linear(lp, on):
     _check(lib().sem_lp_set_linear(lp.handle, int(bool(on))), lp.ctx.handle)
+
+
+class Multigrid:
+    def __init__(self, ctx, handle, keep):
+        self.ctx, self.handle, self._keep = ctx, handle, keep
+        ctx.adopt(self)
+
+    def close(self):
+        if self.handle:
+            self.ctx.bind()
+            lib().sem_mg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sem_mg_create(ctx, gs, D, G, nel, lx, n, amp, dirichlet=False, h2=0.0, h2b=None, degree=0, lo=0.0,
+                  hi=0.0, n_coarse=0, lanczos_steps=0):
+    """The multigrid hierarchy of the n^3 box operator (D, G float64 device
+    tensors as for sem_cg_setup, h1 = 1; h2b = h2 * bm for a Helmholtz operator)."""
+    A = SemOperator(*[_ptr(t) for t in D], None, *[_ptr(t) for t in G], nel, lx, _ptr(h2b))
+    o = SemMgOpts(n, amp, int(bool(dirichlet)), h2, degree, lo, hi, n_coarse, lanczos_steps)
+    h = ctx.bind()
+    out = _vp()
+    _check(lib().sem_mg_create(h, gs.handle, ctypes.byref(A), ctypes.byref(o), ctypes.byref(out)), h)
+    return Multigrid(ctx, out, (D, G, gs, h2b))
+
+
+def sem_mg_destroy(mg):
+    mg.close()
+
+
+def sem_mg_levels(mg):
+    c = _int(0)
+    _check(lib().sem_mg_levels(mg.handle, ctypes.byref(c)), mg.ctx.handle)
+    return c.value
+
+
+def sem_mg_level_info(mg, level):
+    """(n, lx, n_unique, lmax) of a level"""
+    n, lx, nu, lm = _int(0), _int(0), _i64(0), _dbl(0.0)
+    _check(lib().sem_mg_level_info(mg.handle, level, ctypes.byref(n), ctypes.byref(lx), ctypes.byref(nu),
+                                   ctypes.byref(lm)), mg.ctx.handle)
+    return n.value, lx.value, nu.value, lm.value
+
+
+def sem_mg_set_lmax(mg, level, lmax):
+    _check(lib().sem_mg_set_lmax(mg.handle, level, float(lmax)), mg.ctx.handle)
+
+
+def sem_mg_apply(mg, z, r):
+    mg.ctx.bind()
+    _check(lib().sem_mg_apply(mg.handle, _ptr(z), _ptr(r), dtype_code(r)), mg.ctx.handle)
+
+
+def sem_lp_snapshot(lp, x, xstar, b, r_out, err_out, elems, X, T, row0):
+    lp.ctx.bind()
+    _check(lib().sem_lp_snapshot(lp.handle, _ptr(x), _ptr(xstar), _ptr(b), _ptr(r_out), _ptr(err_out),
+                                 _ptr(elems), elems.numel(), _ptr(X), _ptr(T), row0), lp.ctx.handle)
+
+
+def sem_lp_reference_block(ctx, lx=8):
+    """kappa A_ee^-1 of the undeformed element (host float64, (lx^3, lx^3))"""
+    import numpy as np
+    W = np.empty((lx ** 3, lx ** 3))
+    h = ctx.bind()
+    _check(lib().sem_lp_reference_block(h, lx, W.ctypes.data_as(_pdbl)), h)
+    return W

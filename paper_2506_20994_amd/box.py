@@ -94,3 +94,10 @@ class BoxOperator:
     def bind(self, lp):
         """Bind a learned preconditioner to this operator."""
         B.sem_lp_bind(lp, self.D, self.h1, self.G, self.nel, self.lx, self.gs)
+
+    def multigrid(self, h2=0.0, **opts):
+        """The multigrid V-cycle of this box's operator (h1 = 1; with h2 > 0 the
+        Helmholtz operator A + h2 B).  opts: see SemMgOpts."""
+        h2b = h2 * self.bm if h2 > 0 else None
+        return B.sem_mg_create(self.ctx, self.gs, self.D, self.G, self.nel, self.lx, self.n, self.amp,
+                               dirichlet=self.dirichlet, h2=h2, h2b=h2b, **opts)

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libsem.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["context.cpp", "setup.hip", "ax.hip", "gs.hip", "cg.hip", "lp.hip"]
+SOURCES = ["context.cpp", "setup.hip", "ax.hip", "gs.hip", "cg.hip", "lp.hip", "mg.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Wall", "-Wno-unused-function",

@@ -118,8 +118,8 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// FUSE: the solver form.  The kernel returns at once when *skip is non-zero
-// (a converged solve), and each workgroup writes sum_L u_L w_L over its
+// Any form returns at once when skip is given and *skip is non-zero (a
+// converged solve).  FUSE: the solver form's dot: each workgroup writes sum_L u_L w_L over its
 // elements, accumulated in float64, to dot[blockIdx.x] (p^T A p before
 // gather-scatter).
 // GATHER: u is a unique-node vector, read as u[lid[L]] (lid streamed, u
@@ -140,7 +140,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
     constexpr int L2 = LX * LX;
     constexpr int L3 = L2 * LX;
     constexpr bool WP = Shape<LX>::kWavePrivate;
-    if (FUSE && *skip) return;
+    if (skip && *skip) return;
     __shared__ TC s_u[EPB * L3];               // the element's u (wave-private: then the r-flux)
     __shared__ TC s_s[EPB * L3];               // s-flux
     __shared__ TC s_r0[WP ? 1 : EPB * L3];     // r-flux when elements span waves

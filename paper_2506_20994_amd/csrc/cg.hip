@@ -99,26 +99,7 @@ __device__ __forceinline__ T assemble(const T* __restrict__ wc, const int32_t* _
     return s;
 }
 
-// sum of the local copies of unique node u of a field in the local layout:
-// wl[uidx[q]] for q in [uoff[u], uoff[u+1]), the first eight by independent
-// predicated loads, summed in CSR order (the order of assemble above)
-template <typename T>
-__device__ __forceinline__ T assemble_local(const T* __restrict__ wl, const int32_t* __restrict__ uoff,
-                                            const int32_t* __restrict__ uidx, int64_t u) {
-    const int32_t b = uoff[u], e = uoff[u + 1];
-    int32_t L[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) L[q] = b + q < e ? uidx[b + q] : -1;
-    T v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = L[q] >= 0 ? wl[L[q]] : T(0);
-    T s = v[0];
-#pragma unroll
-    for (int q = 1; q < 8; ++q)
-        if (b + q < e) s += v[q];
-    for (int32_t q = b + 8; q < e; ++q) s += wl[uidx[q]];
-    return s;
-}
+using sem::assemble_local;
 
 // out_u = (T) in_L at the first local copy of u (a continuous local field)
 template <typename T>
@@ -631,6 +612,7 @@ struct sem_cg_s {
     double* wl64 = nullptr;                                    // local float64
     float* rhs32 = nullptr;        // IR: normalised inner right-hand side (unique)
     sem_lp_t lp = nullptr;
+    sem_mg_t mg = nullptr;         // multigrid V-cycle (flexible CG), or null
     std::vector<void*> allocs;
 };
 
@@ -640,6 +622,9 @@ namespace {
 // its solves project out the mean; with Dirichlet nodes or a Helmholtz mass
 // term the operator is positive definite.
 inline bool projects(sem_cg_t cg) { return cg->gs->n_masked == 0 && !cg->A64.hb; }
+
+// flexible CG runs whenever a preconditioner other than Jacobi is bound
+inline bool flexible(sem_cg_t cg) { return cg->lp || cg->mg; }
 
 int cg_alloc(sem_cg_t cg, void** p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes);
@@ -705,6 +690,36 @@ bool stagnated(std::vector<std::pair<int, double>>& hist, int it, double rr) {
     return false;
 }
 
+// z = P(r) for one flexible-CG iteration and the partials of fcg_gamma_final:
+// the multigrid V-cycle, or the network (its linear form assembles z inside
+// the dot kernel).  After the solve has fallen back, the kernels take the
+// Jacobi z themselves (S->fallback) and no preconditioner runs.
+template <typename T>
+int precondition(sem_cg_t cg, T* z, const T* r, const T* wu, const T* minv, bool fallen, unsigned g) {
+    hipStream_t st = cg->ctx->stream;
+    const int64_t n = cg->nu;
+    const int* skip = &cg->S->done;
+    const bool f64 = sizeof(T) == 8;
+    int rc = SEM_OK;
+    if (!fallen && cg->mg) {
+        rc = sem::mg_apply(cg->mg, z, r, f64, skip);
+    } else if (!fallen) {
+        const float* zl = nullptr;
+        bool jb = false;
+        rc = sem::lp_apply_partial(cg->lp, r, f64, skip, &zl, &jb);
+        if (rc == SEM_OK) {
+            fcg_dots_asm_kernel<T><<<g, kBlock, 0, st>>>(z, zl, cg->gs->uoff, r, wu, minv, jb, n, cg->S, cg->part);
+            SEM_LAUNCH_CHECK(cg->ctx);
+            return SEM_OK;
+        }
+        rc = sem::lp_apply(cg->lp, z, r, f64, skip, true);    // the nonlinear network
+    }
+    if (rc) return rc;
+    fcg_dots_kernel<T><<<g, kBlock, 0, st>>>(r, z, wu, minv, n, cg->S, cg->part);
+    SEM_LAUNCH_CHECK(cg->ctx);
+    return SEM_OK;
+}
+
 // Mixed-precision CG with residual replacement (reliable updates; Strzodka
 // and Goeddeke 2006, Clark et al. 2010): float32 vectors and the reduced
 // operator drive the Krylov iteration; whenever the float32 residual has
@@ -737,19 +752,9 @@ int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int chec
     std::vector<std::pair<int, double>> rr_hist;
     for (;;) {
         for (int q = 0; q < check_every; ++q) {
-            if (cg->lp) {   // flexible CG step with the network (Jacobi where it is rejected)
-                const float* zl = nullptr;
-                bool jb = false;
-                int rc = SEM_OK;
-                if (!fallen) rc = sem::lp_apply_partial(cg->lp, r, false, &cg->S->done, &zl, &jb);
-                if (!fallen && rc == SEM_OK) {
-                    fcg_dots_asm_kernel<float><<<g, kBlock, 0, st>>>(z, zl, uoff, r, wu, minv, jb, n, cg->S,
-                                                                     cg->part);
-                } else {
-                    if (!fallen) rc = sem::lp_apply(cg->lp, z, r, false, &cg->S->done, true);
-                    if (rc) return rc;
-                    fcg_dots_kernel<float><<<g, kBlock, 0, st>>>(r, z, wu, minv, n, cg->S, cg->part);
-                }
+            if (flexible(cg)) {   // flexible CG step (Jacobi where the output is rejected)
+                int rc = precondition<float>(cg, z, r, wu, minv, fallen, g);
+                if (rc) return rc;
                 fcg_gamma_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
                 fcg_p_kernel<float><<<g, kBlock, 0, st>>>(p, z, r, minv, n, cg->S, cg->part2);
                 rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid);
@@ -772,7 +777,7 @@ int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int chec
         SEM_HIP(ctx, hipStreamSynchronize(st));
         const Scal& H = *cg->S_host;
         if (!H.done) {
-            if (cg->lp && !fallen && stagnated(rr_hist, H.it, H.rr)) {
+            if (flexible(cg) && !fallen && stagnated(rr_hist, H.it, H.rr)) {
                 set_fallback<<<1, 1, 0, st>>>(cg->S);      // Jacobi for good
                 SEM_LAUNCH_CHECK(ctx);
                 fallen = true;
@@ -801,7 +806,7 @@ int rr_run(sem_cg_t cg, Level& lv, double tol, double delta, int maxit, int chec
         // PCG: the paused iteration skipped its direction update, redone with
         // the replaced residual and that iteration's beta (flexible CG forms
         // its direction at the start of the next iteration instead)
-        if (!cg->lp) pcg_p_kernel<float><<<g, kBlock, 0, st>>>(p, r, minv, n, cg->S);
+        if (!flexible(cg)) pcg_p_kernel<float><<<g, kBlock, 0, st>>>(p, r, minv, n, cg->S);
         SEM_LAUNCH_CHECK(ctx);
     }
     *iters_out = cg->S_host->it;
@@ -833,17 +838,8 @@ int fcg_run(sem_cg_t cg, Level& lv, const T* rhs, double tol, int maxit, int che
     std::vector<std::pair<int, double>> hist;   // (iteration, r.r) at each check
     for (;;) {
         for (int q = 0; q < check_every; ++q) {
-            int rc = SEM_OK;
-            const float* zl = nullptr;
-            bool jb = false;
-            if (!fallen) rc = sem::lp_apply_partial(cg->lp, r, f64, &cg->S->done, &zl, &jb);
-            if (!fallen && rc == SEM_OK) {
-                fcg_dots_asm_kernel<T><<<g, kBlock, 0, st>>>(z, zl, uoff, r, wu, minv, jb, n, cg->S, cg->part);
-            } else {
-                if (!fallen) rc = sem::lp_apply(cg->lp, z, r, f64, &cg->S->done, true);
-                if (rc) return rc;
-                fcg_dots_kernel<T><<<g, kBlock, 0, st>>>(r, z, wu, minv, n, cg->S, cg->part);
-            }
+            int rc = precondition<T>(cg, z, r, wu, minv, fallen, g);
+            if (rc) return rc;
             fcg_gamma_final<<<1, kFinal, 0, st>>>(cg->S, cg->part, (int)g);
             fcg_p_kernel<T><<<g, kBlock, 0, st>>>(p, z, r, minv, n, cg->S, cg->part2);
             rc = sem::launch_ax(ctx, lv.kind, lv.A, wl, p, &cg->S->done, cg->part, lid);
@@ -909,6 +905,17 @@ int remove_mean_u(sem_cg_t cg, double* xu) {
 
 }  // namespace
 
+namespace sem {
+
+void pack_factors_f32(hipStream_t st, float* out, const double* const* G, int64_t n, int lx) {
+    Six six;
+    for (int q = 0; q < 6; ++q) six.g[q] = G[q];
+    six.l2 = lx * lx;
+    pack_kernel<float><<<vec_grid(n), kBlock, 0, st>>>(out, six, n);
+}
+
+}  // namespace sem
+
 extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
                             const sem_solve_opts_t* opts, sem_cg_t* out) {
     int rc = sem::enter(ctx);
@@ -970,6 +977,13 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
         if (e == hipSuccess) e = hipHostMalloc(&cg->sums_host, 2 * sizeof(double), hipHostMallocDefault);
         if (e != hipSuccess) return bail(sem::check_hip(ctx, e, "sem_cg_setup: hipHostMalloc"));
     }
+    if (opts->learned && opts->mg)
+        return bail(sem::fail(ctx, SEM_EINVAL, "sem_cg_setup: learned and mg preconditioners are exclusive"));
+    if (opts->mg) {
+        if (sem::mg_nel(opts->mg) != A->nel || sem::mg_plan(opts->mg) != gs)
+            return bail(sem::fail(ctx, SEM_EINVAL, "sem_cg_setup: the multigrid hierarchy is not built on this operator and plan"));
+        cg->mg = opts->mg;
+    }
     if (opts->learned) {
         if (sem::lp_rows(opts->learned) != A->nel || sem::lp_plan(opts->learned) != gs)
             return bail(sem::fail(ctx, SEM_EINVAL, "sem_cg_setup: the network is not bound to this operator and plan"));
@@ -988,7 +1002,7 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
         CG_ALLOC(L64.r, u64); CG_ALLOC(L64.p, u64); CG_ALLOC(L64.minv, u64);
         L64.x = cg->x64;
         L64.wl = cg->wl64;
-        if (cg->lp) { CG_ALLOC(L64.z, u64); CG_ALLOC(L64.wu, u64); }
+        if (flexible(cg)) { CG_ALLOC(L64.z, u64); CG_ALLOC(L64.wu, u64); }
         CG_ALLOC(cg->d64, u64);
         assembled_recip_kernel<double><<<gu, kBlock, 0, st>>>((double*)L64.minv, cg->wl64, gs->uoff, gs->uidx, nu);
     } else {
@@ -998,7 +1012,7 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
         CG_ALLOC(L.x, u32); CG_ALLOC(L.r, u32); CG_ALLOC(L.p, u32); CG_ALLOC(L.minv, u32);
         CG_ALLOC(L.wl, sizeof(float) * n);
         CG_ALLOC(cg->rhs32, u32);
-        if (cg->lp) { CG_ALLOC(L.z, u32); CG_ALLOC(L.wu, u32); }
+        if (flexible(cg)) { CG_ALLOC(L.z, u32); CG_ALLOC(L.wu, u32); }
         assembled_recip_kernel<float><<<gu, kBlock, 0, st>>>((float*)L.minv, cg->wl64, gs->uoff, gs->uidx, nu);
         const int l2 = A->lx * A->lx;
         for (int q = 0; q < 6; ++q) {
@@ -1064,7 +1078,7 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
     if (opts->precision != cg->precision)
         return sem::fail(ctx, SEM_EINVAL, "sem_cg_solve: precision %d differs from set-up (%d)",
                          opts->precision, cg->precision);
-    if (opts->learned != cg->lp)
+    if (opts->learned != cg->lp || opts->mg != cg->mg)
         return sem::fail(ctx, SEM_EINVAL, "sem_cg_solve: preconditioner differs from set-up");
     if (opts->ir_mode != 0 && opts->ir_mode != 1)
         return sem::fail(ctx, SEM_EINVAL, "sem_cg_solve: bad ir_mode %d", opts->ir_mode);
@@ -1090,7 +1104,7 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
     if (cg->precision == SEM_SOLVE_F64) {
         Level& L = cg->lv64;
         int its = 0, brk = 0, nj = 0, fb = 0;
-        if (cg->lp) rc = fcg_run<double>(cg, L, cg->b64, opts->tol, maxit, check, &its, &brk, &nj, &fb);
+        if (flexible(cg)) rc = fcg_run<double>(cg, L, cg->b64, opts->tol, maxit, check, &its, &brk, &nj, &fb);
         else rc = pcg_run<double>(cg, L, cg->b64, opts->tol, maxit, check, &its, &brk);
         if (rc) return rc;
         // The Krylov loop stops on its recursively updated residual, which can
@@ -1112,7 +1126,7 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
             const double tol_d = opts->tol * bnorm / rnorm;
             int its_d = 0, brk_d = 0, nj_d = 0, fb_d = 0;
             L.x = cg->d64;                       // the correction goes to d64, x64 is kept
-            if (cg->lp) rc = fcg_run<double>(cg, L, cg->r64, tol_d, maxit - its, check, &its_d, &brk_d, &nj_d, &fb_d);
+            if (flexible(cg)) rc = fcg_run<double>(cg, L, cg->r64, tol_d, maxit - its, check, &its_d, &brk_d, &nj_d, &fb_d);
             else rc = pcg_run<double>(cg, L, cg->r64, tol_d, maxit - its, check, &its_d, &brk_d);
             L.x = cg->x64;
             if (rc) return rc;
@@ -1164,7 +1178,7 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
             if (rel <= opts->tol || total >= maxit) break;
             ir_scale_kernel<<<gu, kBlock, 0, st>>>(cg->rhs32, cg->r64, cg->sums, inv_nu, nu);
             int its = 0, brk = 0, nj = 0, fb = 0;
-            if (cg->lp)
+            if (flexible(cg))
                 rc = fcg_run<float>(cg, L, cg->rhs32, itol, std::min(imax, maxit - total), check,
                                     &its, &brk, &nj, &fb);
             else
@@ -1225,3 +1239,4 @@ extern "C" int sem_remove_mean(sem_gs_t gs, double* x) {
     SEM_LAUNCH_CHECK(ctx);
     return SEM_OK;
 }
+

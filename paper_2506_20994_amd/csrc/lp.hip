@@ -652,6 +652,16 @@ unsigned grid_of(int64_t n, int64_t cap = 4096) {
 
 }  // namespace
 
+namespace {
+
+// u[L] = 1 where ids[L] == g, else 0
+__global__ void unit_id_kernel(double* __restrict__ u, const int64_t* __restrict__ ids, int64_t g, int64_t n) {
+    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n; L += (int64_t)gridDim.x * blockDim.x)
+        u[L] = ids[L] == g ? 1.0 : 0.0;
+}
+
+}  // namespace
+
 struct sem_lp_s {
     sem_ctx_t ctx = nullptr;
     int64_t max_rows = 0;
@@ -676,6 +686,7 @@ struct sem_lp_s {
     float *geo = nullptr, *kappa = nullptr, *kappa_inv = nullptr;
     bool bound = false;
     sem_gs_t gs = nullptr;
+    sem::AxArgs A64{};        // the bound operator (float64 arrays of the caller)
     const int* skip = nullptr;   // set by the solver: kernels return when *skip != 0
     // energy-norm loss: metric K (512 x 512, bf16) and work arrays
     u16* K = nullptr;
@@ -1007,6 +1018,15 @@ extern "C" int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs) {
     lp->nel = A->nel;
     lp->gs = gs;
     lp->bound = true;
+    lp->A64 = sem::AxArgs{};
+    {
+        const double* Dp[6] = {A->dx, A->dy, A->dz, A->dxt, A->dyt, A->dzt};
+        const double* Gp[6] = {A->g11, A->g22, A->g33, A->g12, A->g13, A->g23};
+        for (int q = 0; q < 6; ++q) { lp->A64.D[q] = Dp[q]; lp->A64.G[q] = Gp[q]; }
+    }
+    lp->A64.h1 = A->h1;
+    lp->A64.nel = A->nel;
+    lp->A64.lx = A->lx;
     geo_kernel<<<(unsigned)A->nel, 64, 0, ctx->stream>>>(lp->geo, lp->kappa, lp->kappa_inv, A->h1, A->g11, A->g22, A->g33,
                                                          A->g12, A->g13, A->g23, A->nel);
     SEM_LAUNCH_CHECK(ctx);
@@ -1065,6 +1085,129 @@ extern "C" int sem_lp_samples(sem_lp_t lp, const double* r, const double* err, c
                                                                       elems, count, row0, nullptr, nullptr,
                                                                       nullptr, nullptr);
     SEM_LAUNCH_CHECK(ctx);
+    return SEM_OK;
+}
+
+namespace {
+
+// r = b - r (r holds the assembled A x), err = xstar - x
+__global__ void pair_kernel(double* __restrict__ r, double* __restrict__ err, const double* __restrict__ b,
+                            const double* __restrict__ x, const double* __restrict__ xstar, int64_t n) {
+    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n; L += (int64_t)gridDim.x * blockDim.x) {
+        r[L] = b[L] - r[L];
+        err[L] = xstar[L] - x[L];
+    }
+}
+
+}  // namespace
+
+extern "C" int sem_lp_snapshot(sem_lp_t lp, const double* x, const double* xstar, const double* b,
+                               double* r_out, double* err_out, const int64_t* elems, int64_t count,
+                               uint16_t* X, float* T, int64_t row0) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_snapshot: null network");
+    sem_ctx_t ctx = lp->ctx;
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (!lp->bound) return sem::fail(ctx, SEM_EINVAL, "sem_lp_snapshot: bind an operator first");
+    if (!x || !xstar || !b || !r_out || !err_out || !X || !T || !elems || count < 0 || row0 < 0)
+        return sem::fail(ctx, SEM_EINVAL, "sem_lp_snapshot: bad argument");
+    const double* outs[2] = {r_out, err_out};
+    const double* ins[3] = {x, xstar, b};
+    for (const double* o : outs)
+        for (const double* i : ins)
+            if (o == i) return sem::fail(ctx, SEM_EINVAL, "sem_lp_snapshot: an output aliases an input");
+    if (r_out == err_out) return sem::fail(ctx, SEM_EINVAL, "sem_lp_snapshot: r_out aliases err_out");
+    const int64_t n = lp->gs->n_local;
+    rc = sem::launch_ax(ctx, sem::AxKind::F64, lp->A64, r_out, x, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    rc = sem::gs_launch(lp->gs, r_out, SEM_F64, nullptr);
+    if (rc) return rc;
+    pair_kernel<<<grid_of(n, 8192), kBlock, 0, ctx->stream>>>(r_out, err_out, b, x, xstar, n);
+    SEM_LAUNCH_CHECK(ctx);
+    return sem_lp_samples(lp, r_out, err_out, elems, count, X, T, row0);
+}
+
+extern "C" int sem_lp_reference_block(sem_ctx_t ctx, int lx, double* W) {
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (!sem::lx_ok(lx)) return sem::fail(ctx, SEM_EUNSUPPORTED_LX, "sem_lp_reference_block: lx=%d", lx);
+    if (!W) return sem::fail(ctx, SEM_EINVAL, "sem_lp_reference_block: null output");
+    const int n = 3, ecen = 13;                     // the centre element of the undeformed periodic 3^3 box
+    const int nel = n * n * n, l2 = lx * lx, nloc = l2 * lx;
+    const int64_t nl = (int64_t)nel * nloc;
+    hipStream_t st = ctx->stream;
+    std::vector<void*> tmp;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);
+        for (void* p : tmp) (void)hipFree(p);
+    };
+    auto alloc = [&](void** p, size_t bytes) -> int {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) return sem::check_hip(ctx, e, "sem_lp_reference_block: hipMalloc");
+        tmp.push_back(*p);
+        return SEM_OK;
+    };
+#define RB_TRY(call) do { int rc_ = (call); if (rc_) { cleanup(); return rc_; } } while (0)
+    double *x, *y, *z, *u, *w, *cols, *Dd;
+    double* G[6];
+    int64_t* ids;
+    RB_TRY(alloc((void**)&x, 8 * nl));
+    RB_TRY(alloc((void**)&y, 8 * nl));
+    RB_TRY(alloc((void**)&z, 8 * nl));
+    RB_TRY(alloc((void**)&u, 8 * nl));
+    RB_TRY(alloc((void**)&w, 8 * nl));
+    RB_TRY(alloc((void**)&cols, 8 * (size_t)nloc * nloc));
+    RB_TRY(alloc((void**)&Dd, 8 * 2 * (size_t)l2));
+    RB_TRY(alloc((void**)&ids, 8 * nl));
+    for (int a = 0; a < 6; ++a) RB_TRY(alloc((void**)&G[a], 8 * nl));
+    RB_TRY(sem_box_mesh(ctx, n, lx, 0.0, x, y, z, ids));
+    RB_TRY(sem_geometry(ctx, x, y, z, nel, lx, G[0], G[1], G[2], G[3], G[4], G[5], nullptr, nullptr));
+    std::vector<int64_t> hids(nl);
+    RB_TRY(sem::check_hip(ctx, hipStreamSynchronize(st), "sem_lp_reference_block: sync"));
+    RB_TRY(sem::check_hip(ctx, hipMemcpy(hids.data(), ids, 8 * nl, hipMemcpyDeviceToHost), "hipMemcpy"));
+    sem_gs_t gs = nullptr;
+    RB_TRY(sem_gs_setup(ctx, hids.data(), nl, &gs));
+    std::vector<double> dx(l2), dxt(l2);
+    sem_gll(lx, nullptr, nullptr, dx.data(), dxt.data());
+    RB_TRY(sem::check_hip(ctx, hipMemcpy(Dd, dx.data(), 8 * l2, hipMemcpyHostToDevice), "hipMemcpy"));
+    RB_TRY(sem::check_hip(ctx, hipMemcpy(Dd + l2, dxt.data(), 8 * l2, hipMemcpyHostToDevice), "hipMemcpy"));
+    sem::AxArgs a{};
+    for (int q = 0; q < 3; ++q) { a.D[q] = Dd; a.D[3 + q] = Dd + l2; }
+    for (int q = 0; q < 6; ++q) a.G[q] = G[q];
+    a.nel = nel;
+    a.lx = lx;
+    // column j: A_G applied to the unit vector of the centre element's node j
+    // (every local copy set), read back on the centre element
+    for (int j = 0; j < nloc; ++j) {
+        unit_id_kernel<<<grid_of(nl, 8192), kBlock, 0, st>>>(u, ids, hids[(int64_t)ecen * nloc + j], nl);
+        rc = sem::launch_ax(ctx, sem::AxKind::F64, a, w, u, nullptr, nullptr, nullptr);
+        if (!rc) rc = sem::gs_launch(gs, w, SEM_F64, nullptr);
+        if (rc) { sem_gs_destroy(gs); cleanup(); return rc; }
+        rc = sem::check_hip(ctx, hipMemcpyAsync(cols + (size_t)j * nloc, w + (int64_t)ecen * nloc, 8 * (size_t)nloc,
+                                                hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+        if (rc) { sem_gs_destroy(gs); cleanup(); return rc; }
+    }
+    sem_gs_destroy(gs);
+    std::vector<double> A((size_t)nloc * nloc), g(3 * (size_t)nloc);
+    RB_TRY(sem::check_hip(ctx, hipStreamSynchronize(st), "sem_lp_reference_block: sync"));
+    RB_TRY(sem::check_hip(ctx, hipMemcpy(A.data(), cols, 8 * (size_t)nloc * nloc, hipMemcpyDeviceToHost), "hipMemcpy"));
+    for (int q = 0; q < 3; ++q)
+        RB_TRY(sem::check_hip(ctx, hipMemcpy(g.data() + (size_t)q * nloc, G[q] + (int64_t)ecen * nloc, 8 * (size_t)nloc,
+                                             hipMemcpyDeviceToHost), "hipMemcpy"));
+    cleanup();
+#undef RB_TRY
+    // A is stored by columns; it is symmetric up to rounding: symmetrise
+    for (int i = 0; i < nloc; ++i)
+        for (int j = i + 1; j < nloc; ++j) {
+            const double v = 0.5 * (A[(size_t)i * nloc + j] + A[(size_t)j * nloc + i]);
+            A[(size_t)i * nloc + j] = A[(size_t)j * nloc + i] = v;
+        }
+    double kappa = 0.0;
+    for (int L = 0; L < nloc; ++L) kappa += g[L] + g[nloc + L] + g[2 * nloc + L];
+    kappa /= 3.0 * nloc;
+    if (!sem::spd_inverse(A, nloc))
+        return sem::fail(ctx, SEM_EBREAKDOWN, "sem_lp_reference_block: element matrix not positive definite");
+    for (size_t q = 0; q < A.size(); ++q) W[q] = kappa * A[q];
     return SEM_OK;
 }
 

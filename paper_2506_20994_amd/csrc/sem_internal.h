@@ -5,6 +5,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "sem.h"
 
@@ -93,7 +94,41 @@ int lp_apply_partial(sem_lp_t lp, const void* r, bool f64, const int* skip, cons
 int64_t lp_rows(sem_lp_t lp);
 sem_gs_t lp_plan(sem_lp_t lp);
 
+// multigrid preconditioner (mg.hip): z = V(r) on unique-node vectors of its
+// finest level's plan, float64 (f64) or float32; kernels return at once when
+// skip && *skip
+int mg_apply(sem_mg_t mg, void* z, const void* r, bool f64, const int* skip);
+sem_gs_t mg_plan(sem_mg_t mg);
+int64_t mg_nel(sem_mg_t mg);
+// inverse of a symmetric positive definite matrix (row-major n x n, float64,
+// in place) by Cholesky factorisation; false if a pivot is not positive
+bool spd_inverse(std::vector<double>& A, int n);
+// the six factors of an element-local operator packed for the solver form
+// (the layout of AxArgs::Gp) in float32; n local nodes, asynchronous on st
+void pack_factors_f32(hipStream_t st, float* out, const double* const* G, int64_t n, int lx);
+
 #ifdef __HIPCC__
+// sum of the local copies of unique node u of a field in the local layout:
+// wl[uidx[q]] for q in [uoff[u], uoff[u+1]), the first eight by independent
+// predicated loads (issued together), summed in CSR order
+template <typename T>
+__device__ __forceinline__ T assemble_local(const T* __restrict__ wl, const int32_t* __restrict__ uoff,
+                                            const int32_t* __restrict__ uidx, int64_t u) {
+    const int32_t b = uoff[u], e = uoff[u + 1];
+    int32_t L[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) L[q] = b + q < e ? uidx[b + q] : -1;
+    T v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = L[q] >= 0 ? wl[L[q]] : T(0);
+    T s = v[0];
+#pragma unroll
+    for (int q = 1; q < 8; ++q)
+        if (b + q < e) s += v[q];
+    for (int32_t q = b + 8; q < e; ++q) s += wl[uidx[q]];
+    return s;
+}
+
 // Workgroup order for L2 locality: the hardware hands consecutive workgroups
 // to the eight XCDs (each with its own L2) in turn.  With a grid of G
 // workgroups, G a multiple of 8, logical block (b mod 8) G/8 + b/8 gives each

@@ -29,13 +29,6 @@ from . import _binding as B
 from .box import BoxOperator
 
 
-def _residual(op, x, b, out):
-    """out = b - gs(Ax(x))"""
-    op.apply(out, x)
-    torch.sub(b, out, out=out)
-    return out
-
-
 def generate(ctx, lp, n=16, boxes=16, snapshots=16, elems_per_snapshot=64, seed=100,
              amp_range=(0.0, 0.2), min_rel_detj=0.05, rhs="fourier", include_zero=False,
              verbose=False, dirichlet=False):
@@ -80,16 +73,15 @@ def generate(ctx, lp, n=16, boxes=16, snapshots=16, elems_per_snapshot=64, seed=
         op.bind(lp)
         xk = torch.empty_like(b)
         rk = torch.empty_like(b)
+        ek = torch.empty_like(b)
         for q, kq in enumerate(its):
             if kq == 0:
                 xk.zero_()
             else:
                 B.sem_cg_solve(cg, xk, b, tol=1e-12, maxit=int(kq), check_every=int(min(kq, 16)))
-            _residual(op, xk, b, rk)
-            err = xs - xk
             els = torch.from_numpy(synth.choice(seed + 30_000 + box * 1000 + q, nel,
                                                 elems_per_snapshot)).cuda()
-            B.sem_lp_samples(lp, rk, err, els, X, T, row)
+            B.sem_lp_snapshot(lp, xk, xs, b, rk, ek, els, X, T, row)   # r = b - A x_k, e = x* - x_k
             row += elems_per_snapshot
         cg.close()
         op.gs.close()
@@ -142,26 +134,7 @@ def init_network(lp, seed=7, mu=None, jacobi_base=None, out_scale=1.0, linear=No
 def reference_block(ctx, lx=8):
     """The classical counterpart of the learned block: kappa times the inverse
     of the assembled operator restricted to the nodes of one element (the local
-    solve of one-level additive Schwarz with minimal overlap), on an undeformed
-    periodic 3^3 box, where every element sees the same matrix.  The columns
-    come from the library's operator and gather-scatter applied to unit
-    vectors; the 512 x 512 inverse is taken on the host.  Returns float64."""
-    n, e = 3, 13                                   # the centre element
-    op = BoxOperator(ctx, n, lx, 0.0, keep_coords=False)
-    nloc = lx ** 3
-    ids = op.ids[e].reshape(-1).cpu().numpy()
-    A = np.empty((nloc, nloc))
-    u = torch.zeros((op.nel, lx, lx, lx), dtype=torch.float64, device=op.ids.device)
-    w = torch.empty_like(u)
-    uu = np.zeros(op.n_unique)
-    for j in range(nloc):
-        uu[ids[j]] = 1.0
-        u = op.scatter(uu)
-        uu[ids[j]] = 0.0
-        op.apply(w, u)
-        A[:, j] = w[e].reshape(-1).cpu().numpy()
-    g = [t[e].reshape(-1).cpu().numpy() for t in op.G[:3]]
-    kappa = float(np.mean(g[0] + g[1] + g[2]) / 3.0)
-    op.gs.close()
-    A = 0.5 * (A + A.T)
-    return kappa * np.linalg.inv(A)
+    solve of one-level additive Schwarz with minimal overlap) of an undeformed
+    periodic box, computed by the library (sem_lp_reference_block).  Returns
+    float64 (lx^3, lx^3)."""
+    return B.sem_lp_reference_block(ctx, lx)

@@ -643,3 +643,48 @@ def test_reference_block_preconditioner(sem_ctx):
         h.close()
     op.gs.close()
 
+
+def test_reference_block_matches_oracle(sem_ctx):
+    """sem_lp_reference_block against the oracle: kappa times the inverse of
+    the principal submatrix of the assembled operator of the undeformed
+    periodic 3^3 box on the centre element's nodes (lx = 4 and 8)."""
+    from oracle.assemble import assembled_matrix
+    for lx in (4, 8):
+        ref = BoxProblem(3, lx, 0.0)
+        A = assembled_matrix(ref.Dh, None, ref.G, ref.ids, ref.nu).toarray()
+        g = ref.ids[13].ravel()
+        Ae = A[np.ix_(g, g)]
+        kappa = np.mean(ref.G[0][13] + ref.G[1][13] + ref.G[2][13]) / 3.0
+        Wref = kappa * np.linalg.inv(Ae)
+        W = P.sem_lp_reference_block(sem_ctx, lx)
+        assert np.max(np.abs(W - Wref)) <= 1e-9 * np.max(np.abs(Wref)), lx
+    with pytest.raises(P.SemError):
+        P.sem_lp_reference_block(sem_ctx, 13)
+
+
+def test_snapshot_pairs(sem_ctx):
+    """sem_lp_snapshot forms r = b - gs(A x) (against the oracle's assembled
+    operator) and err = x* - x (exactly) on the device, and writes the same
+    rows as sem_lp_samples on those fields."""
+    n, amp = 2, 0.1
+    op, lp = _box_with_lp(sem_ctx, n, amp)
+    ref = BoxProblem(n, 8, amp)
+    xG, sG, bG = (synth.unique_normal(ref.nu, s) for s in (80, 81, 82))
+    x, xs, b = op.scatter(xG), op.scatter(sG), op.scatter(bG)
+    r, e = torch.empty_like(x), torch.empty_like(x)
+    els = torch.tensor([5, 1, 6], dtype=torch.int64, device="cuda")
+    X = torch.zeros((3, 528), dtype=torch.bfloat16, device="cuda")
+    T = torch.zeros((3, 512), dtype=torch.float32, device="cuda")
+    P.sem_lp_snapshot(lp, x, xs, b, r, e, els, X, T, 0)
+    torch.cuda.synchronize()
+    rref = (bG - ref.apply(xG))[ref.ids]
+    assert np.max(np.abs(r.cpu().numpy() - rref)) <= 1e-12 * np.max(np.abs(rref))
+    assert torch.equal(e, xs - x)
+    X2, T2 = torch.zeros_like(X), torch.zeros_like(T)
+    P.sem_lp_samples(lp, r, e, els, X2, T2, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(X, X2) and torch.equal(T, T2)
+    with pytest.raises(P.SemError):
+        P.sem_lp_snapshot(lp, x, xs, b, x, e, els, X, T, 0)          # r_out aliases x
+    lp.close()
+    op.gs.close()
