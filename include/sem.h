@@ -212,6 +212,20 @@ int sem_gs_owner(sem_gs_t gs, double* wgt);
  * Poisson problem).  Device float64, n_local.  Asynchronous.  A plan with
  * Dirichlet nodes has no such null space: SEM_EINVAL. */
 int sem_remove_mean(sem_gs_t gs, double* x);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation as sem_remove_mean, same arguments, rules and result, with its
+ * reduction partials in a fixed file-scope device array of the library
+ * (8194 float64 slots, 64 KiB per GPU, held until the process ends) instead of
+ * the context's workspace.  It calls no hipMalloc, hipFree or other allocating
+ * routine; the first call on a device looks up that device's copy of the
+ * array (hipGetSymbolAddress).  A plan whose reduction would need more than
+ * the array's partial slots is refused with SEM_EINVAL (never the case for
+ * plans sem_gs_setup accepts: the reduction grid is capped at 8192 blocks).
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (different streams or host threads) race and give wrong means; calls
+ * serialised on one stream are safe.  Asynchronous. */
+int sem_remove_mean_static(sem_gs_t gs, double* x);
 
 /* ------------------------------------------------------------------ solver */
 

@@ -11,7 +11,7 @@ __all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONV
            "sem_sync", "sem_gll", "sem_box_mesh", "sem_box_mesh_dirichlet", "sem_geometry", "sem_scatter",
            "sem_ax_diag", "sem_fourier", "sem_convert", "sem_ax", "sem_ax_helmholtz", "sem_gs_setup",
            "sem_gs_destroy", "sem_gs_info", "sem_gs_dirichlet_count", "sem_gs", "sem_gs_mult", "Context", "GsPlan",
-           "dtype_code", "EXPORTS", "sem_gs_owner", "sem_remove_mean", "sem_cg_setup",
+           "dtype_code", "EXPORTS", "sem_gs_owner", "sem_remove_mean", "sem_remove_mean_static", "sem_cg_setup",
            "sem_cg_destroy", "sem_cg_solve", "SemOperator", "SemSolveOpts", "SemSolveStats",
            "CgSolver", "SEM_SOLVE_F64", "SEM_SOLVE_F32_IR", "SEM_SOLVE_BF16_IR",
            "LearnedPrecond", "sem_lp_create", "sem_lp_destroy", "sem_lp_set", "sem_lp_get",
@@ -100,6 +100,7 @@ EXPORTS = {
     "sem_gs_mult": (_int, [_vp, _vp]),
     "sem_gs_owner": (_int, [_vp, _vp]),
     "sem_remove_mean": (_int, [_vp, _vp]),
+    "sem_remove_mean_static": (_int, [_vp, _vp]),
     "sem_cg_setup": (_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
     "sem_cg_destroy": (_int, [_vp]),
     "sem_cg_solve": (_int, [_vp, _vp, _vp, _vp, _vp]),
@@ -375,6 +376,11 @@ def sem_gs_owner(gs, wgt):
 def sem_remove_mean(gs, x):
     gs.ctx.bind()
     _check(lib().sem_remove_mean(gs.handle, _ptr(x)), gs.ctx.handle)
+
+
+def sem_remove_mean_static(gs, x):
+    gs.ctx.bind()
+    _check(lib().sem_remove_mean_static(gs.handle, _ptr(x)), gs.ctx.handle)
 
 
 class CgSolver:

@@ -21,6 +21,7 @@
 // number of partials and a fixed summation order: results are bitwise
 // reproducible.
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "sem_internal.h"
@@ -1240,3 +1241,60 @@ extern "C" int sem_remove_mean(sem_gs_t gs, double* x) {
     return SEM_OK;
 }
 
+// ----------------------------------------------------------------------------
+// sem_remove_mean_static: sem_remove_mean with its reduction partials in a
+// fixed device array instead of the context's workspace, for callers that
+// cannot allocate.  Each GPU holds its own copy of `scratch` at its own
+// address; host code never passes the array's name to a kernel, only the
+// address that hipGetSymbolAddress returned for the current device.
+namespace {
+
+constexpr int kScratchSlots = 2 + kGrid;   // the mean, a spare slot, one partial per workgroup
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchSlots];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on device dev (made current by the caller)
+int scratch_address(sem_ctx_t ctx, int dev, double** out) {
+    if (dev < 0 || dev >= kMaxDevices)
+        return sem::fail(ctx, SEM_EINVAL, "sem_remove_mean_static: device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return sem::check_hip(ctx, e, "sem_remove_mean_static: hipGetSymbolAddress");
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SEM_OK;
+}
+
+}  // namespace
+
+extern "C" int sem_remove_mean_static(sem_gs_t gs, double* x) {
+    if (!gs) return sem::fail(nullptr, SEM_EINVAL, "sem_remove_mean_static: null plan");
+    sem_ctx_t ctx = gs->ctx;
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (gs->n_masked > 0)
+        return sem::fail(ctx, SEM_EINVAL, "sem_remove_mean_static: the plan has Dirichlet nodes (no null space)");
+    if (gs->n_local == 0) return SEM_OK;
+    if (!x) return sem::fail(ctx, SEM_EINVAL, "sem_remove_mean_static: null field");
+    const int64_t n = gs->n_local;
+    const unsigned g = vec_grid(n);
+    if (2 + (int64_t)g > kScratchSlots)
+        return sem::fail(ctx, SEM_EINVAL, "sem_remove_mean_static: %u partials exceed the %d-slot scratch array",
+                         g, kScratchSlots);
+    double* sp = nullptr;
+    rc = scratch_address(ctx, ctx->device, &sp);
+    if (rc) return rc;
+    hipStream_t st = ctx->stream;
+    // every partial and the mean are written before they are read: nothing to clear
+    wsum_kernel<<<g, kBlock, 0, st>>>(x, gs->owner, n, sp + 2);
+    wsum_final<<<1, kFinal, 0, st>>>(sp, sp + 2, (int)g);
+    sub_mean_kernel<<<g, kBlock, 0, st>>>(x, sp, (double)gs->n_unique, n);
+    SEM_LAUNCH_CHECK(ctx);
+    return SEM_OK;
+}
