@@ -197,7 +197,7 @@ def solve_comparison(ctx, P, n, lx, amp, tol=1e-10):
         cg.close()
     # the multigrid V-cycle (classical coarse-space preconditioner) in flexible CG
     t0 = time.perf_counter()
-    mg = op.multigrid()
+    mg = op.multigrid(n_coarse=8)
     torch.cuda.synchronize()
     res["mg_setup_s"] = round(time.perf_counter() - t0, 3)
     res["mg_levels"] = [list(P.sem_mg_level_info(mg, q)) for q in range(P.sem_mg_levels(mg))]
@@ -216,7 +216,7 @@ def solve_comparison(ctx, P, n, lx, amp, tol=1e-10):
     op16 = BoxOperator(ctx, n // 2, lx, amp)
     b16 = op16.fourier_rhs(k, a, ph)
     x16 = torch.empty_like(b16)
-    mg16 = op16.multigrid()
+    mg16 = op16.multigrid(n_coarse=8)
     growth = {}
     for name, code, mode, m in (("fp64_pcg", P.SEM_SOLVE_F64, 0, None), ("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1, mg16)):
         _, st = _timed_solve(P, op16, x16, b16, code, mode, None, tol, mg=m)
@@ -267,7 +267,7 @@ def dirichlet_comparison(ctx, P, n, lx, amp, lp=None, tol=1e-10):
         variants.append(("learned_f32_rr", P.SEM_SOLVE_F32_IR, 1, lp))
     if blk is not None:
         variants.append(("classical_block_f32_rr", P.SEM_SOLVE_F32_IR, 1, blk))
-    mg = op.multigrid()
+    mg = op.multigrid(n_coarse=8)
     variants.append(("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1, mg))
     for name, code, mode, net in variants:
         if net is mg:
@@ -315,7 +315,7 @@ def helmholtz_solve_comparison(ctx, P, n, lx, amp, h2=1e3, tol=1e-10):
     variants = [("fp64_pcg", P.SEM_SOLVE_F64, 0, None), ("f32_rr", P.SEM_SOLVE_F32_IR, 1, None)]
     if blk is not None:
         variants.append(("classical_block_f32_rr", P.SEM_SOLVE_F32_IR, 1, blk))
-    mg = op.multigrid(h2=h2)
+    mg = op.multigrid(h2=h2, n_coarse=8)
     variants.append(("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1, mg))
     for name, code, mode, net in variants:
         if net is mg:
@@ -468,6 +468,55 @@ def trials_run(P, n, lx, amp, trials=5, reps=200):
             "frac_of_measured_copy": round(med / statistics.median(copy_gbs), 4)}
 
 
+def mg_run(ctx, P, n, lx, amp, tol=1e-10, sweep=False, repeat=3):
+    """--mode mg: the multigrid-preconditioned solves of the n^3 box (periodic,
+    32 Fourier modes) -- flexible CG in float64 and inside float32 residual
+    replacement -- each solved `repeat` times after one warm-up; with --sweep
+    over the Chebyshev degree, the interval's lower end and the coarsest
+    h-level.  One JSON line."""
+    import torch
+    import synth
+    from paper_2506_20994_amd.box import BoxOperator
+    op = BoxOperator(ctx, n, lx, amp)
+    k, a, ph = synth.fourier_modes(2)
+    b = op.fourier_rhs(k, a, ph)
+    x = torch.empty_like(b)
+    grid = [dict(n_coarse=8)]
+    if sweep:
+        grid = [dict(degree=d, lo=lo, n_coarse=8, graphs=gr) for d in (2, 3, 4) for lo in (0.15, 0.2)
+                for gr in (0, 1)]
+    out = []
+    for cfg in grid:
+        t0 = time.perf_counter()
+        mg = op.multigrid(**{k2: v for k2, v in cfg.items() if k2 != "graphs"})
+        P.sem_mg_set_graphs(mg, cfg.get("graphs", 1))
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        row = dict(cfg, setup_s=round(setup, 3), levels=P.sem_mg_levels(mg))
+        for name, code, mode in (("mg_fcg_f64", P.SEM_SOLVE_F64, 0), ("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1)):
+            cg = op.solver(code, mg=mg)
+            kw = dict(tol=tol, precision=code, ir_mode=mode, mg=mg, maxit=5000)
+            P.sem_cg_solve(cg, x, b, **kw)
+            ms = []
+            for _ in range(repeat):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc, st = P.sem_cg_solve(cg, x, b, **kw)
+                torch.cuda.synchronize()
+                ms.append((time.perf_counter() - t0) * 1e3)
+            cg.close()
+            row[name] = {"ms_min": round(min(ms), 2), "ms": [round(v, 2) for v in ms],
+                         "iterations": st["iterations"], "relres": st["relres"], "converged": st["converged"]}
+        print(f"[bench] mg {cfg}: f64 {row['mg_fcg_f64']['ms_min']} ms {row['mg_fcg_f64']['iterations']} its; "
+              f"f32 {row['mg_f32_rr']['ms_min']} ms {row['mg_f32_rr']['iterations']} its",
+              file=sys.stderr, flush=True)
+        out.append(row)
+        mg.close()
+    op.gs.close()
+    return {"mode": "mg", "workload": f"{n}^3 periodic box lx={lx} amplitude {amp}, 32 Fourier modes, tol {tol}",
+            "runs": out}
+
+
 def scale_run(ctx, P, n=64, amp=0.15, tol=1e-10):
     """The full stack at scale (--mode scale): a 64^3 box (E = 262144) with
     amplitude 0.15 at lx = 8 (134M local nodes) and lx = 10 (262M): operator
@@ -548,7 +597,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-helmholtz", action="store_true",
                     help="skip the Helmholtz timing (it launches the same kernel as sem_ax)")
-    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "scale", "trials"])
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "scale", "trials", "mg"])
+    ap.add_argument("--sweep", action="store_true", help="--mode mg: sweep the V-cycle's parameters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this library runs on one GPU; --gpus {args.gpus} is not supported",
@@ -572,6 +622,11 @@ def main():
         return
     if args.mode == "trials":
         print(json.dumps(trials_run(P, args.n, args.lx, args.amp)), flush=True)
+        return
+    if args.mode == "mg":
+        ctx = P.sem_create()
+        print(json.dumps(mg_run(ctx, P, args.n, args.lx, args.amp, sweep=args.sweep)), flush=True)
+        ctx.close()
         return
     if args.mode == "scale":
         ctx = P.sem_create()

@@ -260,7 +260,7 @@ typedef struct {
     double inner_tol;    /* IR: inner relative residual target (0: 1e-6 F32, 1e-2 BF16) */
     int inner_maxit;     /* IR: iterations per inner solve (0: 500) */
     int max_outer;       /* IR: outer refinement steps (0: 60) */
-    int check_every;     /* iterations between host convergence checks (0: 16) */
+    int check_every;     /* iterations between host convergence checks (0: 16; 4 with mg) */
     sem_lp_t learned;    /* NULL: Jacobi-PCG.  Otherwise flexible CG (Notay's FCG(1))
                             preconditioned by this network, bound to the same operator
                             (sem_lp_bind), with the Jacobi fallback described below */
@@ -271,7 +271,7 @@ typedef struct {
                             accumulated update is added to the float64 x, each time its
                             residual has fallen by the factor `delta`; the search
                             direction is kept */
-    double delta;        /* ir_mode 1: replacement trigger (0: 0.1) */
+    double delta;        /* ir_mode 1: replacement trigger (0: 0.1; 1e-3 with mg) */
     sem_mg_t mg;         /* NULL: none.  Otherwise flexible CG preconditioned by this
                             multigrid V-cycle (sem_mg_create on the same operator and
                             plan); not together with `learned` */
@@ -333,7 +333,8 @@ int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_solve_opts_t
  * evaluated at the fine level's nodes (the coarse Lagrange basis on the same
  * element; the parent's trilinear basis); restriction by its transpose.
  * Smoothing: `degree` steps of the Chebyshev semi-iteration in D^-1 A (D the
- * assembled diagonal) on [lo lmax, hi lmax], lmax of every level estimated by
+ * assembled diagonal) on [lo lmax, hi lmax] (defaults 3, 0.2, 1.1: the fastest
+ * 32^3 lx = 8 solve of a sweep over degree 1-3 and lo 0.2-0.3), lmax of every level estimated by
  * `lanczos_steps` Lanczos steps at creation.  The coarsest level is solved
  * with a dense inverse (at most 2048 unknowns; of A + c 1 1^T on the singular
  * periodic box, c = mean diagonal / unknowns).  V(b): pre-smoothing from 0,
@@ -344,8 +345,8 @@ typedef struct {
     double amp;          /* the box's deformation amplitude (sem_box_mesh) */
     int dirichlet;       /* 1: the Dirichlet box (its plan has Dirichlet nodes), 0: periodic */
     double h2;           /* Helmholtz coefficient (> 0 exactly when A->h2b is set; 0: Poisson) */
-    int degree;          /* Chebyshev steps per smoothing (0: 2) */
-    double lo, hi;       /* smoothing interval in units of lmax (0: 0.3 and 1.1) */
+    int degree;          /* Chebyshev steps per smoothing (0: 3) */
+    double lo, hi;       /* smoothing interval in units of lmax (0: 0.2 and 1.1) */
     int n_coarse;        /* h-coarsening keeps n >= n_coarse (0: 2) */
     int lanczos_steps;   /* Lanczos steps per level for lmax (0: 20) */
 } sem_mg_opts_t;
@@ -366,6 +367,13 @@ int sem_mg_levels(sem_mg_t mg, int* count);
 int sem_mg_level_info(sem_mg_t mg, int level, int* n, int* lx, int64_t* n_unique, double* lmax);
 /* Replace the lmax of a smoothed level (every level but the coarsest). */
 int sem_mg_set_lmax(sem_mg_t mg, int level, double lmax);
+/* Launch mode of the V-cycle (default on): replay it as a HIP graph captured
+ * on first use for each set of (z, r) pointers (the V-cycle's pointers and
+ * the sequence of its launches are fixed), or launch its kernels one by one
+ * (off).  Both give the same result bit for bit.  Graphs are kept until
+ * sem_mg_destroy; a graph captured for pointers whose memory is later freed
+ * is never replayed unless the same pointers are passed again. */
+int sem_mg_set_graphs(sem_mg_t mg, int on);
 /* z = V(r) on unique-node vectors of the finest plan (the layout of
  * sem_lp_apply_unique); dtype SEM_F64 or SEM_F32 for both; z must not alias r.
  * Asynchronous; the hierarchy's work vectors are shared by all calls on mg. */

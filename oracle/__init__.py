@@ -19,7 +19,8 @@ Modules
   assemble  dense assembled matrix, Jacobi diagonal
   solve     textbook Jacobi-PCG, mixed-precision refinement, flexible CG
   quant     round-to-nearest-even float32 / bfloat16 emulation
-  mlp       per-element MLP forward/backward and Adam
+  mlp       per-element MLP forward/backward and Adam, and their bfloat16-storage emulation
+  mg        multigrid V-cycle: p- and h-transfers, Chebyshev-Jacobi smoothing, dense coarsest solve
   cref      ctypes loader for sem_ref.c: the path in plain C (CPU baseline, 32^3 reference solutions)
 
 Parity status of each function is stated in its docstring; anything without

@@ -19,7 +19,7 @@ __all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONV
            "sem_lp_gradients", "sem_lp_adam", "sem_lp_set_metric", "sem_lp_set_jacobi_base", "sem_lp_set_linear", "sem_lp_train_step", "sem_lp_apply", "sem_lp_apply_unique", "sem_lp_save", "sem_lp_load", "sem_lp_set_block", "LP_SLOTS",
            "SEM_LP_IN", "SEM_LP_IN_PAD", "SEM_LP_HIDDEN", "SEM_LP_OUT", "SemMgOpts", "Multigrid",
            "sem_mg_create", "sem_mg_destroy", "sem_mg_levels", "sem_mg_level_info", "sem_mg_set_lmax",
-           "sem_mg_apply", "sem_lp_snapshot", "sem_lp_reference_block"]
+           "sem_mg_apply", "sem_mg_set_graphs", "sem_lp_snapshot", "sem_lp_reference_block"]
 
 SEM_LP_IN, SEM_LP_IN_PAD, SEM_LP_HIDDEN, SEM_LP_OUT = 518, 528, 256, 512
 # slot -> shape of the float32 array it holds (parameters; +6 m, +12 v, +18 grads)
@@ -132,6 +132,7 @@ EXPORTS = {
     "sem_mg_level_info": (_int, [_vp, _int, ctypes.POINTER(_int), ctypes.POINTER(_int), _pi64, _pdbl]),
     "sem_mg_set_lmax": (_int, [_vp, _int, _dbl]),
     "sem_mg_apply": (_int, [_vp, _vp, _vp, _int]),
+    "sem_mg_set_graphs": (_int, [_vp, _int]),
 }
 
 _LIB = None
@@ -614,6 +615,10 @@ def sem_mg_level_info(mg, level):
 
 def sem_mg_set_lmax(mg, level, lmax):
     _check(lib().sem_mg_set_lmax(mg.handle, level, float(lmax)), mg.ctx.handle)
+
+
+def sem_mg_set_graphs(mg, on):
+    _check(lib().sem_mg_set_graphs(mg.handle, int(bool(on))), mg.ctx.handle)
 
 
 def sem_mg_apply(mg, z, r):

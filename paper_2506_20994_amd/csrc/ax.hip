@@ -127,7 +127,7 @@ __device__ __forceinline__ void wave_sync() {
 // a Dirichlet node, read as 0).  The output stays in the local layout
 // (coalesced nontemporal stores); the solver sums the copies of each unique
 // node through the plan's CSR lists.
-template <int LX, int EPB, typename TU, typename TS, typename TC, typename TW, bool FUSE, bool GATHER>
+template <int LX, int EPB, typename TU, typename TS, typename TC, typename TW, bool FUSE, bool GATHER, bool HB>
 __global__ void __launch_bounds__(EPB * LX * LX) __attribute__((amdgpu_waves_per_eu(Shape<LX>::kWavesPerEU, 8)))
 ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
           const TC* __restrict__ dx, const TC* __restrict__ dy, const TC* __restrict__ dz,
@@ -246,7 +246,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
             acc += dj[l] * ss[k * L2 + l * LX + i];
         }
         if (live) {
-            if (hb) acc += Load<TS>::get(hb, base + k * L2) * uc[k];       // Helmholtz: + h2 B u
+            if constexpr (HB) acc += Load<TS>::get(hb, base + k * L2) * uc[k];   // Helmholtz: + h2 B u
             store_nt(w, base + k * L2, (TW)acc);
         }
         if (FUSE) pw += (double)uc[k] * (double)(TW)acc;
@@ -287,7 +287,7 @@ template <int LX> struct Shape3D {
     static constexpr int EPB = 16;
 };
 
-template <int LX, int EPB, typename TS, typename TC, typename TW>
+template <int LX, int EPB, typename TS, typename TC, typename TW, bool HB>
 __global__ void __launch_bounds__(EPB * LX * LX * LX)
 ax3d_kernel(TW* __restrict__ w, const TS* __restrict__ u,
             const TC* __restrict__ dx, const TC* __restrict__ dy, const TC* __restrict__ dz,
@@ -352,14 +352,16 @@ ax3d_kernel(TW* __restrict__ w, const TS* __restrict__ u,
         acc += dj[l] * ss[k * L2 + l * LX + i];
         acc += dk[l] * st[l * L2 + j * LX + i];
     }
-    if (live && hb) acc += Load<TS>::get(hb, g) * uv;   // Helmholtz: + h2 B u
+    if constexpr (HB) if (live) acc += Load<TS>::get(hb, g) * uv;   // Helmholtz: + h2 B u
     if (live) store_nt(w, g, (TW)acc);
 }
 
-template <int LX, typename TU, typename TS, typename TC, typename TW>
-int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const void* h1,
-              const void* const* G, int64_t nel, const int* skip, double* dot, const int32_t* lid,
-              const void* gp, const void* hb) {
+// The Helmholtz term is a template flag (HB), so that the two forms are
+// separate kernels (and separate rows of a kernel trace).
+template <int LX, typename TU, typename TS, typename TC, typename TW, bool HB>
+int launch_form(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const void* h1,
+                const void* const* G, int64_t nel, const int* skip, double* dot, const int32_t* lid,
+                const void* gp, const void* hb) {
     constexpr int EPB = Shape<LX>::EPB;
     const int64_t blocks = (nel + EPB - 1) / EPB;
     if (blocks > 0x7fffffff) return sem::fail(ctx, SEM_EINVAL, "sem_ax: nel too large");
@@ -373,7 +375,7 @@ int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const
         if (!lid && !dot) {
             constexpr int E3 = Shape3D<LX>::EPB;
             const int64_t b3 = (nel + E3 - 1) / E3;
-            ax3d_kernel<LX, E3, TS, TC, TW><<<(unsigned)b3, E3 * LX * LX * LX, 0, ctx->stream>>>(
+            ax3d_kernel<LX, E3, TS, TC, TW, HB><<<(unsigned)b3, E3 * LX * LX * LX, 0, ctx->stream>>>(
                 (TW*)w, (const TS*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2], (const TC*)D[3],
                 (const TC*)D[4], (const TC*)D[5], (const TS*)h1, (const TS*)G[0], (const TS*)G[1],
                 (const TS*)G[2], (const TS*)G[3], (const TS*)G[4], (const TS*)G[5], nel, (const TS*)hb);
@@ -382,16 +384,24 @@ int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const
         }
     }
     if (dot && lid)
-        ax_kernel<LX, EPB, TU, TS, TC, TW, true, true><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
+        ax_kernel<LX, EPB, TU, TS, TC, TW, true, true, HB><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
     else if (lid)
-        ax_kernel<LX, EPB, TU, TS, TC, TW, false, true><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
+        ax_kernel<LX, EPB, TU, TS, TC, TW, false, true, HB><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
     else if (!dot)
-        ax_kernel<LX, EPB, TU, TS, TC, TW, false, false><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
+        ax_kernel<LX, EPB, TU, TS, TC, TW, false, false, HB><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
     else
         return sem::fail(ctx, SEM_EINVAL, "launch_ax: the fused dot needs the solver form");
 #undef SEM_AX_ARGS
     SEM_LAUNCH_CHECK(ctx);
     return SEM_OK;
+}
+
+template <int LX, typename TU, typename TS, typename TC, typename TW>
+int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const void* h1,
+              const void* const* G, int64_t nel, const int* skip, double* dot, const int32_t* lid,
+              const void* gp, const void* hb) {
+    if (hb) return launch_form<LX, TU, TS, TC, TW, true>(ctx, w, u, D, h1, G, nel, skip, dot, lid, gp, hb);
+    return launch_form<LX, TU, TS, TC, TW, false>(ctx, w, u, D, h1, G, nel, skip, dot, lid, gp, hb);
 }
 
 template <typename TU, typename TS, typename TC, typename TW>

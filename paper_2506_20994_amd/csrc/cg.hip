@@ -1086,7 +1086,8 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
 
     if (!(opts->tol > 0.0)) return sem::fail(ctx, SEM_EINVAL, "sem_cg_solve: tol must be > 0");
     *stats = sem_solve_stats_t{};
-    const int check = opts->check_every > 0 ? opts->check_every : 16;
+    // a multigrid iteration costs several operator applications: check more often
+    const int check = opts->check_every > 0 ? opts->check_every : (cg->mg ? 4 : 16);
     const int maxit = opts->maxit > 0 ? opts->maxit : 100000;
     hipStream_t st = ctx->stream;
     const int64_t nu = cg->nu;
@@ -1147,7 +1148,9 @@ extern "C" int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_s
         const bool bf = cg->precision == SEM_SOLVE_BF16_IR;
         if (opts->ir_mode == 1) {
             int its = 0, nrep = 0, brk = 0, nj = 0, fb = 0;
-            rc = rr_run(cg, L, opts->tol, opts->delta > 0 ? opts->delta : 0.1, maxit, check, bnorm, &its,
+            // the V-cycle cuts the residual by about 2x per iteration: replace less often
+            const double delta = opts->delta > 0 ? opts->delta : (cg->mg ? 1e-3 : 0.1);
+            rc = rr_run(cg, L, opts->tol, delta, maxit, check, bnorm, &its,
                         &nrep, &brk, stats->relres_hist, 64, &nj, &fb);
             if (rc) return rc;
             stats->jacobi_steps = nj;

@@ -444,6 +444,13 @@ struct sem_mg_s {
     float *b0 = nullptr, *x0 = nullptr;   // float32 copies for float64 callers
     double* part = nullptr;           // kVecGrid partial sums
     std::vector<void*> allocs;
+    // The V-cycle is a fixed sequence of about 12 launches per level; replayed
+    // as a captured HIP graph (one per set of vector and flag pointers) its
+    // coarse levels are no longer bound by launch latency.
+    bool graphs = true;
+    hipStream_t cap_stream = nullptr;     // private capture stream (default priority)
+    struct Cached { const void* z; const void* r; const int* skip; bool f64; hipGraphExec_t exec; };
+    std::vector<Cached> cache;
 };
 
 namespace {
@@ -647,7 +654,9 @@ bool spd_inverse(std::vector<double>& A, int n) {
 sem_gs_t mg_plan(sem_mg_t mg) { return mg && !mg->L.empty() ? mg->L[0].gs : nullptr; }
 int64_t mg_nel(sem_mg_t mg) { return mg && !mg->L.empty() ? mg->L[0].nel : 0; }
 
-int mg_apply(sem_mg_t mg, void* z, const void* r, bool f64, const int* skip) {
+// the launches of one V-cycle on the context's stream (converting in and out
+// for float64 callers)
+int mg_launch(sem_mg_t mg, void* z, const void* r, bool f64, const int* skip) {
     hipStream_t st = mg->ctx->stream;
     const int64_t nu = mg->L[0].nu;
     const unsigned g = vgrid(nu);
@@ -660,6 +669,40 @@ int mg_apply(sem_mg_t mg, void* z, const void* r, bool f64, const int* skip) {
     return SEM_OK;
 }
 
+// the captured graph of the V-cycle for these pointers (captured on first use)
+int mg_graph(sem_mg_t mg, void* z, const void* r, bool f64, const int* skip, hipGraphExec_t* out) {
+    for (const auto& c : mg->cache)
+        if (c.z == z && c.r == r && c.skip == skip && c.f64 == f64) { *out = c.exec; return SEM_OK; }
+    sem_ctx_t ctx = mg->ctx;
+    if (!mg->cap_stream) SEM_HIP(ctx, hipStreamCreateWithFlags(&mg->cap_stream, hipStreamNonBlocking));
+    hipStream_t saved = ctx->stream;
+    ctx->stream = mg->cap_stream;
+    hipError_t e = hipStreamBeginCapture(mg->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { ctx->stream = saved; return sem::check_hip(ctx, e, "hipStreamBeginCapture"); }
+    int rc = mg_launch(mg, z, r, f64, skip);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(mg->cap_stream, &graph);
+    ctx->stream = saved;
+    if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+    if (e != hipSuccess) return sem::check_hip(ctx, e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return sem::check_hip(ctx, e, "hipGraphInstantiate");
+    mg->cache.push_back({z, r, skip, f64, exec});
+    *out = exec;
+    return SEM_OK;
+}
+
+int mg_apply(sem_mg_t mg, void* z, const void* r, bool f64, const int* skip) {
+    if (!mg->graphs) return mg_launch(mg, z, r, f64, skip);
+    hipGraphExec_t exec = nullptr;
+    int rc = mg_graph(mg, z, r, f64, skip, &exec);
+    if (rc) return rc;
+    SEM_HIP(mg->ctx, hipGraphLaunch(exec, mg->ctx->stream));
+    return SEM_OK;
+}
+
 }  // namespace sem
 
 extern "C" int sem_mg_destroy(sem_mg_t mg) {
@@ -668,6 +711,8 @@ extern "C" int sem_mg_destroy(sem_mg_t mg) {
         (void)hipSetDevice(mg->ctx->device);
         (void)hipStreamSynchronize(mg->ctx->stream);
     }
+    for (auto& c : mg->cache) (void)hipGraphExecDestroy(c.exec);
+    if (mg->cap_stream) (void)hipStreamDestroy(mg->cap_stream);
     for (auto& lv : mg->L)
         if (lv.own_gs) sem_gs_destroy(lv.gs);
     for (void* p : mg->allocs) (void)hipFree(p);
@@ -698,8 +743,8 @@ extern "C" int sem_mg_create(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A
     const double* Gp[6] = {A->g11, A->g22, A->g33, A->g12, A->g13, A->g23};
     for (int q = 0; q < 6; ++q)
         if (!Dp[q] || !Gp[q]) return sem::fail(ctx, SEM_EINVAL, "sem_mg_create: null operator array");
-    const int degree = opts->degree > 0 ? opts->degree : 2;
-    const double lo = opts->lo > 0 ? opts->lo : 0.3, hi = opts->hi > 0 ? opts->hi : 1.1;
+    const int degree = opts->degree > 0 ? opts->degree : 3;
+    const double lo = opts->lo > 0 ? opts->lo : 0.2, hi = opts->hi > 0 ? opts->hi : 1.1;
     const int n_coarse = opts->n_coarse > 0 ? opts->n_coarse : 2;
     const int steps = opts->lanczos_steps > 0 ? opts->lanczos_steps : 20;
     if (degree > 16 || !(hi > lo)) return sem::fail(ctx, SEM_EINVAL, "sem_mg_create: bad degree or interval");
@@ -946,6 +991,12 @@ extern "C" int sem_mg_set_lmax(sem_mg_t mg, int level, double lmax) {
         return sem::fail(mg->ctx, SEM_EINVAL, "sem_mg_set_lmax: bad level %d or lmax", level);
     mg->L[level].lmax = lmax;
     set_chebyshev(mg, mg->L[level]);
+    return SEM_OK;
+}
+
+extern "C" int sem_mg_set_graphs(sem_mg_t mg, int on) {
+    if (!mg) return sem::fail(nullptr, SEM_EINVAL, "sem_mg_set_graphs: null handle");
+    mg->graphs = on != 0;
     return SEM_OK;
 }
 

@@ -35,19 +35,19 @@ def _plan_order(ids, nu):
     return plan_of
 
 
-CASES = [  # n, lx, amp, dirichlet, h2, degree
-    (4, 8, 0.1, False, None, 2),
-    (4, 6, 0.12, True, None, 2),
-    (2, 5, 0.1, False, 20.0, 3),
-    (4, 3, 0.1, True, 5.0, 1),
+CASES = [  # n, lx, amp, dirichlet, h2, degree, lo
+    (4, 8, 0.1, False, None, 2, 0.3),
+    (4, 6, 0.12, True, None, 3, 0.2),
+    (2, 5, 0.1, False, 20.0, 3, 0.3),
+    (4, 3, 0.1, True, 5.0, 1, 0.2),
 ]
 
 
-@pytest.mark.parametrize("n,lx,amp,dirichlet,h2,degree", CASES)
-def test_vcycle_matches_oracle(sem_ctx, n, lx, amp, dirichlet, h2, degree):
+@pytest.mark.parametrize("n,lx,amp,dirichlet,h2,degree,lo", CASES)
+def test_vcycle_matches_oracle(sem_ctx, n, lx, amp, dirichlet, h2, degree, lo):
     op = BoxOperator(sem_ctx, n, lx, amp, dirichlet=dirichlet, keep_coords=False)
-    mg = op.multigrid(h2=h2 or 0.0, degree=degree)
-    H = omg.Hierarchy(n, lx, amp, dirichlet=dirichlet, h2=h2, degree=degree)
+    mg = op.multigrid(h2=h2 or 0.0, degree=degree, lo=lo)
+    H = omg.Hierarchy(n, lx, amp, dirichlet=dirichlet, h2=h2, degree=degree, lo=lo)
     nl = P.sem_mg_levels(mg)
     assert nl == len(H.shapes)
     lmax = []
@@ -91,6 +91,30 @@ def test_vcycle_is_symmetric(sem_ctx):
     a, b = float(u @ Vv), float(v @ Vu)
     assert abs(a - b) <= 1e-5 * (abs(a) + abs(b))
     assert float(u @ Vu) > 0 and float(v @ Vv) > 0
+    mg.close()
+    op.gs.close()
+
+
+def test_vcycle_graph_replays_equal_eager_launches(sem_ctx):
+    """The V-cycle replayed as a captured graph (the default) equals its
+    launches one by one, bit for bit, on every replay, with eager work (new
+    right-hand sides written in between) and float64 / float32 vectors."""
+    op = BoxOperator(sem_ctx, 4, 8, 0.1, keep_coords=False)
+    mg = op.multigrid(n_coarse=2)
+    nu = op.n_unique
+    for dt in (torch.float64, torch.float32):
+        r = torch.empty(nu, dtype=dt, device="cuda")
+        z_graph, z_eager = torch.empty_like(r), torch.empty_like(r)
+        for rep in range(3):
+            r.copy_(torch.from_numpy(synth.unique_normal(nu, 90 + rep)))
+            P.sem_mg_set_graphs(mg, 1)
+            P.sem_mg_apply(mg, z_graph, r)
+            torch.cuda.synchronize()
+            P.sem_mg_set_graphs(mg, 0)
+            P.sem_mg_apply(mg, z_eager, r)
+            torch.cuda.synchronize()
+            assert torch.equal(z_graph, z_eager), (dt, rep)
+            assert torch.isfinite(z_graph).all()
     mg.close()
     op.gs.close()
 
