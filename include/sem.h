@@ -176,6 +176,35 @@ int sem_ax_helmholtz(sem_ctx_t ctx, void* w, const void* u,
                      const void* g12, const void* g13, const void* g23, const void* h2b,
                      int64_t nel, int lx, sem_dtype_t field_dtype, sem_dtype_t out_dtype);
 
+/* Kernel variants of the float64 operator (sem_ax and sem_ax_helmholtz with
+ * field dtype SEM_F64), all computing the same sums (results agree to
+ * rounding):
+ *   SEM_AX_COLUMN     one thread per (i, j) column, u's column in registers,
+ *                     the element's slices and fluxes in LDS (Sec. 4.2, the
+ *                     per-(i, j) thread mapping with a k loop);
+ *   SEM_AX_COLUMN_PF  the same with the opposite choice of fetching the next
+ *                     slice's factors one slice ahead;
+ *   SEM_AX_SLICE      the column mapping with the element passing through LDS
+ *                     one slice at a time (double-buffered, one barrier per
+ *                     slice; 6 lx^2 LDS values per element instead of ~3 lx^3);
+ *   SEM_AX_3D         one thread per node (lx <= 10).
+ * SEM_AX_DEFAULT (-1) is the built-in choice: SEM_AX_3D at lx = 3, SEM_AX_COLUMN
+ * otherwise.  The paper picks among kernel variants by timing them at run
+ * time (Sec. 4); sem_ax_tune does that for one lx and element count. */
+enum { SEM_AX_DEFAULT = -1, SEM_AX_COLUMN = 0, SEM_AX_COLUMN_PF = 1, SEM_AX_SLICE = 2, SEM_AX_3D = 3 };
+#define SEM_AX_VARIANTS 4
+/* Select the variant for lx on this context (SEM_EINVAL if it does not
+ * exist at that lx). */
+int sem_ax_set_variant(sem_ctx_t ctx, int lx, int variant);
+int sem_ax_get_variant(sem_ctx_t ctx, int lx, int* variant);
+/* Time every variant that exists at lx on nel elements of synthetic inputs
+ * (allocated and freed here; `reps` launches each after two warm-ups, HIP
+ * events on the context's stream), select the fastest for lx on this context
+ * and return it in *best.  us (host, SEM_AX_VARIANTS entries, may be NULL)
+ * receives the average launch time of each variant in microseconds, -1 where
+ * a variant does not exist.  Synchronous. */
+int sem_ax_tune(sem_ctx_t ctx, int lx, int64_t nel, int reps, double* us, int* best);
+
 /* ---------------------------------------------------------- gather-scatter */
 
 /* Build the gather-scatter plan (Sec. 2.1) for a local numbering: ids (host
@@ -333,8 +362,8 @@ int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_solve_opts_t
  * evaluated at the fine level's nodes (the coarse Lagrange basis on the same
  * element; the parent's trilinear basis); restriction by its transpose.
  * Smoothing: `degree` steps of the Chebyshev semi-iteration in D^-1 A (D the
- * assembled diagonal) on [lo lmax, hi lmax] (defaults 3, 0.2, 1.1: the fastest
- * 32^3 lx = 8 solve of a sweep over degree 1-3 and lo 0.2-0.3), lmax of every level estimated by
+ * assembled diagonal) on [lo lmax, hi lmax] (defaults 2, 0.15, 1.1: the fastest
+ * 32^3 lx = 8 solve of a sweep over degree 1-4 and lo 0.15-0.3), lmax of every level estimated by
  * `lanczos_steps` Lanczos steps at creation.  The coarsest level is solved
  * with a dense inverse (at most 2048 unknowns; of A + c 1 1^T on the singular
  * periodic box, c = mean diagonal / unknowns).  V(b): pre-smoothing from 0,
@@ -345,8 +374,8 @@ typedef struct {
     double amp;          /* the box's deformation amplitude (sem_box_mesh) */
     int dirichlet;       /* 1: the Dirichlet box (its plan has Dirichlet nodes), 0: periodic */
     double h2;           /* Helmholtz coefficient (> 0 exactly when A->h2b is set; 0: Poisson) */
-    int degree;          /* Chebyshev steps per smoothing (0: 3) */
-    double lo, hi;       /* smoothing interval in units of lmax (0: 0.2 and 1.1) */
+    int degree;          /* Chebyshev steps per smoothing (0: 2) */
+    double lo, hi;       /* smoothing interval in units of lmax (0: 0.15 and 1.1) */
     int n_coarse;        /* h-coarsening keeps n >= n_coarse (0: 2) */
     int lanczos_steps;   /* Lanczos steps per level for lmax (0: 20) */
 } sem_mg_opts_t;
@@ -367,7 +396,7 @@ int sem_mg_levels(sem_mg_t mg, int* count);
 int sem_mg_level_info(sem_mg_t mg, int level, int* n, int* lx, int64_t* n_unique, double* lmax);
 /* Replace the lmax of a smoothed level (every level but the coarsest). */
 int sem_mg_set_lmax(sem_mg_t mg, int level, double lmax);
-/* Launch mode of the V-cycle (default on): replay it as a HIP graph captured
+/* Launch mode of the V-cycle (default off): replay it as a HIP graph captured
  * on first use for each set of (z, r) pointers (the V-cycle's pointers and
  * the sequence of its launches are fixed), or launch its kernels one by one
  * (off).  Both give the same result bit for bit.  Graphs are kept until

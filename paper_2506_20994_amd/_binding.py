@@ -19,13 +19,16 @@ __all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONV
            "sem_lp_gradients", "sem_lp_adam", "sem_lp_set_metric", "sem_lp_set_jacobi_base", "sem_lp_set_linear", "sem_lp_train_step", "sem_lp_apply", "sem_lp_apply_unique", "sem_lp_save", "sem_lp_load", "sem_lp_set_block", "LP_SLOTS",
            "SEM_LP_IN", "SEM_LP_IN_PAD", "SEM_LP_HIDDEN", "SEM_LP_OUT", "SemMgOpts", "Multigrid",
            "sem_mg_create", "sem_mg_destroy", "sem_mg_levels", "sem_mg_level_info", "sem_mg_set_lmax",
-           "sem_mg_apply", "sem_mg_set_graphs", "sem_lp_snapshot", "sem_lp_reference_block"]
+           "sem_mg_apply", "sem_mg_set_graphs", "sem_ax_set_variant", "sem_ax_get_variant", "sem_ax_tune",
+           "SEM_AX_DEFAULT", "SEM_AX_COLUMN", "SEM_AX_COLUMN_PF", "SEM_AX_SLICE", "SEM_AX_3D", "SEM_AX_VARIANTS", "sem_lp_snapshot", "sem_lp_reference_block"]
 
 SEM_LP_IN, SEM_LP_IN_PAD, SEM_LP_HIDDEN, SEM_LP_OUT = 518, 528, 256, 512
 # slot -> shape of the float32 array it holds (parameters; +6 m, +12 v, +18 grads)
 LP_SLOTS = [(256, 518), (256,), (256, 256), (256,), (512, 256), (512,)]
 
 SEM_SOLVE_F64, SEM_SOLVE_F32_IR, SEM_SOLVE_BF16_IR = 0, 1, 2
+SEM_AX_DEFAULT, SEM_AX_COLUMN, SEM_AX_COLUMN_PF, SEM_AX_SLICE, SEM_AX_3D = -1, 0, 1, 2, 3
+SEM_AX_VARIANTS = 4
 
 
 class SemOperator(ctypes.Structure):
@@ -126,6 +129,9 @@ EXPORTS = {
     "sem_lp_set_linear": (_int, [_vp, _int]),
     "sem_lp_snapshot": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64]),
     "sem_lp_reference_block": (_int, [_vp, _int, _pdbl]),
+    "sem_ax_set_variant": (_int, [_vp, _int, _int]),
+    "sem_ax_get_variant": (_int, [_vp, _int, ctypes.POINTER(_int)]),
+    "sem_ax_tune": (_int, [_vp, _int, _i64, _int, _pdbl, ctypes.POINTER(_int)]),
     "sem_mg_create": (_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
     "sem_mg_destroy": (_int, [_vp]),
     "sem_mg_levels": (_int, [_vp, ctypes.POINTER(_int)]),
@@ -639,3 +645,25 @@ def sem_lp_reference_block(ctx, lx=8):
     h = ctx.bind()
     _check(lib().sem_lp_reference_block(h, lx, W.ctypes.data_as(_pdbl)), h)
     return W
+
+
+def sem_ax_set_variant(ctx, lx, variant):
+    h = ctx.bind()
+    _check(lib().sem_ax_set_variant(h, lx, variant), h)
+
+
+def sem_ax_get_variant(ctx, lx):
+    v = _int(0)
+    h = ctx.bind()
+    _check(lib().sem_ax_get_variant(h, lx, ctypes.byref(v)), h)
+    return v.value
+
+
+def sem_ax_tune(ctx, lx, nel, reps=20):
+    """Times the float64 operator's variants at lx on nel elements and selects
+    the fastest; returns (best, [us per variant, -1 where none])."""
+    us = (ctypes.c_double * SEM_AX_VARIANTS)()
+    best = _int(0)
+    h = ctx.bind()
+    _check(lib().sem_ax_tune(h, lx, nel, reps, us, ctypes.byref(best)), h)
+    return best.value, list(us)

@@ -15,6 +15,9 @@
 //   double / double   (SEM_F64)
 //   float  / float    (SEM_F32)
 //   bf16   / float    (SEM_BF16, bf16 stored as uint16_t bit patterns)
+#include <type_traits>
+#include <vector>
+
 #include "sem_internal.h"
 
 namespace {
@@ -127,7 +130,8 @@ __device__ __forceinline__ void wave_sync() {
 // a Dirichlet node, read as 0).  The output stays in the local layout
 // (coalesced nontemporal stores); the solver sums the copies of each unique
 // node through the plan's CSR lists.
-template <int LX, int EPB, typename TU, typename TS, typename TC, typename TW, bool FUSE, bool GATHER, bool HB>
+template <int LX, int EPB, typename TU, typename TS, typename TC, typename TW, bool FUSE, bool GATHER, bool HB,
+          bool PF = Shape<LX>::kPrefetch>
 __global__ void __launch_bounds__(EPB * LX * LX) __attribute__((amdgpu_waves_per_eu(Shape<LX>::kWavesPerEU, 8)))
 ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
           const TC* __restrict__ dx, const TC* __restrict__ dy, const TC* __restrict__ dz,
@@ -196,7 +200,6 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
     TC wt[LX];
 #pragma unroll
     for (int m = 0; m < LX; ++m) wt[m] = 0;
-    constexpr bool PF = Shape<LX>::kPrefetch;
     TC ng[6], nh;                              // the next slice's factors (prefetch)
     if constexpr (PF) load_factors<TS, TC, GATHER>(ng, nh, live, base, ij, L2, h1, g11, g22, g33, g12, g13, g23, gp);
 #pragma unroll 1
@@ -277,6 +280,120 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
     }
 }
 
+// Slice-pipelined column mapping: one thread per (i, j) column as in
+// ax_kernel, but the element passes through LDS one k-slice at a time.  Slice
+// k of u and the r- and s-fluxes of slice k - 1 sit in double buffers, so each
+// slice costs one workgroup barrier, and LDS holds 6 lx^2 values per element
+// instead of ax_kernel's 2-3 lx^3: large elements keep several times more
+// waves in flight.  Register arrays are indexed by the run-time slice only
+// through selects, so they stay in registers.  Plain (public) form only.
+template <int LX> struct ShapeSlice {
+    static constexpr int EPB = (512 / (LX * LX)) < 1 ? 1 : 512 / (LX * LX);
+};
+
+template <int LX, int EPB, typename TS, typename TC, typename TW, bool HB>
+__global__ void __launch_bounds__(EPB * LX * LX)
+ax_slice_kernel(TW* __restrict__ w, const TS* __restrict__ u,
+                const TC* __restrict__ dx, const TC* __restrict__ dy, const TC* __restrict__ dz,
+                const TC* __restrict__ dxt, const TC* __restrict__ dyt, const TC* __restrict__ dzt,
+                const TS* __restrict__ h1, const TS* __restrict__ g11, const TS* __restrict__ g22,
+                const TS* __restrict__ g33, const TS* __restrict__ g12, const TS* __restrict__ g13,
+                const TS* __restrict__ g23, int64_t nel, const TS* __restrict__ hb) {
+    constexpr int L2 = LX * LX;
+    constexpr int L3 = L2 * LX;
+    constexpr int NS = EPB * L2;
+    __shared__ TC s_d[6 * L2];
+    __shared__ TC s_u[2][NS];
+    __shared__ TC s_r[2][NS];
+    __shared__ TC s_s[2][NS];
+    const int tid = threadIdx.x;
+    const int el = tid / L2;
+    const int ij = tid - el * L2;
+    const int i = ij % LX;
+    const int j = ij / LX;
+    const int64_t e = (int64_t)blockIdx.x * EPB + el;
+    const bool live = e < nel;
+    const int64_t base = e * L3 + ij;
+    const int off = el * L2;
+    for (int q = tid; q < L2; q += NS) {
+        s_d[q] = dx[q];
+        s_d[L2 + q] = dy[q];
+        s_d[2 * L2 + q] = dz[q];
+        s_d[3 * L2 + q] = dxt[q];
+        s_d[4 * L2 + q] = dyt[q];
+        s_d[5 * L2 + q] = dzt[q];
+    }
+    TC uc[LX];
+#pragma unroll
+    for (int k = 0; k < LX; ++k) uc[k] = live ? (TC)Load<TS>::get(u, base + k * L2) : TC(0);
+    s_u[0][off + ij] = uc[0];
+    __syncthreads();
+    TC di[LX], dj[LX], ti[LX], tj[LX];
+#pragma unroll
+    for (int l = 0; l < LX; ++l) {
+        di[l] = s_d[l * LX + i];
+        dj[l] = s_d[L2 + l * LX + j];
+        ti[l] = s_d[3 * L2 + l * LX + i];
+        tj[l] = s_d[4 * L2 + l * LX + j];
+    }
+    const TC* sdz = s_d + 2 * L2;
+    const TC* sdzt = s_d + 5 * L2;
+    TC wt[LX];
+#pragma unroll
+    for (int m = 0; m < LX; ++m) wt[m] = 0;
+    // iteration k: the forward passes of slice k (k < LX) and the transposed
+    // r- and s-sums of slice k - 1 (k > 0)
+#pragma unroll 1
+    for (int k = 0; k <= LX; ++k) {
+        if (k > 0) __syncthreads();
+        const int b = k & 1;
+        TC vr = 0, vs = 0;
+        if (k < LX) {
+            TC g[6], H;
+            load_factors<TS, TC, false>(g, H, live, base + k * L2, ij, L2, h1, g11, g22, g33, g12, g13, g23, nullptr);
+            TC r = 0, s = 0, t = 0;
+#pragma unroll
+            for (int l = 0; l < LX; ++l) {
+                r += di[l] * s_u[b][off + j * LX + l];
+                s += dj[l] * s_u[b][off + l * LX + i];
+                t += sdz[l * LX + k] * uc[l];
+            }
+            vr = H * (g[0] * r + g[3] * s + g[4] * t);
+            vs = H * (g[3] * r + g[1] * s + g[5] * t);
+            const TC vt = H * (g[4] * r + g[5] * s + g[2] * t);
+#pragma unroll
+            for (int m = 0; m < LX; ++m) wt[m] += sdzt[k * LX + m] * vt;
+        }
+        if (k > 0) {
+            const int pb = b ^ 1;
+            TC acc = 0;
+#pragma unroll
+            for (int l = 0; l < LX; ++l) {
+                acc += ti[l] * s_r[pb][off + j * LX + l];
+                acc += tj[l] * s_s[pb][off + l * LX + i];
+            }
+#pragma unroll
+            for (int m = 0; m < LX; ++m) wt[m] += (m == k - 1) ? acc : TC(0);
+        }
+        if (k < LX) {
+            s_r[b][off + ij] = vr;
+            s_s[b][off + ij] = vs;
+            TC nx = 0;
+#pragma unroll
+            for (int m = 1; m < LX; ++m) nx = (m == k + 1) ? uc[m] : nx;
+            if (k + 1 < LX) s_u[b ^ 1][off + ij] = nx;
+        }
+    }
+    if (live) {
+#pragma unroll
+        for (int k = 0; k < LX; ++k) {
+            TC acc = wt[k];
+            if constexpr (HB) acc += Load<TS>::get(hb, base + k * L2) * uc[k];   // Helmholtz: + h2 B u
+            store_nt(w, base + k * L2, (TW)acc);
+        }
+    }
+}
+
 // One thread per node ("3D" mapping): every load and store of the streamed
 // arrays is contiguous across the workgroup.  u and the three fluxes go
 // through LDS; each thread keeps the derivative-matrix rows it needs (its i,
@@ -284,7 +401,8 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
 // columns per element leave the column mapping's loads badly fragmented (it
 // measured slower than the column kernel at lx = 5, 6, 7).
 template <int LX> struct Shape3D {
-    static constexpr int EPB = 16;
+    // whole elements per workgroup of at most 1024 threads (none above lx = 10)
+    static constexpr int EPB = LX == 3 ? 16 : (1024 / (LX * LX * LX));
 };
 
 template <int LX, int EPB, typename TS, typename TC, typename TW, bool HB>
@@ -358,13 +476,77 @@ ax3d_kernel(TW* __restrict__ w, const TS* __restrict__ u,
 
 // The Helmholtz term is a template flag (HB), so that the two forms are
 // separate kernels (and separate rows of a kernel trace).
+// the float64 public form's kernel variants (SEM_AX_* of sem.h)
+constexpr bool variant_exists(int lx, int v) {
+    return v == SEM_AX_COLUMN || v == SEM_AX_COLUMN_PF || v == SEM_AX_SLICE || (v == SEM_AX_3D && lx <= 10);
+}
+
+template <int LX, typename TS, typename TC, typename TW, bool HB, bool PF>
+void launch_column(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const void* h1,
+                   const void* const* G, int64_t nel) {
+    constexpr int EPB = Shape<LX>::EPB;
+    ax_kernel<LX, EPB, TS, TS, TC, TW, false, false, HB, PF><<<(unsigned)((nel + EPB - 1) / EPB), EPB * LX * LX, 0,
+                                                               ctx->stream>>>(
+        (TW*)w, (const TS*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2], (const TC*)D[3], (const TC*)D[4],
+        (const TC*)D[5], (const TS*)h1, (const TS*)G[0], (const TS*)G[1], (const TS*)G[2], (const TS*)G[3],
+        (const TS*)G[4], (const TS*)G[5], nel, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+template <int LX, typename TS, typename TC, typename TW, bool HB>
+void launch_3d(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const void* h1,
+               const void* const* G, int64_t nel, const void* hb) {
+    if constexpr (Shape3D<LX>::EPB >= 1) {
+        constexpr int E3 = Shape3D<LX>::EPB;
+        ax3d_kernel<LX, E3, TS, TC, TW, HB><<<(unsigned)((nel + E3 - 1) / E3), E3 * LX * LX * LX, 0, ctx->stream>>>(
+            (TW*)w, (const TS*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2], (const TC*)D[3],
+            (const TC*)D[4], (const TC*)D[5], (const TS*)h1, (const TS*)G[0], (const TS*)G[1],
+            (const TS*)G[2], (const TS*)G[3], (const TS*)G[4], (const TS*)G[5], nel, (const TS*)hb);
+    }
+}
+
+// a non-default variant of the float64 public form; false if it does not exist
+template <int LX, typename TS, typename TC, typename TW, bool HB>
+bool launch_variant(sem_ctx_t ctx, int variant, void* w, const void* u, const void* const* D, const void* h1,
+                    const void* const* G, int64_t nel, const void* hb) {
+    if constexpr (!std::is_same<TS, double>::value) {
+        return false;
+    } else {
+        if (variant == SEM_AX_COLUMN_PF) {
+            launch_column<LX, TS, TC, TW, HB, !Shape<LX>::kPrefetch>(ctx, w, u, D, h1, G, nel);
+            return true;
+        }
+        if (variant == SEM_AX_COLUMN) {
+            launch_column<LX, TS, TC, TW, HB, Shape<LX>::kPrefetch>(ctx, w, u, D, h1, G, nel);
+            return true;
+        }
+        if (variant == SEM_AX_SLICE) {
+            constexpr int ES = ShapeSlice<LX>::EPB;
+            ax_slice_kernel<LX, ES, TS, TC, TW, HB><<<(unsigned)((nel + ES - 1) / ES), ES * LX * LX, 0, ctx->stream>>>(
+                (TW*)w, (const TS*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2], (const TC*)D[3],
+                (const TC*)D[4], (const TC*)D[5], (const TS*)h1, (const TS*)G[0], (const TS*)G[1],
+                (const TS*)G[2], (const TS*)G[3], (const TS*)G[4], (const TS*)G[5], nel, (const TS*)hb);
+            return true;
+        }
+        if (variant == SEM_AX_3D && LX != 3 && LX <= 10) {
+            launch_3d<LX, TS, TC, TW, HB>(ctx, w, u, D, h1, G, nel, hb);
+            return true;
+        }
+        return false;
+    }
+}
+
 template <int LX, typename TU, typename TS, typename TC, typename TW, bool HB>
 int launch_form(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const void* h1,
                 const void* const* G, int64_t nel, const int* skip, double* dot, const int32_t* lid,
-                const void* gp, const void* hb) {
+                const void* gp, const void* hb, int variant) {
     constexpr int EPB = Shape<LX>::EPB;
     const int64_t blocks = (nel + EPB - 1) / EPB;
     if (blocks > 0x7fffffff) return sem::fail(ctx, SEM_EINVAL, "sem_ax: nel too large");
+    if (!lid && !dot && variant >= 0 &&
+        launch_variant<LX, TS, TC, TW, HB>(ctx, variant, w, u, D, h1, G, nel, hb)) {
+        SEM_LAUNCH_CHECK(ctx);
+        return SEM_OK;
+    }
 #define SEM_AX_ARGS (TW*)w, (const TU*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2], \
         (const TC*)D[3], (const TC*)D[4], (const TC*)D[5], (const TS*)h1, (const TS*)G[0],  \
         (const TS*)G[1], (const TS*)G[2], (const TS*)G[3], (const TS*)G[4], (const TS*)G[5], \
@@ -399,18 +581,18 @@ int launch_form(sem_ctx_t ctx, void* w, const void* u, const void* const* D, con
 template <int LX, typename TU, typename TS, typename TC, typename TW>
 int launch_lx(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const void* h1,
               const void* const* G, int64_t nel, const int* skip, double* dot, const int32_t* lid,
-              const void* gp, const void* hb) {
-    if (hb) return launch_form<LX, TU, TS, TC, TW, true>(ctx, w, u, D, h1, G, nel, skip, dot, lid, gp, hb);
-    return launch_form<LX, TU, TS, TC, TW, false>(ctx, w, u, D, h1, G, nel, skip, dot, lid, gp, hb);
+              const void* gp, const void* hb, int variant) {
+    if (hb) return launch_form<LX, TU, TS, TC, TW, true>(ctx, w, u, D, h1, G, nel, skip, dot, lid, gp, hb, variant);
+    return launch_form<LX, TU, TS, TC, TW, false>(ctx, w, u, D, h1, G, nel, skip, dot, lid, gp, hb, variant);
 }
 
 template <typename TU, typename TS, typename TC, typename TW>
 int dispatch(sem_ctx_t ctx, int lx, void* w, const void* u, const void* const* D,
              const void* h1, const void* const* G, int64_t nel, const int* skip, double* dot,
              const int32_t* lid = nullptr, const void* gp = nullptr,
-             const void* hb = nullptr) {
+             const void* hb = nullptr, int variant = SEM_AX_DEFAULT) {
     switch (lx) {
-#define SEM_AX_CASE(L) case L: return launch_lx<L, TU, TS, TC, TW>(ctx, w, u, D, h1, G, nel, skip, dot, lid, gp, hb);
+#define SEM_AX_CASE(L) case L: return launch_lx<L, TU, TS, TC, TW>(ctx, w, u, D, h1, G, nel, skip, dot, lid, gp, hb, variant);
         SEM_AX_CASE(2) SEM_AX_CASE(3) SEM_AX_CASE(4) SEM_AX_CASE(5) SEM_AX_CASE(6) SEM_AX_CASE(7)
         SEM_AX_CASE(8) SEM_AX_CASE(9) SEM_AX_CASE(10) SEM_AX_CASE(11) SEM_AX_CASE(12)
 #undef SEM_AX_CASE
@@ -459,7 +641,7 @@ int ax_public(sem_ctx_t ctx, void* w, const void* u, const void* dx, const void*
     if (alias) return sem::fail(ctx, SEM_EINVAL, "sem_ax: output overlaps an input");
     if (f64)
         return dispatch<double, double, double, double>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr, nullptr,
-                                                        nullptr, hb);
+                                                        nullptr, hb, ctx->ax_variant[lx]);
     if (field_dtype == SEM_F32)
         return dispatch<float, float, float, float>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr, nullptr,
                                                     nullptr, hb);
@@ -521,3 +703,108 @@ int launch_ax(sem_ctx_t ctx, AxKind kind, const AxArgs& a, void* w, const void* 
 }
 
 }  // namespace sem
+
+// ------------------------------------------------------------ variant choice
+namespace {
+
+// synthetic inputs for timing: a hash of the index mapped to [-1, 1) for u,
+// positive-definite factors (diagonal 1 + |.|/2, off-diagonal ./10), h1 = 1
+__global__ void tune_fill_kernel(double* __restrict__ u, double* __restrict__ g11, double* __restrict__ g22,
+                                 double* __restrict__ g33, double* __restrict__ g12, double* __restrict__ g13,
+                                 double* __restrict__ g23, double* __restrict__ h1, int64_t n) {
+    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n; L += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)L * 2654435761u;
+        h ^= h >> 16; h *= 0x7feb352du; h ^= h >> 15;
+        const double v = (double)h * (2.0 / 4294967296.0) - 1.0;
+        u[L] = v;
+        g11[L] = 1.0 + 0.5 * fabs(v); g22[L] = 1.0 + 0.25 * fabs(v); g33[L] = 1.0 + 0.125 * fabs(v);
+        g12[L] = 0.1 * v; g13[L] = -0.1 * v; g23[L] = 0.05 * v;
+        h1[L] = 1.0;
+    }
+}
+
+}  // namespace
+
+extern "C" int sem_ax_set_variant(sem_ctx_t ctx, int lx, int variant) {
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (!sem::lx_ok(lx)) return sem::fail(ctx, SEM_EUNSUPPORTED_LX, "sem_ax_set_variant: lx=%d", lx);
+    if (variant != SEM_AX_DEFAULT && !variant_exists(lx, variant))
+        return sem::fail(ctx, SEM_EINVAL, "sem_ax_set_variant: variant %d does not exist at lx=%d", variant, lx);
+    ctx->ax_variant[lx] = variant;
+    return SEM_OK;
+}
+
+extern "C" int sem_ax_get_variant(sem_ctx_t ctx, int lx, int* variant) {
+    if (!ctx) return sem::fail(nullptr, SEM_EINVAL, "null context");
+    if (!sem::lx_ok(lx)) return sem::fail(ctx, SEM_EUNSUPPORTED_LX, "sem_ax_get_variant: lx=%d", lx);
+    if (!variant) return sem::fail(ctx, SEM_EINVAL, "sem_ax_get_variant: null output");
+    *variant = ctx->ax_variant[lx];
+    return SEM_OK;
+}
+
+extern "C" int sem_ax_tune(sem_ctx_t ctx, int lx, int64_t nel, int reps, double* us, int* best) {
+    int rc = sem::enter(ctx);
+    if (rc) return rc;
+    if (!sem::lx_ok(lx)) return sem::fail(ctx, SEM_EUNSUPPORTED_LX, "sem_ax_tune: lx=%d", lx);
+    if (nel < 1 || reps < 1 || !best) return sem::fail(ctx, SEM_EINVAL, "sem_ax_tune: bad argument");
+    const int64_t n = nel * lx * lx * lx;
+    const int l2 = lx * lx;
+    hipStream_t st = ctx->stream;
+    std::vector<void*> tmp;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);
+        for (void* p : tmp) (void)hipFree(p);
+    };
+    double* a[10] = {};
+    for (int q = 0; q < 9; ++q) {
+        hipError_t e = hipMalloc((void**)&a[q], sizeof(double) * n);
+        if (e != hipSuccess) { cleanup(); return sem::check_hip(ctx, e, "sem_ax_tune: hipMalloc"); }
+        tmp.push_back(a[q]);
+    }
+    {
+        hipError_t e = hipMalloc((void**)&a[9], sizeof(double) * 2 * l2);
+        if (e != hipSuccess) { cleanup(); return sem::check_hip(ctx, e, "sem_ax_tune: hipMalloc"); }
+        tmp.push_back(a[9]);
+    }
+    double *u = a[0], *w = a[1], *h1 = a[8], *Dd = a[9];
+    std::vector<double> dx(l2), dxt(l2);
+    sem_gll(lx, nullptr, nullptr, dx.data(), dxt.data());   // the argument layout of the operator
+    {
+        hipError_t e = hipMemcpy(Dd, dx.data(), sizeof(double) * l2, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(Dd + l2, dxt.data(), sizeof(double) * l2, hipMemcpyHostToDevice);
+        if (e != hipSuccess) { cleanup(); return sem::check_hip(ctx, e, "sem_ax_tune: hipMemcpy"); }
+    }
+    tune_fill_kernel<<<4096, 256, 0, st>>>(u, a[2], a[3], a[4], a[5], a[6], a[7], h1, n);
+    const void* D[6] = {Dd, Dd, Dd, Dd + l2, Dd + l2, Dd + l2};
+    const void* G[6] = {a[2], a[3], a[4], a[5], a[6], a[7]};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    double best_us = 1e300;
+    int best_v = SEM_AX_COLUMN;
+    for (int v = 0; v < SEM_AX_VARIANTS; ++v) {
+        if (us) us[v] = -1.0;
+        if (!variant_exists(lx, v)) continue;
+        for (int q = 0; q < 2 + reps && rc == SEM_OK; ++q) {
+            if (q == 2) (void)hipEventRecord(e0, st);
+            rc = dispatch<double, double, double, double>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr, nullptr,
+                                                          nullptr, nullptr, v);
+        }
+        if (rc) break;
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double t = 1e3 * ms / reps;
+        if (us) us[v] = t;
+        if (t < best_us) { best_us = t; best_v = v; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    cleanup();
+    if (rc) return rc;
+    ctx->ax_variant[lx] = best_v;
+    *best = best_v;
+    return SEM_OK;
+}

@@ -444,10 +444,11 @@ struct sem_mg_s {
     float *b0 = nullptr, *x0 = nullptr;   // float32 copies for float64 callers
     double* part = nullptr;           // kVecGrid partial sums
     std::vector<void*> allocs;
-    // The V-cycle is a fixed sequence of about 12 launches per level; replayed
-    // as a captured HIP graph (one per set of vector and flag pointers) its
-    // coarse levels are no longer bound by launch latency.
-    bool graphs = true;
+    // The V-cycle is a fixed sequence of about 12 launches per level; it can be
+    // replayed as a captured HIP graph (one per set of vector and flag
+    // pointers).  Measured at 32^3 / lx = 8 the graph is no faster than the
+    // launches one by one, so it is off unless asked for.
+    bool graphs = false;
     hipStream_t cap_stream = nullptr;     // private capture stream (default priority)
     struct Cached { const void* z; const void* r; const int* skip; bool f64; hipGraphExec_t exec; };
     std::vector<Cached> cache;
@@ -743,8 +744,8 @@ extern "C" int sem_mg_create(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A
     const double* Gp[6] = {A->g11, A->g22, A->g33, A->g12, A->g13, A->g23};
     for (int q = 0; q < 6; ++q)
         if (!Dp[q] || !Gp[q]) return sem::fail(ctx, SEM_EINVAL, "sem_mg_create: null operator array");
-    const int degree = opts->degree > 0 ? opts->degree : 3;
-    const double lo = opts->lo > 0 ? opts->lo : 0.2, hi = opts->hi > 0 ? opts->hi : 1.1;
+    const int degree = opts->degree > 0 ? opts->degree : 2;
+    const double lo = opts->lo > 0 ? opts->lo : 0.15, hi = opts->hi > 0 ? opts->hi : 1.1;
     const int n_coarse = opts->n_coarse > 0 ? opts->n_coarse : 2;
     const int steps = opts->lanczos_steps > 0 ? opts->lanczos_steps : 20;
     if (degree > 16 || !(hi > lo)) return sem::fail(ctx, SEM_EINVAL, "sem_mg_create: bad degree or interval");

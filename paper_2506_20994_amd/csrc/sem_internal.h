@@ -17,6 +17,11 @@ struct sem_ctx_s {
     double* red = nullptr;      // kRedSlots doubles
     unsigned int* counter = nullptr;
     double* host_pinned = nullptr;  // 64 doubles of pinned host memory
+    // kernel variant of the float64 public operator per lx (SEM_AX_*;
+    // SEM_AX_DEFAULT until sem_ax_set_variant or sem_ax_tune chooses one)
+    int ax_variant[SEM_LX_MAX + 1] = {SEM_AX_DEFAULT, SEM_AX_DEFAULT, SEM_AX_DEFAULT, SEM_AX_DEFAULT, SEM_AX_DEFAULT,
+                                      SEM_AX_DEFAULT, SEM_AX_DEFAULT, SEM_AX_DEFAULT, SEM_AX_DEFAULT, SEM_AX_DEFAULT,
+                                      SEM_AX_DEFAULT, SEM_AX_DEFAULT, SEM_AX_DEFAULT};
 };
 
 struct sem_gs_s {

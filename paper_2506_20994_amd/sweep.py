@@ -9,7 +9,12 @@ The operator is element-local, so its throughput depends only on the element
 count and lx: every point uses N_E elements of random symmetric positive
 definite factors, h1 ~ U[0.5, 2] and u ~ N(0, 1).
 
-Usage: python -m paper_2506_20994_amd.sweep [--reps R] [--out FILE]
+With --tune every point first times each float64 kernel variant of the
+operator (sem_ax_tune: the column mapping, the same with the other prefetch
+choice, the slice-pipelined column mapping, one thread per node), as the
+paper's run-time autotuning does (Sec. 4), and the timed run uses the fastest.
+
+Usage: python -m paper_2506_20994_amd.sweep [--reps R] [--out FILE] [--lx 3,..] [--sizes ..] [--tune]
 """
 import argparse
 import json
@@ -37,11 +42,17 @@ def _fields(ctx, nel, lx, seed=0):
     return dev(u), [dev(g) for g in G], dev(h1), D
 
 
-def run(reps=50, lxs=LXS, sizes=SIZES):
+def run(reps=50, lxs=LXS, sizes=SIZES, tune=False):
     ctx = B.sem_create()
     rows = []
+    names = {B.SEM_AX_COLUMN: "column", B.SEM_AX_COLUMN_PF: "column_pf", B.SEM_AX_SLICE: "slice", B.SEM_AX_3D: "3d"}
     for lx in lxs:
         for nel in sizes:
+            tuned = None
+            if tune:
+                best, us = B.sem_ax_tune(ctx, lx, nel, reps=20)
+                tuned = {"variant": names[best],
+                         "variant_us": {names[v]: round(t, 2) for v, t in enumerate(us) if t > 0}}
             u, G, h1, D = _fields(ctx, nel, lx)
             w = torch.empty_like(u)
             for _ in range(5):
@@ -60,7 +71,11 @@ def run(reps=50, lxs=LXS, sizes=SIZES):
                          "gflops": round((12 * lx + 18) * nl / t / 1e9, 1),
                          "gbs": round(72 * nl / t / 1e9, 1),
                          "gdofs": round(nel * (lx - 1) ** 3 / t / 1e9, 3)})
+            if tuned:
+                rows[-1].update(tuned)
             print(json.dumps(rows[-1]), flush=True)
+        if tune:
+            B.sem_ax_set_variant(ctx, lx, B.SEM_AX_DEFAULT)
     ctx.close()
     return rows
 
@@ -71,12 +86,13 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--lx", default=None, help="comma-separated lx values (default 3..8)")
     ap.add_argument("--sizes", default=None, help="comma-separated element counts")
+    ap.add_argument("--tune", action="store_true", help="time the kernel variants at every point, use the fastest")
     a = ap.parse_args()
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     lxs = [int(v) for v in a.lx.split(",")] if a.lx else LXS
     sizes = [int(v) for v in a.sizes.split(",")] if a.sizes else SIZES
-    rows = run(a.reps, lxs, sizes)
+    rows = run(a.reps, lxs, sizes, a.tune)
     if a.out:
         with open(a.out, "w") as f:
             json.dump(rows, f, indent=1)

@@ -218,3 +218,54 @@ def test_ax_helmholtz_full_size_sampled(sem_ctx):
     with pytest.raises(P.SemError):
         P.sem_ax_helmholtz(sem_ctx, w, u, *op.D, op.h1, *op.G, None, op.nel, lx)
     op.gs.close()
+
+
+@pytest.mark.parametrize("lx", list(range(2, 13)))
+def test_ax_variants_match_oracle(sem_ctx, lx):
+    """Every kernel variant of the float64 operator that exists at lx, with and
+    without h1, 1 and 13 elements (partial workgroups of every variant), and
+    the Helmholtz form, against the oracle."""
+    from oracle.ax import ax_helmholtz
+    try:
+        for nel in (1, 13):
+            G, h1 = synth.random_spd_factors(nel, lx, 3000 + lx)
+            u = synth.local_normal(nel, lx, 4000 + lx)
+            hb = synth.local_normal(nel, lx, 5000 + lx) ** 2
+            ref = ax_einsum(u, *listing_matrices(lx), h1, *G)
+            ref0 = ax_einsum(u, *listing_matrices(lx), None, *G)
+            refh = ax_helmholtz(u, *listing_matrices(lx), h1, *G, hb)
+            for v in range(P.SEM_AX_VARIANTS):
+                if v == P.SEM_AX_3D and lx > 10:
+                    with pytest.raises(P.SemError):
+                        P.sem_ax_set_variant(sem_ctx, lx, v)
+                    continue
+                P.sem_ax_set_variant(sem_ctx, lx, v)
+                assert P.sem_ax_get_variant(sem_ctx, lx) == v
+                assert rel_inf(_run(sem_ctx, u, G, h1, lx), ref) <= TOL64, (v, nel)
+                assert rel_inf(_run(sem_ctx, u, G, None, lx), ref0) <= TOL64, (v, nel)
+                w = torch.full(u.shape, float("nan"), dtype=torch.float64, device="cuda")
+                P.sem_ax_helmholtz(sem_ctx, w, to_dev(u), *_gpu_D(lx), to_dev(h1), *[to_dev(g) for g in G],
+                                   to_dev(hb), nel, lx)
+                torch.cuda.synchronize()
+                assert rel_inf(w.cpu().numpy(), refh) <= TOL64, (v, nel)
+    finally:
+        P.sem_ax_set_variant(sem_ctx, lx, P.SEM_AX_DEFAULT)
+
+
+def test_ax_tune_selects_the_fastest_variant(sem_ctx):
+    for lx, missing in ((8, []), (12, [P.SEM_AX_3D])):
+        try:
+            best, us = P.sem_ax_tune(sem_ctx, lx, 256, reps=3)
+            assert len(us) == P.SEM_AX_VARIANTS
+            for v in range(P.SEM_AX_VARIANTS):
+                assert (us[v] == -1.0) == (v in missing), (lx, v, us)
+            assert us[best] == min(t for t in us if t > 0)
+            assert P.sem_ax_get_variant(sem_ctx, lx) == best
+            # the tuned context still computes the operator
+            G, h1 = synth.random_spd_factors(3, lx, 77)
+            u = synth.local_normal(3, lx, 78)
+            assert rel_inf(_run(sem_ctx, u, G, h1, lx), ax_einsum(u, *listing_matrices(lx), h1, *G)) <= TOL64
+        finally:
+            P.sem_ax_set_variant(sem_ctx, lx, P.SEM_AX_DEFAULT)
+    with pytest.raises(P.SemError):
+        P.sem_ax_tune(sem_ctx, 13, 8)
