@@ -36,14 +36,26 @@ Extra fields:
                 solve; constant plus Fourier source, no projection) on the
                 periodic 32^3 box: float64 Jacobi-PCG against float32 residual
                 replacement, and flexible CG with the classical block.
+  mg_*          (in solve, dirichlet, helmholtz_solve) the same solves with the
+                multigrid V-cycle in flexible CG; solve also reports how the
+                iteration counts grow from the 16^3 to the 32^3 box.
+  learned.as_written_network_f32_rr  the 518-256-256-512 ReLU network with
+                geometric inputs and MSE loss, trained on about 20k element pairs
+                from Fourier right-hand sides, inside float32 residual replacement.
+  box_64cubed   the full stack at scale: the 64^3 box (E = 262144, 134M local
+                nodes, amplitude 0.15) at lx = 8: float64 Jacobi-PCG against
+                float32 residual replacement with the network and with the
+                V-cycle (--no-big skips it).
+  Each solve's err_vs_oracle is the relative 2-norm error against the oracle's
+  own solution at 1024 sampled nodes (tests/golden).
 
 --mode copy times a plain 1 GiB device copy (used to calibrate the HBM byte
 counters of rocprofv3); it prints nothing on stdout.  --mode trials prints one
 JSON line with five trials of the operator (200 launches each, HIP events) and
 five of a 1 GiB device copy, for the median / min and the fraction of the
-measured copy bandwidth.  --mode scale runs the
-full stack on a 64^3 box (lx 8 and 10; several minutes) and prints one JSON
-line of its own.
+measured copy bandwidth.  --mode scale runs the full stack on a 64^3 box (lx 8
+and 10; several minutes) and prints one JSON line of its own.  --mode mg times
+the multigrid solves of the 32^3 box (--sweep: over the V-cycle's parameters).
 """
 import argparse
 import hashlib
@@ -335,7 +347,7 @@ def helmholtz_solve_comparison(ctx, P, n, lx, amp, h2=1e3, tol=1e-10):
     return res
 
 
-def learned_comparison(ctx, P, n, lx, amp, solve=None, tol=1e-10, keep=False):
+def learned_comparison(ctx, P, n, lx, amp, solve=None, tol=1e-10, keep=False, max_rows=None):
     """Train the per-element network (linear form, energy-norm loss, Jacobi
     base) on the GPU from float64 Jacobi-PCG pairs on 16^3 boxes (random
     amplitudes U[0, 0.2], white-noise right-hand sides: residual b, error x*),
@@ -346,7 +358,7 @@ def learned_comparison(ctx, P, n, lx, amp, solve=None, tol=1e-10, keep=False):
     import synth
     from paper_2506_20994_amd.box import BoxOperator
     from paper_2506_20994_amd import learned as LR
-    lp = P.sem_lp_create(ctx, n ** 3)
+    lp = P.sem_lp_create(ctx, max(n ** 3, max_rows or 0))
     LR.init_network(lp, 7, mu=1.0, jacobi_base=True, out_scale=0.0, linear=True)
     t0 = time.perf_counter()
     X, T, info = LR.generate(ctx, lp, n=16, boxes=128, snapshots=1, elems_per_snapshot=4096,
@@ -409,9 +421,33 @@ def learned_comparison(ctx, P, n, lx, amp, solve=None, tol=1e-10, keep=False):
           flush=True)
     cg.close()
     blk.close()
+    # the network exactly as the workload states it: 518 -> 256 -> 256 -> 512 with
+    # ReLU, geometric inputs, biases, MSE loss, trained on about 20k element pairs
+    # from float64 Jacobi-PCG snapshots of Fourier right-hand sides on 16^3 boxes
+    t0 = time.perf_counter()
+    nl = P.sem_lp_create(ctx, n ** 3)
+    LR.init_network(nl, 11, mu=-1.0, jacobi_base=False, out_scale=1.0, linear=False)
+    Xn, Tn, infon = LR.generate(ctx, nl, n=16, boxes=20, snapshots=16, elems_per_snapshot=64, seed=300,
+                                rhs="fourier")
+    histn = LR.train(nl, Xn, Tn, epochs=60, batch=1024, lr=1e-3)
+    del Xn, Tn
+    torch.cuda.empty_cache()
+    op.bind(nl)
+    ms, st = _timed_solve(P, op, x, b, P.SEM_SOLVE_F32_IR, 1, nl, tol)
+    res["as_written_network_f32_rr"] = {
+        "network": "518-256-256-512 ReLU, geometric inputs, MSE, Fourier pairs", "rows": infon["rows"],
+        "train_s": round(time.perf_counter() - t0, 2), "loss_first_epoch": histn[0], "loss_last_epoch": histn[-1],
+        "ms": round(ms, 2), "iterations": st["iterations"], "jacobi_steps": st["jacobi_steps"],
+        "fell_back": st["fell_back"], "relres": st["relres"], "converged": st["converged"],
+        "err_vs_oracle": gold.error(x)}
+    print(f"[bench] learned as_written_network_f32_rr: {ms:.1f} ms, {st['iterations']} its, "
+          f"{st['jacobi_steps']} Jacobi, fell back {st['fell_back']}", file=sys.stderr, flush=True)
+    nl.close()
+    op.bind(lp)
     variants = variants + (("classical_block_f32_rr", None, None, None),)
     base = res["jacobi_pcg_f64"]["ms"]
     res["speedup_vs_fp64_pcg"] = {v[0]: round(base / res[v[0]]["ms"], 3) for v in variants[1:]}
+    res["speedup_vs_fp64_pcg"]["as_written_network_f32_rr"] = round(base / res["as_written_network_f32_rr"]["ms"], 3)
     if solve:    # the same precision without the network: what the network adds
         res["speedup_vs_same_precision_without_network"] = {
             "f32_rr": round(solve["f32_rr"]["ms"] / res["learned_f32_rr"]["ms"], 3),
@@ -466,6 +502,56 @@ def trials_run(P, n, lx, amp, trials=5, reps=200):
             "frac_of_hbm_peak": round(med / HBM_PEAK_GBS, 4),
             "copy_gbs": [round(v, 1) for v in copy_gbs], "copy_gbs_median": round(statistics.median(copy_gbs), 1),
             "frac_of_measured_copy": round(med / statistics.median(copy_gbs), 4)}
+
+
+def big_box_comparison(ctx, P, lp, lx=8, n=64, amp=0.15, tol=1e-10, fp64=True):
+    """The full stack at scale: the 64^3 box (E = 262144, amplitude 0.15; 134M
+    local nodes at lx = 8), Poisson solve to 1e-10 with float32 residual
+    replacement plus the network trained for the 32^3 solves (lx = 8), and with
+    the multigrid V-cycle, against float64 Jacobi-PCG (solved once: 30 s)."""
+    import torch
+    import synth
+    from paper_2506_20994_amd.box import BoxOperator
+    t0 = time.perf_counter()
+    op = BoxOperator(ctx, n, lx, amp, keep_coords=True)
+    k, a, ph = synth.fourier_modes(2)
+    b = op.fourier_rhs(k, a, ph)
+    op.x = op.y = op.z = None
+    x = torch.empty_like(b)
+    torch.cuda.synchronize()
+    res = {"workload": f"{n}^3 periodic box lx={lx} amplitude {amp}, h1=1, 32 Fourier modes, tol {tol}",
+           "n_local": op.n_local, "unique_dofs": op.n_unique, "setup_s": round(time.perf_counter() - t0, 2)}
+    runs = []
+    if fp64:
+        runs.append(("fp64_pcg", P.SEM_SOLVE_F64, 0, None, None, False))
+    if lp is not None and lx == 8:
+        op.bind(lp)
+        runs.append(("learned_f32_rr", P.SEM_SOLVE_F32_IR, 1, lp, None, False))
+    mg = op.multigrid(n_coarse=8)
+    runs.append(("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1, None, mg, True))
+    for name, code, mode, L, m, warm in runs:
+        kw = dict(tol=tol, precision=code, ir_mode=mode, learned=L, mg=m, maxit=200000)
+        cg = op.solver(code, learned=L, mg=m)
+        if warm:
+            P.sem_cg_solve(cg, x, b, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rc, st = P.sem_cg_solve(cg, x, b, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3
+        cg.close()
+        res[name] = {"ms": round(ms, 1), "iterations": st["iterations"], "relres": st["relres"],
+                     "converged": st["converged"], "jacobi_steps": st["jacobi_steps"], "fell_back": st["fell_back"]}
+        print(f"[bench] {n}^3 lx={lx} {name}: {ms:.0f} ms, {st['iterations']} its, relres {st['relres']:.2e}",
+              file=sys.stderr, flush=True)
+    mg.close()
+    if "fp64_pcg" in res:
+        base = res["fp64_pcg"]["ms"]
+        res["speedup_vs_fp64_pcg"] = {r[0]: round(base / res[r[0]]["ms"], 3) for r in runs[1:]}
+    op.gs.close()
+    del op, b, x
+    torch.cuda.empty_cache()
+    return res
 
 
 def mg_run(ctx, P, n, lx, amp, tol=1e-10, sweep=False, repeat=3):
@@ -563,11 +649,15 @@ def scale_run(ctx, P, n=64, amp=0.15, tol=1e-10):
             op.bind(lp)
             variants += [("learned_f32_rr", P.SEM_SOLVE_F32_IR, 1, lp),
                          ("learned_bf16_rr", P.SEM_SOLVE_BF16_IR, 1, lp)]
+        mg = op.multigrid(n_coarse=8)
+        variants += [("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1, "mg"), ("mg_fcg_f64", P.SEM_SOLVE_F64, 0, "mg")]
         for name, code, mode, L in variants:
-            cg = op.solver(code, learned=L)
+            M = mg if L == "mg" else None
+            L = None if L == "mg" else L
+            cg = op.solver(code, learned=L, mg=M)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            rc, st = P.sem_cg_solve(cg, x, b, tol=tol, precision=code, ir_mode=mode, learned=L, maxit=200000)
+            rc, st = P.sem_cg_solve(cg, x, b, tol=tol, precision=code, ir_mode=mode, learned=L, mg=M, maxit=200000)
             torch.cuda.synchronize()
             r[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 1), "iterations": st["iterations"],
                        "relres": st["relres"], "converged": st["converged"],
@@ -576,6 +666,7 @@ def scale_run(ctx, P, n=64, amp=0.15, tol=1e-10):
                   file=sys.stderr, flush=True)
             cg.close()
         r["speedup_vs_fp64_pcg"] = {v[0]: round(r["fp64_pcg"]["ms"] / r[v[0]]["ms"], 3) for v in variants[1:]}
+        mg.close()
         res[f"lx{lx}"] = r
         op.gs.close()
         del op, b, x
@@ -595,6 +686,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-big", action="store_true", help="skip the 64^3 box solves (about a minute)")
     ap.add_argument("--no-helmholtz", action="store_true",
                     help="skip the Helmholtz timing (it launches the same kernel as sem_ax)")
     ap.add_argument("--mode", default="bench", choices=["bench", "copy", "scale", "trials", "mg"])
@@ -737,8 +829,11 @@ def main():
         out["solve"] = solve_comparison(ctx, P, n, lx, amp)
         lp = None
         if not args.no_learned and lx == 8:
-            out["learned"], lp = learned_comparison(ctx, P, n, lx, amp, solve=out["solve"], keep=True)
+            out["learned"], lp = learned_comparison(ctx, P, n, lx, amp, solve=out["solve"], keep=True,
+                                                    max_rows=None if args.no_big else 64 ** 3)
         out["dirichlet"] = dirichlet_comparison(ctx, P, n, lx, amp, lp)
+        if not args.no_big:
+            out["box_64cubed"] = big_box_comparison(ctx, P, lp, lx)
         if lp is not None:
             lp.close()
         out["helmholtz_solve"] = helmholtz_solve_comparison(ctx, P, n, lx, amp)

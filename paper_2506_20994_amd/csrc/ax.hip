@@ -483,13 +483,13 @@ constexpr bool variant_exists(int lx, int v) {
 
 template <int LX, typename TS, typename TC, typename TW, bool HB, bool PF>
 void launch_column(sem_ctx_t ctx, void* w, const void* u, const void* const* D, const void* h1,
-                   const void* const* G, int64_t nel) {
+                   const void* const* G, int64_t nel, const void* hb) {
     constexpr int EPB = Shape<LX>::EPB;
     ax_kernel<LX, EPB, TS, TS, TC, TW, false, false, HB, PF><<<(unsigned)((nel + EPB - 1) / EPB), EPB * LX * LX, 0,
                                                                ctx->stream>>>(
         (TW*)w, (const TS*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2], (const TC*)D[3], (const TC*)D[4],
         (const TC*)D[5], (const TS*)h1, (const TS*)G[0], (const TS*)G[1], (const TS*)G[2], (const TS*)G[3],
-        (const TS*)G[4], (const TS*)G[5], nel, nullptr, nullptr, nullptr, nullptr, nullptr);
+        (const TS*)G[4], (const TS*)G[5], nel, nullptr, nullptr, nullptr, nullptr, (const TS*)hb);
 }
 
 template <int LX, typename TS, typename TC, typename TW, bool HB>
@@ -512,11 +512,11 @@ bool launch_variant(sem_ctx_t ctx, int variant, void* w, const void* u, const vo
         return false;
     } else {
         if (variant == SEM_AX_COLUMN_PF) {
-            launch_column<LX, TS, TC, TW, HB, !Shape<LX>::kPrefetch>(ctx, w, u, D, h1, G, nel);
+            launch_column<LX, TS, TC, TW, HB, !Shape<LX>::kPrefetch>(ctx, w, u, D, h1, G, nel, hb);
             return true;
         }
         if (variant == SEM_AX_COLUMN) {
-            launch_column<LX, TS, TC, TW, HB, Shape<LX>::kPrefetch>(ctx, w, u, D, h1, G, nel);
+            launch_column<LX, TS, TC, TW, HB, Shape<LX>::kPrefetch>(ctx, w, u, D, h1, G, nel, hb);
             return true;
         }
         if (variant == SEM_AX_SLICE) {

@@ -39,13 +39,10 @@ extern "C" int sem_create(sem_ctx_t* out, void* stream) {
     auto* c = new sem_ctx_s();
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipMalloc(&c->red, sizeof(double) * sem::kRedSlots);
-    if (e == hipSuccess) e = hipMalloc(&c->counter, sizeof(unsigned int) * 64);
-    if (e == hipSuccess) e = hipMemset(c->counter, 0, sizeof(unsigned int) * 64);
     if (e == hipSuccess) e = hipHostMalloc(&c->host_pinned, sizeof(double) * 64, hipHostMallocDefault);
     if (e != hipSuccess) {
         int rc = sem::check_hip(nullptr, e, "sem_create");
         if (c->red) (void)hipFree(c->red);
-        if (c->counter) (void)hipFree(c->counter);
         delete c;
         return rc;
     }
@@ -59,7 +56,6 @@ extern "C" int sem_destroy(sem_ctx_t ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->red) (void)hipFree(ctx->red);
-    if (ctx->counter) (void)hipFree(ctx->counter);
     if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
     delete ctx;
     return SEM_OK;

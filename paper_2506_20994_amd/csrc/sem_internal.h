@@ -15,7 +15,6 @@ struct sem_ctx_s {
     std::string err;
     // small device workspace for reductions: partial sums and scalars
     double* red = nullptr;      // kRedSlots doubles
-    unsigned int* counter = nullptr;
     double* host_pinned = nullptr;  // 64 doubles of pinned host memory
     // kernel variant of the float64 public operator per lx (SEM_AX_*;
     // SEM_AX_DEFAULT until sem_ax_set_variant or sem_ax_tune chooses one)
