@@ -15,6 +15,11 @@ Readings taken (none is fixed by the paper):
     even and n/2 >= n_coarse; the last level is solved exactly;
   * each level's operator is re-discretised on the same deformed box
     (oracle.solve.BoxProblem at that n and lx; h1 = 1, Helmholtz h2 B_l);
+    where a coarse level's isoparametric geometry folds (det J <= 0 at some
+    node: coarse trilinear elements resolve the sine map poorly, e.g. at
+    amplitude 0.15), that level takes the amplitude halved until it does not
+    (``level_amplitude``) -- any positive definite coarse operator keeps the
+    V-cycle a valid preconditioner;
   * transfer P: the coarse level's continuous field evaluated at the fine
     level's nodes -- p: the coarse Lagrange basis at the fine GLL points of
     the same element; h: the parent element's trilinear basis at the child's
@@ -52,6 +57,19 @@ def level_shapes(n, lx, n_coarse=2):
         n //= 2
     out.append((n, lx, None))
     return out
+
+
+def level_amplitude(n, lx, a, dirichlet=False, max_halvings=20):
+    """The largest a / 2^m (m >= 0) whose box of n^3 elements at lx has det J >
+    0 at every node (0 after max_halvings)."""
+    from .mesh import box_coords
+    from .geometry import geometric_factors
+    for _ in range(max_halvings + 1):
+        _, _, dj = geometric_factors(*box_coords(n, lx, a), lx)
+        if np.min(dj) > 0.0:
+            return a
+        a *= 0.5
+    return 0.0
 
 
 def p_matrix(lx_f, lx_c):
@@ -134,9 +152,11 @@ class Hierarchy:
         from .assemble import assembled_matrix
         self.shapes = level_shapes(n, lx, n_coarse)
         self.degree, self.lo, self.hi = degree, lo, hi
-        self.boxes, self.A, self.dinv, self.P, self.lmax = [], [], [], [], []
-        for nl, lxl, _ in self.shapes:
-            B = BoxProblem(nl, lxl, a, dirichlet=dirichlet, h2=h2)
+        self.boxes, self.A, self.dinv, self.P, self.lmax, self.amps = [], [], [], [], [], []
+        for q, (nl, lxl, _) in enumerate(self.shapes):
+            al = a if q == 0 else level_amplitude(nl, lxl, a, dirichlet)
+            self.amps.append(al)
+            B = BoxProblem(nl, lxl, al, dirichlet=dirichlet, h2=h2)
             A = assembled_matrix(B.Dh, None, B.G, B.ids, B.nu)
             if h2 is not None:
                 from .gs import gather

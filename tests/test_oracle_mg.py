@@ -145,3 +145,30 @@ def test_vcycle_preconditioner_is_mesh_independent(dirichlet):
         assert it < 0.5 * itj
         its.append(it)
     assert its[1] <= 1.5 * its[0], its
+
+
+def test_folding_coarse_levels_take_a_halved_amplitude():
+    """At amplitude 0.15 the lx = 2 box of 4^3 elements folds (its vertex
+    Jacobians go negative), the lx = 4 one does not: the hierarchy keeps 0.15
+    on the levels that stay unfolded and halves it on the one that folds,
+    exactly as often as needed (the amplitude taken has det J > 0, twice it
+    does not); the V-cycle stays an SPD preconditioner that beats Jacobi."""
+    from oracle.mesh import box_coords
+    from oracle.geometry import geometric_factors
+    H = mg.Hierarchy(4, 4, 0.15, dirichlet=True)
+    assert [s[:2] for s in H.shapes] == [(4, 4), (4, 2), (2, 2)]
+    assert H.amps[0] == 0.15 and H.amps[2] == 0.15
+    a1 = H.amps[1]
+    assert 0 < a1 < 0.15 and 0.15 / a1 == 2 ** round(np.log2(0.15 / a1))
+    assert np.min(geometric_factors(*box_coords(4, 2, a1), 2)[2]) > 0
+    assert np.min(geometric_factors(*box_coords(4, 2, 2 * a1), 2)[2]) <= 0
+    V = H.matrix()
+    assert np.allclose(V, V.T, rtol=0, atol=1e-12 * np.abs(V).max())
+    assert np.linalg.eigvalsh(0.5 * (V + V.T))[0] > 0
+    B = H.boxes[0]
+    k, a, ph = synth.fourier_modes(2, kmax=2)
+    b = B.fourier_rhs(k, a, ph)
+    x, it, _ = fcg1(B.apply, b, H.vcycle, tol=1e-10, project=B.project)
+    assert np.linalg.norm(b - B.apply(x)) <= 1.2e-10 * np.linalg.norm(b)
+    _, itj, _ = pcg(B.apply, b, 1.0 / B.diagonal(), tol=1e-10, project=B.project)
+    assert it < 0.5 * itj
