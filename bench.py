@@ -528,6 +528,7 @@ def big_box_comparison(ctx, P, lp, lx=8, n=64, amp=0.15, tol=1e-10, fp64=True):
         op.bind(lp)
         runs.append(("learned_f32_rr", P.SEM_SOLVE_F32_IR, 1, lp, None, False))
     mg = op.multigrid(n_coarse=8)
+    res["mg_levels"] = [list(P.sem_mg_level_info(mg, q)) for q in range(P.sem_mg_levels(mg))]
     runs.append(("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1, None, mg, True))
     for name, code, mode, L, m, warm in runs:
         kw = dict(tol=tol, precision=code, ir_mode=mode, learned=L, mg=m, maxit=200000)

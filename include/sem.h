@@ -358,7 +358,9 @@ int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_solve_opts_t
  * then the lx = 2 box n^3 -> (n/2)^3 while n is even and n/2 >= n_coarse
  * (h-coarsening).  Each level below the first is re-discretised by the
  * library's set-up calls on the same deformed box (h1 = 1; h2 times that
- * level's mass for Helmholtz operators).  Transfer: the coarse level's field
+ * level's mass for Helmholtz operators); a level whose geometry would fold
+ * (det J <= 0 at a node: coarse trilinear elements of a strongly deformed box)
+ * takes the amplitude halved until it does not.  Transfer: the coarse level's field
  * evaluated at the fine level's nodes (the coarse Lagrange basis on the same
  * element; the parent's trilinear basis); restriction by its transpose.
  * Smoothing: `degree` steps of the Chebyshev semi-iteration in D^-1 A (D the
@@ -391,9 +393,11 @@ int sem_mg_create(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A, const sem
 int sem_mg_destroy(sem_mg_t mg);
 /* Number of levels (host out). */
 int sem_mg_levels(sem_mg_t mg, int* count);
-/* Level `level` (0 = the caller's): elements per side, lx, unknowns, and the
- * estimated lmax of D^-1 A (0 on the coarsest level).  Any out may be NULL. */
-int sem_mg_level_info(sem_mg_t mg, int level, int* n, int* lx, int64_t* n_unique, double* lmax);
+/* Level `level` (0 = the caller's): elements per side, lx, unknowns, the
+ * estimated lmax of D^-1 A (0 on the coarsest level) and the deformation
+ * amplitude of the level's box.  Any out may be NULL. */
+int sem_mg_level_info(sem_mg_t mg, int level, int* n, int* lx, int64_t* n_unique, double* lmax,
+                      double* amp);
 /* Replace the lmax of a smoothed level (every level but the coarsest). */
 int sem_mg_set_lmax(sem_mg_t mg, int level, double lmax);
 /* Launch mode of the V-cycle (default off): replay it as a HIP graph captured

@@ -135,7 +135,7 @@ EXPORTS = {
     "sem_mg_create": (_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
     "sem_mg_destroy": (_int, [_vp]),
     "sem_mg_levels": (_int, [_vp, ctypes.POINTER(_int)]),
-    "sem_mg_level_info": (_int, [_vp, _int, ctypes.POINTER(_int), ctypes.POINTER(_int), _pi64, _pdbl]),
+    "sem_mg_level_info": (_int, [_vp, _int, ctypes.POINTER(_int), ctypes.POINTER(_int), _pi64, _pdbl, _pdbl]),
     "sem_mg_set_lmax": (_int, [_vp, _int, _dbl]),
     "sem_mg_apply": (_int, [_vp, _vp, _vp, _int]),
     "sem_mg_set_graphs": (_int, [_vp, _int]),
@@ -612,11 +612,11 @@ def sem_mg_levels(mg):
 
 
 def sem_mg_level_info(mg, level):
-    """(n, lx, n_unique, lmax) of a level"""
-    n, lx, nu, lm = _int(0), _int(0), _i64(0), _dbl(0.0)
+    """(n, lx, n_unique, lmax, amplitude) of a level"""
+    n, lx, nu, lm, am = _int(0), _int(0), _i64(0), _dbl(0.0), _dbl(0.0)
     _check(lib().sem_mg_level_info(mg.handle, level, ctypes.byref(n), ctypes.byref(lx), ctypes.byref(nu),
-                                   ctypes.byref(lm)), mg.ctx.handle)
-    return n.value, lx.value, nu.value, lm.value
+                                   ctypes.byref(lm), ctypes.byref(am)), mg.ctx.handle)
+    return n.value, lx.value, nu.value, lm.value, am.value
 
 
 def sem_mg_set_lmax(mg, level, lmax):

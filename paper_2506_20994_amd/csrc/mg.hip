@@ -419,6 +419,7 @@ void lagrange_matrix(const std::vector<double>& xf, const std::vector<double>& x
 
 struct MgLevel {
     int n = 0, lx = 0;
+    double amp = 0.0;                 // deformation amplitude of this level's box
     int64_t nel = 0, nloc = 0, nu = 0;
     sem_gs_t gs = nullptr;
     bool own_gs = false;
@@ -807,6 +808,7 @@ extern "C" int sem_mg_create(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A
         MG_TMP(dl, sizeof(double) * nloc);
         if (q == 0) {
             lv.gs = gs;
+            lv.amp = opts->amp;
             for (int a = 0; a < 6; ++a) { D64[a] = Dp[a]; G64[a] = Gp[a]; }
             hb64 = A->h2b;
         } else {
@@ -820,10 +822,19 @@ extern "C" int sem_mg_create(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A
             MG_TMP(ids, sizeof(int64_t) * nloc);
             for (int a = 0; a < 6; ++a) MG_TMP(G[a], sizeof(double) * nloc);
             MG_TMP(Dd, sizeof(double) * 2 * l2);
-            MG_TTRY(opts->dirichlet ? sem_box_mesh_dirichlet(ctx, lv.n, lx, opts->amp, x, y, z, ids)
-                                    : sem_box_mesh(ctx, lv.n, lx, opts->amp, x, y, z, ids));
-            double mindet = 0.0;
-            MG_TTRY(sem_geometry(ctx, x, y, z, lv.nel, lx, G[0], G[1], G[2], G[3], G[4], G[5], bm, &mindet));
+            // a level whose geometry folds (coarse trilinear elements of a strongly
+            // deformed box) takes the amplitude halved until det J > 0 everywhere
+            double amp = opts->amp, mindet = 0.0;
+            for (int halvings = 0;; ++halvings) {
+                MG_TTRY(opts->dirichlet ? sem_box_mesh_dirichlet(ctx, lv.n, lx, amp, x, y, z, ids)
+                                        : sem_box_mesh(ctx, lv.n, lx, amp, x, y, z, ids));
+                const int grc = sem_geometry(ctx, x, y, z, lv.nel, lx, G[0], G[1], G[2], G[3], G[4], G[5], bm,
+                                             &mindet);
+                if (grc == SEM_EGEOMETRY && halvings < 20) { amp = halvings == 19 ? 0.0 : 0.5 * amp; continue; }
+                MG_TTRY(grc);
+                break;
+            }
+            lv.amp = amp;
             std::vector<int64_t> hids(nloc);
             MG_TTRY(sem::check_hip(ctx, hipStreamSynchronize(st), "sem_mg_create: hipStreamSynchronize"));
             MG_TTRY(sem::check_hip(ctx, hipMemcpy(hids.data(), ids, sizeof(int64_t) * nloc, hipMemcpyDeviceToHost),
@@ -973,7 +984,8 @@ extern "C" int sem_mg_levels(sem_mg_t mg, int* count) {
     return SEM_OK;
 }
 
-extern "C" int sem_mg_level_info(sem_mg_t mg, int level, int* n, int* lx, int64_t* n_unique, double* lmax) {
+extern "C" int sem_mg_level_info(sem_mg_t mg, int level, int* n, int* lx, int64_t* n_unique, double* lmax,
+                                 double* amp) {
     if (!mg) return sem::fail(nullptr, SEM_EINVAL, "sem_mg_level_info: null handle");
     if (level < 0 || level >= (int)mg->L.size())
         return sem::fail(mg->ctx, SEM_EINVAL, "sem_mg_level_info: level %d outside [0, %d)", level,
@@ -983,6 +995,7 @@ extern "C" int sem_mg_level_info(sem_mg_t mg, int level, int* n, int* lx, int64_
     if (lx) *lx = lv.lx;
     if (n_unique) *n_unique = lv.nu;
     if (lmax) *lmax = lv.lmax;
+    if (amp) *amp = lv.amp;
     return SEM_OK;
 }
 

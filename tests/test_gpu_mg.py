@@ -37,6 +37,7 @@ def _plan_order(ids, nu):
 
 CASES = [  # n, lx, amp, dirichlet, h2, degree, lo
     (4, 8, 0.1, False, None, 2, 0.3),
+    (4, 4, 0.15, True, None, 2, 0.15),          # the lx = 2 level folds at 0.15: halved amplitude
     (4, 6, 0.12, True, None, 3, 0.2),
     (2, 5, 0.1, False, 20.0, 3, 0.3),
     (4, 3, 0.1, True, 5.0, 1, 0.2),
@@ -52,8 +53,8 @@ def test_vcycle_matches_oracle(sem_ctx, n, lx, amp, dirichlet, h2, degree, lo):
     assert nl == len(H.shapes)
     lmax = []
     for q, (nq, lq, _) in enumerate(H.shapes):
-        gn, glx, gnu, glm = P.sem_mg_level_info(mg, q)
-        assert (gn, glx, gnu) == (nq, lq, H.boxes[q].nu), q
+        gn, glx, gnu, glm, gam = P.sem_mg_level_info(mg, q)
+        assert (gn, glx, gnu, gam) == (nq, lq, H.boxes[q].nu, H.amps[q]), q
         if q + 1 < nl:
             # Lanczos Ritz values lie below lmax; 20 steps come within a few per cent
             assert 0.95 * H.lmax[q] <= glm <= (1 + 1e-4) * H.lmax[q], (q, glm, H.lmax[q])
