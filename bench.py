@@ -688,6 +688,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-big", action="store_true", help="skip the 64^3 box solves (about a minute)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in operator variant")
     ap.add_argument("--no-helmholtz", action="store_true",
                     help="skip the Helmholtz timing (it launches the same kernel as sem_ax)")
     ap.add_argument("--mode", default="bench", choices=["bench", "copy", "scale", "trials", "mg"])
@@ -736,6 +737,21 @@ def main():
     w = torch.empty_like(u)
     print(f"[bench] box {n}^3 lx={lx} amp={amp}: n_local={op.n_local} "
           f"min detJ={op.min_detj:.3e}", file=sys.stderr, flush=True)
+
+    # run-time choice of the operator's kernel variant on this element count
+    # (the paper's autotuning): every variant timed on synthetic inputs, the
+    # fastest kept for the timed steps
+    names = {P.SEM_AX_COLUMN: "column", P.SEM_AX_COLUMN_PF: "column_pf", P.SEM_AX_SLICE: "slice",
+             P.SEM_AX_3D: "3d"}
+    kernels = {P.SEM_AX_COLUMN: f"ax_kernel<{lx}, double>", P.SEM_AX_COLUMN_PF: f"ax_kernel<{lx}, double>",
+               P.SEM_AX_SLICE: f"ax_slice_kernel<{lx}, double>", P.SEM_AX_3D: f"ax3d_kernel<{lx}, double>"}
+    variant = P.SEM_AX_DEFAULT
+    tune_us = None
+    if not args.no_tune:
+        variant, tune_us = P.sem_ax_tune(ctx, lx, op.nel, reps=20)
+        print(f"[bench] operator variant: {names[variant]} "
+              f"({', '.join(f'{names[v]} {t:.1f} us' for v, t in enumerate(tune_us) if t > 0)})",
+              file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         op.ax(w, u)
@@ -813,7 +829,11 @@ def main():
                    "nel": op.nel, "lx": lx, "n_local": n_local, "unique_dofs": nel_dofs},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": f"ax_kernel<{lx}, double>",
+                     "traffic": traffic,
+                     "kernel": kernels.get(variant, f"ax3d_kernel<{lx}, double>" if lx == 3 else f"ax_kernel<{lx}, double>"),
+                     "variant": names.get(variant, "default"),
+                     "variant_us": None if tune_us is None else
+                     {names[v]: round(t, 2) for v, t in enumerate(tune_us) if t > 0},
                      "avg_launch_us": round(ax_ms * 1e3, 2),
                      "alg_bytes_per_launch": alg_bytes},
         "gs": {"avg_launch_us": round(gs_ms * 1e3, 2), "shared_ids": n_shared, "shared_entries": n_entries,

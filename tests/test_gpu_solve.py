@@ -305,7 +305,8 @@ def test_helmholtz_flexible_cg_with_block(sem_ctx):
 def test_box_64cubed_against_c_oracle(sem_ctx):
     """The full stack at scale (64^3 box, E = 262144, lx = 8, 134M local nodes,
     amplitude 0.15): gs(Ax(u)) at every local node against the plain-C
-    oracle's assembled operator (1e-12); the right-hand side at every unique
+    oracle's assembled operator (within 1e-13 of the node's rounding bound);
+    the right-hand side at every unique
     node (1e-12); a solve to relres 1e-10 with float32 residual replacement and
     the multigrid V-cycle, its residual 2-norm recomputed by the C oracle over
     all 89.9M unique nodes (<= 1.1e-10)."""
@@ -343,8 +344,17 @@ def test_box_64cubed_against_c_oracle(sem_ctx):
     _BIG.clear()
     big = cref.BigBox(n, lx, amp)
     ref = big.apply(uu)[ids]
-    assert np.max(np.abs(wl - ref)) <= 1e-12 * np.max(np.abs(ref))
-    del wl, ref
+    # rounding bound node by node: the same operator on |u| with |D| and |G|
+    # bounds every partial sum either side forms (in any order); float64
+    # sums of a few hundred such terms stay within 1e-13 of that bound.  At
+    # amplitude 0.15 the bound is up to ~10x the field's maximum where the
+    # Jacobian is small, so the plain 1e-12 of the 32^3 box does not apply.
+    S = cref.gather(cref.ax(np.abs(uu[ids]), np.abs(big.Dh), None, [np.abs(g) for g in big.G]), ids, nu)[ids]
+    d = np.abs(wl - ref)
+    print(f"64^3 operator: max |dw| / max |w| = {np.max(d) / np.max(np.abs(ref)):.2e}, "
+          f"max |dw| / bound = {np.max(d / S):.2e}")
+    assert np.max(d / S) <= 1e-13
+    del wl, ref, S, d
     bref = big.fourier_rhs(k, a, ph)
     assert np.max(np.abs(bg - bref)) <= 1e-12 * np.max(np.abs(bref))
     rel = np.linalg.norm(bref - big.apply(xg)) / np.linalg.norm(bref)
