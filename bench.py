@@ -570,8 +570,8 @@ def mg_run(ctx, P, n, lx, amp, tol=1e-10, sweep=False, repeat=3):
     x = torch.empty_like(b)
     grid = [dict(n_coarse=8)]
     if sweep:
-        grid = [dict(degree=d, lo=lo, n_coarse=8, graphs=gr) for d in (2, 3, 4) for lo in (0.15, 0.2)
-                for gr in (0, 1)]
+        grid = [dict(degree=d, lo=lo, n_coarse=8, fine_bf16=fb) for d in (2, 3) for lo in (0.1, 0.15)
+                for fb in (0, 1)]
     out = []
     for cfg in grid:
         t0 = time.perf_counter()

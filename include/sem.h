@@ -380,6 +380,9 @@ typedef struct {
     double lo, hi;       /* smoothing interval in units of lmax (0: 0.15 and 1.1) */
     int n_coarse;        /* h-coarsening keeps n >= n_coarse (0: 2) */
     int lanczos_steps;   /* Lanczos steps per level for lmax (0: 20) */
+    int fine_bf16;       /* 1: the finest level's smoothing operator stores its factors (and
+                            h2 B) in bfloat16, as SEM_SOLVE_BF16_IR does (half the bytes of
+                            its four applications per V-cycle); 0: float32 */
 } sem_mg_opts_t;
 
 /* Build the hierarchy for the operator A (h1 must be NULL) on the plan gs of

@@ -915,6 +915,13 @@ void pack_factors_f32(hipStream_t st, float* out, const double* const* G, int64_
     pack_kernel<float><<<vec_grid(n), kBlock, 0, st>>>(out, six, n);
 }
 
+void pack_factors_bf16(hipStream_t st, uint16_t* out, const double* const* G, int64_t n, int lx) {
+    Six six;
+    for (int q = 0; q < 6; ++q) six.g[q] = G[q];
+    six.l2 = lx * lx;
+    pack_kernel<uint16_t><<<vec_grid(n), kBlock, 0, st>>>(out, six, n);
+}
+
 }  // namespace sem
 
 extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,

@@ -423,7 +423,8 @@ struct MgLevel {
     int64_t nel = 0, nloc = 0, nu = 0;
     sem_gs_t gs = nullptr;
     bool own_gs = false;
-    sem::AxArgs A{};                  // float32 solver form
+    sem::AxArgs A{};                  // float32 solver form (factors float32 or bfloat16)
+    sem::AxKind axkind = sem::AxKind::F32;
     float* minv = nullptr;
     float *x = nullptr, *r = nullptr, *d = nullptr, *b = nullptr;   // unique
     float *wl = nullptr, *bl = nullptr;                             // local
@@ -477,7 +478,7 @@ int sum_parts(sem_mg_t mg, int n, double* out) {
 }
 
 int level_ax(sem_mg_t mg, MgLevel& lv, float* wl, const float* u, const int* skip) {
-    return sem::launch_ax(mg->ctx, sem::AxKind::F32, lv.A, wl, u, skip, nullptr, lv.gs->lid);
+    return sem::launch_ax(mg->ctx, lv.axkind, lv.A, wl, u, skip, nullptr, lv.gs->lid);
 }
 
 // lmax of D^-1 A on level lv: the largest Ritz value of `steps` Lanczos steps
@@ -863,7 +864,14 @@ extern "C" int sem_mg_create(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A
             lv.A.D[a] = d;
             lv.A.G[a] = nullptr;
         }
-        {
+        const bool bf = q == 0 && opts->fine_bf16;   // bfloat16 factors on the finest level
+        lv.axkind = bf ? sem::AxKind::F32_BF16 : sem::AxKind::F32;
+        if (bf) {
+            uint16_t* gp = nullptr;
+            MG_ALLOC(gp, sizeof(uint16_t) * 6 * nloc);
+            sem::pack_factors_bf16(st, gp, G64, nloc, lx);
+            lv.A.Gp = gp;
+        } else {
             float* gp = nullptr;
             MG_ALLOC(gp, sizeof(float) * 6 * nloc);
             sem::pack_factors_f32(st, gp, G64, nloc, lx);
@@ -872,9 +880,10 @@ extern "C" int sem_mg_create(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A
         lv.A.h1 = nullptr;
         lv.A.hb = nullptr;
         if (hb64) {
-            float* hb = nullptr;
-            MG_ALLOC(hb, sizeof(float) * nloc);
-            to_f32_kernel<<<gl, kBlock, 0, st>>>(hb, hb64, 1.0, nloc);
+            void* hb = nullptr;
+            MG_ALLOC(hb, (bf ? sizeof(uint16_t) : sizeof(float)) * nloc);
+            if (bf) MG_TTRY(sem_convert(ctx, hb, SEM_BF16, hb64, SEM_F64, nloc));
+            else to_f32_kernel<<<gl, kBlock, 0, st>>>((float*)hb, hb64, 1.0, nloc);
             lv.A.hb = hb;
         }
         lv.A.nel = lv.nel;

@@ -110,6 +110,7 @@ bool spd_inverse(std::vector<double>& A, int n);
 // the six factors of an element-local operator packed for the solver form
 // (the layout of AxArgs::Gp) in float32; n local nodes, asynchronous on st
 void pack_factors_f32(hipStream_t st, float* out, const double* const* G, int64_t n, int lx);
+void pack_factors_bf16(hipStream_t st, uint16_t* out, const double* const* G, int64_t n, int lx);
 
 #ifdef __HIPCC__
 // sum of the local copies of unique node u of a field in the local layout:

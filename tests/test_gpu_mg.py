@@ -78,6 +78,36 @@ def test_vcycle_matches_oracle(sem_ctx, n, lx, amp, dirichlet, h2, degree, lo):
     op.gs.close()
 
 
+def test_vcycle_with_bf16_fine_level_matches_oracle(sem_ctx):
+    """fine_bf16: the finest level's smoothing operator with bfloat16 factors,
+    against the oracle whose finest operator is assembled from the same
+    bfloat16-rounded factors (float64 -> float32 -> bfloat16, reading R16);
+    the Jacobi diagonal stays the float64 one on both sides."""
+    from oracle.assemble import assembled_matrix
+    from oracle.quant import to_bf16
+    n, lx, amp = 4, 8, 0.1
+    op = BoxOperator(sem_ctx, n, lx, amp, keep_coords=False)
+    mg = op.multigrid(degree=2, lo=0.15, fine_bf16=True)
+    H = omg.Hierarchy(n, lx, amp, degree=2, lo=0.15)
+    B = H.boxes[0]
+    H.A[0] = assembled_matrix(B.Dh, None, tuple(to_bf16(g) for g in B.G), B.ids, B.nu).tocsr()
+    H.set_lmax([P.sem_mg_level_info(mg, q)[3] for q in range(len(H.shapes) - 1)])
+    plan_of = _plan_order(B.ids, B.nu)
+    rG = synth.unique_normal(B.nu, 73)
+    zref = H.vcycle(rG)
+    rp = np.empty(B.nu)
+    rp[plan_of] = rG
+    r = torch.from_numpy(rp).cuda()
+    z = torch.full_like(r, float("nan"))
+    P.sem_mg_apply(mg, z, r)
+    torch.cuda.synchronize()
+    zg = z.cpu().numpy()[plan_of]
+    err = np.max(np.abs(zg - zref)) / np.max(np.abs(zref))
+    assert err <= MG_TOL, err
+    mg.close()
+    op.gs.close()
+
+
 def test_vcycle_is_symmetric(sem_ctx):
     """V is a symmetric map: u^T V(v) = v^T V(u) up to float32 rounding."""
     op = BoxOperator(sem_ctx, 4, 6, 0.1, keep_coords=False)
