@@ -742,9 +742,10 @@ def main():
     # (the paper's autotuning): every variant timed on synthetic inputs, the
     # fastest kept for the timed steps
     names = {P.SEM_AX_COLUMN: "column", P.SEM_AX_COLUMN_PF: "column_pf", P.SEM_AX_SLICE: "slice",
-             P.SEM_AX_3D: "3d"}
+             P.SEM_AX_3D: "3d", P.SEM_AX_WAVE: "wave"}
     kernels = {P.SEM_AX_COLUMN: f"ax_kernel<{lx}, double>", P.SEM_AX_COLUMN_PF: f"ax_kernel<{lx}, double>",
-               P.SEM_AX_SLICE: f"ax_slice_kernel<{lx}, double>", P.SEM_AX_3D: f"ax3d_kernel<{lx}, double>"}
+               P.SEM_AX_SLICE: f"ax_slice_kernel<{lx}, double>", P.SEM_AX_3D: f"ax3d_kernel<{lx}, double>",
+               P.SEM_AX_WAVE: f"ax_kernel<{lx}, double> (one element per wave)"}
     variant = P.SEM_AX_DEFAULT
     tune_us = None
     if not args.no_tune:

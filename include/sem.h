@@ -187,12 +187,17 @@ int sem_ax_helmholtz(sem_ctx_t ctx, void* w, const void* u,
  *   SEM_AX_SLICE      the column mapping with the element passing through LDS
  *                     one slice at a time (double-buffered, one barrier per
  *                     slice; 6 lx^2 LDS values per element instead of ~3 lx^3);
- *   SEM_AX_3D         one thread per node (lx <= 10).
+ *   SEM_AX_3D         one thread per node (lx <= 10);
+ *   SEM_AX_WAVE       the column mapping with each element's lx^2 columns on
+ *                     16, 32 or 64 lanes of one wave (lx = 3, 5, 6, 7), so an
+ *                     element never spans two waves and needs no workgroup
+ *                     barrier (as the column mapping has at lx = 2, 4, 8).
  * SEM_AX_DEFAULT (-1) is the built-in choice: SEM_AX_3D at lx = 3, SEM_AX_COLUMN
  * otherwise.  The paper picks among kernel variants by timing them at run
  * time (Sec. 4); sem_ax_tune does that for one lx and element count. */
-enum { SEM_AX_DEFAULT = -1, SEM_AX_COLUMN = 0, SEM_AX_COLUMN_PF = 1, SEM_AX_SLICE = 2, SEM_AX_3D = 3 };
-#define SEM_AX_VARIANTS 4
+enum { SEM_AX_DEFAULT = -1, SEM_AX_COLUMN = 0, SEM_AX_COLUMN_PF = 1, SEM_AX_SLICE = 2, SEM_AX_3D = 3,
+       SEM_AX_WAVE = 4 };
+#define SEM_AX_VARIANTS 5
 /* Select the variant for lx on this context (SEM_EINVAL if it does not
  * exist at that lx). */
 int sem_ax_set_variant(sem_ctx_t ctx, int lx, int variant);

@@ -20,15 +20,15 @@ __all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONV
            "SEM_LP_IN", "SEM_LP_IN_PAD", "SEM_LP_HIDDEN", "SEM_LP_OUT", "SemMgOpts", "Multigrid",
            "sem_mg_create", "sem_mg_destroy", "sem_mg_levels", "sem_mg_level_info", "sem_mg_set_lmax",
            "sem_mg_apply", "sem_mg_set_graphs", "sem_ax_set_variant", "sem_ax_get_variant", "sem_ax_tune",
-           "SEM_AX_DEFAULT", "SEM_AX_COLUMN", "SEM_AX_COLUMN_PF", "SEM_AX_SLICE", "SEM_AX_3D", "SEM_AX_VARIANTS", "sem_lp_snapshot", "sem_lp_reference_block"]
+           "SEM_AX_DEFAULT", "SEM_AX_COLUMN", "SEM_AX_COLUMN_PF", "SEM_AX_SLICE", "SEM_AX_3D", "SEM_AX_WAVE", "SEM_AX_VARIANTS", "sem_lp_snapshot", "sem_lp_reference_block"]
 
 SEM_LP_IN, SEM_LP_IN_PAD, SEM_LP_HIDDEN, SEM_LP_OUT = 518, 528, 256, 512
 # slot -> shape of the float32 array it holds (parameters; +6 m, +12 v, +18 grads)
 LP_SLOTS = [(256, 518), (256,), (256, 256), (256,), (512, 256), (512,)]
 
 SEM_SOLVE_F64, SEM_SOLVE_F32_IR, SEM_SOLVE_BF16_IR = 0, 1, 2
-SEM_AX_DEFAULT, SEM_AX_COLUMN, SEM_AX_COLUMN_PF, SEM_AX_SLICE, SEM_AX_3D = -1, 0, 1, 2, 3
-SEM_AX_VARIANTS = 4
+SEM_AX_DEFAULT, SEM_AX_COLUMN, SEM_AX_COLUMN_PF, SEM_AX_SLICE, SEM_AX_3D, SEM_AX_WAVE = -1, 0, 1, 2, 3, 4
+SEM_AX_VARIANTS = 5
 
 
 class SemOperator(ctypes.Structure):

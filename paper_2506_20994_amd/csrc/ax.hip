@@ -130,9 +130,11 @@ __device__ __forceinline__ void wave_sync() {
 // a Dirichlet node, read as 0).  The output stays in the local layout
 // (coalesced nontemporal stores); the solver sums the copies of each unique
 // node through the plan's CSR lists.
+// TPE: threads per element (lx^2, or a power of two above it that divides 64,
+// so that every element sits inside one wave; the extra lanes idle)
 template <int LX, int EPB, typename TU, typename TS, typename TC, typename TW, bool FUSE, bool GATHER, bool HB,
-          bool PF = Shape<LX>::kPrefetch>
-__global__ void __launch_bounds__(EPB * LX * LX) __attribute__((amdgpu_waves_per_eu(Shape<LX>::kWavesPerEU, 8)))
+          bool PF = Shape<LX>::kPrefetch, int TPE = LX * LX>
+__global__ void __launch_bounds__(EPB * TPE) __attribute__((amdgpu_waves_per_eu(Shape<LX>::kWavesPerEU, 8)))
 ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
           const TC* __restrict__ dx, const TC* __restrict__ dy, const TC* __restrict__ dz,
           const TC* __restrict__ dxt, const TC* __restrict__ dyt, const TC* __restrict__ dzt,
@@ -143,7 +145,8 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
           const TS* __restrict__ gp, const TS* __restrict__ hb) {
     constexpr int L2 = LX * LX;
     constexpr int L3 = L2 * LX;
-    constexpr bool WP = Shape<LX>::kWavePrivate;
+    constexpr bool WP = (64 % TPE) == 0;
+    static_assert(TPE >= L2, "threads per element");
     if (skip && *skip) return;
     __shared__ TC s_u[EPB * L3];               // the element's u (wave-private: then the r-flux)
     __shared__ TC s_s[EPB * L3];               // s-flux
@@ -151,12 +154,14 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
     __shared__ TC s_d[6 * L2];                 // dx, dy, dz, dxt, dyt, dzt
 
     const int tid = threadIdx.x;
-    const int el = tid / L2;
-    const int ij = tid - el * L2;
+    const int el = tid / TPE;
+    const int ijr = tid - el * TPE;
+    const bool act = TPE == L2 || ijr < L2;    // a lane with a column
+    const int ij = act ? ijr : 0;
     const int i = ij % LX;
     const int j = ij / LX;
     const int64_t e = (int64_t)blockIdx.x * EPB + el;
-    const bool live = e < nel;
+    const bool live = act && e < nel;
     const int64_t base = e * L3 + ij;
     TC* su = s_u + el * L3;
     TC* ss = s_s + el * L3;
@@ -164,7 +169,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
     const TC* sdz = s_d + 2 * L2;
     const TC* sdzt = s_d + 5 * L2;
 
-    for (int q = tid; q < L2; q += EPB * L2) {
+    for (int q = tid; q < L2; q += EPB * TPE) {
         s_d[q] = dx[q];
         s_d[L2 + q] = dy[q];
         s_d[2 * L2 + q] = dz[q];
@@ -184,8 +189,10 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
         else
             uc[k] = live ? (TC)Load<TU>::get(u, base + k * L2) : TC(0);
     }
+    if (act) {
 #pragma unroll
-    for (int k = 0; k < LX; ++k) su[k * L2 + ij] = uc[k];
+        for (int k = 0; k < LX; ++k) su[k * L2 + ij] = uc[k];
+    }
     __syncthreads();   // s_d is shared by every wave of the workgroup
 
     TC di[LX], dj[LX];
@@ -227,8 +234,10 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
         const TC vs = H * (G12 * r + G22 * s + G23 * t);
         const TC vt = H * (G13 * r + G23 * s + G33 * t);
         if (WP) wave_sync();   // every lane has read slice k before it is overwritten
-        sr[k * L2 + ij] = vr;
-        ss[k * L2 + ij] = vs;
+        if (act) {
+            sr[k * L2 + ij] = vr;
+            ss[k * L2 + ij] = vs;
+        }
 #pragma unroll
         for (int m = 0; m < LX; ++m) wt[m] += sdzt[k * LX + m] * vt;
     }
@@ -255,7 +264,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
         if (FUSE) pw += (double)uc[k] * (double)(TW)acc;
     }
     if (FUSE) {
-        constexpr int NT = EPB * L2;
+        constexpr int NT = EPB * TPE;
         if constexpr (NT % 64 == 0) {          // whole waves: shuffle, then one value per wave
             __shared__ double s_red[NT / 64];
             pw = sem::wave_sum(pw);
@@ -478,7 +487,8 @@ ax3d_kernel(TW* __restrict__ w, const TS* __restrict__ u,
 // separate kernels (and separate rows of a kernel trace).
 // the float64 public form's kernel variants (SEM_AX_* of sem.h)
 constexpr bool variant_exists(int lx, int v) {
-    return v == SEM_AX_COLUMN || v == SEM_AX_COLUMN_PF || v == SEM_AX_SLICE || (v == SEM_AX_3D && lx <= 10);
+    return v == SEM_AX_COLUMN || v == SEM_AX_COLUMN_PF || v == SEM_AX_SLICE || (v == SEM_AX_3D && lx <= 10) ||
+           (v == SEM_AX_WAVE && (lx == 3 || lx == 5 || lx == 6 || lx == 7));
 }
 
 template <int LX, typename TS, typename TC, typename TW, bool HB, bool PF>
@@ -526,6 +536,19 @@ bool launch_variant(sem_ctx_t ctx, int variant, void* w, const void* u, const vo
                 (const TC*)D[4], (const TC*)D[5], (const TS*)h1, (const TS*)G[0], (const TS*)G[1],
                 (const TS*)G[2], (const TS*)G[3], (const TS*)G[4], (const TS*)G[5], nel, (const TS*)hb);
             return true;
+        }
+        if constexpr (LX == 3 || LX == 5 || LX == 6 || LX == 7) {
+            if (variant == SEM_AX_WAVE) {      // lx^2 columns padded to 16, 32 or 64 lanes
+                constexpr int TPE = LX == 3 ? 16 : LX == 5 ? 32 : 64;
+                constexpr int EW = 256 / TPE;
+                ax_kernel<LX, EW, TS, TS, TC, TW, false, false, HB, Shape<LX>::kPrefetch, TPE>
+                    <<<(unsigned)((nel + EW - 1) / EW), EW * TPE, 0, ctx->stream>>>(
+                        (TW*)w, (const TS*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2], (const TC*)D[3],
+                        (const TC*)D[4], (const TC*)D[5], (const TS*)h1, (const TS*)G[0], (const TS*)G[1],
+                        (const TS*)G[2], (const TS*)G[3], (const TS*)G[4], (const TS*)G[5], nel, nullptr, nullptr,
+                        nullptr, nullptr, (const TS*)hb);
+                return true;
+            }
         }
         if (variant == SEM_AX_3D && LX != 3 && LX <= 10) {
             launch_3d<LX, TS, TC, TW, HB>(ctx, w, u, D, h1, G, nel, hb);

@@ -45,7 +45,8 @@ def _fields(ctx, nel, lx, seed=0):
 def run(reps=50, lxs=LXS, sizes=SIZES, tune=False):
     ctx = B.sem_create()
     rows = []
-    names = {B.SEM_AX_COLUMN: "column", B.SEM_AX_COLUMN_PF: "column_pf", B.SEM_AX_SLICE: "slice", B.SEM_AX_3D: "3d"}
+    names = {B.SEM_AX_COLUMN: "column", B.SEM_AX_COLUMN_PF: "column_pf", B.SEM_AX_SLICE: "slice", B.SEM_AX_3D: "3d",
+             B.SEM_AX_WAVE: "wave"}
     for lx in lxs:
         for nel in sizes:
             tuned = None

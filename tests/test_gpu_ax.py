@@ -220,6 +220,14 @@ def test_ax_helmholtz_full_size_sampled(sem_ctx):
     op.gs.close()
 
 
+def _variant_exists(lx, v):
+    if v == P.SEM_AX_3D:
+        return lx <= 10
+    if v == P.SEM_AX_WAVE:
+        return lx in (3, 5, 6, 7)
+    return True
+
+
 @pytest.mark.parametrize("lx", list(range(2, 13)))
 def test_ax_variants_match_oracle(sem_ctx, lx):
     """Every kernel variant of the float64 operator that exists at lx, with and
@@ -235,7 +243,7 @@ def test_ax_variants_match_oracle(sem_ctx, lx):
             ref0 = ax_einsum(u, *listing_matrices(lx), None, *G)
             refh = ax_helmholtz(u, *listing_matrices(lx), h1, *G, hb)
             for v in range(P.SEM_AX_VARIANTS):
-                if v == P.SEM_AX_3D and lx > 10:
+                if not _variant_exists(lx, v):
                     with pytest.raises(P.SemError):
                         P.sem_ax_set_variant(sem_ctx, lx, v)
                     continue
@@ -253,7 +261,7 @@ def test_ax_variants_match_oracle(sem_ctx, lx):
 
 
 def test_ax_tune_selects_the_fastest_variant(sem_ctx):
-    for lx, missing in ((8, []), (12, [P.SEM_AX_3D])):
+    for lx, missing in ((6, []), (8, [P.SEM_AX_WAVE]), (12, [P.SEM_AX_3D, P.SEM_AX_WAVE])):
         try:
             best, us = P.sem_ax_tune(sem_ctx, lx, 256, reps=3)
             assert len(us) == P.SEM_AX_VARIANTS
