@@ -27,6 +27,13 @@ Readings taken (none is fixed by the paper):
   * smoother: k steps of the Chebyshev semi-iteration in D^-1 A (D the
     assembled diagonal) for the interval [lo lmax, hi lmax], lmax the largest
     eigenvalue of D^-1 A (exact here; estimated by the library);
+  * Galerkin option: every lx = 2 level below the first takes A_c = P^T A_f P
+    (A_f the level above it, with its mass term) instead of a re-discretised
+    operator, so it needs no geometry of its own (its amplitude is reported as
+    0); on strongly deformed boxes this keeps the coarse correction an
+    A-orthogonal projection where the halved-amplitude coarse boxes of the
+    re-discretised hierarchy approximate the operator poorly (Galerkin coarse
+    operators: Trottenberg, Oosterlee and Schueller 2001);
   * coarsest level: (A + c 1 1^T)^-1 on the singular periodic box (c = mean
     diagonal / n_unique; on mean-free right-hand sides this is the
     pseudo-inverse), A^-1 otherwise;
@@ -37,7 +44,11 @@ the Chebyshev steps equal the closed-form polynomial T_k((theta - D^-1 A) /
 delta) / T_k(theta / delta) acting on the error; the two-level V-cycle's
 error propagator equals S (I - P A_c^-1 P^T A) S from dense algebra; the
 V-cycle is a symmetric positive definite preconditioner; preconditioned CG
-needs about as many iterations on 8^3 as on 4^3 elements.
+needs about as many iterations on 8^3 as on 4^3 elements; with Galerkin
+levels the two-grid coarse correction I - P A_c^-1 P^T A is idempotent and
+A-self-adjoint (it is not with re-discretised levels), constants stay in the
+null space of the periodic Poisson levels, and the solve on a folding box
+needs fewer iterations than with re-discretised levels.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -146,26 +157,36 @@ class Hierarchy:
     """Levels of the box (n, lx, amplitude a; periodic or Dirichlet; h2 for
     the Helmholtz form) with their assembled matrices, diagonals, transfers
     and the exact lmax of D^-1 A (replace by ``set_lmax`` to reproduce a
-    caller's estimates)."""
+    caller's estimates).  galerkin: the lx = 2 levels below the first are
+    P^T A P of the level above."""
 
-    def __init__(self, n, lx, a, dirichlet=False, h2=None, n_coarse=2, degree=2, lo=0.3, hi=1.1):
+    def __init__(self, n, lx, a, dirichlet=False, h2=None, n_coarse=2, degree=2, lo=0.3, hi=1.1,
+                 galerkin=False):
         from .assemble import assembled_matrix
         self.shapes = level_shapes(n, lx, n_coarse)
         self.degree, self.lo, self.hi = degree, lo, hi
         self.boxes, self.A, self.dinv, self.P, self.lmax, self.amps = [], [], [], [], [], []
+        # Galerkin levels: every lx = 2 level below the first (no geometry: amplitude 0)
+        self.galerkin = [galerkin and q > 0 and lxl == 2 for q, (_, lxl, _) in enumerate(self.shapes)]
         for q, (nl, lxl, _) in enumerate(self.shapes):
-            al = a if q == 0 else level_amplitude(nl, lxl, a, dirichlet)
+            if self.galerkin[q]:
+                al = 0.0
+            else:
+                al = a if q == 0 else level_amplitude(nl, lxl, a, dirichlet)
             self.amps.append(al)
-            B = BoxProblem(nl, lxl, al, dirichlet=dirichlet, h2=h2)
-            A = assembled_matrix(B.Dh, None, B.G, B.ids, B.nu)
-            if h2 is not None:
-                from .gs import gather
-                A = A + sp.diags(gather(h2 * B.B, B.ids, B.nu))
-            self.boxes.append(B)
-            self.A.append(A.tocsr())
-            self.dinv.append(1.0 / A.diagonal())
+            self.boxes.append(BoxProblem(nl, lxl, al, dirichlet=dirichlet, h2=h2))
         for q, (_, _, kind) in enumerate(self.shapes[:-1]):
             self.P.append(prolongation(self.boxes[q], self.boxes[q + 1], kind))
+        for q, B in enumerate(self.boxes):
+            if self.galerkin[q]:
+                A = self.P[q - 1].T @ self.A[q - 1] @ self.P[q - 1]
+            else:
+                A = assembled_matrix(B.Dh, None, B.G, B.ids, B.nu)
+                if h2 is not None:
+                    from .gs import gather
+                    A = A + sp.diags(gather(h2 * B.B, B.ids, B.nu))
+            self.A.append(A.tocsr())
+            self.dinv.append(1.0 / A.diagonal())
         for q in range(len(self.shapes) - 1):
             Dm = sp.diags(np.sqrt(self.dinv[q]))
             M = Dm @ self.A[q] @ Dm

@@ -172,3 +172,55 @@ def test_folding_coarse_levels_take_a_halved_amplitude():
     assert np.linalg.norm(b - B.apply(x)) <= 1.2e-10 * np.linalg.norm(b)
     _, itj, _ = pcg(B.apply, b, 1.0 / B.diagonal(), tol=1e-10, project=B.project)
     assert it < 0.5 * itj
+
+
+@pytest.mark.parametrize("dirichlet,h2", [(True, None), (False, None), (False, 5.0)])
+def test_galerkin_coarse_correction_is_an_a_orthogonal_projection(dirichlet, h2):
+    """With Galerkin levels the two-grid coarse correction T = I - P A_c^-1 P^T A
+    of every level pair is idempotent and A-self-adjoint (A T = T^T A); the
+    re-discretised levels of the same box do not have this property.  On the
+    periodic Poisson box the singular levels keep the constants in their null
+    space.  The box folds at amplitude 0.15 (4^3 elements, lx = 4 -> 2 -> 2)."""
+    kw = dict(dirichlet=dirichlet, h2=h2)
+    Hg = mg.Hierarchy(4, 4, 0.15, galerkin=True, **kw)
+    Hr = mg.Hierarchy(4, 4, 0.15, **kw)
+    assert [s[:2] for s in Hg.shapes] == [(4, 4), (4, 2), (2, 2)]
+    assert Hg.galerkin == [False, True, True] and Hg.amps[1:] == [0.0, 0.0]
+
+    def defect(H, q):
+        A = H.A[q].toarray()
+        P = H.P[q].toarray()
+        Ac = H.A[q + 1].toarray()
+        if H.boxes[q + 1].project:       # singular: solve on the complement of the constants
+            Ac = Ac + np.ones_like(Ac)
+        T = np.eye(len(A)) - P @ np.linalg.solve(Ac, P.T @ A)
+        scale = np.abs(T).max()
+        return np.abs(T @ T - T).max() / scale, np.abs(A @ T - T.T @ A).max() / (np.abs(A).max() * scale)
+
+    for q in range(2):
+        idem, sym = defect(Hg, q)
+        assert idem <= 1e-10 and sym <= 1e-10, (q, idem, sym)
+    assert max(defect(Hr, 0)) > 1e-3        # re-discretised: not a projection
+    if not dirichlet and h2 is None:
+        for q in (1, 2):
+            one = np.ones(Hg.boxes[q].nu)
+            assert np.abs(Hg.A[q] @ one).max() <= 1e-12 * abs(Hg.A[q]).max()
+
+
+def test_galerkin_levels_beat_rediscretised_ones_on_a_folding_box():
+    """On an 8^3 lx = 4 Dirichlet box at amplitude 0.15 (its lx = 2 levels
+    fold), flexible CG with the Galerkin V-cycle converges in fewer iterations
+    than with the re-discretised one; both reach relres 1e-10 and the Galerkin
+    V-cycle is symmetric positive definite on a smaller box."""
+    its = {}
+    for g in (False, True):
+        H = mg.Hierarchy(8, 4, 0.15, dirichlet=True, galerkin=g)
+        B = H.boxes[0]
+        k, a, ph = synth.fourier_modes(2, kmax=2)
+        b = B.fourier_rhs(k, a, ph)
+        x, its[g], _ = fcg1(B.apply, b, H.vcycle, tol=1e-10, project=B.project)
+        assert np.linalg.norm(b - B.apply(x)) <= 1.2e-10 * np.linalg.norm(b)
+    assert its[True] < its[False], its
+    V = mg.Hierarchy(2, 4, 0.15, dirichlet=True, galerkin=True).matrix()
+    assert np.allclose(V, V.T, rtol=0, atol=1e-12 * np.abs(V).max())
+    assert np.linalg.eigvalsh(0.5 * (V + V.T))[0] > 0
