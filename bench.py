@@ -69,6 +69,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE_F64 = 72
+# the multigrid V-cycle of every solve entry: 3 Chebyshev steps on [0.1, 1.1] lmax,
+# bfloat16 factors on the finest level, Galerkin lx = 2 levels, coarsest h-level 8^3
+MG_OPTS = dict(degree=3, lo=0.1, fine_bf16=1, galerkin=1, n_coarse=8)
 
 
 def kernel_source_hash():
@@ -209,7 +212,7 @@ def solve_comparison(ctx, P, n, lx, amp, tol=1e-10):
         cg.close()
     # the multigrid V-cycle (classical coarse-space preconditioner) in flexible CG
     t0 = time.perf_counter()
-    mg = op.multigrid(n_coarse=8)
+    mg = op.multigrid(**MG_OPTS)
     torch.cuda.synchronize()
     res["mg_setup_s"] = round(time.perf_counter() - t0, 3)
     res["mg_levels"] = [list(P.sem_mg_level_info(mg, q)) for q in range(P.sem_mg_levels(mg))]
@@ -228,7 +231,7 @@ def solve_comparison(ctx, P, n, lx, amp, tol=1e-10):
     op16 = BoxOperator(ctx, n // 2, lx, amp)
     b16 = op16.fourier_rhs(k, a, ph)
     x16 = torch.empty_like(b16)
-    mg16 = op16.multigrid(n_coarse=8)
+    mg16 = op16.multigrid(**MG_OPTS)
     growth = {}
     for name, code, mode, m in (("fp64_pcg", P.SEM_SOLVE_F64, 0, None), ("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1, mg16)):
         _, st = _timed_solve(P, op16, x16, b16, code, mode, None, tol, mg=m)
@@ -279,7 +282,7 @@ def dirichlet_comparison(ctx, P, n, lx, amp, lp=None, tol=1e-10):
         variants.append(("learned_f32_rr", P.SEM_SOLVE_F32_IR, 1, lp))
     if blk is not None:
         variants.append(("classical_block_f32_rr", P.SEM_SOLVE_F32_IR, 1, blk))
-    mg = op.multigrid(n_coarse=8)
+    mg = op.multigrid(**MG_OPTS)
     variants.append(("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1, mg))
     for name, code, mode, net in variants:
         if net is mg:
@@ -327,7 +330,7 @@ def helmholtz_solve_comparison(ctx, P, n, lx, amp, h2=1e3, tol=1e-10):
     variants = [("fp64_pcg", P.SEM_SOLVE_F64, 0, None), ("f32_rr", P.SEM_SOLVE_F32_IR, 1, None)]
     if blk is not None:
         variants.append(("classical_block_f32_rr", P.SEM_SOLVE_F32_IR, 1, blk))
-    mg = op.multigrid(h2=h2, n_coarse=8)
+    mg = op.multigrid(h2=h2, **MG_OPTS)
     variants.append(("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1, mg))
     for name, code, mode, net in variants:
         if net is mg:
@@ -527,7 +530,7 @@ def big_box_comparison(ctx, P, lp, lx=8, n=64, amp=0.15, tol=1e-10, fp64=True):
     if lp is not None and lx == 8:
         op.bind(lp)
         runs.append(("learned_f32_rr", P.SEM_SOLVE_F32_IR, 1, lp, None, False))
-    mg = op.multigrid(n_coarse=8)
+    mg = op.multigrid(**MG_OPTS)
     res["mg_levels"] = [list(P.sem_mg_level_info(mg, q)) for q in range(P.sem_mg_levels(mg))]
     runs.append(("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1, None, mg, True))
     for name, code, mode, L, m, warm in runs:
@@ -568,10 +571,9 @@ def mg_run(ctx, P, n, lx, amp, tol=1e-10, sweep=False, repeat=3):
     k, a, ph = synth.fourier_modes(2)
     b = op.fourier_rhs(k, a, ph)
     x = torch.empty_like(b)
-    grid = [dict(n_coarse=8)]
+    grid = [dict(MG_OPTS)]
     if sweep:
-        grid = [dict(degree=d, lo=lo, n_coarse=8, fine_bf16=fb) for d in (2, 3) for lo in (0.1, 0.15)
-                for fb in (0, 1)]
+        grid = [dict(MG_OPTS, degree=d, galerkin=g, n_coarse=nc) for d in (2, 3) for g in (0, 1) for nc in (4, 8)]
     out = []
     for cfg in grid:
         t0 = time.perf_counter()
@@ -650,7 +652,7 @@ def scale_run(ctx, P, n=64, amp=0.15, tol=1e-10):
             op.bind(lp)
             variants += [("learned_f32_rr", P.SEM_SOLVE_F32_IR, 1, lp),
                          ("learned_bf16_rr", P.SEM_SOLVE_BF16_IR, 1, lp)]
-        mg = op.multigrid(n_coarse=8)
+        mg = op.multigrid(**MG_OPTS)
         variants += [("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1, "mg"), ("mg_fcg_f64", P.SEM_SOLVE_F64, 0, "mg")]
         for name, code, mode, L in variants:
             M = mg if L == "mg" else None

@@ -365,7 +365,8 @@ int sem_cg_solve(sem_cg_t cg, double* x, const double* b, const sem_solve_opts_t
  * library's set-up calls on the same deformed box (h1 = 1; h2 times that
  * level's mass for Helmholtz operators); a level whose geometry would fold
  * (det J <= 0 at a node: coarse trilinear elements of a strongly deformed box)
- * takes the amplitude halved until it does not.  Transfer: the coarse level's field
+ * takes the amplitude halved until it does not (or, with opts->galerkin, every
+ * lx = 2 level below the first is P^T A P of the level above).  Transfer: the coarse level's field
  * evaluated at the fine level's nodes (the coarse Lagrange basis on the same
  * element; the parent's trilinear basis); restriction by its transpose.
  * Smoothing: `degree` steps of the Chebyshev semi-iteration in D^-1 A (D the
@@ -388,6 +389,13 @@ typedef struct {
     int fine_bf16;       /* 1: the finest level's smoothing operator stores its factors (and
                             h2 B) in bfloat16, as SEM_SOLVE_BF16_IR does (half the bytes of
                             its four applications per V-cycle); 0: float32 */
+    int galerkin;        /* 1: every lx = 2 level below the first is the Galerkin product
+                            P^T A P of the level above (float64 set-up from the float64
+                            operators, kept as one dense 8 x 8 float32 matrix per element;
+                            no geometry of its own, amplitude reported 0), instead of a
+                            re-discretised box: the coarse correction stays an A-orthogonal
+                            projection where coarse boxes of a strongly deformed mesh fold;
+                            0: re-discretised */
 } sem_mg_opts_t;
 
 /* Build the hierarchy for the operator A (h1 must be NULL) on the plan gs of

@@ -49,7 +49,7 @@ class SemMgOpts(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("amp", ctypes.c_double), ("dirichlet", ctypes.c_int),
                 ("h2", ctypes.c_double), ("degree", ctypes.c_int), ("lo", ctypes.c_double),
                 ("hi", ctypes.c_double), ("n_coarse", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
-                ("fine_bf16", ctypes.c_int)]
+                ("fine_bf16", ctypes.c_int), ("galerkin", ctypes.c_int)]
 
 
 class SemSolveStats(ctypes.Structure):
@@ -591,11 +591,12 @@ class Multigrid:
 
 
 def sem_mg_create(ctx, gs, D, G, nel, lx, n, amp, dirichlet=False, h2=0.0, h2b=None, degree=0, lo=0.0,
-                  hi=0.0, n_coarse=0, lanczos_steps=0, fine_bf16=False):
+                  hi=0.0, n_coarse=0, lanczos_steps=0, fine_bf16=False, galerkin=False):
     """The multigrid hierarchy of the n^3 box operator (D, G float64 device
     tensors as for sem_cg_setup, h1 = 1; h2b = h2 * bm for a Helmholtz operator)."""
     A = SemOperator(*[_ptr(t) for t in D], None, *[_ptr(t) for t in G], nel, lx, _ptr(h2b))
-    o = SemMgOpts(n, amp, int(bool(dirichlet)), h2, degree, lo, hi, n_coarse, lanczos_steps, int(bool(fine_bf16)))
+    o = SemMgOpts(n, amp, int(bool(dirichlet)), h2, degree, lo, hi, n_coarse, lanczos_steps, int(bool(fine_bf16)),
+                  int(bool(galerkin)))
     h = ctx.bind()
     out = _vp()
     _check(lib().sem_mg_create(h, gs.handle, ctypes.byref(A), ctypes.byref(o), ctypes.byref(out)), h)

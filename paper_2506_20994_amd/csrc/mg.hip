@@ -13,6 +13,13 @@
 //  * Every level below the first is re-discretised by the library's own set-up
 //    calls (box mesh, isoparametric geometry, gather-scatter plan) on the same
 //    deformed box, with h1 = 1 and, for Helmholtz operators, h2 B of that level.
+//    With the Galerkin option every lx = 2 level below the first is instead
+//    P^T A P of the level above (no geometry of its own).  P acts element by
+//    element, so that product is the sum over elements of J^T A_e J: one dense
+//    8 x 8 matrix per lx = 2 element -- for a p-transfer from the same element's
+//    operator applied to the 8 interpolated coarse basis functions, for an
+//    h-transfer summed over the 8 children (Trottenberg, Oosterlee and
+//    Schueller 2001 for Galerkin coarse operators).
 //  * Transfer P: the coarse level's continuous field evaluated at the fine
 //    level's nodes -- p: the coarse Lagrange basis at the fine GLL points of
 //    the same element; h: the parent element's trilinear basis at the child's
@@ -243,6 +250,96 @@ coarse_kernel(float* __restrict__ x, const float* __restrict__ bin, const float*
     }
 }
 
+// Galerkin level operator: w_l = M_e u_e, one thread per local node of the
+// lx = 2 elements (M row-major per element, 8 x 8; Dirichlet nodes read 0)
+__global__ void dense_ax_kernel(float* __restrict__ wl, const float* __restrict__ u, const float* __restrict__ M,
+                                const int32_t* __restrict__ lid, int64_t nloc, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    MG_LOOP(L, nloc) {
+        const int64_t e8 = L & ~(int64_t)7;
+        const float* row = M + 8 * L;
+        float s = 0.f;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int32_t id = lid[e8 + a];
+            s += row[a] * (id >= 0 ? u[id] : 0.f);
+        }
+        wl[L] = s;
+    }
+}
+
+// The coarse basis function bc (0..7, lexicographic over the 2 x 2 x 2 coarse
+// element) interpolated to the lf^3 nodes of every element: J[i][a] (lf x 2).
+__global__ void basis_field_kernel(double* __restrict__ ul, const double* __restrict__ J, int lf, int bc,
+                                   int64_t n) {
+    const int f3 = lf * lf * lf;
+    const int ax = bc & 1, ay = (bc >> 1) & 1, az = bc >> 2;
+    MG_LOOP(L, n) {
+        const int q = (int)(L % f3);
+        const int i = q % lf, j = (q / lf) % lf, k = q / (lf * lf);
+        ul[L] = J[k * 2 + az] * J[j * 2 + ay] * J[i * 2 + ax];
+    }
+}
+
+// Column bc of the Galerkin element matrices: M_e[a][bc] = sum_i J3[i][a] (A_e J3[:, bc])[i]
+// from wl = A (basis field bc), one thread per (element, a).
+__global__ void project_basis_kernel(double* __restrict__ M, const double* __restrict__ wl,
+                                     const double* __restrict__ J, int lf, int bc, int64_t nel) {
+    const int f3 = lf * lf * lf;
+    MG_LOOP(t, nel * 8) {
+        const int64_t e = t >> 3;
+        const int a = (int)(t & 7);
+        const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+        const double* w = wl + e * f3;
+        double s = 0.0;
+        for (int q = 0; q < f3; ++q) {
+            const int i = q % lf, j = (q / lf) % lf, k = q / (lf * lf);
+            s += J[k * 2 + az] * J[j * 2 + ay] * J[i * 2 + ax] * w[q];
+        }
+        M[e * 64 + a * 8 + bc] = s;
+    }
+}
+
+// h-Galerkin: M_E = sum over the 8 children c of J_c^T M_c J_c, J_c the
+// parent's trilinear basis at the child's vertices (reference coordinate
+// -1 + parity + i); one thread per (coarse element, a, b).
+__global__ void galerkin_h_kernel(double* __restrict__ Mc, const double* __restrict__ Mf, int nf, int nc,
+                                  int64_t nelc) {
+    MG_LOOP(t, nelc * 64) {
+        const int64_t E = t >> 6;
+        const int a = (int)((t >> 3) & 7), b = (int)(t & 7);
+        const int64_t ecx = E % nc, ecy = (E / nc) % nc, ecz = E / ((int64_t)nc * nc);
+        double s = 0.0;
+        for (int ch = 0; ch < 8; ++ch) {
+            const int px = ch & 1, py = (ch >> 1) & 1, pz = ch >> 2;
+            const int64_t ef = (2 * ecx + px) + nf * ((2 * ecy + py) + (int64_t)nf * (2 * ecz + pz));
+            const double* m = Mf + ef * 64;
+            double ja[8], jb[8];
+            for (int i = 0; i < 8; ++i) {    // J_c[i][a]: product over x, y, z of phi_{a_d}(-1 + p_d + i_d)
+                const int ix = i & 1, iy = (i >> 1) & 1, iz = i >> 2;
+                auto phi = [](int p, int ii, int aa) {
+                    const double eta = -1.0 + p + ii;
+                    return aa ? 0.5 * (1.0 + eta) : 0.5 * (1.0 - eta);
+                };
+                ja[i] = phi(px, ix, a & 1) * phi(py, iy, (a >> 1) & 1) * phi(pz, iz, a >> 2);
+                jb[i] = phi(px, ix, b & 1) * phi(py, iy, (b >> 1) & 1) * phi(pz, iz, b >> 2);
+            }
+            for (int i = 0; i < 8; ++i) {
+                if (ja[i] == 0.0) continue;
+                double r = 0.0;
+                for (int j = 0; j < 8; ++j) r += m[i * 8 + j] * jb[j];
+                s += ja[i] * r;
+            }
+        }
+        Mc[t] = s;
+    }
+}
+
+// the diagonals of the element matrices in the local layout
+__global__ void mat_diag_kernel(double* __restrict__ dl, const double* __restrict__ M, int64_t nloc) {
+    MG_LOOP(L, nloc) dl[L] = M[8 * L + (L & 7)];
+}
+
 // ----------------------------------------------------------------- set-up
 __global__ void to_f32_kernel(float* __restrict__ out, const double* __restrict__ in, double scale, int64_t n) {
     MG_LOOP(L, n) out[L] = (float)(scale * in[L]);
@@ -434,6 +531,7 @@ struct MgLevel {
     std::vector<float> c1, c2;        // Chebyshev steps 1 .. degree-1
     int kind = -1;                    // transfer to the next level: 0 p, 1 h
     float* J = nullptr;               // [2][lx][lx of the next level]
+    float* M = nullptr;               // Galerkin level: 8 x 8 element matrices (else null)
 };
 
 struct sem_mg_s {
@@ -478,6 +576,11 @@ int sum_parts(sem_mg_t mg, int n, double* out) {
 }
 
 int level_ax(sem_mg_t mg, MgLevel& lv, float* wl, const float* u, const int* skip) {
+    if (lv.M) {
+        dense_ax_kernel<<<vgrid(lv.nloc), kBlock, 0, mg->ctx->stream>>>(wl, u, lv.M, lv.gs->lid, lv.nloc, skip);
+        SEM_LAUNCH_CHECK(mg->ctx);
+        return SEM_OK;
+    }
     return sem::launch_ax(mg->ctx, lv.axkind, lv.A, wl, u, skip, nullptr, lv.gs->lid);
 }
 
@@ -792,6 +895,14 @@ extern "C" int sem_mg_create(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A
 #define MG_TMP(ptr, bytes) do { int rc_ = tmp_alloc((void**)&(ptr), (bytes)); if (rc_) { free_tmp(); return bail(rc_); } } while (0)
 #define MG_TTRY(call) do { int rc_ = (call); if (rc_) { free_tmp(); return bail(rc_); } } while (0)
 
+    // Galerkin element matrices (float64, 64 per element) of the current and the
+    // next level; freed when set-up ends
+    struct Carry {
+        std::vector<void*> v;
+        ~Carry() { for (void* p : v) (void)hipFree(p); }
+    } carry;
+    const bool galerkin = opts->galerkin != 0;
+    double* cur64 = nullptr;
     for (int q = 0; q < nl; ++q) {
         MgLevel& lv = mg->L[q];
         lv.n = ns[q];
@@ -802,8 +913,9 @@ extern "C" int sem_mg_create(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A
         lv.nloc = lv.nel * l2 * lx;
         const int64_t nloc = lv.nloc;
         const unsigned gl = vgrid(nloc);
-        const double* D64[6];
-        const double* G64[6];
+        const bool gal = galerkin && q > 0 && lx == 2;     // this level is P^T A P of the one above
+        const double* D64[6] = {};
+        const double* G64[6] = {};
         const double* hb64 = nullptr;
         double* dl = nullptr;               // element diagonal (float64, local)
         MG_TMP(dl, sizeof(double) * nloc);
@@ -813,84 +925,106 @@ extern "C" int sem_mg_create(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A
             for (int a = 0; a < 6; ++a) { D64[a] = Dp[a]; G64[a] = Gp[a]; }
             hb64 = A->h2b;
         } else {
-            double *x = nullptr, *y = nullptr, *z = nullptr, *bm = nullptr, *Dd = nullptr;
+            double *x = nullptr, *y = nullptr, *z = nullptr;
             int64_t* ids = nullptr;
-            double* G[6];
             MG_TMP(x, sizeof(double) * nloc);
             MG_TMP(y, sizeof(double) * nloc);
             MG_TMP(z, sizeof(double) * nloc);
-            MG_TMP(bm, sizeof(double) * nloc);
             MG_TMP(ids, sizeof(int64_t) * nloc);
-            for (int a = 0; a < 6; ++a) MG_TMP(G[a], sizeof(double) * nloc);
-            MG_TMP(Dd, sizeof(double) * 2 * l2);
-            // a level whose geometry folds (coarse trilinear elements of a strongly
-            // deformed box) takes the amplitude halved until det J > 0 everywhere
-            double amp = opts->amp, mindet = 0.0;
-            for (int halvings = 0;; ++halvings) {
-                MG_TTRY(opts->dirichlet ? sem_box_mesh_dirichlet(ctx, lv.n, lx, amp, x, y, z, ids)
-                                        : sem_box_mesh(ctx, lv.n, lx, amp, x, y, z, ids));
-                const int grc = sem_geometry(ctx, x, y, z, lv.nel, lx, G[0], G[1], G[2], G[3], G[4], G[5], bm,
-                                             &mindet);
-                if (grc == SEM_EGEOMETRY && halvings < 20) { amp = halvings == 19 ? 0.0 : 0.5 * amp; continue; }
-                MG_TTRY(grc);
-                break;
+            if (gal) {      // the node numbering only
+                MG_TTRY(opts->dirichlet ? sem_box_mesh_dirichlet(ctx, lv.n, lx, 0.0, x, y, z, ids)
+                                        : sem_box_mesh(ctx, lv.n, lx, 0.0, x, y, z, ids));
+                lv.amp = 0.0;
+            } else {
+                double *bm = nullptr, *Dd = nullptr;
+                double* G[6];
+                MG_TMP(bm, sizeof(double) * nloc);
+                for (int a = 0; a < 6; ++a) MG_TMP(G[a], sizeof(double) * nloc);
+                MG_TMP(Dd, sizeof(double) * 2 * l2);
+                // a level whose geometry folds (coarse trilinear elements of a strongly
+                // deformed box) takes the amplitude halved until det J > 0 everywhere
+                double amp = opts->amp, mindet = 0.0;
+                for (int halvings = 0;; ++halvings) {
+                    MG_TTRY(opts->dirichlet ? sem_box_mesh_dirichlet(ctx, lv.n, lx, amp, x, y, z, ids)
+                                            : sem_box_mesh(ctx, lv.n, lx, amp, x, y, z, ids));
+                    const int grc = sem_geometry(ctx, x, y, z, lv.nel, lx, G[0], G[1], G[2], G[3], G[4], G[5], bm,
+                                                 &mindet);
+                    if (grc == SEM_EGEOMETRY && halvings < 20) { amp = halvings == 19 ? 0.0 : 0.5 * amp; continue; }
+                    MG_TTRY(grc);
+                    break;
+                }
+                lv.amp = amp;
+                std::vector<double> dx(l2), dxt(l2);
+                MG_TTRY(sem_gll(lx, nullptr, nullptr, dx.data(), dxt.data()));
+                MG_TTRY(sem::check_hip(ctx, hipMemcpy(Dd, dx.data(), sizeof(double) * l2, hipMemcpyHostToDevice),
+                                       "sem_mg_create: hipMemcpy"));
+                MG_TTRY(sem::check_hip(ctx, hipMemcpy(Dd + l2, dxt.data(), sizeof(double) * l2,
+                                                      hipMemcpyHostToDevice), "sem_mg_create: hipMemcpy"));
+                for (int a = 0; a < 3; ++a) { D64[a] = Dd; D64[3 + a] = Dd + l2; }
+                for (int a = 0; a < 6; ++a) G64[a] = G[a];
+                if (opts->h2 > 0.0) {
+                    scale_f64_kernel<<<gl, kBlock, 0, st>>>(bm, opts->h2, nloc);   // bm <- h2 bm
+                    hb64 = bm;
+                }
             }
-            lv.amp = amp;
             std::vector<int64_t> hids(nloc);
             MG_TTRY(sem::check_hip(ctx, hipStreamSynchronize(st), "sem_mg_create: hipStreamSynchronize"));
             MG_TTRY(sem::check_hip(ctx, hipMemcpy(hids.data(), ids, sizeof(int64_t) * nloc, hipMemcpyDeviceToHost),
                                    "sem_mg_create: hipMemcpy"));
             MG_TTRY(sem_gs_setup(ctx, hids.data(), nloc, &lv.gs));
             lv.own_gs = true;
-            std::vector<double> dx(l2), dxt(l2);
-            MG_TTRY(sem_gll(lx, nullptr, nullptr, dx.data(), dxt.data()));
-            MG_TTRY(sem::check_hip(ctx, hipMemcpy(Dd, dx.data(), sizeof(double) * l2, hipMemcpyHostToDevice),
-                                   "sem_mg_create: hipMemcpy"));
-            MG_TTRY(sem::check_hip(ctx, hipMemcpy(Dd + l2, dxt.data(), sizeof(double) * l2, hipMemcpyHostToDevice),
-                                   "sem_mg_create: hipMemcpy"));
-            for (int a = 0; a < 3; ++a) { D64[a] = Dd; D64[3 + a] = Dd + l2; }
-            for (int a = 0; a < 6; ++a) G64[a] = G[a];
-            if (opts->h2 > 0.0) {
-                scale_f64_kernel<<<gl, kBlock, 0, st>>>(bm, opts->h2, nloc);   // bm <- h2 bm
-                hb64 = bm;
-            }
         }
         lv.nu = lv.gs->n_unique;
-        // float32 solver form
-        for (int a = 0; a < 6; ++a) {
-            float* d = nullptr;
-            MG_ALLOC(d, sizeof(float) * l2);
-            to_f32_kernel<<<1, kBlock, 0, st>>>(d, D64[a], 1.0, l2);
-            lv.A.D[a] = d;
-            lv.A.G[a] = nullptr;
-        }
-        const bool bf = q == 0 && opts->fine_bf16;   // bfloat16 factors on the finest level
-        lv.axkind = bf ? sem::AxKind::F32_BF16 : sem::AxKind::F32;
-        if (bf) {
-            uint16_t* gp = nullptr;
-            MG_ALLOC(gp, sizeof(uint16_t) * 6 * nloc);
-            sem::pack_factors_bf16(st, gp, G64, nloc, lx);
-            lv.A.Gp = gp;
+        // the float64 operator of a re-discretised level (and of the first)
+        sem::AxArgs a64{};
+        for (int a = 0; a < 6; ++a) { a64.D[a] = D64[a]; a64.G[a] = G64[a]; }
+        a64.h1 = nullptr;
+        a64.hb = hb64;
+        a64.nel = lv.nel;
+        a64.lx = lx;
+        if (gal) {
+            // float32 element matrices for the V-cycle; Jacobi from their diagonals
+            MG_ALLOC(lv.M, sizeof(float) * 64 * lv.nel);
+            to_f32_kernel<<<vgrid(64 * lv.nel), kBlock, 0, st>>>(lv.M, cur64, 1.0, 64 * lv.nel);
+            mat_diag_kernel<<<gl, kBlock, 0, st>>>(dl, cur64, nloc);
         } else {
-            float* gp = nullptr;
-            MG_ALLOC(gp, sizeof(float) * 6 * nloc);
-            sem::pack_factors_f32(st, gp, G64, nloc, lx);
-            lv.A.Gp = gp;
+            // float32 solver form
+            for (int a = 0; a < 6; ++a) {
+                float* d = nullptr;
+                MG_ALLOC(d, sizeof(float) * l2);
+                to_f32_kernel<<<1, kBlock, 0, st>>>(d, D64[a], 1.0, l2);
+                lv.A.D[a] = d;
+                lv.A.G[a] = nullptr;
+            }
+            const bool bf = q == 0 && opts->fine_bf16;   // bfloat16 factors on the finest level
+            lv.axkind = bf ? sem::AxKind::F32_BF16 : sem::AxKind::F32;
+            if (bf) {
+                uint16_t* gp = nullptr;
+                MG_ALLOC(gp, sizeof(uint16_t) * 6 * nloc);
+                sem::pack_factors_bf16(st, gp, G64, nloc, lx);
+                lv.A.Gp = gp;
+            } else {
+                float* gp = nullptr;
+                MG_ALLOC(gp, sizeof(float) * 6 * nloc);
+                sem::pack_factors_f32(st, gp, G64, nloc, lx);
+                lv.A.Gp = gp;
+            }
+            lv.A.h1 = nullptr;
+            lv.A.hb = nullptr;
+            if (hb64) {
+                void* hb = nullptr;
+                MG_ALLOC(hb, (bf ? sizeof(uint16_t) : sizeof(float)) * nloc);
+                if (bf) MG_TTRY(sem_convert(ctx, hb, SEM_BF16, hb64, SEM_F64, nloc));
+                else to_f32_kernel<<<gl, kBlock, 0, st>>>((float*)hb, hb64, 1.0, nloc);
+                lv.A.hb = hb;
+            }
+            lv.A.nel = lv.nel;
+            lv.A.lx = lx;
+            // Jacobi: the assembled diagonal of A (+ h2 B)
+            MG_TTRY(sem_ax_diag(ctx, dl, D64[0], nullptr, G64[0], G64[1], G64[2], G64[3], G64[4], G64[5], lv.nel,
+                                lx));
+            if (hb64) add_scaled_kernel<<<gl, kBlock, 0, st>>>(dl, hb64, 1.0, nloc);
         }
-        lv.A.h1 = nullptr;
-        lv.A.hb = nullptr;
-        if (hb64) {
-            void* hb = nullptr;
-            MG_ALLOC(hb, (bf ? sizeof(uint16_t) : sizeof(float)) * nloc);
-            if (bf) MG_TTRY(sem_convert(ctx, hb, SEM_BF16, hb64, SEM_F64, nloc));
-            else to_f32_kernel<<<gl, kBlock, 0, st>>>((float*)hb, hb64, 1.0, nloc);
-            lv.A.hb = hb;
-        }
-        lv.A.nel = lv.nel;
-        lv.A.lx = lx;
-        // Jacobi: the assembled diagonal of A (+ h2 B)
-        MG_TTRY(sem_ax_diag(ctx, dl, D64[0], nullptr, G64[0], G64[1], G64[2], G64[3], G64[4], G64[5], lv.nel, lx));
-        if (hb64) add_scaled_kernel<<<gl, kBlock, 0, st>>>(dl, hb64, 1.0, nloc);
         MG_ALLOC(lv.minv, sizeof(float) * lv.nu);
         diag_recip_kernel<<<vgrid(lv.nu), kBlock, 0, st>>>(lv.minv, dl, lv.gs->uoff, lv.gs->uidx, lv.nu);
         MG_ALLOC(lv.own, nloc);
@@ -904,28 +1038,43 @@ extern "C" int sem_mg_create(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A
         if (q > 0) MG_ALLOC(lv.bl, sizeof(float) * nloc);
         SEM_LAUNCH_CHECK(ctx);
         if (q == nl - 1) {
-            // the coarsest matrix, column by column, with the float64 operator
             const int64_t m = lv.nu;
-            double *ul = nullptr, *wl = nullptr, *cols = nullptr;
-            MG_TMP(ul, sizeof(double) * nloc);
-            MG_TMP(wl, sizeof(double) * nloc);
-            MG_TMP(cols, sizeof(double) * m * m);
-            sem::AxArgs a64{};
-            for (int a = 0; a < 6; ++a) { a64.D[a] = D64[a]; a64.G[a] = G64[a]; }
-            a64.h1 = nullptr;
-            a64.hb = hb64;
-            a64.nel = lv.nel;
-            a64.lx = lx;
-            for (int64_t j = 0; j < m; ++j) {
-                unit_local_kernel<<<gl, kBlock, 0, st>>>(ul, lv.gs->lid, j, nloc);
-                MG_TTRY(sem::launch_ax(ctx, sem::AxKind::F64, a64, wl, ul, nullptr, nullptr, nullptr));
-                column_kernel<<<vgrid(m), kBlock, 0, st>>>(cols + j * m, wl, lv.gs->uoff, lv.gs->uidx, m);
+            std::vector<double> Ac((size_t)m * m, 0.0);
+            if (gal) {
+                // assembled from the element matrices: A[i][j] += M_e[a][b] over the
+                // element's nodes a, b with plan indices i, j (Dirichlet nodes skipped)
+                std::vector<double> Mh((size_t)64 * lv.nel);
+                std::vector<int32_t> lidh(nloc);
+                MG_TTRY(sem::check_hip(ctx, hipStreamSynchronize(st), "sem_mg_create: hipStreamSynchronize"));
+                MG_TTRY(sem::check_hip(ctx, hipMemcpy(Mh.data(), cur64, sizeof(double) * Mh.size(),
+                                                      hipMemcpyDeviceToHost), "sem_mg_create: hipMemcpy"));
+                MG_TTRY(sem::check_hip(ctx, hipMemcpy(lidh.data(), lv.gs->lid, sizeof(int32_t) * nloc,
+                                                      hipMemcpyDeviceToHost), "sem_mg_create: hipMemcpy"));
+                for (int64_t e = 0; e < lv.nel; ++e)
+                    for (int a = 0; a < 8; ++a) {
+                        const int32_t i = lidh[e * 8 + a];
+                        if (i < 0) continue;
+                        for (int b = 0; b < 8; ++b) {
+                            const int32_t j = lidh[e * 8 + b];
+                            if (j >= 0) Ac[(size_t)i * m + j] += Mh[e * 64 + a * 8 + b];
+                        }
+                    }
+            } else {
+                // the coarsest matrix, column by column, with the float64 operator
+                double *ul = nullptr, *wl = nullptr, *cols = nullptr;
+                MG_TMP(ul, sizeof(double) * nloc);
+                MG_TMP(wl, sizeof(double) * nloc);
+                MG_TMP(cols, sizeof(double) * m * m);
+                for (int64_t j = 0; j < m; ++j) {
+                    unit_local_kernel<<<gl, kBlock, 0, st>>>(ul, lv.gs->lid, j, nloc);
+                    MG_TTRY(sem::launch_ax(ctx, sem::AxKind::F64, a64, wl, ul, nullptr, nullptr, nullptr));
+                    column_kernel<<<vgrid(m), kBlock, 0, st>>>(cols + j * m, wl, lv.gs->uoff, lv.gs->uidx, m);
+                }
+                SEM_LAUNCH_CHECK(ctx);
+                MG_TTRY(sem::check_hip(ctx, hipStreamSynchronize(st), "sem_mg_create: hipStreamSynchronize"));
+                MG_TTRY(sem::check_hip(ctx, hipMemcpy(Ac.data(), cols, sizeof(double) * m * m,
+                                                      hipMemcpyDeviceToHost), "sem_mg_create: hipMemcpy"));
             }
-            SEM_LAUNCH_CHECK(ctx);
-            std::vector<double> Ac((size_t)m * m);
-            MG_TTRY(sem::check_hip(ctx, hipStreamSynchronize(st), "sem_mg_create: hipStreamSynchronize"));
-            MG_TTRY(sem::check_hip(ctx, hipMemcpy(Ac.data(), cols, sizeof(double) * m * m, hipMemcpyDeviceToHost),
-                                   "sem_mg_create: hipMemcpy"));
             for (int64_t i = 0; i < m; ++i)        // symmetrise (rounding only)
                 for (int64_t j = i + 1; j < m; ++j) {
                     const double s = 0.5 * (Ac[i * m + j] + Ac[j * m + i]);
@@ -945,6 +1094,49 @@ extern "C" int sem_mg_create(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A
             MG_ALLOC(mg->ainv, sizeof(float) * m * m);
             MG_TTRY(sem::check_hip(ctx, hipMemcpy(mg->ainv, Af.data(), sizeof(float) * m * m, hipMemcpyHostToDevice),
                                    "sem_mg_create: hipMemcpy"));
+        } else if (galerkin && lxs[q + 1] == 2) {
+            // the next level's element matrices (float64), from this level's operator
+            const int64_t nel1 = (int64_t)ns[q + 1] * ns[q + 1] * ns[q + 1];
+            double* next64 = nullptr;
+            {
+                hipError_t e = hipMalloc((void**)&next64, sizeof(double) * 64 * nel1);
+                if (e != hipSuccess) { free_tmp(); return bail(sem::check_hip(ctx, e, "sem_mg_create: hipMalloc")); }
+                carry.v.push_back(next64);
+            }
+            const double* mine = cur64;            // this level's element matrices (Galerkin level)
+            if (!gal) {
+                // J^T A_e J column by column: A applied to the 8 coarse basis functions
+                // interpolated to this level (the identity for an lx = 2 level), then
+                // projected with J^T.  For a p-transfer J is the lx = 2 basis at this
+                // level's GLL points; for an h-transfer these are this level's own matrices.
+                double *ul = nullptr, *wl = nullptr, *Jd = nullptr, *own64 = nullptr;
+                MG_TMP(ul, sizeof(double) * nloc);
+                MG_TMP(wl, sizeof(double) * nloc);
+                MG_TMP(Jd, sizeof(double) * 2 * lx);
+                std::vector<double> xf(lx), Jh(2 * lx);
+                sem::gll_host(lx, xf.data(), nullptr, nullptr);
+                for (int i = 0; i < lx; ++i) {
+                    Jh[i * 2 + 0] = kinds[q] == 0 ? 0.5 * (1.0 - xf[i]) : (i == 0 ? 1.0 : 0.0);
+                    Jh[i * 2 + 1] = kinds[q] == 0 ? 0.5 * (1.0 + xf[i]) : (i == 1 ? 1.0 : 0.0);
+                }
+                MG_TTRY(sem::check_hip(ctx, hipMemcpy(Jd, Jh.data(), sizeof(double) * 2 * lx, hipMemcpyHostToDevice),
+                                       "sem_mg_create: hipMemcpy"));
+                double* dst = next64;
+                if (kinds[q] == 1) {
+                    MG_TMP(own64, sizeof(double) * 64 * lv.nel);
+                    dst = own64;
+                }
+                for (int bc = 0; bc < 8; ++bc) {
+                    basis_field_kernel<<<gl, kBlock, 0, st>>>(ul, Jd, lx, bc, nloc);
+                    MG_TTRY(sem::launch_ax(ctx, sem::AxKind::F64, a64, wl, ul, nullptr, nullptr, nullptr));
+                    project_basis_kernel<<<vgrid(8 * lv.nel), kBlock, 0, st>>>(dst, wl, Jd, lx, bc, lv.nel);
+                }
+                mine = own64;
+            }
+            if (kinds[q] == 1)
+                galerkin_h_kernel<<<vgrid(64 * nel1), kBlock, 0, st>>>(next64, mine, lv.n, ns[q + 1], nel1);
+            SEM_LAUNCH_CHECK(ctx);
+            cur64 = next64;
         }
         free_tmp();
     }

@@ -35,20 +35,28 @@ def _plan_order(ids, nu):
     return plan_of
 
 
-CASES = [  # n, lx, amp, dirichlet, h2, degree, lo
-    (4, 8, 0.1, False, None, 2, 0.3),
-    (4, 4, 0.15, True, None, 2, 0.15),          # the lx = 2 level folds at 0.15: halved amplitude
-    (4, 6, 0.12, True, None, 3, 0.2),
-    (2, 5, 0.1, False, 20.0, 3, 0.3),
-    (4, 3, 0.1, True, 5.0, 1, 0.2),
+CASES = [  # n, lx, amp, dirichlet, h2, degree, lo, galerkin
+    (4, 8, 0.1, False, None, 2, 0.3, False),
+    (4, 4, 0.15, True, None, 2, 0.15, False),   # the lx = 2 level folds at 0.15: halved amplitude
+    (4, 6, 0.12, True, None, 3, 0.2, False),
+    (2, 5, 0.1, False, 20.0, 3, 0.3, False),
+    (4, 3, 0.1, True, 5.0, 1, 0.2, False),
+    # Galerkin lx = 2 levels: from a p-level (lx 4, 3, 5 -> 2), then h-levels; the
+    # periodic singular coarsest level; Helmholtz; a first level of lx = 2 (its
+    # own element matrices feed the h-product)
+    (4, 4, 0.15, True, None, 2, 0.15, True),
+    (4, 8, 0.1, False, None, 2, 0.3, True),
+    (4, 6, 0.12, True, None, 3, 0.2, True),
+    (2, 5, 0.1, False, 20.0, 3, 0.3, True),
+    (4, 2, 0.1, True, 5.0, 2, 0.2, True),
 ]
 
 
-@pytest.mark.parametrize("n,lx,amp,dirichlet,h2,degree,lo", CASES)
-def test_vcycle_matches_oracle(sem_ctx, n, lx, amp, dirichlet, h2, degree, lo):
+@pytest.mark.parametrize("n,lx,amp,dirichlet,h2,degree,lo,galerkin", CASES)
+def test_vcycle_matches_oracle(sem_ctx, n, lx, amp, dirichlet, h2, degree, lo, galerkin):
     op = BoxOperator(sem_ctx, n, lx, amp, dirichlet=dirichlet, keep_coords=False)
-    mg = op.multigrid(h2=h2 or 0.0, degree=degree, lo=lo)
-    H = omg.Hierarchy(n, lx, amp, dirichlet=dirichlet, h2=h2, degree=degree, lo=lo)
+    mg = op.multigrid(h2=h2 or 0.0, degree=degree, lo=lo, galerkin=galerkin)
+    H = omg.Hierarchy(n, lx, amp, dirichlet=dirichlet, h2=h2, degree=degree, lo=lo, galerkin=galerkin)
     nl = P.sem_mg_levels(mg)
     assert nl == len(H.shapes)
     lmax = []
@@ -203,6 +211,41 @@ def test_multigrid_iterations_do_not_grow_with_the_mesh(sem_ctx):
         op.gs.close()
     print(f"multigrid FCG iterations: {its}")
     assert its[16] <= 1.5 * its[8], its
+
+
+def test_galerkin_levels_on_a_folding_box(sem_ctx):
+    """8^3 lx = 8 Dirichlet box at amplitude 0.15, where the re-discretised
+    lx = 2 levels fold and take a halved amplitude: flexible CG with Galerkin
+    lx = 2 levels converges to relres 1e-10 (recomputed by the oracle) in fewer
+    iterations than with the re-discretised ones."""
+    n, lx, amp = 8, 8, 0.15
+    op = BoxOperator(sem_ctx, n, lx, amp, dirichlet=True)
+    ref = BoxProblem(n, lx, amp, dirichlet=True)
+    k, a, ph = synth.fourier_modes(3)
+    b = op.fourier_rhs(k, a, ph, project=False)
+    bref = ref.fourier_rhs(k, a, ph)
+    free = ref.ids >= 0
+    its = {}
+    for g in (False, True):
+        mg = op.multigrid(galerkin=g, n_coarse=2)
+        amps = [P.sem_mg_level_info(mg, q)[4] for q in range(P.sem_mg_levels(mg))]
+        cg = op.solver(P.SEM_SOLVE_F32_IR, mg=mg)
+        x = torch.empty_like(b)
+        rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10, precision=P.SEM_SOLVE_F32_IR, ir_mode=1, mg=mg)
+        torch.cuda.synchronize()
+        assert rc == P.SEM_OK and st["converged"] and not st["fell_back"], st
+        xg = np.zeros(ref.nu)
+        xg[ref.ids[free]] = x.cpu().numpy()[free]
+        assert np.linalg.norm(bref - ref.apply(xg)) / np.linalg.norm(bref) <= 1.2e-10
+        its[g] = st["iterations"]
+        print(f"galerkin={g}: {its[g]} its, level amplitudes {amps}")
+        if g:
+            assert amps[0] == amp and all(v == 0.0 for v, (_, l, _) in zip(amps[1:], omg.level_shapes(n, lx)[1:])
+                                          if l == 2)
+        cg.close()
+        mg.close()
+    assert its[True] < its[False], its
+    op.gs.close()
 
 
 def test_multigrid_errors(sem_ctx):
