@@ -32,10 +32,25 @@ __global__ void gs_kernel(T* __restrict__ u, const int32_t* __restrict__ off,
         if (g < n_shared + n_masked) u[midx[g - n_shared]] = T(0);
         return;
     }
+    // the first eight copies (a hexahedral mesh has at most eight) by independent
+    // predicated loads issued together, summed in CSR order; any further copies
+    // one by one
     const int32_t b = off[g], e = off[g + 1];
-    T s = 0;
-    for (int32_t q = b; q < e; ++q) s += u[idx[q]];
-    for (int32_t q = b; q < e; ++q) u[idx[q]] = s;
+    int32_t L[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) L[q] = b + q < e ? idx[b + q] : -1;
+    T v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = L[q] >= 0 ? u[L[q]] : T(0);
+    T s = v[0];
+#pragma unroll
+    for (int q = 1; q < 8; ++q)
+        if (L[q] >= 0) s += v[q];
+    for (int32_t q = b + 8; q < e; ++q) s += u[idx[q]];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (L[q] >= 0) u[L[q]] = s;
+    for (int32_t q = b + 8; q < e; ++q) u[idx[q]] = s;
 }
 
 __global__ void mult_kernel(double* __restrict__ mult, const int32_t* __restrict__ off,
