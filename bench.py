@@ -562,8 +562,8 @@ def mg_run(ctx, P, n, lx, amp, tol=1e-10, sweep=False, repeat=3):
     """--mode mg: the multigrid-preconditioned solves of the n^3 box (periodic,
     32 Fourier modes) -- flexible CG in float64 and inside float32 residual
     replacement -- each solved `repeat` times after one warm-up; with --sweep
-    over the Chebyshev degree, the interval's lower end and the coarsest
-    h-level.  One JSON line."""
+    over the Chebyshev degree, Galerkin or re-discretised lx = 2 levels and the
+    coarsest h-level (at n >= 64 over the degree only).  One JSON line."""
     import torch
     import synth
     from paper_2506_20994_amd.box import BoxOperator
@@ -572,7 +572,9 @@ def mg_run(ctx, P, n, lx, amp, tol=1e-10, sweep=False, repeat=3):
     b = op.fourier_rhs(k, a, ph)
     x = torch.empty_like(b)
     grid = [dict(MG_OPTS)]
-    if sweep:
+    if sweep and n >= 64:      # the strongly deformed 64^3 box: the smoothing degree
+        grid = [dict(MG_OPTS, degree=d) for d in (3, 4, 6)]
+    elif sweep:
         grid = [dict(MG_OPTS, degree=d, galerkin=g, n_coarse=nc) for d in (2, 3) for g in (0, 1) for nc in (4, 8)]
     out = []
     for cfg in grid:
@@ -740,9 +742,9 @@ def main():
     print(f"[bench] box {n}^3 lx={lx} amp={amp}: n_local={op.n_local} "
           f"min detJ={op.min_detj:.3e}", file=sys.stderr, flush=True)
 
-    # run-time choice of the operator's kernel variant on this element count
-    # (the paper's autotuning): every variant timed on synthetic inputs, the
-    # fastest kept for the timed steps
+    # run-time choice of the operator's kernel variant (the paper's autotuning):
+    # every variant timed on the workload's own fields, the fastest kept for the
+    # timed steps
     names = {P.SEM_AX_COLUMN: "column", P.SEM_AX_COLUMN_PF: "column_pf", P.SEM_AX_SLICE: "slice",
              P.SEM_AX_3D: "3d", P.SEM_AX_WAVE: "wave"}
     kernels = {P.SEM_AX_COLUMN: f"ax_kernel<{lx}, double>", P.SEM_AX_COLUMN_PF: f"ax_kernel<{lx}, double>",
@@ -751,7 +753,7 @@ def main():
     variant = P.SEM_AX_DEFAULT
     tune_us = None
     if not args.no_tune:
-        variant, tune_us = P.sem_ax_tune(ctx, lx, op.nel, reps=20)
+        variant, tune_us = P.sem_ax_tune_on(ctx, w, u, *op.D, op.h1, *op.G, op.nel, lx, reps=50)
         print(f"[bench] operator variant: {names[variant]} "
               f"({', '.join(f'{names[v]} {t:.1f} us' for v, t in enumerate(tune_us) if t > 0)})",
               file=sys.stderr, flush=True)

@@ -209,6 +209,14 @@ int sem_ax_get_variant(sem_ctx_t ctx, int lx, int* variant);
  * receives the average launch time of each variant in microseconds, -1 where
  * a variant does not exist.  Synchronous. */
 int sem_ax_tune(sem_ctx_t ctx, int lx, int64_t nel, int reps, double* us, int* best);
+/* The same timing on the caller's own float64 operands (the arguments of
+ * sem_ax, h1 may be NULL; w is overwritten, no allocation), as the paper's
+ * autotuning times the variants on the call it serves (Sec. 4).  SEM_EINVAL
+ * for null arrays or an output that overlaps an input. */
+int sem_ax_tune_on(sem_ctx_t ctx, void* w, const void* u, const void* dx, const void* dy, const void* dz,
+                   const void* dxt, const void* dyt, const void* dzt, const void* h1, const void* g11,
+                   const void* g22, const void* g33, const void* g12, const void* g13, const void* g23,
+                   int64_t nel, int lx, int reps, double* us, int* best);
 
 /* ---------------------------------------------------------- gather-scatter */
 

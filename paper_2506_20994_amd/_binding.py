@@ -19,7 +19,7 @@ __all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONV
            "sem_lp_gradients", "sem_lp_adam", "sem_lp_set_metric", "sem_lp_set_jacobi_base", "sem_lp_set_linear", "sem_lp_train_step", "sem_lp_apply", "sem_lp_apply_unique", "sem_lp_save", "sem_lp_load", "sem_lp_set_block", "LP_SLOTS",
            "SEM_LP_IN", "SEM_LP_IN_PAD", "SEM_LP_HIDDEN", "SEM_LP_OUT", "SemMgOpts", "Multigrid",
            "sem_mg_create", "sem_mg_destroy", "sem_mg_levels", "sem_mg_level_info", "sem_mg_set_lmax",
-           "sem_mg_apply", "sem_mg_set_graphs", "sem_ax_set_variant", "sem_ax_get_variant", "sem_ax_tune",
+           "sem_mg_apply", "sem_mg_set_graphs", "sem_ax_set_variant", "sem_ax_get_variant", "sem_ax_tune", "sem_ax_tune_on",
            "SEM_AX_DEFAULT", "SEM_AX_COLUMN", "SEM_AX_COLUMN_PF", "SEM_AX_SLICE", "SEM_AX_3D", "SEM_AX_WAVE", "SEM_AX_VARIANTS", "sem_lp_snapshot", "sem_lp_reference_block"]
 
 SEM_LP_IN, SEM_LP_IN_PAD, SEM_LP_HIDDEN, SEM_LP_OUT = 518, 528, 256, 512
@@ -133,6 +133,7 @@ EXPORTS = {
     "sem_ax_set_variant": (_int, [_vp, _int, _int]),
     "sem_ax_get_variant": (_int, [_vp, _int, ctypes.POINTER(_int)]),
     "sem_ax_tune": (_int, [_vp, _int, _i64, _int, _pdbl, ctypes.POINTER(_int)]),
+    "sem_ax_tune_on": (_int, [_vp, _vp, _vp] + [_vp] * 6 + [_vp] * 7 + [_i64, _int, _int, _pdbl, ctypes.POINTER(_int)]),
     "sem_mg_create": (_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
     "sem_mg_destroy": (_int, [_vp]),
     "sem_mg_levels": (_int, [_vp, ctypes.POINTER(_int)]),
@@ -668,4 +669,16 @@ def sem_ax_tune(ctx, lx, nel, reps=20):
     best = _int(0)
     h = ctx.bind()
     _check(lib().sem_ax_tune(h, lx, nel, reps, us, ctypes.byref(best)), h)
+    return best.value, list(us)
+
+
+def sem_ax_tune_on(ctx, w, u, dx, dy, dz, dxt, dyt, dzt, h1, g11, g22, g33, g12, g13, g23, nel, lx, reps=20):
+    """Times the float64 operator's variants on these operands (w is
+    overwritten) and selects the fastest; returns (best, [us per variant])."""
+    us = (ctypes.c_double * SEM_AX_VARIANTS)()
+    best = _int(0)
+    h = ctx.bind()
+    _check(lib().sem_ax_tune_on(h, _ptr(w), _ptr(u), _ptr(dx), _ptr(dy), _ptr(dz), _ptr(dxt), _ptr(dyt),
+                                _ptr(dzt), _ptr(h1), _ptr(g11), _ptr(g22), _ptr(g33), _ptr(g12), _ptr(g13),
+                                _ptr(g23), nel, lx, reps, us, ctypes.byref(best)), h)
     return best.value, list(us)

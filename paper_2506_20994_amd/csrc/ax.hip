@@ -766,6 +766,47 @@ extern "C" int sem_ax_get_variant(sem_ctx_t ctx, int lx, int* variant) {
     return SEM_OK;
 }
 
+namespace {
+
+// every float64 variant that exists at lx timed on the given operands (`reps`
+// launches after two warm-ups, HIP events on the context's stream); the
+// fastest is selected on the context
+int time_variants(sem_ctx_t ctx, int lx, void* w, const void* u, const void* const* D, const void* h1,
+                  const void* const* G, int64_t nel, int reps, double* us, int* best) {
+    hipStream_t st = ctx->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SEM_HIP(ctx, hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) { (void)hipEventDestroy(e0); return sem::check_hip(ctx, he, "hipEventCreate"); }
+    double best_us = 1e300;
+    int best_v = SEM_AX_COLUMN, rc = SEM_OK;
+    for (int v = 0; v < SEM_AX_VARIANTS; ++v) {
+        if (us) us[v] = -1.0;
+        if (!variant_exists(lx, v)) continue;
+        for (int q = 0; q < 2 + reps && rc == SEM_OK; ++q) {
+            if (q == 2) (void)hipEventRecord(e0, st);
+            rc = dispatch<double, double, double, double>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr, nullptr,
+                                                          nullptr, nullptr, v);
+        }
+        if (rc) break;
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double t = 1e3 * ms / reps;
+        if (us) us[v] = t;
+        if (t < best_us) { best_us = t; best_v = v; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    ctx->ax_variant[lx] = best_v;
+    *best = best_v;
+    return SEM_OK;
+}
+
+}  // namespace
+
 extern "C" int sem_ax_tune(sem_ctx_t ctx, int lx, int64_t nel, int reps, double* us, int* best) {
     int rc = sem::enter(ctx);
     if (rc) return rc;
@@ -801,33 +842,27 @@ extern "C" int sem_ax_tune(sem_ctx_t ctx, int lx, int64_t nel, int reps, double*
     tune_fill_kernel<<<4096, 256, 0, st>>>(u, a[2], a[3], a[4], a[5], a[6], a[7], h1, n);
     const void* D[6] = {Dd, Dd, Dd, Dd + l2, Dd + l2, Dd + l2};
     const void* G[6] = {a[2], a[3], a[4], a[5], a[6], a[7]};
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
-    double best_us = 1e300;
-    int best_v = SEM_AX_COLUMN;
-    for (int v = 0; v < SEM_AX_VARIANTS; ++v) {
-        if (us) us[v] = -1.0;
-        if (!variant_exists(lx, v)) continue;
-        for (int q = 0; q < 2 + reps && rc == SEM_OK; ++q) {
-            if (q == 2) (void)hipEventRecord(e0, st);
-            rc = dispatch<double, double, double, double>(ctx, lx, w, u, D, h1, G, nel, nullptr, nullptr, nullptr,
-                                                          nullptr, nullptr, v);
-        }
-        if (rc) break;
-        (void)hipEventRecord(e1, st);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        const double t = 1e3 * ms / reps;
-        if (us) us[v] = t;
-        if (t < best_us) { best_us = t; best_v = v; }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    rc = time_variants(ctx, lx, w, u, D, h1, G, nel, reps, us, best);
     cleanup();
+    return rc;
+}
+
+extern "C" int sem_ax_tune_on(sem_ctx_t ctx, void* w, const void* u, const void* dx, const void* dy,
+                              const void* dz, const void* dxt, const void* dyt, const void* dzt, const void* h1,
+                              const void* g11, const void* g22, const void* g33, const void* g12,
+                              const void* g13, const void* g23, int64_t nel, int lx, int reps, double* us,
+                              int* best) {
+    int rc = sem::enter(ctx);
     if (rc) return rc;
-    ctx->ax_variant[lx] = best_v;
-    *best = best_v;
-    return SEM_OK;
+    if (!sem::lx_ok(lx)) return sem::fail(ctx, SEM_EUNSUPPORTED_LX, "sem_ax_tune_on: lx=%d", lx);
+    if (nel < 1 || reps < 1 || !best || !w || !u) return sem::fail(ctx, SEM_EINVAL, "sem_ax_tune_on: bad argument");
+    const void* D[6] = {dx, dy, dz, dxt, dyt, dzt};
+    const void* G[6] = {g11, g22, g33, g12, g13, g23};
+    for (int q = 0; q < 6; ++q)
+        if (!D[q] || !G[q]) return sem::fail(ctx, SEM_EINVAL, "sem_ax_tune_on: null operator array");
+    const size_t nb = (size_t)nel * lx * lx * lx * sizeof(double), nd = (size_t)lx * lx * sizeof(double);
+    bool alias = overlaps(w, nb, u, nb) || overlaps(w, nb, h1, nb);
+    for (int q = 0; q < 6; ++q) alias = alias || overlaps(w, nb, G[q], nb) || overlaps(w, nb, D[q], nd);
+    if (alias) return sem::fail(ctx, SEM_EINVAL, "sem_ax_tune_on: output overlaps an input");
+    return time_variants(ctx, lx, w, u, D, h1, G, nel, reps, us, best);
 }

@@ -10,9 +10,10 @@ count and lx: every point uses N_E elements of random symmetric positive
 definite factors, h1 ~ U[0.5, 2] and u ~ N(0, 1).
 
 With --tune every point first times each float64 kernel variant of the
-operator (sem_ax_tune: the column mapping, the same with the other prefetch
-choice, the slice-pipelined column mapping, one thread per node), as the
-paper's run-time autotuning does (Sec. 4), and the timed run uses the fastest.
+operator on its own fields (sem_ax_tune_on: the column mapping, the same with
+the other prefetch choice, the slice-pipelined column mapping, one thread per
+node, one element per wave), as the paper's run-time autotuning does (Sec. 4),
+and the timed run uses the fastest.
 
 Usage: python -m paper_2506_20994_amd.sweep [--reps R] [--out FILE] [--lx 3,..] [--sizes ..] [--tune]
 """
@@ -50,12 +51,12 @@ def run(reps=50, lxs=LXS, sizes=SIZES, tune=False):
     for lx in lxs:
         for nel in sizes:
             tuned = None
-            if tune:
-                best, us = B.sem_ax_tune(ctx, lx, nel, reps=20)
-                tuned = {"variant": names[best],
-                         "variant_us": {names[v]: round(t, 2) for v, t in enumerate(us) if t > 0}}
             u, G, h1, D = _fields(ctx, nel, lx)
             w = torch.empty_like(u)
+            if tune:
+                best, us = B.sem_ax_tune_on(ctx, w, u, *D, h1, *G, nel, lx, reps=20)
+                tuned = {"variant": names[best],
+                         "variant_us": {names[v]: round(t, 2) for v, t in enumerate(us) if t > 0}}
             for _ in range(5):
                 B.sem_ax(ctx, w, u, *D, h1, *G, nel, lx)
             st = torch.cuda.current_stream()

@@ -277,3 +277,33 @@ def test_ax_tune_selects_the_fastest_variant(sem_ctx):
             P.sem_ax_set_variant(sem_ctx, lx, P.SEM_AX_DEFAULT)
     with pytest.raises(P.SemError):
         P.sem_ax_tune(sem_ctx, 13, 8)
+
+
+@pytest.mark.parametrize("lx,use_h1", [(5, True), (8, True), (8, False)])
+def test_ax_tune_on_the_callers_operands(sem_ctx, lx, use_h1):
+    """sem_ax_tune_on times the variants on the caller's own fields (w is
+    scratch), selects the fastest, and the tuned operator on those fields
+    equals the oracle; an output overlapping an input is refused."""
+    nel = 200
+    G, h1 = synth.random_spd_factors(nel, lx, 91)
+    h1 = h1 if use_h1 else None
+    u = synth.local_normal(nel, lx, 92)
+    du = to_dev(u, torch.float64)
+    dG = [to_dev(g, torch.float64) for g in G]
+    dh = None if h1 is None else to_dev(h1, torch.float64)
+    D = _gpu_D(lx, torch.float64)
+    w = torch.empty_like(du)
+    try:
+        best, us = P.sem_ax_tune_on(sem_ctx, w, du, *D, dh, *dG, nel, lx, reps=3)
+        assert us[best] == min(t for t in us if t > 0)
+        assert P.sem_ax_get_variant(sem_ctx, lx) == best
+        w.fill_(float("nan"))
+        P.sem_ax(sem_ctx, w, du, *D, dh, *dG, nel, lx)
+        torch.cuda.synchronize()
+        ref = ax_einsum(u, *listing_matrices(lx), h1, *G)
+        assert rel_inf(w.cpu().numpy(), ref) <= TOL64
+        with pytest.raises(P.SemError) as ei:
+            P.sem_ax_tune_on(sem_ctx, du, du, *D, dh, *dG, nel, lx, reps=1)
+        assert ei.value.code == P.SEM_EINVAL
+    finally:
+        P.sem_ax_set_variant(sem_ctx, lx, P.SEM_AX_DEFAULT)
