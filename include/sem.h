@@ -204,10 +204,12 @@ int sem_ax_set_variant(sem_ctx_t ctx, int lx, int variant);
 int sem_ax_get_variant(sem_ctx_t ctx, int lx, int* variant);
 /* Time every variant that exists at lx on nel elements of synthetic inputs
  * (allocated and freed here; `reps` launches each after two warm-ups, HIP
- * events on the context's stream), select the fastest for lx on this context
- * and return it in *best.  us (host, SEM_AX_VARIANTS entries, may be NULL)
- * receives the average launch time of each variant in microseconds, -1 where
- * a variant does not exist.  Synchronous. */
+ * events on the context's stream; two rounds over the variants, each
+ * variant's faster round kept, so that the clock ramp of an idle GPU does not
+ * penalise the variant timed first), select the fastest for lx on this
+ * context and return it in *best.  us (host, SEM_AX_VARIANTS entries, may be
+ * NULL) receives the average launch time of each variant in microseconds, -1
+ * where a variant does not exist.  Synchronous. */
 int sem_ax_tune(sem_ctx_t ctx, int lx, int64_t nel, int reps, double* us, int* best);
 /* The same timing on the caller's own float64 operands (the arguments of
  * sem_ax, h1 may be NULL; w is overwritten, no allocation), as the paper's
