@@ -52,7 +52,6 @@ constexpr int kVecGrid = 2048;
 constexpr int kMaxF3 = SEM_LX_MAX * SEM_LX_MAX * SEM_LX_MAX;   // fine element nodes
 constexpr int kMaxC = SEM_LX_MAX / 2;                          // coarse lx of any transfer
 constexpr int64_t kCoarseMax = 2048;                           // unknowns of the dense coarsest solve
-constexpr int kCoarseThreads = 1024;
 
 #define MG_LOOP(i, n) \
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
@@ -233,8 +232,11 @@ prolong_kernel(float* __restrict__ xf, const float* __restrict__ xc, const int32
 }
 
 // Coarsest level: x = Ainv b with b assembled from the restricted local field
-// (bl) or given (bin); one workgroup.
-__global__ void __launch_bounds__(kCoarseThreads)
+// (bl) or given (bin).  Every workgroup assembles all of b into LDS, then each
+// of its waves forms kCoarseRows rows of Ainv b, the lanes striding along the
+// row (coalesced) and a wave sum closing it.
+constexpr int kCoarseRows = 4;
+__global__ void __launch_bounds__(kBlock)
 coarse_kernel(float* __restrict__ x, const float* __restrict__ bin, const float* __restrict__ bl,
               const float* __restrict__ ainv, const int32_t* __restrict__ uoff, const int32_t* __restrict__ uidx,
               int nu, const int* __restrict__ skip) {
@@ -242,12 +244,23 @@ coarse_kernel(float* __restrict__ x, const float* __restrict__ bin, const float*
     __shared__ float sb[kCoarseMax];
     for (int u = threadIdx.x; u < nu; u += blockDim.x) sb[u] = bl ? assemble_local(bl, uoff, uidx, u) : bin[u];
     __syncthreads();
-    for (int i = threadIdx.x; i < nu; i += blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int row0 = (blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * kCoarseRows;
+    for (int q = 0; q < kCoarseRows; ++q) {
+        const int i = row0 + q;
+        if (i >= nu) break;                       // uniform across the wave
         const float* row = ainv + (int64_t)i * nu;
         float s = 0.f;
-        for (int j = 0; j < nu; ++j) s += row[j] * sb[j];
-        x[i] = s;
+        for (int j = lane; j < nu; j += 64) s += row[j] * sb[j];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == 0) x[i] = s;
     }
+}
+
+unsigned coarse_grid(int64_t nu) {
+    const int64_t rows_per_block = (kBlock / 64) * kCoarseRows;
+    return (unsigned)std::max<int64_t>(1, (nu + rows_per_block - 1) / rows_per_block);
 }
 
 // Galerkin level operator: w_l = M_e u_e, one thread per local node of the
@@ -651,7 +664,7 @@ int vcycle(sem_mg_t mg, float* xout, const float* bin, const int* skip) {
     auto& Ls = mg->L;
     if (nl == 1) {
         MgLevel& c = Ls[0];
-        coarse_kernel<<<1, kCoarseThreads, 0, st>>>(xout, bin, nullptr, mg->ainv, c.gs->uoff, c.gs->uidx,
+        coarse_kernel<<<coarse_grid(c.nu), kBlock, 0, st>>>(xout, bin, nullptr, mg->ainv, c.gs->uoff, c.gs->uidx,
                                                     (int)c.nu, skip);
         SEM_LAUNCH_CHECK(mg->ctx);
         return SEM_OK;
@@ -678,7 +691,7 @@ int vcycle(sem_mg_t mg, float* xout, const float* bin, const int* skip) {
     }
     {
         MgLevel& c = Ls[nl - 1];
-        coarse_kernel<<<1, kCoarseThreads, 0, st>>>(c.x, nullptr, c.bl, mg->ainv, c.gs->uoff, c.gs->uidx,
+        coarse_kernel<<<coarse_grid(c.nu), kBlock, 0, st>>>(c.x, nullptr, c.bl, mg->ainv, c.gs->uoff, c.gs->uidx,
                                                     (int)c.nu, skip);
         SEM_LAUNCH_CHECK(mg->ctx);
     }
