@@ -611,24 +611,27 @@ def mg_run(ctx, P, n, lx, amp, tol=1e-10, sweep=False, repeat=3):
 def scale_run(ctx, P, n=64, amp=0.15, tol=1e-10):
     """The full stack at scale (--mode scale): a 64^3 box (E = 262144) with
     amplitude 0.15 at lx = 8 (134M local nodes) and lx = 10 (262M): operator
-    throughput, float64 Jacobi-PCG against float32 residual replacement, and at
-    lx = 8 the network (trained as in learned_comparison on 16^3 boxes) with
-    float32 / bfloat16 residual replacement.  Several minutes of GPU time."""
+    throughput, float64 Jacobi-PCG against float32 residual replacement, the
+    network for that lx (trained as in learned_comparison on 16^3 boxes: 128 at
+    lx = 8, 64 at lx = 10) with float32 / bfloat16 residual replacement, and the
+    multigrid V-cycle.  Several minutes of GPU time."""
     import torch
     import synth
     from paper_2506_20994_amd.box import BoxOperator
     from paper_2506_20994_amd import learned as LR
-    lp = P.sem_lp_create(ctx, n ** 3)
-    LR.init_network(lp, 7, mu=1.0, jacobi_base=True, out_scale=0.0, linear=True)
-    t0 = time.perf_counter()
-    X, T, _ = LR.generate(ctx, lp, n=16, boxes=128, snapshots=1, elems_per_snapshot=4096,
-                          rhs="noise", include_zero=True)
-    LR.train(lp, X, T, epochs=60, batch=1024, lr=3e-4)
-    del X, T
-    torch.cuda.empty_cache()
-    res = {"workload": f"{n}^3 box amplitude {amp}, h1=1, 32 Fourier modes, tol {tol}",
-           "training_s": round(time.perf_counter() - t0, 1)}
+    res = {"workload": f"{n}^3 box amplitude {amp}, h1=1, 32 Fourier modes, tol {tol}"}
     for lx in (8, 10):
+        lp = P.sem_lp_create(ctx, n ** 3, lx=lx)
+        LR.init_network(lp, 7, mu=1.0, jacobi_base=True, out_scale=0.0, linear=True)
+        t0 = time.perf_counter()
+        X, T, _ = LR.generate(ctx, lp, n=16, boxes=128 if lx == 8 else 64, snapshots=1,
+                              elems_per_snapshot=4096, rhs="noise", include_zero=True)
+        LR.train(lp, X, T, epochs=60, batch=1024, lr=3e-4)
+        del X, T
+        torch.cuda.empty_cache()
+        res[f"training_s_lx{lx}"] = round(time.perf_counter() - t0, 1)
+        print(f"[bench] scale lx={lx}: network trained in {res[f'training_s_lx{lx}']} s", file=sys.stderr,
+              flush=True)
         op = BoxOperator(ctx, n, lx, amp)
         r = {"n_local": op.n_local}
         u = op.scatter(synth.unique_normal(op.n_unique, 0))
@@ -650,10 +653,9 @@ def scale_run(ctx, P, n=64, amp=0.15, tol=1e-10):
         b = op.fourier_rhs(k, a, ph)
         x = torch.empty_like(b)
         variants = [("fp64_pcg", P.SEM_SOLVE_F64, 0, None), ("f32_rr", P.SEM_SOLVE_F32_IR, 1, None)]
-        if lx == 8:
-            op.bind(lp)
-            variants += [("learned_f32_rr", P.SEM_SOLVE_F32_IR, 1, lp),
-                         ("learned_bf16_rr", P.SEM_SOLVE_BF16_IR, 1, lp)]
+        op.bind(lp)
+        variants += [("learned_f32_rr", P.SEM_SOLVE_F32_IR, 1, lp),
+                     ("learned_bf16_rr", P.SEM_SOLVE_BF16_IR, 1, lp)]
         mg = op.multigrid(**MG_OPTS)
         variants += [("mg_f32_rr", P.SEM_SOLVE_F32_IR, 1, "mg"), ("mg_fcg_f64", P.SEM_SOLVE_F64, 0, "mg")]
         for name, code, mode, L in variants:
@@ -674,9 +676,9 @@ def scale_run(ctx, P, n=64, amp=0.15, tol=1e-10):
         mg.close()
         res[f"lx{lx}"] = r
         op.gs.close()
+        lp.close()
         del op, b, x
         torch.cuda.empty_cache()
-    lp.close()
     return res
 
 

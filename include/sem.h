@@ -440,25 +440,36 @@ int sem_mg_apply(sem_mg_t mg, void* z, const void* r, sem_dtype_t dtype);
 
 /* --------------------------------------------- learned preconditioner */
 
-/* A per-element network for lx = 8 elements: inputs are the element's
- * residual r_e / s_e (512 values, s_e = ||r_e||_2) and six geometric features
+/* A per-element network for elements of n = lx^3 nodes (lx even, 4..12; the
+ * workload's network is lx = 8, n = 512): inputs are the element's residual
+ * r_e / s_e (n values, s_e = ||r_e||_2) and six geometric features
  * mean(h1 g_ab) / kappa_e (kappa_e = mean(h1 (g11 + g22 + g33)) / 3); layers
- * Linear(518, 256)-ReLU-Linear(256, 256)-ReLU-Linear(256, 512).  Applied as
+ * Linear(n + 6, 256)-ReLU-Linear(256, 256)-ReLU-Linear(256, n).  Applied as
  *   z = Q Q^T (mult^-1 (s_e / kappa_e) NN(x_e)).
  * Training minimises the mean squared error against t_e = err_e kappa_e / s_e
  * with Adam.  Products run on bf16 MFMA with float32 accumulation; weights,
  * moments, loss and bias gradients are float32.
- * Parameter slots for sem_lp_set/get: 0 W1 (256 x 518, row-major, out x in),
- * 1 b1 (256), 2 W2 (256 x 256), 3 b2, 4 W3 (512 x 256), 5 b3 (512); add 6 for
- * Adam's first moments, 12 for the second moments, 18 for the gradients. */
+ * Parameter slots for sem_lp_set/get: 0 W1 (256 x (n + 6), row-major, out x
+ * in), 1 b1 (256), 2 W2 (256 x 256), 3 b2, 4 W3 (n x 256), 5 b3 (n); add 6 for
+ * Adam's first moments, 12 for the second moments, 18 for the gradients.
+ * Feature rows (sem_lp_samples, sem_lp_forward, sem_lp_gradients) are n + 6
+ * values zero padded to a multiple of 16 (528 at lx = 8); target and output
+ * rows are n wide.  The sizes below are those of lx = 8. */
 #define SEM_LP_IN 518
 #define SEM_LP_IN_PAD 528      /* row width of feature matrices (zero padded) */
 #define SEM_LP_HIDDEN 256
 #define SEM_LP_OUT 512
 
-/* Allocate a network with zero weights and workspace for up to max_rows rows
- * (elements per inference, or batch rows per training step). */
+/* Allocate a network for lx = 8 elements with zero weights and workspace for
+ * up to max_rows rows (elements per inference, or batch rows per training
+ * step). */
 int sem_lp_create(sem_ctx_t ctx, int64_t max_rows, sem_lp_t* lp);
+/* The same for elements of lx^3 nodes, lx even in [4, 12] (SEM_EUNSUPPORTED_LX
+ * otherwise).  At lx = 8 the linear form's product runs in a weight-stationary
+ * kernel written for 512 x 512 blocks; at other lx in the general MFMA product. */
+int sem_lp_create_lx(sem_ctx_t ctx, int lx, int64_t max_rows, sem_lp_t* lp);
+/* The element size lx the network was created for. */
+int sem_lp_lx(sem_lp_t lp, int* lx);
 int sem_lp_destroy(sem_lp_t lp);
 /* Copy `count` float32 values (host) into / out of slot `which`; count must
  * equal the slot's size.  Synchronous. */
@@ -487,7 +498,7 @@ int sem_lp_load(sem_lp_t lp, const char* path);
 int sem_lp_set_metric(sem_lp_t lp, double mu);
 /* Linear form (on != 0): identity activations, biases unused (their
  * gradients are zero), geometric inputs zeroed.  The network output is then
- * W x with W = W3 W2 W1 (the first 512 input columns), and inference applies
+ * W x with W = W3 W2 W1 (the first n input columns), and inference applies
  * the symmetric additive preconditioner
  *     z = sum_e Q_e S_e W_s S_e Q_e^T r / kappa_e  (+ Minv r with the Jacobi base),
  * W_s = (W + W^T) / 2 held in bfloat16, S_e = diag(mult^-1/2) on the element's
@@ -497,8 +508,8 @@ int sem_lp_set_metric(sem_lp_t lp, double mu);
  * the element block of the inverse operator.  Applies to training and
  * inference from the next call on. */
 int sem_lp_set_linear(sem_lp_t lp, int on);
-/* Set the linear form's 512 x 512 element block directly (host float32,
- * row-major, count = 512 * 512) instead of folding it from the weights: the
+/* Set the linear form's n x n element block directly (host float32,
+ * row-major, count = n * n) instead of folding it from the weights: the
  * preconditioner becomes z = sum_e Q_e S_e W_s S_e Q_e^T r / kappa_e (+ Minv r
  * with the Jacobi base), W_s the symmetric part of W, applied by the same
  * kernels.  For classical (non-learned) element blocks used as a comparison.
@@ -512,15 +523,15 @@ int sem_lp_set_block(sem_lp_t lp, const float* W, int64_t count);
  * correction to Jacobi (a network that outputs zero is exactly Jacobi).
  * Takes effect at the next sem_lp_bind. */
 int sem_lp_set_jacobi_base(sem_lp_t lp, int on);
-/* Bind to an operator (lx = 8, nel <= max_rows) and its plan: computes the
+/* Bind to an operator (the network's lx, nel <= max_rows) and its plan: computes the
  * per-element geometric features and keeps the operator's arrays for
  * sem_lp_snapshot (they must stay valid while bound).  Needed by sem_lp_samples / sem_lp_apply.
  * Only the stiffness is read (A->h2b is ignored): with a Helmholtz solve the
  * Jacobi base uses the stiffness diagonal. */
 int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs);
 /* Training rows for `count` elements elems[] (device int64) of the bound
- * operator: X[row0 + q] = inputs (bf16, SEM_LP_IN_PAD wide) from the residual
- * r, and, if T != NULL, T[row0 + q] = err_e kappa_e / s_e (float32, 512 wide)
+ * operator: X[row0 + q] = inputs (bf16, the padded feature width) from the residual
+ * r, and, if T != NULL, T[row0 + q] = err_e kappa_e / s_e (float32, n wide)
  * from the error err.  r, err: device float64 fields of the bound operator. */
 int sem_lp_samples(sem_lp_t lp, const double* r, const double* err, const int64_t* elems,
                    int64_t count, uint16_t* X, float* T, int64_t row0);
@@ -543,10 +554,10 @@ int sem_lp_snapshot(sem_lp_t lp, const double* x, const double* xstar, const dou
  * vectors; the (lx^3)^2 matrix is symmetrised and inverted by Cholesky on the
  * host.  W: host float64, (lx^3)^2, row-major.  Allocates and frees
  * temporary device memory; synchronous.  Pass it (rounded to float32) to
- * sem_lp_set_block for lx = 8. */
+ * sem_lp_set_block of a network of the same lx. */
 int sem_lp_reference_block(sem_ctx_t ctx, int lx, double* W);
-/* Y = NN(X) for `rows` rows (X device bf16 rows x SEM_LP_IN_PAD, Y device
- * float32 rows x 512). */
+/* Y = NN(X) for `rows` rows (X device bf16 rows x the padded feature width, Y device
+ * float32 rows x n). */
 int sem_lp_forward(sem_lp_t lp, const uint16_t* X, int64_t rows, float* Y);
 /* Gradients of the batch MSE into the gradient slots; *loss (host) receives
  * the loss.  X, T device, B rows (B % 8 == 0). */
@@ -559,7 +570,7 @@ int sem_lp_adam(sem_lp_t lp, double lr, double beta1, double beta2, double eps);
 int sem_lp_train_step(sem_lp_t lp, const uint16_t* X, const float* T, const int64_t* rows,
                       int64_t B, double lr, float* loss);
 /* z = P(r) on the bound operator; dtype SEM_F64 or SEM_F32 for both.
- * z and r are continuous fields in the local layout (nel * 512 values). */
+ * z and r are continuous fields in the local layout (nel * n values). */
 int sem_lp_apply(sem_lp_t lp, void* z, const void* r, sem_dtype_t dtype);
 /* The same on unique-node vectors of the bound plan (sem_gs_info's n_unique
  * values, the layout sem_cg_solve iterates in): unique nodes are numbered in

@@ -16,15 +16,28 @@ __all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONV
            "CgSolver", "SEM_SOLVE_F64", "SEM_SOLVE_F32_IR", "SEM_SOLVE_BF16_IR",
            "LearnedPrecond", "sem_lp_create", "sem_lp_destroy", "sem_lp_set", "sem_lp_get",
            "sem_lp_set_step", "sem_lp_get_step", "sem_lp_bind", "sem_lp_samples", "sem_lp_forward",
-           "sem_lp_gradients", "sem_lp_adam", "sem_lp_set_metric", "sem_lp_set_jacobi_base", "sem_lp_set_linear", "sem_lp_train_step", "sem_lp_apply", "sem_lp_apply_unique", "sem_lp_save", "sem_lp_load", "sem_lp_set_block", "LP_SLOTS",
+           "sem_lp_gradients", "sem_lp_adam", "sem_lp_set_metric", "sem_lp_set_jacobi_base", "sem_lp_set_linear", "sem_lp_train_step", "sem_lp_apply", "sem_lp_apply_unique", "sem_lp_save", "sem_lp_load", "sem_lp_set_block", "LP_SLOTS", "lp_slots", "lp_sizes", "sem_lp_lx",
            "SEM_LP_IN", "SEM_LP_IN_PAD", "SEM_LP_HIDDEN", "SEM_LP_OUT", "SemMgOpts", "Multigrid",
            "sem_mg_create", "sem_mg_destroy", "sem_mg_levels", "sem_mg_level_info", "sem_mg_set_lmax",
            "sem_mg_apply", "sem_mg_set_graphs", "sem_ax_set_variant", "sem_ax_get_variant", "sem_ax_tune", "sem_ax_tune_on",
            "SEM_AX_DEFAULT", "SEM_AX_COLUMN", "SEM_AX_COLUMN_PF", "SEM_AX_SLICE", "SEM_AX_3D", "SEM_AX_WAVE", "SEM_AX_VARIANTS", "sem_lp_snapshot", "sem_lp_reference_block"]
 
-SEM_LP_IN, SEM_LP_IN_PAD, SEM_LP_HIDDEN, SEM_LP_OUT = 518, 528, 256, 512
-# slot -> shape of the float32 array it holds (parameters; +6 m, +12 v, +18 grads)
-LP_SLOTS = [(256, 518), (256,), (256, 256), (256,), (512, 256), (512,)]
+SEM_LP_IN, SEM_LP_IN_PAD, SEM_LP_HIDDEN, SEM_LP_OUT = 518, 528, 256, 512      # lx = 8
+
+
+def lp_sizes(lx):
+    """(outputs n = lx^3, inputs n + 6, padded feature width) of a network for lx"""
+    n = lx ** 3
+    return n, n + 6, (n + 6 + 15) // 16 * 16
+
+
+def lp_slots(lx=8):
+    """slot -> shape of the float32 array it holds (parameters; +6 m, +12 v, +18 grads)"""
+    n, ni, _ = lp_sizes(lx)
+    return [(256, ni), (256,), (256, 256), (256,), (n, 256), (n,)]
+
+
+LP_SLOTS = lp_slots(8)
 
 SEM_SOLVE_F64, SEM_SOLVE_F32_IR, SEM_SOLVE_BF16_IR = 0, 1, 2
 SEM_AX_DEFAULT, SEM_AX_COLUMN, SEM_AX_COLUMN_PF, SEM_AX_SLICE, SEM_AX_3D, SEM_AX_WAVE = -1, 0, 1, 2, 3, 4
@@ -109,6 +122,8 @@ EXPORTS = {
     "sem_cg_destroy": (_int, [_vp]),
     "sem_cg_solve": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "sem_lp_create": (_int, [_vp, _i64, ctypes.POINTER(_vp)]),
+    "sem_lp_create_lx": (_int, [_vp, _int, _i64, ctypes.POINTER(_vp)]),
+    "sem_lp_lx": (_int, [_vp, ctypes.POINTER(_int)]),
     "sem_lp_destroy": (_int, [_vp]),
     "sem_lp_set": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_float), _i64]),
     "sem_lp_get": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_float), _i64]),
@@ -443,8 +458,9 @@ def sem_cg_solve(cg, x, b, **opts):
 
 
 class LearnedPrecond:
-    def __init__(self, ctx, handle, max_rows):
-        self.ctx, self.handle, self.max_rows = ctx, handle, max_rows
+    def __init__(self, ctx, handle, max_rows, lx=8):
+        self.ctx, self.handle, self.max_rows, self.lx = ctx, handle, max_rows, lx
+        self.n_out, self.n_in, self.n_in_pad = lp_sizes(lx)
         self._bound = None
         ctx.adopt(self)
 
@@ -460,11 +476,18 @@ class LearnedPrecond:
             pass
 
 
-def sem_lp_create(ctx, max_rows):
+def sem_lp_create(ctx, max_rows, lx=8):
+    """A network for elements of lx^3 nodes (sem_lp_create_lx)."""
     out = _vp()
     h = ctx.bind()
-    _check(lib().sem_lp_create(h, int(max_rows), ctypes.byref(out)), h)
-    return LearnedPrecond(ctx, out, max_rows)
+    _check(lib().sem_lp_create_lx(h, int(lx), int(max_rows), ctypes.byref(out)), h)
+    return LearnedPrecond(ctx, out, max_rows, lx)
+
+
+def sem_lp_lx(lp):
+    v = _int(0)
+    _check(lib().sem_lp_lx(lp.handle, ctypes.byref(v)), lp.ctx.handle)
+    return v.value
 
 
 def sem_lp_destroy(lp):
@@ -480,7 +503,7 @@ def sem_lp_set(lp, which, values):
 
 def sem_lp_get(lp, which):
     import numpy as np
-    shape = LP_SLOTS[which % 6]
+    shape = lp_slots(lp.lx)[which % 6]
     a = np.empty(shape, dtype=np.float32)
     _check(lib().sem_lp_get(lp.handle, which, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                             a.size), lp.ctx.handle)

@@ -1,6 +1,6 @@
-// Learned per-element preconditioner: a 518-256-256-512 MLP applied to each
-// lx = 8 element's normalised residual plus six geometric features, trained on
-// the GPU with Adam.  The dense contractions run on bf16 MFMA
+// Learned per-element preconditioner: an (n + 6)-256-256-n MLP, n = lx^3 (518-256-
+// 256-512 at lx = 8), applied to each element's normalised residual plus six
+// geometric features, trained on the GPU with Adam.  The dense contractions run on bf16 MFMA
 // (v_mfma_f32_16x16x32_bf16) with float32 accumulation; master weights, Adam
 // moments, the loss and the bias gradients are float32.
 //
@@ -19,6 +19,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16;
 
+// the lx = 8 sizes (the weight-stationary linear product is written for them);
+// a network's own sizes are lx^3 outputs, lx^3 + 6 inputs padded to 16
 constexpr int kIn = 518, kInPad = 528, kHid = 256, kOut = 512;
 constexpr int kBlock = 256;
 
@@ -34,6 +36,8 @@ enum { EPI_BIAS = 1, EPI_RELU = 2, EPI_MASK = 4 };
 constexpr int BM = 128, BN = 128, BK = 64, LDK = BK + 8;
 
 // C = A . B^T (+bias[n]) (relu) (*(mask[m][n] > 0)); Cf float and/or Cb bf16.
+// With pos, the float output of (m, n) goes to Cf[pos[m * ldc + n]], scaled by
+// rowscale[m].
 // Requires K % 8 == 0, lda % 8 == 0, ldb % 8 == 0 and 16-byte aligned bases.
 // 128 x 128 tile per 256-thread workgroup, each wave 64 x 64 as 4 x 4
 // 16x16x32 MFMA blocks; the next 64-wide k-slab is fetched into registers
@@ -41,7 +45,8 @@ constexpr int BM = 128, BN = 128, BK = 64, LDK = BK + 8;
 __global__ void __launch_bounds__(256)
 gemm_nt(int M, int N, int K, const u16* __restrict__ A, int lda, const u16* __restrict__ B, int ldb,
         const float* __restrict__ bias, const u16* __restrict__ mask, int ldm,
-        float* __restrict__ Cf, u16* __restrict__ Cb, int ldc, int epi, const int* __restrict__ skip) {
+        float* __restrict__ Cf, u16* __restrict__ Cb, int ldc, int epi, const int* __restrict__ skip,
+        const float* __restrict__ rowscale, const int32_t* __restrict__ pos) {
     if (skip && *skip) return;
     __shared__ __attribute__((aligned(16))) u16 sA[BM * LDK];
     __shared__ __attribute__((aligned(16))) u16 sB[BN * LDK];
@@ -114,7 +119,8 @@ gemm_nt(int M, int N, int K, const u16* __restrict__ A, int lda, const u16* __re
                 float v = acc[i][j][q] + bv;
                 if (epi & EPI_RELU) v = fmaxf(v, 0.f);
                 if ((epi & EPI_MASK) && !(bf16_f(mask[(int64_t)m * ldm + n]) > 0.f)) v = 0.f;
-                if (Cf) Cf[(int64_t)m * ldc + n] = v;
+                if (pos) Cf[pos[(int64_t)m * ldc + n]] = v * rowscale[m];
+                else if (Cf) Cf[(int64_t)m * ldc + n] = v;
                 if (Cb) Cb[(int64_t)m * ldc + n] = bf16_rne(v);
             }
         }
@@ -175,14 +181,14 @@ __global__ void weights_to_bf16(u16* __restrict__ out, int ldo, u16* __restrict_
     }
 }
 
-// batch gather: Xb[i] = X[rows[i]] (bf16, kInPad wide), Tb[i] = T[rows[i]] (float, kOut)
+// batch gather: Xb[i] = X[rows[i]] (bf16, nip wide), Tb[i] = T[rows[i]] (float, no)
 __global__ void gather_rows(u16* __restrict__ Xb, float* __restrict__ Tb, const u16* __restrict__ X,
-                            const float* __restrict__ T, const int64_t* __restrict__ rows, int B) {
+                            const float* __restrict__ T, const int64_t* __restrict__ rows, int B, int nip, int no) {
     const int i = blockIdx.x;
     if (i >= B) return;
     const int64_t r = rows[i];
-    for (int c = threadIdx.x; c < kInPad; c += blockDim.x) Xb[(int64_t)i * kInPad + c] = X[r * kInPad + c];
-    for (int c = threadIdx.x; c < kOut; c += blockDim.x) Tb[(int64_t)i * kOut + c] = T[r * kOut + c];
+    for (int c = threadIdx.x; c < nip; c += blockDim.x) Xb[(int64_t)i * nip + c] = X[r * nip + c];
+    for (int c = threadIdx.x; c < no; c += blockDim.x) Tb[(int64_t)i * no + c] = T[r * no + c];
 }
 
 // d3 = 2 (Y3 - T) / (B * kOut) as float and bf16; per-block partial of sum (Y3 - T)^2
@@ -305,50 +311,52 @@ __global__ void geo_kernel(float* __restrict__ geo, float* __restrict__ kappa, f
                            const double* __restrict__ h1, const double* __restrict__ g11,
                            const double* __restrict__ g22, const double* __restrict__ g33,
                            const double* __restrict__ g12, const double* __restrict__ g13,
-                           const double* __restrict__ g23, int64_t nel) {
+                           const double* __restrict__ g23, int64_t nel, int no) {
     const int64_t e = blockIdx.x;
     if (e >= nel) return;
     const double* G[6] = {g11, g22, g33, g12, g13, g23};
     double s[6] = {0, 0, 0, 0, 0, 0};
-    for (int q = threadIdx.x; q < kOut; q += 64) {
-        const int64_t L = e * kOut + q;
+    for (int q = threadIdx.x; q < no; q += 64) {
+        const int64_t L = e * no + q;
         const double h = h1 ? h1[L] : 1.0;
         for (int a = 0; a < 6; ++a) s[a] += h * G[a][L];
     }
     for (int a = 0; a < 6; ++a) s[a] = sem::wave_sum(s[a]);
     if (threadIdx.x == 0) {
-        const double kap = (s[0] + s[1] + s[2]) / (3.0 * kOut);
+        const double kap = (s[0] + s[1] + s[2]) / (3.0 * no);
         kappa[e] = (float)kap;
         kappa_inv[e] = (float)(1.0 / kap);
-        for (int a = 0; a < 6; ++a) geo[e * 6 + a] = (float)(s[a] / kOut / kap);
+        for (int a = 0; a < 6; ++a) geo[e * 6 + a] = (float)(s[a] / no / kap);
     }
 }
 
-// X[row] = [bf16(r_e / s_e) (512), geo (6), 0 (10)]; scale[row] = s_e / kappa_e;
+// X[row] = [bf16(r_e / s_e) (no), geo (6), 0 (to nip)]; scale[row] = s_e / kappa_e;
 // optionally T[row] = err_e * kappa_e / s_e.  With uoff (unique layout) or mult
 // (local layout) the residual is first weighted by S = mult^-1/2 (the linear
-// form's symmetric apply).  One wave per element.
-template <typename T>
+// form's symmetric apply).  One wave per element, NC = ceil(no / 64) nodes per lane.
+template <typename T, int NC>
 __global__ void features_kernel(u16* __restrict__ X, float* __restrict__ scale, float* __restrict__ Tt,
                                 const T* __restrict__ r, const double* __restrict__ err,
                                 const double* __restrict__ minv,
                                 const float* __restrict__ geo, const float* __restrict__ kappa,
                                 const int64_t* __restrict__ elems, int64_t count, int64_t row0,
                                 const int* __restrict__ skip, const int32_t* __restrict__ lid,
-                                const int32_t* __restrict__ uoff, const double* __restrict__ mult) {
+                                const int32_t* __restrict__ uoff, const double* __restrict__ mult,
+                                int no, int nip) {
     if (skip && *skip) return;
     const int64_t q = blockIdx.x;
     if (q >= count) return;
     const int64_t e = elems ? elems[q] : q;
     const int64_t row = row0 + q;
     const int lane = threadIdx.x;
-    double v[8];
+    double v[NC];
     double ss = 0.0;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int64_t L = e * kOut + c * 64 + lane;
-        const int64_t u = lid ? (int64_t)lid[L] : L;
-        if (u < 0) v[c] = 0.0;                                         // Dirichlet node
+    for (int c = 0; c < NC; ++c) {
+        const int n = c * 64 + lane;
+        const int64_t L = e * no + n;
+        const int64_t u = n >= no ? -1 : lid ? (int64_t)lid[L] : L;
+        if (u < 0) v[c] = 0.0;                                         // Dirichlet node (or past no)
         else if (uoff) v[c] = (double)r[u] * rsqrt((double)(uoff[u + 1] - uoff[u]));  // S = mult^-1/2
         else if (mult) v[c] = (double)r[u] * rsqrt(mult[L]);
         else v[c] = (double)r[u];
@@ -358,16 +366,19 @@ __global__ void features_kernel(u16* __restrict__ X, float* __restrict__ scale, 
     const double s = sqrt(ss) + 1e-30;
     const double kap = (double)kappa[e];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) X[row * kInPad + c * 64 + lane] = bf16_rne((float)(v[c] / s));
-    if (lane < kInPad - kOut)
-        X[row * kInPad + kOut + lane] = (lane < 6 && geo) ? bf16_rne(geo[e * 6 + lane]) : (u16)0;
+    for (int c = 0; c < NC; ++c)
+        if (c * 64 + lane < no) X[row * nip + c * 64 + lane] = bf16_rne((float)(v[c] / s));
+    if (lane < nip - no)
+        X[row * nip + no + lane] = (lane < 6 && geo) ? bf16_rne(geo[e * 6 + lane]) : (u16)0;
     if (lane == 0 && scale) scale[row] = (float)(s / kap);
     if (Tt) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int64_t L = e * kOut + c * 64 + lane;
+        for (int c = 0; c < NC; ++c) {
+            const int n = c * 64 + lane;
+            if (n >= no) continue;
+            const int64_t L = e * no + n;
             const double ev = minv ? err[L] - minv[L] * v[c] : err[L];   // Jacobi base removed
-            Tt[row * kOut + c * 64 + lane] = (float)(ev * kap / s);
+            Tt[row * no + n] = (float)(ev * kap / s);
         }
     }
 }
@@ -378,11 +389,11 @@ template <typename T>
 __global__ void lp_output_kernel(T* __restrict__ z, const float* __restrict__ Y3,
                                  const float* __restrict__ scale, const double* __restrict__ mult,
                                  const double* __restrict__ minv, const T* __restrict__ r,
-                                 int64_t n, const int* __restrict__ skip, bool sym) {
+                                 int64_t n, const int* __restrict__ skip, bool sym, int no) {
     if (skip && *skip) return;
     for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < n;
          L += (int64_t)gridDim.x * blockDim.x) {
-        double v = (double)scale[L / kOut] * (double)Y3[L];
+        double v = (double)scale[L / no] * (double)Y3[L];
         if (sym) {     // S y + Minv r / mult; the gather-scatter sums the copies
             v *= rsqrt(mult[L]);
             if (minv) v += minv[L] * (double)r[L] / mult[L];
@@ -401,7 +412,7 @@ __global__ void lp_output_unique_kernel(T* __restrict__ z, const float* __restri
                                         const float* __restrict__ scale, const double* __restrict__ minv,
                                         const T* __restrict__ r, const int32_t* __restrict__ uoff,
                                         const int32_t* __restrict__ uidx, int64_t nu,
-                                        const int* __restrict__ skip, bool sym) {
+                                        const int* __restrict__ skip, bool sym, int no) {
     if (skip && *skip) return;
     for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < nu;
          u += (int64_t)gridDim.x * blockDim.x) {
@@ -409,7 +420,7 @@ __global__ void lp_output_unique_kernel(T* __restrict__ z, const float* __restri
         double s = 0.0;
         for (int32_t q = b; q < e; ++q) {
             const int32_t L = uidx[q];
-            s += (double)scale[L / kOut] * (double)Y3[L];
+            s += (double)scale[L / no] * (double)Y3[L];
         }
         s *= sym ? rsqrt((double)(e - b)) : 1.0 / (double)(e - b);
         if (minv) s += minv[uidx[b]] * (double)r[u];
@@ -452,7 +463,8 @@ __device__ __forceinline__ float ld_free(const T* __restrict__ r, int32_t u) {
 // gathered array.
 template <typename T>
 __global__ void lin_gather_kernel(u16* __restrict__ X, const T* __restrict__ r, const float* __restrict__ sl,
-                                  const int32_t* __restrict__ lid, int64_t n8, const int* __restrict__ skip) {
+                                  const int32_t* __restrict__ lid, int64_t n8, const int* __restrict__ skip,
+                                  int no, int nip) {
     if (skip && *skip) return;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n8;
          t += (int64_t)gridDim.x * blockDim.x) {
@@ -470,7 +482,7 @@ __global__ void lin_gather_kernel(u16* __restrict__ X, const T* __restrict__ r, 
         v[5] = ld_free(r, i1.y) * s1.y;
         v[6] = ld_free(r, i1.z) * s1.z;
         v[7] = ld_free(r, i1.w) * s1.w;
-        *reinterpret_cast<bf16x8*>(X + (L / kOut) * kInPad + (L % kOut)) = pack_bf16x8(v);
+        *reinterpret_cast<bf16x8*>(X + (L / no) * nip + (L % no)) = pack_bf16x8(v);
     }
 }
 
@@ -665,11 +677,13 @@ __global__ void unit_id_kernel(double* __restrict__ u, const int64_t* __restrict
 struct sem_lp_s {
     sem_ctx_t ctx = nullptr;
     int64_t max_rows = 0;
-    // float32 masters, Adam moments, gradients (W1 gradient is 256 x 528)
+    // element size: lx, no = lx^3 outputs, ni = no + 6 inputs, nip = ni padded to 16
+    int lx = 8, no = kOut, ni = kIn, nip = kInPad;
+    // float32 masters, Adam moments, gradients (W1 gradient is 256 x nip)
     float *W[3] = {}, *b[3] = {}, *mW[3] = {}, *mb[3] = {}, *vW[3] = {}, *vb[3] = {};
     float *gW[3] = {}, *gb[3] = {};
     int64_t step = 0;
-    // bf16 copies: W1 (256 x 528), W2 (256 x 256), W3 (512 x 256), W2^T, W3^T
+    // bf16 copies: W1 (256 x nip), W2 (256 x 256), W3 (no x 256), W2^T, W3^T
     u16 *W1b = nullptr, *W2b = nullptr, *W3b = nullptr, *W2t = nullptr, *W3t = nullptr;
     double mu = -1.0;         // training metric (< 0: mean squared error)
     bool dirty = true;        // bf16 copies of the weights out of date
@@ -678,7 +692,7 @@ struct sem_lp_s {
     // activations / work for up to max_rows rows
     u16 *X = nullptr, *Y1 = nullptr, *Y2 = nullptr, *d3b = nullptr, *d2b = nullptr, *d1b = nullptr;
     float *Y3 = nullptr, *T = nullptr, *d3f = nullptr, *d2f = nullptr, *d1f = nullptr, *scale = nullptr;
-    u16 *tA = nullptr, *tB = nullptr;   // transposes (kInPad x max_rows each)
+    u16 *tA = nullptr, *tB = nullptr;   // transposes (nip x max_rows each)
     double* part = nullptr;
     float* loss = nullptr;
     // bound operator (inference)
@@ -688,12 +702,12 @@ struct sem_lp_s {
     sem_gs_t gs = nullptr;
     sem::AxArgs A64{};        // the bound operator (float64 arrays of the caller)
     const int* skip = nullptr;   // set by the solver: kernels return when *skip != 0
-    // energy-norm loss: metric K (512 x 512, bf16) and work arrays
+    // energy-norm loss: metric K (no x no, bf16) and work arrays
     u16* K = nullptr;
     float *dF = nullptr, *Kd = nullptr;
     u16* dB = nullptr;
     // linear form: identity activations, no biases, geometric inputs zeroed;
-    // inference then uses the folded matrix (W3 W2 W1)[:, :512] (bf16)
+    // inference then uses the folded matrix (W3 W2 W1)[:, :no] (bf16)
     bool linear = false;
     float *T32 = nullptr, *Wf32 = nullptr;
     u16* Wfb = nullptr;
@@ -710,8 +724,8 @@ struct sem_lp_s {
 
 namespace {
 
-constexpr int kParamRows[3] = {kHid, kHid, kOut};
-constexpr int kParamCols[3] = {kIn, kHid, kHid};
+int param_rows(const sem_lp_s* lp, int layer) { return layer == 2 ? lp->no : kHid; }
+int param_cols(const sem_lp_s* lp, int layer) { return layer == 0 ? lp->ni : kHid; }
 
 int lp_alloc(sem_lp_t lp, void** p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes);
@@ -722,11 +736,34 @@ int lp_alloc(sem_lp_t lp, void** p, size_t bytes) {
 }
 
 int gemm(sem_lp_t lp, int M, int N, int K, const u16* A, int lda, const u16* B, int ldb,
-         const float* bias, const u16* mask, int ldm, float* Cf, u16* Cb, int ldc, int epi) {
+         const float* bias, const u16* mask, int ldm, float* Cf, u16* Cb, int ldc, int epi,
+         const float* rowscale = nullptr, const int32_t* pos = nullptr) {
     if (M == 0 || N == 0) return SEM_OK;
     dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
     gemm_nt<<<grid, 256, 0, lp->ctx->stream>>>(M, N, K, A, lda, B, ldb, bias, mask, ldm, Cf, Cb, ldc, epi,
-                                               lp->skip);
+                                               lp->skip, rowscale, pos);
+    SEM_LAUNCH_CHECK(lp->ctx);
+    return SEM_OK;
+}
+
+// features_kernel for this network's element size (ceil(no / 64) nodes per lane)
+template <typename T>
+int launch_features(sem_lp_t lp, int64_t count, u16* X, float* scale, float* Tt, const T* r, const double* err,
+                    const double* minv, const float* geo, const int64_t* elems, int64_t row0, const int* skip,
+                    const int32_t* lid, const int32_t* uoff, const double* mult) {
+    hipStream_t st = lp->ctx->stream;
+    const unsigned g = (unsigned)count;
+#define LP_FEAT(NC) features_kernel<T, NC><<<g, 64, 0, st>>>(X, scale, Tt, r, err, minv, geo, lp->kappa, elems, \
+                                                              count, row0, skip, lid, uoff, mult, lp->no, lp->nip)
+    switch ((lp->no + 63) / 64) {
+        case 1: LP_FEAT(1); break;
+        case 4: LP_FEAT(4); break;
+        case 8: LP_FEAT(8); break;
+        case 16: LP_FEAT(16); break;
+        case 27: LP_FEAT(27); break;
+        default: return sem::fail(lp->ctx, SEM_EUNSUPPORTED_LX, "sem_lp: element size %d", lp->no);
+    }
+#undef LP_FEAT
     SEM_LAUNCH_CHECK(lp->ctx);
     return SEM_OK;
 }
@@ -741,25 +778,26 @@ int transpose(sem_lp_t lp, u16* out, int ldo, const u16* in, int ldi, int rows, 
 int refresh_bf16(sem_lp_t lp) {
     if (!lp->dirty) return SEM_OK;
     hipStream_t st = lp->ctx->stream;
-    weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W1b, kInPad, nullptr, lp->W[0], kHid, kIn);
+    weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W1b, lp->nip, nullptr, lp->W[0], kHid, lp->ni);
     weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W2b, kHid, lp->W2t, lp->W[1], kHid, kHid);
-    weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W3b, kHid, lp->W3t, lp->W[2], kOut, kHid);
+    weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W3b, kHid, lp->W3t, lp->W[2], lp->no, kHid);
     SEM_LAUNCH_CHECK(lp->ctx);
     lp->dirty = false;
     return SEM_OK;
 }
 
-// symmetric part of the folded (W3 W2 W1)[:, :512] of the linear form, in bf16;
+// symmetric part of the folded (W3 W2 W1)[:, :no] of the linear form, in bf16;
 // needed by inference only, so training steps do not recompute it
 int refresh_fold(sem_lp_t lp) {
     int rc = refresh_bf16(lp);
     if (rc || !lp->fold_dirty || !lp->linear || !lp->Wfb) return rc;
     hipStream_t st = lp->ctx->stream;
-    matmul_f32<<<dim3((kHid + 255) / 256, kOut), 256, 0, st>>>(lp->T32, lp->W[2], lp->W[1], kOut, kHid,
-                                                               kHid, kHid, kHid, kHid);
-    matmul_f32<<<dim3((kOut + 255) / 256, kOut), 256, 0, st>>>(lp->Wf32, lp->T32, lp->W[0], kOut, kHid,
-                                                               kOut, kHid, kIn, kOut);
-    sym_to_bf16<<<256, kBlock, 0, st>>>(lp->Wfb, lp->Wf32, kOut);
+    const int no = lp->no;
+    matmul_f32<<<dim3((kHid + 255) / 256, no), 256, 0, st>>>(lp->T32, lp->W[2], lp->W[1], no, kHid,
+                                                             kHid, kHid, kHid, kHid);
+    matmul_f32<<<dim3((no + 255) / 256, no), 256, 0, st>>>(lp->Wf32, lp->T32, lp->W[0], no, kHid,
+                                                           no, kHid, lp->ni, no);
+    sym_to_bf16<<<256, kBlock, 0, st>>>(lp->Wfb, lp->Wf32, no);
     SEM_LAUNCH_CHECK(lp->ctx);
     lp->fold_dirty = false;
     return SEM_OK;
@@ -772,9 +810,9 @@ int forward(sem_lp_t lp, const u16* X, int64_t M) {
     if (M > 0x7fffffff) return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp: too many rows");
     const int m = (int)M;
     const int hid = lp->linear ? 0 : EPI_BIAS | EPI_RELU, out = lp->linear ? 0 : EPI_BIAS;
-    rc = gemm(lp, m, kHid, kInPad, X, kInPad, lp->W1b, kInPad, lp->b[0], nullptr, 0, nullptr, lp->Y1, kHid, hid);
+    rc = gemm(lp, m, kHid, lp->nip, X, lp->nip, lp->W1b, lp->nip, lp->b[0], nullptr, 0, nullptr, lp->Y1, kHid, hid);
     if (!rc) rc = gemm(lp, m, kHid, kHid, lp->Y1, kHid, lp->W2b, kHid, lp->b[1], nullptr, 0, nullptr, lp->Y2, kHid, hid);
-    if (!rc) rc = gemm(lp, m, kOut, kHid, lp->Y2, kHid, lp->W3b, kHid, lp->b[2], nullptr, 0, lp->Y3, nullptr, kOut, out);
+    if (!rc) rc = gemm(lp, m, lp->no, kHid, lp->Y2, kHid, lp->W3b, kHid, lp->b[2], nullptr, 0, lp->Y3, nullptr, lp->no, out);
     return rc;
 }
 
@@ -782,9 +820,9 @@ float** param_slot(sem_lp_t lp, int which, int64_t* count, int* ld) {
     // 0..5 params, 6..11 first moments, 12..17 second moments, 18..23 gradients
     const int kind = which / 6, idx = which % 6, layer = idx / 2;
     const bool isW = (idx % 2) == 0;
-    *count = isW ? (int64_t)kParamRows[layer] * kParamCols[layer] : kParamRows[layer];
-    *ld = isW ? kParamCols[layer] : 1;
-    if (kind == 3 && isW && layer == 0) *ld = kInPad;
+    *count = isW ? (int64_t)param_rows(lp, layer) * param_cols(lp, layer) : param_rows(lp, layer);
+    *ld = isW ? param_cols(lp, layer) : 1;
+    if (kind == 3 && isW && layer == 0) *ld = lp->nip;
     switch (kind) {
         case 0: return isW ? &lp->W[layer] : &lp->b[layer];
         case 1: return isW ? &lp->mW[layer] : &lp->mb[layer];
@@ -796,42 +834,60 @@ float** param_slot(sem_lp_t lp, int which, int64_t* count, int* ld) {
 
 }  // namespace
 
-extern "C" int sem_lp_create(sem_ctx_t ctx, int64_t max_rows, sem_lp_t* out) {
+extern "C" int sem_lp_create_lx(sem_ctx_t ctx, int lx, int64_t max_rows, sem_lp_t* out) {
     int rc = sem::enter(ctx);
     if (rc) return rc;
     if (!out) return sem::fail(ctx, SEM_EINVAL, "sem_lp_create: null output");
     *out = nullptr;
+    if (lx < 4 || lx > SEM_LX_MAX || lx % 2)
+        return sem::fail(ctx, SEM_EUNSUPPORTED_LX, "sem_lp_create: lx=%d (the network takes even lx in [4, %d])", lx,
+                         SEM_LX_MAX);
     if (max_rows < 1 || max_rows > (1ll << 26))
         return sem::fail(ctx, SEM_EINVAL, "sem_lp_create: max_rows=%lld outside [1, 2^26]", (long long)max_rows);
     auto* lp = new sem_lp_s();
     lp->ctx = ctx;
     lp->max_rows = max_rows;
+    lp->lx = lx;
+    lp->no = lx * lx * lx;
+    lp->ni = lp->no + 6;
+    lp->nip = (lp->ni + 15) / 16 * 16;
+    const int no = lp->no, nip = lp->nip;
     auto bail = [&](int code) { sem_lp_destroy(lp); return code; };
 #define LP_ALLOC(ptr, bytes) do { int rc_ = lp_alloc(lp, (void**)&(ptr), (bytes)); if (rc_) return bail(rc_); } while (0)
     for (int l = 0; l < 3; ++l) {
-        const size_t nw = (size_t)kParamRows[l] * kParamCols[l], nb = kParamRows[l];
+        const size_t nw = (size_t)param_rows(lp, l) * param_cols(lp, l), nb = param_rows(lp, l);
         LP_ALLOC(lp->W[l], 4 * nw); LP_ALLOC(lp->mW[l], 4 * nw); LP_ALLOC(lp->vW[l], 4 * nw);
         LP_ALLOC(lp->b[l], 4 * nb); LP_ALLOC(lp->mb[l], 4 * nb); LP_ALLOC(lp->vb[l], 4 * nb);
-        LP_ALLOC(lp->gW[l], 4 * (size_t)kParamRows[l] * (l == 0 ? kInPad : kParamCols[l]));
+        LP_ALLOC(lp->gW[l], 4 * (size_t)param_rows(lp, l) * (l == 0 ? nip : param_cols(lp, l)));
         LP_ALLOC(lp->gb[l], 4 * nb);
     }
-    LP_ALLOC(lp->W1b, 2 * (size_t)kHid * kInPad);
+    LP_ALLOC(lp->W1b, 2 * (size_t)kHid * nip);
     LP_ALLOC(lp->W2b, 2 * (size_t)kHid * kHid);
-    LP_ALLOC(lp->W3b, 2 * (size_t)kOut * kHid);
+    LP_ALLOC(lp->W3b, 2 * (size_t)no * kHid);
     LP_ALLOC(lp->W2t, 2 * (size_t)kHid * kHid);
-    LP_ALLOC(lp->W3t, 2 * (size_t)kHid * kOut);
+    LP_ALLOC(lp->W3t, 2 * (size_t)kHid * no);
     const size_t R = (size_t)max_rows;
-    LP_ALLOC(lp->X, 2 * R * kInPad);
+    LP_ALLOC(lp->X, 2 * R * nip);
     LP_ALLOC(lp->Y1, 2 * R * kHid);
     LP_ALLOC(lp->Y2, 2 * R * kHid);
-    LP_ALLOC(lp->Y3, 4 * R * kOut);
-    LP_ALLOC(lp->T, 4 * R * kOut);
+    LP_ALLOC(lp->Y3, 4 * R * no);
+    LP_ALLOC(lp->T, 4 * R * no);
     LP_ALLOC(lp->scale, 4 * R);
     LP_ALLOC(lp->part, 8 * 4096);
     LP_ALLOC(lp->loss, 4);
 #undef LP_ALLOC
     SEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     *out = lp;
+    return SEM_OK;
+}
+
+extern "C" int sem_lp_create(sem_ctx_t ctx, int64_t max_rows, sem_lp_t* out) {
+    return sem_lp_create_lx(ctx, 8, max_rows, out);
+}
+
+extern "C" int sem_lp_lx(sem_lp_t lp, int* lx) {
+    if (!lp || !lx) return sem::fail(lp ? lp->ctx : nullptr, SEM_EINVAL, "sem_lp_lx: null argument");
+    *lx = lp->lx;
     return SEM_OK;
 }
 
@@ -857,9 +913,10 @@ extern "C" int sem_lp_set(sem_lp_t lp, int which, const float* host, int64_t cou
     if (count != n) return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_set: slot %d holds %lld values, got %lld",
                                      which, (long long)n, (long long)count);
     SEM_HIP(lp->ctx, hipStreamSynchronize(lp->ctx->stream));
-    if (ld == kInPad) {   // W1 gradient: 256 x 518 values into a 256 x 528 array
+    if (which == 18) {   // W1 gradient: 256 x ni values into a 256 x nip array
         for (int r = 0; r < kHid; ++r)
-            SEM_HIP(lp->ctx, hipMemcpy(*slot + (size_t)r * kInPad, host + (size_t)r * kIn, 4 * kIn, hipMemcpyHostToDevice));
+            SEM_HIP(lp->ctx, hipMemcpy(*slot + (size_t)r * ld, host + (size_t)r * lp->ni, 4 * (size_t)lp->ni,
+                                       hipMemcpyHostToDevice));
     } else {
         SEM_HIP(lp->ctx, hipMemcpy(*slot, host, 4 * (size_t)n, hipMemcpyHostToDevice));
     }
@@ -878,9 +935,10 @@ extern "C" int sem_lp_get(sem_lp_t lp, int which, float* host, int64_t count) {
     if (count != n) return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_get: slot %d holds %lld values, got %lld",
                                      which, (long long)n, (long long)count);
     SEM_HIP(lp->ctx, hipStreamSynchronize(lp->ctx->stream));
-    if (ld == kInPad) {
+    if (which == 18) {
         for (int r = 0; r < kHid; ++r)
-            SEM_HIP(lp->ctx, hipMemcpy(host + (size_t)r * kIn, *slot + (size_t)r * kInPad, 4 * kIn, hipMemcpyDeviceToHost));
+            SEM_HIP(lp->ctx, hipMemcpy(host + (size_t)r * lp->ni, *slot + (size_t)r * ld, 4 * (size_t)lp->ni,
+                                       hipMemcpyDeviceToHost));
     } else {
         SEM_HIP(lp->ctx, hipMemcpy(host, *slot, 4 * (size_t)n, hipMemcpyDeviceToHost));
     }
@@ -909,15 +967,15 @@ extern "C" int sem_lp_set_metric(sem_lp_t lp, double mu) {
         lp->K = nullptr;
         return SEM_OK;
     }
-    constexpr int lx = 8;
-    double xi[lx], w[lx], D[lx * lx];   // D[m*lx + i] = l_i'(xi_m)
-    sem::gll_host(lx, xi, w, D);
-    double Kh[lx][lx];                  // 1-D stiffness sum_m w_m l_i'(xi_m) l_i''(xi_m)
+    const int lx = lp->lx, kOut = lp->no;
+    std::vector<double> xi(lx), w(lx), D((size_t)lx * lx);   // D[m*lx + i] = l_i'(xi_m)
+    sem::gll_host(lx, xi.data(), w.data(), D.data());
+    std::vector<double> Kh((size_t)lx * lx);   // 1-D stiffness sum_m w_m l_i'(xi_m) l_i''(xi_m)
     for (int i = 0; i < lx; ++i)
         for (int ip = 0; ip < lx; ++ip) {
             double s = 0.0;
             for (int m = 0; m < lx; ++m) s += w[m] * D[m * lx + i] * D[m * lx + ip];
-            Kh[i][ip] = s;
+            Kh[(size_t)i * lx + ip] = s;
         }
     double wsum = 0.0;
     for (int i = 0; i < lx; ++i) wsum += w[i];
@@ -928,9 +986,9 @@ extern "C" int sem_lp_set_metric(sem_lp_t lp, double mu) {
         for (int q = 0; q < kOut; ++q) {
             const int ip = q % lx, jp = (q / lx) % lx, kp = q / (lx * lx);
             double v = 0.0;
-            if (j == jp && k == kp) v += Kh[i][ip] * w[j] * w[k];
-            if (i == ip && k == kp) v += w[i] * Kh[j][jp] * w[k];
-            if (i == ip && j == jp) v += w[i] * w[j] * Kh[k][kp];
+            if (j == jp && k == kp) v += Kh[(size_t)i * lx + ip] * w[j] * w[k];
+            if (i == ip && k == kp) v += w[i] * Kh[(size_t)j * lx + jp] * w[k];
+            if (i == ip && j == jp) v += w[i] * w[j] * Kh[(size_t)k * lx + kp];
             v /= kappa;
             if (p == q) v += mu * w[i] * w[j] * w[k] / kappa;
             const float f = (float)v;
@@ -967,14 +1025,15 @@ extern "C" int sem_lp_set_linear(sem_lp_t lp, int on) {
     if (rc) return rc;
     lp->linear = on != 0;
     if (lp->linear && !lp->Wfb) {
+        const size_t no = (size_t)lp->no;
         void* p = nullptr;
-        rc = lp_alloc(lp, &p, 4 * (size_t)kOut * kHid);
+        rc = lp_alloc(lp, &p, 4 * no * kHid);
         if (rc) return rc;
         lp->T32 = (float*)p;
-        rc = lp_alloc(lp, &p, 4 * (size_t)kOut * kOut);
+        rc = lp_alloc(lp, &p, 4 * no * no);
         if (rc) return rc;
         lp->Wf32 = (float*)p;
-        rc = lp_alloc(lp, &p, 2 * (size_t)kOut * kOut);
+        rc = lp_alloc(lp, &p, 2 * no * no);
         if (rc) return rc;
         lp->Wfb = (u16*)p;
     }
@@ -995,11 +1054,12 @@ extern "C" int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs) {
     int rc = sem::enter(ctx);
     if (rc) return rc;
     if (!A || !gs) return sem::fail(ctx, SEM_EINVAL, "sem_lp_bind: null operator or plan");
-    if (A->lx != 8) return sem::fail(ctx, SEM_EUNSUPPORTED_LX, "sem_lp_bind: the network is built for lx = 8, got %d", A->lx);
+    if (A->lx != lp->lx)
+        return sem::fail(ctx, SEM_EUNSUPPORTED_LX, "sem_lp_bind: the network is built for lx = %d, got %d", lp->lx, A->lx);
     if (A->nel < 1 || A->nel > lp->max_rows)
         return sem::fail(ctx, SEM_EINVAL, "sem_lp_bind: nel=%lld outside [1, max_rows=%lld]",
                          (long long)A->nel, (long long)lp->max_rows);
-    if (gs->n_local != A->nel * kOut) return sem::fail(ctx, SEM_EINVAL, "sem_lp_bind: plan size mismatch");
+    if (gs->n_local != A->nel * lp->no) return sem::fail(ctx, SEM_EINVAL, "sem_lp_bind: plan size mismatch");
     if (!A->g11 || !A->g22 || !A->g33 || !A->g12 || !A->g13 || !A->g23)
         return sem::fail(ctx, SEM_EINVAL, "sem_lp_bind: null geometric factor");
     if (lp->geo_cap < A->nel) {
@@ -1028,7 +1088,7 @@ extern "C" int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs) {
     lp->A64.nel = A->nel;
     lp->A64.lx = A->lx;
     geo_kernel<<<(unsigned)A->nel, 64, 0, ctx->stream>>>(lp->geo, lp->kappa, lp->kappa_inv, A->h1, A->g11, A->g22, A->g33,
-                                                         A->g12, A->g13, A->g23, A->nel);
+                                                         A->g12, A->g13, A->g23, A->nel, lp->no);
     SEM_LAUNCH_CHECK(ctx);
     if (lp->sl_n < gs->n_local) {
         void* p = nullptr;
@@ -1040,7 +1100,7 @@ extern "C" int sem_lp_bind(sem_lp_t lp, const sem_operator_t* A, sem_gs_t gs) {
     sl_kernel<<<grid_of(gs->n_local), kBlock, 0, ctx->stream>>>(lp->sl, gs->lid, gs->uoff, gs->n_local);
     SEM_LAUNCH_CHECK(ctx);
     if (lp->jacobi_base) {
-        const int64_t n = A->nel * kOut;
+        const int64_t n = A->nel * lp->no;
         if (lp->minv_n < n) {
             void* p = nullptr;
             rc = lp_alloc(lp, &p, 8 * (size_t)n);
@@ -1079,13 +1139,8 @@ extern "C" int sem_lp_samples(sem_lp_t lp, const double* r, const double* err, c
     if (!r || !X || !elems || count < 0 || row0 < 0 || (T && !err))
         return sem::fail(ctx, SEM_EINVAL, "sem_lp_samples: bad argument");
     if (count == 0) return SEM_OK;
-    features_kernel<double><<<(unsigned)count, 64, 0, ctx->stream>>>(X, nullptr, T, r, err,
-                                                                      lp->jacobi_base ? lp->minv : nullptr,
-                                                                      lp->linear ? nullptr : lp->geo, lp->kappa,
-                                                                      elems, count, row0, nullptr, nullptr,
-                                                                      nullptr, nullptr);
-    SEM_LAUNCH_CHECK(ctx);
-    return SEM_OK;
+    return launch_features<double>(lp, count, X, nullptr, T, r, err, lp->jacobi_base ? lp->minv : nullptr,
+                                   lp->linear ? nullptr : lp->geo, elems, row0, nullptr, nullptr, nullptr, nullptr);
 }
 
 namespace {
@@ -1220,7 +1275,7 @@ extern "C" int sem_lp_forward(sem_lp_t lp, const uint16_t* X, int64_t rows, floa
     if (rows == 0) return SEM_OK;
     rc = forward(lp, X, rows);
     if (rc) return rc;
-    SEM_HIP(ctx, hipMemcpyAsync(Y, lp->Y3, 4 * (size_t)rows * kOut, hipMemcpyDeviceToDevice, ctx->stream));
+    SEM_HIP(ctx, hipMemcpyAsync(Y, lp->Y3, 4 * (size_t)rows * lp->no, hipMemcpyDeviceToDevice, ctx->stream));
     return SEM_OK;
 }
 
@@ -1237,6 +1292,7 @@ static int lp_backward(sem_lp_t lp, const uint16_t* Xb, const float* Tb, int B) 
     hipStream_t st = ctx->stream;
     int rc = forward(lp, Xb, B);
     if (rc) return rc;
+    const int kOut = lp->no, kInPad = lp->nip;     // this network's sizes
     const int64_t n3 = (int64_t)B * kOut;
     const unsigned g = grid_of(n3);
     if (lp->K) {
@@ -1252,7 +1308,7 @@ static int lp_backward(sem_lp_t lp, const uint16_t* Xb, const float* Tb, int B) 
     }
     SEM_LAUNCH_CHECK(ctx);
     // layer 3: gW3 = d3^T Y2, gb3 = colsum d3, d2 = (d3 W3) * (Y2 > 0)
-    rc = transpose(lp, lp->tA, B, lp->d3b, kOut, B, kOut);           // d3^T: 512 x B
+    rc = transpose(lp, lp->tA, B, lp->d3b, kOut, B, kOut);           // d3^T: no x B
     if (!rc) rc = transpose(lp, lp->tB, B, lp->Y2, kHid, B, kHid);   // Y2^T: 256 x B
     if (!rc) rc = gemm(lp, kOut, kHid, B, lp->tA, B, lp->tB, B, nullptr, nullptr, 0, lp->gW[2], nullptr, kHid, 0);
     const int mask = lp->linear ? 0 : EPI_MASK;
@@ -1281,6 +1337,7 @@ static int lp_backward(sem_lp_t lp, const uint16_t* Xb, const float* Tb, int B) 
 static int lp_train_buffers(sem_lp_t lp, int B) {
     if (lp->d3f) return SEM_OK;
     const size_t R = (size_t)lp->max_rows;
+    const size_t kOut = (size_t)lp->no, kInPad = (size_t)lp->nip;
     void* p = nullptr;
     int rc;
 #define LP_ALLOC2(ptr, bytes) do { rc = lp_alloc(lp, &p, (bytes)); if (rc) return rc; ptr = (decltype(ptr))p; } while (0)
@@ -1325,9 +1382,9 @@ extern "C" int sem_lp_adam(sem_lp_t lp, double lr, double beta1, double beta2, d
     const double c1 = 1.0 - std::pow(beta1, (double)lp->step);
     const double c2 = 1.0 - std::pow(beta2, (double)lp->step);
     for (int l = 0; l < 3; ++l) {
-        const int rows = kParamRows[l], cols = kParamCols[l];
+        const int rows = param_rows(lp, l), cols = param_cols(lp, l);
         adam_kernel<<<grid_of((int64_t)rows * cols), kBlock, 0, ctx->stream>>>(
-            lp->W[l], lp->mW[l], lp->vW[l], lp->gW[l], rows, cols, l == 0 ? kInPad : cols, (float)lr,
+            lp->W[l], lp->mW[l], lp->vW[l], lp->gW[l], rows, cols, l == 0 ? lp->nip : cols, (float)lr,
             (float)beta1, (float)(1.0 - beta1), (float)beta2, (float)(1.0 - beta2), (float)eps,
             (float)c1, (float)c2);
         adam_kernel<<<grid_of(rows), kBlock, 0, ctx->stream>>>(
@@ -1349,7 +1406,7 @@ extern "C" int sem_lp_train_step(sem_lp_t lp, const uint16_t* X, const float* T,
         return sem::fail(ctx, SEM_EINVAL, "sem_lp_train_step: bad batch (%lld)", (long long)B);
     rc = lp_train_buffers(lp, (int)B);
     if (rc) return rc;
-    gather_rows<<<(unsigned)B, 256, 0, ctx->stream>>>(lp->X, lp->T, X, T, rows, (int)B);
+    gather_rows<<<(unsigned)B, 256, 0, ctx->stream>>>(lp->X, lp->T, X, T, rows, (int)B, lp->nip, lp->no);
     SEM_LAUNCH_CHECK(ctx);
     rc = lp_backward(lp, lp->X, lp->T, (int)B);
     if (rc) return rc;
@@ -1370,9 +1427,15 @@ int lin_product(sem_lp_t lp, const T* r) {
     sem_ctx_t ctx = lp->ctx;
     hipStream_t st = ctx->stream;
     const int64_t nel = lp->nel;
-    lin_gather_kernel<T><<<grid_of(nel * kOut / 8, 8192), kBlock, 0, st>>>(lp->X, r, lp->sl, lp->gs->lid,
-                                                                       nel * kOut / 8, lp->skip);
+    lin_gather_kernel<T><<<grid_of(nel * lp->no / 8, 8192), kBlock, 0, st>>>(lp->X, r, lp->sl, lp->gs->lid,
+                                                                         nel * lp->no / 8, lp->skip, lp->no,
+                                                                         lp->nip);
     SEM_LAUNCH_CHECK(ctx);
+    if (lp->no != kOut) {   // other element sizes: the general product, outputs scattered to CSR order
+        if (nel > 0x7fffffff) return sem::fail(ctx, SEM_EINVAL, "sem_lp: too many elements");
+        return gemm(lp, (int)nel, lp->no, lp->no, lp->X, lp->nip, lp->Wfb, lp->no, nullptr, nullptr, 0, lp->Y3,
+                    nullptr, lp->no, 0, lp->kappa_inv, lp->gs->upos);
+    }
     const int64_t nchunks = (nel + kWsChunk - 1) / kWsChunk;
     const int groups = (int)std::min<int64_t>(kWsGroupsMax, (nchunks + 7) / 8 * 8);
     lin_gemm_kernel<<<(unsigned)(2 * groups), 512, 0, st>>>(lp->Y3, lp->X, lp->gs->upos, lp->kappa_inv, lp->Wfb,
@@ -1396,18 +1459,15 @@ int lp_apply_t(sem_lp_t lp, T* z, const T* r, bool unique) {
         SEM_LAUNCH_CHECK(ctx);
         return SEM_OK;
     }
-    features_kernel<T><<<(unsigned)nel, 64, 0, st>>>(lp->X, lp->scale, nullptr, r, nullptr, nullptr,
-                                                     lp->linear ? nullptr : lp->geo, lp->kappa, nullptr,
-                                                     nel, 0, lp->skip,
-                                                     unique ? lp->gs->lid : nullptr,
-                                                     lp->linear && unique ? lp->gs->uoff : nullptr,
-                                                     lp->linear && !unique ? lp->gs->mult : nullptr);
-    SEM_LAUNCH_CHECK(ctx);
-    int rc;
+    int rc = launch_features<T>(lp, nel, lp->X, lp->scale, nullptr, r, nullptr, nullptr,
+                                lp->linear ? nullptr : lp->geo, nullptr, 0, lp->skip,
+                                unique ? lp->gs->lid : nullptr, lp->linear && unique ? lp->gs->uoff : nullptr,
+                                lp->linear && !unique ? lp->gs->mult : nullptr);
+    if (rc) return rc;
     if (lp->linear) {   // one product with the folded matrix
         rc = refresh_fold(lp);
-        if (!rc) rc = gemm(lp, (int)nel, kOut, kOut, lp->X, kInPad, lp->Wfb, kOut, nullptr, nullptr, 0,
-                           lp->Y3, nullptr, kOut, 0);
+        if (!rc) rc = gemm(lp, (int)nel, lp->no, lp->no, lp->X, lp->nip, lp->Wfb, lp->no, nullptr, nullptr, 0,
+                           lp->Y3, nullptr, lp->no, 0);
     } else {
         rc = forward(lp, lp->X, nel);
     }
@@ -1416,14 +1476,14 @@ int lp_apply_t(sem_lp_t lp, T* z, const T* r, bool unique) {
         const int64_t nu = lp->gs->n_unique;
         lp_output_unique_kernel<T><<<grid_of(nu), kBlock, 0, st>>>(
             z, lp->Y3, lp->scale, lp->jacobi_base ? lp->minv : nullptr, r, lp->gs->uoff, lp->gs->uidx,
-            nu, lp->skip, lp->linear);
+            nu, lp->skip, lp->linear, lp->no);
         SEM_LAUNCH_CHECK(ctx);
         return SEM_OK;
     }
-    const int64_t n = nel * kOut;
+    const int64_t n = nel * lp->no;
     lp_output_kernel<T><<<grid_of(n), kBlock, 0, st>>>(z, lp->Y3, lp->scale, lp->gs->mult,
                                                        lp->jacobi_base ? lp->minv : nullptr, r, n, lp->skip,
-                                                       lp->linear);
+                                                       lp->linear, lp->no);
     SEM_LAUNCH_CHECK(ctx);
     return gs_launch(lp->gs, z, sizeof(T) == 8 ? SEM_F64 : SEM_F32, lp->skip);
 }
@@ -1546,15 +1606,15 @@ extern "C" int sem_lp_set_block(sem_lp_t lp, const float* W, int64_t count) {
     if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_set_block: null network");
     int rc = sem::enter(lp->ctx);
     if (rc) return rc;
-    if (!W || count != (int64_t)kOut * kOut)
-        return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_set_block: need %d x %d values", kOut, kOut);
+    if (!W || count != (int64_t)lp->no * lp->no)
+        return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_set_block: need %d x %d values", lp->no, lp->no);
     rc = sem_lp_set_linear(lp, 1);
     if (rc) return rc;
     rc = refresh_bf16(lp);
     if (rc) return rc;
     SEM_HIP(lp->ctx, hipStreamSynchronize(lp->ctx->stream));
     SEM_HIP(lp->ctx, hipMemcpy(lp->Wf32, W, 4 * (size_t)count, hipMemcpyHostToDevice));
-    sym_to_bf16<<<256, kBlock, 0, lp->ctx->stream>>>(lp->Wfb, lp->Wf32, kOut);
+    sym_to_bf16<<<256, kBlock, 0, lp->ctx->stream>>>(lp->Wfb, lp->Wf32, lp->no);
     SEM_LAUNCH_CHECK(lp->ctx);
     lp->fold_dirty = false;      // until the weights change again
     return SEM_OK;

@@ -4,7 +4,8 @@ float64 Jacobi-PCG solves, minibatch training, held-out evaluation.
 Orchestration only: every array is produced by libsem.so kernels (mesh,
 geometry, solves, operator, features, MLP, Adam); random draws come from
 ``synth``.  Recipe:
-  * training boxes: n^3 periodic, lx = 8, deformation amplitude ~ U[0, 0.2],
+  * training boxes: n^3 periodic, the network's lx (8 by default),
+    deformation amplitude ~ U[0, 0.2],
     draws whose minimum det J falls below 5% of the undeformed value rejected
     (the map folds near 1 / (2 pi));
   * right-hand side: 32 random Fourier modes per box ("fourier"), or white
@@ -32,14 +33,15 @@ from .box import BoxOperator
 def generate(ctx, lp, n=16, boxes=16, snapshots=16, elems_per_snapshot=64, seed=100,
              amp_range=(0.0, 0.2), min_rel_detj=0.05, rhs="fourier", include_zero=False,
              verbose=False, dirichlet=False):
-    """Returns (X bf16 [rows, 528], T float32 [rows, 512], info).  With
-    ``dirichlet`` the pairs come from boxes with u = 0 on the boundary (no mean
-    projection of the right-hand side)."""
-    lx = 8
+    """Returns (X bf16 [rows, padded feature width (528 at lx = 8)], T float32
+    [rows, lx^3], info) for the network's lx.  With ``dirichlet`` the pairs
+    come from boxes with u = 0 on the boundary (no mean projection of the
+    right-hand side)."""
+    lx = lp.lx
     nel = n ** 3
     rows = boxes * snapshots * elems_per_snapshot
-    X = torch.zeros((rows, B.SEM_LP_IN_PAD), dtype=torch.bfloat16, device="cuda")
-    T = torch.zeros((rows, B.SEM_LP_OUT), dtype=torch.float32, device="cuda")
+    X = torch.zeros((rows, lp.n_in_pad), dtype=torch.bfloat16, device="cuda")
+    T = torch.zeros((rows, lp.n_out), dtype=torch.float32, device="cuda")
     row, box, draw, rejected = 0, 0, 0, 0
     t0 = time.perf_counter()
     amps = []
@@ -125,7 +127,7 @@ def init_network(lp, seed=7, mu=None, jacobi_base=None, out_scale=1.0, linear=No
         B.sem_lp_set_jacobi_base(lp, jacobi_base)
     if linear is not None:
         B.sem_lp_set_linear(lp, linear)
-    params = synth.mlp_init(seed)
+    params = synth.mlp_init(seed, (lp.n_in, 256, 256, lp.n_out))
     params[4] = params[4] * out_scale
     for s, p in enumerate(params):
         B.sem_lp_set(lp, s, p.astype(np.float32))

@@ -1,0 +1,289 @@
+"""The learned preconditioner for other element sizes (sem_lp_create_lx:
+n = lx^3 outputs, n + 6 inputs): forward, gradients, features, the local and
+unique-layout applies and a given block, element by element against the
+oracle's bfloat16-storage emulation (oracle/mlp.py, whose functions take any
+size), at lx = 4 and 10; and at lx = 10 the classical block and a trained
+linear network in flexible CG.  Tolerances as in test_gpu_learned.py."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import mlp
+from oracle.quant import to_bf16
+from oracle.solve import BoxProblem
+from tests.helpers import to_dev
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2506_20994_amd")
+from paper_2506_20994_amd.box import BoxOperator  # noqa: E402
+
+GRAD_TOL = 2e-2
+EW_BLOCK = 1e-4
+EW_NET = 2e-3
+LXS = [4, 10]
+
+
+def _ew(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def _nrm(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def _params(lx, seed, bias_scale=0.1):
+    n = lx ** 3
+    p = synth.mlp_init(seed, (n + 6, 256, 256, n))
+    r = synth.rng(seed + 1)
+    return [q if q.ndim == 2 else bias_scale * r.standard_normal(q.shape) for q in p]
+
+
+def _load(lp, params):
+    for s, q in enumerate(params):
+        P.sem_lp_set(lp, s, q.astype(np.float32))
+
+
+def _f32(params):
+    return [q.astype(np.float32).astype(np.float64) for q in params]
+
+
+def _inputs(lx, B, seed):
+    n = lx ** 3
+    _, ni, nip = P.lp_sizes(lx)
+    r = synth.rng(seed)
+    X = r.standard_normal((B, ni))
+    X[:, :n] /= np.linalg.norm(X[:, :n], axis=1, keepdims=True)
+    Xq = to_bf16(X)
+    Xpad = np.zeros((B, nip), dtype=np.float32)
+    Xpad[:, :ni] = Xq
+    T = r.standard_normal((B, n)) * 0.1
+    return Xq, torch.from_numpy(Xpad).to(torch.bfloat16).cuda(), T
+
+
+def _plan_order(ids, nu):
+    _, first = np.unique(ids.ravel(), return_index=True)
+    plan_of = np.empty(nu, dtype=np.int64)
+    plan_of[np.argsort(first)] = np.arange(nu)
+    return plan_of
+
+
+@pytest.mark.parametrize("lx", LXS)
+def test_sizes_and_errors(sem_ctx, lx):
+    lp = P.sem_lp_create(sem_ctx, 16, lx=lx)
+    assert P.sem_lp_lx(lp) == lx
+    n, ni, nip = P.lp_sizes(lx)
+    assert P.sem_lp_get(lp, 0).shape == (256, ni) and P.sem_lp_get(lp, 4).shape == (n, 256)
+    with pytest.raises(P.SemError) as ei:          # the block of another size
+        P.sem_lp_set_block(lp, np.zeros((512, 512)) if lx != 8 else np.zeros((64, 64)))
+    assert ei.value.code == P.SEM_EINVAL
+    op = BoxOperator(sem_ctx, 2, 8, 0.1, keep_coords=False)
+    with pytest.raises(P.SemError) as ei:          # bound to an operator of another lx
+        op.bind(lp)
+    assert ei.value.code == P.SEM_EUNSUPPORTED_LX
+    op.gs.close()
+    lp.close()
+    for bad in (3, 14):
+        with pytest.raises(P.SemError) as ei:
+            P.sem_lp_create(sem_ctx, 16, lx=bad)
+        assert ei.value.code == P.SEM_EUNSUPPORTED_LX
+
+
+@pytest.mark.parametrize("lx", LXS)
+@pytest.mark.parametrize("form", ["mse", "metric", "linear"])
+def test_forward_and_gradients(sem_ctx, lx, form):
+    B = 128
+    n = lx ** 3
+    params = _params(lx, 30 + lx)
+    lp = P.sem_lp_create(sem_ctx, B, lx=lx)
+    _load(lp, params)
+    K = None
+    linear = form == "linear"
+    if form == "metric":
+        P.sem_lp_set_metric(lp, 1.0)
+        K = mlp.reference_metric(lx, 1.0)
+    if linear:
+        P.sem_lp_set_linear(lp, 1)
+    Xq, Xd, T = _inputs(lx, B, 31 + lx)
+    Y = torch.empty((B, n), dtype=torch.float32, device="cuda")
+    P.sem_lp_forward(lp, Xd, Y)
+    torch.cuda.synchronize()
+    yq = mlp.forward_bf16(_f32(params), Xq, linear=linear)[2]
+    assert _ew(Y.cpu().numpy(), yq) <= EW_NET, _ew(Y.cpu().numpy(), yq)
+    loss = P.sem_lp_gradients(lp, Xd, to_dev(T.astype(np.float32)))
+    lq, gq = mlp.backward_bf16(_f32(params), Xq, T.astype(np.float32).astype(np.float64), K, linear=linear)
+    assert abs(loss - lq) <= 1e-3 * lq
+    l_ref, g_ref = mlp.backward([to_bf16(q) if q.ndim == 2 else q for q in _f32(params)], Xq, T, K,
+                                linear=linear)
+    for s in range(6):
+        g = P.sem_lp_get(lp, 18 + s)
+        if linear and s % 2:
+            assert np.all(g == 0)
+            continue
+        assert _nrm(g, g_ref[s]) <= GRAD_TOL, (s, _nrm(g, g_ref[s]))
+        assert _ew(g, gq[s]) <= EW_NET, (s, _ew(g, gq[s]))
+    lp.close()
+
+
+@pytest.mark.parametrize("lx", LXS)
+def test_features_and_targets(sem_ctx, lx):
+    n_box, amp = 2, 0.1
+    n = lx ** 3
+    _, ni, nip = P.lp_sizes(lx)
+    op = BoxOperator(sem_ctx, n_box, lx, amp)
+    lp = P.sem_lp_create(sem_ctx, op.nel, lx=lx)
+    op.bind(lp)
+    ref = BoxProblem(n_box, lx, amp)
+    rG, eG = synth.unique_normal(ref.nu, 41), synth.unique_normal(ref.nu, 42)
+    els = torch.tensor([3, 0, 7, 5], dtype=torch.int64, device="cuda")
+    X = torch.zeros((6, nip), dtype=torch.bfloat16, device="cuda")
+    T = torch.zeros((6, n), dtype=torch.float32, device="cuda")
+    P.sem_lp_samples(lp, op.scatter(rG), op.scatter(eG), els, X, T, 2)
+    torch.cuda.synchronize()
+    sel = els.cpu().numpy()
+    Xr, s, kap = mlp.features(rG[ref.ids][sel], tuple(g[sel] for g in ref.G), None)
+    Tr = mlp.targets(eG[ref.ids][sel], s, kap)
+    Xg = X.float().cpu().numpy()
+    assert np.all(Xg[:2] == 0) and np.all(Xg[2:, ni:] == 0)
+    assert np.max(np.abs(Xg[2:, :ni] - to_bf16(Xr)) / np.maximum(np.abs(to_bf16(Xr)), 1e-30)) <= 2 ** -7
+    np.testing.assert_allclose(T[2:].cpu().numpy(), Tr, rtol=1e-5, atol=1e-7 * np.abs(Tr).max())
+    lp.close()
+    op.gs.close()
+
+
+@pytest.mark.parametrize("lx", LXS)
+def test_local_applies(sem_ctx, lx):
+    """Nonlinear and linear applies on the local layout, float64 and float32."""
+    n_box, amp = 2, 0.1
+    op = BoxOperator(sem_ctx, n_box, lx, amp)
+    ref = BoxProblem(n_box, lx, amp)
+    rG = synth.unique_normal(ref.nu, 51)
+    for linear in (False, True):
+        lp = P.sem_lp_create(sem_ctx, op.nel, lx=lx)
+        if linear:
+            P.sem_lp_set_linear(lp, 1)
+        op.bind(lp)
+        params = _params(lx, 50 + int(linear))
+        _load(lp, params)
+        f32 = _f32(params)
+        if linear:
+            zq = mlp.apply_block_bf16(mlp.folded_matrix(f32, lx ** 3), rG[ref.ids], ref.G, None, ref.ids,
+                                      ref.nu, normalise=True)
+        else:
+            zq = mlp.apply_bf16(f32, rG[ref.ids], ref.G, None, ref.ids, ref.nu)
+        for dt in (torch.float64, torch.float32):
+            r = op.scatter(rG).to(dt)
+            z = torch.empty_like(r)
+            P.sem_lp_apply(lp, z, r)
+            torch.cuda.synchronize()
+            assert _ew(z.double().cpu().numpy(), zq) <= EW_NET, (linear, dt, _ew(z.double().cpu().numpy(), zq))
+        lp.close()
+    op.gs.close()
+
+
+@pytest.mark.parametrize("lx", LXS)
+@pytest.mark.parametrize("jb", [False, True])
+def test_unique_linear_apply(sem_ctx, lx, jb):
+    """The solver's apply on unique-node vectors (at lx != 8 the general MFMA
+    product with the outputs scattered to CSR order), float64 and float32."""
+    n_box, amp = 3, 0.1
+    op = BoxOperator(sem_ctx, n_box, lx, amp)
+    lp = P.sem_lp_create(sem_ctx, op.nel, lx=lx)
+    P.sem_lp_set_linear(lp, 1)
+    P.sem_lp_set_jacobi_base(lp, int(jb))
+    op.bind(lp)
+    params = _params(lx, 54)
+    _load(lp, params)
+    ref = BoxProblem(n_box, lx, amp)
+    rG = synth.unique_normal(ref.nu, 55)
+    f32 = _f32(params)
+    zlq = mlp.apply_block_bf16(mlp.folded_matrix(f32, lx ** 3), rG[ref.ids], ref.G, None, ref.ids, ref.nu,
+                               normalise=False, f32_decisions=True)
+    zq = np.zeros(ref.nu)
+    zq[ref.ids.ravel()] = zlq.ravel()
+    if jb:
+        zq += rG / ref.diagonal()
+    plan_of = _plan_order(ref.ids, ref.nu)
+    rp = np.empty(ref.nu)
+    rp[plan_of] = rG
+    for dt in (torch.float64, torch.float32):
+        r = torch.from_numpy(rp).to(dt).cuda()
+        z = torch.full_like(r, float("nan"))
+        P.sem_lp_apply_unique(lp, z, r)
+        torch.cuda.synchronize()
+        zg = z.double().cpu().numpy()[plan_of]
+        assert np.all(np.isfinite(zg))
+        assert _ew(zg, zq) <= EW_NET, (dt, _ew(zg, zq))
+    lp.close()
+    op.gs.close()
+
+
+@pytest.mark.parametrize("lx", LXS)
+def test_set_block(sem_ctx, lx):
+    n_box, amp, n = 3, 0.1, lx ** 3
+    op = BoxOperator(sem_ctx, n_box, lx, amp)
+    lp = P.sem_lp_create(sem_ctx, op.nel, lx=lx)
+    op.bind(lp)
+    W = synth.rng(64).standard_normal((n, n)) * 0.05
+    P.sem_lp_set_block(lp, W)
+    ref = BoxProblem(n_box, lx, amp)
+    rG = synth.unique_normal(ref.nu, 65)
+    plan_of = _plan_order(ref.ids, ref.nu)
+    rp = np.empty(ref.nu)
+    rp[plan_of] = rG
+    r = torch.from_numpy(rp).cuda()
+    z = torch.empty_like(r)
+    P.sem_lp_apply_unique(lp, z, r)
+    torch.cuda.synchronize()
+    zlq = mlp.apply_block_bf16(W, rG[ref.ids], ref.G, None, ref.ids, ref.nu, normalise=False, f32_decisions=True)
+    zq = np.zeros(ref.nu)
+    zq[ref.ids.ravel()] = zlq.ravel()
+    assert _ew(z.cpu().numpy()[plan_of], zq) <= EW_BLOCK, _ew(z.cpu().numpy()[plan_of], zq)
+    lp.close()
+    op.gs.close()
+
+
+def test_lx10_classical_block_and_trained_network(sem_ctx):
+    """lx = 10: the classical block, and the linear network trained on the GPU
+    with the energy-norm loss on float64 Jacobi-PCG pairs (white-noise
+    right-hand sides) from 256 8^3 boxes (131k element rows, as at lx = 8), both
+    cut the flexible-CG iteration count on a held-out 10^3 box well below
+    Jacobi-PCG's, with no Jacobi fallback, inside float32 residual
+    replacement."""
+    from paper_2506_20994_amd import learned as LR
+    lx, n = 10, 10
+    op = BoxOperator(sem_ctx, n, lx, 0.1)
+    k, a, ph = synth.fourier_modes(5)
+    b = op.fourier_rhs(k, a, ph)
+    x = torch.empty_like(b)
+    cg0 = op.solver(P.SEM_SOLVE_F64)
+    _, st0 = P.sem_cg_solve(cg0, x, b, tol=1e-10)
+    blk = P.sem_lp_create(sem_ctx, op.nel, lx=lx)
+    op.bind(blk)
+    P.sem_lp_set_block(blk, LR.reference_block(sem_ctx, lx))
+    lp = P.sem_lp_create(sem_ctx, max(op.nel, 1024), lx=lx)
+    LR.init_network(lp, 7, mu=1.0, jacobi_base=True, out_scale=0.0, linear=True)
+    X, T, _ = LR.generate(sem_ctx, lp, n=8, boxes=256, snapshots=1, elems_per_snapshot=512, seed=400,
+                          rhs="noise", include_zero=True)
+    assert torch.isfinite(T).all()
+    hist = LR.train(lp, X, T, epochs=60, batch=1024, lr=3e-4)
+    assert hist[-1] < hist[0]
+    del X, T
+    op.bind(lp)
+    its = {}
+    for name, h in (("classical", blk), ("learned", lp)):
+        cg = op.solver(P.SEM_SOLVE_F32_IR, learned=h)
+        _, st = P.sem_cg_solve(cg, x, b, tol=1e-10, precision=P.SEM_SOLVE_F32_IR, ir_mode=1, learned=h)
+        assert st["converged"] and st["relres"] <= 1e-10, (name, st)
+        assert st["jacobi_steps"] == 0 and not st["fell_back"], (name, st)
+        its[name] = st["iterations"]
+        cg.close()
+    print(f"lx=10 10^3: Jacobi-PCG {st0['iterations']} its; {its}")
+    assert its["classical"] <= 0.6 * st0["iterations"]
+    assert its["learned"] <= 0.6 * st0["iterations"]
+    for h in (cg0, blk, lp):
+        h.close()
+    op.gs.close()
