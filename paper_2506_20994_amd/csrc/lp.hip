@@ -7,6 +7,7 @@
 // GEMM form used throughout: C[M][N] = A[M][K] . B[N][K]^T with both operands
 // k-contiguous (row-major bf16); the other products of backpropagation are
 // brought to this form with explicit transposes.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -1347,9 +1348,12 @@ static int lp_train_buffers(sem_lp_t lp, int B) {
     LP_ALLOC2(lp->d2b, 2 * R * kHid);
     LP_ALLOC2(lp->d1f, 4 * R * kHid);
     LP_ALLOC2(lp->d1b, 2 * R * kHid);
-    LP_ALLOC2(lp->tA, 2 * R * kInPad);
-    LP_ALLOC2(lp->tB, 2 * R * kInPad);
-    LP_ALLOC2(lp->colpart, 4 * ((R + kColRows - 1) / kColRows) * kOut);
+    // the transposes hold no x B, 256 x B or nip x B values, the column-sum
+    // partials chunks x no or chunks x 256 (no < 256 for lx < 8)
+    const size_t wide = std::max<size_t>(kInPad, (size_t)kHid), cols = std::max<size_t>(kOut, (size_t)kHid);
+    LP_ALLOC2(lp->tA, 2 * R * wide);
+    LP_ALLOC2(lp->tB, 2 * R * wide);
+    LP_ALLOC2(lp->colpart, 4 * ((R + kColRows - 1) / kColRows) * cols);
 #undef LP_ALLOC2
     (void)B;
     return SEM_OK;
