@@ -465,11 +465,15 @@ int sem_mg_apply(sem_mg_t mg, void* z, const void* r, sem_dtype_t dtype);
  * step). */
 int sem_lp_create(sem_ctx_t ctx, int64_t max_rows, sem_lp_t* lp);
 /* The same for elements of lx^3 nodes, lx even in [4, 12] (SEM_EUNSUPPORTED_LX
- * otherwise).  At lx = 8 the linear form's product runs in a weight-stationary
- * kernel written for 512 x 512 blocks; at other lx in the general MFMA product. */
-int sem_lp_create_lx(sem_ctx_t ctx, int lx, int64_t max_rows, sem_lp_t* lp);
-/* The element size lx the network was created for. */
-int sem_lp_lx(sem_lp_t lp, int* lx);
+ * otherwise), with hidden layers of width `hidden` (a multiple of 16 in
+ * [16, 1024]; 0: 256, the workload's).  The linear form's block then has rank
+ * at most `hidden`.  At lx = 8 the linear form's product runs in a
+ * weight-stationary kernel written for 512 x 512 blocks; at other lx in the
+ * general MFMA product.  Slot sizes follow: W1 hidden x (n + 6), W2 hidden x
+ * hidden, W3 n x hidden. */
+int sem_lp_create_lx(sem_ctx_t ctx, int lx, int hidden, int64_t max_rows, sem_lp_t* lp);
+/* The element size lx and hidden width (may be NULL) the network was created for. */
+int sem_lp_lx(sem_lp_t lp, int* lx, int* hidden);
 int sem_lp_destroy(sem_lp_t lp);
 /* Copy `count` float32 values (host) into / out of slot `which`; count must
  * equal the slot's size.  Synchronous. */

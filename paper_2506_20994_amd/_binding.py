@@ -31,10 +31,11 @@ def lp_sizes(lx):
     return n, n + 6, (n + 6 + 15) // 16 * 16
 
 
-def lp_slots(lx=8):
+def lp_slots(lx=8, hidden=256):
     """slot -> shape of the float32 array it holds (parameters; +6 m, +12 v, +18 grads)"""
     n, ni, _ = lp_sizes(lx)
-    return [(256, ni), (256,), (256, 256), (256,), (n, 256), (n,)]
+    h = hidden
+    return [(h, ni), (h,), (h, h), (h,), (n, h), (n,)]
 
 
 LP_SLOTS = lp_slots(8)
@@ -122,8 +123,8 @@ EXPORTS = {
     "sem_cg_destroy": (_int, [_vp]),
     "sem_cg_solve": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "sem_lp_create": (_int, [_vp, _i64, ctypes.POINTER(_vp)]),
-    "sem_lp_create_lx": (_int, [_vp, _int, _i64, ctypes.POINTER(_vp)]),
-    "sem_lp_lx": (_int, [_vp, ctypes.POINTER(_int)]),
+    "sem_lp_create_lx": (_int, [_vp, _int, _int, _i64, ctypes.POINTER(_vp)]),
+    "sem_lp_lx": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int)]),
     "sem_lp_destroy": (_int, [_vp]),
     "sem_lp_set": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_float), _i64]),
     "sem_lp_get": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_float), _i64]),
@@ -458,8 +459,8 @@ def sem_cg_solve(cg, x, b, **opts):
 
 
 class LearnedPrecond:
-    def __init__(self, ctx, handle, max_rows, lx=8):
-        self.ctx, self.handle, self.max_rows, self.lx = ctx, handle, max_rows, lx
+    def __init__(self, ctx, handle, max_rows, lx=8, hidden=256):
+        self.ctx, self.handle, self.max_rows, self.lx, self.hidden = ctx, handle, max_rows, lx, hidden
         self.n_out, self.n_in, self.n_in_pad = lp_sizes(lx)
         self._bound = None
         ctx.adopt(self)
@@ -476,18 +477,20 @@ class LearnedPrecond:
             pass
 
 
-def sem_lp_create(ctx, max_rows, lx=8):
-    """A network for elements of lx^3 nodes (sem_lp_create_lx)."""
+def sem_lp_create(ctx, max_rows, lx=8, hidden=256):
+    """A network for elements of lx^3 nodes with hidden layers of width
+    `hidden` (sem_lp_create_lx)."""
     out = _vp()
     h = ctx.bind()
-    _check(lib().sem_lp_create_lx(h, int(lx), int(max_rows), ctypes.byref(out)), h)
-    return LearnedPrecond(ctx, out, max_rows, lx)
+    _check(lib().sem_lp_create_lx(h, int(lx), int(hidden), int(max_rows), ctypes.byref(out)), h)
+    return LearnedPrecond(ctx, out, max_rows, lx, hidden)
 
 
 def sem_lp_lx(lp):
-    v = _int(0)
-    _check(lib().sem_lp_lx(lp.handle, ctypes.byref(v)), lp.ctx.handle)
-    return v.value
+    """(lx, hidden width) of the network"""
+    v, hd = _int(0), _int(0)
+    _check(lib().sem_lp_lx(lp.handle, ctypes.byref(v), ctypes.byref(hd)), lp.ctx.handle)
+    return v.value, hd.value
 
 
 def sem_lp_destroy(lp):
@@ -503,7 +506,7 @@ def sem_lp_set(lp, which, values):
 
 def sem_lp_get(lp, which):
     import numpy as np
-    shape = lp_slots(lp.lx)[which % 6]
+    shape = lp_slots(lp.lx, lp.hidden)[which % 6]
     a = np.empty(shape, dtype=np.float32)
     _check(lib().sem_lp_get(lp.handle, which, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                             a.size), lp.ctx.handle)

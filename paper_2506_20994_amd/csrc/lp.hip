@@ -678,8 +678,9 @@ __global__ void unit_id_kernel(double* __restrict__ u, const int64_t* __restrict
 struct sem_lp_s {
     sem_ctx_t ctx = nullptr;
     int64_t max_rows = 0;
-    // element size: lx, no = lx^3 outputs, ni = no + 6 inputs, nip = ni padded to 16
-    int lx = 8, no = kOut, ni = kIn, nip = kInPad;
+    // element size: lx, no = lx^3 outputs, ni = no + 6 inputs, nip = ni padded to 16;
+    // nh the width of the two hidden layers
+    int lx = 8, no = kOut, ni = kIn, nip = kInPad, nh = kHid;
     // float32 masters, Adam moments, gradients (W1 gradient is 256 x nip)
     float *W[3] = {}, *b[3] = {}, *mW[3] = {}, *mb[3] = {}, *vW[3] = {}, *vb[3] = {};
     float *gW[3] = {}, *gb[3] = {};
@@ -725,8 +726,8 @@ struct sem_lp_s {
 
 namespace {
 
-int param_rows(const sem_lp_s* lp, int layer) { return layer == 2 ? lp->no : kHid; }
-int param_cols(const sem_lp_s* lp, int layer) { return layer == 0 ? lp->ni : kHid; }
+int param_rows(const sem_lp_s* lp, int layer) { return layer == 2 ? lp->no : lp->nh; }
+int param_cols(const sem_lp_s* lp, int layer) { return layer == 0 ? lp->ni : lp->nh; }
 
 int lp_alloc(sem_lp_t lp, void** p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes);
@@ -777,6 +778,7 @@ int transpose(sem_lp_t lp, u16* out, int ldo, const u16* in, int ldi, int rows, 
 }
 
 int refresh_bf16(sem_lp_t lp) {
+    const int kHid = lp->nh;     // this network's hidden width
     if (!lp->dirty) return SEM_OK;
     hipStream_t st = lp->ctx->stream;
     weights_to_bf16<<<256, kBlock, 0, st>>>(lp->W1b, lp->nip, nullptr, lp->W[0], kHid, lp->ni);
@@ -790,6 +792,7 @@ int refresh_bf16(sem_lp_t lp) {
 // symmetric part of the folded (W3 W2 W1)[:, :no] of the linear form, in bf16;
 // needed by inference only, so training steps do not recompute it
 int refresh_fold(sem_lp_t lp) {
+    const int kHid = lp->nh;     // this network's hidden width
     int rc = refresh_bf16(lp);
     if (rc || !lp->fold_dirty || !lp->linear || !lp->Wfb) return rc;
     hipStream_t st = lp->ctx->stream;
@@ -806,6 +809,7 @@ int refresh_fold(sem_lp_t lp) {
 
 // forward of rows [0, M) of lp->X into Y1, Y2 (bf16) and Y3 (float)
 int forward(sem_lp_t lp, const u16* X, int64_t M) {
+    const int kHid = lp->nh;     // this network's hidden width
     int rc = refresh_bf16(lp);
     if (rc) return rc;
     if (M > 0x7fffffff) return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp: too many rows");
@@ -835,7 +839,7 @@ float** param_slot(sem_lp_t lp, int which, int64_t* count, int* ld) {
 
 }  // namespace
 
-extern "C" int sem_lp_create_lx(sem_ctx_t ctx, int lx, int64_t max_rows, sem_lp_t* out) {
+extern "C" int sem_lp_create_lx(sem_ctx_t ctx, int lx, int hidden, int64_t max_rows, sem_lp_t* out) {
     int rc = sem::enter(ctx);
     if (rc) return rc;
     if (!out) return sem::fail(ctx, SEM_EINVAL, "sem_lp_create: null output");
@@ -845,10 +849,15 @@ extern "C" int sem_lp_create_lx(sem_ctx_t ctx, int lx, int64_t max_rows, sem_lp_
                          SEM_LX_MAX);
     if (max_rows < 1 || max_rows > (1ll << 26))
         return sem::fail(ctx, SEM_EINVAL, "sem_lp_create: max_rows=%lld outside [1, 2^26]", (long long)max_rows);
+    if (hidden == 0) hidden = kHid;
+    if (hidden < 16 || hidden > 1024 || hidden % 16)
+        return sem::fail(ctx, SEM_EINVAL, "sem_lp_create: hidden width %d (a multiple of 16 in [16, 1024])", hidden);
     auto* lp = new sem_lp_s();
     lp->ctx = ctx;
     lp->max_rows = max_rows;
     lp->lx = lx;
+    lp->nh = hidden;
+    const int kHid = hidden;
     lp->no = lx * lx * lx;
     lp->ni = lp->no + 6;
     lp->nip = (lp->ni + 15) / 16 * 16;
@@ -883,12 +892,13 @@ extern "C" int sem_lp_create_lx(sem_ctx_t ctx, int lx, int64_t max_rows, sem_lp_
 }
 
 extern "C" int sem_lp_create(sem_ctx_t ctx, int64_t max_rows, sem_lp_t* out) {
-    return sem_lp_create_lx(ctx, 8, max_rows, out);
+    return sem_lp_create_lx(ctx, 8, kHid, max_rows, out);
 }
 
-extern "C" int sem_lp_lx(sem_lp_t lp, int* lx) {
+extern "C" int sem_lp_lx(sem_lp_t lp, int* lx, int* hidden) {
     if (!lp || !lx) return sem::fail(lp ? lp->ctx : nullptr, SEM_EINVAL, "sem_lp_lx: null argument");
     *lx = lp->lx;
+    if (hidden) *hidden = lp->nh;
     return SEM_OK;
 }
 
@@ -914,8 +924,8 @@ extern "C" int sem_lp_set(sem_lp_t lp, int which, const float* host, int64_t cou
     if (count != n) return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_set: slot %d holds %lld values, got %lld",
                                      which, (long long)n, (long long)count);
     SEM_HIP(lp->ctx, hipStreamSynchronize(lp->ctx->stream));
-    if (which == 18) {   // W1 gradient: 256 x ni values into a 256 x nip array
-        for (int r = 0; r < kHid; ++r)
+    if (which == 18) {   // W1 gradient: nh x ni values into an nh x nip array
+        for (int r = 0; r < lp->nh; ++r)
             SEM_HIP(lp->ctx, hipMemcpy(*slot + (size_t)r * ld, host + (size_t)r * lp->ni, 4 * (size_t)lp->ni,
                                        hipMemcpyHostToDevice));
     } else {
@@ -937,7 +947,7 @@ extern "C" int sem_lp_get(sem_lp_t lp, int which, float* host, int64_t count) {
                                      which, (long long)n, (long long)count);
     SEM_HIP(lp->ctx, hipStreamSynchronize(lp->ctx->stream));
     if (which == 18) {
-        for (int r = 0; r < kHid; ++r)
+        for (int r = 0; r < lp->nh; ++r)
             SEM_HIP(lp->ctx, hipMemcpy(host + (size_t)r * lp->ni, *slot + (size_t)r * ld, 4 * (size_t)lp->ni,
                                        hipMemcpyDeviceToHost));
     } else {
@@ -1021,6 +1031,7 @@ extern "C" int sem_lp_set_metric(sem_lp_t lp, double mu) {
 }
 
 extern "C" int sem_lp_set_linear(sem_lp_t lp, int on) {
+    const int kHid = lp->nh;     // this network's hidden width
     if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_set_linear: null network");
     int rc = sem::enter(lp->ctx);
     if (rc) return rc;
@@ -1289,6 +1300,7 @@ static void colsum(sem_lp_t lp, float* out, const float* d, int rows, int cols) 
 
 // gradients of the batch loss into the gradient slots (and the loss into *loss_dev)
 static int lp_backward(sem_lp_t lp, const uint16_t* Xb, const float* Tb, int B) {
+    const int kHid = lp->nh;     // this network's hidden width
     sem_ctx_t ctx = lp->ctx;
     hipStream_t st = ctx->stream;
     int rc = forward(lp, Xb, B);
@@ -1336,6 +1348,7 @@ static int lp_backward(sem_lp_t lp, const uint16_t* Xb, const float* Tb, int B) 
 }
 
 static int lp_train_buffers(sem_lp_t lp, int B) {
+    const int kHid = lp->nh;     // this network's hidden width
     if (lp->d3f) return SEM_OK;
     const size_t R = (size_t)lp->max_rows;
     const size_t kOut = (size_t)lp->no, kInPad = (size_t)lp->nip;

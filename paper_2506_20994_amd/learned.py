@@ -127,7 +127,7 @@ def init_network(lp, seed=7, mu=None, jacobi_base=None, out_scale=1.0, linear=No
         B.sem_lp_set_jacobi_base(lp, jacobi_base)
     if linear is not None:
         B.sem_lp_set_linear(lp, linear)
-    params = synth.mlp_init(seed, (lp.n_in, 256, 256, lp.n_out))
+    params = synth.mlp_init(seed, (lp.n_in, lp.hidden, lp.hidden, lp.n_out))
     params[4] = params[4] * out_scale
     for s, p in enumerate(params):
         B.sem_lp_set(lp, s, p.astype(np.float32))

@@ -35,9 +35,9 @@ def _nrm(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
-def _params(lx, seed, bias_scale=0.1):
+def _params(lx, seed, bias_scale=0.1, hidden=256):
     n = lx ** 3
-    p = synth.mlp_init(seed, (n + 6, 256, 256, n))
+    p = synth.mlp_init(seed, (n + 6, hidden, hidden, n))
     r = synth.rng(seed + 1)
     return [q if q.ndim == 2 else bias_scale * r.standard_normal(q.shape) for q in p]
 
@@ -74,7 +74,7 @@ def _plan_order(ids, nu):
 @pytest.mark.parametrize("lx", LXS)
 def test_sizes_and_errors(sem_ctx, lx):
     lp = P.sem_lp_create(sem_ctx, 16, lx=lx)
-    assert P.sem_lp_lx(lp) == lx
+    assert P.sem_lp_lx(lp) == (lx, 256)
     n, ni, nip = P.lp_sizes(lx)
     assert P.sem_lp_get(lp, 0).shape == (256, ni) and P.sem_lp_get(lp, 4).shape == (n, 256)
     with pytest.raises(P.SemError) as ei:          # the block of another size
@@ -90,15 +90,21 @@ def test_sizes_and_errors(sem_ctx, lx):
         with pytest.raises(P.SemError) as ei:
             P.sem_lp_create(sem_ctx, 16, lx=bad)
         assert ei.value.code == P.SEM_EUNSUPPORTED_LX
+    for bad in (8, 100, 2048):
+        with pytest.raises(P.SemError) as ei:
+            P.sem_lp_create(sem_ctx, 16, lx=lx, hidden=bad)
+        assert ei.value.code == P.SEM_EINVAL
 
 
-@pytest.mark.parametrize("lx", LXS)
+@pytest.mark.parametrize("lx,hidden", [(4, 256), (10, 256), (10, 512), (8, 128)])
 @pytest.mark.parametrize("form", ["mse", "metric", "linear"])
-def test_forward_and_gradients(sem_ctx, lx, form):
+def test_forward_and_gradients(sem_ctx, lx, hidden, form):
+    """Also other hidden widths (sem_lp_create_lx's `hidden`)."""
     B = 128
     n = lx ** 3
-    params = _params(lx, 30 + lx)
-    lp = P.sem_lp_create(sem_ctx, B, lx=lx)
+    params = _params(lx, 30 + lx, hidden=hidden)
+    lp = P.sem_lp_create(sem_ctx, B, lx=lx, hidden=hidden)
+    assert P.sem_lp_lx(lp) == (lx, hidden)
     _load(lp, params)
     K = None
     linear = form == "linear"
@@ -184,18 +190,18 @@ def test_local_applies(sem_ctx, lx):
     op.gs.close()
 
 
-@pytest.mark.parametrize("lx", LXS)
+@pytest.mark.parametrize("lx,hidden", [(4, 256), (10, 256), (10, 512)])
 @pytest.mark.parametrize("jb", [False, True])
-def test_unique_linear_apply(sem_ctx, lx, jb):
+def test_unique_linear_apply(sem_ctx, lx, hidden, jb):
     """The solver's apply on unique-node vectors (at lx != 8 the general MFMA
     product with the outputs scattered to CSR order), float64 and float32."""
     n_box, amp = 3, 0.1
     op = BoxOperator(sem_ctx, n_box, lx, amp)
-    lp = P.sem_lp_create(sem_ctx, op.nel, lx=lx)
+    lp = P.sem_lp_create(sem_ctx, op.nel, lx=lx, hidden=hidden)
     P.sem_lp_set_linear(lp, 1)
     P.sem_lp_set_jacobi_base(lp, int(jb))
     op.bind(lp)
-    params = _params(lx, 54)
+    params = _params(lx, 54, hidden=hidden)
     _load(lp, params)
     ref = BoxProblem(n_box, lx, amp)
     rG = synth.unique_normal(ref.nu, 55)
