@@ -612,9 +612,11 @@ def scale_run(ctx, P, n=64, amp=0.15, tol=1e-10):
     """The full stack at scale (--mode scale): a 64^3 box (E = 262144) with
     amplitude 0.15 at lx = 8 (134M local nodes) and lx = 10 (262M): operator
     throughput, float64 Jacobi-PCG against float32 residual replacement, the
-    network for that lx (trained as in learned_comparison on 16^3 boxes: 128 at
-    lx = 8, 64 at lx = 10) with float32 / bfloat16 residual replacement, and the
-    multigrid V-cycle.  Several minutes of GPU time."""
+    network for that lx (trained as in learned_comparison: at lx = 8 on 128 16^3
+    boxes; at lx = 10 on 256 8^3 boxes, whose 256 amplitude draws gave a block
+    that stays usable on the strongly deformed box, where 64 16^3 boxes did
+    not) with float32 / bfloat16 residual replacement, and the multigrid
+    V-cycle.  Several minutes of GPU time."""
     import torch
     import synth
     from paper_2506_20994_amd.box import BoxOperator
@@ -624,8 +626,9 @@ def scale_run(ctx, P, n=64, amp=0.15, tol=1e-10):
         lp = P.sem_lp_create(ctx, n ** 3, lx=lx)
         LR.init_network(lp, 7, mu=1.0, jacobi_base=True, out_scale=0.0, linear=True)
         t0 = time.perf_counter()
-        X, T, _ = LR.generate(ctx, lp, n=16, boxes=128 if lx == 8 else 64, snapshots=1,
-                              elems_per_snapshot=4096, rhs="noise", include_zero=True)
+        nb, boxes, per = (16, 128, 4096) if lx == 8 else (8, 256, 512)
+        X, T, _ = LR.generate(ctx, lp, n=nb, boxes=boxes, snapshots=1, elems_per_snapshot=per, rhs="noise",
+                              include_zero=True)
         LR.train(lp, X, T, epochs=60, batch=1024, lr=3e-4)
         del X, T
         torch.cuda.empty_cache()
