@@ -521,6 +521,12 @@ int sem_lp_set_linear(sem_lp_t lp, int on);
  * change (sem_lp_set, a training step or sem_lp_load), which folds them
  * again. */
 int sem_lp_set_block(sem_lp_t lp, const float* W, int64_t count);
+/* The kernel of the linear form's product on unique-node vectors (the
+ * solver's apply): 0 automatic (the weight-stationary kernel at lx = 8, the
+ * general MFMA product otherwise), 1 the weight-stationary kernel (lx = 8
+ * only, SEM_EINVAL otherwise), 2 the general product, whose epilogue scales by
+ * 1/kappa_e and scatters to CSR order.  Both compute the same sums. */
+int sem_lp_set_product(sem_lp_t lp, int kind);
 /* Jacobi base (on != 0): the preconditioner becomes z = Minv r + P_net(r),
  * Minv the inverse assembled diagonal of the bound operator, and training
  * targets become (err - Minv r) kappa / s, so the network learns the

@@ -16,7 +16,7 @@ __all__ = ["SemError", "SEM_F64", "SEM_F32", "SEM_BF16", "SEM_OK", "SEM_NOT_CONV
            "CgSolver", "SEM_SOLVE_F64", "SEM_SOLVE_F32_IR", "SEM_SOLVE_BF16_IR",
            "LearnedPrecond", "sem_lp_create", "sem_lp_destroy", "sem_lp_set", "sem_lp_get",
            "sem_lp_set_step", "sem_lp_get_step", "sem_lp_bind", "sem_lp_samples", "sem_lp_forward",
-           "sem_lp_gradients", "sem_lp_adam", "sem_lp_set_metric", "sem_lp_set_jacobi_base", "sem_lp_set_linear", "sem_lp_train_step", "sem_lp_apply", "sem_lp_apply_unique", "sem_lp_save", "sem_lp_load", "sem_lp_set_block", "LP_SLOTS", "lp_slots", "lp_sizes", "sem_lp_lx",
+           "sem_lp_gradients", "sem_lp_adam", "sem_lp_set_metric", "sem_lp_set_jacobi_base", "sem_lp_set_linear", "sem_lp_train_step", "sem_lp_apply", "sem_lp_apply_unique", "sem_lp_save", "sem_lp_load", "sem_lp_set_block", "LP_SLOTS", "lp_slots", "lp_sizes", "sem_lp_lx", "sem_lp_set_product",
            "SEM_LP_IN", "SEM_LP_IN_PAD", "SEM_LP_HIDDEN", "SEM_LP_OUT", "SemMgOpts", "Multigrid",
            "sem_mg_create", "sem_mg_destroy", "sem_mg_levels", "sem_mg_level_info", "sem_mg_set_lmax",
            "sem_mg_apply", "sem_mg_set_graphs", "sem_ax_set_variant", "sem_ax_get_variant", "sem_ax_tune", "sem_ax_tune_on",
@@ -125,6 +125,7 @@ EXPORTS = {
     "sem_lp_create": (_int, [_vp, _i64, ctypes.POINTER(_vp)]),
     "sem_lp_create_lx": (_int, [_vp, _int, _int, _i64, ctypes.POINTER(_vp)]),
     "sem_lp_lx": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int)]),
+    "sem_lp_set_product": (_int, [_vp, _int]),
     "sem_lp_destroy": (_int, [_vp]),
     "sem_lp_set": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_float), _i64]),
     "sem_lp_get": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_float), _i64]),
@@ -484,6 +485,11 @@ def sem_lp_create(ctx, max_rows, lx=8, hidden=256):
     h = ctx.bind()
     _check(lib().sem_lp_create_lx(h, int(lx), int(hidden), int(max_rows), ctypes.byref(out)), h)
     return LearnedPrecond(ctx, out, max_rows, lx, hidden)
+
+
+def sem_lp_set_product(lp, kind):
+    """0 automatic, 1 weight-stationary (lx = 8), 2 general MFMA product"""
+    _check(lib().sem_lp_set_product(lp.handle, int(kind)), lp.ctx.handle)
 
 
 def sem_lp_lx(lp):

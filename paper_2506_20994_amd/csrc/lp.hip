@@ -681,6 +681,9 @@ struct sem_lp_s {
     // element size: lx, no = lx^3 outputs, ni = no + 6 inputs, nip = ni padded to 16;
     // nh the width of the two hidden layers
     int lx = 8, no = kOut, ni = kIn, nip = kInPad, nh = kHid;
+    // the linear form's unique-layout product: 0 automatic (weight-stationary at
+    // lx = 8, the general product otherwise), 1 weight-stationary, 2 general
+    int product = 0;
     // float32 masters, Adam moments, gradients (W1 gradient is 256 x nip)
     float *W[3] = {}, *b[3] = {}, *mW[3] = {}, *mb[3] = {}, *vW[3] = {}, *vb[3] = {};
     float *gW[3] = {}, *gb[3] = {};
@@ -1448,7 +1451,7 @@ int lin_product(sem_lp_t lp, const T* r) {
                                                                          nel * lp->no / 8, lp->skip, lp->no,
                                                                          lp->nip);
     SEM_LAUNCH_CHECK(ctx);
-    if (lp->no != kOut) {   // other element sizes: the general product, outputs scattered to CSR order
+    if (lp->no != kOut || lp->product == 2) {   // the general product, outputs scattered to CSR order
         if (nel > 0x7fffffff) return sem::fail(ctx, SEM_EINVAL, "sem_lp: too many elements");
         return gemm(lp, (int)nel, lp->no, lp->no, lp->X, lp->nip, lp->Wfb, lp->no, nullptr, nullptr, 0, lp->Y3,
                     nullptr, lp->no, 0, lp->kappa_inv, lp->gs->upos);
@@ -1617,6 +1620,15 @@ extern "C" int sem_lp_load(sem_lp_t lp, const char* path) {
     for (int w = 0; !rc && w < 18; ++w) rc = sem_lp_set(lp, w, slots[w].data(), (int64_t)slots[w].size());
     if (!rc) rc = sem_lp_set_step(lp, step);
     return rc;
+}
+
+extern "C" int sem_lp_set_product(sem_lp_t lp, int kind) {
+    if (!lp) return sem::fail(nullptr, SEM_EINVAL, "sem_lp_set_product: null network");
+    if (kind < 0 || kind > 2 || (kind == 1 && lp->no != kOut))
+        return sem::fail(lp->ctx, SEM_EINVAL, "sem_lp_set_product: kind %d (the weight-stationary product needs lx = 8)",
+                         kind);
+    lp->product = kind;
+    return SEM_OK;
 }
 
 extern "C" int sem_lp_set_block(sem_lp_t lp, const float* W, int64_t count) {

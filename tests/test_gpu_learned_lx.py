@@ -190,14 +190,19 @@ def test_local_applies(sem_ctx, lx):
     op.gs.close()
 
 
-@pytest.mark.parametrize("lx,hidden", [(4, 256), (10, 256), (10, 512)])
+@pytest.mark.parametrize("lx,hidden", [(4, 256), (10, 256), (10, 512), (8, 256)])
 @pytest.mark.parametrize("jb", [False, True])
 def test_unique_linear_apply(sem_ctx, lx, hidden, jb):
-    """The solver's apply on unique-node vectors (at lx != 8 the general MFMA
-    product with the outputs scattered to CSR order), float64 and float32."""
+    """The solver's apply on unique-node vectors with the general MFMA product
+    (outputs scattered to CSR order; at lx = 8 chosen by sem_lp_set_product),
+    float64 and float32."""
     n_box, amp = 3, 0.1
     op = BoxOperator(sem_ctx, n_box, lx, amp)
     lp = P.sem_lp_create(sem_ctx, op.nel, lx=lx, hidden=hidden)
+    P.sem_lp_set_product(lp, 2)
+    if lx != 8:
+        with pytest.raises(P.SemError):
+            P.sem_lp_set_product(lp, 1)
     P.sem_lp_set_linear(lp, 1)
     P.sem_lp_set_jacobi_base(lp, int(jb))
     op.bind(lp)
