@@ -231,6 +231,166 @@ prolong_kernel(float* __restrict__ xf, const float* __restrict__ xc, const int32
     }
 }
 
+// The p-transfers (same elements, lxf -> lxc) with one wave per element and
+// four elements per workgroup, so that no workgroup barrier is needed between
+// the three contractions (the wave orders its own LDS traffic).  A lane takes
+// whole fine rows (k, j) -- a row's lid, owner flags and values are contiguous
+// -- and the coarse side is spread over the lanes.
+constexpr int kWaveElems = 4;
+
+// P^T: blc[E][c][b][a] = sum_{k,j,i} J[k][c] J[j][b] J[i][a] (owner-masked r_f)[E][k][j][i]
+template <int LF, int LC>
+__global__ void __launch_bounds__(64 * kWaveElems)
+restrict_p_wave_kernel(float* __restrict__ blc, const float* __restrict__ rf, const int32_t* __restrict__ lidf,
+                       const uint8_t* __restrict__ ownf, const float* __restrict__ J, int64_t nel,
+                       const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    constexpr int F2 = LF * LF, F3 = F2 * LF, C3 = LC * LC * LC;
+    __shared__ float sJ[LF * LC];
+    __shared__ float s1[kWaveElems][LF * LF * LC];   // [k][j][a]
+    __shared__ float s2[kWaveElems][LF * LC * LC];   // [k][b][a]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int q = tid; q < LF * LC; q += blockDim.x) sJ[q] = J[q];
+    __syncthreads();
+    const int64_t E = (int64_t)blockIdx.x * kWaveElems + w;
+    const bool live = E < nel;
+    for (int row = lane; row < F2; row += 64) {            // row = k LF + j
+        float v[LF];
+        const int64_t L0 = E * F3 + (int64_t)row * LF;
+#pragma unroll
+        for (int i = 0; i < LF; ++i) v[i] = (live && ownf[L0 + i]) ? rf[lidf[L0 + i]] : 0.f;
+#pragma unroll
+        for (int a = 0; a < LC; ++a) {
+            float s = 0.f;
+#pragma unroll
+            for (int i = 0; i < LF; ++i) s += sJ[i * LC + a] * v[i];
+            s1[w][row * LC + a] = s;
+        }
+    }
+    sem::wave_fence_barrier();
+    for (int o = lane; o < LF * LC * LC; o += 64) {
+        const int a = o % LC, b = (o / LC) % LC, k = o / (LC * LC);
+        float s = 0.f;
+#pragma unroll
+        for (int j = 0; j < LF; ++j) s += sJ[j * LC + b] * s1[w][(k * LF + j) * LC + a];
+        s2[w][o] = s;
+    }
+    sem::wave_fence_barrier();
+    for (int o = lane; o < C3; o += 64) {
+        const int a = o % LC, b = (o / LC) % LC, c = o / (LC * LC);
+        float s = 0.f;
+#pragma unroll
+        for (int k = 0; k < LF; ++k) s += sJ[k * LC + c] * s2[w][(k * LC + b) * LC + a];
+        if (live) blc[E * C3 + o] = s;
+    }
+}
+
+// x_f += P x_c at the owner nodes of each fine element
+template <int LF, int LC>
+__global__ void __launch_bounds__(64 * kWaveElems)
+prolong_p_wave_kernel(float* __restrict__ xf, const float* __restrict__ xc, const int32_t* __restrict__ lidf,
+                      const uint8_t* __restrict__ ownf, const int32_t* __restrict__ lidc, const float* __restrict__ J,
+                      int64_t nel, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    constexpr int F2 = LF * LF, F3 = F2 * LF, C3 = LC * LC * LC;
+    __shared__ float sJ[LF * LC];
+    __shared__ float sc[kWaveElems][C3];              // [c][b][a]
+    __shared__ float t1[kWaveElems][LC * LC * LF];    // [c][b][i]
+    __shared__ float t2[kWaveElems][LC * LF * LF];    // [c][j][i]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int q = tid; q < LF * LC; q += blockDim.x) sJ[q] = J[q];
+    __syncthreads();
+    const int64_t E = (int64_t)blockIdx.x * kWaveElems + w;
+    const bool live = E < nel;
+    for (int o = lane; o < C3; o += 64) {
+        const int32_t id = live ? lidc[E * C3 + o] : -1;
+        sc[w][o] = id >= 0 ? xc[id] : 0.f;
+    }
+    sem::wave_fence_barrier();
+    for (int o = lane; o < LC * LC * LF; o += 64) {
+        const int i = o % LF, cb = o / LF;
+        float s = 0.f;
+#pragma unroll
+        for (int a = 0; a < LC; ++a) s += sJ[i * LC + a] * sc[w][cb * LC + a];
+        t1[w][o] = s;
+    }
+    sem::wave_fence_barrier();
+    for (int o = lane; o < LC * LF * LF; o += 64) {
+        const int i = o % LF, j = (o / LF) % LF, c = o / (LF * LF);
+        float s = 0.f;
+#pragma unroll
+        for (int b = 0; b < LC; ++b) s += sJ[j * LC + b] * t1[w][(c * LC + b) * LF + i];
+        t2[w][o] = s;
+    }
+    sem::wave_fence_barrier();
+    if (!live) return;
+    for (int row = lane; row < F2; row += 64) {            // row = k LF + j
+        const int k = row / LF, j = row % LF;
+        const int64_t L0 = E * F3 + (int64_t)row * LF;
+#pragma unroll
+        for (int i = 0; i < LF; ++i) {
+            float s = 0.f;
+#pragma unroll
+            for (int c = 0; c < LC; ++c) s += sJ[k * LC + c] * t2[w][(c * LF + j) * LF + i];
+            if (ownf[L0 + i]) xf[lidf[L0 + i]] += s;
+        }
+    }
+}
+
+// P^T of an h-transfer (lx = 2 boxes): one thread per coarse element node c,
+// summing over the 8 children and their 8 nodes with the parent's trilinear
+// basis at the child's vertices
+__global__ void restrict_h_kernel(float* __restrict__ blc, const float* __restrict__ rf, const int32_t* __restrict__ lidf,
+                                  const uint8_t* __restrict__ ownf, int nf, int nc, int64_t nelc,
+                                  const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    MG_LOOP(t, nelc * 8) {
+        const int64_t E = t >> 3;
+        const int c = (int)(t & 7), ax = c & 1, ay = (c >> 1) & 1, az = c >> 2;
+        const int64_t ecx = E % nc, ecy = (E / nc) % nc, ecz = E / ((int64_t)nc * nc);
+        float acc = 0.f;
+        for (int ch = 0; ch < 8; ++ch) {
+            const int px = ch & 1, py = (ch >> 1) & 1, pz = ch >> 2;
+            const int64_t ef = (2 * ecx + px) + nf * ((2 * ecy + py) + (int64_t)nf * (2 * ecz + pz));
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int ix = i & 1, iy = (i >> 1) & 1, iz = i >> 2;
+                // phi_a(eta), eta = -1 + p + i in {-1, 0, 1}: 1, 1/2 or 0
+                const float wx = (float)(ax ? px + ix : 2 - px - ix) * 0.5f;
+                const float wy = (float)(ay ? py + iy : 2 - py - iy) * 0.5f;
+                const float wz = (float)(az ? pz + iz : 2 - pz - iz) * 0.5f;
+                const float wgt = wx * wy * wz;
+                const int64_t L = ef * 8 + i;
+                if (wgt != 0.f && ownf[L]) acc += wgt * rf[lidf[L]];
+            }
+        }
+        blc[t] = acc;
+    }
+}
+
+// dispatch of the p-transfer wave kernels for the (lxf, lxc) pairs the level
+// shapes produce; false if there is none (the workgroup-per-element kernels run)
+#define MG_PAIRS(X) X(3, 2) X(4, 2) X(5, 2) X(6, 3) X(7, 3) X(8, 4) X(9, 4) X(10, 5) X(11, 5) X(12, 6)
+bool restrict_p_wave(hipStream_t st, int lf, int lc, float* blc, const float* rf, const int32_t* lidf,
+                     const uint8_t* ownf, const float* J, int64_t nel, const int* skip) {
+    const unsigned g = (unsigned)((nel + kWaveElems - 1) / kWaveElems);
+#define MG_R(F, C) if (lf == F && lc == C) { \
+        restrict_p_wave_kernel<F, C><<<g, 64 * kWaveElems, 0, st>>>(blc, rf, lidf, ownf, J, nel, skip); return true; }
+    MG_PAIRS(MG_R)
+#undef MG_R
+    return false;
+}
+bool prolong_p_wave(hipStream_t st, int lf, int lc, float* xf, const float* xc, const int32_t* lidf,
+                    const uint8_t* ownf, const int32_t* lidc, const float* J, int64_t nel, const int* skip) {
+    const unsigned g = (unsigned)((nel + kWaveElems - 1) / kWaveElems);
+#define MG_P(F, C) if (lf == F && lc == C) { \
+        prolong_p_wave_kernel<F, C><<<g, 64 * kWaveElems, 0, st>>>(xf, xc, lidf, ownf, lidc, J, nel, skip); return true; }
+    MG_PAIRS(MG_P)
+#undef MG_P
+    return false;
+}
+#undef MG_PAIRS
+
 // Coarsest level: x = Ainv b with b assembled from the restricted local field
 // (bl) or given (bin).  Every workgroup assembles all of b into LDS, then each
 // of its waves forms kCoarseRows rows of Ainv b, the lanes striding along the
@@ -685,8 +845,13 @@ int vcycle(sem_mg_t mg, float* xout, const float* bin, const int* skip) {
         }
         if ((rc = level_ax(mg, lv, lv.wl, lv.d, skip))) return rc;
         cheb_resid_kernel<<<g, kBlock, 0, st>>>(lv.r, lv.wl, uoff, uidx, lv.nu, skip);
-        restrict_kernel<<<(unsigned)nx.nel, kBlock, 0, st>>>(nx.bl, lv.r, lv.gs->lid, lv.own, lv.J, lv.lx, nx.lx,
-                                                              lv.kind, lv.n, nx.n, nx.nel, skip);
+        if (lv.kind == 1 && lv.lx == 2)
+            restrict_h_kernel<<<vgrid(8 * nx.nel), kBlock, 0, st>>>(nx.bl, lv.r, lv.gs->lid, lv.own, lv.n, nx.n,
+                                                                    nx.nel, skip);
+        else if (lv.kind != 0 || !restrict_p_wave(st, lv.lx, nx.lx, nx.bl, lv.r, lv.gs->lid, lv.own, lv.J, nx.nel,
+                                                  skip))
+            restrict_kernel<<<(unsigned)nx.nel, kBlock, 0, st>>>(nx.bl, lv.r, lv.gs->lid, lv.own, lv.J, lv.lx,
+                                                                  nx.lx, lv.kind, lv.n, nx.n, nx.nel, skip);
         SEM_LAUNCH_CHECK(mg->ctx);
     }
     {
@@ -703,9 +868,11 @@ int vcycle(sem_mg_t mg, float* xout, const float* bin, const int* skip) {
         float* x = q == 0 ? xout : lv.x;
         const float* b = q == 0 ? bin : lv.b;
         const int f3 = lv.lx * lv.lx * lv.lx;
-        prolong_kernel<<<(unsigned)lv.nel, f3 <= 64 ? 64 : kBlock, 0, st>>>(x, nx.x, lv.gs->lid, lv.own,
-                                                                            nx.gs->lid, lv.J, lv.lx, nx.lx, lv.kind,
-                                                                            lv.n, nx.n, lv.nel, skip);
+        if (lv.kind != 0 || !prolong_p_wave(st, lv.lx, nx.lx, x, nx.x, lv.gs->lid, lv.own, nx.gs->lid, lv.J,
+                                            lv.nel, skip))
+            prolong_kernel<<<(unsigned)lv.nel, f3 <= 64 ? 64 : kBlock, 0, st>>>(x, nx.x, lv.gs->lid, lv.own,
+                                                                                nx.gs->lid, lv.J, lv.lx, nx.lx,
+                                                                                lv.kind, lv.n, nx.n, lv.nel, skip);
         if ((rc = level_ax(mg, lv, lv.wl, x, skip))) return rc;
         cheb_post_kernel<<<g, kBlock, 0, st>>>(x, lv.r, lv.d, b, lv.wl, lv.minv, lv.c0, uoff, uidx, lv.nu, skip);
         for (int m = 1; m < mg->degree; ++m) {

@@ -142,6 +142,14 @@ __device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t G) {
     return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3);
 }
 
+// order LDS traffic within one wave (no workgroup barrier): a fence on each
+// side of the wave barrier keeps the compiler from moving LDS accesses across it
+__device__ __forceinline__ void wave_fence_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // sum over the 64 lanes of a wave
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -49,6 +49,12 @@ CASES = [  # n, lx, amp, dirichlet, h2, degree, lo, galerkin
     (4, 6, 0.12, True, None, 3, 0.2, True),
     (2, 5, 0.1, False, 20.0, 3, 0.3, True),
     (4, 2, 0.1, True, 5.0, 2, 0.2, True),
+    # every p-transfer pair the level shapes produce (lx 7 -> 3, 9 -> 4, 10 -> 5, 11 -> 5, 12 -> 6)
+    (2, 7, 0.1, True, None, 2, 0.2, False),
+    (2, 9, 0.1, False, None, 2, 0.3, True),
+    (2, 10, 0.1, False, None, 2, 0.3, True),
+    (2, 11, 0.1, True, None, 2, 0.2, True),
+    (2, 12, 0.1, False, None, 2, 0.3, True),
 ]
 
 
