@@ -238,6 +238,30 @@ prolong_kernel(float* __restrict__ xf, const float* __restrict__ xc, const int32
 // -- and the coarse side is spread over the lanes.
 constexpr int kWaveElems = 4;
 
+// a fine row's unique indices and owner flags (LF consecutive local nodes from
+// L0): vector loads when LF is a multiple of 4 (L0 is then 16-byte aligned for
+// the indices and 4-byte aligned for the flags)
+template <int LF>
+__device__ __forceinline__ void load_row(int32_t (&id)[LF], bool (&own)[LF], const int32_t* __restrict__ lidf,
+                                         const uint8_t* __restrict__ ownf, int64_t L0) {
+    if constexpr (LF % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < LF / 4; ++q) {
+            const int4 v = *reinterpret_cast<const int4*>(lidf + L0 + 4 * q);
+            const uint32_t f = *reinterpret_cast<const uint32_t*>(ownf + L0 + 4 * q);
+            id[4 * q] = v.x; id[4 * q + 1] = v.y; id[4 * q + 2] = v.z; id[4 * q + 3] = v.w;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) own[4 * q + b] = ((f >> (8 * b)) & 0xffu) != 0u;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < LF; ++i) {
+            id[i] = lidf[L0 + i];
+            own[i] = ownf[L0 + i] != 0;
+        }
+    }
+}
+
 // P^T: blc[E][c][b][a] = sum_{k,j,i} J[k][c] J[j][b] J[i][a] (owner-masked r_f)[E][k][j][i]
 template <int LF, int LC>
 __global__ void __launch_bounds__(64 * kWaveElems)
@@ -256,9 +280,12 @@ restrict_p_wave_kernel(float* __restrict__ blc, const float* __restrict__ rf, co
     const bool live = E < nel;
     for (int row = lane; row < F2; row += 64) {            // row = k LF + j
         float v[LF];
+        int32_t id[LF];
+        bool own[LF];
         const int64_t L0 = E * F3 + (int64_t)row * LF;
+        if (live) load_row<LF>(id, own, lidf, ownf, L0);
 #pragma unroll
-        for (int i = 0; i < LF; ++i) v[i] = (live && ownf[L0 + i]) ? rf[lidf[L0 + i]] : 0.f;
+        for (int i = 0; i < LF; ++i) v[i] = (live && own[i]) ? rf[id[i]] : 0.f;
 #pragma unroll
         for (int a = 0; a < LC; ++a) {
             float s = 0.f;
@@ -327,13 +354,47 @@ prolong_p_wave_kernel(float* __restrict__ xf, const float* __restrict__ xc, cons
     for (int row = lane; row < F2; row += 64) {            // row = k LF + j
         const int k = row / LF, j = row % LF;
         const int64_t L0 = E * F3 + (int64_t)row * LF;
+        int32_t id[LF];
+        bool own[LF];
+        load_row<LF>(id, own, lidf, ownf, L0);
+        // the row's owner nodes are distinct unique nodes: all loads first, then the stores
+        float old[LF];
+#pragma unroll
+        for (int i = 0; i < LF; ++i) old[i] = own[i] ? xf[id[i]] : 0.f;
 #pragma unroll
         for (int i = 0; i < LF; ++i) {
             float s = 0.f;
 #pragma unroll
             for (int c = 0; c < LC; ++c) s += sJ[k * LC + c] * t2[w][(c * LF + j) * LF + i];
-            if (ownf[L0 + i]) xf[lidf[L0 + i]] += s;
+            if (own[i]) xf[id[i]] = old[i] + s;
         }
+    }
+}
+
+// x_f += P x_c of an h-transfer (lx = 2 boxes): one thread per fine local node,
+// adding at its owner copy the parent's trilinear interpolant at its vertex
+__global__ void prolong_h_kernel(float* __restrict__ xf, const float* __restrict__ xc, const int32_t* __restrict__ lidf,
+                                 const uint8_t* __restrict__ ownf, const int32_t* __restrict__ lidc, int nf, int nc,
+                                 int64_t nelf, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    MG_LOOP(L, nelf * 8) {
+        if (!ownf[L]) continue;
+        const int64_t e = L >> 3;
+        const int i = (int)(L & 7), ix = i & 1, iy = (i >> 1) & 1, iz = i >> 2;
+        const int64_t ex = e % nf, ey = (e / nf) % nf, ez = e / ((int64_t)nf * nf);
+        const int px = (int)(ex & 1), py = (int)(ey & 1), pz = (int)(ez & 1);
+        const int64_t E = (ex >> 1) + nc * ((ey >> 1) + (int64_t)nc * (ez >> 1));
+        float s = 0.f;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int ax = c & 1, ay = (c >> 1) & 1, az = c >> 2;
+            const float wgt = (float)(ax ? px + ix : 2 - px - ix) * (float)(ay ? py + iy : 2 - py - iy) *
+                              (float)(az ? pz + iz : 2 - pz - iz) * 0.125f;
+            if (wgt == 0.f) continue;
+            const int32_t id = lidc[E * 8 + c];
+            if (id >= 0) s += wgt * xc[id];
+        }
+        xf[lidf[L]] += s;
     }
 }
 
@@ -868,8 +929,11 @@ int vcycle(sem_mg_t mg, float* xout, const float* bin, const int* skip) {
         float* x = q == 0 ? xout : lv.x;
         const float* b = q == 0 ? bin : lv.b;
         const int f3 = lv.lx * lv.lx * lv.lx;
-        if (lv.kind != 0 || !prolong_p_wave(st, lv.lx, nx.lx, x, nx.x, lv.gs->lid, lv.own, nx.gs->lid, lv.J,
-                                            lv.nel, skip))
+        if (lv.kind == 1 && lv.lx == 2)
+            prolong_h_kernel<<<vgrid(8 * lv.nel), kBlock, 0, st>>>(x, nx.x, lv.gs->lid, lv.own, nx.gs->lid, lv.n,
+                                                                   nx.n, lv.nel, skip);
+        else if (lv.kind != 0 || !prolong_p_wave(st, lv.lx, nx.lx, x, nx.x, lv.gs->lid, lv.own, nx.gs->lid, lv.J,
+                                                 lv.nel, skip))
             prolong_kernel<<<(unsigned)lv.nel, f3 <= 64 ? 64 : kBlock, 0, st>>>(x, nx.x, lv.gs->lid, lv.own,
                                                                                 nx.gs->lid, lv.J, lv.lx, nx.lx,
                                                                                 lv.kind, lv.n, nx.n, lv.nel, skip);
