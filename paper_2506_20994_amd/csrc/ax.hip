@@ -41,34 +41,38 @@ template <> struct Load<uint16_t> {
 template <typename T>
 __device__ __forceinline__ void store_nt(T* p, int64_t o, T v) { __builtin_nontemporal_store(v, p + o); }
 
-// Solver copies of the six factors, slice-blocked in pairs: for the slice
-// (e, k) the pairs (g11, g22), (g33, g12), (g13, g23) of all lx*lx columns are
-// stored as three consecutive runs of lx*lx two-element vectors, so each wave
-// load is one contiguous block (1 KiB in float64 at lx = 8).
+// Solver copies of the six factors (float64, float32), slice-blocked in
+// pairs: for the slice (e, k) the pairs (g11, g22), (g33, g12), (g13, g23) of
+// all lx*lx columns are stored as three consecutive runs of lx*lx two-element
+// vectors, so each wave load is one contiguous block (1 KiB in float64 at
+// lx = 8).  o is the node's local offset, ij its column.
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef float fvec2 __attribute__((ext_vector_type(2)));
 template <typename TS> struct Packed;
 template <> struct Packed<double> {
-    __device__ static void get(const double* gp, int64_t slice, int ij, int l2, double* g) {
-        const dvec2* q = reinterpret_cast<const dvec2*>(gp) + slice * 3 + ij;
+    __device__ static void get(const double* gp, int64_t o, int ij, int l2, double* g) {
+        const dvec2* q = reinterpret_cast<const dvec2*>(gp) + (o - ij) * 3 + ij;
         const dvec2 a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + l2),
                     c = __builtin_nontemporal_load(q + 2 * l2);
         g[0] = a.x; g[1] = a.y; g[2] = b.x; g[3] = b.y; g[4] = c.x; g[5] = c.y;
     }
 };
 template <> struct Packed<float> {
-    __device__ static void get(const float* gp, int64_t slice, int ij, int l2, float* g) {
-        const fvec2* q = reinterpret_cast<const fvec2*>(gp) + slice * 3 + ij;
+    __device__ static void get(const float* gp, int64_t o, int ij, int l2, float* g) {
+        const fvec2* q = reinterpret_cast<const fvec2*>(gp) + (o - ij) * 3 + ij;
         const fvec2 a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + l2),
                     c = __builtin_nontemporal_load(q + 2 * l2);
         g[0] = a.x; g[1] = a.y; g[2] = b.x; g[3] = b.y; g[4] = c.x; g[5] = c.y;
     }
 };
+// bfloat16 copies: one 12-byte record per node, (h1 g11, h1 g22, h1 g33,
+// h1 g12, h1 g13, h1 g23), h1 folded in when the copy is made; a lane reads its
+// node with one 12-byte load and a wave one contiguous block
 template <> struct Packed<uint16_t> {
-    __device__ static void get(const uint16_t* gp, int64_t slice, int ij, int l2, float* g) {
-        const uint32_t* q = reinterpret_cast<const uint32_t*>(gp) + slice * 3 + ij;
-        const uint32_t a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + l2),
-                       c = __builtin_nontemporal_load(q + 2 * l2);
+    __device__ static void get(const uint16_t* gp, int64_t o, int, int, float* g) {
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(gp) + 3 * o;
+        const uint32_t a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + 1),
+                       c = __builtin_nontemporal_load(q + 2);
         g[0] = __uint_as_float(a << 16); g[1] = __uint_as_float(a & 0xffff0000u);
         g[2] = __uint_as_float(b << 16); g[3] = __uint_as_float(b & 0xffff0000u);
         g[4] = __uint_as_float(c << 16); g[5] = __uint_as_float(c & 0xffff0000u);
@@ -107,7 +111,8 @@ __device__ __forceinline__ void load_factors(TC (&g)[6], TC& h, bool live, int64
         return;
     }
     if constexpr (GATHER) {                    // the solver form reads the packed factors
-        Packed<TS>::get(gp, o - ij, ij, l2, g);   // o - ij = e lx^3 + k lx^2
+        Packed<TS>::get(gp, o, ij, l2, g);
+        if constexpr (std::is_same<TS, uint16_t>::value) return;   // h1 is folded into the record
     } else {
         g[0] = Load<TS>::get(g11, o); g[1] = Load<TS>::get(g22, o); g[2] = Load<TS>::get(g33, o);
         g[3] = Load<TS>::get(g12, o); g[4] = Load<TS>::get(g13, o); g[5] = Load<TS>::get(g23, o);

@@ -361,6 +361,17 @@ template <> __device__ __forceinline__ double cvt<double>(double v) { return v; 
 template <> __device__ __forceinline__ float cvt<float>(double v) { return (float)v; }
 template <> __device__ __forceinline__ uint16_t cvt<uint16_t>(double v) { return bf16_rne((float)v); }
 
+// the bfloat16 solver copy: per node the record (h1 g11, h1 g22, h1 g33,
+// h1 g12, h1 g13, h1 g23), each product rounded float64 -> float32 -> bfloat16
+// (h1 = 1 when the operator has none)
+__global__ void pack_bf16_kernel(uint16_t* __restrict__ out, Six G, const double* __restrict__ h1, int64_t n) {
+    GRID_LOOP(L, n) {
+        const double h = h1 ? h1[L] : 1.0;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) out[6 * L + a] = bf16_rne((float)(h * G.g[a][L]));
+    }
+}
+
 template <typename T>
 __global__ void pack_kernel(T* __restrict__ out, Six G, int64_t n) {
     GRID_LOOP(L, n) {
@@ -915,11 +926,12 @@ void pack_factors_f32(hipStream_t st, float* out, const double* const* G, int64_
     pack_kernel<float><<<vec_grid(n), kBlock, 0, st>>>(out, six, n);
 }
 
-void pack_factors_bf16(hipStream_t st, uint16_t* out, const double* const* G, int64_t n, int lx) {
+void pack_factors_bf16(hipStream_t st, uint16_t* out, const double* const* G, const double* h1, int64_t n,
+                       int lx) {
     Six six;
     for (int q = 0; q < 6; ++q) six.g[q] = G[q];
     six.l2 = lx * lx;
-    pack_kernel<uint16_t><<<vec_grid(n), kBlock, 0, st>>>(out, six, n);
+    pack_bf16_kernel<<<vec_grid(n), kBlock, 0, st>>>(out, six, h1, n);
 }
 
 }  // namespace sem
@@ -1035,15 +1047,14 @@ extern "C" int sem_cg_setup(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A,
         {
             void* d = nullptr;
             CG_ALLOC(d, vs * 6 * n);
-            if (bf) pack_kernel<uint16_t><<<gl, kBlock, 0, st>>>((uint16_t*)d, six, n);
+            if (bf) pack_bf16_kernel<<<gl, kBlock, 0, st>>>((uint16_t*)d, six, A->h1, n);   // h1 folded in
             else pack_kernel<float><<<gl, kBlock, 0, st>>>((float*)d, six, n);
             L.A.Gp = d;
         }
-        if (A->h1) {
+        if (A->h1 && !bf) {
             void* d = nullptr;
             CG_ALLOC(d, vs * n);
-            if (bf) to_bf16_kernel<<<gl, kBlock, 0, st>>>((uint16_t*)d, A->h1, n);
-            else to_type_kernel<float><<<gl, kBlock, 0, st>>>((float*)d, A->h1, n);
+            to_type_kernel<float><<<gl, kBlock, 0, st>>>((float*)d, A->h1, n);
             L.A.h1 = d;
         }
         if (A->h2b) {          // the mass term in the storage type of h1 and G

@@ -1245,7 +1245,7 @@ extern "C" int sem_mg_create(sem_ctx_t ctx, sem_gs_t gs, const sem_operator_t* A
             if (bf) {
                 uint16_t* gp = nullptr;
                 MG_ALLOC(gp, sizeof(uint16_t) * 6 * nloc);
-                sem::pack_factors_bf16(st, gp, G64, nloc, lx);
+                sem::pack_factors_bf16(st, gp, G64, nullptr, nloc, lx);
                 lv.A.Gp = gp;
             } else {
                 float* gp = nullptr;

@@ -63,10 +63,12 @@ struct AxArgs {
     const void* G[6];
     int64_t nel;
     int lx;
-    // the solver form (lid != 0) reads the six factors from one slice-blocked
-    // array: for slice s = e lx^3 + k lx^2 (a multiple of lx^2) and column ij,
-    // pair a of (g11,g22), (g33,g12), (g13,g23) sits at 2-vector index
-    // 3 s + a lx^2 + ij, in the storage type
+    // the solver form (lid != 0) reads the six factors from one packed array.
+    // float64, float32: slice-blocked; for slice s = e lx^3 + k lx^2 (a
+    // multiple of lx^2) and column ij, pair a of (g11,g22), (g33,g12),
+    // (g13,g23) sits at 2-vector index 3 s + a lx^2 + ij.  bfloat16: one
+    // record (h1 g11, h1 g22, h1 g33, h1 g12, h1 g13, h1 g23) per local node L
+    // at 6 L, h1 folded in (h1 is then null)
     const void* Gp = nullptr;
     // Helmholtz: h2 B per local node in the storage type (+ h2 B u), or null
     const void* hb = nullptr;
@@ -108,9 +110,11 @@ int64_t mg_nel(sem_mg_t mg);
 // in place) by Cholesky factorisation; false if a pivot is not positive
 bool spd_inverse(std::vector<double>& A, int n);
 // the six factors of an element-local operator packed for the solver form
-// (the layout of AxArgs::Gp) in float32; n local nodes, asynchronous on st
+// (the layout of AxArgs::Gp) in float32 or bfloat16 (times h1, when given);
+// n local nodes, asynchronous on st
 void pack_factors_f32(hipStream_t st, float* out, const double* const* G, int64_t n, int lx);
-void pack_factors_bf16(hipStream_t st, uint16_t* out, const double* const* G, int64_t n, int lx);
+void pack_factors_bf16(hipStream_t st, uint16_t* out, const double* const* G, const double* h1, int64_t n,
+                       int lx);
 
 #ifdef __HIPCC__
 // sum of the local copies of unique node u of a field in the local layout:

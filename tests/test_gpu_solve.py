@@ -79,6 +79,25 @@ def test_refinement(sem_ctx, prec, mode):
     cg.close()
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_refinement_with_h1(sem_ctx, prec):
+    """A variable h1 (the bfloat16 solver copy folds it into the six factors):
+    the refined solution still meets the oracle's residual and solution."""
+    op, b, ref, bref = _setup(sem_ctx, 3, 8, 0.1, with_h1=True)
+    code = P.SEM_SOLVE_F32_IR if prec == "f32" else P.SEM_SOLVE_BF16_IR
+    cg = op.solver(code)
+    x = torch.empty_like(b)
+    rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10, precision=code, ir_mode=1)
+    torch.cuda.synchronize()
+    assert rc == P.SEM_OK and st["converged"], st
+    xg = _unique(ref, x.cpu().numpy())
+    rel = np.linalg.norm(bref - ref.apply(xg)) / np.linalg.norm(bref)
+    assert rel <= 1.2e-10
+    xs, _, _ = pcg(ref.apply, bref, 1.0 / ref.diagonal(), tol=1e-13)
+    assert np.max(np.abs(xg - xs)) <= 1e-6 * np.max(np.abs(xs))
+    cg.close()
+
+
 def test_solve_is_deterministic(sem_ctx):
     op, b, _, _ = _setup(sem_ctx, 2, 6, 0.1)
     cg = op.solver(P.SEM_SOLVE_F64)
