@@ -192,8 +192,7 @@ int sem_ax_helmholtz(sem_ctx_t ctx, void* w, const void* u,
  *                     16, 32 or 64 lanes of one wave (lx = 3, 5, 6, 7), so an
  *                     element never spans two waves and needs no workgroup
  *                     barrier (as the column mapping has at lx = 2, 4, 8).
- * SEM_AX_DEFAULT (-1) is the built-in choice: SEM_AX_3D at lx = 3, SEM_AX_COLUMN
- * otherwise.  The paper picks among kernel variants by timing them at run
+ * SEM_AX_DEFAULT (-1) is the built-in choice: SEM_AX_COLUMN.  The paper picks among kernel variants by timing them at run
  * time (Sec. 4); sem_ax_tune does that for one lx and element count. */
 enum { SEM_AX_DEFAULT = -1, SEM_AX_COLUMN = 0, SEM_AX_COLUMN_PF = 1, SEM_AX_SLICE = 2, SEM_AX_3D = 3,
        SEM_AX_WAVE = 4 };

@@ -41,6 +41,38 @@ template <> struct Load<uint16_t> {
 template <typename T>
 __device__ __forceinline__ void store_nt(T* p, int64_t o, T v) { __builtin_nontemporal_store(v, p + o); }
 
+// The same accesses through the caches, for element slices that are not whole
+// 128-byte lines: a line shared by two slices (or two elements) is then read
+// from HBM once, where the nontemporal form fetched it again for its second
+// user.  In float64 the nontemporal form counted 1.43, 1.22 and 1.22 times the
+// algorithmic bytes at lx = 5, 6, 7 and 1.08-1.11 at lx = 9, 10, 11; through the
+// caches 1.00-1.10.  That made lx = 3, 5, 6, 7 faster (5: 67 -> 51 us at
+// 32768 elements) but lx = 9, 10, 11 slower by 1-3 %: there the occupancy, not
+// the bytes, bounds the kernel, so they keep the nontemporal form.
+template <typename T> struct LoadC;
+template <> struct LoadC<double> {
+    __device__ static double get(const double* p, int64_t o) { return p[o]; }
+};
+template <> struct LoadC<float> {
+    __device__ static float get(const float* p, int64_t o) { return p[o]; }
+};
+template <> struct LoadC<uint16_t> {
+    __device__ static float get(const uint16_t* p, int64_t o) { return __uint_as_float((uint32_t)p[o] << 16); }
+};
+template <bool NT, typename T>
+__device__ __forceinline__ auto ld(const T* p, int64_t o) {
+    if constexpr (NT) return Load<T>::get(p, o);
+    else return LoadC<T>::get(p, o);
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st(T* p, int64_t o, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p + o);
+    else p[o] = v;
+}
+// nontemporal streaming when an lx^2 slice of TS is a whole number of lines, or lx >= 9
+template <int LX, typename TS>
+constexpr bool kStreamNT = (LX * LX * sizeof(TS)) % 128 == 0 || LX >= 9;
+
 // Solver copies of the six factors (float64, float32), slice-blocked in
 // pairs: for the slice (e, k) the pairs (g11, g22), (g33, g12), (g13, g23) of
 // all lx*lx columns are stored as three consecutive runs of lx*lx two-element
@@ -98,7 +130,7 @@ template <int LX> struct Shape {
 
 // h1 and the six factors at offset o (node ij of a slice) of a live element;
 // h = 1 and zero factors for a dead one
-template <typename TS, typename TC, bool GATHER>
+template <typename TS, typename TC, bool GATHER, bool NT = true>
 __device__ __forceinline__ void load_factors(TC (&g)[6], TC& h, bool live, int64_t o, int ij, int l2,
                                              const TS* __restrict__ h1, const TS* __restrict__ g11,
                                              const TS* __restrict__ g22, const TS* __restrict__ g33,
@@ -114,10 +146,10 @@ __device__ __forceinline__ void load_factors(TC (&g)[6], TC& h, bool live, int64
         Packed<TS>::get(gp, o, ij, l2, g);
         if constexpr (std::is_same<TS, uint16_t>::value) return;   // h1 is folded into the record
     } else {
-        g[0] = Load<TS>::get(g11, o); g[1] = Load<TS>::get(g22, o); g[2] = Load<TS>::get(g33, o);
-        g[3] = Load<TS>::get(g12, o); g[4] = Load<TS>::get(g13, o); g[5] = Load<TS>::get(g23, o);
+        g[0] = ld<NT>(g11, o); g[1] = ld<NT>(g22, o); g[2] = ld<NT>(g33, o);
+        g[3] = ld<NT>(g12, o); g[4] = ld<NT>(g13, o); g[5] = ld<NT>(g23, o);
     }
-    if (h1) h = Load<TS>::get(h1, o);
+    if (h1) h = ld<NT>(h1, o);
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -152,6 +184,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
     constexpr int L3 = L2 * LX;
     constexpr bool WP = (64 % TPE) == 0;
     static_assert(TPE >= L2, "threads per element");
+    constexpr bool NT = GATHER || kStreamNT<LX, TS>;
     if (skip && *skip) return;
     __shared__ TC s_u[EPB * L3];               // the element's u (wave-private: then the r-flux)
     __shared__ TC s_s[EPB * L3];               // s-flux
@@ -192,7 +225,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
             uc[k] = q >= 0 ? (TC)u[q] : TC(0);
         }
         else
-            uc[k] = live ? (TC)Load<TU>::get(u, base + k * L2) : TC(0);
+            uc[k] = live ? (TC)ld<NT>(u, base + k * L2) : TC(0);
     }
     if (act) {
 #pragma unroll
@@ -213,7 +246,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
 #pragma unroll
     for (int m = 0; m < LX; ++m) wt[m] = 0;
     TC ng[6], nh;                              // the next slice's factors (prefetch)
-    if constexpr (PF) load_factors<TS, TC, GATHER>(ng, nh, live, base, ij, L2, h1, g11, g22, g33, g12, g13, g23, gp);
+    if constexpr (PF) load_factors<TS, TC, GATHER, NT>(ng, nh, live, base, ij, L2, h1, g11, g22, g33, g12, g13, g23, gp);
 #pragma unroll 1
     for (int k = 0; k < LX; ++k) {
         const int64_t o = base + k * L2;
@@ -223,9 +256,9 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
             for (int a = 0; a < 6; ++a) g[a] = ng[a];
             H = nh;
             if (k + 1 < LX)
-                load_factors<TS, TC, GATHER>(ng, nh, live, o + L2, ij, L2, h1, g11, g22, g33, g12, g13, g23, gp);
+                load_factors<TS, TC, GATHER, NT>(ng, nh, live, o + L2, ij, L2, h1, g11, g22, g33, g12, g13, g23, gp);
         } else {
-            load_factors<TS, TC, GATHER>(g, H, live, o, ij, L2, h1, g11, g22, g33, g12, g13, g23, gp);
+            load_factors<TS, TC, GATHER, NT>(g, H, live, o, ij, L2, h1, g11, g22, g33, g12, g13, g23, gp);
         }
         TC r = 0, s = 0, t = 0;
 #pragma unroll
@@ -263,8 +296,8 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
             acc += dj[l] * ss[k * L2 + l * LX + i];
         }
         if (live) {
-            if constexpr (HB) acc += Load<TS>::get(hb, base + k * L2) * uc[k];   // Helmholtz: + h2 B u
-            store_nt(w, base + k * L2, (TW)acc);
+            if constexpr (HB) acc += ld<NT>(hb, base + k * L2) * uc[k];   // Helmholtz: + h2 B u
+            st<NT>(w, base + k * L2, (TW)acc);
         }
         if (FUSE) pw += (double)uc[k] * (double)(TW)acc;
     }
@@ -316,6 +349,7 @@ ax_slice_kernel(TW* __restrict__ w, const TS* __restrict__ u,
     constexpr int L2 = LX * LX;
     constexpr int L3 = L2 * LX;
     constexpr int NS = EPB * L2;
+    constexpr bool NT = kStreamNT<LX, TS>;
     __shared__ TC s_d[6 * L2];
     __shared__ TC s_u[2][NS];
     __shared__ TC s_r[2][NS];
@@ -339,7 +373,7 @@ ax_slice_kernel(TW* __restrict__ w, const TS* __restrict__ u,
     }
     TC uc[LX];
 #pragma unroll
-    for (int k = 0; k < LX; ++k) uc[k] = live ? (TC)Load<TS>::get(u, base + k * L2) : TC(0);
+    for (int k = 0; k < LX; ++k) uc[k] = live ? (TC)ld<NT>(u, base + k * L2) : TC(0);
     s_u[0][off + ij] = uc[0];
     __syncthreads();
     TC di[LX], dj[LX], ti[LX], tj[LX];
@@ -364,7 +398,8 @@ ax_slice_kernel(TW* __restrict__ w, const TS* __restrict__ u,
         TC vr = 0, vs = 0;
         if (k < LX) {
             TC g[6], H;
-            load_factors<TS, TC, false>(g, H, live, base + k * L2, ij, L2, h1, g11, g22, g33, g12, g13, g23, nullptr);
+            load_factors<TS, TC, false, NT>(g, H, live, base + k * L2, ij, L2, h1, g11, g22, g33, g12, g13, g23,
+                                            nullptr);
             TC r = 0, s = 0, t = 0;
 #pragma unroll
             for (int l = 0; l < LX; ++l) {
@@ -402,8 +437,8 @@ ax_slice_kernel(TW* __restrict__ w, const TS* __restrict__ u,
 #pragma unroll
         for (int k = 0; k < LX; ++k) {
             TC acc = wt[k];
-            if constexpr (HB) acc += Load<TS>::get(hb, base + k * L2) * uc[k];   // Helmholtz: + h2 B u
-            store_nt(w, base + k * L2, (TW)acc);
+            if constexpr (HB) acc += ld<NT>(hb, base + k * L2) * uc[k];   // Helmholtz: + h2 B u
+            st<NT>(w, base + k * L2, (TW)acc);
         }
     }
 }
@@ -411,9 +446,9 @@ ax_slice_kernel(TW* __restrict__ w, const TS* __restrict__ u,
 // One thread per node ("3D" mapping): every load and store of the streamed
 // arrays is contiguous across the workgroup.  u and the three fluxes go
 // through LDS; each thread keeps the derivative-matrix rows it needs (its i,
-// j, k) in registers.  Used for the public operator at lx = 3, where nine
-// columns per element leave the column mapping's loads badly fragmented (it
-// measured slower than the column kernel at lx = 5, 6, 7).
+// j, k) in registers.  One of the variants the run-time tuning times; with
+// the cached streaming of the column mapping it is the slower one at every lx
+// measured (lx = 3: 18.1 against 13.9 us at 32768 elements).
 template <int LX> struct Shape3D {
     // whole elements per workgroup of at most 1024 threads (none above lx = 10)
     static constexpr int EPB = LX == 3 ? 16 : (1024 / (LX * LX * LX));
@@ -581,18 +616,6 @@ int launch_form(sem_ctx_t ctx, void* w, const void* u, const void* const* D, con
         nel, skip, dot, lid, (const TS*)gp, (const TS*)hb
     const dim3 grid((unsigned)blocks), block(EPB * LX * LX);
     if (lid && !gp) return sem::fail(ctx, SEM_EINVAL, "launch_ax: the solver form needs packed factors");
-    if constexpr (LX == 3) {
-        if (!lid && !dot) {
-            constexpr int E3 = Shape3D<LX>::EPB;
-            const int64_t b3 = (nel + E3 - 1) / E3;
-            ax3d_kernel<LX, E3, TS, TC, TW, HB><<<(unsigned)b3, E3 * LX * LX * LX, 0, ctx->stream>>>(
-                (TW*)w, (const TS*)u, (const TC*)D[0], (const TC*)D[1], (const TC*)D[2], (const TC*)D[3],
-                (const TC*)D[4], (const TC*)D[5], (const TS*)h1, (const TS*)G[0], (const TS*)G[1],
-                (const TS*)G[2], (const TS*)G[3], (const TS*)G[4], (const TS*)G[5], nel, (const TS*)hb);
-            SEM_LAUNCH_CHECK(ctx);
-            return SEM_OK;
-        }
-    }
     if (dot && lid)
         ax_kernel<LX, EPB, TU, TS, TC, TW, true, true, HB><<<grid, block, 0, ctx->stream>>>(SEM_AX_ARGS);
     else if (lid)
