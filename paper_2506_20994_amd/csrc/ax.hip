@@ -188,7 +188,14 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
     if (skip && *skip) return;
     __shared__ TC s_u[EPB * L3];               // the element's u (wave-private: then the r-flux)
     __shared__ TC s_s[EPB * L3];               // s-flux
-    __shared__ TC s_r0[WP ? 1 : EPB * L3];     // r-flux when elements span waves
+    // Elements spanning waves write the r-flux of slice k over slice k of u
+    // after a workgroup barrier (every wave has read it) instead of into a third
+    // array, where the LDS this frees admits one more workgroup per CU
+    // (lx = 7: 3 -> 4, lx = 9 and 11: 2 -> 3; 4-5 % faster at lx 9 and 11).  At
+    // the other lx the registers, not the LDS, cap the workgroups, and the
+    // barrier per slice would cost without a gain.
+    constexpr bool ALIAS = !WP && (LX == 7 || LX == 9 || LX == 11);
+    __shared__ TC s_r0[(WP || ALIAS) ? 1 : EPB * L3];     // r-flux when elements span waves
     __shared__ TC s_d[6 * L2];                 // dx, dy, dz, dxt, dyt, dzt
 
     const int tid = threadIdx.x;
@@ -203,7 +210,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
     const int64_t base = e * L3 + ij;
     TC* su = s_u + el * L3;
     TC* ss = s_s + el * L3;
-    TC* sr = WP ? su : s_r0 + el * L3;
+    TC* sr = (WP || ALIAS) ? su : s_r0 + el * L3;
     const TC* sdz = s_d + 2 * L2;
     const TC* sdzt = s_d + 5 * L2;
 
@@ -272,6 +279,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
         const TC vs = H * (G12 * r + G22 * s + G23 * t);
         const TC vt = H * (G13 * r + G23 * s + G33 * t);
         if (WP) wave_sync();   // every lane has read slice k before it is overwritten
+        else if (ALIAS) __syncthreads();
         if (act) {
             sr[k * L2 + ij] = vr;
             ss[k * L2 + ij] = vs;
