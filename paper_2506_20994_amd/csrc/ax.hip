@@ -112,14 +112,19 @@ template <> struct Packed<uint16_t> {
 };
 
 #ifndef SEM_AX_PREFETCH
-#define SEM_AX_PREFETCH(LX) ((LX) != 2 && (LX) != 8)
+#define SEM_AX_PREFETCH(LX) ((LX) != 2 && (LX) != 8 && (LX) != 12)
 #endif
 
 template <int LX> struct Shape {
     static constexpr bool kWavePrivate = (64 % (LX * LX)) == 0;
-    // occupancy floor (waves per SIMD) handed to the register allocator (a
-    // floor of 3 at lx = 10 gave three waves per SIMD but a slower kernel)
-    static constexpr int kWavesPerEU = 1;
+    // occupancy floor (waves per SIMD) handed to the register allocator.  At
+    // lx = 12 the kernel needs 169 VGPRs, two waves per SIMD; a floor of 3
+    // brings it to 168 (two spilled, outside the slice loop) and, with the LDS
+    // alias below, four workgroups per CU instead of two: 950 -> 774 us at
+    // 32768 elements (without prefetch; with it 11 registers spill and it
+    // slows down).  Floors elsewhere spilled inside the loop and lost (lx = 9,
+    // 10: 4 waves per SIMD, 331 and 534 against 325 and 433 us).
+    static constexpr int kWavesPerEU = LX == 12 ? 3 : 1;
     // fetch the next slice's h1 and G while the current slice is computed
     static constexpr bool kPrefetch = SEM_AX_PREFETCH(LX);
     // elements per workgroup: about four waves, LDS of float64 within ~64 KiB
@@ -191,10 +196,11 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
     // Elements spanning waves write the r-flux of slice k over slice k of u
     // after a workgroup barrier (every wave has read it) instead of into a third
     // array, where the LDS this frees admits one more workgroup per CU
-    // (lx = 7: 3 -> 4, lx = 9 and 11: 2 -> 3; 4-5 % faster at lx 9 and 11).  At
-    // the other lx the registers, not the LDS, cap the workgroups, and the
-    // barrier per slice would cost without a gain.
-    constexpr bool ALIAS = !WP && (LX == 7 || LX == 9 || LX == 11);
+    // (lx = 7: 3 -> 4, lx = 9 and 11: 2 -> 3, 4-5 % faster at lx 9 and 11;
+    // lx = 12 with its register floor: 3 -> 4).  At the other lx the
+    // registers, not the LDS, cap the workgroups, and the barrier per slice
+    // would cost without a gain.
+    constexpr bool ALIAS = !WP && (LX == 7 || LX == 9 || LX == 11 || LX == 12);
     __shared__ TC s_r0[(WP || ALIAS) ? 1 : EPB * L3];     // r-flux when elements span waves
     __shared__ TC s_d[6 * L2];                 // dx, dy, dz, dxt, dyt, dzt
 
