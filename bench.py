@@ -243,6 +243,33 @@ def solve_comparison(ctx, P, n, lx, amp, tol=1e-10):
     return res
 
 
+def pcg_run(ctx, P, n, lx, amp, tol=1e-10, maxit=600):
+    """The solver's iteration on its own, for kernel traces and counters: one
+    float64 Jacobi-PCG and one float32 residual-replacement solve of the bench's
+    periodic box, each capped at maxit iterations."""
+    import torch
+    import synth
+    from paper_2506_20994_amd.box import BoxOperator
+    op = BoxOperator(ctx, n, lx, amp)
+    k, a, ph = synth.fourier_modes(2)
+    b = op.fourier_rhs(k, a, ph)
+    x = torch.empty_like(b)
+    out = {"mode": "pcg", "workload": f"{n}^3 box lx={lx} amplitude {amp}, h1=1, 32 Fourier modes, "
+                                      f"at most {maxit} iterations"}
+    for name, code, mode in (("fp64_pcg", P.SEM_SOLVE_F64, 0), ("f32_rr", P.SEM_SOLVE_F32_IR, 1)):
+        cg = op.solver(code)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = P.sem_cg_solve(cg, x, b, tol=tol, precision=code, ir_mode=mode, maxit=maxit)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        cg.close()
+        out[name] = {"ms": round(ms, 2), "iterations": st["iterations"],
+                     "us_per_iteration": round(1e3 * ms / max(st["iterations"], 1), 1)}
+        print(f"[bench] pcg {name}: {ms:.1f} ms, {st['iterations']} its", file=sys.stderr, flush=True)
+    return out
+
+
 def _timed_solve(P, op, x, b, code, mode, lp, tol, mg=None, h2b=None):
     """One warm-up and one timed sem_cg_solve; returns (ms, stats)."""
     import torch
@@ -700,7 +727,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in operator variant")
     ap.add_argument("--no-helmholtz", action="store_true",
                     help="skip the Helmholtz timing (it launches the same kernel as sem_ax)")
-    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "scale", "trials", "mg"])
+    ap.add_argument("--mode", default="bench", choices=["bench", "copy", "scale", "trials", "mg", "pcg"])
     ap.add_argument("--sweep", action="store_true", help="--mode mg: sweep the V-cycle's parameters")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -729,6 +756,11 @@ def main():
     if args.mode == "mg":
         ctx = P.sem_create()
         print(json.dumps(mg_run(ctx, P, args.n, args.lx, args.amp, sweep=args.sweep)), flush=True)
+        ctx.close()
+        return
+    if args.mode == "pcg":
+        ctx = P.sem_create()
+        print(json.dumps(pcg_run(ctx, P, args.n, args.lx, args.amp)), flush=True)
         ctx.close()
         return
     if args.mode == "scale":
