@@ -93,8 +93,9 @@ def load_traffic(n_local):
 
 def cpu_baseline(lx, target_s=10.0):
     """The plain-C oracle (oracle/sem_ref.c) on this host: the operator on all
-    threads (the headline, GDOF/s) and on one thread, float64 Jacobi-PCG to
-    relres 1e-10 on the 16^3 box, and 20 PCG iterations on the 32^3 box."""
+    threads (the headline, GDOF/s) and on one thread, the operator at lx = 6, 10
+    and 12 on all threads, float64 Jacobi-PCG to relres 1e-10 on the 16^3 box,
+    and 20 PCG iterations on the 32^3 box."""
     import numpy as np
     import synth
     from oracle import cref
@@ -105,7 +106,7 @@ def cpu_baseline(lx, target_s=10.0):
     Dh = deriv_matrix(gll_nodes_weights(lx - 1)[0])
     threads = cref.num_threads()
 
-    def rate(seconds):
+    def rate(seconds, u=u, Dh=Dh, h1=h1, G=G):
         cref.ax(u, Dh, h1, G)                # warm-up
         reps, t0 = 0, time.perf_counter()
         while True:
@@ -125,6 +126,14 @@ def cpu_baseline(lx, target_s=10.0):
     reps1, el1 = rate(2.0)
     cref.set_threads(threads)
     out["ax_1_thread_gdofs"] = round(reps1 * nel * (lx - 1) ** 3 / el1 / 1e9, 4)
+    by_lx = {}
+    for lo in (6, 10, 12):                   # about as many local nodes as the lx sample
+        ne = max(64, nel * lx ** 3 // lo ** 3)
+        Go, ho = synth.random_spd_factors(ne, lo, 123)
+        uo = synth.local_normal(ne, lo, 124)
+        ro, eo = rate(1.5, uo, deriv_matrix(gll_nodes_weights(lo - 1)[0]), ho, Go)
+        by_lx[str(lo)] = round(ro * ne * (lo - 1) ** 3 / eo / 1e9, 4)
+    out["ax_gdofs_by_lx"] = by_lx
     k, a, ph = synth.fourier_modes(2)
     box = cref.BigBox(16, lx, 0.1)
     b = box.fourier_rhs(k, a, ph)
@@ -142,7 +151,7 @@ def cpu_baseline(lx, target_s=10.0):
     out["pcg_32cubed_20_iterations"] = {"s": round(el, 2), "ms_per_iteration": round(el / its * 1e3, 1),
                                         "threads": threads}
     print(f"[bench] cpu baseline: {out['value']:.3f} GDOF/s on {threads} threads, "
-          f"{out['ax_1_thread_gdofs']:.3f} on 1; PCG 16^3 {out['pcg_16cubed']['s']} s; "
+          f"{out['ax_1_thread_gdofs']:.3f} on 1; lx 6/10/12 {by_lx}; PCG 16^3 {out['pcg_16cubed']['s']} s; "
           f"32^3 {out['pcg_32cubed_20_iterations']['ms_per_iteration']} ms/iteration",
           file=sys.stderr, flush=True)
     return out
