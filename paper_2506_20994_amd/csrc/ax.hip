@@ -246,11 +246,18 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
     }
     __syncthreads();   // s_d is shared by every wave of the workgroup
 
-    TC di[LX], dj[LX];
+    // The float64 solver form at lx = 8 reads the j-direction rows of D from LDS
+    // instead of keeping them in registers: 138 -> 122 VGPRs, four waves per
+    // SIMD instead of three, and the float64 PCG iteration 436 -> 418 us at 32^3.
+    // The public form measured the same either way (188.1 us) and the float32
+    // and bfloat16 forms, already at 64-78 VGPRs, slower, so they keep them.
+    constexpr bool DJL = LX == 8 && GATHER && std::is_same<TC, double>::value;
+    TC di[LX], dj[DJL ? 1 : LX];
+    const TC* sdj = s_d + L2;
 #pragma unroll
     for (int l = 0; l < LX; ++l) {
         di[l] = s_d[l * LX + i];
-        dj[l] = s_d[L2 + l * LX + j];
+        if constexpr (!DJL) dj[l] = s_d[L2 + l * LX + j];
     }
 
     // forward passes slice by slice; the t-flux of slice k is folded straight
@@ -277,7 +284,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
 #pragma unroll
         for (int l = 0; l < LX; ++l) {
             r += di[l] * su[k * L2 + j * LX + l];
-            s += dj[l] * su[k * L2 + l * LX + i];
+            s += (DJL ? sdj[l * LX + j] : dj[DJL ? 0 : l]) * su[k * L2 + l * LX + i];
             t += sdz[l * LX + k] * uc[l];
         }
         const TC G11 = g[0], G22 = g[1], G33 = g[2], G12 = g[3], G13 = g[4], G23 = g[5];
@@ -298,7 +305,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
 #pragma unroll
     for (int l = 0; l < LX; ++l) {
         di[l] = s_d[3 * L2 + l * LX + i];
-        dj[l] = s_d[4 * L2 + l * LX + j];
+        if constexpr (!DJL) dj[l] = s_d[4 * L2 + l * LX + j];
     }
     double pw = 0.0;
 #pragma unroll
@@ -307,7 +314,7 @@ ax_kernel(TW* __restrict__ w, const TU* __restrict__ u,
 #pragma unroll
         for (int l = 0; l < LX; ++l) {
             acc += di[l] * sr[k * L2 + j * LX + l];
-            acc += dj[l] * ss[k * L2 + l * LX + i];
+            acc += (DJL ? s_d[4 * L2 + l * LX + j] : dj[DJL ? 0 : l]) * ss[k * L2 + l * LX + i];
         }
         if (live) {
             if constexpr (HB) acc += ld<NT>(hb, base + k * L2) * uc[k];   // Helmholtz: + h2 B u
