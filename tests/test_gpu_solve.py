@@ -55,6 +55,32 @@ def test_pcg_f64(sem_ctx, n, lx, amp, h1):
     cg.close()
 
 
+@pytest.mark.parametrize("lx,prec,h1", [(7, "f64", True), (9, "f64", False), (11, "f64", True), (12, "f64", False),
+                                        (7, "f32", False), (9, "bf16", True), (12, "f32", True), (12, "bf16", False)])
+def test_solver_form_at_lx_with_shared_flux_storage(sem_ctx, lx, prec, h1):
+    """The solver's operator at lx = 7, 9, 11, 12, where the r-flux of a slice
+    overwrites the slice of u in LDS after a workgroup barrier (and lx = 12
+    runs under a register floor): float64 Jacobi-PCG and float32 / bfloat16
+    residual replacement on a 2^3 box against the oracle's operator and
+    solution."""
+    op, b, ref, bref = _setup(sem_ctx, 2, lx, 0.1, with_h1=h1)
+    code = {"f64": P.SEM_SOLVE_F64, "f32": P.SEM_SOLVE_F32_IR, "bf16": P.SEM_SOLVE_BF16_IR}[prec]
+    cg = op.solver(code)
+    x = torch.empty_like(b)
+    rc, st = P.sem_cg_solve(cg, x, b, tol=1e-10, precision=code, ir_mode=0 if prec == "f64" else 1)
+    torch.cuda.synchronize()
+    assert rc == P.SEM_OK and st["converged"], st
+    xg = _unique(ref, x.cpu().numpy())
+    rel = np.linalg.norm(bref - ref.apply(xg)) / np.linalg.norm(bref)
+    assert rel <= 1.2e-10, rel
+    xs, ito, _ = pcg(ref.apply, bref, 1.0 / ref.diagonal(), tol=1e-13)
+    assert np.max(np.abs(xg - xs)) <= 1e-6 * np.max(np.abs(xs))
+    if prec == "f64":
+        _, ito, _ = pcg(ref.apply, bref, 1.0 / ref.diagonal(), tol=1e-10)
+        assert abs(st["iterations"] - ito) <= 2, (st["iterations"], ito)
+    cg.close()
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_refinement(sem_ctx, prec, mode):
